@@ -1,0 +1,99 @@
+"""Seeded synthetic input densities.
+
+This module holds no arithmetic of the solver: it only draws the densities f, g
+that both the GPU path and the CPU oracle receive as data.  The paper's own
+inputs (MRI slices, photographs) are not available, so these recipes stand in
+for them; each is a positive 1-periodic density on the unit torus scaled to
+grid mean one.
+
+Recipes
+-------
+manufactured(N, A)
+    Section 5.1 procedure with g = 1: pick psi* = A sin(2 pi x1) sin(2 pi x2) and
+    set f = det(I + D^2 psi*) in closed form, which has mean exactly one.
+blobs(N, seed)
+    0.1 + a sum of 8 periodic Gaussian blobs: centres uniform on the torus,
+    widths uniform in [0.03, 0.1], peak weights uniform in [0.5, 1.5]; each blob
+    is summed over its 3 x 3 nearest periodic images; then scaled to mean one.
+    Draw order per density: centres (8 x 2), widths (8), weights (8); f first,
+    then g, from numpy.random.default_rng(seed).
+smooth_noise(N, seed, sigma_px)
+    f = exp(z / 2) with z white noise filtered by a unit-gain periodic Gaussian
+    of width sigma_px grid cells; scaled to mean one.  Draws f, then g.
+
+Grid convention everywhere: F[i, j] is the value at (x1, x2) = (i/N, j/N).
+"""
+
+import numpy as np
+
+SEED_BASE = 20261203
+
+
+def seed_for(config, index):
+    """Documented seed schedule: one seed per (config, pair index)."""
+    return SEED_BASE + 1000 * int(config) + int(index)
+
+
+def grid(N):
+    x = np.arange(N, dtype=np.float64) / N
+    return np.meshgrid(x, x, indexing="ij")
+
+
+def manufactured(N, A=0.01):
+    """(f, g, psi_star) for psi* = A sin(2 pi x1) sin(2 pi x2), g = 1."""
+    X1, X2 = grid(N)
+    s1, s2 = np.sin(2 * np.pi * X1), np.sin(2 * np.pi * X2)
+    c1, c2 = np.cos(2 * np.pi * X1), np.cos(2 * np.pi * X2)
+    c = 4.0 * np.pi ** 2 * A
+    psi = A * s1 * s2
+    # psi_11 = psi_22 = -c s1 s2, psi_12 = c c1 c2
+    f = (1.0 - c * s1 * s2) ** 2 - (c * c1 * c2) ** 2
+    g = np.ones((N, N))
+    return f, g, psi
+
+
+def _blob_density(N, rng):
+    X1, X2 = grid(N)
+    centres = rng.uniform(0.0, 1.0, size=(8, 2))
+    sigmas = rng.uniform(0.03, 0.1, size=8)
+    weights = rng.uniform(0.5, 1.5, size=8)
+    d = np.full((N, N), 0.1)
+    for b in range(8):
+        for p1 in (-1, 0, 1):
+            for p2 in (-1, 0, 1):
+                dx = X1 - centres[b, 0] - p1
+                dy = X2 - centres[b, 1] - p2
+                d += weights[b] * np.exp(-(dx * dx + dy * dy) / (2.0 * sigmas[b] ** 2))
+    return d / d.mean()
+
+
+def blobs(N, seed):
+    """(f, g): independent blob densities drawn from one generator."""
+    rng = np.random.default_rng(seed)
+    f = _blob_density(N, rng)
+    g = _blob_density(N, rng)
+    return f, g
+
+
+def _noise_density(N, rng, sigma_px):
+    xi = rng.standard_normal((N, N))
+    k = np.fft.fftfreq(N, d=1.0 / N)
+    K2 = k[:, None] ** 2 + k[None, :] ** 2
+    filt = np.exp(-2.0 * np.pi ** 2 * sigma_px ** 2 * K2 / (N * N))
+    z = np.fft.ifft2(np.fft.fft2(xi) * filt).real
+    d = np.exp(0.5 * z)
+    return d / d.mean()
+
+
+def smooth_noise(N, seed, sigma_px=4.0):
+    """(f, g): exp(z/2) densities from Gaussian-filtered periodic white noise."""
+    rng = np.random.default_rng(seed)
+    f = _noise_density(N, rng, sigma_px)
+    g = _noise_density(N, rng, sigma_px)
+    return f, g
+
+
+def mixed_sizes(npairs, seed, sizes=(128, 256, 384, 512)):
+    """Grid sizes for a batch of uneven pairs, drawn uniformly from `sizes`."""
+    rng = np.random.default_rng(seed)
+    return [int(s) for s in rng.choice(np.asarray(sizes), size=npairs)]

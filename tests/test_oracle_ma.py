@@ -1,0 +1,321 @@
+"""Pins for oracle.ma: Strain's operator, GMRES, and the damped Newton loop.
+
+Each test checks the oracle against something other than itself: closed-form
+spectral collocation matrices (Trefethen, Spectral Methods in MATLAB, ch. 3),
+dense linear algebra, analytic solutions, or numbers the paper prints.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import fd, ma
+from paper_1009_6039_amd import workloads as W
+
+
+# ---------------------------------------------------------------- dense references
+
+def trefethen_d1(N):
+    """Closed-form Fourier first-derivative matrix on [0,1) with N (even) nodes."""
+    h = 2 * math.pi / N
+    D = np.zeros((N, N))
+    for j in range(N):
+        for l in range(N):
+            if j != l:
+                D[j, l] = 0.5 * (-1) ** (j - l) / math.tan((j - l) * h / 2)
+    return 2 * math.pi * D
+
+
+def trefethen_d2(N):
+    """Closed-form Fourier second-derivative matrix on [0,1) (not the square of D1)."""
+    h = 2 * math.pi / N
+    D = np.zeros((N, N))
+    for j in range(N):
+        for l in range(N):
+            if j == l:
+                D[j, l] = -math.pi ** 2 / (3 * h * h) - 1.0 / 6.0
+            else:
+                D[j, l] = -((-1) ** (j - l)) / (2 * math.sin((j - l) * h / 2) ** 2)
+    return 4 * math.pi ** 2 * D
+
+
+def dense_operator(coef, N):
+    """L = a11 D11 + 2 a12 D12 + a22 D22 + b1 D1 + b2 D2 on row-major vec(u), u[i,j], i <-> x1."""
+    D1, D2, I = trefethen_d1(N), trefethen_d2(N), np.eye(N)
+    a11, a12, a22, b1, b2 = [np.broadcast_to(c, (N, N)).ravel() for c in coef]
+    return (a11[:, None] * np.kron(D2, I) + 2 * a12[:, None] * np.kron(D1, D1)
+            + a22[:, None] * np.kron(I, D2) + b1[:, None] * np.kron(D1, I)
+            + b2[:, None] * np.kron(I, D1))
+
+
+def random_coefficients(N, seed):
+    rng = np.random.default_rng(seed)
+    x = np.arange(N) / N
+    X1, X2 = np.meshgrid(x, x, indexing="ij")
+    gy = 1 + 0.4 * np.cos(2 * np.pi * X1 + rng.uniform()) * np.sin(2 * np.pi * X2)
+    u11 = 0.3 * np.sin(2 * np.pi * (X1 + X2))
+    u22 = 0.2 * np.cos(4 * np.pi * X2)
+    u12 = 0.15 + 0.1 * np.sin(2 * np.pi * X1)  # nonzero mean: abar12 != 0
+    a11, a22, a12 = gy * (1 + u22), gy * (1 + u11), -gy * u12
+    b1 = 0.5 * rng.standard_normal((N, N))
+    b2 = 0.5 * rng.standard_normal((N, N))
+    return a11, a12, a22, b1, b2
+
+
+# ---------------------------------------------------------------- Strain operator
+
+def test_trefethen_matrices_are_the_fourier_multipliers():
+    # independent check that the closed forms encode reading P8 (D1 kills Nyquist, D2 keeps it)
+    N = 8
+    x = np.arange(N) / N
+    for k in range(-N // 2, N // 2):
+        e = np.exp(2j * np.pi * k * x)
+        m1 = 0.0 if k == -N // 2 else 2j * np.pi * k
+        if k == -N // 2:  # the Nyquist mode is real on the grid: derivative of cos(pi N x) is 0
+            e = e.real
+        assert np.allclose(trefethen_d1(N) @ e, m1 * e, atol=1e-9)
+        assert np.allclose(trefethen_d2(N) @ e, -(2 * np.pi * k) ** 2 * e, atol=1e-8)
+
+
+@pytest.mark.parametrize("N", [8, 12])
+def test_strain_matvec_equals_dense_collocation_product(N):
+    coef = random_coefficients(N, N)
+    abar = ma.averaged(coef)
+    rho = ma.symbol(abar, N)
+    L = dense_operator(coef, N)
+    Lbar = dense_operator(abar, N)
+    A = L @ np.linalg.pinv(Lbar, rcond=1e-12)
+    v = np.random.default_rng(7).standard_normal((N, N))
+    assert np.allclose(ma.strain_apply(v, coef, rho).ravel(), A @ v.ravel(), rtol=1e-9, atol=1e-9)
+    theta = ma.lbar_inverse(v, rho)
+    assert np.allclose(theta.ravel(), np.linalg.pinv(Lbar, rcond=1e-12) @ v.ravel(), atol=1e-10)
+
+
+def test_symbol_is_hermitian_and_zero_only_at_the_constant_mode():
+    N = 16
+    abar = (1.3, -0.2, 0.9, 0.4, -0.7)
+    rho = ma.symbol(abar, N)
+    idx = (-np.arange(N)) % N
+    assert np.allclose(rho[idx][:, idx], np.conj(rho), rtol=1e-14, atol=0)
+    assert rho[0, 0] == 0
+    assert np.count_nonzero(rho == 0) == 1
+    # the averaged operator is elliptic: Re S(k) < 0 for k != 0
+    S = 1.0 / rho[rho != 0]
+    assert np.all(S.real < 0)
+
+
+def test_strain_operator_outputs_are_real():
+    N = 16
+    coef = random_coefficients(N, 3)
+    rho = ma.symbol(ma.averaged(coef), N)
+    s = rho * np.fft.fft2(np.random.default_rng(1).standard_normal((N, N)))
+    m1, m2 = ma.multipliers(N)
+    for mult in (m2[:, None], m2[None, :], m1[:, None] * m1[None, :], m1[:, None], m1[None, :],
+                 np.ones((1, 1))):
+        z = np.fft.ifft2(mult * s)
+        assert np.max(np.abs(z.imag)) < 1e-12 * max(1.0, np.max(np.abs(z.real)))
+
+
+# ---------------------------------------------------------------- GMRES
+
+def test_gmres_matches_dense_solution():
+    N = 8
+    coef = random_coefficients(N, 11)
+    rho = ma.symbol(ma.averaged(coef), N)
+    A = np.stack([ma.strain_apply(e.reshape(N, N), coef, rho).ravel()
+                  for e in np.eye(N * N)], axis=1)
+    h = (A @ np.random.default_rng(5).standard_normal(N * N)).reshape(N, N)
+    sig, its, conv = ma.gmres(lambda v: ma.strain_apply(v, coef, rho), h, m=N * N, tol=1e-12)
+    assert conv
+    ref = np.linalg.lstsq(A, h.ravel(), rcond=None)[0].reshape(N, N)
+    # sigma is defined up to the kernel of A (constants); theta = Lbar^{-1} sigma is unique
+    assert np.allclose(ma.lbar_inverse(sig, rho), ma.lbar_inverse(ref, rho), atol=1e-10)
+
+
+def test_restarted_gmres_reaches_tolerance_and_counts_iterations():
+    N = 16
+    coef = random_coefficients(N, 2)
+    rho = ma.symbol(ma.averaged(coef), N)
+    op = lambda v: ma.strain_apply(v, coef, rho)  # noqa: E731
+    h = op(np.random.default_rng(9).standard_normal((N, N)))
+    sig, its, conv = ma.gmres(op, h, m=3, tol=1e-8, max_restarts=200)
+    assert conv and its > 3
+    assert np.linalg.norm(h - op(sig)) <= 1.01e-8 * np.linalg.norm(h)
+
+
+def test_gmres_identity_converges_in_one_iteration():
+    b = np.random.default_rng(0).standard_normal((8, 8))
+    x, its, conv = ma.gmres(lambda v: 2.0 * v, b, m=10, tol=1e-12)
+    assert conv and its == 1 and np.allclose(x, b / 2)
+
+
+# ---------------------------------------------------------------- Newton loop
+
+def test_first_step_with_uniform_target_is_a_spectral_poisson_solve():
+    # g = 1, u0 = 0: L = Lbar = Laplacian, A = I on mean-zero fields, theta0 = Lap^{-1}(f - 1)/tau
+    N = 16
+    f, g, _ = W.manufactured(N, A=0.02)
+    prob = ma.Problem(f, g)
+    ev = ma.evaluate(np.zeros((N, N)), prob)
+    tau = 3.0
+    coef = ma.coefficients(ev)
+    rho = ma.symbol(ma.averaged(coef), N)
+    sig, its, _ = ma.gmres(lambda v: ma.strain_apply(v, coef, rho), ev.r / tau, tol=1e-12)
+    assert its == 1
+    theta = ma.lbar_inverse(sig, rho)
+    D2, I = trefethen_d2(N), np.eye(N)
+    lap = np.kron(D2, I) + np.kron(I, D2)
+    ref = np.linalg.pinv(lap, rcond=1e-12) @ ((prob.f - 1.0) / tau).ravel()
+    assert np.allclose(theta.ravel(), ref, atol=1e-12)
+
+
+def test_discrete_exact_manufactured_solution_is_recovered():
+    # f := det(I + D_h^2 psi*) translated to mean 1, g = 1: the discrete fixed point is psi* itself
+    N = 32
+    _, g, ps = W.manufactured(N, A=0.01)
+    u1, u2, u11, u22, u12 = fd.derivatives(ps, 1.0 / N)
+    fdisc = (1 + u11) * (1 + u22) - u12 ** 2
+    fdisc = fdisc - fdisc.mean() + 1.0
+    psi, _, rep = ma.solve(fdisc, g, tau=1.0, tol=1e-13)
+    assert rep.status == ma.OK
+    assert np.max(np.abs(psi - ps)) < 1e-10
+
+
+def test_fourth_order_grid_convergence_on_the_manufactured_example():
+    # Section 5.1 reports observed orders 4.3521, 4.0035, 3.9965, 3.9990 for grids 16..256
+    errs = []
+    for N in (16, 32, 64):
+        f, g, ps = W.manufactured(N)
+        psi, _, rep = ma.solve(f, g, tau=1.0, tol=1e-11)
+        assert rep.status == ma.OK
+        errs.append(math.sqrt(np.mean((psi - ps) ** 2)))
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+    assert abs(orders[-1] - 3.9990) < 0.05
+    assert all(3.9 < o < 4.4 for o in orders)
+
+
+def test_equal_densities_give_zero_potential_without_iterating():
+    N = 32
+    f, _ = W.blobs(N, 5)
+    psi, mp, rep = ma.solve(f, f.copy(), tau=1.0, tol=1e-12)
+    assert rep.status == ma.OK and rep.newton_iters == 0
+    assert np.all(psi == 0)
+    x = np.arange(N) / N
+    assert np.allclose(mp[0], x[:, None]) and np.allclose(mp[1], x[None, :])
+
+
+def test_mass_and_gauge_are_preserved():
+    N = 32
+    f, g = W.blobs(N, 8)
+    prob = ma.Problem(f, g)
+    u = 0.002 * np.random.default_rng(0).standard_normal((N, N))
+    u -= u.mean()
+    ev = ma.evaluate(u, prob)
+    assert abs(np.mean(ev.ft) - 1.0) < 1e-14
+    assert abs(np.mean(ev.r)) < 1e-14
+    psi, _, rep = ma.solve(f, g, tau=1.0, tol=1e-8, damping_policy="backtrack", gmres_tol=0.1)
+    assert rep.status == ma.OK
+    assert abs(np.mean(psi)) < 1e-15 * max(1, rep.newton_iters) * 100
+
+
+def test_w2_closed_form():
+    # g = 1, psi* = A sin sin: d(f,g) = int |grad psi*|^2 f = 2 pi^2 A^2 (Section 5.2 distance)
+    A = 0.01
+    f, g, _ = W.manufactured(64, A=A)
+    _, _, rep = ma.solve(f, g, tau=1.0, tol=1e-11)
+    assert rep.w2sq == pytest.approx(2 * math.pi ** 2 * A ** 2, rel=1e-5)
+
+
+def test_nyquist_mode_decays_at_the_rate_the_paper_reports():
+    # Section 5.1: the residual of the FFT implementation decays by "about 0.45" per iteration.
+    # For a Nyquist-mode error the fourth-order and spectral second-derivative symbols differ
+    # by the factor (64/12)/pi^2, so one tau=1 step leaves 1 - 64/(12 pi^2) = 0.4596 of it.
+    N = 32
+    f = np.ones((N, N))
+    u0 = 1e-7 * (-1.0) ** np.arange(N)[:, None] * np.ones((1, N))
+    prob = ma.Problem(f, f)
+    ev0 = ma.evaluate(u0, prob)
+    theta, _ = ma.newton_direction(ev0, prob, 1.0, 0, 10, 1e-12, 20)
+    ev1 = ma.evaluate(u0 + theta, prob)
+    rate = ev1.res_rms / ev0.res_rms
+    assert rate == pytest.approx(1 - 64 / (12 * math.pi ** 2), abs=2e-4)
+    assert abs(rate - 0.45) < 0.015
+
+
+def test_larger_damping_converges_more_slowly():
+    # Figure error_diff_tau: bigger tau, slower convergence; rate bound 1 - 1/(2 tau) (Section 3.3)
+    f, g, _ = W.manufactured(32, A=0.01)
+    iters = []
+    for tau in (1.0, 2.0, 4.0):
+        _, _, rep = ma.solve(f, g, tau=tau, tol=1e-9, history=True)
+        assert rep.status == ma.OK
+        iters.append(rep.newton_iters)
+        h = rep.history
+        tail = h[-1] / h[-2]
+        if tau > 1:
+            assert tail <= 1 - 1 / (2 * tau) + 1e-3
+    assert iters[0] < iters[1] < iters[2]
+
+
+def test_iterates_stay_convex_on_blob_pairs():
+    N = 64
+    f, g = W.blobs(N, W.seed_for(1, 0))
+    psi, _, rep = ma.solve(f, g, tau=1.0, tol=1e-6, damping_policy="backtrack", gmres_tol=0.1)
+    assert rep.status == ma.OK and rep.min_det > 0 and rep.res_rms <= 1e-6
+
+
+def test_fixed_full_step_on_blob_pair_loses_convexity():
+    f, g = W.blobs(64, W.seed_for(1, 0))
+    _, _, rep = ma.solve(f, g, tau=1.0, tol=1e-6, gmres_tol=0.1)
+    assert rep.status == ma.ENONCONVEX
+
+
+@pytest.mark.parametrize("bad", ["odd", "small", "tau", "tol", "neg", "nan"])
+def test_invalid_arguments_are_rejected(bad):
+    f = np.ones((16, 16))
+    g = np.ones((16, 16))
+    kw = dict(tau=1.0, tol=1e-6)
+    if bad == "odd":
+        f = g = np.ones((15, 15))
+    elif bad == "small":
+        f = g = np.ones((6, 6))
+    elif bad == "tau":
+        kw["tau"] = 0.5
+    elif bad == "tol":
+        kw["tol"] = 0.0
+    elif bad == "neg":
+        f = f.copy()
+        f[3, 3] = -1
+    elif bad == "nan":
+        g = g.copy()
+        g[0, 0] = np.nan
+    with pytest.raises(ValueError):
+        ma.solve(f, g, **kw)
+
+
+def test_linearisation_is_the_derivative_of_M():
+    # eq. (linearmaeq) is the directional derivative of M(u) = g(x + grad u) det(I + D^2 u).
+    # With an analytic g (the Section 5.1 form) and smooth u, theta, the central difference
+    # of f_n along theta must match L theta evaluated with the oracle's coefficients.
+    N = 64
+    al = 0.3
+
+    def g_an(y1, y2):
+        c1, c2 = np.cos(2 * np.pi * y1), np.cos(2 * np.pi * y2)
+        s1, s2 = np.sin(2 * np.pi * y1), np.sin(2 * np.pi * y2)
+        return 1 + al * c1 * c2, -2 * np.pi * al * s1 * c2, -2 * np.pi * al * c1 * s2
+
+    x = np.arange(N) / N
+    X1, X2 = np.meshgrid(x, x, indexing="ij")
+    prob = ma.Problem(np.ones((N, N)), np.ones((N, N)), g_analytic=g_an)
+    u = 0.01 * np.cos(2 * np.pi * X1) * np.sin(2 * np.pi * X2) + 0.004 * np.sin(2 * np.pi * (X1 - X2))
+    theta = np.sin(2 * np.pi * X1 + 0.3) * np.cos(2 * np.pi * X2) + 0.5 * np.sin(4 * np.pi * X2)
+    eps = 1e-6
+    dfn = (ma.evaluate(u + eps * theta, prob).fn - ma.evaluate(u - eps * theta, prob).fn) / (2 * eps)
+    ev = ma.evaluate(u, prob)
+    a11, a12, a22, b1, b2 = ma.coefficients(ev)
+    h = 1.0 / N
+    t1, t2, t11, t22, t12 = fd.derivatives(theta, h)
+    Ltheta = a11 * t11 + 2 * a12 * t12 + a22 * t22 + b1 * t1 + b2 * t2
+    assert np.max(np.abs(dfn - Ltheta)) < 1e-7 * np.max(np.abs(Ltheta))
