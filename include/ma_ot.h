@@ -1,0 +1,178 @@
+/*
+ * ma_ot.h -- C ABI of the MI355X damped-Newton Monge-Ampere optimal-transport solver.
+ *
+ * Method: Saumier, Agueh, Khouider, "An efficient numerical algorithm for the L2
+ * optimal transport problem with applications to image processing" (2010).
+ * For 1-periodic probability densities f, g on the unit torus the library solves
+ * the Monge-Ampere equation g(x + grad u) det(I + D^2 u) = f  (Section 3.1, eq. ma2)
+ * for the mean-zero periodic potential u with |x|^2/2 + u convex, by the damped
+ * Newton iteration of eq. (linma), each linear step solved by Strain's FFT method
+ * with restarted GMRES(m) (Section 4.2).  The optimal map is x + grad u
+ * (Theorem CE1 and Section 5.2).
+ *
+ * Conventions shared by every entry point
+ *   - Grids are N x N, h = 1/N, node (i, j) at (x1, x2) = (i h, j h)  (Section 4).
+ *     Arrays are row-major [i][j]: i indexes x1, j (contiguous) indexes x2.
+ *   - Field pointers are DEVICE pointers (HIP global memory) unless marked host.
+ *     The caller owns every pointer it passes; the library never frees them and
+ *     never writes to inputs.  Outputs are written on return codes >= 0.
+ *   - `stream` is a hipStream_t cast to void* (NULL = the default stream).  Calls
+ *     are stream-ordered; the solve entry points synchronise `stream` before they
+ *     return because their Newton loop reads per-pair status on the host.
+ *   - Supported N: even, 16 <= N <= 2048, N a multiple of 16, N = 2^a 3^b.
+ *   - Return codes: MA_OK (0); soft failures > 0 with the best iterate written;
+ *     hard failures < 0 with nothing written.  ma_strerror() names each code.
+ *   - One plan serves one stream at a time; plans are not thread-safe.
+ */
+#ifndef MA_OT_H
+#define MA_OT_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MA_OT_ABI_VERSION 1
+
+/* return / status codes */
+#define MA_OK 0           /* converged: rms residual <= tol                           */
+#define MA_ENOCONV 1      /* max Newton iterations, or step halving exhausted         */
+#define MA_ENONCONVEX 2   /* det(I + D^2 u) <= 0 or trace <= 0 at an iterate (Sec. 3.3) */
+#define MA_ENAN 3         /* a non-finite residual                                    */
+#define MA_EINVAL (-1)    /* bad argument: N, tau < 1, tol <= 0, density <= 0 or NaN  */
+#define MA_ENOMEM (-2)    /* device allocation failed                                 */
+#define MA_EHIP (-3)      /* a HIP runtime call failed                                */
+
+/* interpolation of g and grad g at x + grad u (Section 4) */
+#define MA_INTERP_BILINEAR 0
+#define MA_INTERP_NEAREST 1
+/* linear operator: full eq. (linearmaeq), or without the grad g term (Remarks, Sec. 3.3) */
+#define MA_OP_FULL 0
+#define MA_OP_NO_DRIFT 1
+/* damping: fixed tau (eq. linma); or halve the step (double tau) while the trial
+ * iterate is non-convex or does not lower the residual, relaxing tau back towards
+ * the caller's value after each accepted step.  Both keep tau >= 1. */
+#define MA_DAMP_FIXED 0
+#define MA_DAMP_BACKTRACK 1
+
+typedef struct ma_options {
+  int max_newton;          /* Newton iterations before MA_ENOCONV (100)              */
+  int gmres_m;             /* GMRES restart length m, 1..30 (10, Section 5.1)       */
+  int gmres_max_restarts;  /* restarts per linear solve (20)                         */
+  double gmres_tol;        /* relative residual of the linear solve (1e-4, Sec. 5.1) */
+  int interp;              /* MA_INTERP_*                                            */
+  int op_mode;             /* MA_OP_*                                                */
+  int damping_policy;      /* MA_DAMP_*                                              */
+  int max_backtrack;       /* step halvings per Newton step before failing (12)      */
+} ma_options;
+
+typedef struct ma_report {
+  int status;              /* MA_OK or a soft failure code                           */
+  int newton_iters;        /* Newton directions computed                             */
+  int gmres_iters;         /* GMRES inner iterations (operator applications)         */
+  int backtracks;          /* rejected trial steps (MA_DAMP_BACKTRACK)               */
+  double res_rms;          /* sqrt(mean (f - f~_n)^2) at the returned iterate        */
+  double res_max;          /* max |f - f~_n|                                         */
+  double res0_rms;         /* residual at the initial iterate                        */
+  double mass_defect;      /* mean(f_n) - 1 before the translation of eq. translation */
+  double min_det;          /* min det(I + D^2 u) at the returned iterate             */
+  double w2sq;             /* mean(|grad u|^2 f): the transport distance (Sec. 5.2)  */
+  double tau_final;        /* damping in force at exit                               */
+  double time_ms;          /* wall time of the call that produced this report        */
+} ma_report;
+
+typedef struct ma_plan ma_plan;
+
+/* ABI version compiled into the library (MA_OT_ABI_VERSION). */
+int ma_abi_version(void);
+
+/* Fills *opt with the defaults listed above. */
+void ma_options_default(ma_options* opt);
+
+/* Static string naming a return/status code. */
+const char* ma_strerror(int code);
+
+/* Creates a plan holding all device workspace for up to `batch_capacity` pairs of
+ * size up to `n_max` (workspace grows on demand past that).  `opt` may be NULL
+ * (defaults).  Returns MA_OK, MA_EINVAL or MA_ENOMEM; *out is NULL on failure. */
+int ma_plan_create(int n_max, int batch_capacity, const ma_options* opt, ma_plan** out);
+
+/* Releases the plan and its device memory.  NULL is allowed. */
+void ma_plan_destroy(ma_plan* plan);
+
+/* Replaces the plan's options (validated; MA_EINVAL leaves them unchanged). */
+int ma_plan_set_options(ma_plan* plan, const ma_options* opt);
+
+/* Solves one pair (Section 3.1 algorithm, Section 4.2 linear solver).
+ *   f, g    N*N FP64 densities, positive and finite; each is scaled to grid mean one.
+ *   damping tau >= 1 of eq. (linma).  tol > 0: stop when sqrt(mean r^2) <= tol.
+ *   psi0    N*N FP64 initial potential or NULL for u0 = 0; its mean is removed.
+ *   psi     N*N FP64 out: the mean-zero potential u.
+ *   map     2*N*N FP64 out: [0] = x1 + d1 u, [1] = x2 + d2 u (unwrapped, fourth-order
+ *           differences), or NULL.
+ *   rep     host out (may be NULL). */
+int ma_solve(ma_plan* plan, const double* f, const double* g, int n, double damping,
+             double tol, const double* psi0, double* psi, double* map, ma_report* rep,
+             void* stream);
+
+/* Solves `npairs` independent pairs, possibly of different sizes, together: every
+ * kernel launch serves all pairs of one grid size and each pair follows its own
+ * Newton / GMRES / step-halving state on the device.  All arrays of pointers are
+ * HOST arrays of `npairs` device pointers (psi0 may be NULL, or hold NULL entries;
+ * map may be NULL or hold NULL entries); n is a host array of sizes; reps a host
+ * array of npairs reports (may be NULL).  Returns the largest per-pair status
+ * (hard errors first). */
+int ma_solve_batched(ma_plan* plan, int npairs, const int* n, const double* const* f,
+                     const double* const* g, const double* const* psi0, double damping,
+                     double tol, double* const* psi, double* const* map, ma_report* reps,
+                     void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Single steps of the hot path, for verification and profiling.  They run the
+ * same kernels as the solver on one pair, using the plan's workspace, and are
+ * stream-ordered (no host synchronisation unless a host output is requested).
+ * ------------------------------------------------------------------------- */
+
+/* Section 4 + eq. (ma2), (translation), (linearmaeq): fourth-order derivatives of u,
+ * g and the grid gradient of g interpolated at x + grad u, f_n, the translated
+ * residual and the operator coefficients.
+ *   u, f, g   N*N FP64; f and g are used as given (no rescaling).
+ *   r         N*N FP32 out: r = f - f~_n.
+ *   coef      5*N*N FP32 out: planes a11, a12, a22, b1, b2 (op_mode applies).
+ *   scalars   host out, 12 doubles: res_rms, res_max, mass_defect, min_det,
+ *             min_trace, abar11, abar12, abar22, bbar1, bbar2 (Simpson means,
+ *             Section 4.2), w2 = mean(|grad u|^2 f), mean(u).  Synchronises. */
+int ma_step_residual(ma_plan* plan, int n, const double* u, const double* f,
+                     const double* g, float* r, float* coef, double* scalars, void* stream);
+
+/* Forward 2-D DFT of a real N*N FP32 field (the row and column FFT passes):
+ * spec is N*(N/2) complex FP32 (interleaved re, im).  For 1 <= s < N/2,
+ * spec[k1][s] = sum_{i,j} v[i][j] exp(-2 pi i (k1 i + s j)/N).  Slot s = 0 holds
+ * the column transform of the packed real row coefficients:
+ * spec[k1][0] = sum_i (X_i[0] + i X_i[N/2]) exp(-2 pi i k1 i/N), where
+ * X_i[k] = sum_j v[i][j] exp(-2 pi i k j/N). */
+int ma_step_fft2(ma_plan* plan, int n, const float* v, float* spec, void* stream);
+
+/* Strain's operator (Section 4.2): w = L Lbar^{-1} v with coefficient planes `coef`
+ * (5*N*N FP32, order a11, a12, a22, b1, b2) and host averages abar[5]. */
+int ma_step_strain_apply(ma_plan* plan, int n, const float* v, const float* coef,
+                         const double* abar, float* w, void* stream);
+
+/* theta = Lbar^{-1} sigma (Section 4.2): the mean-zero solution of the averaged
+ * operator, via rhobar(k). */
+int ma_step_lbar_inverse(ma_plan* plan, int n, const float* sigma, const double* abar,
+                         float* theta, void* stream);
+
+/* Restarted GMRES(m) on L Lbar^{-1} sigma = h (Section 4.2), zero start, stopping
+ * at ||h - A sigma|| <= tol ||h|| (estimated by the Givens rotations), followed by
+ * theta = Lbar^{-1} sigma: the linear step of one Newton iteration.  h, theta N*N
+ * FP32; coef 5*N*N FP32; abar host[5]; iters host out (operator applications).
+ * Synchronises. */
+int ma_step_gmres(ma_plan* plan, int n, const float* h, const float* coef,
+                  const double* abar, int m, double tol, int max_restarts, float* theta,
+                  int* iters, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MA_OT_H */

@@ -1,0 +1,152 @@
+// Device data structures shared by the kernels and the host driver.
+//
+// Every pair (f, g) being solved owns one PairDesc (pointers into the plan's
+// arena) and one PairState (its Newton / GMRES / step-halving state machine).
+// Kernels launched for a class of equal-size pairs take blockIdx.y as the index
+// into that class's list of pair ids.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define MA_MMAX 30        // largest GMRES restart length compiled in
+#define MA_RES_TX_MAX 64  // residual-kernel tile width (columns)
+#define MA_RES_TY 16      // residual-kernel tile height (rows)
+#define MA_NPART_RES 16   // partial sums per residual block
+#define MA_BLOCK 256
+
+// per-pair phase of the Newton loop
+enum : int {
+  PH_INIT = 0,       // nothing evaluated yet
+  PH_SOLVE = 1,      // a Newton direction is being computed this tick
+  PH_BACKTRACK = 2,  // the last trial was rejected: halve the step, evaluate again
+  PH_REVERT = 3,     // halving exhausted: undo the trial step, evaluate, stop
+  PH_DONE = 5,
+};
+
+// g, and the fourth-order grid gradient of g, interleaved for one 16-byte gather
+struct __align__(16) GS {
+  double g;
+  float g1, g2;
+};
+
+struct PairDesc {
+  int n;
+  int cls;  // index of the size class this pair belongs to
+  int nblk_res, nblk_rows;
+  // caller buffers
+  const double* f_in;
+  const double* g_in;
+  const double* psi0_in;
+  double* psi_out;
+  double* map_out;
+  // workspace
+  double* u;       // n*n   current iterate
+  double* f;       // n*n   f scaled to mean one
+  GS* gs;          // n*n   g scaled to mean one, with its gradient
+  float* coef;     // 5*n*n a11, a12, a22, b1, b2
+  float* r;        // n*n   f - f_n (the translation constant is added by its readers)
+  float* theta;    // n*n   last Newton correction
+  float* x;        // n*n   GMRES solution accumulated over restarts
+  float* V;        // (m+1)*n*n Krylov basis, stored unnormalised (see vscale)
+  float2* H;       // n*(n/2) half spectrum after the row pass
+  float2* T;       // 3*n*(n/2) column-pass outputs
+  double* part;    // per-block partial sums
+};
+
+struct PairState {
+  // --- Newton control -----------------------------------------------------
+  int phase, status;
+  int newton_iters, gmres_iters, backtracks, bt_step;
+  int valid;            // set by the set-up kernel: 1 = densities positive and finite
+  int pad0;
+  unsigned counter;     // last-block counter, reset by the last block
+  unsigned pad1;
+  double tau0, tau;     // caller's damping, damping in force
+  double tol;
+  double step;          // multiplier of theta applied to the current trial
+  double axpy;          // coefficient the next update kernel applies to theta
+  double res_rms, res_max, res0, res_prev, mass_c, min_det, min_tr, w2, mean_u;
+  double abar[5];
+  double mean_f, mean_g, mean_psi0;
+  // --- GMRES ----------------------------------------------------------------
+  int gm_running;       // an Arnoldi cycle is in progress
+  int gm_restart;       // the cycle ended short of the tolerance: restart
+  int gm_cycle;         // restarts done in this solve
+  int gm_k;             // basis size at the end of the cycle
+  double bnorm, gm_target;
+  double vscale[MA_MMAX + 1];       // v_l = vscale[l] * V[l]
+  double Hm[(MA_MMAX + 1) * MA_MMAX];  // Hessenberg, column-major: Hm[j*(MMAX+1)+i]
+  double cs[MA_MMAX], sn[MA_MMAX], gv[MA_MMAX + 1], y[MA_MMAX + 1], q[MA_MMAX + 1];
+};
+
+// parameters common to one launch (passed by value)
+struct LaunchCtx {
+  const PairDesc* desc;
+  PairState* st;
+  const int* pair_ids;  // pairs of this size class
+  int m;                // GMRES restart length
+  int max_newton, max_restarts, max_backtrack, damping_policy, interp, op_mode;
+  double gmres_tol;
+};
+
+__device__ inline int pair_of_block(const LaunchCtx& c) { return c.pair_ids[blockIdx.y]; }
+
+// ---------------------------------------------------------------------------
+// Block reductions (FP64), deterministic order.
+// ---------------------------------------------------------------------------
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ inline double wave_min(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ inline double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Reduces K values per thread across the block; result valid in thread 0 only.
+// kinds[k]: 0 = sum, 1 = min, 2 = max.  scratch: >= (blockDim/64) * K doubles of LDS.
+template <int K>
+__device__ inline void block_reduce(double (&v)[K], const int (&kinds)[K], double* scratch) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double t = v[k];
+    t = kinds[k] == 0 ? wave_sum(t) : (kinds[k] == 1 ? wave_min(t) : wave_max(t));
+    if (lane == 0) scratch[wid * K + k] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double t = scratch[k];
+      for (int w = 1; w < nw; ++w) {
+        double s = scratch[w * K + k];
+        t = kinds[k] == 0 ? t + s : (kinds[k] == 1 ? fmin(t, s) : fmax(t, s));
+      }
+      v[k] = t;
+    }
+  }
+  __syncthreads();
+}
+
+// Publishes this block's partials and reports whether it is the last block of the
+// pair to finish; the last block then sees every block's partials.
+__device__ inline bool publish_and_check_last(unsigned* counter, unsigned nblocks) {
+  __shared__ int is_last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned prev = atomicAdd(counter, 1u);
+    is_last = (prev == nblocks - 1);
+  }
+  __syncthreads();
+  if (is_last) __threadfence();
+  return is_last != 0;
+}

@@ -1,0 +1,163 @@
+// Mixed-radix (2, 3, 4, 8) self-sorting Stockham FFT on data resident in LDS.
+//
+// A block runs NF independent length-N complex transforms that sit in LDS.
+// LAYOUT_ROWS:  element e of transform t at lds[t * N + e]   (row FFTs)
+// LAYOUT_COLS:  element e of transform t at lds[e * NF + t]  (column FFTs; the
+//               transform index varies fastest so neighbouring lanes hit
+//               neighbouring LDS words)
+// Stage with radix R after sub-length Ns (Ns = product of earlier radices): the
+// butterfly j reads x[j + r N/R], r < R, multiplies by w^(r (j mod Ns)) with
+// w = exp(-+2 pi i / (Ns R)), runs a length-R DFT and writes
+// x[(j / Ns) Ns R + (j mod Ns) + r Ns].  The output is in natural order.
+// Twiddles come from a table tw[m] = exp(-2 pi i m / N) built on the host in FP64.
+#pragma once
+#include <hip/hip_runtime.h>
+
+enum { LAYOUT_ROWS = 0, LAYOUT_COLS = 1 };
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+// multiply by -i (forward) or +i (inverse)
+template <bool INV>
+__device__ __forceinline__ float2 rot90(float2 a) {
+  return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft2(float2& a, float2& b) {
+  float2 t = a;
+  a = cadd(t, b);
+  b = csub(t, b);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft3(float2& a, float2& b, float2& c) {
+  const float s3 = 0.86602540378443864676f;  // sin(pi/3)
+  float2 t1 = cadd(b, c);
+  float2 t2 = make_float2(a.x - 0.5f * t1.x, a.y - 0.5f * t1.y);
+  float2 d = csub(b, c);
+  // (b - c) * (-+ i sqrt(3)/2)
+  float2 t3 = rot90<INV>(make_float2(d.x * s3, d.y * s3));
+  a = cadd(a, t1);
+  b = cadd(t2, t3);
+  c = csub(t2, t3);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft4(float2& v0, float2& v1, float2& v2, float2& v3) {
+  float2 t0 = cadd(v0, v2), t1 = csub(v0, v2);
+  float2 t2 = cadd(v1, v3), t3 = rot90<INV>(csub(v1, v3));
+  v0 = cadd(t0, t2);
+  v2 = csub(t0, t2);
+  v1 = cadd(t1, t3);
+  v3 = csub(t1, t3);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft8(float2 (&v)[8]) {
+  const float r2 = 0.70710678118654752440f;
+  float2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  float2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+  dft4<INV>(e0, e1, e2, e3);
+  dft4<INV>(o0, o1, o2, o3);
+  // o_k *= w8^k, w8 = exp(-+ 2 pi i / 8)
+  o1 = INV ? make_float2(r2 * (o1.x - o1.y), r2 * (o1.x + o1.y))
+           : make_float2(r2 * (o1.x + o1.y), r2 * (o1.y - o1.x));
+  o2 = rot90<INV>(o2);
+  o3 = INV ? make_float2(-r2 * (o3.x + o3.y), r2 * (o3.x - o3.y))
+           : make_float2(r2 * (o3.y - o3.x), -r2 * (o3.x + o3.y));
+  v[0] = cadd(e0, o0);
+  v[4] = csub(e0, o0);
+  v[1] = cadd(e1, o1);
+  v[5] = csub(e1, o1);
+  v[2] = cadd(e2, o2);
+  v[6] = csub(e2, o2);
+  v[3] = cadd(e3, o3);
+  v[7] = csub(e3, o3);
+}
+
+template <int R, bool INV>
+__device__ __forceinline__ void dft(float2 (&v)[R]) {
+  if constexpr (R == 2) dft2<INV>(v[0], v[1]);
+  else if constexpr (R == 3) dft3<INV>(v[0], v[1], v[2]);
+  else if constexpr (R == 4) dft4<INV>(v[0], v[1], v[2], v[3]);
+  else dft8<INV>(v);
+}
+
+// radix used for the remaining length REM: a factor 3 first, then eights, with
+// sixteen split as 4 x 4 and leftovers as 4 or 2
+__host__ __device__ constexpr int pick_radix(int rem) {
+  return (rem % 3 == 0) ? 3 : (rem == 16 ? 4 : (rem % 8 == 0 ? 8 : (rem % 4 == 0 ? 4 : 2)));
+}
+
+template <int N, int NF, int LAYOUT>
+__device__ __forceinline__ int lds_index(int t, int e) {
+  if constexpr (LAYOUT == LAYOUT_ROWS) return t * N + e;
+  else return e * NF + t;
+}
+
+template <int N, int NS, int R, int NF, int BLOCK, bool INV, int LAYOUT>
+__device__ __forceinline__ void fft_stage(float2* lds, const float2* __restrict__ tw) {
+  constexpr int NB = N / R;                  // butterflies per transform
+  constexpr int ITEMS = NF * NB;
+  constexpr int PER = (ITEMS + BLOCK - 1) / BLOCK;
+  constexpr int TWS = N / (NS * R);          // twiddle stride in the length-N table
+  float2 v[PER][R];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int it = threadIdx.x + q * BLOCK;
+    if (ITEMS % BLOCK == 0 || it < ITEMS) {
+      int t, j;
+      if constexpr (LAYOUT == LAYOUT_ROWS) { t = it / NB; j = it % NB; }
+      else { t = it % NF; j = it / NF; }
+      const int k = j % NS;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        float2 x = lds[lds_index<N, NF, LAYOUT>(t, j + r * NB)];
+        if (NS > 1 && r > 0) {
+          float2 w = tw[k * r * TWS];  // k r < NS R, so the index is below N
+          if (INV) w.y = -w.y;
+          x = cmul(x, w);
+        }
+        v[q][r] = x;
+      }
+      dft<R, INV>(v[q]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int it = threadIdx.x + q * BLOCK;
+    if (ITEMS % BLOCK == 0 || it < ITEMS) {
+      int t, j;
+      if constexpr (LAYOUT == LAYOUT_ROWS) { t = it / NB; j = it % NB; }
+      else { t = it % NF; j = it / NF; }
+      const int k = j % NS;
+      const int base = (j / NS) * NS * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[lds_index<N, NF, LAYOUT>(t, base + r * NS)] = v[q][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <int N, int NS, int NF, int BLOCK, bool INV, int LAYOUT>
+__device__ __forceinline__ void fft_stages(float2* lds, const float2* __restrict__ tw) {
+  if constexpr (NS < N) {
+    constexpr int R = pick_radix(N / NS);
+    fft_stage<N, NS, R, NF, BLOCK, INV, LAYOUT>(lds, tw);
+    fft_stages<N, NS * R, NF, BLOCK, INV, LAYOUT>(lds, tw);
+  }
+}
+
+// In-place transforms of NF sequences in LDS.  Caller synchronises before (data
+// written) — the routine ends with a barrier so results are visible on return.
+template <int N, int NF, int BLOCK, bool INV, int LAYOUT>
+__device__ __forceinline__ void fft_lds(float2* lds, const float2* __restrict__ tw) {
+  fft_stages<N, 1, NF, BLOCK, INV, LAYOUT>(lds, tw);
+}

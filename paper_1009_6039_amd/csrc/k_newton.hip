@@ -1,0 +1,425 @@
+// FP64 kernels of the Newton loop: set-up, the fused residual / coefficient
+// kernel and its per-pair decision logic, the step-halving update and the outputs.
+//
+// Section 3.1 (eq. ma2, linearmaeq, linma) and Section 4 (fourth-order differences,
+// interpolation of g, eq. translation) of Saumier, Agueh, Khouider.
+#include "common.h"
+#include "ma_ot.h"
+#include "kernels.h"
+
+// ---------------------------------------------------------------------------
+// Set-up: means of f, g, psi0 and the validity of the densities.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(MA_BLOCK) void k_setup_sums(LaunchCtx c, int nblk) {
+  const int p = pair_of_block(c);
+  const PairDesc& d = c.desc[p];
+  PairState& s = c.st[p];
+  const long nn = (long)d.n * d.n;
+  double sf = 0, sg = 0, sp = 0, bad = 0;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (long)nblk * blockDim.x) {
+    double fv = d.f_in[e], gv = d.g_in[e];
+    sf += fv;
+    sg += gv;
+    if (!(fv > 0.0) || !(gv > 0.0) || !isfinite(fv) || !isfinite(gv)) bad += 1.0;
+    if (d.psi0_in) {
+      double pv = d.psi0_in[e];
+      sp += pv;
+      if (!isfinite(pv)) bad += 1.0;
+    }
+  }
+  __shared__ double scratch[(MA_BLOCK / 64) * 4];
+  double v[4] = {sf, sg, sp, bad};
+  const int kinds[4] = {0, 0, 0, 0};
+  block_reduce<4>(v, kinds, scratch);
+  double* part = d.part;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 4; ++k) part[blockIdx.x * 4 + k] = v[k];
+  if (publish_and_check_last(&s.counter, nblk)) {
+    if (threadIdx.x == 0) {
+      double t[4] = {0, 0, 0, 0};
+      for (int b = 0; b < nblk; ++b)
+        for (int k = 0; k < 4; ++k) t[k] += part[b * 4 + k];
+      s.mean_f = t[0] / (double)nn;
+      s.mean_g = t[1] / (double)nn;
+      s.mean_psi0 = t[2] / (double)nn;
+      s.valid = (t[3] == 0.0) && isfinite(t[0]) && isfinite(t[1]) && isfinite(t[2]);
+      s.counter = 0;
+    }
+  }
+}
+
+// f and g scaled to mean one (reading P1), the fourth-order grid gradient of g
+// (reading P5) and the initial iterate u0 = psi0 - mean(psi0) or 0.
+__global__ __launch_bounds__(MA_BLOCK) void k_setup_fields(LaunchCtx c) {
+  const int p = pair_of_block(c);
+  const PairDesc& d = c.desc[p];
+  const PairState& s = c.st[p];
+  const int n = d.n;
+  const long nn = (long)n * n;
+  const double inv_f = 1.0 / s.mean_f, inv_g = 1.0 / s.mean_g;
+  const double inv12h = (double)n / 12.0;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (long)gridDim.x * blockDim.x) {
+    const int i = (int)(e / n), j = (int)(e % n);
+    const int im1 = (i + n - 1) % n, im2 = (i + n - 2) % n, ip1 = (i + 1) % n, ip2 = (i + 2) % n;
+    const int jm1 = (j + n - 1) % n, jm2 = (j + n - 2) % n, jp1 = (j + 1) % n, jp2 = (j + 2) % n;
+    const double* g = d.g_in;
+    double g1 = (g[(long)im2 * n + j] - 8.0 * g[(long)im1 * n + j] + 8.0 * g[(long)ip1 * n + j] -
+                 g[(long)ip2 * n + j]) * inv12h * inv_g;
+    double g2 = (g[(long)i * n + jm2] - 8.0 * g[(long)i * n + jm1] + 8.0 * g[(long)i * n + jp1] -
+                 g[(long)i * n + jp2]) * inv12h * inv_g;
+    GS v;
+    v.g = g[e] * inv_g;
+    v.g1 = (float)g1;
+    v.g2 = (float)g2;
+    d.gs[e] = v;
+    d.f[e] = d.f_in[e] * inv_f;
+    d.u[e] = d.psi0_in ? d.psi0_in[e] - s.mean_psi0 : 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Per-pair Newton decisions, run by one thread after a residual evaluation.
+// ---------------------------------------------------------------------------
+// tot: sum fn, sum r, sum r^2, Simpson sums of a11 a12 a22 b1 b2, sum |grad u|^2 f,
+//      sum u, min det, min trace, max r, min r, count of non-finite values
+__device__ static void newton_decide(PairState& s, const LaunchCtx& c, int n, const double* tot) {
+  const double NN = (double)n * n;
+  const double cst = tot[0] / NN - 1.0;  // mean(f_n) - 1: the translation of eq. (translation)
+  const double ss = tot[2] + 2.0 * cst * tot[1] + NN * cst * cst;  // sum (r_raw + cst)^2
+  const double res = sqrt(fmax(ss, 0.0) / NN);
+  const bool finite = tot[14] == 0.0 && isfinite(res);
+  const bool convex = finite && tot[10] > 0.0 && tot[11] > 0.0;
+  const int ph = s.phase;
+
+  if (ph == PH_REVERT) {  // the restored iterate: record it and stop (status already set)
+    s.res_rms = res;
+    s.res_max = fmax(fabs(tot[12] + cst), fabs(tot[13] + cst));
+    s.mass_c = cst;
+    s.min_det = tot[10];
+    s.w2 = tot[8] / NN;
+    s.mean_u = tot[9] / NN;
+    s.phase = PH_DONE;
+    return;
+  }
+  const bool trial = (ph == PH_SOLVE || ph == PH_BACKTRACK);
+  if (trial && c.damping_policy == MA_DAMP_BACKTRACK) {
+    const bool accept = convex && res < s.res_prev;
+    if (!accept) {
+      s.backtracks++;
+      s.bt_step++;
+      s.tau *= 2.0;
+      if (s.bt_step > c.max_backtrack) {  // give up: restore the last accepted iterate
+        s.status = MA_ENOCONV;
+        s.phase = PH_REVERT;
+        s.axpy = -s.step;
+      } else {
+        s.phase = PH_BACKTRACK;
+        s.axpy = -0.5 * s.step;
+        s.step *= 0.5;
+      }
+      return;
+    }
+    s.tau = fmax(s.tau0, 0.5 * s.tau);
+  }
+  // the evaluation is accepted: record it
+  s.res_rms = res;
+  s.res_max = fmax(fabs(tot[12] + cst), fabs(tot[13] + cst));
+  s.mass_c = cst;
+  s.min_det = tot[10];
+  s.min_tr = tot[11];
+  s.w2 = tot[8] / NN;
+  s.mean_u = tot[9] / NN;
+  for (int k = 0; k < 5; ++k) s.abar[k] = tot[3 + k];
+  if (ph == PH_INIT) s.res0 = res;
+  if (!finite) {
+    s.status = MA_ENAN;
+    s.phase = PH_DONE;
+  } else if (!convex) {
+    s.status = MA_ENONCONVEX;
+    s.phase = PH_DONE;
+  } else if (res <= s.tol) {
+    s.status = MA_OK;
+    s.phase = PH_DONE;
+  } else if (s.newton_iters >= c.max_newton) {
+    s.status = MA_ENOCONV;
+    s.phase = PH_DONE;
+  } else {
+    // next Newton direction: GMRES on L Lbar^{-1} sigma = r / tau (Section 4.2)
+    s.phase = PH_SOLVE;
+    s.newton_iters++;
+    s.res_prev = res;
+    s.bt_step = 0;
+    s.step = 1.0;
+    s.bnorm = sqrt(fmax(ss, 0.0)) / s.tau;
+    s.gm_target = c.gmres_tol * s.bnorm;
+    s.gm_running = s.bnorm > 0.0;
+    s.gm_restart = 0;
+    s.gm_cycle = 0;
+    s.gm_k = 0;
+    s.vscale[0] = s.bnorm > 0.0 ? 1.0 / s.bnorm : 0.0;
+    s.gv[0] = s.bnorm;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fused residual + coefficient kernel (one Newton evaluation).
+// Tile: TX columns x MA_RES_TY rows per block, halo 2 staged in LDS (FP64).
+// ---------------------------------------------------------------------------
+template <int TX>
+__global__ __launch_bounds__(MA_BLOCK) void k_residual(LaunchCtx c, int step_mode) {
+  const int p = pair_of_block(c);
+  const PairDesc& d = c.desc[p];
+  PairState& s = c.st[p];
+  if (s.phase == PH_DONE) return;
+  constexpr int TY = MA_RES_TY;
+  constexpr int LW = TX + 4;
+  __shared__ double tile[(TY + 4) * LW];
+  __shared__ double scratch[(MA_BLOCK / 64) * MA_NPART_RES];
+  const int n = d.n;
+  const int nbx = n / TX;
+  const int i0 = (blockIdx.x / nbx) * TY, j0 = (blockIdx.x % nbx) * TX;
+  const double* __restrict__ u = d.u;
+  for (int e = threadIdx.x; e < (TY + 4) * LW; e += MA_BLOCK) {
+    const int li = e / LW, lj = e % LW;
+    const int gi = (i0 + li - 2 + n) % n, gj = (j0 + lj - 2 + n) % n;
+    tile[e] = u[(long)gi * n + gj];
+  }
+  __syncthreads();
+
+  const double N = (double)n;
+  const double i12h = N / 12.0, i12h2 = N * N / 12.0, i144h2 = N * N / 144.0;
+  const double wnorm = 1.0 / (9.0 * N * N);
+  double acc[MA_NPART_RES];
+  for (int k = 0; k < 10; ++k) acc[k] = 0.0;
+  acc[10] = 1e300;   // min det
+  acc[11] = 1e300;   // min trace
+  acc[12] = -1e300;  // max r
+  acc[13] = 1e300;   // min r
+  acc[14] = 0.0;     // non-finite count
+  acc[15] = 0.0;
+  const GS* __restrict__ gs = d.gs;
+  const long nn = (long)n * n;
+  constexpr int TROWS = MA_BLOCK / TX;
+  const int tx = threadIdx.x % TX, ty0 = threadIdx.x / TX;
+  for (int ty = ty0; ty < TY; ty += TROWS) {
+    const int li = ty + 2, lj = tx + 2;
+    const int i = i0 + ty, j = j0 + tx;
+#define U(a, b) tile[(li + (a)) * LW + lj + (b)]
+    const double u1 = (U(-2, 0) - 8.0 * U(-1, 0) + 8.0 * U(1, 0) - U(2, 0)) * i12h;
+    const double u2 = (U(0, -2) - 8.0 * U(0, -1) + 8.0 * U(0, 1) - U(0, 2)) * i12h;
+    const double u11 = (-U(-2, 0) + 16.0 * U(-1, 0) - 30.0 * U(0, 0) + 16.0 * U(1, 0) - U(2, 0)) * i12h2;
+    const double u22 = (-U(0, -2) + 16.0 * U(0, -1) - 30.0 * U(0, 0) + 16.0 * U(0, 1) - U(0, 2)) * i12h2;
+    double q[5];
+#pragma unroll
+    for (int a = -2; a <= 2; ++a)
+      q[a + 2] = (a == 0) ? 0.0 : (U(a, -2) - 8.0 * U(a, -1) + 8.0 * U(a, 1) - U(a, 2));
+    const double u12 = (q[0] - 8.0 * q[1] + 8.0 * q[3] - q[4]) * i144h2;
+#undef U
+    // g and grad g at y = x + grad u (Section 4), periodic
+    // a diverging iterate must not produce a wild gather index (it is flagged below)
+    double t1 = (double)i + N * u1, t2 = (double)j + N * u2;
+    if (!(fabs(t1) < 1e15)) t1 = 0.0;
+    if (!(fabs(t2) < 1e15)) t2 = 0.0;
+    double gy, gy1, gy2;
+    if (c.interp == MA_INTERP_NEAREST) {
+      long a = (long)floor(t1 + 0.5), b = (long)floor(t2 + 0.5);
+      a %= n; if (a < 0) a += n;
+      b %= n; if (b < 0) b += n;
+      GS v = gs[a * n + b];
+      gy = v.g; gy1 = v.g1; gy2 = v.g2;
+    } else {
+      const double f1 = floor(t1), f2 = floor(t2);
+      const double wa = t1 - f1, wb = t2 - f2;
+      long a = (long)f1 % n, b = (long)f2 % n;
+      if (a < 0) a += n;
+      if (b < 0) b += n;
+      const long a1 = (a + 1 == n) ? 0 : a + 1, b1 = (b + 1 == n) ? 0 : b + 1;
+      const GS v00 = gs[a * n + b], v10 = gs[a1 * n + b], v01 = gs[a * n + b1], v11 = gs[a1 * n + b1];
+      const double w00 = (1 - wa) * (1 - wb), w10 = wa * (1 - wb), w01 = (1 - wa) * wb, w11 = wa * wb;
+      gy = w00 * v00.g + w10 * v10.g + w01 * v01.g + w11 * v11.g;
+      gy1 = w00 * v00.g1 + w10 * v10.g1 + w01 * v01.g1 + w11 * v11.g1;
+      gy2 = w00 * v00.g2 + w10 * v10.g2 + w01 * v01.g2 + w11 * v11.g2;
+    }
+    const double det = (1.0 + u11) * (1.0 + u22) - u12 * u12;
+    const double fn = gy * det;
+    const long e = (long)i * n + j;
+    const double fv = d.f[e];
+    const double rr = fv - fn;
+    const double a11 = gy * (1.0 + u22), a22 = gy * (1.0 + u11), a12 = -gy * u12;
+    const double b1 = c.op_mode == MA_OP_NO_DRIFT ? 0.0 : det * gy1;
+    const double b2 = c.op_mode == MA_OP_NO_DRIFT ? 0.0 : det * gy2;
+    d.r[e] = (float)rr;
+    d.coef[e] = (float)a11;
+    d.coef[nn + e] = (float)a12;
+    d.coef[2 * nn + e] = (float)a22;
+    d.coef[3 * nn + e] = (float)b1;
+    d.coef[4 * nn + e] = (float)b2;
+    // periodic Simpson weights (reading P7): 2h/3 at even nodes, 4h/3 at odd ones
+    const double w = (double)((i & 1) ? 4 : 2) * (double)((j & 1) ? 4 : 2) * wnorm;
+    acc[0] += fn;
+    acc[1] += rr;
+    acc[2] += rr * rr;
+    acc[3] += w * a11;
+    acc[4] += w * a12;
+    acc[5] += w * a22;
+    acc[6] += w * b1;
+    acc[7] += w * b2;
+    acc[8] += (u1 * u1 + u2 * u2) * fv;
+    acc[9] += tile[li * LW + lj];
+    acc[10] = fmin(acc[10], det);
+    acc[11] = fmin(acc[11], 2.0 + u11 + u22);
+    acc[12] = fmax(acc[12], rr);
+    acc[13] = fmin(acc[13], rr);
+    if (!isfinite(rr) || !isfinite(det)) acc[14] += 1.0;
+  }
+  const int kinds[MA_NPART_RES] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 2, 1, 0, 0};
+  block_reduce<MA_NPART_RES>(acc, kinds, scratch);
+  const int nblk = gridDim.x;
+  double* part = d.part;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < MA_NPART_RES; ++k) part[(long)blockIdx.x * MA_NPART_RES + k] = acc[k];
+  if (publish_and_check_last(&s.counter, nblk)) {
+    // every thread folds a strided subset of blocks, then a fixed-order block reduction
+    double t[MA_NPART_RES];
+    for (int k = 0; k < MA_NPART_RES; ++k) t[k] = (kinds[k] == 1) ? 1e300 : (kinds[k] == 2 ? -1e300 : 0.0);
+    for (int b = threadIdx.x; b < nblk; b += MA_BLOCK) {
+      const volatile double* pb = part + (long)b * MA_NPART_RES;
+      for (int k = 0; k < MA_NPART_RES; ++k) {
+        double v = pb[k];
+        t[k] = kinds[k] == 0 ? t[k] + v : (kinds[k] == 1 ? fmin(t[k], v) : fmax(t[k], v));
+      }
+    }
+    block_reduce<MA_NPART_RES>(t, kinds, scratch);
+    if (threadIdx.x == 0) {
+      if (step_mode) {
+        // single-step use: record the evaluation only
+        const double NN = (double)n * n;
+        const double cst = t[0] / NN - 1.0;
+        const double ss = t[2] + 2.0 * cst * t[1] + NN * cst * cst;
+        s.res_rms = sqrt(fmax(ss, 0.0) / NN);
+        s.res_max = fmax(fabs(t[12] + cst), fabs(t[13] + cst));
+        s.mass_c = cst;
+        s.min_det = t[10];
+        s.min_tr = t[11];
+        s.w2 = t[8] / NN;
+        s.mean_u = t[9] / NN;
+        for (int k = 0; k < 5; ++k) s.abar[k] = t[3 + k];
+      } else {
+        newton_decide(s, c, n, t);
+      }
+      s.counter = 0;
+    }
+  }
+}
+
+// r + translation constant, as FP32, for the single-step entry point
+__global__ __launch_bounds__(MA_BLOCK) void k_residual_shift(LaunchCtx c, float* out) {
+  const int p = pair_of_block(c);
+  const PairDesc& d = c.desc[p];
+  const float cst = (float)c.st[p].mass_c;
+  const long nn = (long)d.n * d.n;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (long)gridDim.x * blockDim.x)
+    out[e] = d.r[e] + cst;
+}
+
+// u += axpy * theta for pairs halving a rejected step or restoring the last iterate
+__global__ __launch_bounds__(MA_BLOCK) void k_step_update(LaunchCtx c) {
+  const int p = pair_of_block(c);
+  const PairDesc& d = c.desc[p];
+  const PairState& s = c.st[p];
+  if (s.phase != PH_BACKTRACK && s.phase != PH_REVERT) return;
+  const double a = s.axpy;
+  const long nn = (long)d.n * d.n;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (long)gridDim.x * blockDim.x)
+    d.u[e] += a * (double)d.theta[e];
+}
+
+// psi = u - mean(u); map = x + D_h u (fourth-order differences), unwrapped
+__global__ __launch_bounds__(MA_BLOCK) void k_outputs(LaunchCtx c) {
+  const int p = pair_of_block(c);
+  const PairDesc& d = c.desc[p];
+  const PairState& s = c.st[p];
+  const int n = d.n;
+  const long nn = (long)n * n;
+  const double mu = s.mean_u, i12h = (double)n / 12.0, h = 1.0 / (double)n;
+  const double* u = d.u;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (long)gridDim.x * blockDim.x) {
+    const int i = (int)(e / n), j = (int)(e % n);
+    d.psi_out[e] = u[e] - mu;
+    if (d.map_out) {
+      const int im1 = (i + n - 1) % n, im2 = (i + n - 2) % n, ip1 = (i + 1) % n, ip2 = (i + 2) % n;
+      const int jm1 = (j + n - 1) % n, jm2 = (j + n - 2) % n, jp1 = (j + 1) % n, jp2 = (j + 2) % n;
+      const double u1 = (u[(long)im2 * n + j] - 8.0 * u[(long)im1 * n + j] + 8.0 * u[(long)ip1 * n + j] -
+                         u[(long)ip2 * n + j]) * i12h;
+      const double u2 = (u[(long)i * n + jm2] - 8.0 * u[(long)i * n + jm1] + 8.0 * u[(long)i * n + jp1] -
+                         u[(long)i * n + jp2]) * i12h;
+      d.map_out[e] = (double)i * h + u1;
+      d.map_out[nn + e] = (double)j * h + u2;
+    }
+  }
+}
+
+// counts pairs per phase and pending restarts for the host loop
+__global__ void k_summary(const PairState* st, const int* ids, int npairs, int* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int restart = 0, invalid = 0;
+  for (int q = 0; q < npairs; ++q) {
+    const PairState& s = st[ids[q]];
+    cnt[s.phase]++;
+    if (s.phase == PH_SOLVE && s.gm_restart) restart++;
+    if (!s.valid) invalid++;
+  }
+  for (int k = 0; k < 6; ++k) out[k] = cnt[k];
+  out[6] = restart;
+  out[7] = invalid;
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+void launch_setup_fields(const LaunchCtx& c, int n, int npairs, hipStream_t st) {
+  int nb2 = (int)((long)n * n / (MA_BLOCK * 4));
+  nb2 = nb2 < 1 ? 1 : (nb2 > 4096 ? 4096 : nb2);
+  hipLaunchKernelGGL(k_setup_fields, dim3(nb2, npairs), dim3(MA_BLOCK), 0, st, c);
+}
+
+void launch_setup(const LaunchCtx& c, int n, int npairs, hipStream_t st) {
+  int nblk = (int)((long)n * n / 4096);
+  nblk = nblk < 1 ? 1 : (nblk > 256 ? 256 : nblk);
+  hipLaunchKernelGGL(k_setup_sums, dim3(nblk, npairs), dim3(MA_BLOCK), 0, st, c, nblk);
+  launch_setup_fields(c, n, npairs, st);
+}
+
+int residual_tile_x(int n) { return (n % 64 == 0) ? 64 : ((n % 32 == 0) ? 32 : 16); }
+
+int residual_blocks(int n) { return (n / residual_tile_x(n)) * (n / MA_RES_TY); }
+
+void launch_residual(const LaunchCtx& c, int n, int npairs, int step_mode, hipStream_t st) {
+  const int tx = residual_tile_x(n);
+  dim3 grid(residual_blocks(n), npairs);
+  if (tx == 64) hipLaunchKernelGGL(k_residual<64>, grid, dim3(MA_BLOCK), 0, st, c, step_mode);
+  else if (tx == 32) hipLaunchKernelGGL(k_residual<32>, grid, dim3(MA_BLOCK), 0, st, c, step_mode);
+  else hipLaunchKernelGGL(k_residual<16>, grid, dim3(MA_BLOCK), 0, st, c, step_mode);
+}
+
+static int elementwise_blocks(int n) {
+  long b = (long)n * n / (MA_BLOCK * 4);
+  return b < 1 ? 1 : (int)(b > 4096 ? 4096 : b);
+}
+
+void launch_residual_shift(const LaunchCtx& c, int n, float* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_residual_shift, dim3(elementwise_blocks(n), 1), dim3(MA_BLOCK), 0, st, c, out);
+}
+
+void launch_step_update(const LaunchCtx& c, int n, int npairs, hipStream_t st) {
+  hipLaunchKernelGGL(k_step_update, dim3(elementwise_blocks(n), npairs), dim3(MA_BLOCK), 0, st, c);
+}
+
+void launch_outputs(const LaunchCtx& c, int n, int npairs, hipStream_t st) {
+  hipLaunchKernelGGL(k_outputs, dim3(elementwise_blocks(n), npairs), dim3(MA_BLOCK), 0, st, c);
+}
+
+void launch_summary(const PairState* s, const int* ids, int npairs, int* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_summary, dim3(1), dim3(64), 0, st, s, ids, npairs, out);
+}

@@ -1,0 +1,33 @@
+// Host-side launchers of the device kernels (one call per size class).
+#pragma once
+#include "common.h"
+
+// pass modes
+enum : int {
+  PA_INIT = 0,     // v0 = (r + translation) / tau, stored as V[0]
+  PA_PLAIN = 1,    // V[0] as written by the restart kernel
+  PA_ARNOLDI = 2,  // Gram-Schmidt update of V[jn] against V[0..jn-1]
+  PA_RECOVER = 3,  // sigma = x + sum y_l v_l
+  PA_STEP = 4,     // V[0] as given (single-step entry points)
+};
+enum : int { PB_MATVEC = 0, PB_RECOVER = 1, PB_FORWARD = 2 };
+enum : int { PC_MATVEC = 0, PC_RECOVER = 1, PC_THETA_ONLY = 2 };
+
+void launch_setup(const LaunchCtx& c, int n, int npairs, hipStream_t st);
+void launch_setup_fields(const LaunchCtx& c, int n, int npairs, hipStream_t st);
+int residual_tile_x(int n);
+int residual_blocks(int n);
+void launch_residual(const LaunchCtx& c, int n, int npairs, int step_mode, hipStream_t st);
+void launch_residual_shift(const LaunchCtx& c, int n, float* out, hipStream_t st);
+void launch_step_update(const LaunchCtx& c, int n, int npairs, hipStream_t st);
+void launch_outputs(const LaunchCtx& c, int n, int npairs, hipStream_t st);
+void launch_summary(const PairState* s, const int* ids, int npairs, int* out, hipStream_t st);
+
+// FFT passes and GMRES kernels; `tw` is the length-n twiddle table
+bool fft_size_supported(int n);
+int passA_blocks(int n);
+int passC_blocks(int n);
+void launch_passA(const LaunchCtx& c, int n, int npairs, int mode, int jn, const float2* tw, hipStream_t st);
+void launch_passB(const LaunchCtx& c, int n, int npairs, int mode, int j, const float2* tw, hipStream_t st);
+void launch_passC(const LaunchCtx& c, int n, int npairs, int mode, int j, const float2* tw, hipStream_t st);
+void launch_restart(const LaunchCtx& c, int n, int npairs, hipStream_t st);

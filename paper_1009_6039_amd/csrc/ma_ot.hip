@@ -1,0 +1,587 @@
+// C ABI and host driver of the solver: plans, workspace arena, the per-tick
+// launch sequence of the damped Newton loop (eq. linma) with its GMRES(m) linear
+// solves (Section 4.2), and the single-step entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <vector>
+
+#include "common.h"
+#include "kernels.h"
+#include "ma_ot.h"
+
+namespace {
+
+#define HIP_TRY(x)                          \
+  do {                                      \
+    if ((x) != hipSuccess) return MA_EHIP;  \
+  } while (0)
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+struct Class {
+  int n;
+  std::vector<int> ids;
+  int* d_ids = nullptr;  // slice of the plan's id buffer
+  const float2* tw = nullptr;
+};
+
+}  // namespace
+
+struct ma_plan {
+  ma_options opt;
+  int n_max = 0, cap = 0;
+  char* arena = nullptr;
+  size_t arena_bytes = 0;
+  PairDesc* d_desc = nullptr;
+  PairState* d_state = nullptr;
+  int* d_ids = nullptr;
+  int pairs_cap = 0;
+  int* d_summary = nullptr;
+  int* h_summary = nullptr;
+  std::map<int, float2*> tw;
+  std::vector<PairDesc> h_desc;
+  std::vector<PairState> h_state;
+};
+
+namespace {
+
+size_t part_doubles(int n) {
+  size_t a = (size_t)residual_blocks(n) * MA_NPART_RES;
+  size_t b = (size_t)passC_blocks(n) * (MA_MMAX + 1);
+  size_t c = (size_t)passA_blocks(n) + 16;
+  size_t d = 256 * 4;
+  return std::max(std::max(a, b), std::max(c, d));
+}
+
+size_t pair_bytes(int n, int m) {
+  const size_t nn = (size_t)n * n;
+  size_t b = 0;
+  b += align256(8 * nn) * 2;              // u, f
+  b += align256(16 * nn);                 // gs
+  b += align256(20 * nn);                 // coef
+  b += align256(4 * nn) * 3;              // r, theta, x
+  b += align256(4 * nn * (size_t)(m + 1));  // V
+  b += align256(4 * nn);                  // H
+  b += align256(12 * nn);                 // T
+  b += align256(8 * part_doubles(n));     // partials
+  return b;
+}
+
+void carve(PairDesc& d, char*& p, int n, int m) {
+  const size_t nn = (size_t)n * n;
+  auto take = [&](size_t bytes) {
+    char* q = p;
+    p += align256(bytes);
+    return q;
+  };
+  d.n = n;
+  d.u = (double*)take(8 * nn);
+  d.f = (double*)take(8 * nn);
+  d.gs = (GS*)take(16 * nn);
+  d.coef = (float*)take(20 * nn);
+  d.r = (float*)take(4 * nn);
+  d.theta = (float*)take(4 * nn);
+  d.x = (float*)take(4 * nn);
+  d.V = (float*)take(4 * nn * (size_t)(m + 1));
+  d.H = (float2*)take(4 * nn);
+  d.T = (float2*)take(12 * nn);
+  d.part = (double*)take(8 * part_doubles(n));
+  d.nblk_res = residual_blocks(n);
+  d.nblk_rows = passA_blocks(n);
+}
+
+bool n_ok(int n) { return n >= 16 && n <= 2048 && n % 16 == 0 && fft_size_supported(n); }
+
+int validate_options(const ma_options& o) {
+  if (o.max_newton < 0 || o.gmres_m < 1 || o.gmres_m > MA_MMAX || o.gmres_max_restarts < 0 ||
+      !(o.gmres_tol > 0.0) || (o.interp != MA_INTERP_BILINEAR && o.interp != MA_INTERP_NEAREST) ||
+      (o.op_mode != MA_OP_FULL && o.op_mode != MA_OP_NO_DRIFT) ||
+      (o.damping_policy != MA_DAMP_FIXED && o.damping_policy != MA_DAMP_BACKTRACK) || o.max_backtrack < 0)
+    return MA_EINVAL;
+  return MA_OK;
+}
+
+int ensure_twiddles(ma_plan* P, int n) {
+  if (P->tw.count(n)) return MA_OK;
+  std::vector<float2> h(n);
+  for (int m = 0; m < n; ++m) {
+    const double a = -2.0 * M_PI * (double)m / (double)n;
+    h[m] = make_float2((float)std::cos(a), (float)std::sin(a));
+  }
+  float2* d = nullptr;
+  if (hipMalloc(&d, sizeof(float2) * n) != hipSuccess) return MA_ENOMEM;
+  if (hipMemcpy(d, h.data(), sizeof(float2) * n, hipMemcpyHostToDevice) != hipSuccess) {
+    hipFree(d);
+    return MA_EHIP;
+  }
+  P->tw[n] = d;
+  return MA_OK;
+}
+
+// workspace for `ns` pairs; descriptors carved in order
+int ensure_workspace(ma_plan* P, const std::vector<int>& ns) {
+  const int m = P->opt.gmres_m;
+  size_t need = 0;
+  for (int n : ns) need += pair_bytes(n, m);
+  if (need > P->arena_bytes) {
+    if (P->arena) hipFree(P->arena);
+    P->arena = nullptr;
+    P->arena_bytes = 0;
+    if (hipMalloc(&P->arena, need) != hipSuccess) return MA_ENOMEM;
+    P->arena_bytes = need;
+  }
+  const int np = (int)ns.size();
+  if (np > P->pairs_cap) {
+    if (P->d_desc) hipFree(P->d_desc);
+    if (P->d_state) hipFree(P->d_state);
+    if (P->d_ids) hipFree(P->d_ids);
+    P->d_desc = nullptr;
+    P->d_state = nullptr;
+    P->d_ids = nullptr;
+    P->pairs_cap = 0;
+    if (hipMalloc(&P->d_desc, sizeof(PairDesc) * np) != hipSuccess) return MA_ENOMEM;
+    if (hipMalloc(&P->d_state, sizeof(PairState) * np) != hipSuccess) return MA_ENOMEM;
+    if (hipMalloc(&P->d_ids, sizeof(int) * np) != hipSuccess) return MA_ENOMEM;
+    P->pairs_cap = np;
+  }
+  P->h_desc.assign(np, PairDesc{});
+  char* p = P->arena;
+  for (int q = 0; q < np; ++q) carve(P->h_desc[q], p, ns[q], P->opt.gmres_m);
+  for (int n : ns) {
+    int e = ensure_twiddles(P, n);
+    if (e) return e;
+  }
+  return MA_OK;
+}
+
+LaunchCtx make_ctx(const ma_plan* P, const int* d_ids) {
+  LaunchCtx c;
+  c.desc = P->d_desc;
+  c.st = P->d_state;
+  c.pair_ids = d_ids;
+  c.m = P->opt.gmres_m;
+  c.max_newton = P->opt.max_newton;
+  c.max_restarts = P->opt.gmres_max_restarts;
+  c.max_backtrack = P->opt.max_backtrack;
+  c.damping_policy = P->opt.damping_policy;
+  c.interp = P->opt.interp;
+  c.op_mode = P->opt.op_mode;
+  c.gmres_tol = P->opt.gmres_tol;
+  return c;
+}
+
+PairState fresh_state(double tau, double tol) {
+  PairState s;
+  std::memset(&s, 0, sizeof(s));
+  s.phase = PH_INIT;
+  s.status = MA_ENOCONV;
+  s.tau0 = tau;
+  s.tau = tau;
+  s.tol = tol;
+  s.step = 1.0;
+  s.mean_f = s.mean_g = 1.0;
+  return s;
+}
+
+// groups pairs by size; uploads id lists
+int build_classes(ma_plan* P, const std::vector<int>& ns, std::vector<Class>& cls, hipStream_t st) {
+  std::map<int, std::vector<int>> by;
+  for (int q = 0; q < (int)ns.size(); ++q) by[ns[q]].push_back(q);
+  std::vector<int> flat;
+  for (auto& kv : by) {
+    Class c;
+    c.n = kv.first;
+    c.ids = kv.second;
+    c.tw = P->tw[c.n];
+    c.d_ids = P->d_ids + flat.size();
+    flat.insert(flat.end(), kv.second.begin(), kv.second.end());
+    cls.push_back(c);
+  }
+  HIP_TRY(hipMemcpyAsync(P->d_ids, flat.data(), sizeof(int) * flat.size(), hipMemcpyHostToDevice, st));
+  return MA_OK;
+}
+
+int read_summary(ma_plan* P, int npairs, hipStream_t st) {
+  launch_summary(P->d_state, P->d_ids, npairs, P->d_summary, st);
+  HIP_TRY(hipMemcpyAsync(P->h_summary, P->d_summary, sizeof(int) * 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return MA_OK;
+}
+
+void launch_cycle_body(const ma_plan* P, const std::vector<Class>& cls, hipStream_t st) {
+  const int m = P->opt.gmres_m;
+  for (int j = 0; j < m; ++j)
+    for (const Class& c : cls) {
+      LaunchCtx x = make_ctx(P, c.d_ids);
+      const int np = (int)c.ids.size();
+      launch_passB(x, c.n, np, PB_MATVEC, j, c.tw, st);
+      launch_passC(x, c.n, np, PC_MATVEC, j, c.tw, st);
+      launch_passA(x, c.n, np, PA_ARNOLDI, j + 1, c.tw, st);
+    }
+}
+
+// the whole damped Newton loop for the pairs already described in P->h_desc
+int run_solver(ma_plan* P, int npairs, double damping, double tol, hipStream_t st, std::vector<Class>& cls) {
+  HIP_TRY(hipMemcpyAsync(P->d_desc, P->h_desc.data(), sizeof(PairDesc) * npairs, hipMemcpyHostToDevice, st));
+  P->h_state.assign(npairs, fresh_state(damping, tol));
+  HIP_TRY(hipMemcpyAsync(P->d_state, P->h_state.data(), sizeof(PairState) * npairs, hipMemcpyHostToDevice, st));
+  for (const Class& c : cls) launch_setup(make_ctx(P, c.d_ids), c.n, (int)c.ids.size(), st);
+  int e = read_summary(P, npairs, st);
+  if (e) return e;
+  if (P->h_summary[7] > 0) return MA_EINVAL;
+
+  const long max_ticks = (long)(P->opt.max_newton + 1) * (P->opt.max_backtrack + 3) + 8;
+  for (long tick = 0; tick < max_ticks; ++tick) {
+    for (const Class& c : cls) launch_residual(make_ctx(P, c.d_ids), c.n, (int)c.ids.size(), 0, st);
+    e = read_summary(P, npairs, st);
+    if (e) return e;
+    const int n_solve = P->h_summary[PH_SOLVE];
+    const int n_update = P->h_summary[PH_BACKTRACK] + P->h_summary[PH_REVERT];
+    if (n_solve == 0 && n_update == 0) break;  // every pair is done
+    if (n_solve > 0) {
+      for (const Class& c : cls)
+        launch_passA(make_ctx(P, c.d_ids), c.n, (int)c.ids.size(), PA_INIT, 0, c.tw, st);
+      launch_cycle_body(P, cls, st);
+      for (int cyc = 0; cyc < P->opt.gmres_max_restarts; ++cyc) {
+        e = read_summary(P, npairs, st);
+        if (e) return e;
+        if (P->h_summary[6] == 0) break;
+        for (const Class& c : cls) {
+          LaunchCtx x = make_ctx(P, c.d_ids);
+          launch_restart(x, c.n, (int)c.ids.size(), st);
+          launch_passA(x, c.n, (int)c.ids.size(), PA_PLAIN, 0, c.tw, st);
+        }
+        launch_cycle_body(P, cls, st);
+      }
+      for (const Class& c : cls) {
+        LaunchCtx x = make_ctx(P, c.d_ids);
+        const int np = (int)c.ids.size();
+        launch_passA(x, c.n, np, PA_RECOVER, 0, c.tw, st);
+        launch_passB(x, c.n, np, PB_RECOVER, 0, c.tw, st);
+        launch_passC(x, c.n, np, PC_RECOVER, 0, c.tw, st);
+      }
+    }
+    if (n_update > 0)
+      for (const Class& c : cls) launch_step_update(make_ctx(P, c.d_ids), c.n, (int)c.ids.size(), st);
+  }
+  for (const Class& c : cls) launch_outputs(make_ctx(P, c.d_ids), c.n, (int)c.ids.size(), st);
+  HIP_TRY(hipMemcpyAsync(P->h_state.data(), P->d_state, sizeof(PairState) * npairs, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return MA_OK;
+}
+
+void fill_report(const PairState& s, ma_report* r, double ms) {
+  r->status = s.phase == PH_DONE ? s.status : MA_ENOCONV;
+  r->newton_iters = s.newton_iters;
+  r->gmres_iters = s.gmres_iters;
+  r->backtracks = s.backtracks;
+  r->res_rms = s.res_rms;
+  r->res_max = s.res_max;
+  r->res0_rms = s.res0;
+  r->mass_defect = s.mass_c;
+  r->min_det = s.min_det;
+  r->w2sq = s.w2;
+  r->tau_final = s.tau;
+  r->time_ms = ms;
+}
+
+// one-pair workspace for the step entry points; state copied from `s`
+int step_prepare(ma_plan* P, int n, const PairState& s, hipStream_t st, Class& c) {
+  if (!n_ok(n)) return MA_EINVAL;
+  std::vector<int> ns(1, n);
+  int e = ensure_workspace(P, ns);
+  if (e) return e;
+  std::vector<Class> cls;
+  e = build_classes(P, ns, cls, st);
+  if (e) return e;
+  c = cls[0];
+  HIP_TRY(hipMemcpyAsync(P->d_desc, P->h_desc.data(), sizeof(PairDesc), hipMemcpyHostToDevice, st));
+  P->h_state.assign(1, s);
+  HIP_TRY(hipMemcpyAsync(P->d_state, P->h_state.data(), sizeof(PairState), hipMemcpyHostToDevice, st));
+  return MA_OK;
+}
+
+PairState step_state(const double* abar) {
+  PairState s = fresh_state(1.0, 1.0);
+  s.phase = PH_SOLVE;
+  s.gm_running = 1;
+  s.vscale[0] = 1.0;
+  if (abar)
+    for (int k = 0; k < 5; ++k) s.abar[k] = abar[k];
+  return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ma_abi_version(void) { return MA_OT_ABI_VERSION; }
+
+void ma_options_default(ma_options* o) {
+  if (!o) return;
+  o->max_newton = 100;
+  o->gmres_m = 10;
+  o->gmres_max_restarts = 20;
+  o->gmres_tol = 1e-4;
+  o->interp = MA_INTERP_BILINEAR;
+  o->op_mode = MA_OP_FULL;
+  o->damping_policy = MA_DAMP_FIXED;
+  o->max_backtrack = 12;
+}
+
+const char* ma_strerror(int code) {
+  switch (code) {
+    case MA_OK: return "converged";
+    case MA_ENOCONV: return "no convergence within the iteration limits";
+    case MA_ENONCONVEX: return "iterate lost convexity (det or trace of I + D^2 u not positive)";
+    case MA_ENAN: return "non-finite residual";
+    case MA_EINVAL: return "invalid argument";
+    case MA_ENOMEM: return "device allocation failed";
+    case MA_EHIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+int ma_plan_create(int n_max, int batch_capacity, const ma_options* opt, ma_plan** out) {
+  if (!out) return MA_EINVAL;
+  *out = nullptr;
+  if (!n_ok(n_max) || batch_capacity < 1) return MA_EINVAL;
+  ma_plan* P = new ma_plan();
+  if (opt) P->opt = *opt;
+  else ma_options_default(&P->opt);
+  if (validate_options(P->opt)) {
+    delete P;
+    return MA_EINVAL;
+  }
+  P->n_max = n_max;
+  P->cap = batch_capacity;
+  if (hipMalloc(&P->d_summary, sizeof(int) * 8) != hipSuccess ||
+      hipHostMalloc(&P->h_summary, sizeof(int) * 8, hipHostMallocDefault) != hipSuccess) {
+    ma_plan_destroy(P);
+    return MA_ENOMEM;
+  }
+  std::vector<int> ns(batch_capacity, n_max);
+  int e = ensure_workspace(P, ns);
+  if (e) {
+    ma_plan_destroy(P);
+    return e;
+  }
+  *out = P;
+  return MA_OK;
+}
+
+void ma_plan_destroy(ma_plan* P) {
+  if (!P) return;
+  if (P->arena) hipFree(P->arena);
+  if (P->d_desc) hipFree(P->d_desc);
+  if (P->d_state) hipFree(P->d_state);
+  if (P->d_ids) hipFree(P->d_ids);
+  if (P->d_summary) hipFree(P->d_summary);
+  if (P->h_summary) hipHostFree(P->h_summary);
+  for (auto& kv : P->tw) hipFree(kv.second);
+  delete P;
+}
+
+int ma_plan_set_options(ma_plan* P, const ma_options* opt) {
+  if (!P || !opt || validate_options(*opt)) return MA_EINVAL;
+  P->opt = *opt;
+  return MA_OK;
+}
+
+int ma_solve_batched(ma_plan* P, int npairs, const int* n, const double* const* f, const double* const* g,
+                     const double* const* psi0, double damping, double tol, double* const* psi,
+                     double* const* map, ma_report* reps, void* stream) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!P || npairs < 1 || !n || !f || !g || !psi || !(damping >= 1.0) || !(tol > 0.0)) return MA_EINVAL;
+  std::vector<int> ns(n, n + npairs);
+  for (int q = 0; q < npairs; ++q)
+    if (!n_ok(ns[q]) || !f[q] || !g[q] || !psi[q]) return MA_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  int e = ensure_workspace(P, ns);
+  if (e) return e;
+  for (int q = 0; q < npairs; ++q) {
+    PairDesc& d = P->h_desc[q];
+    d.f_in = f[q];
+    d.g_in = g[q];
+    d.psi0_in = psi0 ? psi0[q] : nullptr;
+    d.psi_out = psi[q];
+    d.map_out = map ? map[q] : nullptr;
+  }
+  std::vector<Class> cls;
+  e = build_classes(P, ns, cls, st);
+  if (e) return e;
+  e = run_solver(P, npairs, damping, tol, st, cls);
+  if (e) return e;
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  int worst = MA_OK;
+  for (int q = 0; q < npairs; ++q) {
+    ma_report r;
+    fill_report(P->h_state[q], &r, ms);
+    if (reps) reps[q] = r;
+    worst = std::max(worst, r.status);
+  }
+  return worst;
+}
+
+int ma_solve(ma_plan* P, const double* f, const double* g, int n, double damping, double tol,
+             const double* psi0, double* psi, double* map, ma_report* rep, void* stream) {
+  const double* fa[1] = {f};
+  const double* ga[1] = {g};
+  const double* pa[1] = {psi0};
+  double* oa[1] = {psi};
+  double* ma[1] = {map};
+  return ma_solve_batched(P, 1, &n, fa, ga, pa, damping, tol, oa, ma, rep, stream);
+}
+
+int ma_step_residual(ma_plan* P, int n, const double* u, const double* f, const double* g, float* r,
+                     float* coef, double* scalars, void* stream) {
+  if (!P || !u || !f || !g) return MA_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  Class c;
+  int e = step_prepare(P, n, fresh_state(1.0, 1.0), st, c);
+  if (e) return e;
+  PairDesc& d = P->h_desc[0];
+  d.f_in = f;
+  d.g_in = g;
+  d.psi0_in = u;  // u0 = u - 0: the state's means are 1 and 0, so f and g are used as given
+  HIP_TRY(hipMemcpyAsync(P->d_desc, P->h_desc.data(), sizeof(PairDesc), hipMemcpyHostToDevice, st));
+  LaunchCtx x = make_ctx(P, c.d_ids);
+  launch_setup_fields(x, n, 1, st);
+  launch_residual(x, n, 1, 1, st);
+  if (r) launch_residual_shift(x, n, r, st);
+  if (coef) HIP_TRY(hipMemcpyAsync(coef, d.coef, 20 * (size_t)n * n, hipMemcpyDeviceToDevice, st));
+  if (scalars) {
+    HIP_TRY(hipMemcpyAsync(P->h_state.data(), P->d_state, sizeof(PairState), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const PairState& q = P->h_state[0];
+    const double v[12] = {q.res_rms, q.res_max, q.mass_c, q.min_det, q.min_tr, q.abar[0],
+                          q.abar[1], q.abar[2], q.abar[3], q.abar[4], q.w2, q.mean_u};
+    std::memcpy(scalars, v, sizeof(v));
+  }
+  return MA_OK;
+}
+
+int ma_step_fft2(ma_plan* P, int n, const float* v, float* spec, void* stream) {
+  if (!P || !v || !spec) return MA_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  Class c;
+  int e = step_prepare(P, n, step_state(nullptr), st, c);
+  if (e) return e;
+  const PairDesc& d = P->h_desc[0];
+  HIP_TRY(hipMemcpyAsync(d.V, v, 4 * (size_t)n * n, hipMemcpyDeviceToDevice, st));
+  LaunchCtx x = make_ctx(P, c.d_ids);
+  launch_passA(x, n, 1, PA_STEP, 0, c.tw, st);
+  launch_passB(x, n, 1, PB_FORWARD, 0, c.tw, st);
+  HIP_TRY(hipMemcpyAsync(spec, d.T, 4 * (size_t)n * n, hipMemcpyDeviceToDevice, st));
+  return MA_OK;
+}
+
+int ma_step_strain_apply(ma_plan* P, int n, const float* v, const float* coef, const double* abar, float* w,
+                         void* stream) {
+  if (!P || !v || !coef || !abar || !w) return MA_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  Class c;
+  int e = step_prepare(P, n, step_state(abar), st, c);
+  if (e) return e;
+  const PairDesc& d = P->h_desc[0];
+  const size_t nn = (size_t)n * n;
+  HIP_TRY(hipMemcpyAsync(d.V, v, 4 * nn, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(hipMemcpyAsync(d.coef, coef, 20 * nn, hipMemcpyDeviceToDevice, st));
+  LaunchCtx x = make_ctx(P, c.d_ids);
+  launch_passA(x, n, 1, PA_STEP, 0, c.tw, st);
+  launch_passB(x, n, 1, PB_MATVEC, 0, c.tw, st);
+  launch_passC(x, n, 1, PC_MATVEC, 0, c.tw, st);
+  HIP_TRY(hipMemcpyAsync(w, d.V + nn, 4 * nn, hipMemcpyDeviceToDevice, st));
+  return MA_OK;
+}
+
+int ma_step_lbar_inverse(ma_plan* P, int n, const float* sigma, const double* abar, float* theta,
+                         void* stream) {
+  if (!P || !sigma || !abar || !theta) return MA_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  Class c;
+  int e = step_prepare(P, n, step_state(abar), st, c);
+  if (e) return e;
+  const PairDesc& d = P->h_desc[0];
+  const size_t nn = (size_t)n * n;
+  HIP_TRY(hipMemcpyAsync(d.V, sigma, 4 * nn, hipMemcpyDeviceToDevice, st));
+  LaunchCtx x = make_ctx(P, c.d_ids);
+  launch_passA(x, n, 1, PA_STEP, 0, c.tw, st);
+  launch_passB(x, n, 1, PB_RECOVER, 0, c.tw, st);
+  launch_passC(x, n, 1, PC_THETA_ONLY, 0, c.tw, st);
+  HIP_TRY(hipMemcpyAsync(theta, d.theta, 4 * nn, hipMemcpyDeviceToDevice, st));
+  return MA_OK;
+}
+
+int ma_step_gmres(ma_plan* P, int n, const float* h, const float* coef, const double* abar, int m, double tol,
+                  int max_restarts, float* theta, int* iters, void* stream) {
+  if (!P || !h || !coef || !abar || !theta || m < 1 || m > MA_MMAX || !(tol > 0.0) || max_restarts < 0)
+    return MA_EINVAL;
+  if (!n_ok(n)) return MA_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const size_t nn = (size_t)n * n;
+  std::vector<float> hh(nn);
+  HIP_TRY(hipMemcpyAsync(hh.data(), h, 4 * nn, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  double b2 = 0.0;
+  for (float v : hh) b2 += (double)v * v;
+  const double bn = std::sqrt(b2);
+  ma_options saved = P->opt;
+  P->opt.gmres_m = m;
+  P->opt.gmres_max_restarts = max_restarts;
+  P->opt.gmres_tol = tol;
+  PairState s = step_state(abar);
+  s.bnorm = bn;
+  s.gm_target = tol * bn;
+  s.gm_running = bn > 0.0;
+  s.vscale[0] = bn > 0.0 ? 1.0 / bn : 0.0;
+  s.gv[0] = bn;
+  s.mass_c = 0.0;
+  Class c;
+  int e = step_prepare(P, n, s, st, c);
+  if (e) {
+    P->opt = saved;
+    return e;
+  }
+  const PairDesc& d = P->h_desc[0];
+  std::vector<Class> cls(1, c);
+  int rc = MA_OK;
+  do {
+    if (hipMemcpyAsync(d.r, h, 4 * nn, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(d.coef, coef, 20 * nn, hipMemcpyDeviceToDevice, st) != hipSuccess) {
+      rc = MA_EHIP;
+      break;
+    }
+    LaunchCtx x = make_ctx(P, c.d_ids);
+    launch_passA(x, n, 1, PA_INIT, 0, c.tw, st);
+    launch_cycle_body(P, cls, st);
+    for (int cyc = 0; cyc < max_restarts; ++cyc) {
+      if ((rc = read_summary(P, 1, st))) break;
+      if (P->h_summary[6] == 0) break;
+      launch_restart(x, n, 1, st);
+      launch_passA(x, n, 1, PA_PLAIN, 0, c.tw, st);
+      launch_cycle_body(P, cls, st);
+    }
+    if (rc) break;
+    launch_passA(x, n, 1, PA_RECOVER, 0, c.tw, st);
+    launch_passB(x, n, 1, PB_RECOVER, 0, c.tw, st);
+    launch_passC(x, n, 1, PC_THETA_ONLY, 0, c.tw, st);
+    if (hipMemcpyAsync(theta, d.theta, 4 * nn, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(P->h_state.data(), P->d_state, sizeof(PairState), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+      rc = MA_EHIP;
+      break;
+    }
+    if (iters) *iters = P->h_state[0].gmres_iters;
+  } while (0);
+  P->opt = saved;
+  return rc;
+}
+
+}  // extern "C"

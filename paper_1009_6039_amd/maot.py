@@ -1,0 +1,252 @@
+"""Python binding of libmaot.so (ctypes): argument marshalling only.
+
+Every step of the solver runs in the library's HIP kernels.  Tensors are torch
+CUDA (HIP) tensors, float64 for densities and potentials, float32 for the
+single-step fields; they are passed to the C ABI as device pointers together with
+the current torch stream.  The library must be built (``paper_1009_6039_amd.build``);
+importing this module fails loudly if it is not.
+"""
+
+import ctypes
+import os
+
+import torch
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmaot.so")
+
+OK, ENOCONV, ENONCONVEX, ENAN = 0, 1, 2, 3
+EINVAL, ENOMEM, EHIP = -1, -2, -3
+INTERP = {"bilinear": 0, "nearest": 1}
+OP_MODE = {"full": 0, "no_drift": 1}
+DAMPING = {"fixed": 0, "backtrack": 1}
+
+EXPORTED = ("ma_abi_version", "ma_options_default", "ma_strerror", "ma_plan_create",
+            "ma_plan_destroy", "ma_plan_set_options", "ma_solve", "ma_solve_batched",
+            "ma_step_residual", "ma_step_fft2", "ma_step_strain_apply",
+            "ma_step_lbar_inverse", "ma_step_gmres")
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("max_newton", ctypes.c_int), ("gmres_m", ctypes.c_int),
+                ("gmres_max_restarts", ctypes.c_int), ("gmres_tol", ctypes.c_double),
+                ("interp", ctypes.c_int), ("op_mode", ctypes.c_int),
+                ("damping_policy", ctypes.c_int), ("max_backtrack", ctypes.c_int)]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("newton_iters", ctypes.c_int),
+                ("gmres_iters", ctypes.c_int), ("backtracks", ctypes.c_int),
+                ("res_rms", ctypes.c_double), ("res_max", ctypes.c_double),
+                ("res0_rms", ctypes.c_double), ("mass_defect", ctypes.c_double),
+                ("min_det", ctypes.c_double), ("w2sq", ctypes.c_double),
+                ("tau_final", ctypes.c_double), ("time_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_lib = None
+
+
+def load():
+    """Loads libmaot.so once; raises if it is missing (no fallback path exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libmaot.so is not built: run python -m paper_1009_6039_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    I, D = ctypes.c_int, ctypes.c_double
+    lib.ma_abi_version.restype = I
+    lib.ma_options_default.argtypes = [ctypes.POINTER(Options)]
+    lib.ma_strerror.restype = ctypes.c_char_p
+    lib.ma_strerror.argtypes = [I]
+    lib.ma_plan_create.argtypes = [I, I, ctypes.POINTER(Options), ctypes.POINTER(P)]
+    lib.ma_plan_destroy.argtypes = [P]
+    lib.ma_plan_set_options.argtypes = [P, ctypes.POINTER(Options)]
+    lib.ma_solve.argtypes = [P, P, P, I, D, D, P, P, P, ctypes.POINTER(Report), P]
+    lib.ma_solve_batched.argtypes = [P, I, ctypes.POINTER(I), ctypes.POINTER(P), ctypes.POINTER(P),
+                                     ctypes.POINTER(P), D, D, ctypes.POINTER(P), ctypes.POINTER(P),
+                                     ctypes.POINTER(Report), P]
+    lib.ma_step_residual.argtypes = [P, I, P, P, P, P, P, ctypes.POINTER(D), P]
+    lib.ma_step_fft2.argtypes = [P, I, P, P, P]
+    lib.ma_step_strain_apply.argtypes = [P, I, P, P, ctypes.POINTER(D), P, P]
+    lib.ma_step_lbar_inverse.argtypes = [P, I, P, ctypes.POINTER(D), P, P]
+    lib.ma_step_gmres.argtypes = [P, I, P, P, ctypes.POINTER(D), I, D, I, P, ctypes.POINTER(I), P]
+    for name in EXPORTED:
+        getattr(lib, name).restype = getattr(lib, name).restype or I
+    lib.ma_plan_destroy.restype = None
+    lib.ma_options_default.restype = None
+    _lib = lib
+    return lib
+
+
+def strerror(code):
+    return load().ma_strerror(int(code)).decode()
+
+
+class MAError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__("%s: %s (%d)" % (what, strerror(code), code))
+        self.code = code
+
+
+def _check(code, what):
+    if code < 0:
+        raise MAError(code, what)
+    return code
+
+
+def make_options(**kw):
+    o = Options()
+    load().ma_options_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if k == "interp":
+            v = INTERP[v] if isinstance(v, str) else v
+        elif k == "op_mode":
+            v = OP_MODE[v] if isinstance(v, str) else v
+        elif k == "damping_policy":
+            v = DAMPING[v] if isinstance(v, str) else v
+        if not hasattr(o, k):
+            raise TypeError("unknown option %r" % k)
+        setattr(o, k, v)
+    return o
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, dtype):
+    if t is None:
+        return None
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise TypeError("expected a contiguous %s CUDA tensor" % dtype)
+    return t
+
+
+class Plan:
+    """Owns one ma_plan (device workspace, options)."""
+
+    def __init__(self, n_max=512, batch_capacity=1, **opts):
+        lib = load()
+        self.options = make_options(**opts)
+        h = ctypes.c_void_p()
+        _check(lib.ma_plan_create(int(n_max), int(batch_capacity), ctypes.byref(self.options),
+                                  ctypes.byref(h)), "ma_plan_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load().ma_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_options(self, **opts):
+        self.options = make_options(**opts)
+        _check(load().ma_plan_set_options(self._h, ctypes.byref(self.options)), "ma_plan_set_options")
+
+    # -- full solves ------------------------------------------------------------
+    def solve(self, f, g, damping=1.0, tol=1e-6, psi0=None, want_map=True):
+        f = _dev(f, torch.float64)
+        g = _dev(g, torch.float64)
+        psi0 = _dev(psi0, torch.float64)
+        n = f.shape[0]
+        psi = torch.empty_like(f)
+        mp = torch.empty((2, n, n), dtype=torch.float64, device=f.device) if want_map else None
+        rep = Report()
+        code = load().ma_solve(self._h, _ptr(f), _ptr(g), n, float(damping), float(tol), _ptr(psi0),
+                               _ptr(psi), _ptr(mp), ctypes.byref(rep), _stream())
+        _check(code, "ma_solve")
+        return psi, mp, rep.as_dict()
+
+    def solve_batched(self, fs, gs, damping=1.0, tol=1e-6, psi0s=None, want_map=False):
+        npairs = len(fs)
+        ns = (ctypes.c_int * npairs)(*[int(f.shape[0]) for f in fs])
+        fs = [_dev(f, torch.float64) for f in fs]
+        gs = [_dev(g, torch.float64) for g in gs]
+        psis = [torch.empty_like(f) for f in fs]
+        maps = [torch.empty((2,) + tuple(f.shape), dtype=torch.float64, device=f.device)
+                for f in fs] if want_map else None
+        arr = ctypes.c_void_p * npairs
+        fa = arr(*[t.data_ptr() for t in fs])
+        ga = arr(*[t.data_ptr() for t in gs])
+        pa = arr(*[(_dev(t, torch.float64).data_ptr() if t is not None else 0) for t in psi0s]) \
+            if psi0s is not None else None
+        oa = arr(*[t.data_ptr() for t in psis])
+        ma_ = arr(*[t.data_ptr() for t in maps]) if maps is not None else None
+        reps = (Report * npairs)()
+        code = load().ma_solve_batched(self._h, npairs, ns, fa, ga, pa, float(damping), float(tol),
+                                       oa, ma_, reps, _stream())
+        _check(code, "ma_solve_batched")
+        return psis, maps, [r.as_dict() for r in reps]
+
+    # -- single steps -------------------------------------------------------------
+    def step_residual(self, u, f, g):
+        u, f, g = (_dev(t, torch.float64) for t in (u, f, g))
+        n = u.shape[0]
+        r = torch.empty((n, n), dtype=torch.float32, device=u.device)
+        coef = torch.empty((5, n, n), dtype=torch.float32, device=u.device)
+        sc = (ctypes.c_double * 12)()
+        _check(load().ma_step_residual(self._h, n, _ptr(u), _ptr(f), _ptr(g), _ptr(r), _ptr(coef),
+                                       sc, _stream()), "ma_step_residual")
+        names = ("res_rms", "res_max", "mass_defect", "min_det", "min_trace", "abar11", "abar12",
+                 "abar22", "bbar1", "bbar2", "w2", "mean_u")
+        return r, coef, dict(zip(names, list(sc)))
+
+    def step_fft2(self, v):
+        v = _dev(v, torch.float32)
+        n = v.shape[0]
+        spec = torch.empty((n, n // 2, 2), dtype=torch.float32, device=v.device)
+        _check(load().ma_step_fft2(self._h, n, _ptr(v), _ptr(spec), _stream()), "ma_step_fft2")
+        return torch.view_as_complex(spec)
+
+    def step_strain_apply(self, v, coef, abar):
+        v = _dev(v, torch.float32)
+        coef = _dev(coef, torch.float32)
+        n = v.shape[0]
+        w = torch.empty_like(v)
+        ab = (ctypes.c_double * 5)(*[float(a) for a in abar])
+        _check(load().ma_step_strain_apply(self._h, n, _ptr(v), _ptr(coef), ab, _ptr(w), _stream()),
+               "ma_step_strain_apply")
+        return w
+
+    def step_lbar_inverse(self, sigma, abar):
+        sigma = _dev(sigma, torch.float32)
+        n = sigma.shape[0]
+        theta = torch.empty_like(sigma)
+        ab = (ctypes.c_double * 5)(*[float(a) for a in abar])
+        _check(load().ma_step_lbar_inverse(self._h, n, _ptr(sigma), ab, _ptr(theta), _stream()),
+               "ma_step_lbar_inverse")
+        return theta
+
+    def step_gmres(self, h, coef, abar, m=10, tol=1e-4, max_restarts=20):
+        h = _dev(h, torch.float32)
+        coef = _dev(coef, torch.float32)
+        n = h.shape[0]
+        theta = torch.empty_like(h)
+        ab = (ctypes.c_double * 5)(*[float(a) for a in abar])
+        its = ctypes.c_int(0)
+        _check(load().ma_step_gmres(self._h, n, _ptr(h), _ptr(coef), ab, int(m), float(tol),
+                                    int(max_restarts), _ptr(theta), ctypes.byref(its), _stream()),
+               "ma_step_gmres")
+        return theta, its.value
+
+
+def solve(f, g, damping=1.0, tol=1e-6, psi0=None, **opts):
+    """One-shot solve: returns (psi, map, report) for CUDA float64 tensors f, g."""
+    plan = Plan(n_max=f.shape[0], batch_capacity=1, **opts)
+    try:
+        return plan.solve(f, g, damping=damping, tol=tol, psi0=psi0)
+    finally:
+        plan.close()

@@ -1,0 +1,73 @@
+"""The C ABI library loads and exports every symbol include/ma_ot.h declares (no GPU calls)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ma_ot.h")
+LIB = os.path.join(ROOT, "paper_1009_6039_amd", "libmaot.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ma_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libmaot.so is not built (python -m paper_1009_6039_amd.build)")
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_expected_entry_points():
+    names = declared_functions()
+    for must in ("ma_plan_create", "ma_plan_destroy", "ma_solve", "ma_solve_batched",
+                 "ma_step_residual", "ma_step_strain_apply", "ma_step_gmres"):
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_every_declared_symbol():
+    from paper_1009_6039_amd import maot
+    assert sorted(maot.EXPORTED) == declared_functions()
+
+
+def test_abi_version_matches_header(lib):
+    m = re.search(r"#define MA_OT_ABI_VERSION (\d+)", open(HEADER).read())
+    assert lib.ma_abi_version() == int(m.group(1))
+
+
+def test_default_options_and_error_strings(lib):
+    from paper_1009_6039_amd import maot
+    o = maot.make_options()
+    assert (o.max_newton, o.gmres_m, o.gmres_max_restarts) == (100, 10, 20)
+    assert o.gmres_tol == 1e-4 and o.max_backtrack == 12
+    assert maot.strerror(0) == "converged"
+    assert "invalid" in maot.strerror(-1)
+
+
+@pytest.mark.parametrize("n", [0, 8, 15, 24, 40, 4096])
+def test_plan_create_rejects_unsupported_sizes_without_touching_the_gpu(lib, n):
+    from paper_1009_6039_amd import maot
+    h = ctypes.c_void_p()
+    o = maot.make_options()
+    assert lib.ma_plan_create(n, 1, ctypes.byref(o), ctypes.byref(h)) == -1
+    assert h.value is None
+
+
+def test_plan_create_rejects_bad_options(lib):
+    from paper_1009_6039_amd import maot
+    h = ctypes.c_void_p()
+    for bad in (dict(gmres_m=0), dict(gmres_m=31), dict(gmres_tol=0.0), dict(interp=7),
+                dict(damping_policy=3), dict(max_backtrack=-1)):
+        o = maot.make_options(**bad)
+        assert lib.ma_plan_create(64, 1, ctypes.byref(o), ctypes.byref(h)) == -1
