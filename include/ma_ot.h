@@ -127,6 +127,27 @@ int ma_solve_batched(ma_plan* plan, int npairs, const int* n, const double* cons
                      void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Timing hook for one kernel class, used by the benchmark to report a roofline.
+ * While enabled, every launch of that class inside ma_solve / ma_solve_batched is
+ * bracketed by HIP events on the caller's stream, and each launch adds the
+ * algorithmic bytes of the pairs it actually serves (inputs read once, outputs
+ * written once; pairs that skip the launch add nothing) to a device counter.
+ * ------------------------------------------------------------------------- */
+#define MA_PROF_NONE 0
+#define MA_PROF_RESIDUAL 1   /* fused residual / coefficient kernel             */
+#define MA_PROF_ROW_A 2      /* row pass A: Krylov vector build + forward rows  */
+#define MA_PROF_COLUMN 3     /* column pass B with the spectral multiply        */
+#define MA_PROF_ROW_C 4      /* row pass C: inverse rows + combine + dots       */
+
+/* Selects the class to time (MA_PROF_NONE disables) and clears the counters. */
+int ma_plan_profile(ma_plan* plan, int kernel_class);
+
+/* Totals since ma_plan_profile: summed event time (ms), launches, algorithmic
+ * bytes.  Any pointer may be NULL.  Synchronises nothing (counters are final once
+ * the solve call has returned). */
+int ma_plan_profile_read(ma_plan* plan, double* ms, long long* launches, double* bytes);
+
+/* ---------------------------------------------------------------------------
  * Single steps of the hot path, for verification and profiling.  They run the
  * same kernels as the solver on one pair, using the plan's workspace, and are
  * stream-ordered (no host synchronisation unless a host output is requested).

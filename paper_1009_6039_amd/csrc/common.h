@@ -59,8 +59,7 @@ struct PairState {
   int newton_iters, gmres_iters, backtracks, bt_step;
   int valid;            // set by the set-up kernel: 1 = densities positive and finite
   int pad0;
-  unsigned counter;     // last-block counter, reset by the last block
-  unsigned pad1;
+  int pad1, pad2;
   double tau0, tau;     // caller's damping, damping in force
   double tol;
   double step;          // multiplier of theta applied to the current trial
@@ -87,7 +86,14 @@ struct LaunchCtx {
   int m;                // GMRES restart length
   int max_newton, max_restarts, max_backtrack, damping_policy, interp, op_mode;
   double gmres_tol;
+  unsigned long long* prof_bytes;  // algorithmic-byte counter of the timed class, or null
 };
+
+// adds one pair's algorithmic bytes for this launch (timed class only)
+__device__ inline void count_bytes(const LaunchCtx& c, double bytes_per_point, int n) {
+  if (c.prof_bytes && blockIdx.x == 0 && threadIdx.x == 0)
+    atomicAdd(c.prof_bytes, (unsigned long long)(bytes_per_point * (double)n * (double)n));
+}
 
 __device__ inline int pair_of_block(const LaunchCtx& c) { return c.pair_ids[blockIdx.y]; }
 
@@ -136,17 +142,20 @@ __device__ inline void block_reduce(double (&v)[K], const int (&kinds)[K], doubl
   __syncthreads();
 }
 
-// Publishes this block's partials and reports whether it is the last block of the
-// pair to finish; the last block then sees every block's partials.
-__device__ inline bool publish_and_check_last(unsigned* counter, unsigned nblocks) {
-  __shared__ int is_last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned prev = atomicAdd(counter, 1u);
-    is_last = (prev == nblocks - 1);
+// Fixed-order fold of per-block partials (K values per block) inside a
+// one-block-per-pair finalize kernel: thread t takes blocks t, t + blockDim, ...,
+// then a block reduction.  Result valid in thread 0.
+template <int K>
+__device__ inline void fold_partials(const double* part, int nblk, const int (&kinds)[K], double (&t)[K],
+                                     double* scratch) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) t[k] = kinds[k] == 1 ? 1e300 : (kinds[k] == 2 ? -1e300 : 0.0);
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const double v = part[(long)b * K + k];
+      t[k] = kinds[k] == 0 ? t[k] + v : (kinds[k] == 1 ? fmin(t[k], v) : fmax(t[k], v));
+    }
   }
-  __syncthreads();
-  if (is_last) __threadfence();
-  return is_last != 0;
+  block_reduce<K>(t, kinds, scratch);
 }

@@ -31,20 +31,24 @@ __global__ __launch_bounds__(MA_BLOCK) void k_setup_sums(LaunchCtx c, int nblk) 
   double v[4] = {sf, sg, sp, bad};
   const int kinds[4] = {0, 0, 0, 0};
   block_reduce<4>(v, kinds, scratch);
-  double* part = d.part;
   if (threadIdx.x == 0)
-    for (int k = 0; k < 4; ++k) part[blockIdx.x * 4 + k] = v[k];
-  if (publish_and_check_last(&s.counter, nblk)) {
-    if (threadIdx.x == 0) {
-      double t[4] = {0, 0, 0, 0};
-      for (int b = 0; b < nblk; ++b)
-        for (int k = 0; k < 4; ++k) t[k] += part[b * 4 + k];
-      s.mean_f = t[0] / (double)nn;
-      s.mean_g = t[1] / (double)nn;
-      s.mean_psi0 = t[2] / (double)nn;
-      s.valid = (t[3] == 0.0) && isfinite(t[0]) && isfinite(t[1]) && isfinite(t[2]);
-      s.counter = 0;
-    }
+    for (int k = 0; k < 4; ++k) d.part[blockIdx.x * 4 + k] = v[k];
+}
+
+__global__ __launch_bounds__(MA_BLOCK) void k_setup_finalize(LaunchCtx c, int nblk) {
+  const int p = pair_of_block(c);
+  const PairDesc& d = c.desc[p];
+  PairState& s = c.st[p];
+  __shared__ double scratch[(MA_BLOCK / 64) * 4];
+  const int kinds[4] = {0, 0, 0, 0};
+  double t[4];
+  fold_partials<4>(d.part, nblk, kinds, t, scratch);
+  if (threadIdx.x == 0) {
+    const double nn = (double)d.n * d.n;
+    s.mean_f = t[0] / nn;
+    s.mean_g = t[1] / nn;
+    s.mean_psi0 = t[2] / nn;
+    s.valid = (t[3] == 0.0) && isfinite(t[0]) && isfinite(t[1]) && isfinite(t[2]);
   }
 }
 
@@ -166,11 +170,12 @@ __device__ static void newton_decide(PairState& s, const LaunchCtx& c, int n, co
 // Tile: TX columns x MA_RES_TY rows per block, halo 2 staged in LDS (FP64).
 // ---------------------------------------------------------------------------
 template <int TX>
-__global__ __launch_bounds__(MA_BLOCK) void k_residual(LaunchCtx c, int step_mode) {
+__global__ __launch_bounds__(MA_BLOCK) void k_residual(LaunchCtx c) {
   const int p = pair_of_block(c);
   const PairDesc& d = c.desc[p];
   PairState& s = c.st[p];
   if (s.phase == PH_DONE) return;
+  count_bytes(c, 56.0, d.n);  // u 8, f 8, g with gradient 16 (once), r 4, coefficients 20
   constexpr int TY = MA_RES_TY;
   constexpr int LW = TX + 4;
   __shared__ double tile[(TY + 4) * LW];
@@ -274,41 +279,36 @@ __global__ __launch_bounds__(MA_BLOCK) void k_residual(LaunchCtx c, int step_mod
   }
   const int kinds[MA_NPART_RES] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 2, 1, 0, 0};
   block_reduce<MA_NPART_RES>(acc, kinds, scratch);
-  const int nblk = gridDim.x;
-  double* part = d.part;
   if (threadIdx.x == 0)
-    for (int k = 0; k < MA_NPART_RES; ++k) part[(long)blockIdx.x * MA_NPART_RES + k] = acc[k];
-  if (publish_and_check_last(&s.counter, nblk)) {
-    // every thread folds a strided subset of blocks, then a fixed-order block reduction
-    double t[MA_NPART_RES];
-    for (int k = 0; k < MA_NPART_RES; ++k) t[k] = (kinds[k] == 1) ? 1e300 : (kinds[k] == 2 ? -1e300 : 0.0);
-    for (int b = threadIdx.x; b < nblk; b += MA_BLOCK) {
-      const volatile double* pb = part + (long)b * MA_NPART_RES;
-      for (int k = 0; k < MA_NPART_RES; ++k) {
-        double v = pb[k];
-        t[k] = kinds[k] == 0 ? t[k] + v : (kinds[k] == 1 ? fmin(t[k], v) : fmax(t[k], v));
-      }
-    }
-    block_reduce<MA_NPART_RES>(t, kinds, scratch);
-    if (threadIdx.x == 0) {
-      if (step_mode) {
-        // single-step use: record the evaluation only
-        const double NN = (double)n * n;
-        const double cst = t[0] / NN - 1.0;
-        const double ss = t[2] + 2.0 * cst * t[1] + NN * cst * cst;
-        s.res_rms = sqrt(fmax(ss, 0.0) / NN);
-        s.res_max = fmax(fabs(t[12] + cst), fabs(t[13] + cst));
-        s.mass_c = cst;
-        s.min_det = t[10];
-        s.min_tr = t[11];
-        s.w2 = t[8] / NN;
-        s.mean_u = t[9] / NN;
-        for (int k = 0; k < 5; ++k) s.abar[k] = t[3 + k];
-      } else {
-        newton_decide(s, c, n, t);
-      }
-      s.counter = 0;
-    }
+    for (int k = 0; k < MA_NPART_RES; ++k) d.part[(long)blockIdx.x * MA_NPART_RES + k] = acc[k];
+}
+
+// folds the residual partials of one pair and runs its Newton decisions
+__global__ __launch_bounds__(MA_BLOCK) void k_residual_finalize(LaunchCtx c, int nblk, int step_mode) {
+  const int p = pair_of_block(c);
+  const PairDesc& d = c.desc[p];
+  PairState& s = c.st[p];
+  if (s.phase == PH_DONE) return;
+  __shared__ double scratch[(MA_BLOCK / 64) * MA_NPART_RES];
+  const int kinds[MA_NPART_RES] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 2, 1, 0, 0};
+  double t[MA_NPART_RES];
+  fold_partials<MA_NPART_RES>(d.part, nblk, kinds, t, scratch);
+  if (threadIdx.x != 0) return;
+  const int n = d.n;
+  if (step_mode) {  // single-step use: record the evaluation only
+    const double NN = (double)n * n;
+    const double cst = t[0] / NN - 1.0;
+    const double ss = t[2] + 2.0 * cst * t[1] + NN * cst * cst;
+    s.res_rms = sqrt(fmax(ss, 0.0) / NN);
+    s.res_max = fmax(fabs(t[12] + cst), fabs(t[13] + cst));
+    s.mass_c = cst;
+    s.min_det = t[10];
+    s.min_tr = t[11];
+    s.w2 = t[8] / NN;
+    s.mean_u = t[9] / NN;
+    for (int k = 0; k < 5; ++k) s.abar[k] = t[3 + k];
+  } else {
+    newton_decide(s, c, n, t);
   }
 }
 
@@ -388,6 +388,7 @@ void launch_setup(const LaunchCtx& c, int n, int npairs, hipStream_t st) {
   int nblk = (int)((long)n * n / 4096);
   nblk = nblk < 1 ? 1 : (nblk > 256 ? 256 : nblk);
   hipLaunchKernelGGL(k_setup_sums, dim3(nblk, npairs), dim3(MA_BLOCK), 0, st, c, nblk);
+  hipLaunchKernelGGL(k_setup_finalize, dim3(1, npairs), dim3(MA_BLOCK), 0, st, c, nblk);
   launch_setup_fields(c, n, npairs, st);
 }
 
@@ -398,9 +399,11 @@ int residual_blocks(int n) { return (n / residual_tile_x(n)) * (n / MA_RES_TY); 
 void launch_residual(const LaunchCtx& c, int n, int npairs, int step_mode, hipStream_t st) {
   const int tx = residual_tile_x(n);
   dim3 grid(residual_blocks(n), npairs);
-  if (tx == 64) hipLaunchKernelGGL(k_residual<64>, grid, dim3(MA_BLOCK), 0, st, c, step_mode);
-  else if (tx == 32) hipLaunchKernelGGL(k_residual<32>, grid, dim3(MA_BLOCK), 0, st, c, step_mode);
-  else hipLaunchKernelGGL(k_residual<16>, grid, dim3(MA_BLOCK), 0, st, c, step_mode);
+  if (tx == 64) hipLaunchKernelGGL(k_residual<64>, grid, dim3(MA_BLOCK), 0, st, c);
+  else if (tx == 32) hipLaunchKernelGGL(k_residual<32>, grid, dim3(MA_BLOCK), 0, st, c);
+  else hipLaunchKernelGGL(k_residual<16>, grid, dim3(MA_BLOCK), 0, st, c);
+  hipLaunchKernelGGL(k_residual_finalize, dim3(1, npairs), dim3(MA_BLOCK), 0, st, c, residual_blocks(n),
+                     step_mode);
 }
 
 static int elementwise_blocks(int n) {

@@ -163,6 +163,15 @@ __global__ __launch_bounds__(Cfg<N>::A_BLOCK) void k_passA(LaunchCtx c, int mode
     cf[l] = mode == PA_ARNOLDI ? (float)(s.Hm[(jn - 1) * (MA_MMAX + 1) + l] * s.vscale[l]) : (float)s.y[l];
   }
   const float cst = (float)s.mass_c, inv_tau = (float)(1.0 / s.tau);
+  {  // algorithmic bytes per point: vectors read, Krylov vector written, half spectrum written
+    const bool fft = !(mode == PA_ARNOLDI && jn >= c.m);
+    double b = fft ? 4.0 : 0.0;
+    if (mode == PA_INIT) b += 8.0;
+    else if (mode == PA_PLAIN || mode == PA_STEP) b += 4.0;
+    else if (mode == PA_ARNOLDI) b += 4.0 * (jn + 1) + 4.0;
+    else b += 4.0 * (nv + (usex ? 1 : 0));
+    count_bytes(c, b, N);
+  }
   __syncthreads();
 
   const int row0 = 2 * blockIdx.x * PPB;
@@ -226,29 +235,11 @@ __global__ __launch_bounds__(Cfg<N>::A_BLOCK) void k_passA(LaunchCtx c, int mode
     }
   }
 
-  if (mode == PA_ARNOLDI) {
+  if (mode == PA_ARNOLDI) {  // partial ||w'||^2, folded by k_arnoldi_finalize
     double v[1] = {(double)nrm};
     const int kinds[1] = {0};
     block_reduce<1>(v, kinds, scratch);
     if (threadIdx.x == 0) d.part[blockIdx.x] = v[0];
-    if (publish_and_check_last(&s.counter, gridDim.x)) {
-      double t[1] = {0.0};
-      for (int b = threadIdx.x; b < (int)gridDim.x; b += BLOCK) t[0] += ((volatile double*)d.part)[b];
-      block_reduce<1>(t, kinds, scratch);
-      if (threadIdx.x == 0) {
-        arnoldi_close(s, c, jn, t[0]);
-        s.counter = 0;
-      }
-    }
-  } else if (mode == PA_PLAIN) {
-    if (publish_and_check_last(&s.counter, gridDim.x)) {
-      if (threadIdx.x == 0) {
-        s.gm_running = 1;
-        s.gm_restart = 0;
-        s.gm_cycle++;
-        s.counter = 0;
-      }
-    }
   }
 }
 
@@ -259,7 +250,6 @@ template <int N>
 __global__ __launch_bounds__(Cfg<N>::B_BLOCK) void k_passB(LaunchCtx c, int mode, int j,
                                                            const float2* __restrict__ tw) {
   constexpr int CPB = Cfg<N>::B_CPB, BLOCK = Cfg<N>::B_BLOCK, NH = N / 2;
-  constexpr int PER = N * CPB / BLOCK;
   const int p = pair_of_block(c);
   const PairDesc& d = c.desc[p];
   const PairState& s = c.st[p];
@@ -268,73 +258,80 @@ __global__ __launch_bounds__(Cfg<N>::B_BLOCK) void k_passB(LaunchCtx c, int mode
   else if (mode == PB_RECOVER) run = s.phase == PH_SOLVE;
   else run = true;
   if (!run) return;
+  count_bytes(c, mode == PB_MATVEC ? 16.0 : 8.0, N);  // half spectrum in, one or three out
 
-  __shared__ float2 lds[N * CPB];
+  // S: the column spectra, then rhobar * sigmahat; W: work buffer for derived spectra.
+  // Element (row or wavenumber e, column cc) sits at e * CPB + cc.
+  __shared__ float2 S[N * CPB];
+  __shared__ float2 Wb[N * CPB];
   const int s0 = blockIdx.x * CPB;
   for (int e = threadIdx.x; e < N * CPB; e += BLOCK) {
     const int i = e / CPB, cc = e % CPB;
-    lds[e] = d.H[(long)i * NH + s0 + cc];
+    S[e] = d.H[(long)i * NH + s0 + cc];
   }
   __syncthreads();
-  fft_lds<N, CPB, BLOCK, false, LAYOUT_COLS>(lds, tw);
+  fft_lds<N, CPB, BLOCK, false, LAYOUT_COLS>(S, tw);
   if (mode == PB_FORWARD) {
     for (int e = threadIdx.x; e < N * CPB; e += BLOCK) {
       const int i = e / CPB, cc = e % CPB;
-      d.T[(long)i * NH + s0 + cc] = lds[e];
+      d.T[(long)i * NH + s0 + cc] = S[e];
     }
     return;
   }
   const float scale = (float)((mode == PB_MATVEC ? s.vscale[j] : 1.0) / ((double)N * (double)N));
   float ab[5];
   for (int k = 0; k < 5; ++k) ab[k] = (float)s.abar[k];
-  const int cc = threadIdx.x % CPB;
-  const int slot = s0 + cc;
-  const bool packed = slot == 0;
-  float2 sA[PER], sB[PER];
-#pragma unroll
-  for (int t = 0; t < PER; ++t) {
-    const int e = threadIdx.x + t * BLOCK;
-    const int q = e / CPB;
-    const float2 z = lds[e];
-    if (!packed) {
-      sA[t] = cscale(cmul(rhobar<N>(q, slot, ab), z), scale);
-      sB[t] = make_float2(0.f, 0.f);
+  // wavenumbers q and N - q together: slot 0 packs the DC and Nyquist columns of the
+  // rows, which separate with the partner coefficient; every later multiplier m(q)
+  // then acts on the packed value P = sA + i sB directly
+  for (int it = threadIdx.x; it < (NH + 1) * CPB; it += BLOCK) {
+    const int q = it / CPB, cc = it % CPB;
+    const int qm = (N - q) % N;
+    const int slot = s0 + cc;
+    const float2 z = S[q * CPB + cc], zm = S[qm * CPB + cc];
+    float2 vq, vm;
+    if (slot != 0) {
+      vq = cscale(cmul(rhobar<N>(q, slot, ab), z), scale);
+      vm = cscale(cmul(rhobar<N>(qm, slot, ab), zm), scale);
     } else {
-      // column 0 holds DC + i Nyquist of the rows: separate the two real columns
-      const float2 zm = lds[((N - q) % N) * CPB + cc];
       const float2 A = make_float2(0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y));
       const float2 B = make_float2(0.5f * (z.y + zm.y), -0.5f * (z.x - zm.x));
-      sA[t] = cscale(cmul(rhobar<N>(q, 0, ab), A), scale);
-      sB[t] = cscale(cmul(rhobar<N>(q, -NH, ab), B), scale);
+      const float2 aq = cmul(rhobar<N>(q, 0, ab), A), bq = cmul(rhobar<N>(q, -NH, ab), B);
+      const float2 am = cmul(rhobar<N>(qm, 0, ab), cconj(A)), bm = cmul(rhobar<N>(qm, -NH, ab), cconj(B));
+      vq = cscale(make_float2(aq.x - bq.y, aq.y + bq.x), scale);
+      vm = cscale(make_float2(am.x - bm.y, am.y + bm.x), scale);
     }
+    S[q * CPB + cc] = vq;
+    if (qm != q) S[qm * CPB + cc] = vm;
   }
+  __syncthreads();
+  // derived spectra 2 pi i k1 and -(2 pi k1)^2 (matvec only), then the plain one in place
   const int nout = mode == PB_MATVEC ? 3 : 1;
-  for (int o = 0; o < nout; ++o) {
-    __syncthreads();
-#pragma unroll
-    for (int t = 0; t < PER; ++t) {
-      const int e = threadIdx.x + t * BLOCK;
-      const int q = e / CPB;
-      const int k1s = q < NH ? q : q - N;
-      float2 va = sA[t], vb = sB[t];
-      if (o == 1) {  // 2 pi i k1, zero at the Nyquist wavenumber
-        const float w = (q == NH) ? 0.f : TWO_PI * (float)k1s;
-        va = times_i(w, va);
-        vb = times_i(w, vb);
-      } else if (o == 2) {  // -(2 pi k1)^2
-        const float w = TWO_PI * (float)k1s;
-        va = cscale(va, -w * w);
-        vb = cscale(vb, -w * w);
+  for (int oo = 0; oo < nout; ++oo) {
+    const int o = (oo + 1) % 3 == 0 || nout == 1 ? 0 : oo + 1;  // order 1, 2, 0
+    float2* L = (o == 0) ? S : Wb;
+    if (o != 0) {
+      for (int e = threadIdx.x; e < N * CPB; e += BLOCK) {
+        const int q = e / CPB;
+        const int k1s = q < NH ? q : q - N;
+        const float2 v = S[e];
+        if (o == 1) {
+          const float w = (q == NH) ? 0.f : TWO_PI * (float)k1s;  // zero at the Nyquist wavenumber
+          Wb[e] = times_i(w, v);
+        } else {
+          const float w = TWO_PI * (float)k1s;
+          Wb[e] = cscale(v, -w * w);
+        }
       }
-      lds[e] = packed ? make_float2(va.x - vb.y, va.y + vb.x) : va;
+      __syncthreads();
     }
-    __syncthreads();
-    fft_lds<N, CPB, BLOCK, true, LAYOUT_COLS>(lds, tw);
+    fft_lds<N, CPB, BLOCK, true, LAYOUT_COLS>(L, tw);
     float2* To = d.T + (long)o * N * NH;
     for (int e = threadIdx.x; e < N * CPB; e += BLOCK) {
       const int i = e / CPB, c2 = e % CPB;
-      To[(long)i * NH + s0 + c2] = lds[e];
+      To[(long)i * NH + s0 + c2] = L[e];
     }
+    __syncthreads();
   }
 }
 
@@ -352,6 +349,9 @@ __global__ __launch_bounds__(Cfg<N>::C_BLOCK) void k_passC(LaunchCtx c, int mode
   const bool run = mode == PC_MATVEC ? (s.phase == PH_SOLVE && s.gm_running) : (s.phase == PH_SOLVE);
   if (!run) return;
 
+  // three half spectra 12, coefficients 20, Krylov vectors for the dots, w 4 (matvec);
+  // one half spectrum 4, theta 4, u read and written 16 (recovery)
+  count_bytes(c, mode == PC_MATVEC ? 36.0 + 4.0 * (j + 1) : (mode == PC_RECOVER ? 24.0 : 8.0), N);
   __shared__ float2 lds[5 * PPB * N];
   __shared__ double red[(BLOCK / 64) * (MA_MMAX + 1)];
   const int row0 = 2 * blockIdx.x * PPB;
@@ -445,7 +445,7 @@ __global__ __launch_bounds__(Cfg<N>::C_BLOCK) void k_passC(LaunchCtx c, int mode
         dots[l] += wa * Vl[ea] + wb * Vl[eb];
       }
   }
-  // block reduction of the j+1 inner products (fixed order)
+  // block reduction of the j+1 inner products (fixed order); folded by k_dots_finalize
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
   for (int l = 0; l <= MA_MMAX; ++l)
@@ -459,15 +459,49 @@ __global__ __launch_bounds__(Cfg<N>::C_BLOCK) void k_passC(LaunchCtx c, int mode
     for (int w = 0; w < BLOCK / 64; ++w) t += red[w * (MA_MMAX + 1) + threadIdx.x];
     d.part[(long)blockIdx.x * (MA_MMAX + 1) + threadIdx.x] = t;
   }
-  if (publish_and_check_last(&s.counter, gridDim.x)) {
-    if (threadIdx.x <= j) {
-      double t = 0.0;
-      const volatile double* pv = d.part;
-      for (int b = 0; b < (int)gridDim.x; ++b) t += pv[(long)b * (MA_MMAX + 1) + threadIdx.x];
-      s.Hm[j * (MA_MMAX + 1) + threadIdx.x] = t * s.vscale[threadIdx.x];
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) s.counter = 0;
+}
+
+// h[l][j] = <w, v_l> for l <= j from the pass-C partials (one block per pair)
+__global__ __launch_bounds__(256) void k_dots_finalize(LaunchCtx c, int j, int nblk) {
+  const int p = pair_of_block(c);
+  const PairDesc& d = c.desc[p];
+  PairState& s = c.st[p];
+  if (!(s.phase == PH_SOLVE && s.gm_running)) return;
+  __shared__ double red[8][32];
+  const int l = threadIdx.x & 31, grp = threadIdx.x >> 5;  // 8 groups of 32 lanes
+  double t = 0.0;
+  if (l <= j)
+    for (int b = grp; b < nblk; b += 8) t += d.part[(long)b * (MA_MMAX + 1) + l];
+  red[grp][l] = t;
+  __syncthreads();
+  if (threadIdx.x <= j) {
+    double u = 0.0;
+    for (int g2 = 0; g2 < 8; ++g2) u += red[g2][threadIdx.x];
+    s.Hm[j * (MA_MMAX + 1) + threadIdx.x] = u * s.vscale[threadIdx.x];
+  }
+}
+
+// ||w'|| from the pass-A partials, then the rotations and the convergence test
+__global__ __launch_bounds__(256) void k_arnoldi_finalize(LaunchCtx c, int jn, int nblk) {
+  const int p = pair_of_block(c);
+  const PairDesc& d = c.desc[p];
+  PairState& s = c.st[p];
+  if (!(s.phase == PH_SOLVE && s.gm_running)) return;
+  __shared__ double scratch[4];
+  const int kinds[1] = {0};
+  double t[1];
+  fold_partials<1>(d.part, nblk, kinds, t, scratch);
+  if (threadIdx.x == 0) arnoldi_close(s, c, jn, t[0]);
+}
+
+// a restarted cycle begins: its first vector has been transformed by pass A
+__global__ void k_cycle_begin(LaunchCtx c) {
+  const int p = pair_of_block(c);
+  PairState& s = c.st[p];
+  if (threadIdx.x == 0 && s.phase == PH_SOLVE && s.gm_restart) {
+    s.gm_running = 1;
+    s.gm_restart = 0;
+    s.gm_cycle++;
   }
 }
 
@@ -533,6 +567,14 @@ int passC_blocks(int n) {
 }
 
 void launch_passA(const LaunchCtx& c, int n, int npairs, int mode, int jn, const float2* tw, hipStream_t st) {
+  launch_passA_only(c, n, npairs, mode, jn, tw, st);
+  if (mode == PA_ARNOLDI)
+    hipLaunchKernelGGL(k_arnoldi_finalize, dim3(1, npairs), dim3(256), 0, st, c, jn, passA_blocks(n));
+  else if (mode == PA_PLAIN)
+    hipLaunchKernelGGL(k_cycle_begin, dim3(1, npairs), dim3(64), 0, st, c);
+}
+
+void launch_passA_only(const LaunchCtx& c, int n, int npairs, int mode, int jn, const float2* tw, hipStream_t st) {
   switch (n) {
 #define X(NV)                                                                                  \
   case NV:                                                                                     \
@@ -559,6 +601,12 @@ void launch_passB(const LaunchCtx& c, int n, int npairs, int mode, int j, const 
 }
 
 void launch_passC(const LaunchCtx& c, int n, int npairs, int mode, int j, const float2* tw, hipStream_t st) {
+  launch_passC_only(c, n, npairs, mode, j, tw, st);
+  if (mode == PC_MATVEC)
+    hipLaunchKernelGGL(k_dots_finalize, dim3(1, npairs), dim3(256), 0, st, c, j, passC_blocks(n));
+}
+
+void launch_passC_only(const LaunchCtx& c, int n, int npairs, int mode, int j, const float2* tw, hipStream_t st) {
   switch (n) {
 #define X(NV)                                                                                  \
   case NV:                                                                                     \

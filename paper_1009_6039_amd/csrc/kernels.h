@@ -28,6 +28,8 @@ bool fft_size_supported(int n);
 int passA_blocks(int n);
 int passC_blocks(int n);
 void launch_passA(const LaunchCtx& c, int n, int npairs, int mode, int jn, const float2* tw, hipStream_t st);
+void launch_passA_only(const LaunchCtx& c, int n, int npairs, int mode, int jn, const float2* tw, hipStream_t st);
 void launch_passB(const LaunchCtx& c, int n, int npairs, int mode, int j, const float2* tw, hipStream_t st);
 void launch_passC(const LaunchCtx& c, int n, int npairs, int mode, int j, const float2* tw, hipStream_t st);
+void launch_passC_only(const LaunchCtx& c, int n, int npairs, int mode, int j, const float2* tw, hipStream_t st);
 void launch_restart(const LaunchCtx& c, int n, int npairs, hipStream_t st);

@@ -47,6 +47,13 @@ struct ma_plan {
   std::map<int, float2*> tw;
   std::vector<PairDesc> h_desc;
   std::vector<PairState> h_state;
+  // timing hook
+  int prof_kind = MA_PROF_NONE;
+  unsigned long long* d_prof = nullptr;
+  std::vector<hipEvent_t> ev;  // start/end pairs
+  int ev_used = 0;
+  double prof_ms = 0.0;
+  long long prof_launches = 0;
 };
 
 namespace {
@@ -160,8 +167,9 @@ int ensure_workspace(ma_plan* P, const std::vector<int>& ns) {
   return MA_OK;
 }
 
-LaunchCtx make_ctx(const ma_plan* P, const int* d_ids) {
+LaunchCtx make_ctx(const ma_plan* P, const int* d_ids, int kind = MA_PROF_NONE) {
   LaunchCtx c;
+  c.prof_bytes = (kind != MA_PROF_NONE && kind == P->prof_kind) ? P->d_prof : nullptr;
   c.desc = P->d_desc;
   c.st = P->d_state;
   c.pair_ids = d_ids;
@@ -207,22 +215,70 @@ int build_classes(ma_plan* P, const std::vector<int>& ns, std::vector<Class>& cl
   return MA_OK;
 }
 
+// event brackets around launches of the timed class
+bool prof_begin(ma_plan* P, int kind, hipStream_t st) {
+  if (kind == MA_PROF_NONE || kind != P->prof_kind) return false;
+  if ((int)P->ev.size() < 2 * (P->ev_used + 1)) {
+    for (int k = 0; k < 2; ++k) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return false;
+      P->ev.push_back(e);
+    }
+  }
+  hipEventRecord(P->ev[2 * P->ev_used], st);
+  return true;
+}
+void prof_end(ma_plan* P, bool on, hipStream_t st) {
+  if (!on) return;
+  hipEventRecord(P->ev[2 * P->ev_used + 1], st);
+  P->ev_used++;
+}
+// after a stream synchronisation: fold the recorded brackets into the totals
+void prof_flush(ma_plan* P) {
+  for (int i = 0; i < P->ev_used; ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, P->ev[2 * i], P->ev[2 * i + 1]) == hipSuccess) P->prof_ms += ms;
+    P->prof_launches++;
+  }
+  P->ev_used = 0;
+}
+
+void L_res(ma_plan* P, const Class& c, int step_mode, hipStream_t st) {
+  bool on = prof_begin(P, MA_PROF_RESIDUAL, st);
+  launch_residual(make_ctx(P, c.d_ids, MA_PROF_RESIDUAL), c.n, (int)c.ids.size(), step_mode, st);
+  prof_end(P, on, st);
+}
+void L_A(ma_plan* P, const Class& c, int mode, int jn, hipStream_t st) {
+  bool on = prof_begin(P, MA_PROF_ROW_A, st);
+  launch_passA(make_ctx(P, c.d_ids, MA_PROF_ROW_A), c.n, (int)c.ids.size(), mode, jn, c.tw, st);
+  prof_end(P, on, st);
+}
+void L_B(ma_plan* P, const Class& c, int mode, int j, hipStream_t st) {
+  bool on = prof_begin(P, MA_PROF_COLUMN, st);
+  launch_passB(make_ctx(P, c.d_ids, MA_PROF_COLUMN), c.n, (int)c.ids.size(), mode, j, c.tw, st);
+  prof_end(P, on, st);
+}
+void L_C(ma_plan* P, const Class& c, int mode, int j, hipStream_t st) {
+  bool on = prof_begin(P, MA_PROF_ROW_C, st);
+  launch_passC(make_ctx(P, c.d_ids, MA_PROF_ROW_C), c.n, (int)c.ids.size(), mode, j, c.tw, st);
+  prof_end(P, on, st);
+}
+
 int read_summary(ma_plan* P, int npairs, hipStream_t st) {
   launch_summary(P->d_state, P->d_ids, npairs, P->d_summary, st);
   HIP_TRY(hipMemcpyAsync(P->h_summary, P->d_summary, sizeof(int) * 8, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
+  prof_flush(P);
   return MA_OK;
 }
 
-void launch_cycle_body(const ma_plan* P, const std::vector<Class>& cls, hipStream_t st) {
+void launch_cycle_body(ma_plan* P, const std::vector<Class>& cls, hipStream_t st) {
   const int m = P->opt.gmres_m;
   for (int j = 0; j < m; ++j)
     for (const Class& c : cls) {
-      LaunchCtx x = make_ctx(P, c.d_ids);
-      const int np = (int)c.ids.size();
-      launch_passB(x, c.n, np, PB_MATVEC, j, c.tw, st);
-      launch_passC(x, c.n, np, PC_MATVEC, j, c.tw, st);
-      launch_passA(x, c.n, np, PA_ARNOLDI, j + 1, c.tw, st);
+      L_B(P, c, PB_MATVEC, j, st);
+      L_C(P, c, PC_MATVEC, j, st);
+      L_A(P, c, PA_ARNOLDI, j + 1, st);
     }
 }
 
@@ -238,33 +294,29 @@ int run_solver(ma_plan* P, int npairs, double damping, double tol, hipStream_t s
 
   const long max_ticks = (long)(P->opt.max_newton + 1) * (P->opt.max_backtrack + 3) + 8;
   for (long tick = 0; tick < max_ticks; ++tick) {
-    for (const Class& c : cls) launch_residual(make_ctx(P, c.d_ids), c.n, (int)c.ids.size(), 0, st);
+    for (const Class& c : cls) L_res(P, c, 0, st);
     e = read_summary(P, npairs, st);
     if (e) return e;
     const int n_solve = P->h_summary[PH_SOLVE];
     const int n_update = P->h_summary[PH_BACKTRACK] + P->h_summary[PH_REVERT];
     if (n_solve == 0 && n_update == 0) break;  // every pair is done
     if (n_solve > 0) {
-      for (const Class& c : cls)
-        launch_passA(make_ctx(P, c.d_ids), c.n, (int)c.ids.size(), PA_INIT, 0, c.tw, st);
+      for (const Class& c : cls) L_A(P, c, PA_INIT, 0, st);
       launch_cycle_body(P, cls, st);
       for (int cyc = 0; cyc < P->opt.gmres_max_restarts; ++cyc) {
         e = read_summary(P, npairs, st);
         if (e) return e;
         if (P->h_summary[6] == 0) break;
         for (const Class& c : cls) {
-          LaunchCtx x = make_ctx(P, c.d_ids);
-          launch_restart(x, c.n, (int)c.ids.size(), st);
-          launch_passA(x, c.n, (int)c.ids.size(), PA_PLAIN, 0, c.tw, st);
+          launch_restart(make_ctx(P, c.d_ids), c.n, (int)c.ids.size(), st);
+          L_A(P, c, PA_PLAIN, 0, st);
         }
         launch_cycle_body(P, cls, st);
       }
       for (const Class& c : cls) {
-        LaunchCtx x = make_ctx(P, c.d_ids);
-        const int np = (int)c.ids.size();
-        launch_passA(x, c.n, np, PA_RECOVER, 0, c.tw, st);
-        launch_passB(x, c.n, np, PB_RECOVER, 0, c.tw, st);
-        launch_passC(x, c.n, np, PC_RECOVER, 0, c.tw, st);
+        L_A(P, c, PA_RECOVER, 0, st);
+        L_B(P, c, PB_RECOVER, 0, st);
+        L_C(P, c, PC_RECOVER, 0, st);
       }
     }
     if (n_update > 0)
@@ -273,6 +325,7 @@ int run_solver(ma_plan* P, int npairs, double damping, double tol, hipStream_t s
   for (const Class& c : cls) launch_outputs(make_ctx(P, c.d_ids), c.n, (int)c.ids.size(), st);
   HIP_TRY(hipMemcpyAsync(P->h_state.data(), P->d_state, sizeof(PairState) * npairs, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
+  prof_flush(P);
   return MA_OK;
 }
 
@@ -361,7 +414,9 @@ int ma_plan_create(int n_max, int batch_capacity, const ma_options* opt, ma_plan
   }
   P->n_max = n_max;
   P->cap = batch_capacity;
-  if (hipMalloc(&P->d_summary, sizeof(int) * 8) != hipSuccess ||
+  if (hipMalloc(&P->d_prof, sizeof(unsigned long long)) != hipSuccess ||
+      hipMemset(P->d_prof, 0, sizeof(unsigned long long)) != hipSuccess ||
+      hipMalloc(&P->d_summary, sizeof(int) * 8) != hipSuccess ||
       hipHostMalloc(&P->h_summary, sizeof(int) * 8, hipHostMallocDefault) != hipSuccess) {
     ma_plan_destroy(P);
     return MA_ENOMEM;
@@ -385,12 +440,35 @@ void ma_plan_destroy(ma_plan* P) {
   if (P->d_summary) hipFree(P->d_summary);
   if (P->h_summary) hipHostFree(P->h_summary);
   for (auto& kv : P->tw) hipFree(kv.second);
+  for (hipEvent_t e : P->ev) hipEventDestroy(e);
+  if (P->d_prof) hipFree(P->d_prof);
   delete P;
 }
 
 int ma_plan_set_options(ma_plan* P, const ma_options* opt) {
   if (!P || !opt || validate_options(*opt)) return MA_EINVAL;
   P->opt = *opt;
+  return MA_OK;
+}
+
+int ma_plan_profile(ma_plan* P, int kind) {
+  if (!P || kind < MA_PROF_NONE || kind > MA_PROF_ROW_C) return MA_EINVAL;
+  HIP_TRY(hipDeviceSynchronize());
+  P->prof_kind = kind;
+  P->prof_ms = 0.0;
+  P->prof_launches = 0;
+  P->ev_used = 0;
+  HIP_TRY(hipMemset(P->d_prof, 0, sizeof(unsigned long long)));
+  return MA_OK;
+}
+
+int ma_plan_profile_read(ma_plan* P, double* ms, long long* launches, double* bytes) {
+  if (!P) return MA_EINVAL;
+  unsigned long long b = 0;
+  HIP_TRY(hipMemcpy(&b, P->d_prof, sizeof(b), hipMemcpyDeviceToHost));
+  if (ms) *ms = P->prof_ms;
+  if (launches) *launches = P->prof_launches;
+  if (bytes) *bytes = (double)b;
   return MA_OK;
 }
 

@@ -20,8 +20,11 @@ INTERP = {"bilinear": 0, "nearest": 1}
 OP_MODE = {"full": 0, "no_drift": 1}
 DAMPING = {"fixed": 0, "backtrack": 1}
 
+PROF = {"none": 0, "residual": 1, "row_a": 2, "column": 3, "row_c": 4}
+
 EXPORTED = ("ma_abi_version", "ma_options_default", "ma_strerror", "ma_plan_create",
             "ma_plan_destroy", "ma_plan_set_options", "ma_solve", "ma_solve_batched",
+            "ma_plan_profile", "ma_plan_profile_read",
             "ma_step_residual", "ma_step_fft2", "ma_step_strain_apply",
             "ma_step_lbar_inverse", "ma_step_gmres")
 
@@ -69,6 +72,9 @@ def load():
     lib.ma_solve_batched.argtypes = [P, I, ctypes.POINTER(I), ctypes.POINTER(P), ctypes.POINTER(P),
                                      ctypes.POINTER(P), D, D, ctypes.POINTER(P), ctypes.POINTER(P),
                                      ctypes.POINTER(Report), P]
+    lib.ma_plan_profile.argtypes = [P, I]
+    lib.ma_plan_profile_read.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_longlong),
+                                         ctypes.POINTER(D)]
     lib.ma_step_residual.argtypes = [P, I, P, P, P, P, P, ctypes.POINTER(D), P]
     lib.ma_step_fft2.argtypes = [P, I, P, P, P]
     lib.ma_step_strain_apply.argtypes = [P, I, P, P, ctypes.POINTER(D), P, P]
@@ -155,6 +161,18 @@ class Plan:
     def set_options(self, **opts):
         self.options = make_options(**opts)
         _check(load().ma_plan_set_options(self._h, ctypes.byref(self.options)), "ma_plan_set_options")
+
+    # -- timing hook -------------------------------------------------------------
+    def profile(self, kernel_class):
+        """Times every launch of one kernel class ("residual", "row_a", "column", "row_c")."""
+        k = PROF[kernel_class] if isinstance(kernel_class, str) else int(kernel_class)
+        _check(load().ma_plan_profile(self._h, k), "ma_plan_profile")
+
+    def profile_read(self):
+        ms, n, b = ctypes.c_double(), ctypes.c_longlong(), ctypes.c_double()
+        _check(load().ma_plan_profile_read(self._h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b)),
+               "ma_plan_profile_read")
+        return {"ms": ms.value, "launches": n.value, "bytes": b.value}
 
     # -- full solves ------------------------------------------------------------
     def solve(self, f, g, damping=1.0, tol=1e-6, psi0=None, want_map=True):
