@@ -34,7 +34,21 @@ def parse():
     ap.add_argument("--profile-class", default="row_c",
                     help="kernel class timed for the roofline: residual, row_a, column, row_c")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB mebibytes (scales HBM byte counters)")
     return ap.parse_args()
+
+
+def copy_probe(mib):
+    """A plain copy kernel of known size: reads and writes mib MiB once."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4}), flush=True)
 
 
 def cpu_baseline(f, g, args):
@@ -52,6 +66,9 @@ def cpu_baseline(f, g, args):
 
 def main():
     args = parse()
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this solver build runs on a single device "
               "(batches of pairs would shard across GPUs without communication; see the design notes)",
@@ -116,7 +133,8 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None, "launches": prof["launches"],
                      "avg_launch_us": round(1e3 * prof["ms"] / max(prof["launches"], 1), 3),
-                     "bytes_per_launch": round(prof["bytes"] / max(prof["launches"], 1))},
+                     "bytes_per_launch": round(prof["bytes"] / max(prof["launches"], 1)),
+                     "algorithmic_bytes_total": prof["bytes"]},
     }
     if not args.no_cpu_baseline:
         f0, g0 = host_pairs[0]

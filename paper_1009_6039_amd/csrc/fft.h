@@ -117,14 +117,23 @@ __device__ __forceinline__ void fft_stage(float2* lds, const float2* __restrict_
       else { t = it % NF; j = it / NF; }
       const int k = j % NS;
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        float2 x = lds[lds_index<N, NF, LAYOUT>(t, j + r * NB)];
-        if (NS > 1 && r > 0) {
-          float2 w = tw[k * r * TWS];  // k r < NS R, so the index is below N
-          if (INV) w.y = -w.y;
-          x = cmul(x, w);
+      for (int r = 0; r < R; ++r) v[q][r] = lds[lds_index<N, NF, LAYOUT>(t, j + r * NB)];
+      if (NS > 1) {
+        // w^r for r < R from at most three table entries (k r < NS R, so indices stay
+        // below N); products of two table values keep the error within a few ulp
+        float2 w[R];
+        w[1] = tw[k * TWS];
+        if constexpr (R >= 3) w[2] = tw[2 * k * TWS];
+        if constexpr (R == 4) w[3] = cmul(w[1], w[2]);
+        if constexpr (R == 8) {
+          w[4] = tw[4 * k * TWS];
+          w[3] = cmul(w[1], w[2]);
+          w[5] = cmul(w[4], w[1]);
+          w[6] = cmul(w[4], w[2]);
+          w[7] = cmul(w[4], w[3]);
         }
-        v[q][r] = x;
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], INV ? cconj(w[r]) : w[r]);
       }
       dft<R, INV>(v[q]);
     }

@@ -359,20 +359,19 @@ __global__ __launch_bounds__(MA_BLOCK) void k_outputs(LaunchCtx c) {
   }
 }
 
-// counts pairs per phase and pending restarts for the host loop
-__global__ void k_summary(const PairState* st, const int* ids, int npairs, int* out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  int cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  int restart = 0, invalid = 0;
-  for (int q = 0; q < npairs; ++q) {
+// counts pairs per phase, pending restarts and invalid inputs for the host loop
+__global__ __launch_bounds__(256) void k_summary(const PairState* st, const int* ids, int npairs, int* out) {
+  __shared__ int cnt[8];
+  if (threadIdx.x < 8) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  for (int q = threadIdx.x; q < npairs; q += blockDim.x) {
     const PairState& s = st[ids[q]];
-    cnt[s.phase]++;
-    if (s.phase == PH_SOLVE && s.gm_restart) restart++;
-    if (!s.valid) invalid++;
+    atomicAdd(&cnt[s.phase], 1);  // phases are 0..5
+    if (s.phase == PH_SOLVE && s.gm_restart) atomicAdd(&cnt[6], 1);
+    if (!s.valid) atomicAdd(&cnt[7], 1);
   }
-  for (int k = 0; k < 6; ++k) out[k] = cnt[k];
-  out[6] = restart;
-  out[7] = invalid;
+  __syncthreads();
+  if (threadIdx.x < 8) out[threadIdx.x] = cnt[threadIdx.x];
 }
 
 // ---------------------------------------------------------------------------
@@ -396,12 +395,12 @@ int residual_tile_x(int n) { return (n % 64 == 0) ? 64 : ((n % 32 == 0) ? 32 : 1
 
 int residual_blocks(int n) { return (n / residual_tile_x(n)) * (n / MA_RES_TY); }
 
-void launch_residual(const LaunchCtx& c, int n, int npairs, int step_mode, hipStream_t st) {
+void launch_residual(const LaunchCtx& c, int n, int npairs, int step_mode, hipStream_t st, const TimedLaunch& ev) {
   const int tx = residual_tile_x(n);
   dim3 grid(residual_blocks(n), npairs);
-  if (tx == 64) hipLaunchKernelGGL(k_residual<64>, grid, dim3(MA_BLOCK), 0, st, c);
-  else if (tx == 32) hipLaunchKernelGGL(k_residual<32>, grid, dim3(MA_BLOCK), 0, st, c);
-  else hipLaunchKernelGGL(k_residual<16>, grid, dim3(MA_BLOCK), 0, st, c);
+  if (tx == 64) MA_LAUNCH(ev, k_residual<64>, grid, dim3(MA_BLOCK), st, c);
+  else if (tx == 32) MA_LAUNCH(ev, k_residual<32>, grid, dim3(MA_BLOCK), st, c);
+  else MA_LAUNCH(ev, k_residual<16>, grid, dim3(MA_BLOCK), st, c);
   hipLaunchKernelGGL(k_residual_finalize, dim3(1, npairs), dim3(MA_BLOCK), 0, st, c, residual_blocks(n),
                      step_mode);
 }
@@ -424,5 +423,5 @@ void launch_outputs(const LaunchCtx& c, int n, int npairs, hipStream_t st) {
 }
 
 void launch_summary(const PairState* s, const int* ids, int npairs, int* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_summary, dim3(1), dim3(64), 0, st, s, ids, npairs, out);
+  hipLaunchKernelGGL(k_summary, dim3(1), dim3(256), 0, st, s, ids, npairs, out);
 }

@@ -29,9 +29,9 @@ __host__ __device__ constexpr int pow2_div(int limit, int m) {
   while (p * 2 <= limit && m % (p * 2) == 0) p *= 2;
   return p;
 }
-__host__ __device__ constexpr int round_block(int t) {
+__host__ __device__ constexpr int round_block(int t, int cap = 256) {
   int b = ((t + 63) / 64) * 64;
-  return b < 64 ? 64 : (b > 256 ? 256 : b);
+  return b < 64 ? 64 : (b > cap ? cap : b);
 }
 
 // launch geometry per grid size
@@ -43,7 +43,7 @@ struct Cfg {
   static constexpr int B_CPB = pow2_div(4096 / N > 0 ? 4096 / N : 1, NH);   // columns per block
   static constexpr int B_BLOCK = round_block(B_CPB * N / 8);
   static constexpr int C_PPB = pow2_div(512 / N > 0 ? 512 / N : 1, NH);     // row pairs per block
-  static constexpr int C_BLOCK = round_block(5 * C_PPB * N / 8);
+  static constexpr int C_BLOCK = round_block(5 * C_PPB * N / 8, 320);  // one butterfly per thread at 512
   static_assert((N * B_CPB) % B_BLOCK == 0, "column pass: whole elements per thread");
   static_assert(B_BLOCK % B_CPB == 0, "column pass: fixed column per thread");
 };
@@ -461,17 +461,28 @@ __global__ __launch_bounds__(Cfg<N>::C_BLOCK) void k_passC(LaunchCtx c, int mode
   }
 }
 
-// h[l][j] = <w, v_l> for l <= j from the pass-C partials (one block per pair)
+// h[l][j] = <w, v_l> for l <= j from the pass-C partials (one block per pair).
+// Lane l of group g sums blocks g, g + 8, ...; the loads are independent.
 __global__ __launch_bounds__(256) void k_dots_finalize(LaunchCtx c, int j, int nblk) {
   const int p = pair_of_block(c);
   const PairDesc& d = c.desc[p];
   PairState& s = c.st[p];
   if (!(s.phase == PH_SOLVE && s.gm_running)) return;
   __shared__ double red[8][32];
-  const int l = threadIdx.x & 31, grp = threadIdx.x >> 5;  // 8 groups of 32 lanes
+  const int l = threadIdx.x & 31, grp = threadIdx.x >> 5;
   double t = 0.0;
-  if (l <= j)
-    for (int b = grp; b < nblk; b += 8) t += d.part[(long)b * (MA_MMAX + 1) + l];
+  if (l <= j) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int b = grp;
+    for (; b + 24 < nblk; b += 32) {
+      a0 += d.part[(long)b * (MA_MMAX + 1) + l];
+      a1 += d.part[(long)(b + 8) * (MA_MMAX + 1) + l];
+      a2 += d.part[(long)(b + 16) * (MA_MMAX + 1) + l];
+      a3 += d.part[(long)(b + 24) * (MA_MMAX + 1) + l];
+    }
+    for (; b < nblk; b += 8) a0 += d.part[(long)b * (MA_MMAX + 1) + l];
+    t = (a0 + a1) + (a2 + a3);
+  }
   red[grp][l] = t;
   __syncthreads();
   if (threadIdx.x <= j) {
@@ -566,20 +577,22 @@ int passC_blocks(int n) {
   }
 }
 
-void launch_passA(const LaunchCtx& c, int n, int npairs, int mode, int jn, const float2* tw, hipStream_t st) {
-  launch_passA_only(c, n, npairs, mode, jn, tw, st);
+void launch_passA(const LaunchCtx& c, int n, int npairs, int mode, int jn, const float2* tw, hipStream_t st,
+                  const TimedLaunch& ev) {
+  launch_passA_only(c, n, npairs, mode, jn, tw, st, ev);
   if (mode == PA_ARNOLDI)
     hipLaunchKernelGGL(k_arnoldi_finalize, dim3(1, npairs), dim3(256), 0, st, c, jn, passA_blocks(n));
   else if (mode == PA_PLAIN)
     hipLaunchKernelGGL(k_cycle_begin, dim3(1, npairs), dim3(64), 0, st, c);
 }
 
-void launch_passA_only(const LaunchCtx& c, int n, int npairs, int mode, int jn, const float2* tw, hipStream_t st) {
+void launch_passA_only(const LaunchCtx& c, int n, int npairs, int mode, int jn, const float2* tw, hipStream_t st,
+                       const TimedLaunch& ev) {
   switch (n) {
 #define X(NV)                                                                                  \
   case NV:                                                                                     \
-    hipLaunchKernelGGL(k_passA<NV>, dim3(NV / 2 / Cfg<NV>::A_PPB, npairs), dim3(Cfg<NV>::A_BLOCK), 0, \
-                       st, c, mode, jn, tw);                                                   \
+    MA_LAUNCH(ev, k_passA<NV>, dim3(NV / 2 / Cfg<NV>::A_PPB, npairs), dim3(Cfg<NV>::A_BLOCK), st, c, \
+              mode, jn, tw);                                                                   \
     break;
     MA_FOR_EACH_N(X)
 #undef X
@@ -587,12 +600,13 @@ void launch_passA_only(const LaunchCtx& c, int n, int npairs, int mode, int jn, 
   }
 }
 
-void launch_passB(const LaunchCtx& c, int n, int npairs, int mode, int j, const float2* tw, hipStream_t st) {
+void launch_passB(const LaunchCtx& c, int n, int npairs, int mode, int j, const float2* tw, hipStream_t st,
+                  const TimedLaunch& ev) {
   switch (n) {
 #define X(NV)                                                                                  \
   case NV:                                                                                     \
-    hipLaunchKernelGGL(k_passB<NV>, dim3(NV / 2 / Cfg<NV>::B_CPB, npairs), dim3(Cfg<NV>::B_BLOCK), 0, \
-                       st, c, mode, j, tw);                                                    \
+    MA_LAUNCH(ev, k_passB<NV>, dim3(NV / 2 / Cfg<NV>::B_CPB, npairs), dim3(Cfg<NV>::B_BLOCK), st, c, \
+              mode, j, tw);                                                                    \
     break;
     MA_FOR_EACH_N(X)
 #undef X
@@ -600,18 +614,20 @@ void launch_passB(const LaunchCtx& c, int n, int npairs, int mode, int j, const 
   }
 }
 
-void launch_passC(const LaunchCtx& c, int n, int npairs, int mode, int j, const float2* tw, hipStream_t st) {
-  launch_passC_only(c, n, npairs, mode, j, tw, st);
+void launch_passC(const LaunchCtx& c, int n, int npairs, int mode, int j, const float2* tw, hipStream_t st,
+                  const TimedLaunch& ev) {
+  launch_passC_only(c, n, npairs, mode, j, tw, st, ev);
   if (mode == PC_MATVEC)
     hipLaunchKernelGGL(k_dots_finalize, dim3(1, npairs), dim3(256), 0, st, c, j, passC_blocks(n));
 }
 
-void launch_passC_only(const LaunchCtx& c, int n, int npairs, int mode, int j, const float2* tw, hipStream_t st) {
+void launch_passC_only(const LaunchCtx& c, int n, int npairs, int mode, int j, const float2* tw, hipStream_t st,
+                       const TimedLaunch& ev) {
   switch (n) {
 #define X(NV)                                                                                  \
   case NV:                                                                                     \
-    hipLaunchKernelGGL(k_passC<NV>, dim3(NV / 2 / Cfg<NV>::C_PPB, npairs), dim3(Cfg<NV>::C_BLOCK), 0, \
-                       st, c, mode, j, tw);                                                    \
+    MA_LAUNCH(ev, k_passC<NV>, dim3(NV / 2 / Cfg<NV>::C_PPB, npairs), dim3(Cfg<NV>::C_BLOCK), st, c, \
+              mode, j, tw);                                                                    \
     break;
     MA_FOR_EACH_N(X)
 #undef X

@@ -1,6 +1,21 @@
 // Host-side launchers of the device kernels (one call per size class).
 #pragma once
+#include <hip/hip_ext.h>
+
 #include "common.h"
+
+// Optional start/stop events stamped at the kernel's own start and end
+// (hipExtLaunchKernelGGL), used by the timing hook.
+struct TimedLaunch {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+#define MA_LAUNCH(ev, kernel, grid, block, st, ...)                                           \
+  do {                                                                                        \
+    if ((ev).start)                                                                           \
+      hipExtLaunchKernelGGL(kernel, grid, block, 0, st, (ev).start, (ev).stop, 0, __VA_ARGS__); \
+    else                                                                                      \
+      hipLaunchKernelGGL(kernel, grid, block, 0, st, __VA_ARGS__);                            \
+  } while (0)
 
 // pass modes
 enum : int {
@@ -17,7 +32,8 @@ void launch_setup(const LaunchCtx& c, int n, int npairs, hipStream_t st);
 void launch_setup_fields(const LaunchCtx& c, int n, int npairs, hipStream_t st);
 int residual_tile_x(int n);
 int residual_blocks(int n);
-void launch_residual(const LaunchCtx& c, int n, int npairs, int step_mode, hipStream_t st);
+void launch_residual(const LaunchCtx& c, int n, int npairs, int step_mode, hipStream_t st,
+                     const TimedLaunch& ev = TimedLaunch());
 void launch_residual_shift(const LaunchCtx& c, int n, float* out, hipStream_t st);
 void launch_step_update(const LaunchCtx& c, int n, int npairs, hipStream_t st);
 void launch_outputs(const LaunchCtx& c, int n, int npairs, hipStream_t st);
@@ -27,9 +43,14 @@ void launch_summary(const PairState* s, const int* ids, int npairs, int* out, hi
 bool fft_size_supported(int n);
 int passA_blocks(int n);
 int passC_blocks(int n);
-void launch_passA(const LaunchCtx& c, int n, int npairs, int mode, int jn, const float2* tw, hipStream_t st);
-void launch_passA_only(const LaunchCtx& c, int n, int npairs, int mode, int jn, const float2* tw, hipStream_t st);
-void launch_passB(const LaunchCtx& c, int n, int npairs, int mode, int j, const float2* tw, hipStream_t st);
-void launch_passC(const LaunchCtx& c, int n, int npairs, int mode, int j, const float2* tw, hipStream_t st);
-void launch_passC_only(const LaunchCtx& c, int n, int npairs, int mode, int j, const float2* tw, hipStream_t st);
+void launch_passA(const LaunchCtx& c, int n, int npairs, int mode, int jn, const float2* tw, hipStream_t st,
+                  const TimedLaunch& ev = TimedLaunch());
+void launch_passA_only(const LaunchCtx& c, int n, int npairs, int mode, int jn, const float2* tw, hipStream_t st,
+                  const TimedLaunch& ev = TimedLaunch());
+void launch_passB(const LaunchCtx& c, int n, int npairs, int mode, int j, const float2* tw, hipStream_t st,
+                  const TimedLaunch& ev = TimedLaunch());
+void launch_passC(const LaunchCtx& c, int n, int npairs, int mode, int j, const float2* tw, hipStream_t st,
+                  const TimedLaunch& ev = TimedLaunch());
+void launch_passC_only(const LaunchCtx& c, int n, int npairs, int mode, int j, const float2* tw, hipStream_t st,
+                  const TimedLaunch& ev = TimedLaunch());
 void launch_restart(const LaunchCtx& c, int n, int npairs, hipStream_t st);

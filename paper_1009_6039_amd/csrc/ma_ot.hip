@@ -215,25 +215,21 @@ int build_classes(ma_plan* P, const std::vector<int>& ns, std::vector<Class>& cl
   return MA_OK;
 }
 
-// event brackets around launches of the timed class
-bool prof_begin(ma_plan* P, int kind, hipStream_t st) {
-  if (kind == MA_PROF_NONE || kind != P->prof_kind) return false;
-  if ((int)P->ev.size() < 2 * (P->ev_used + 1)) {
-    for (int k = 0; k < 2; ++k) {
-      hipEvent_t e;
-      if (hipEventCreate(&e) != hipSuccess) return false;
-      P->ev.push_back(e);
-    }
+// events stamped at the start and end of each launch of the timed class
+TimedLaunch prof_events(ma_plan* P, int kind) {
+  TimedLaunch ev;
+  if (kind == MA_PROF_NONE || kind != P->prof_kind) return ev;
+  while ((int)P->ev.size() < 2 * (P->ev_used + 1)) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return TimedLaunch();
+    P->ev.push_back(e);
   }
-  hipEventRecord(P->ev[2 * P->ev_used], st);
-  return true;
-}
-void prof_end(ma_plan* P, bool on, hipStream_t st) {
-  if (!on) return;
-  hipEventRecord(P->ev[2 * P->ev_used + 1], st);
+  ev.start = P->ev[2 * P->ev_used];
+  ev.stop = P->ev[2 * P->ev_used + 1];
   P->ev_used++;
+  return ev;
 }
-// after a stream synchronisation: fold the recorded brackets into the totals
+// after a stream synchronisation: fold the recorded launches into the totals
 void prof_flush(ma_plan* P) {
   for (int i = 0; i < P->ev_used; ++i) {
     float ms = 0.f;
@@ -244,24 +240,20 @@ void prof_flush(ma_plan* P) {
 }
 
 void L_res(ma_plan* P, const Class& c, int step_mode, hipStream_t st) {
-  bool on = prof_begin(P, MA_PROF_RESIDUAL, st);
-  launch_residual(make_ctx(P, c.d_ids, MA_PROF_RESIDUAL), c.n, (int)c.ids.size(), step_mode, st);
-  prof_end(P, on, st);
+  launch_residual(make_ctx(P, c.d_ids, MA_PROF_RESIDUAL), c.n, (int)c.ids.size(), step_mode, st,
+                  prof_events(P, MA_PROF_RESIDUAL));
 }
 void L_A(ma_plan* P, const Class& c, int mode, int jn, hipStream_t st) {
-  bool on = prof_begin(P, MA_PROF_ROW_A, st);
-  launch_passA(make_ctx(P, c.d_ids, MA_PROF_ROW_A), c.n, (int)c.ids.size(), mode, jn, c.tw, st);
-  prof_end(P, on, st);
+  launch_passA(make_ctx(P, c.d_ids, MA_PROF_ROW_A), c.n, (int)c.ids.size(), mode, jn, c.tw, st,
+               prof_events(P, MA_PROF_ROW_A));
 }
 void L_B(ma_plan* P, const Class& c, int mode, int j, hipStream_t st) {
-  bool on = prof_begin(P, MA_PROF_COLUMN, st);
-  launch_passB(make_ctx(P, c.d_ids, MA_PROF_COLUMN), c.n, (int)c.ids.size(), mode, j, c.tw, st);
-  prof_end(P, on, st);
+  launch_passB(make_ctx(P, c.d_ids, MA_PROF_COLUMN), c.n, (int)c.ids.size(), mode, j, c.tw, st,
+               prof_events(P, MA_PROF_COLUMN));
 }
 void L_C(ma_plan* P, const Class& c, int mode, int j, hipStream_t st) {
-  bool on = prof_begin(P, MA_PROF_ROW_C, st);
-  launch_passC(make_ctx(P, c.d_ids, MA_PROF_ROW_C), c.n, (int)c.ids.size(), mode, j, c.tw, st);
-  prof_end(P, on, st);
+  launch_passC(make_ctx(P, c.d_ids, MA_PROF_ROW_C), c.n, (int)c.ids.size(), mode, j, c.tw, st,
+               prof_events(P, MA_PROF_ROW_C));
 }
 
 int read_summary(ma_plan* P, int npairs, hipStream_t st) {
