@@ -22,4 +22,4 @@ routine, brute force, or a value the paper prints, except where a module header
 says "parity unpinned".
 """
 
-from . import fd, interp, ma  # noqa: F401
+from . import cnn, fd, interp, ma  # noqa: F401

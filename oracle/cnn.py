@@ -1,0 +1,133 @@
+"""The warm-start network in FP64: periodic 3x3 convolutions, ReLU, MSE loss, Adam.
+
+TEST INFRASTRUCTURE ONLY (see the package header).
+
+The network is not part of the paper; it supplies the Newton initial guess.
+Layers l = 0..L-1: z_l = conv3x3_periodic(h_l, W_l) + b_l, h_{l+1} = relu(z_l) for
+l < L-1 and h_L = z_{L-1} (no activation on the output).  Input channels are
+(f - 1, g - 1) for densities scaled to mean one.  The output c approximates the
+fourth-order difference Laplacian of the solver's potential; the initial guess is
+psi0 = (discrete Laplacian)^{-1} c with zero mean (the head, applied outside the
+network).
+
+Convolution convention: out[co, i, j] = b[co] + sum_{ci, a, b} W[co, ci, a, b] *
+x[ci, (i + a - 1) mod H, (j + b - 1) mod W], a, b in {0, 1, 2}.
+
+Optional BF16 emulation (`bf16=True`): the GPU kernels store inputs, weights and
+inter-layer activations in BF16 (round to nearest even) and accumulate in FP32;
+the oracle then rounds the same tensors to BF16 values and accumulates in FP64.
+
+Pins: tests/test_oracle_cnn.py (convolution against a brute-force loop and
+against translation invariance; gradients against central differences; BF16
+rounding against hand-computed bit patterns; Adam against its published update
+written for one scalar).
+"""
+
+import numpy as np
+
+
+def bf16_round(x):
+    """Round to the nearest BF16 value (ties to even), returned as float64."""
+    a = np.asarray(x, dtype=np.float32)
+    u = a.view(np.uint32).astype(np.uint64)
+    lsb = (u >> 16) & 1
+    r = ((u + 0x7FFF + lsb) >> 16) << 16
+    nan = np.isnan(a)
+    out = r.astype(np.uint32).view(np.float32).astype(np.float64)
+    out[nan] = np.nan
+    return out
+
+
+def conv3x3(x, W, b):
+    """Periodic 3x3 convolution of x (C_in, H, W) with W (C_out, C_in, 3, 3) plus bias."""
+    C_out = W.shape[0]
+    H, Wd = x.shape[1], x.shape[2]
+    out = np.zeros((C_out, H, Wd))
+    for a in range(3):
+        for c in range(3):
+            xs = np.roll(np.roll(x, -(a - 1), axis=1), -(c - 1), axis=2)  # xs[:, i, j] = x[:, i+a-1, j+c-1]
+            out += np.tensordot(W[:, :, a, c], xs, axes=([1], [0]))
+    return out + b[:, None, None]
+
+
+def conv3x3_input_grad(dz, W):
+    """d(sum dz * conv(x))/dx: the correlation with the flipped kernel."""
+    C_in = W.shape[1]
+    H, Wd = dz.shape[1], dz.shape[2]
+    dx = np.zeros((C_in, H, Wd))
+    for a in range(3):
+        for c in range(3):
+            t = np.tensordot(W[:, :, a, c], dz, axes=([0], [0]))  # (C_in, H, W) at output positions
+            dx += np.roll(np.roll(t, a - 1, axis=1), c - 1, axis=2)
+    return dx
+
+
+def conv3x3_weight_grad(dz, x):
+    """d(sum dz * conv(x))/dW and /db."""
+    C_out, C_in = dz.shape[0], x.shape[0]
+    dW = np.zeros((C_out, C_in, 3, 3))
+    for a in range(3):
+        for c in range(3):
+            xs = np.roll(np.roll(x, -(a - 1), axis=1), -(c - 1), axis=2)
+            dW[:, :, a, c] = np.tensordot(dz, xs, axes=([1, 2], [1, 2]))
+    return dW, dz.sum(axis=(1, 2))
+
+
+def init_params(channels=32, layers=8, c_in=2, c_out=1, seed=0):
+    """He-normal weights scaled by 1/sqrt(9 C_in), zero biases; returns a list of (W, b)."""
+    rng = np.random.default_rng(seed)
+    chans = [c_in] + [channels] * (layers - 1) + [c_out]
+    params = []
+    for l in range(layers):
+        ci, co = chans[l], chans[l + 1]
+        W = rng.standard_normal((co, ci, 3, 3)) * np.sqrt(2.0 / (9 * ci))
+        if l == layers - 1:
+            W *= 0.1
+        params.append((W, np.zeros(co)))
+    return params
+
+
+def forward(x, params, bf16=False):
+    """Returns (output c, cache of layer inputs and pre-activations)."""
+    r = bf16_round if bf16 else (lambda v: v)
+    h = r(x)
+    cache = []
+    L = len(params)
+    for l, (W, b) in enumerate(params):
+        z = conv3x3(h, r(W), b)
+        cache.append((h, z))
+        if l < L - 1:
+            h = r(np.maximum(z, 0.0))
+        else:
+            h = z
+    return h, cache
+
+
+def mse(c, t):
+    return float(np.mean((c - t) ** 2))
+
+
+def backward(c, t, cache, params, bf16=False):
+    """Gradients of mse(c, t) with respect to every (W, b)."""
+    r = bf16_round if bf16 else (lambda v: v)
+    dh = 2.0 * (c - t) / c.size
+    grads = [None] * len(params)
+    L = len(params)
+    for l in range(L - 1, -1, -1):
+        h, z = cache[l]
+        dz = dh if l == L - 1 else dh * (z > 0)
+        W = r(params[l][0])
+        dW, db = conv3x3_weight_grad(dz, h)
+        grads[l] = (dW, db)
+        if l > 0:
+            dh = conv3x3_input_grad(dz, W)
+    return grads
+
+
+def adam_step(p, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam update (Kingma and Ba, 2015) with bias correction; returns (p, m, v)."""
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    mhat = m / (1.0 - beta1 ** t)
+    vhat = v / (1.0 - beta2 ** t)
+    return p - lr * mhat / (np.sqrt(vhat) + eps), m, v

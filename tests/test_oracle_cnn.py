@@ -1,0 +1,140 @@
+"""Pins for oracle.cnn: convolution, gradients, BF16 rounding, Adam."""
+
+import numpy as np
+import pytest
+
+from oracle import cnn
+
+
+def brute_conv(x, W, b):
+    C_out, C_in = W.shape[:2]
+    H, Wd = x.shape[1:]
+    out = np.zeros((C_out, H, Wd))
+    for co in range(C_out):
+        for i in range(H):
+            for j in range(Wd):
+                s = b[co]
+                for ci in range(C_in):
+                    for a in range(3):
+                        for c in range(3):
+                            s += W[co, ci, a, c] * x[ci, (i + a - 1) % H, (j + c - 1) % Wd]
+                out[co, i, j] = s
+    return out
+
+
+def test_convolution_matches_brute_force():
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal((3, 5, 6))
+    W = rng.standard_normal((2, 3, 3, 3))
+    b = rng.standard_normal(2)
+    assert np.allclose(cnn.conv3x3(x, W, b), brute_conv(x, W, b), atol=1e-12)
+
+
+def test_convolution_commutes_with_periodic_shifts():
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((4, 8, 8))
+    W = rng.standard_normal((3, 4, 3, 3))
+    b = rng.standard_normal(3)
+    sh = lambda v: np.roll(np.roll(v, 3, axis=1), -2, axis=2)  # noqa: E731
+    assert np.allclose(cnn.conv3x3(sh(x), W, b), sh(cnn.conv3x3(x, W, b)), atol=1e-12)
+
+
+def _loss(params, x, t):
+    c, _ = cnn.forward(x, params)
+    return cnn.mse(c, t)
+
+
+def test_gradients_match_central_differences():
+    rng = np.random.default_rng(2)
+    params = cnn.init_params(channels=4, layers=3, c_in=2, c_out=1, seed=3)
+    params = [(W, rng.standard_normal(b.shape) * 0.1) for W, b in params]
+    x = rng.standard_normal((2, 8, 8))
+    t = rng.standard_normal((1, 8, 8))
+    c, cache = cnn.forward(x, params)
+    grads = cnn.backward(c, t, cache, params)
+    eps = 1e-6
+    for l in range(len(params)):
+        W, b = params[l]
+        for idx in [tuple(rng.integers(0, s) for s in W.shape) for _ in range(6)]:
+            Wp, Wm = W.copy(), W.copy()
+            Wp[idx] += eps
+            Wm[idx] -= eps
+            pp = list(params)
+            pp[l] = (Wp, b)
+            lp = _loss(pp, x, t)
+            pp[l] = (Wm, b)
+            lm = _loss(pp, x, t)
+            fdv = (lp - lm) / (2 * eps)
+            assert grads[l][0][idx] == pytest.approx(fdv, rel=1e-5, abs=1e-9)
+        for k in range(b.shape[0]):
+            bp, bm = b.copy(), b.copy()
+            bp[k] += eps
+            bm[k] -= eps
+            pp = list(params)
+            pp[l] = (W, bp)
+            lp = _loss(pp, x, t)
+            pp[l] = (W, bm)
+            lm = _loss(pp, x, t)
+            assert grads[l][1][k] == pytest.approx((lp - lm) / (2 * eps), rel=1e-5, abs=1e-9)
+
+
+def test_input_gradient_matches_central_differences():
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal((3, 6, 7))
+    W = rng.standard_normal((2, 3, 3, 3))
+    b = np.zeros(2)
+    dz = rng.standard_normal((2, 6, 7))
+    dx = cnn.conv3x3_input_grad(dz, W)
+    eps = 1e-6
+    for idx in [(0, 0, 0), (1, 5, 6), (2, 3, 2), (0, 2, 5)]:
+        xp, xm = x.copy(), x.copy()
+        xp[idx] += eps
+        xm[idx] -= eps
+        fdv = (np.sum(dz * cnn.conv3x3(xp, W, b)) - np.sum(dz * cnn.conv3x3(xm, W, b))) / (2 * eps)
+        assert dx[idx] == pytest.approx(fdv, rel=1e-6)
+
+
+@pytest.mark.parametrize("value,expected", [
+    (1.0, 1.0),
+    (1.0 + 2.0 ** -8, 1.0),                      # tie: mantissa of 1.0 is even
+    (1.0 + 3 * 2.0 ** -8, 1.0 + 2.0 ** -6),      # tie between odd and even: to even
+    (1.0 + 2.0 ** -8 + 2.0 ** -20, 1.0 + 2.0 ** -7),
+    (3.14159265, 3.140625),
+    (-3.14159265, -3.140625),
+    (2.0 ** -130, 2.0 ** -130),                  # a subnormal that fits exactly
+    (0.0, 0.0),
+])
+def test_bf16_rounding(value, expected):
+    assert cnn.bf16_round(np.array([value]))[0] == expected
+
+
+def test_adam_first_step_moves_by_the_learning_rate():
+    # with bias correction the first step is lr * g / (|g| + eps)
+    p = np.array([1.0, -2.0, 0.5])
+    g = np.array([0.3, -4.0, 0.0])
+    p1, m, v = cnn.adam_step(p, g, np.zeros(3), np.zeros(3), 1, lr=0.01)
+    assert np.allclose(p1, p - 0.01 * g / (np.abs(g) + 1e-8), atol=1e-15)
+    assert p1[2] == p[2]
+
+
+def test_training_reduces_the_loss():
+    rng = np.random.default_rng(5)
+    params = cnn.init_params(channels=4, layers=2, seed=6)
+    x = rng.standard_normal((2, 8, 8))
+    t = 0.5 * x[:1] - 0.3 * x[1:]
+    ms = [(np.zeros_like(W), np.zeros_like(b)) for W, b in params]
+    vs = [(np.zeros_like(W), np.zeros_like(b)) for W, b in params]
+    c, _ = cnn.forward(x, params)
+    l0 = cnn.mse(c, t)
+    for step in range(1, 60):
+        c, cache = cnn.forward(x, params)
+        grads = cnn.backward(c, t, cache, params)
+        new = []
+        for l, ((W, b), (gW, gb)) in enumerate(zip(params, grads)):
+            W, mW, vW = cnn.adam_step(W, gW, ms[l][0], vs[l][0], step, 0.01)
+            b, mb, vb = cnn.adam_step(b, gb, ms[l][1], vs[l][1], step, 0.01)
+            ms[l], vs[l] = (mW, mb), (vW, vb)
+            new.append((W, b))
+        params = new
+    c, _ = cnn.forward(x, params)
+    assert cnn.mse(c, t) < 0.2 * l0
