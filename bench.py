@@ -31,6 +31,7 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--gmres-tol", type=float, default=0.1)
     ap.add_argument("--damping-policy", default="backtrack")
+    ap.add_argument("--symbol", default="spectral", help="spectral (the paper) or fd4 (option)")
     ap.add_argument("--profile-class", default="row_c",
                     help="kernel class timed for the roofline: residual, row_a, column, row_c")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -59,7 +60,7 @@ def cpu_baseline(f, g, args):
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
         psi, _, rep = ma.solve(f, g, tau=1.0, tol=args.tol, damping_policy=args.damping_policy,
-                               gmres_tol=args.gmres_tol, max_newton=300)
+                               gmres_tol=args.gmres_tol, max_newton=300, symbol=args.symbol)
         dt = time.perf_counter() - t0
     return psi, rep, dt
 
@@ -84,7 +85,7 @@ def main():
     fs = [torch.from_numpy(f).cuda() for f, _ in host_pairs]
     gs = [torch.from_numpy(g).cuda() for _, g in host_pairs]
     plan = maot.Plan(n_max=N, batch_capacity=B, damping_policy=args.damping_policy,
-                     gmres_tol=args.gmres_tol, max_newton=300)
+                     gmres_tol=args.gmres_tol, max_newton=300, symbol=args.symbol)
 
     def step():
         psis, _, reps = plan.solve_batched(fs, gs, damping=1.0, tol=args.tol)
@@ -124,7 +125,7 @@ def main():
         "config": {"workload": "blob-density pairs %dx%d (8 periodic Gaussian blobs, 0.1 floor), "
                                "batch %d per step, rms residual %.0e, plain zero init" % (N, N, B, args.tol),
                    "n": N, "batch": B, "tol": args.tol, "damping_policy": args.damping_policy,
-                   "gmres_tol": args.gmres_tol, "gmres_m": 10, "init": "zero"},
+                   "gmres_tol": args.gmres_tol, "gmres_m": 10, "init": "zero", "symbol": args.symbol},
         "newton_iters_mean": float(np.mean([r["newton_iters"] for r in reps])),
         "gmres_iters_mean": float(np.mean([r["gmres_iters"] for r in reps])),
         "backtracks_mean": float(np.mean([r["backtracks"] for r in reps])),

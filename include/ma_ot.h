@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define MA_OT_ABI_VERSION 1
+#define MA_OT_ABI_VERSION 2
 
 /* return / status codes */
 #define MA_OK 0           /* converged: rms residual <= tol                           */
@@ -53,6 +53,12 @@ extern "C" {
  * the caller's value after each accepted step.  Both keep tau >= 1. */
 #define MA_DAMP_FIXED 0
 #define MA_DAMP_BACKTRACK 1
+/* multipliers of the derivatives in the linear solve: the paper's 2 pi i k and
+ * -(2 pi k)^2 (Section 4.2), or the symbols of the fourth-order differences used for
+ * the residual (an option: the linear solve then uses the Jacobian of the discrete
+ * residual; the fixed point is unchanged) */
+#define MA_SYMBOL_SPECTRAL 0
+#define MA_SYMBOL_FD4 1
 
 typedef struct ma_options {
   int max_newton;          /* Newton iterations before MA_ENOCONV (100)              */
@@ -63,6 +69,7 @@ typedef struct ma_options {
   int op_mode;             /* MA_OP_*                                                */
   int damping_policy;      /* MA_DAMP_*                                              */
   int max_backtrack;       /* step halvings per Newton step before failing (12)      */
+  int symbol;              /* MA_SYMBOL_* (MA_SYMBOL_SPECTRAL)                       */
 } ma_options;
 
 typedef struct ma_report {

@@ -160,19 +160,34 @@ def averaged(coef):
 # Strain's FFT operator (Section 4.2)
 # ---------------------------------------------------------------------------
 
-def multipliers(N):
-    """Spectral multipliers of d/dx and d^2/dx^2 in FFT order (reading P8)."""
+def multipliers(N, symbol="spectral"):
+    """Multipliers of d/dx and d^2/dx^2 in FFT order.
+
+    "spectral" (the paper, Section 4.2): 2 pi i k and -(2 pi k)^2, reading P8 at -N/2.
+    "fd4" (an option, not the paper): the symbols of the fourth-order differences of
+    Section 4, i (8 sin t - sin 2t)/(6h) and (32 cos t - 2 cos 2t - 30)/(12 h^2), t = 2 pi k h,
+    so that the linear solve uses the Jacobian of the discrete residual.
+    """
     k = np.fft.fftfreq(N, d=1.0 / N)
+    if symbol == "fd4":
+        h = 1.0 / N
+        t = 2.0 * np.pi * k * h
+        m1 = 1j * (8.0 * np.sin(t) - np.sin(2.0 * t)) / (6.0 * h)
+        m1[k == -N // 2] = 0.0
+        m2 = (32.0 * np.cos(t) - 2.0 * np.cos(2.0 * t) - 30.0) / (12.0 * h * h)
+        return m1, m2
+    if symbol != "spectral":
+        raise ValueError("symbol must be 'spectral' or 'fd4'")
     m1 = 2j * np.pi * k
     m1[k == -N // 2] = 0.0
     m2 = -(2.0 * np.pi * k) ** 2
     return m1, m2
 
 
-def symbol(abar, N):
+def symbol(abar, N, symbol="spectral"):
     """rhobar(k): the inverse symbol of the averaged operator, zero where the symbol is 0."""
     a11, a12, a22, b1, b2 = abar
-    m1, m2 = multipliers(N)
+    m1, m2 = multipliers(N, symbol)
     K1 = m1[:, None]
     K2 = m1[None, :]
     S = (a11 * m2[:, None] + 2.0 * a12 * (K1 * K2) + a22 * m2[None, :]
@@ -185,10 +200,10 @@ def symbol(abar, N):
     return rho
 
 
-def strain_apply(v, coef, rho):
+def strain_apply(v, coef, rho, symbol="spectral"):
     """A v = L Lbar^{-1} v = sum a_ij alpha_ij + sum b_i beta_i (Section 4.2)."""
     N = v.shape[0]
-    m1, m2 = multipliers(N)
+    m1, m2 = multipliers(N, symbol)
     a11, a12, a22, b1, b2 = coef
     s = rho * np.fft.fft2(v)
     alpha11 = np.fft.ifft2(m2[:, None] * s).real
@@ -277,20 +292,22 @@ class Report(dict):
     __getattr__ = dict.__getitem__
 
 
-def newton_direction(ev, prob, rhs_scale, op_mode, gmres_m, gmres_tol, gmres_max_restarts):
+def newton_direction(ev, prob, rhs_scale, op_mode, gmres_m, gmres_tol, gmres_max_restarts,
+                     symbol_kind="spectral"):
     """theta solving D M theta = r * rhs_scale by Strain's method; returns (theta, its)."""
     coef = coefficients(ev, op_mode)
     abar = averaged(coef)
-    rho = symbol(abar, prob.N)
+    rho = symbol(abar, prob.N, symbol_kind)
     rhs = ev.r * rhs_scale
-    sigma, its, _ = gmres(lambda v: strain_apply(v, coef, rho), rhs,
+    sigma, its, _ = gmres(lambda v: strain_apply(v, coef, rho, symbol_kind), rhs,
                           m=gmres_m, tol=gmres_tol, max_restarts=gmres_max_restarts)
     return lbar_inverse(sigma, rho), its
 
 
 def solve(f, g, tau=1.0, tol=1e-6, psi0=None, max_newton=100, gmres_m=10,
           gmres_tol=1e-4, gmres_max_restarts=20, interp="bilinear", op_mode=0,
-          damping_policy="fixed", max_backtrack=12, g_analytic=None, history=False):
+          damping_policy="fixed", max_backtrack=12, g_analytic=None, history=False,
+          symbol="spectral"):
     """Damped Newton (eq. linma) with Strain's linear solver (Section 4.2).
 
     Returns (psi, map, report): psi is the mean-zero potential u on the grid, map is
@@ -327,7 +344,7 @@ def solve(f, g, tau=1.0, tol=1e-6, psi0=None, max_newton=100, gmres_m=10,
             status = ENOCONV
             break
         theta, its = newton_direction(ev, prob, 1.0 / tau_cur, op_mode, gmres_m,
-                                      gmres_tol, gmres_max_restarts)
+                                      gmres_tol, gmres_max_restarts, symbol)
         gm_total += its
         n += 1
         if damping_policy == "fixed":

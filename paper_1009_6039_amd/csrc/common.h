@@ -86,6 +86,7 @@ struct LaunchCtx {
   int m;                // GMRES restart length
   int max_newton, max_restarts, max_backtrack, damping_policy, interp, op_mode;
   double gmres_tol;
+  const float2* mt;  // per-wavenumber multipliers (Im d/dx, d^2/dx^2) of the selected symbol
   unsigned long long* prof_bytes;  // algorithmic-byte counter of the timed class, or null
 };
 

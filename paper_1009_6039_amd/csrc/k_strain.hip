@@ -48,23 +48,16 @@ struct Cfg {
   static_assert(B_BLOCK % B_CPB == 0, "column pass: fixed column per thread");
 };
 
-constexpr float TWO_PI = 6.28318530717958647692f;
-
 // rhobar(k): inverse symbol of the averaged operator (Section 4.2), zero at k = 0.
-// q: FFT index of k1; k2s: signed k2 (-N/2 for the Nyquist column)
+// q: FFT index of k1; q2: FFT index of k2 (N/2 for the Nyquist column).
+// mt[q] = (Im of the first-derivative multiplier, second-derivative multiplier).
 template <int N>
-__device__ __forceinline__ float2 rhobar(int q, int k2s, const float (&ab)[5]) {
-  const int k1s = q < N / 2 ? q : q - N;
-  const float d1a = (q == N / 2) ? 0.f : TWO_PI * (float)k1s;
-  const float t1 = TWO_PI * (float)k1s;
-  const float d2a = -t1 * t1;
-  const float d1b = (k2s == -N / 2) ? 0.f : TWO_PI * (float)k2s;
-  const float t2 = TWO_PI * (float)k2s;
-  const float d2b = -t2 * t2;
-  // S = a11 (i d1a)^2-type terms: second derivatives d2, mixed (i d1a)(i d1b) = -d1a d1b
-  const float re = ab[0] * d2a + ab[2] * d2b - 2.f * ab[1] * d1a * d1b;
-  const float im = ab[3] * d1a + ab[4] * d1b;
-  if (q == 0 && k2s == 0) return make_float2(0.f, 0.f);
+__device__ __forceinline__ float2 rhobar(int q, int q2, const float (&ab)[5], const float2* __restrict__ mt) {
+  if (q == 0 && q2 == 0) return make_float2(0.f, 0.f);
+  const float2 m1 = mt[q], m2 = mt[q2];
+  // S = a11 d2(k1) + 2 a12 (i d1(k1))(i d1(k2)) + a22 d2(k2) + i (b1 d1(k1) + b2 d1(k2))
+  const float re = ab[0] * m1.y + ab[2] * m2.y - 2.f * ab[1] * m1.x * m2.x;
+  const float im = ab[3] * m1.x + ab[4] * m2.x;
   const float den = re * re + im * im;
   return make_float2(re / den, -im / den);
 }
@@ -291,13 +284,14 @@ __global__ __launch_bounds__(Cfg<N>::B_BLOCK) void k_passB(LaunchCtx c, int mode
     const float2 z = S[q * CPB + cc], zm = S[qm * CPB + cc];
     float2 vq, vm;
     if (slot != 0) {
-      vq = cscale(cmul(rhobar<N>(q, slot, ab), z), scale);
-      vm = cscale(cmul(rhobar<N>(qm, slot, ab), zm), scale);
+      vq = cscale(cmul(rhobar<N>(q, slot, ab, c.mt), z), scale);
+      vm = cscale(cmul(rhobar<N>(qm, slot, ab, c.mt), zm), scale);
     } else {
       const float2 A = make_float2(0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y));
       const float2 B = make_float2(0.5f * (z.y + zm.y), -0.5f * (z.x - zm.x));
-      const float2 aq = cmul(rhobar<N>(q, 0, ab), A), bq = cmul(rhobar<N>(q, -NH, ab), B);
-      const float2 am = cmul(rhobar<N>(qm, 0, ab), cconj(A)), bm = cmul(rhobar<N>(qm, -NH, ab), cconj(B));
+      const float2 aq = cmul(rhobar<N>(q, 0, ab, c.mt), A), bq = cmul(rhobar<N>(q, NH, ab, c.mt), B);
+      const float2 am = cmul(rhobar<N>(qm, 0, ab, c.mt), cconj(A));
+      const float2 bm = cmul(rhobar<N>(qm, NH, ab, c.mt), cconj(B));
       vq = cscale(make_float2(aq.x - bq.y, aq.y + bq.x), scale);
       vm = cscale(make_float2(am.x - bm.y, am.y + bm.x), scale);
     }
@@ -313,15 +307,9 @@ __global__ __launch_bounds__(Cfg<N>::B_BLOCK) void k_passB(LaunchCtx c, int mode
     if (o != 0) {
       for (int e = threadIdx.x; e < N * CPB; e += BLOCK) {
         const int q = e / CPB;
-        const int k1s = q < NH ? q : q - N;
+        const float2 m = c.mt[q];
         const float2 v = S[e];
-        if (o == 1) {
-          const float w = (q == NH) ? 0.f : TWO_PI * (float)k1s;  // zero at the Nyquist wavenumber
-          Wb[e] = times_i(w, v);
-        } else {
-          const float w = TWO_PI * (float)k1s;
-          Wb[e] = cscale(v, -w * w);
-        }
+        Wb[e] = (o == 1) ? times_i(m.x, v) : cscale(v, m.y);
       }
       __syncthreads();
     }
@@ -397,9 +385,9 @@ __global__ __launch_bounds__(Cfg<N>::C_BLOCK) void k_passC(LaunchCtx c, int mode
     const float2 t0b = T0[ib], t1b = T1[ib], t2b = T2[ib];
     float2* L = lds + 5 * pp * N;
     if (k == 0) {
-      // DC (.x) and Nyquist (.y) are real; 2 pi i k2 vanishes at both, -(2 pi k2)^2 at DC
-      const float wn = TWO_PI * (float)NH;
-      const float d2n = -wn * wn;
+      // DC (.x) and Nyquist (.y) are real; the first-derivative multiplier vanishes at
+      // both, the second-derivative one at DC
+      const float d2n = c.mt[NH].y;
       L[0] = make_float2(t2a.x, t1a.x);
       L[NH] = make_float2(t2a.y, t1a.y);
       L[N] = make_float2(0.f, 0.f);
@@ -411,12 +399,12 @@ __global__ __launch_bounds__(Cfg<N>::C_BLOCK) void k_passC(LaunchCtx c, int mode
       L[4 * N] = make_float2(0.f, 0.f);
       L[4 * N + NH] = make_float2(d2n * t0a.y, d2n * t0b.y);
     } else {
-      const float w = TWO_PI * (float)k;
+      const float2 m = c.mt[k];
       put_pair<N>(L, k, t2a, t1a);
-      put_pair<N>(L + N, k, times_i(w, t1a), times_i(w, t0a));
+      put_pair<N>(L + N, k, times_i(m.x, t1a), times_i(m.x, t0a));
       put_pair<N>(L + 2 * N, k, t2b, t1b);
-      put_pair<N>(L + 3 * N, k, times_i(w, t1b), times_i(w, t0b));
-      put_pair<N>(L + 4 * N, k, cscale(t0a, -w * w), cscale(t0b, -w * w));
+      put_pair<N>(L + 3 * N, k, times_i(m.x, t1b), times_i(m.x, t0b));
+      put_pair<N>(L + 4 * N, k, cscale(t0a, m.y), cscale(t0b, m.y));
     }
   }
   __syncthreads();

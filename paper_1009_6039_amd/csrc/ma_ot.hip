@@ -29,6 +29,7 @@ struct Class {
   std::vector<int> ids;
   int* d_ids = nullptr;  // slice of the plan's id buffer
   const float2* tw = nullptr;
+  const float2* mt = nullptr;
 };
 
 }  // namespace
@@ -45,6 +46,7 @@ struct ma_plan {
   int* d_summary = nullptr;
   int* h_summary = nullptr;
   std::map<int, float2*> tw;
+  std::map<std::pair<int, int>, float2*> mt;  // (n, symbol) -> derivative multipliers
   std::vector<PairDesc> h_desc;
   std::vector<PairState> h_state;
   // timing hook
@@ -109,7 +111,8 @@ int validate_options(const ma_options& o) {
   if (o.max_newton < 0 || o.gmres_m < 1 || o.gmres_m > MA_MMAX || o.gmres_max_restarts < 0 ||
       !(o.gmres_tol > 0.0) || (o.interp != MA_INTERP_BILINEAR && o.interp != MA_INTERP_NEAREST) ||
       (o.op_mode != MA_OP_FULL && o.op_mode != MA_OP_NO_DRIFT) ||
-      (o.damping_policy != MA_DAMP_FIXED && o.damping_policy != MA_DAMP_BACKTRACK) || o.max_backtrack < 0)
+      (o.damping_policy != MA_DAMP_FIXED && o.damping_policy != MA_DAMP_BACKTRACK) || o.max_backtrack < 0 ||
+      (o.symbol != MA_SYMBOL_SPECTRAL && o.symbol != MA_SYMBOL_FD4))
     return MA_EINVAL;
   return MA_OK;
 }
@@ -128,6 +131,39 @@ int ensure_twiddles(ma_plan* P, int n) {
     return MA_EHIP;
   }
   P->tw[n] = d;
+  return MA_OK;
+}
+
+// (Im of the first-derivative multiplier, second-derivative multiplier) per FFT index q,
+// computed in FP64: 2 pi i k, -(2 pi k)^2 (Section 4.2), or the fourth-order
+// difference symbols i (8 sin t - sin 2t)/(6h), (-64 sin^2(t/2) + 4 sin^2 t)/(12 h^2),
+// t = 2 pi k h; the first-derivative multiplier is zero at k = -N/2 in both.
+int ensure_multipliers(ma_plan* P, int n, int symbol) {
+  const auto key = std::make_pair(n, symbol);
+  if (P->mt.count(key)) return MA_OK;
+  std::vector<float2> h(n);
+  for (int q = 0; q < n; ++q) {
+    const double ks = q < n / 2 ? q : q - n;
+    double d1, d2;
+    if (symbol == MA_SYMBOL_FD4) {
+      const double t = 2.0 * M_PI * ks / n;
+      d1 = (8.0 * std::sin(t) - std::sin(2.0 * t)) * n / 6.0;
+      const double s1 = std::sin(0.5 * t), s2 = std::sin(t);
+      d2 = (-64.0 * s1 * s1 + 4.0 * s2 * s2) * (double)n * n / 12.0;
+    } else {
+      d1 = 2.0 * M_PI * ks;
+      d2 = -(2.0 * M_PI * ks) * (2.0 * M_PI * ks);
+    }
+    if (q == n / 2) d1 = 0.0;
+    h[q] = make_float2((float)d1, (float)d2);
+  }
+  float2* d = nullptr;
+  if (hipMalloc(&d, sizeof(float2) * n) != hipSuccess) return MA_ENOMEM;
+  if (hipMemcpy(d, h.data(), sizeof(float2) * n, hipMemcpyHostToDevice) != hipSuccess) {
+    hipFree(d);
+    return MA_EHIP;
+  }
+  P->mt[key] = d;
   return MA_OK;
 }
 
@@ -162,17 +198,19 @@ int ensure_workspace(ma_plan* P, const std::vector<int>& ns) {
   for (int q = 0; q < np; ++q) carve(P->h_desc[q], p, ns[q], P->opt.gmres_m);
   for (int n : ns) {
     int e = ensure_twiddles(P, n);
+    if (!e) e = ensure_multipliers(P, n, P->opt.symbol);
     if (e) return e;
   }
   return MA_OK;
 }
 
-LaunchCtx make_ctx(const ma_plan* P, const int* d_ids, int kind = MA_PROF_NONE) {
+LaunchCtx make_ctx(const ma_plan* P, const Class& cl, int kind = MA_PROF_NONE) {
   LaunchCtx c;
   c.prof_bytes = (kind != MA_PROF_NONE && kind == P->prof_kind) ? P->d_prof : nullptr;
   c.desc = P->d_desc;
   c.st = P->d_state;
-  c.pair_ids = d_ids;
+  c.pair_ids = cl.d_ids;
+  c.mt = cl.mt;
   c.m = P->opt.gmres_m;
   c.max_newton = P->opt.max_newton;
   c.max_restarts = P->opt.gmres_max_restarts;
@@ -207,6 +245,7 @@ int build_classes(ma_plan* P, const std::vector<int>& ns, std::vector<Class>& cl
     c.n = kv.first;
     c.ids = kv.second;
     c.tw = P->tw[c.n];
+    c.mt = P->mt[std::make_pair(c.n, P->opt.symbol)];
     c.d_ids = P->d_ids + flat.size();
     flat.insert(flat.end(), kv.second.begin(), kv.second.end());
     cls.push_back(c);
@@ -240,19 +279,19 @@ void prof_flush(ma_plan* P) {
 }
 
 void L_res(ma_plan* P, const Class& c, int step_mode, hipStream_t st) {
-  launch_residual(make_ctx(P, c.d_ids, MA_PROF_RESIDUAL), c.n, (int)c.ids.size(), step_mode, st,
+  launch_residual(make_ctx(P, c, MA_PROF_RESIDUAL), c.n, (int)c.ids.size(), step_mode, st,
                   prof_events(P, MA_PROF_RESIDUAL));
 }
 void L_A(ma_plan* P, const Class& c, int mode, int jn, hipStream_t st) {
-  launch_passA(make_ctx(P, c.d_ids, MA_PROF_ROW_A), c.n, (int)c.ids.size(), mode, jn, c.tw, st,
+  launch_passA(make_ctx(P, c, MA_PROF_ROW_A), c.n, (int)c.ids.size(), mode, jn, c.tw, st,
                prof_events(P, MA_PROF_ROW_A));
 }
 void L_B(ma_plan* P, const Class& c, int mode, int j, hipStream_t st) {
-  launch_passB(make_ctx(P, c.d_ids, MA_PROF_COLUMN), c.n, (int)c.ids.size(), mode, j, c.tw, st,
+  launch_passB(make_ctx(P, c, MA_PROF_COLUMN), c.n, (int)c.ids.size(), mode, j, c.tw, st,
                prof_events(P, MA_PROF_COLUMN));
 }
 void L_C(ma_plan* P, const Class& c, int mode, int j, hipStream_t st) {
-  launch_passC(make_ctx(P, c.d_ids, MA_PROF_ROW_C), c.n, (int)c.ids.size(), mode, j, c.tw, st,
+  launch_passC(make_ctx(P, c, MA_PROF_ROW_C), c.n, (int)c.ids.size(), mode, j, c.tw, st,
                prof_events(P, MA_PROF_ROW_C));
 }
 
@@ -279,7 +318,7 @@ int run_solver(ma_plan* P, int npairs, double damping, double tol, hipStream_t s
   HIP_TRY(hipMemcpyAsync(P->d_desc, P->h_desc.data(), sizeof(PairDesc) * npairs, hipMemcpyHostToDevice, st));
   P->h_state.assign(npairs, fresh_state(damping, tol));
   HIP_TRY(hipMemcpyAsync(P->d_state, P->h_state.data(), sizeof(PairState) * npairs, hipMemcpyHostToDevice, st));
-  for (const Class& c : cls) launch_setup(make_ctx(P, c.d_ids), c.n, (int)c.ids.size(), st);
+  for (const Class& c : cls) launch_setup(make_ctx(P, c), c.n, (int)c.ids.size(), st);
   int e = read_summary(P, npairs, st);
   if (e) return e;
   if (P->h_summary[7] > 0) return MA_EINVAL;
@@ -300,7 +339,7 @@ int run_solver(ma_plan* P, int npairs, double damping, double tol, hipStream_t s
         if (e) return e;
         if (P->h_summary[6] == 0) break;
         for (const Class& c : cls) {
-          launch_restart(make_ctx(P, c.d_ids), c.n, (int)c.ids.size(), st);
+          launch_restart(make_ctx(P, c), c.n, (int)c.ids.size(), st);
           L_A(P, c, PA_PLAIN, 0, st);
         }
         launch_cycle_body(P, cls, st);
@@ -312,9 +351,9 @@ int run_solver(ma_plan* P, int npairs, double damping, double tol, hipStream_t s
       }
     }
     if (n_update > 0)
-      for (const Class& c : cls) launch_step_update(make_ctx(P, c.d_ids), c.n, (int)c.ids.size(), st);
+      for (const Class& c : cls) launch_step_update(make_ctx(P, c), c.n, (int)c.ids.size(), st);
   }
-  for (const Class& c : cls) launch_outputs(make_ctx(P, c.d_ids), c.n, (int)c.ids.size(), st);
+  for (const Class& c : cls) launch_outputs(make_ctx(P, c), c.n, (int)c.ids.size(), st);
   HIP_TRY(hipMemcpyAsync(P->h_state.data(), P->d_state, sizeof(PairState) * npairs, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   prof_flush(P);
@@ -378,6 +417,7 @@ void ma_options_default(ma_options* o) {
   o->op_mode = MA_OP_FULL;
   o->damping_policy = MA_DAMP_FIXED;
   o->max_backtrack = 12;
+  o->symbol = MA_SYMBOL_SPECTRAL;
 }
 
 const char* ma_strerror(int code) {
@@ -432,6 +472,7 @@ void ma_plan_destroy(ma_plan* P) {
   if (P->d_summary) hipFree(P->d_summary);
   if (P->h_summary) hipHostFree(P->h_summary);
   for (auto& kv : P->tw) hipFree(kv.second);
+  for (auto& kv : P->mt) hipFree(kv.second);
   for (hipEvent_t e : P->ev) hipEventDestroy(e);
   if (P->d_prof) hipFree(P->d_prof);
   delete P;
@@ -521,7 +562,7 @@ int ma_step_residual(ma_plan* P, int n, const double* u, const double* f, const 
   d.g_in = g;
   d.psi0_in = u;  // u0 = u - 0: the state's means are 1 and 0, so f and g are used as given
   HIP_TRY(hipMemcpyAsync(P->d_desc, P->h_desc.data(), sizeof(PairDesc), hipMemcpyHostToDevice, st));
-  LaunchCtx x = make_ctx(P, c.d_ids);
+  LaunchCtx x = make_ctx(P, c);
   launch_setup_fields(x, n, 1, st);
   launch_residual(x, n, 1, 1, st);
   if (r) launch_residual_shift(x, n, r, st);
@@ -545,7 +586,7 @@ int ma_step_fft2(ma_plan* P, int n, const float* v, float* spec, void* stream) {
   if (e) return e;
   const PairDesc& d = P->h_desc[0];
   HIP_TRY(hipMemcpyAsync(d.V, v, 4 * (size_t)n * n, hipMemcpyDeviceToDevice, st));
-  LaunchCtx x = make_ctx(P, c.d_ids);
+  LaunchCtx x = make_ctx(P, c);
   launch_passA(x, n, 1, PA_STEP, 0, c.tw, st);
   launch_passB(x, n, 1, PB_FORWARD, 0, c.tw, st);
   HIP_TRY(hipMemcpyAsync(spec, d.T, 4 * (size_t)n * n, hipMemcpyDeviceToDevice, st));
@@ -563,7 +604,7 @@ int ma_step_strain_apply(ma_plan* P, int n, const float* v, const float* coef, c
   const size_t nn = (size_t)n * n;
   HIP_TRY(hipMemcpyAsync(d.V, v, 4 * nn, hipMemcpyDeviceToDevice, st));
   HIP_TRY(hipMemcpyAsync(d.coef, coef, 20 * nn, hipMemcpyDeviceToDevice, st));
-  LaunchCtx x = make_ctx(P, c.d_ids);
+  LaunchCtx x = make_ctx(P, c);
   launch_passA(x, n, 1, PA_STEP, 0, c.tw, st);
   launch_passB(x, n, 1, PB_MATVEC, 0, c.tw, st);
   launch_passC(x, n, 1, PC_MATVEC, 0, c.tw, st);
@@ -581,7 +622,7 @@ int ma_step_lbar_inverse(ma_plan* P, int n, const float* sigma, const double* ab
   const PairDesc& d = P->h_desc[0];
   const size_t nn = (size_t)n * n;
   HIP_TRY(hipMemcpyAsync(d.V, sigma, 4 * nn, hipMemcpyDeviceToDevice, st));
-  LaunchCtx x = make_ctx(P, c.d_ids);
+  LaunchCtx x = make_ctx(P, c);
   launch_passA(x, n, 1, PA_STEP, 0, c.tw, st);
   launch_passB(x, n, 1, PB_RECOVER, 0, c.tw, st);
   launch_passC(x, n, 1, PC_THETA_ONLY, 0, c.tw, st);
@@ -628,7 +669,7 @@ int ma_step_gmres(ma_plan* P, int n, const float* h, const float* coef, const do
       rc = MA_EHIP;
       break;
     }
-    LaunchCtx x = make_ctx(P, c.d_ids);
+    LaunchCtx x = make_ctx(P, c);
     launch_passA(x, n, 1, PA_INIT, 0, c.tw, st);
     launch_cycle_body(P, cls, st);
     for (int cyc = 0; cyc < max_restarts; ++cyc) {

@@ -19,6 +19,7 @@ EINVAL, ENOMEM, EHIP = -1, -2, -3
 INTERP = {"bilinear": 0, "nearest": 1}
 OP_MODE = {"full": 0, "no_drift": 1}
 DAMPING = {"fixed": 0, "backtrack": 1}
+SYMBOL = {"spectral": 0, "fd4": 1}
 
 PROF = {"none": 0, "residual": 1, "row_a": 2, "column": 3, "row_c": 4}
 
@@ -33,7 +34,8 @@ class Options(ctypes.Structure):
     _fields_ = [("max_newton", ctypes.c_int), ("gmres_m", ctypes.c_int),
                 ("gmres_max_restarts", ctypes.c_int), ("gmres_tol", ctypes.c_double),
                 ("interp", ctypes.c_int), ("op_mode", ctypes.c_int),
-                ("damping_policy", ctypes.c_int), ("max_backtrack", ctypes.c_int)]
+                ("damping_policy", ctypes.c_int), ("max_backtrack", ctypes.c_int),
+                ("symbol", ctypes.c_int)]
 
 
 class Report(ctypes.Structure):
@@ -114,6 +116,8 @@ def make_options(**kw):
             v = OP_MODE[v] if isinstance(v, str) else v
         elif k == "damping_policy":
             v = DAMPING[v] if isinstance(v, str) else v
+        elif k == "symbol":
+            v = SYMBOL[v] if isinstance(v, str) else v
         if not hasattr(o, k):
             raise TypeError("unknown option %r" % k)
         setattr(o, k, v)

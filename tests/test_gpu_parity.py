@@ -85,6 +85,21 @@ def test_strain_operator_matches_oracle(plan, N):
     assert relerr(w, ref) < 1e-4
 
 
+@pytest.mark.parametrize("N", [16, 96, 512])
+def test_strain_operator_fd4_symbol_matches_oracle(maot, N):
+    p = maot.Plan(n_max=N, batch_capacity=1, symbol="fd4")
+    try:
+        prob, u, ev, coef, abar = realistic_fields(N, W.seed_for(1, N + 5))
+        v = np.random.default_rng(5).standard_normal((N, N)).astype(np.float32)
+        w = host(p.step_strain_apply(dev(v, torch.float32), dev(coef, torch.float32), abar))
+        ref = ma.strain_apply(v.astype(np.float64), tuple(coef), ma.symbol(abar, N, "fd4"), "fd4")
+        assert relerr(w, ref) < 1e-4
+        th = host(p.step_lbar_inverse(dev(v, torch.float32), abar))
+        assert relerr(th, ma.lbar_inverse(v.astype(np.float64), ma.symbol(abar, N, "fd4"))) < 1e-4
+    finally:
+        p.close()
+
+
 @pytest.mark.parametrize("N", [16, 64, 384, 512])
 def test_averaged_operator_inverse_matches_oracle(plan, N):
     _, _, _, coef, abar = realistic_fields(N, W.seed_for(1, N + 1))
@@ -239,6 +254,22 @@ def test_c1_pair_512_to_residual_1e6(maot):
         err2 = np.max(np.abs(host(psi2) - psi_ref)) / np.max(np.abs(psi_ref))
         print("C1 512 tol 1e-8: rel err %.3e, newton %d" % (err2, rep2["newton_iters"]))
         assert rep2["status"] == 0 and err2 <= 1e-6, (rep2, err2)
+    finally:
+        p.close()
+
+
+def test_fd4_symbol_solve_matches_oracle(maot):
+    N = 128
+    f, g = W.blobs(N, W.seed_for(1, 3))
+    ref, _, rr = ma.solve(f, g, tau=1.0, tol=1e-11, damping_policy="backtrack", gmres_tol=0.1,
+                          max_newton=300, symbol="fd4")
+    assert rr.status == ma.OK
+    p = maot.Plan(n_max=N, batch_capacity=1, damping_policy="backtrack", gmres_tol=0.1, max_newton=300,
+                  symbol="fd4")
+    try:
+        psi, _, rep = p.solve(dev(f), dev(g), damping=1.0, tol=1e-9)
+        assert rep["status"] == 0
+        assert np.max(np.abs(host(psi) - ref)) <= 1e-6 * np.max(np.abs(ref))
     finally:
         p.close()
 

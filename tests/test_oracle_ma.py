@@ -319,3 +319,30 @@ def test_linearisation_is_the_derivative_of_M():
     t1, t2, t11, t22, t12 = fd.derivatives(theta, h)
     Ltheta = a11 * t11 + 2 * a12 * t12 + a22 * t22 + b1 * t1 + b2 * t2
     assert np.max(np.abs(dfn - Ltheta)) < 1e-7 * np.max(np.abs(Ltheta))
+
+
+def test_fd4_symbol_option_is_the_difference_operator():
+    # the "fd4" multipliers are exactly the fourth-order difference operators of oracle.fd
+    N = 16
+    rng = np.random.default_rng(3)
+    u = rng.standard_normal((N, N))
+    m1, m2 = ma.multipliers(N, "fd4")
+    U = np.fft.fft2(u)
+    h = 1.0 / N
+    # the first-derivative symbol is zero at -N/2 in both conventions; remove that mode
+    nyq = np.cos(np.pi * np.arange(N))
+    u0 = u - np.outer(nyq, np.ones(N)) * (nyq @ u.sum(axis=1)) / (N * N)
+    assert np.allclose(np.fft.ifft2(m2[:, None] * U).real, fd.d2(u, 0, h), atol=1e-9)
+    assert np.allclose(np.fft.ifft2(m2[None, :] * U).real, fd.d2(u, 1, h), atol=1e-9)
+    assert np.allclose(np.fft.ifft2(m1[:, None] * np.fft.fft2(u0)).real, fd.d1(u0, 0, h), atol=1e-9)
+
+
+def test_fd4_symbol_newton_converges_to_the_same_fixed_point_faster():
+    N = 64
+    f, g = W.blobs(N, W.seed_for(1, 1))
+    a, _, ra = ma.solve(f, g, tol=1e-10, damping_policy="backtrack", gmres_tol=0.1, max_newton=300)
+    b, _, rb = ma.solve(f, g, tol=1e-10, damping_policy="backtrack", gmres_tol=0.1, max_newton=300,
+                        symbol="fd4")
+    assert ra.status == rb.status == ma.OK
+    assert np.max(np.abs(a - b)) < 1e-9 * max(1.0, np.max(np.abs(a))) * 10
+    assert rb.newton_iters < ra.newton_iters
