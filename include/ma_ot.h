@@ -199,6 +199,49 @@ int ma_step_gmres(ma_plan* plan, int n, const float* h, const float* coef,
                   const double* abar, int m, double tol, int max_restarts, float* theta,
                   int* iters, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Learned warm start (not in the paper): a periodic-padded 3x3 convolutional
+ * network, BF16 on MFMA with FP32 accumulation, trained on pairs the solver
+ * produces.  It maps (f - 1, g - 1) at resolution n_net to c, an estimate of the
+ * fourth-order difference Laplacian of the potential; the initial guess is
+ * psi0 = (that Laplacian)^{-1} c, mean zero.  Zero-init Newton stays the fallback
+ * (the caller re-solves pairs the warm start does not help).
+ *
+ * Parameters are FP32 masters in the order W_0, b_0, W_1, b_1, ... with
+ * W_l[co][ci][3][3], 2 input channels, `channels` hidden, 1 output channel.
+ * Network inputs are BF16 tensors [batch][n_net][n_net][8] (channels 0 and 1 are
+ * f/mean f - 1 and g/mean g - 1, the rest zero), made by ma_cnn_prepare_input.
+ * ------------------------------------------------------------------------- */
+typedef struct ma_cnn ma_cnn;
+
+/* layers >= 2, channels == 32, n_net a multiple of 32, max_batch >= 1. */
+int ma_cnn_create(int layers, int channels, int n_net, int max_batch, ma_cnn** out);
+void ma_cnn_destroy(ma_cnn* net);
+long ma_cnn_param_count(const ma_cnn* net);
+/* host FP32 arrays of ma_cnn_param_count values; set also resets the Adam state */
+int ma_cnn_set_params(ma_cnn* net, const float* host_params, long count);
+int ma_cnn_get_params(const ma_cnn* net, float* host_params, long count);
+
+/* f, g: device FP64 [batch][n_net][n_net]; x: device BF16 [batch][n_net][n_net][8]. */
+int ma_cnn_prepare_input(ma_cnn* net, const double* f, const double* g, int batch, void* x, void* stream);
+/* target = fourth-order difference Laplacian of psi (device FP64 -> FP32), [batch][n][n]. */
+int ma_cnn_laplacian(ma_cnn* net, const double* psi, int batch, int n, float* target, void* stream);
+/* c: device FP32 [batch][n_net][n_net]. */
+int ma_cnn_forward(ma_cnn* net, const void* x, int batch, float* c, void* stream);
+/* forward, MSE against target, backward: gradients (device FP32, parameter order)
+ * and the loss (host) without updating.  Synchronises. */
+int ma_cnn_gradients(ma_cnn* net, const void* x, const float* target, int batch, float* grads, float* loss,
+                     void* stream);
+/* one Adam step (beta 0.9, 0.999, eps 1e-8) on the MSE loss; loss (host) may be NULL
+ * (then no synchronisation). */
+int ma_cnn_train_step(ma_cnn* net, const void* x, const float* target, int batch, float lr, float* loss,
+                      void* stream);
+/* psi0 for npairs pairs of size n (n == n_net, or n == 2 n_net: the densities are
+ * restricted by full weighting and c is prolonged bilinearly before the head).
+ * Arrays of pointers are host arrays of device pointers. */
+int ma_cnn_warm_start(ma_cnn* net, int npairs, int n, const double* const* f, const double* const* g,
+                      double* const* psi0, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -107,15 +107,18 @@ def mse(c, t):
     return float(np.mean((c - t) ** 2))
 
 
-def backward(c, t, cache, params, bf16=False):
-    """Gradients of mse(c, t) with respect to every (W, b)."""
+def backward(c, t, cache, params, bf16=False, count=None):
+    """Gradients of mse(c, t) with respect to every (W, b).
+
+    With bf16=True the gradients flowing between layers are rounded to BF16, as the
+    GPU kernels store them."""
     r = bf16_round if bf16 else (lambda v: v)
-    dh = 2.0 * (c - t) / c.size
+    dh = 2.0 * (c - t) / (c.size if count is None else count)
     grads = [None] * len(params)
     L = len(params)
     for l in range(L - 1, -1, -1):
         h, z = cache[l]
-        dz = dh if l == L - 1 else dh * (z > 0)
+        dz = r(dh if l == L - 1 else dh * (z > 0))
         W = r(params[l][0])
         dW, db = conv3x3_weight_grad(dz, h)
         grads[l] = (dW, db)
@@ -131,3 +134,61 @@ def adam_step(p, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     mhat = m / (1.0 - beta1 ** t)
     vhat = v / (1.0 - beta2 ** t)
     return p - lr * mhat / (np.sqrt(vhat) + eps), m, v
+
+
+# ---------------------------------------------------------------------------
+# Around the network: target, head and resolution changes
+# ---------------------------------------------------------------------------
+
+def laplacian_fd4(u):
+    """The fourth-order difference Laplacian of Section 4 (the training target)."""
+    from . import fd
+    h = 1.0 / u.shape[0]
+    return fd.d2(u, 0, h) + fd.d2(u, 1, h)
+
+
+def inverse_laplacian_fd4(c):
+    """Mean-zero solution psi of laplacian_fd4(psi) = c - mean(c) (the warm-start head)."""
+    from . import ma
+    N = c.shape[0]
+    return ma.lbar_inverse(c, ma.symbol((1.0, 0.0, 1.0, 0.0, 0.0), N, "fd4"))
+
+
+def restrict_full_weighting(x):
+    """2n x 2n -> n x n: weights (1/4, 1/2, 1/4) in each direction around fine node 2a."""
+    w = {-1: 0.25, 0: 0.5, 1: 0.25}
+    y = np.zeros_like(x)
+    for p, wp in w.items():
+        for q, wq in w.items():
+            y += wp * wq * np.roll(np.roll(x, -p, axis=0), -q, axis=1)
+    return y[::2, ::2]
+
+
+def prolong_bilinear(x):
+    """n x n -> 2n x 2n periodic bilinear interpolation between coarse nodes."""
+    n = x.shape[0]
+    y = np.zeros((2 * n, 2 * n))
+    xr = np.roll(x, -1, axis=0)
+    xc = np.roll(x, -1, axis=1)
+    xrc = np.roll(xr, -1, axis=1)
+    y[::2, ::2] = x
+    y[1::2, ::2] = 0.5 * (x + xr)
+    y[::2, 1::2] = 0.5 * (x + xc)
+    y[1::2, 1::2] = 0.25 * (x + xr + xc + xrc)
+    return y
+
+
+def network_input(f, g):
+    return np.stack([f / f.mean() - 1.0, g / g.mean() - 1.0])
+
+
+def warm_start(f, g, params, n_net, bf16=True):
+    """psi0 for one pair: restrict if needed, run the network, prolong, invert the Laplacian."""
+    n = f.shape[0]
+    if n == 2 * n_net:
+        f, g = restrict_full_weighting(f), restrict_full_weighting(g)
+    c, _ = forward(network_input(f, g), params, bf16=bf16)
+    c = c[0]
+    if n == 2 * n_net:
+        c = prolong_bilinear(c)
+    return inverse_laplacian_fd4(c)

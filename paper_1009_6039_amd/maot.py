@@ -27,7 +27,10 @@ EXPORTED = ("ma_abi_version", "ma_options_default", "ma_strerror", "ma_plan_crea
             "ma_plan_destroy", "ma_plan_set_options", "ma_solve", "ma_solve_batched",
             "ma_plan_profile", "ma_plan_profile_read",
             "ma_step_residual", "ma_step_fft2", "ma_step_strain_apply",
-            "ma_step_lbar_inverse", "ma_step_gmres")
+            "ma_step_lbar_inverse", "ma_step_gmres",
+            "ma_cnn_create", "ma_cnn_destroy", "ma_cnn_param_count", "ma_cnn_set_params",
+            "ma_cnn_get_params", "ma_cnn_prepare_input", "ma_cnn_laplacian", "ma_cnn_forward",
+            "ma_cnn_gradients", "ma_cnn_train_step", "ma_cnn_warm_start")
 
 
 class Options(ctypes.Structure):
@@ -82,8 +85,22 @@ def load():
     lib.ma_step_strain_apply.argtypes = [P, I, P, P, ctypes.POINTER(D), P, P]
     lib.ma_step_lbar_inverse.argtypes = [P, I, P, ctypes.POINTER(D), P, P]
     lib.ma_step_gmres.argtypes = [P, I, P, P, ctypes.POINTER(D), I, D, I, P, ctypes.POINTER(I), P]
+    F, L = ctypes.c_float, ctypes.c_long
+    lib.ma_cnn_create.argtypes = [I, I, I, I, ctypes.POINTER(P)]
+    lib.ma_cnn_destroy.argtypes = [P]
+    lib.ma_cnn_param_count.argtypes = [P]
+    lib.ma_cnn_param_count.restype = L
+    lib.ma_cnn_set_params.argtypes = [P, ctypes.POINTER(F), L]
+    lib.ma_cnn_get_params.argtypes = [P, ctypes.POINTER(F), L]
+    lib.ma_cnn_prepare_input.argtypes = [P, P, P, I, P, P]
+    lib.ma_cnn_laplacian.argtypes = [P, P, I, I, P, P]
+    lib.ma_cnn_forward.argtypes = [P, P, I, P, P]
+    lib.ma_cnn_gradients.argtypes = [P, P, P, I, P, ctypes.POINTER(F), P]
+    lib.ma_cnn_train_step.argtypes = [P, P, P, I, F, ctypes.POINTER(F), P]
+    lib.ma_cnn_warm_start.argtypes = [P, I, I, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), P]
     for name in EXPORTED:
         getattr(lib, name).restype = getattr(lib, name).restype or I
+    lib.ma_cnn_destroy.restype = None
     lib.ma_plan_destroy.restype = None
     lib.ma_options_default.restype = None
     _lib = lib
@@ -263,6 +280,96 @@ class Plan:
                                     int(max_restarts), _ptr(theta), ctypes.byref(its), _stream()),
                "ma_step_gmres")
         return theta, its.value
+
+
+class WarmStartNet:
+    """The warm-start network (ma_cnn): BF16 MFMA convolutions with FP32 masters."""
+
+    def __init__(self, layers=8, channels=32, n_net=256, max_batch=16):
+        lib = load()
+        h = ctypes.c_void_p()
+        _check(lib.ma_cnn_create(layers, channels, n_net, max_batch, ctypes.byref(h)), "ma_cnn_create")
+        self._h = h
+        self.layers, self.channels, self.n_net, self.max_batch = layers, channels, n_net, max_batch
+        self.count = int(lib.ma_cnn_param_count(h))
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load().ma_cnn_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, flat):
+        import numpy as np
+        a = np.ascontiguousarray(flat, dtype=np.float32)
+        if a.size != self.count:
+            raise ValueError("expected %d parameters" % self.count)
+        _check(load().ma_cnn_set_params(self._h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), a.size),
+               "ma_cnn_set_params")
+
+    def get_params(self):
+        import numpy as np
+        a = np.empty(self.count, dtype=np.float32)
+        _check(load().ma_cnn_get_params(self._h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), a.size),
+               "ma_cnn_get_params")
+        return a
+
+    def prepare_input(self, f, g):
+        """f, g: CUDA float64 [batch, n_net, n_net] -> BF16 input [batch, n_net, n_net, 8]."""
+        f = _dev(f, torch.float64)
+        g = _dev(g, torch.float64)
+        x = torch.empty(f.shape + (8,), dtype=torch.bfloat16, device=f.device)
+        _check(load().ma_cnn_prepare_input(self._h, _ptr(f), _ptr(g), f.shape[0], _ptr(x), _stream()),
+               "ma_cnn_prepare_input")
+        return x
+
+    def laplacian(self, psi):
+        psi = _dev(psi, torch.float64)
+        out = torch.empty(psi.shape, dtype=torch.float32, device=psi.device)
+        _check(load().ma_cnn_laplacian(self._h, _ptr(psi), psi.shape[0], psi.shape[-1], _ptr(out), _stream()),
+               "ma_cnn_laplacian")
+        return out
+
+    def forward(self, x):
+        x = _dev(x, torch.bfloat16)
+        c = torch.empty(x.shape[:3], dtype=torch.float32, device=x.device)
+        _check(load().ma_cnn_forward(self._h, _ptr(x), x.shape[0], _ptr(c), _stream()), "ma_cnn_forward")
+        return c
+
+    def gradients(self, x, target):
+        x = _dev(x, torch.bfloat16)
+        target = _dev(target, torch.float32)
+        grads = torch.empty(self.count, dtype=torch.float32, device=x.device)
+        loss = ctypes.c_float()
+        _check(load().ma_cnn_gradients(self._h, _ptr(x), _ptr(target), x.shape[0], _ptr(grads),
+                                       ctypes.byref(loss), _stream()), "ma_cnn_gradients")
+        return grads, loss.value
+
+    def train_step(self, x, target, lr, want_loss=False):
+        x = _dev(x, torch.bfloat16)
+        target = _dev(target, torch.float32)
+        loss = ctypes.c_float()
+        _check(load().ma_cnn_train_step(self._h, _ptr(x), _ptr(target), x.shape[0], float(lr),
+                                        ctypes.byref(loss) if want_loss else None, _stream()),
+               "ma_cnn_train_step")
+        return loss.value if want_loss else None
+
+    def warm_start(self, fs, gs):
+        """Initial potentials for lists of CUDA float64 densities of one size."""
+        n = int(fs[0].shape[0])
+        npairs = len(fs)
+        psis = [torch.empty_like(f) for f in fs]
+        arr = ctypes.c_void_p * npairs
+        fa = arr(*[_dev(t, torch.float64).data_ptr() for t in fs])
+        ga = arr(*[_dev(t, torch.float64).data_ptr() for t in gs])
+        pa = arr(*[t.data_ptr() for t in psis])
+        _check(load().ma_cnn_warm_start(self._h, npairs, n, fa, ga, pa, _stream()), "ma_cnn_warm_start")
+        return psis
 
 
 def solve(f, g, damping=1.0, tol=1e-6, psi0=None, **opts):

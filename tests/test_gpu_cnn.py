@@ -1,0 +1,150 @@
+"""GPU parity of the warm-start network kernels against the FP64 oracle with BF16 emulation.
+
+The GPU stores inputs, weights, activations and inter-layer gradients in BF16 and
+accumulates in FP32; the oracle rounds the same tensors to BF16 and accumulates in
+FP64.  FP32-vs-FP64 accumulation order can flip a rare BF16 rounding of an
+intermediate value, so tensors are compared by relative L2 error.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import cnn
+from paper_1009_6039_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def maot():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1009_6039_amd import maot as m
+    m.load()
+    return m
+
+
+def flat(params):
+    return np.concatenate([np.concatenate([Wl.ravel(), bl.ravel()]) for Wl, bl in params]).astype(np.float32)
+
+
+def f32_params(seed, layers=8):
+    rng = np.random.default_rng(seed + 100)
+    p = cnn.init_params(channels=32, layers=layers, seed=seed)
+    p = [(Wl.astype(np.float32).astype(np.float64), (0.05 * rng.standard_normal(bl.shape)).astype(np.float32)
+          .astype(np.float64)) for Wl, bl in p]
+    return p
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def inputs(n, batch, seed):
+    pairs = [W.blobs(n, W.seed_for(4, seed + k)) for k in range(batch)]
+    f = np.stack([a for a, _ in pairs])
+    g = np.stack([b for _, b in pairs])
+    return f, g
+
+
+def test_forward_matches_oracle(maot):
+    n, B = 32, 2
+    params = f32_params(1)
+    net = maot.WarmStartNet(layers=8, channels=32, n_net=n, max_batch=B)
+    try:
+        net.set_params(flat(params))
+        f, g = inputs(n, B, 0)
+        x = net.prepare_input(torch.from_numpy(f).cuda(), torch.from_numpy(g).cuda())
+        c = net.forward(x)
+        torch.cuda.synchronize()
+        c = c.cpu().numpy().astype(np.float64)
+        for k in range(B):
+            ref, _ = cnn.forward(cnn.network_input(f[k], g[k]), params, bf16=True)
+            assert rel_l2(c[k], ref[0]) < 2e-3, k
+        # the prepared input is the BF16 rounding of (f/mean - 1, g/mean - 1)
+        xin = x.float().cpu().numpy()
+        assert np.array_equal(xin[0, :, :, 0], cnn.bf16_round(f[0] / f[0].mean() - 1.0).astype(np.float32))
+        assert np.all(xin[..., 2:] == 0)
+    finally:
+        net.close()
+
+
+def test_gradients_match_oracle(maot):
+    n, B = 32, 2
+    params = f32_params(2)
+    net = maot.WarmStartNet(layers=8, channels=32, n_net=n, max_batch=B)
+    try:
+        net.set_params(flat(params))
+        f, g = inputs(n, B, 10)
+        t = np.stack([0.3 * (a / a.mean() - b / b.mean()) for a, b in zip(f, g)]).astype(np.float32)
+        x = net.prepare_input(torch.from_numpy(f).cuda(), torch.from_numpy(g).cuda())
+        grads, loss = net.gradients(x, torch.from_numpy(t).cuda())
+        torch.cuda.synchronize()
+        grads = grads.cpu().numpy().astype(np.float64)
+        tot, lref = None, 0.0
+        for k in range(B):
+            c, cache = cnn.forward(cnn.network_input(f[k], g[k]), params, bf16=True)
+            gk = cnn.backward(c, t[k:k + 1].astype(np.float64), cache, params, bf16=True, count=B * n * n)
+            lref += np.sum((c - t[k]) ** 2) / (B * n * n)
+            tot = gk if tot is None else [(a[0] + b[0], a[1] + b[1]) for a, b in zip(tot, gk)]
+        assert loss == pytest.approx(lref, rel=1e-3)
+        ref = flat(tot).astype(np.float64)
+        off = 0
+        for l, (Wl, bl) in enumerate(params):
+            nw, nb = Wl.size, bl.size
+            assert rel_l2(grads[off:off + nw], ref[off:off + nw]) < 2e-2, ("W", l)
+            assert rel_l2(grads[off + nw:off + nw + nb], ref[off + nw:off + nw + nb]) < 2e-2, ("b", l)
+            off += nw + nb
+    finally:
+        net.close()
+
+
+def test_adam_steps_reduce_the_loss(maot):
+    n, B = 32, 4
+    net = maot.WarmStartNet(layers=8, channels=32, n_net=n, max_batch=B)
+    try:
+        net.set_params(flat(f32_params(3)))
+        f, g = inputs(n, B, 20)
+        t = np.stack([0.5 * (a / a.mean() - b / b.mean()) for a, b in zip(f, g)]).astype(np.float32)
+        x = net.prepare_input(torch.from_numpy(f).cuda(), torch.from_numpy(g).cuda())
+        tt = torch.from_numpy(t).cuda()
+        _, l0 = net.gradients(x, tt)
+        for _ in range(40):
+            net.train_step(x, tt, 2e-3)
+        _, l1 = net.gradients(x, tt)
+        assert l1 < 0.5 * l0, (l0, l1)
+    finally:
+        net.close()
+
+
+def test_laplacian_target_matches_oracle(maot):
+    net = maot.WarmStartNet(layers=2, channels=32, n_net=32, max_batch=1)
+    try:
+        u = np.random.default_rng(4).standard_normal((2, 48, 48)) * 1e-3
+        out = net.laplacian(torch.from_numpy(u).cuda())
+        torch.cuda.synchronize()
+        out = out.cpu().numpy()
+        for k in range(2):
+            assert rel_l2(out[k], cnn.laplacian_fd4(u[k])) < 1e-6
+    finally:
+        net.close()
+
+
+@pytest.mark.parametrize("n", [32, 64])
+def test_warm_start_matches_oracle(maot, n):
+    n_net = 32
+    params = f32_params(5)
+    net = maot.WarmStartNet(layers=8, channels=32, n_net=n_net, max_batch=2)
+    try:
+        net.set_params(flat(params))
+        f, g = inputs(n, 3, 30)
+        psis = net.warm_start([torch.from_numpy(a).cuda() for a in f], [torch.from_numpy(b).cuda() for b in g])
+        torch.cuda.synchronize()
+        for k in range(3):
+            ref = cnn.warm_start(f[k], g[k], params, n_net)
+            got = psis[k].cpu().numpy()
+            assert rel_l2(got, ref) < 3e-3, k
+            assert abs(got.mean()) < 1e-6 * np.max(np.abs(ref))
+    finally:
+        net.close()

@@ -138,3 +138,58 @@ def test_training_reduces_the_loss():
         params = new
     c, _ = cnn.forward(x, params)
     assert cnn.mse(c, t) < 0.2 * l0
+
+
+def test_laplacian_target_and_head_invert_each_other():
+    rng = np.random.default_rng(8)
+    u = rng.standard_normal((16, 16))
+    u -= u.mean()
+    assert np.allclose(cnn.inverse_laplacian_fd4(cnn.laplacian_fd4(u)), u, atol=1e-10)
+    # on a Fourier mode the target is the fourth-order symbol times the mode
+    N = 32
+    x = np.arange(N) / N
+    X1, X2 = np.meshgrid(x, x, indexing="ij")
+    e = np.cos(2 * np.pi * 3 * X1)
+    t = 2 * np.pi * 3 / N
+    sym = (32 * np.cos(t) - 2 * np.cos(2 * t) - 30) * N * N / 12
+    assert np.allclose(cnn.laplacian_fd4(e), sym * e, atol=1e-8)
+
+
+def test_restriction_and_prolongation():
+    N = 32
+    x = np.arange(2 * N) / (2 * N)
+    X1, X2 = np.meshgrid(x, x, indexing="ij")
+    assert np.allclose(cnn.restrict_full_weighting(np.full((2 * N, 2 * N), 3.0)), 3.0)
+    # full weighting of a mode multiplies it by cos^2(pi k h) in each direction
+    k = 3
+    e = np.cos(2 * np.pi * k * X1)
+    damp = np.cos(np.pi * k / (2 * N)) ** 2
+    assert np.allclose(cnn.restrict_full_weighting(e), damp * e[::2, ::2], atol=1e-12)
+    # bilinear prolongation reproduces coarse values at even nodes and averages between
+    c = np.random.default_rng(9).standard_normal((8, 8))
+    y = cnn.prolong_bilinear(c)
+    assert np.array_equal(y[::2, ::2], c)
+    assert np.allclose(y[1, 2], 0.5 * (c[0, 1] + c[1, 1]))
+    assert np.allclose(y[15, 15], 0.25 * (c[7, 7] + c[0, 7] + c[7, 0] + c[0, 0]))
+
+
+def test_batched_gradient_normalisation():
+    rng = np.random.default_rng(10)
+    params = cnn.init_params(channels=4, layers=2, seed=1)
+    xs = [rng.standard_normal((2, 8, 8)) for _ in range(2)]
+    ts = [rng.standard_normal((1, 8, 8)) for _ in range(2)]
+    # the batch loss is the mean over all samples and pixels: per-sample gradients with
+    # count = total elements add up to the gradient of the batch loss
+    tot = None
+    for x, t in zip(xs, ts):
+        c, cache = cnn.forward(x, params)
+        g = cnn.backward(c, t, cache, params, count=2 * 64)
+        tot = g if tot is None else [(a[0] + b[0], a[1] + b[1]) for a, b in zip(tot, g)]
+    l_batch = np.mean([cnn.mse(cnn.forward(x, params)[0], t) for x, t in zip(xs, ts)])
+    eps = 1e-6
+    W, b = params[0]
+    Wp = W.copy()
+    Wp[1, 0, 1, 2] += eps
+    pp = [(Wp, b), params[1]]
+    l_p = np.mean([cnn.mse(cnn.forward(x, pp)[0], t) for x, t in zip(xs, ts)])
+    assert tot[0][0][1, 0, 1, 2] == pytest.approx((l_p - l_batch) / eps, rel=1e-4)
