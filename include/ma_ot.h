@@ -85,6 +85,8 @@ typedef struct ma_report {
   double w2sq;             /* mean(|grad u|^2 f): the transport distance (Sec. 5.2)  */
   double tau_final;        /* damping in force at exit                               */
   double time_ms;          /* wall time of the call that produced this report        */
+  int warm_steps;          /* 1 if a given initial potential (possibly halved) was kept */
+  int pad;
 } ma_report;
 
 typedef struct ma_plan ma_plan;
@@ -112,7 +114,11 @@ int ma_plan_set_options(ma_plan* plan, const ma_options* opt);
 /* Solves one pair (Section 3.1 algorithm, Section 4.2 linear solver).
  *   f, g    N*N FP64 densities, positive and finite; each is scaled to grid mean one.
  *   damping tau >= 1 of eq. (linma).  tol > 0: stop when sqrt(mean r^2) <= tol.
- *   psi0    N*N FP64 initial potential or NULL for u0 = 0; its mean is removed.
+ *   psi0    N*N FP64 initial potential or NULL for u0 = 0.  Given one, the solve
+ *           starts from u = 0 and tries psi0 - mean(psi0) as its first step: the step
+ *           is kept if the iterate is convex and the residual drops, halved
+ *           otherwise, and abandoned for u = 0 after max_backtrack halvings (an
+ *           addition: it makes any initial guess safe to offer).
  *   psi     N*N FP64 out: the mean-zero potential u.
  *   map     2*N*N FP64 out: [0] = x1 + d1 u, [1] = x2 + d2 u (unwrapped, fourth-order
  *           differences), or NULL.
@@ -202,7 +208,7 @@ int ma_step_gmres(ma_plan* plan, int n, const float* h, const float* coef,
 /* ---------------------------------------------------------------------------
  * Learned warm start (not in the paper): a periodic-padded 3x3 convolutional
  * network, BF16 on MFMA with FP32 accumulation, trained on pairs the solver
- * produces.  It maps (f - 1, g - 1) at resolution n_net to c, an estimate of the
+ * produces.  It maps (log f, log g) at resolution n_net to c, an estimate of the
  * fourth-order difference Laplacian of the potential; the initial guess is
  * psi0 = (that Laplacian)^{-1} c, mean zero.  Zero-init Newton stays the fallback
  * (the caller re-solves pairs the warm start does not help).
@@ -210,7 +216,7 @@ int ma_step_gmres(ma_plan* plan, int n, const float* h, const float* coef,
  * Parameters are FP32 masters in the order W_0, b_0, W_1, b_1, ... with
  * W_l[co][ci][3][3], 2 input channels, `channels` hidden, 1 output channel.
  * Network inputs are BF16 tensors [batch][n_net][n_net][8] (channels 0 and 1 are
- * f/mean f - 1 and g/mean g - 1, the rest zero), made by ma_cnn_prepare_input.
+ * log(f/mean f) and log(g/mean g), the rest zero), made by ma_cnn_prepare_input.
  * ------------------------------------------------------------------------- */
 typedef struct ma_cnn ma_cnn;
 

@@ -5,7 +5,7 @@ TEST INFRASTRUCTURE ONLY (see the package header).
 The network is not part of the paper; it supplies the Newton initial guess.
 Layers l = 0..L-1: z_l = conv3x3_periodic(h_l, W_l) + b_l, h_{l+1} = relu(z_l) for
 l < L-1 and h_L = z_{L-1} (no activation on the output).  Input channels are
-(f - 1, g - 1) for densities scaled to mean one.  The output c approximates the
+(log f, log g) for densities scaled to mean one.  The output c approximates the
 fourth-order difference Laplacian of the solver's potential; the initial guess is
 psi0 = (discrete Laplacian)^{-1} c with zero mean (the head, applied outside the
 network).
@@ -179,7 +179,8 @@ def prolong_bilinear(x):
 
 
 def network_input(f, g):
-    return np.stack([f / f.mean() - 1.0, g / g.mean() - 1.0])
+    """(log f, log g) of the densities scaled to mean one."""
+    return np.stack([np.log(f / f.mean()), np.log(g / g.mean())])
 
 
 def warm_start(f, g, params, n_net, bf16=True):

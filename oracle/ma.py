@@ -310,6 +310,9 @@ def solve(f, g, tau=1.0, tol=1e-6, psi0=None, max_newton=100, gmres_m=10,
           symbol="spectral"):
     """Damped Newton (eq. linma) with Strain's linear solver (Section 4.2).
 
+    psi0, if given, is tried as a first step from u = 0 (accepted if convex and the
+    residual drops, halved otherwise, abandoned after max_backtrack halvings).
+
     Returns (psi, map, report): psi is the mean-zero potential u on the grid, map is
     x + D_h u as a (2, N, N) array (unwrapped: the additive map of Theorem CE1),
     report holds status, iteration counts and residual measures.
@@ -318,18 +321,29 @@ def solve(f, g, tau=1.0, tol=1e-6, psi0=None, max_newton=100, gmres_m=10,
     check_inputs(f, g, tau, tol)
     prob = Problem(np.asarray(f, np.float64), np.asarray(g, np.float64), interp, g_analytic)
     N = prob.N
-    if psi0 is None:
-        u = np.zeros((N, N))
-    else:
-        u = np.asarray(psi0, dtype=np.float64) - np.mean(psi0)
+    u = np.zeros((N, N))
     ev = evaluate(u, prob)
     res0 = ev.res_rms
     hist = [ev.res_rms]
     n = 0
     gm_total = 0
     backtracks = 0
+    warm_steps = 0
     tau_cur = float(tau)
     status = None
+    if psi0 is not None and ev.finite and ev.res_rms > tol:
+        # checked start (not in the paper): psi0 is tried as a first step from u = 0 and
+        # halved while the trial is non-convex or does not lower the residual; after
+        # max_backtrack halvings the solve continues from u = 0
+        step = np.asarray(psi0, dtype=np.float64) - np.mean(psi0)
+        for k in range(max_backtrack + 1):
+            ev_try = evaluate(step, prob)
+            if ev_try.convex and ev_try.res_rms < ev.res_rms:
+                u, ev = step, ev_try
+                warm_steps = 1
+                hist.append(ev.res_rms)
+                break
+            step = 0.5 * step
     while True:
         if not ev.finite:
             status = ENAN
@@ -375,7 +389,7 @@ def solve(f, g, tau=1.0, tol=1e-6, psi0=None, max_newton=100, gmres_m=10,
                  res_max=ev.res_max, res0_rms=res0, mass_defect=ev.mass_defect,
                  min_det=ev.min_det, w2sq=float(np.mean((ev.u1 ** 2 + ev.u2 ** 2) * prob.f)),
                  time_ms=1e3 * (time.perf_counter() - t0), backtracks=backtracks,
-                 tau_final=tau_cur)
+                 tau_final=tau_cur, warm_steps=warm_steps)
     if history:
         rep["history"] = hist
     return psi, mp, rep

@@ -45,7 +45,7 @@ struct PairDesc {
   GS* gs;          // n*n   g scaled to mean one, with its gradient
   float* coef;     // 5*n*n a11, a12, a22, b1, b2
   float* r;        // n*n   f - f_n (the translation constant is added by its readers)
-  float* theta;    // n*n   last Newton correction
+  double* theta;   // n*n   last Newton correction (the initial potential before the first step)
   float* x;        // n*n   GMRES solution accumulated over restarts
   float* V;        // (m+1)*n*n Krylov basis, stored unnormalised (see vscale)
   float2* H;       // n*(n/2) half spectrum after the row pass
@@ -58,7 +58,10 @@ struct PairState {
   int phase, status;
   int newton_iters, gmres_iters, backtracks, bt_step;
   int valid;            // set by the set-up kernel: 1 = densities positive and finite
-  int pad0;
+  int warm;             // an initial potential was given: it is tried as the first step
+  int warm_trial;       // the current trial is that step
+  int warm_fallback;    // the trial was abandoned: continue from u = 0
+  int warm_steps;       // 1 if the initial potential (possibly halved) was accepted
   int pad1, pad2;
   double tau0, tau;     // caller's damping, damping in force
   double tol;

@@ -2,7 +2,8 @@
 // accumulation, and what inference and training need around them.
 //
 // Activations are BF16, channels last ([sample][row][column][channel]); the
-// network input has 8 stored channels (f - 1, g - 1, six zeros), hidden layers 32.
+// network input has 8 stored channels (log f, log g of the mean-one densities, six
+// zeros), hidden layers 32.
 // A convolution is an implicit GEMM per 16-pixel strip: D[co][pixel] =
 // sum_k A[co][k] B[k][pixel] with k = tap * C_in + ci, computed by
 // v_mfma_f32_16x16x32_bf16 (lane l holds A[l%16][8(l/16)..+7], B[8(l/16)..+7][l%16]
@@ -215,7 +216,7 @@ __global__ void k_pack(const float* __restrict__ Wm, int Co, int Ci, int flip, i
   out[idx] = (bf16)v;
 }
 
-// network input: channels (f/mean f - 1, g/mean g - 1, 0 x 6)
+// network input: channels (log(f/mean f), log(g/mean g), 0 x 6)
 __global__ void k_means(const double* __restrict__ f, const double* __restrict__ g, int n, double* __restrict__ means) {
   const int s = blockIdx.x >> 1, which = blockIdx.x & 1;
   const double* x = (which ? g : f) + (size_t)s * n * n;
@@ -238,8 +239,8 @@ __global__ void k_input(const double* __restrict__ f, const double* __restrict__
   if (i >= total) return;
   const int s = (int)(i / ((size_t)n * n));
   bf16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
-  v[0] = (bf16)(float)(f[i] / means[2 * s] - 1.0);
-  v[1] = (bf16)(float)(g[i] / means[2 * s + 1] - 1.0);
+  v[0] = (bf16)(float)log(f[i] / means[2 * s]);
+  v[1] = (bf16)(float)log(g[i] / means[2 * s + 1]);
   out[i] = v;
 }
 

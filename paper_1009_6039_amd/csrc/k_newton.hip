@@ -77,7 +77,12 @@ __global__ __launch_bounds__(MA_BLOCK) void k_setup_fields(LaunchCtx c) {
     v.g2 = (float)g2;
     d.gs[e] = v;
     d.f[e] = d.f_in[e] * inv_f;
-    d.u[e] = d.psi0_in ? d.psi0_in[e] - s.mean_psi0 : 0.0;
+    if (s.warm) {  // checked start: u0 = 0, the initial potential waits in theta
+      d.u[e] = 0.0;
+      d.theta[e] = d.psi0_in[e] - s.mean_psi0;
+    } else {
+      d.u[e] = d.psi0_in ? d.psi0_in[e] - s.mean_psi0 : 0.0;
+    }
   }
 }
 
@@ -95,7 +100,9 @@ __device__ static void newton_decide(PairState& s, const LaunchCtx& c, int n, co
   const bool convex = finite && tot[10] > 0.0 && tot[11] > 0.0;
   const int ph = s.phase;
 
-  if (ph == PH_REVERT) {  // the restored iterate: record it and stop (status already set)
+  if (ph == PH_REVERT && s.warm_fallback) {
+    s.warm_fallback = 0;  // the initial potential never helped: continue Newton from u = 0
+  } else if (ph == PH_REVERT) {  // the restored iterate: record it and stop (status already set)
     s.res_rms = res;
     s.res_max = fmax(fabs(tot[12] + cst), fabs(tot[13] + cst));
     s.mass_c = cst;
@@ -106,16 +113,23 @@ __device__ static void newton_decide(PairState& s, const LaunchCtx& c, int n, co
     return;
   }
   const bool trial = (ph == PH_SOLVE || ph == PH_BACKTRACK);
-  if (trial && c.damping_policy == MA_DAMP_BACKTRACK) {
+  if (trial && (c.damping_policy == MA_DAMP_BACKTRACK || s.warm_trial)) {
     const bool accept = convex && res < s.res_prev;
     if (!accept) {
-      s.backtracks++;
       s.bt_step++;
-      s.tau *= 2.0;
+      if (!s.warm_trial) {
+        s.backtracks++;
+        s.tau *= 2.0;
+      }
       if (s.bt_step > c.max_backtrack) {  // give up: restore the last accepted iterate
-        s.status = MA_ENOCONV;
         s.phase = PH_REVERT;
         s.axpy = -s.step;
+        if (s.warm_trial) {
+          s.warm_trial = 0;
+          s.warm_fallback = 1;
+        } else {
+          s.status = MA_ENOCONV;
+        }
       } else {
         s.phase = PH_BACKTRACK;
         s.axpy = -0.5 * s.step;
@@ -123,7 +137,12 @@ __device__ static void newton_decide(PairState& s, const LaunchCtx& c, int n, co
       }
       return;
     }
-    s.tau = fmax(s.tau0, 0.5 * s.tau);
+    if (s.warm_trial) {
+      s.warm_trial = 0;
+      s.warm_steps = 1;
+    } else if (c.damping_policy == MA_DAMP_BACKTRACK) {
+      s.tau = fmax(s.tau0, 0.5 * s.tau);
+    }
   }
   // the evaluation is accepted: record it
   s.res_rms = res;
@@ -135,6 +154,16 @@ __device__ static void newton_decide(PairState& s, const LaunchCtx& c, int n, co
   s.mean_u = tot[9] / NN;
   for (int k = 0; k < 5; ++k) s.abar[k] = tot[3 + k];
   if (ph == PH_INIT) s.res0 = res;
+  if (ph == PH_INIT && s.warm && finite && res > s.tol) {
+    // checked start: try the initial potential (stored in theta) as the first step
+    s.phase = PH_BACKTRACK;
+    s.warm_trial = 1;
+    s.axpy = 1.0;
+    s.step = 1.0;
+    s.bt_step = 0;
+    s.res_prev = res;
+    return;
+  }
   if (!finite) {
     s.status = MA_ENAN;
     s.phase = PH_DONE;
@@ -331,7 +360,7 @@ __global__ __launch_bounds__(MA_BLOCK) void k_step_update(LaunchCtx c) {
   const double a = s.axpy;
   const long nn = (long)d.n * d.n;
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (long)gridDim.x * blockDim.x)
-    d.u[e] += a * (double)d.theta[e];
+    d.u[e] += a * d.theta[e];
 }
 
 // psi = u - mean(u); map = x + D_h u (fourth-order differences), unwrapped

@@ -338,8 +338,8 @@ __global__ __launch_bounds__(Cfg<N>::C_BLOCK) void k_passC(LaunchCtx c, int mode
   if (!run) return;
 
   // three half spectra 12, coefficients 20, Krylov vectors for the dots, w 4 (matvec);
-  // one half spectrum 4, theta 4, u read and written 16 (recovery)
-  count_bytes(c, mode == PC_MATVEC ? 36.0 + 4.0 * (j + 1) : (mode == PC_RECOVER ? 24.0 : 8.0), N);
+  // one half spectrum 4, theta 8, u read and written 16 (recovery)
+  count_bytes(c, mode == PC_MATVEC ? 36.0 + 4.0 * (j + 1) : (mode == PC_RECOVER ? 28.0 : 8.0), N);
   __shared__ float2 lds[5 * PPB * N];
   __shared__ double red[(BLOCK / 64) * (MA_MMAX + 1)];
   const int row0 = 2 * blockIdx.x * PPB;
@@ -367,11 +367,14 @@ __global__ __launch_bounds__(Cfg<N>::C_BLOCK) void k_passC(LaunchCtx c, int mode
       const int pp = e / N, jj = e % N;
       const long ea = (long)(row0 + 2 * pp) * N + jj, eb = ea + N;
       const float2 z = lds[pp * N + jj];
-      d.theta[ea] = z.x;
-      d.theta[eb] = z.y;
-      if (mode == PC_RECOVER) {
+      if (mode == PC_RECOVER) {  // FP64 correction kept for step halving; u in FP64
+        d.theta[ea] = (double)z.x;
+        d.theta[eb] = (double)z.y;
         d.u[ea] += (double)z.x;
         d.u[eb] += (double)z.y;
+      } else {  // single-step use: FP32 result in the x buffer
+        d.x[ea] = z.x;
+        d.x[eb] = z.y;
       }
     }
     return;

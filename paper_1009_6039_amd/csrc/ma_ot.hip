@@ -74,7 +74,8 @@ size_t pair_bytes(int n, int m) {
   b += align256(8 * nn) * 2;              // u, f
   b += align256(16 * nn);                 // gs
   b += align256(20 * nn);                 // coef
-  b += align256(4 * nn) * 3;              // r, theta, x
+  b += align256(4 * nn) * 2;              // r, x
+  b += align256(8 * nn);                  // theta
   b += align256(4 * nn * (size_t)(m + 1));  // V
   b += align256(4 * nn);                  // H
   b += align256(12 * nn);                 // T
@@ -95,7 +96,7 @@ void carve(PairDesc& d, char*& p, int n, int m) {
   d.gs = (GS*)take(16 * nn);
   d.coef = (float*)take(20 * nn);
   d.r = (float*)take(4 * nn);
-  d.theta = (float*)take(4 * nn);
+  d.theta = (double*)take(8 * nn);
   d.x = (float*)take(4 * nn);
   d.V = (float*)take(4 * nn * (size_t)(m + 1));
   d.H = (float2*)take(4 * nn);
@@ -317,6 +318,7 @@ void launch_cycle_body(ma_plan* P, const std::vector<Class>& cls, hipStream_t st
 int run_solver(ma_plan* P, int npairs, double damping, double tol, hipStream_t st, std::vector<Class>& cls) {
   HIP_TRY(hipMemcpyAsync(P->d_desc, P->h_desc.data(), sizeof(PairDesc) * npairs, hipMemcpyHostToDevice, st));
   P->h_state.assign(npairs, fresh_state(damping, tol));
+  for (int q = 0; q < npairs; ++q) P->h_state[q].warm = P->h_desc[q].psi0_in != nullptr;
   HIP_TRY(hipMemcpyAsync(P->d_state, P->h_state.data(), sizeof(PairState) * npairs, hipMemcpyHostToDevice, st));
   for (const Class& c : cls) launch_setup(make_ctx(P, c), c.n, (int)c.ids.size(), st);
   int e = read_summary(P, npairs, st);
@@ -373,6 +375,7 @@ void fill_report(const PairState& s, ma_report* r, double ms) {
   r->w2sq = s.w2;
   r->tau_final = s.tau;
   r->time_ms = ms;
+  r->warm_steps = s.warm_steps;
 }
 
 // one-pair workspace for the step entry points; state copied from `s`
@@ -626,7 +629,7 @@ int ma_step_lbar_inverse(ma_plan* P, int n, const float* sigma, const double* ab
   launch_passA(x, n, 1, PA_STEP, 0, c.tw, st);
   launch_passB(x, n, 1, PB_RECOVER, 0, c.tw, st);
   launch_passC(x, n, 1, PC_THETA_ONLY, 0, c.tw, st);
-  HIP_TRY(hipMemcpyAsync(theta, d.theta, 4 * nn, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(hipMemcpyAsync(theta, d.x, 4 * nn, hipMemcpyDeviceToDevice, st));
   return MA_OK;
 }
 
@@ -683,7 +686,7 @@ int ma_step_gmres(ma_plan* P, int n, const float* h, const float* coef, const do
     launch_passA(x, n, 1, PA_RECOVER, 0, c.tw, st);
     launch_passB(x, n, 1, PB_RECOVER, 0, c.tw, st);
     launch_passC(x, n, 1, PC_THETA_ONLY, 0, c.tw, st);
-    if (hipMemcpyAsync(theta, d.theta, 4 * nn, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+    if (hipMemcpyAsync(theta, d.x, 4 * nn, hipMemcpyDeviceToDevice, st) != hipSuccess ||
         hipMemcpyAsync(P->h_state.data(), P->d_state, sizeof(PairState), hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess) {
       rc = MA_EHIP;

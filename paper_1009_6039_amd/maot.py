@@ -47,7 +47,8 @@ class Report(ctypes.Structure):
                 ("res_rms", ctypes.c_double), ("res_max", ctypes.c_double),
                 ("res0_rms", ctypes.c_double), ("mass_defect", ctypes.c_double),
                 ("min_det", ctypes.c_double), ("w2sq", ctypes.c_double),
-                ("tau_final", ctypes.c_double), ("time_ms", ctypes.c_double)]
+                ("tau_final", ctypes.c_double), ("time_ms", ctypes.c_double),
+                ("warm_steps", ctypes.c_int), ("pad", ctypes.c_int)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

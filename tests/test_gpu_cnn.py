@@ -62,9 +62,12 @@ def test_forward_matches_oracle(maot):
         for k in range(B):
             ref, _ = cnn.forward(cnn.network_input(f[k], g[k]), params, bf16=True)
             assert rel_l2(c[k], ref[0]) < 2e-3, k
-        # the prepared input is the BF16 rounding of (f/mean - 1, g/mean - 1)
+        # the prepared input is the BF16 rounding of (log(f/mean), log(g/mean)); the device
+        # logarithm may differ from NumPy's in the last FP32 bit, which moves rare roundings
         xin = x.float().cpu().numpy()
-        assert np.array_equal(xin[0, :, :, 0], cnn.bf16_round(f[0] / f[0].mean() - 1.0).astype(np.float32))
+        ref_in = cnn.bf16_round(np.log(f[0] / f[0].mean())).astype(np.float32)
+        assert np.mean(xin[0, :, :, 0] == ref_in) > 0.99
+        assert np.max(np.abs(xin[0, :, :, 0] - ref_in)) <= 2.0 ** -7 * np.max(np.abs(ref_in))
         assert np.all(xin[..., 2:] == 0)
     finally:
         net.close()

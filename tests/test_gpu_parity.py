@@ -274,6 +274,24 @@ def test_fd4_symbol_solve_matches_oracle(maot):
         p.close()
 
 
+def test_checked_start_matches_oracle(maot):
+    N = 64
+    f, g, ps = W.manufactured(N, A=0.01)
+    ref, _, r0 = ma.solve(f, g, tol=1e-11)
+    p = maot.Plan(n_max=N, batch_capacity=1)
+    try:
+        psi, _, rep = p.solve(dev(f), dev(g), damping=1.0, tol=1e-10, psi0=dev(ps))
+        assert rep["status"] == 0 and rep["warm_steps"] == 1 and rep["newton_iters"] < r0.newton_iters
+        assert np.max(np.abs(host(psi) - ref)) <= 1e-6 * np.max(np.abs(ref))
+        bad = 3.0 * np.sin(2 * np.pi * np.arange(N) / N)[:, None] * np.ones((1, N))
+        psi, _, rep = p.solve(dev(f), dev(g), damping=1.0, tol=1e-10, psi0=dev(bad))
+        _, _, rb = ma.solve(f, g, tol=1e-10, psi0=bad)
+        assert rep["status"] == 0 and rep["warm_steps"] == rb.warm_steps
+        assert np.max(np.abs(host(psi) - ref)) <= 1e-6 * np.max(np.abs(ref))
+    finally:
+        p.close()
+
+
 # ------------------------------------------------------------------ batched
 
 def test_batched_equals_single_bitwise(maot):

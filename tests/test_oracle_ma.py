@@ -346,3 +346,17 @@ def test_fd4_symbol_newton_converges_to_the_same_fixed_point_faster():
     assert ra.status == rb.status == ma.OK
     assert np.max(np.abs(a - b)) < 1e-9 * max(1.0, np.max(np.abs(a))) * 10
     assert rb.newton_iters < ra.newton_iters
+
+
+def test_checked_start_accepts_a_good_guess_and_survives_a_bad_one():
+    N = 32
+    f, g, ps = W.manufactured(N, A=0.01)
+    ref, _, r0 = ma.solve(f, g, tol=1e-10)
+    # a good guess is taken at full step and saves Newton iterations
+    good, _, rg = ma.solve(f, g, tol=1e-10, psi0=ps)
+    assert rg.warm_steps == 1 and rg.newton_iters < r0.newton_iters
+    assert np.max(np.abs(good - ref)) < 1e-9
+    # a guess that makes I + D^2 psi indefinite is halved until it helps, or dropped
+    bad = 3.0 * np.sin(2 * np.pi * np.arange(N) / N)[:, None] * np.ones((1, N))
+    out, _, rb = ma.solve(f, g, tol=1e-10, psi0=bad)
+    assert rb.status == ma.OK and np.max(np.abs(out - ref)) < 1e-9
