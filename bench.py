@@ -3,10 +3,17 @@
 
 One step solves a batch of blob-density pairs (8 periodic Gaussian blobs on a 0.1
 floor, seeded) of size 512 x 512 with the damped Newton / Strain-GMRES method to
-an rms residual of 1e-6, all pairs in one batched call.  The inputs are resident
-in device memory before the timed region.  Prints one JSON line.
+an rms residual of 1e-6, all pairs in one batched call.  Arms: the plain method
+(Newton from zero) and the learned start (the warm-start network's guess for every
+pair, computed inside the timed region, then Newton from it), each with the linear
+solve's symbols taken from the fourth-order differences (fd4: the Jacobian of the
+discrete residual, the same fixed point in fewer iterations) and with the paper's
+spectral symbols.  `value` is the first symbol's learned-start throughput; every arm
+is reported beside it.  The inputs are resident in device memory before the timed
+region.  Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--batch B] [--gpus 1]
+  python bench.py [--steps K] [--warmup W] [--batch B] [--gpus 1] [--init both|zero|learned]
+                  [--symbols fd4,spectral]
 """
 
 import argparse
@@ -17,6 +24,7 @@ import time
 
 import numpy as np
 
+HERE = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 METRIC = "Newton-solved pairs/sec at 512^2 to residual 1e-6; learned-init vs plain"
 
@@ -31,9 +39,14 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--gmres-tol", type=float, default=0.1)
     ap.add_argument("--damping-policy", default="backtrack")
-    ap.add_argument("--symbol", default="spectral", help="spectral (the paper) or fd4 (option)")
+    ap.add_argument("--symbols", default="fd4,spectral",
+                    help="comma list of linear-solve symbols; the first is the headline")
     ap.add_argument("--profile-class", default="row_c",
                     help="kernel class timed for the roofline: residual, row_a, column, row_c")
+    ap.add_argument("--init", default="both", choices=("both", "zero", "learned"),
+                    help="arms to time; value is the learned arm unless only zero is run")
+    ap.add_argument("--weights", default=os.path.join(HERE, "paper_1009_6039_amd", "warmstart_256.npz"))
+    ap.add_argument("--cpu-pairs", type=int, default=4, help="pairs in the oracle's timed sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB mebibytes (scales HBM byte counters)")
@@ -52,17 +65,40 @@ def copy_probe(mib):
     print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4}), flush=True)
 
 
-def cpu_baseline(f, g, args):
-    """The FP64 oracle on one pair of the same workload, pinned to one thread."""
+def load_weights(path):
+    """Trained warm-start parameters and their shape (layers, channels, n_net)."""
+    d = np.load(path, allow_pickle=False)
+    meta = json.loads(str(d["meta"]))
+    return d["params"].astype(np.float32), meta
+
+
+def cpu_baseline(pairs, args, params=None, meta=None):
+    """The FP64 oracle on a sample of pairs of the same workload, pinned to one thread:
+    the network's start (BF16 emulation) when params are given, then the solve."""
     from threadpoolctl import threadpool_limits
-    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
-    from oracle import ma
+    sys.path.insert(0, HERE)
+    from oracle import cnn, ma
+    psis = []
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        psi, _, rep = ma.solve(f, g, tau=1.0, tol=args.tol, damping_policy=args.damping_policy,
-                               gmres_tol=args.gmres_tol, max_newton=300, symbol=args.symbol)
+        for f, g in pairs:
+            psi0 = None
+            if params is not None:
+                shaped = cnn.unflatten_params(params, meta["layers"], meta["channels"])
+                psi0 = cnn.warm_start(f, g, shaped, meta["n_net"])
+            psi, _, _ = ma.solve(f, g, tau=1.0, tol=args.tol, damping_policy=args.damping_policy,
+                                 gmres_tol=args.gmres_tol, max_newton=300, symbol=args.symbol0, psi0=psi0)
+            psis.append(psi)
         dt = time.perf_counter() - t0
-    return psi, rep, dt
+    return psis, dt
+
+
+def summary(reps):
+    return {"newton_iters_mean": float(np.mean([r["newton_iters"] for r in reps])),
+            "gmres_iters_mean": float(np.mean([r["gmres_iters"] for r in reps])),
+            "backtracks_mean": float(np.mean([r["backtracks"] for r in reps])),
+            "warm_accepted": int(sum(r["warm_steps"] for r in reps)),
+            "res_rms_max": float(max(r["res_rms"] for r in reps))}
 
 
 def main():
@@ -72,7 +108,7 @@ def main():
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this solver build runs on a single device "
-              "(batches of pairs would shard across GPUs without communication; see the design notes)",
+              "(batches of pairs would shard across GPUs without communication)",
               file=sys.stderr)
         sys.exit(2)
     import torch
@@ -84,31 +120,56 @@ def main():
     host_pairs = [W.blobs(N, s) for s in seeds]
     fs = [torch.from_numpy(f).cuda() for f, _ in host_pairs]
     gs = [torch.from_numpy(g).cuda() for _, g in host_pairs]
-    plan = maot.Plan(n_max=N, batch_capacity=B, damping_policy=args.damping_policy,
-                     gmres_tol=args.gmres_tol, max_newton=300, symbol=args.symbol)
+    symbols = args.symbols.split(",")
+    args.symbol0 = symbols[0]
+    plans = {sym: maot.Plan(n_max=N, batch_capacity=B, damping_policy=args.damping_policy,
+                            gmres_tol=args.gmres_tol, max_newton=300, symbol=sym) for sym in symbols}
 
-    def step():
-        psis, _, reps = plan.solve_batched(fs, gs, damping=1.0, tol=args.tol)
+    net, params, meta = None, None, None
+    if args.init != "zero":
+        params, meta = load_weights(args.weights)
+        net = maot.WarmStartNet(layers=meta["layers"], channels=meta["channels"], n_net=meta["n_net"],
+                                max_batch=B)
+        net.set_params(params)
+
+    def step(plan, learned):
+        psi0 = net.warm_start(fs, gs) if learned else None
+        psis, _, reps = plan.solve_batched(fs, gs, damping=1.0, tol=args.tol, psi0s=psi0)
         bad = [r for r in reps if r["status"] != 0 or r["res_rms"] > args.tol]
         if bad:
             raise RuntimeError("unsolved pairs: %d (first: %s)" % (len(bad), bad[0]))
         return psis, reps
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    plan.profile(args.profile_class)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        psis, reps = step()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    prof = plan.profile_read()
-    plan.profile("none")
+    def timed(plan, learned, profile):
+        for _ in range(args.warmup):
+            step(plan, learned)
+        torch.cuda.synchronize()
+        if profile:
+            plan.profile(args.profile_class)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            psis, reps = step(plan, learned)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        prof = plan.profile_read() if profile else None
+        plan.profile("none")
+        return elapsed, psis, reps, prof
+
+    inits = {"both": ("zero", "learned"), "zero": ("zero",), "learned": ("learned",)}[args.init]
+    head = (symbols[0], inits[-1])
+    arms = {}
+    for sym in reversed(symbols):  # the headline arm runs last: its launches end the kernel trace
+        for init in inits:
+            arms[(sym, init)] = timed(plans[sym], init == "learned", (sym, init) == head)
+            print("arm %s/%s: %.3f pairs/s" % (sym, init, B * args.steps / arms[(sym, init)][0]),
+                  file=sys.stderr, flush=True)
+    elapsed, psis, reps, prof = arms[head]
 
     pairs = B * args.steps
     value = pairs / elapsed
     achieved = prof["bytes"] / (prof["ms"] * 1e-3) / 1e9 if prof["ms"] > 0 else 0.0
+    init_txt = ("learned start (8-layer 32-channel network at 256^2, checked)" if head[1] == "learned"
+                else "zero init")
     out = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -123,30 +184,40 @@ def main():
         "dtype": "f32/f64",
         "data": "synthetic",
         "config": {"workload": "blob-density pairs %dx%d (8 periodic Gaussian blobs, 0.1 floor), "
-                               "batch %d per step, rms residual %.0e, plain zero init" % (N, N, B, args.tol),
+                               "batch %d per step, rms residual %.0e, %s, %s symbols"
+                               % (N, N, B, args.tol, init_txt, head[0]),
                    "n": N, "batch": B, "tol": args.tol, "damping_policy": args.damping_policy,
-                   "gmres_tol": args.gmres_tol, "gmres_m": 10, "init": "zero", "symbol": args.symbol},
-        "newton_iters_mean": float(np.mean([r["newton_iters"] for r in reps])),
-        "gmres_iters_mean": float(np.mean([r["gmres_iters"] for r in reps])),
-        "backtracks_mean": float(np.mean([r["backtracks"] for r in reps])),
-        "res_rms_max": float(max(r["res_rms"] for r in reps)),
-        "roofline": {"bound": "hbm", "kernel": args.profile_class, "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "launches": prof["launches"],
-                     "avg_launch_us": round(1e3 * prof["ms"] / max(prof["launches"], 1), 3),
-                     "bytes_per_launch": round(prof["bytes"] / max(prof["launches"], 1)),
-                     "algorithmic_bytes_total": prof["bytes"]},
+                   "gmres_tol": args.gmres_tol, "gmres_m": 10, "init": head[1], "symbol": head[0]},
     }
+    out.update(summary(reps))
+    out["arms"] = {}
+    for (sym, init), (el, _, rp, _) in arms.items():
+        out["arms"]["%s/%s" % (sym, init)] = dict(value=round(pairs / el, 3),
+                                                  ms_per_step=round(1e3 * el / args.steps, 3), **summary(rp))
+    for sym in symbols:
+        if (sym, "zero") in arms and (sym, "learned") in arms:
+            out["learned_vs_plain_" + sym] = round(arms[(sym, "zero")][0] / arms[(sym, "learned")][0], 4)
+    out["roofline"] = {"bound": "hbm", "kernel": args.profile_class, "achieved": round(achieved, 1),
+                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                       "traffic": None, "launches": prof["launches"],
+                       "avg_launch_us": round(1e3 * prof["ms"] / max(prof["launches"], 1), 3),
+                       "bytes_per_launch": round(prof["bytes"] / max(prof["launches"], 1)),
+                       "algorithmic_bytes_total": prof["bytes"]}
     if not args.no_cpu_baseline:
-        f0, g0 = host_pairs[0]
-        psi_ref, rep_ref, dt = cpu_baseline(f0, g0, args)
-        err = float(np.max(np.abs(psis[0].cpu().numpy() - psi_ref)) / np.max(np.abs(psi_ref)))
-        out["cpu_baseline"] = {"value": round(1.0 / dt, 5), "unit": "pairs/s", "cores": 1, "kind": "oracle",
-                               "sample": "1 pair (seed %d) of the same workload, FP64 NumPy oracle, "
-                                         "one thread, %.1f s" % (seeds[0], dt)}
-        out["err_vs_oracle_pair0"] = err
+        k = min(args.cpu_pairs, B)
+        refs, dt = cpu_baseline(host_pairs[:k], args, params if head[1] == "learned" else None, meta)
+        err = max(float(np.max(np.abs(psis[q].cpu().numpy() - refs[q])) / np.max(np.abs(refs[q])))
+                  for q in range(k))
+        out["cpu_baseline"] = {"value": round(k / dt, 5), "unit": "pairs/s", "cores": 1, "kind": "oracle",
+                               "sample": "%d pairs (seeds %d..%d) of the same workload (%s, %s symbols), FP64 "
+                                         "NumPy oracle, one thread, %.1f s"
+                                         % (k, seeds[0], seeds[k - 1], init_txt, head[0], dt)}
+        out["err_vs_oracle_max"] = err
     print(json.dumps(out), flush=True)
-    plan.close()
+    if net is not None:
+        net.close()
+    for plan in plans.values():
+        plan.close()
 
 
 if __name__ == "__main__":

@@ -208,10 +208,12 @@ int ma_step_gmres(ma_plan* plan, int n, const float* h, const float* coef,
 /* ---------------------------------------------------------------------------
  * Learned warm start (not in the paper): a periodic-padded 3x3 convolutional
  * network, BF16 on MFMA with FP32 accumulation, trained on pairs the solver
- * produces.  It maps (log f, log g) at resolution n_net to c, an estimate of the
- * fourth-order difference Laplacian of the potential; the initial guess is
- * psi0 = (that Laplacian)^{-1} c, mean zero.  Zero-init Newton stays the fallback
- * (the caller re-solves pairs the warm start does not help).
+ * produces.  Linearising the equation about psi = 0 (Section 2) gives
+ * Laplacian(psi) = log f - log g to first order for mean-one densities; the network
+ * maps (log f, log g) at resolution n_net to c, its estimate of the remainder of the
+ * fourth-order difference Laplacian of the potential, and the initial guess is
+ * psi0 = (that Laplacian)^{-1} (c + log f - log g), mean zero.  The solver takes
+ * psi0 as a checked start (ma_solve), so zero-init Newton stays the fallback.
  *
  * Parameters are FP32 masters in the order W_0, b_0, W_1, b_1, ... with
  * W_l[co][ci][3][3], 2 input channels, `channels` hidden, 1 output channel.
@@ -230,8 +232,11 @@ int ma_cnn_get_params(const ma_cnn* net, float* host_params, long count);
 
 /* f, g: device FP64 [batch][n_net][n_net]; x: device BF16 [batch][n_net][n_net][8]. */
 int ma_cnn_prepare_input(ma_cnn* net, const double* f, const double* g, int batch, void* x, void* stream);
-/* target = fourth-order difference Laplacian of psi (device FP64 -> FP32), [batch][n][n]. */
-int ma_cnn_laplacian(ma_cnn* net, const double* psi, int batch, int n, float* target, void* stream);
+/* Training target, device FP64 in, FP32 out, all [batch][n][n]: the fourth-order
+ * difference Laplacian of psi minus log(f / mean f) - log(g / mean g).  f and g may
+ * both be NULL (then the plain Laplacian); one NULL without the other is MA_EINVAL. */
+int ma_cnn_target(ma_cnn* net, const double* psi, const double* f, const double* g, int batch, int n,
+                  float* target, void* stream);
 /* c: device FP32 [batch][n_net][n_net]. */
 int ma_cnn_forward(ma_cnn* net, const void* x, int batch, float* c, void* stream);
 /* forward, MSE against target, backward: gradients (device FP32, parameter order)
@@ -243,7 +248,8 @@ int ma_cnn_gradients(ma_cnn* net, const void* x, const float* target, int batch,
 int ma_cnn_train_step(ma_cnn* net, const void* x, const float* target, int batch, float lr, float* loss,
                       void* stream);
 /* psi0 for npairs pairs of size n (n == n_net, or n == 2 n_net: the densities are
- * restricted by full weighting and c is prolonged bilinearly before the head).
+ * restricted by full weighting for the network and c is prolonged bilinearly; the log
+ * ratio is taken at full resolution).
  * Arrays of pointers are host arrays of device pointers. */
 int ma_cnn_warm_start(ma_cnn* net, int npairs, int n, const double* const* f, const double* const* g,
                       double* const* psi0, void* stream);

@@ -5,10 +5,11 @@ TEST INFRASTRUCTURE ONLY (see the package header).
 The network is not part of the paper; it supplies the Newton initial guess.
 Layers l = 0..L-1: z_l = conv3x3_periodic(h_l, W_l) + b_l, h_{l+1} = relu(z_l) for
 l < L-1 and h_L = z_{L-1} (no activation on the output).  Input channels are
-(log f, log g) for densities scaled to mean one.  The output c approximates the
-fourth-order difference Laplacian of the solver's potential; the initial guess is
-psi0 = (discrete Laplacian)^{-1} c with zero mean (the head, applied outside the
-network).
+(log f, log g) for densities scaled to mean one.  Linearised about psi = 0 the
+equation of Section 2 reads Laplacian(psi) = log f - log g; the output c approximates
+what that misses of the fourth-order difference Laplacian of the solver's potential,
+and the initial guess is psi0 = (discrete Laplacian)^{-1} (c + log f - log g) with
+zero mean (the head, applied outside the network).
 
 Convolution convention: out[co, i, j] = b[co] + sum_{ci, a, b} W[co, ci, a, b] *
 x[ci, (i + a - 1) mod H, (j + b - 1) mod W], a, b in {0, 1, 2}.
@@ -85,6 +86,22 @@ def init_params(channels=32, layers=8, c_in=2, c_out=1, seed=0):
             W *= 0.1
         params.append((W, np.zeros(co)))
     return params
+
+
+def unflatten_params(flat, layers, channels, c_in=2, c_out=1):
+    """Flat array in the order W_0, b_0, W_1, b_1, ... (W_l[co][ci][3][3]) -> [(W, b)]."""
+    chans = [c_in] + [channels] * (layers - 1) + [c_out]
+    out, k = [], 0
+    flat = np.asarray(flat, dtype=np.float64)
+    for l in range(layers):
+        ci, co = chans[l], chans[l + 1]
+        W = flat[k:k + co * ci * 9].reshape(co, ci, 3, 3)
+        k += co * ci * 9
+        out.append((W, flat[k:k + co].copy()))
+        k += co
+    if k != flat.size:
+        raise ValueError("parameter count %d does not match %d" % (flat.size, k))
+    return out
 
 
 def forward(x, params, bf16=False):
@@ -183,13 +200,24 @@ def network_input(f, g):
     return np.stack([np.log(f / f.mean()), np.log(g / g.mean())])
 
 
+def log_ratio(f, g):
+    """log f - log g for mean-one densities: the Laplacian of the linearised solution."""
+    return np.log(f / f.mean()) - np.log(g / g.mean())
+
+
+def training_target(psi, f=None, g=None):
+    """laplacian_fd4(psi) - log_ratio(f, g) (the plain Laplacian without f, g)."""
+    t = laplacian_fd4(psi)
+    return t if f is None else t - log_ratio(f, g)
+
+
 def warm_start(f, g, params, n_net, bf16=True):
-    """psi0 for one pair: restrict if needed, run the network, prolong, invert the Laplacian."""
+    """psi0 for one pair: restrict if needed, run the network, prolong, add the log
+    ratio at full resolution, invert the Laplacian."""
     n = f.shape[0]
-    if n == 2 * n_net:
-        f, g = restrict_full_weighting(f), restrict_full_weighting(g)
-    c, _ = forward(network_input(f, g), params, bf16=bf16)
+    fr, gr = (restrict_full_weighting(f), restrict_full_weighting(g)) if n == 2 * n_net else (f, g)
+    c, _ = forward(network_input(fr, gr), params, bf16=bf16)
     c = c[0]
     if n == 2 * n_net:
         c = prolong_bilinear(c)
-    return inverse_laplacian_fd4(c)
+    return inverse_laplacian_fd4(c + log_ratio(f, g))

@@ -11,11 +11,17 @@ void cnn_conv(int cin, int cout_pad, int mode, const void* in, const void* wp, c
 void cnn_wgrad(int cin, int cout, const void* h, const void* dz, int batch, int H, int W, int cout_real, int cin_real,
                float* part, float* partb, int nblk, float* gw, float* gb, hipStream_t st);
 void cnn_pack(const float* Wm, int Co, int Ci, int flip, int cin_store, int cout_pad, void* out, hipStream_t st);
-void cnn_input(const double* f, const double* g, int batch, int n, double* means, void* x, hipStream_t st);
+constexpr int CNN_MEAN_PARTS = 64;  // partial sums per field in the mean reductions
+void cnn_means(const double* f, const double* g, int batch, int n, double* part, double* means, hipStream_t st);
+void cnn_input(const double* f, const double* g, int batch, int n, double* part, double* means, void* x,
+               hipStream_t st);
 void cnn_mse(const float* c, const float* t, size_t count, void* dz, float* part, int nblk, float* loss, hipStream_t st);
 void cnn_adam(float* p, const float* g, float* m, float* v, int count, float lr, float b1, float b2, float c1, float c2,
               float eps, hipStream_t st);
-void cnn_laplacian(const double* u, int batch, int n, float* out, hipStream_t st);
+void cnn_target(const double* u, const double* f, const double* g, int batch, int n, double* part, double* means,
+                float* out, hipStream_t st);
+void cnn_add_log_ratio(const float* c, const double* f, const double* g, int n, double* part, double* means,
+                       float* out, hipStream_t st);
 void cnn_restrict(const double* x, int n_coarse, double* y, hipStream_t st);
 void cnn_prolong(const float* x, int n_coarse, float* y, hipStream_t st);
 void cnn_to_double(const float* x, size_t count, double* y, hipStream_t st);

@@ -8,6 +8,7 @@
 
 #include "cnn.h"
 #include "ma_ot.h"
+#include "plan_internal.h"
 
 namespace {
 
@@ -43,7 +44,7 @@ struct ma_cnn {
   long step = 0;
   std::vector<Buf> wfwd, wbwd;     // packed BF16 weights per layer
   std::vector<Buf> act;            // h_1 .. h_{L-1}, BF16 32 channels
-  Buf c, dz_last, dzA, dzB, part, partb, lpart, loss, means, fx, gx, cbuf, cup, theta;
+  Buf c, dz_last, dzA, dzB, part, partb, lpart, loss, means, mpart, fx, gx, cbuf, cup, clin, theta;
   ma_plan* head = nullptr;         // fourth-order inverse Laplacian for the warm-start head
   int head_n = 0;
 };
@@ -189,8 +190,8 @@ void ma_cnn_destroy(ma_cnn* N) {
   for (auto& b : N->wfwd) b.release();
   for (auto& b : N->wbwd) b.release();
   for (auto& b : N->act) b.release();
-  for (Buf* b : {&N->c, &N->dz_last, &N->dzA, &N->dzB, &N->part, &N->partb, &N->lpart, &N->loss, &N->means, &N->fx,
-                 &N->gx, &N->cbuf, &N->cup, &N->theta})
+  for (Buf* b : {&N->c, &N->dz_last, &N->dzA, &N->dzB, &N->part, &N->partb, &N->lpart, &N->loss, &N->means, &N->mpart, &N->fx,
+                 &N->gx, &N->cbuf, &N->cup, &N->clin, &N->theta})
     b->release();
   if (N->head) ma_plan_destroy(N->head);
   delete N;
@@ -220,13 +221,17 @@ int ma_cnn_get_params(const ma_cnn* N, float* host, long count) {
 int ma_cnn_prepare_input(ma_cnn* N, const double* f, const double* g, int batch, void* x, void* stream) {
   if (!N || !f || !g || !x || batch < 1) return MA_EINVAL;
   TRY(N->means.ensure((size_t)2 * batch * 8));
-  cnn_input(f, g, batch, N->n, (double*)N->means.p, x, (hipStream_t)stream);
+  TRY(N->mpart.ensure((size_t)2 * batch * CNN_MEAN_PARTS * 8));
+  cnn_input(f, g, batch, N->n, (double*)N->mpart.p, (double*)N->means.p, x, (hipStream_t)stream);
   return hipGetLastError() == hipSuccess ? MA_OK : MA_EHIP;
 }
 
-int ma_cnn_laplacian(ma_cnn* N, const double* psi, int batch, int n, float* target, void* stream) {
-  if (!N || !psi || !target || batch < 1 || n < 8) return MA_EINVAL;
-  cnn_laplacian(psi, batch, n, target, (hipStream_t)stream);
+int ma_cnn_target(ma_cnn* N, const double* psi, const double* f, const double* g, int batch, int n, float* target,
+                  void* stream) {
+  if (!N || !psi || !target || batch < 1 || n < 8 || (!f) != (!g)) return MA_EINVAL;
+  TRY(N->means.ensure((size_t)2 * batch * 8));
+  TRY(N->mpart.ensure((size_t)2 * batch * CNN_MEAN_PARTS * 8));
+  cnn_target(psi, f, g, batch, n, (double*)N->mpart.p, (double*)N->means.p, target, (hipStream_t)stream);
   return hipGetLastError() == hipSuccess ? MA_OK : MA_EHIP;
 }
 
@@ -281,17 +286,23 @@ int ma_cnn_warm_start(ma_cnn* N, int npairs, int n, const double* const* f, cons
     ma_options o;
     ma_options_default(&o);
     o.symbol = MA_SYMBOL_FD4;
-    TRY(ma_plan_create(n, 1, &o, &N->head));
+    o.gmres_m = 1;  // the head applies Lbar^{-1} only: one basis vector of workspace
+    TRY(ma_plan_create(n, N->max_batch, &o, &N->head));
     N->head_n = n;
   }
   const int B = N->max_batch;
-  const size_t pr = (size_t)nr * nr;
+  const size_t pr = (size_t)nr * nr, pn = (size_t)n * n;
   TRY(N->fx.ensure((size_t)B * pr * 8));
   TRY(N->gx.ensure((size_t)B * pr * 8));
   TRY(N->cbuf.ensure((size_t)B * pr * 2 * 8));  // network input (8 BF16 channels = 16 bytes per pixel)
-  TRY(N->cup.ensure((size_t)n * n * 4));
-  TRY(N->theta.ensure((size_t)n * n * 4));
+  TRY(N->cup.ensure(pn * 4));
+  TRY(N->clin.ensure((size_t)B * pn * 4));
+  TRY(N->theta.ensure((size_t)B * pn * 4));
+  TRY(N->means.ensure((size_t)2 * B * 8));
+  TRY(N->mpart.ensure((size_t)2 * B * CNN_MEAN_PARTS * 8));
   const double lap[5] = {1.0, 0.0, 1.0, 0.0, 0.0};  // averaged operator = the Laplacian
+  std::vector<const float*> sig(B);
+  std::vector<float*> th(B);
   for (int q0 = 0; q0 < npairs; q0 += B) {
     const int b = (npairs - q0 < B) ? npairs - q0 : B;
     for (int k = 0; k < b; ++k) {
@@ -314,9 +325,14 @@ int ma_cnn_warm_start(ma_cnn* N, int npairs, int n, const double* const* f, cons
         cnn_prolong(ck, nr, (float*)N->cup.p, st);
         src = (const float*)N->cup.p;
       }
-      TRY(ma_step_lbar_inverse(N->head, n, src, lap, (float*)N->theta.p, stream));
-      cnn_to_double((const float*)N->theta.p, (size_t)n * n, psi0[q0 + k], st);
+      float* lk = (float*)N->clin.p + (size_t)k * pn;
+      cnn_add_log_ratio(src, f[q0 + k], g[q0 + k], n, (double*)N->mpart.p + (size_t)2 * k * CNN_MEAN_PARTS,
+                        (double*)N->means.p + 2 * k, lk, st);
+      sig[k] = lk;
+      th[k] = (float*)N->theta.p + (size_t)k * pn;
     }
+    TRY(plan_lbar_inverse_many(N->head, n, b, sig.data(), lap, th.data(), st));
+    for (int k = 0; k < b; ++k) cnn_to_double(th[k], pn, psi0[q0 + k], st);
   }
   return hipGetLastError() == hipSuccess ? MA_OK : MA_EHIP;
 }

@@ -217,19 +217,34 @@ __global__ void k_pack(const float* __restrict__ Wm, int Co, int Ci, int flip, i
 }
 
 // network input: channels (log(f/mean f), log(g/mean g), 0 x 6)
-__global__ void k_means(const double* __restrict__ f, const double* __restrict__ g, int n, double* __restrict__ means) {
-  const int s = blockIdx.x >> 1, which = blockIdx.x & 1;
-  const double* x = (which ? g : f) + (size_t)s * n * n;
+// means of f and g per sample: MEAN_BLOCKS partial sums per field (each a contiguous
+// chunk, coalesced), then a fixed-order fold, so the result does not depend on timing
+constexpr int MEAN_BLOCKS = CNN_MEAN_PARTS;
+__global__ void k_mean_partials(const double* __restrict__ f, const double* __restrict__ g, int n,
+                                double* __restrict__ part) {
+  const int field = blockIdx.y, s = field >> 1;
+  const double* x = ((field & 1) ? g : f) + (size_t)s * n * n;
+  const size_t total = (size_t)n * n, chunk = (total + MEAN_BLOCKS - 1) / MEAN_BLOCKS;
+  const size_t lo = blockIdx.x * chunk, hi = lo + chunk < total ? lo + chunk : total;
   __shared__ double red[256];
   double a = 0.0;
-  for (int i = threadIdx.x; i < n * n; i += 256) a += x[i];
+  for (size_t i = lo + threadIdx.x; i < hi; i += 256) a += x[i];
   red[threadIdx.x] = a;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) means[blockIdx.x] = red[0] / ((double)n * n);
+  if (threadIdx.x == 0) part[(size_t)field * MEAN_BLOCKS + blockIdx.x] = red[0];
+}
+
+__global__ void k_mean_fold(const double* __restrict__ part, int nfields, double inv_count,
+                            double* __restrict__ means) {
+  const int field = blockIdx.x * blockDim.x + threadIdx.x;
+  if (field >= nfields) return;
+  double a = 0.0;
+  for (int b = 0; b < MEAN_BLOCKS; ++b) a += part[(size_t)field * MEAN_BLOCKS + b];
+  means[field] = a * inv_count;
 }
 
 __global__ void k_input(const double* __restrict__ f, const double* __restrict__ g, const double* __restrict__ means,
@@ -286,16 +301,30 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
   p[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
 }
 
-// fourth-order difference Laplacian of FP64 fields (the training target)
-__global__ void k_laplacian(const double* __restrict__ u, int batch, int n, float* __restrict__ out) {
+// training target: the fourth-order difference Laplacian of FP64 fields u, minus
+// log(f / mean f) - log(g / mean g) when f and g are given (the network then learns
+// the correction to the linearised equation)
+__global__ void k_target(const double* __restrict__ u, const double* __restrict__ f, const double* __restrict__ g,
+                         const double* __restrict__ means, int batch, int n, float* __restrict__ out) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (size_t)batch * n * n) return;
-  const size_t base = (i / ((size_t)n * n)) * n * n;
+  const size_t s = i / ((size_t)n * n), base = s * n * n;
   const int r = (int)((i / n) % n), c = (int)(i % n);
   auto U = [&](int a, int b) { return u[base + (size_t)wrap(r + a, n) * n + wrap(c + b, n)]; };
-  const double s = -U(-2, 0) + 16.0 * U(-1, 0) - 60.0 * U(0, 0) + 16.0 * U(1, 0) - U(2, 0) - U(0, -2) +
-                   16.0 * U(0, -1) + 16.0 * U(0, 1) - U(0, 2);
-  out[i] = (float)(s * (double)n * n / 12.0);
+  const double lap = -U(-2, 0) + 16.0 * U(-1, 0) - 60.0 * U(0, 0) + 16.0 * U(1, 0) - U(2, 0) - U(0, -2) +
+                     16.0 * U(0, -1) + 16.0 * U(0, 1) - U(0, 2);
+  double t = lap * (double)n * n / 12.0;
+  if (f) t -= log(f[i] / means[2 * s]) - log(g[i] / means[2 * s + 1]);
+  out[i] = (float)t;
+}
+
+// c + log(f / mean f) - log(g / mean g) for one pair (the linearised part of the warm start)
+__global__ void k_add_log_ratio(const float* __restrict__ c, const double* __restrict__ f,
+                                const double* __restrict__ g, const double* __restrict__ means, int n,
+                                float* __restrict__ out) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)n * n) return;
+  out[i] = (float)((double)c[i] + log(f[i] / means[0]) - log(g[i] / means[1]));
 }
 
 // full-weighting restriction 2n -> n (node-centred: fine node 2a maps to coarse node a)
@@ -376,8 +405,15 @@ void cnn_pack(const float* Wm, int Co, int Ci, int flip, int cin_store, int cout
                      (bf16*)out);
 }
 
-void cnn_input(const double* f, const double* g, int batch, int n, double* means, void* x, hipStream_t st) {
-  hipLaunchKernelGGL(k_means, dim3(2 * batch), dim3(256), 0, st, f, g, n, means);
+void cnn_means(const double* f, const double* g, int batch, int n, double* part, double* means, hipStream_t st) {
+  hipLaunchKernelGGL(k_mean_partials, dim3(MEAN_BLOCKS, 2 * batch), dim3(256), 0, st, f, g, n, part);
+  hipLaunchKernelGGL(k_mean_fold, dim3(nblocks(2 * batch, 64)), dim3(64), 0, st, part, 2 * batch,
+                     1.0 / ((double)n * n), means);
+}
+
+void cnn_input(const double* f, const double* g, int batch, int n, double* part, double* means, void* x,
+               hipStream_t st) {
+  cnn_means(f, g, batch, n, part, means, st);
   hipLaunchKernelGGL(k_input, dim3(nblocks((size_t)batch * n * n, 256)), dim3(256), 0, st, f, g, means, batch, n,
                      (bf16x8*)x);
 }
@@ -392,8 +428,17 @@ void cnn_adam(float* p, const float* g, float* m, float* v, int count, float lr,
   hipLaunchKernelGGL(k_adam, dim3(nblocks(count, 256)), dim3(256), 0, st, p, g, m, v, count, lr, b1, b2, c1, c2, eps);
 }
 
-void cnn_laplacian(const double* u, int batch, int n, float* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_laplacian, dim3(nblocks((size_t)batch * n * n, 256)), dim3(256), 0, st, u, batch, n, out);
+void cnn_target(const double* u, const double* f, const double* g, int batch, int n, double* part, double* means,
+                float* out, hipStream_t st) {
+  if (f) cnn_means(f, g, batch, n, part, means, st);
+  hipLaunchKernelGGL(k_target, dim3(nblocks((size_t)batch * n * n, 256)), dim3(256), 0, st, u, f, g, means, batch, n,
+                     out);
+}
+
+void cnn_add_log_ratio(const float* c, const double* f, const double* g, int n, double* part, double* means,
+                       float* out, hipStream_t st) {
+  cnn_means(f, g, 1, n, part, means, st);
+  hipLaunchKernelGGL(k_add_log_ratio, dim3(nblocks((size_t)n * n, 256)), dim3(256), 0, st, c, f, g, means, n, out);
 }
 
 void cnn_restrict(const double* x, int n_coarse, double* y, hipStream_t st) {

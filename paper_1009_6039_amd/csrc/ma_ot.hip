@@ -14,6 +14,7 @@
 #include "common.h"
 #include "kernels.h"
 #include "ma_ot.h"
+#include "plan_internal.h"
 
 namespace {
 
@@ -405,6 +406,29 @@ PairState step_state(const double* abar) {
 }
 
 }  // namespace
+
+int plan_lbar_inverse_many(ma_plan* P, int n, int count, const float* const* sigma, const double* abar,
+                           float* const* theta, hipStream_t st) {
+  if (!P || count < 1 || !sigma || !abar || !theta || !n_ok(n)) return MA_EINVAL;
+  std::vector<int> ns(count, n);
+  int e = ensure_workspace(P, ns);
+  if (e) return e;
+  std::vector<Class> cls;
+  e = build_classes(P, ns, cls, st);
+  if (e) return e;
+  for (int q = 0; q < count; ++q) {  // the step modes read only V[0] and write only x
+    P->h_desc[q].V = const_cast<float*>(sigma[q]);
+    P->h_desc[q].x = theta[q];
+  }
+  HIP_TRY(hipMemcpyAsync(P->d_desc, P->h_desc.data(), sizeof(PairDesc) * count, hipMemcpyHostToDevice, st));
+  P->h_state.assign(count, step_state(abar));
+  HIP_TRY(hipMemcpyAsync(P->d_state, P->h_state.data(), sizeof(PairState) * count, hipMemcpyHostToDevice, st));
+  LaunchCtx x = make_ctx(P, cls[0]);
+  launch_passA(x, n, count, PA_STEP, 0, cls[0].tw, st);
+  launch_passB(x, n, count, PB_RECOVER, 0, cls[0].tw, st);
+  launch_passC(x, n, count, PC_THETA_ONLY, 0, cls[0].tw, st);
+  return hipGetLastError() == hipSuccess ? MA_OK : MA_EHIP;
+}
 
 extern "C" {
 

@@ -29,7 +29,7 @@ EXPORTED = ("ma_abi_version", "ma_options_default", "ma_strerror", "ma_plan_crea
             "ma_step_residual", "ma_step_fft2", "ma_step_strain_apply",
             "ma_step_lbar_inverse", "ma_step_gmres",
             "ma_cnn_create", "ma_cnn_destroy", "ma_cnn_param_count", "ma_cnn_set_params",
-            "ma_cnn_get_params", "ma_cnn_prepare_input", "ma_cnn_laplacian", "ma_cnn_forward",
+            "ma_cnn_get_params", "ma_cnn_prepare_input", "ma_cnn_target", "ma_cnn_forward",
             "ma_cnn_gradients", "ma_cnn_train_step", "ma_cnn_warm_start")
 
 
@@ -94,7 +94,7 @@ def load():
     lib.ma_cnn_set_params.argtypes = [P, ctypes.POINTER(F), L]
     lib.ma_cnn_get_params.argtypes = [P, ctypes.POINTER(F), L]
     lib.ma_cnn_prepare_input.argtypes = [P, P, P, I, P, P]
-    lib.ma_cnn_laplacian.argtypes = [P, P, I, I, P, P]
+    lib.ma_cnn_target.argtypes = [P, P, P, P, I, I, P, P]
     lib.ma_cnn_forward.argtypes = [P, P, I, P, P]
     lib.ma_cnn_gradients.argtypes = [P, P, P, I, P, ctypes.POINTER(F), P]
     lib.ma_cnn_train_step.argtypes = [P, P, P, I, F, ctypes.POINTER(F), P]
@@ -329,11 +329,17 @@ class WarmStartNet:
                "ma_cnn_prepare_input")
         return x
 
-    def laplacian(self, psi):
+    def target(self, psi, f=None, g=None):
+        """Training target [batch, n, n] FP32: Laplacian of psi minus the log-density ratio
+        (the plain Laplacian when f and g are None)."""
         psi = _dev(psi, torch.float64)
+        if f is not None:
+            f = _dev(f, torch.float64)
+            g = _dev(g, torch.float64)
         out = torch.empty(psi.shape, dtype=torch.float32, device=psi.device)
-        _check(load().ma_cnn_laplacian(self._h, _ptr(psi), psi.shape[0], psi.shape[-1], _ptr(out), _stream()),
-               "ma_cnn_laplacian")
+        _check(load().ma_cnn_target(self._h, _ptr(psi), _ptr(f) if f is not None else None,
+                                    _ptr(g) if g is not None else None, psi.shape[0], psi.shape[-1], _ptr(out),
+                                    _stream()), "ma_cnn_target")
         return out
 
     def forward(self, x):

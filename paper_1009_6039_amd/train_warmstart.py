@@ -7,7 +7,8 @@ memory and gathers minibatches):
   2. solved on the GPU to rms residual 1e-8 (step-halving damping, fourth-order
      symbol: the same fixed point, fewer iterations);
   3. network input (log f, log g of the mean-one densities) in BF16 and target = the fourth-order
-     difference Laplacian of the solution, both kept on the device;
+     difference Laplacian of the solution minus log f + log g (what the linearised
+     equation misses), both kept on the device;
   4. Adam on the MSE loss (cosine learning-rate decay), seeded shuffles, a held-out
      split for the validation loss;
   5. an evaluation: Newton iterations from zero and from the learned start on
@@ -57,30 +58,32 @@ def generate(maot, net, npairs, n, chunk=128, workers=16, tol=1e-8, log=print):
                      max_newton=300, symbol="fd4")
     t0 = time.time()
     newton = []
-    bad = 0
+    ok = np.zeros(npairs, dtype=bool)
     jobs = [(q0, min(chunk, npairs - q0), n) for q0 in range(0, npairs, chunk)]
     with mp.get_context("spawn").Pool(workers) as pool:
         for (q0, b, _), arr in zip(jobs, pool.imap(_gen_chunk, jobs)):
             fg = torch.from_numpy(arr).cuda()
             f, g = fg[:, 0].contiguous(), fg[:, 1].contiguous()
             psis, _, reps = plan.solve_batched(list(f.unbind(0)), list(g.unbind(0)), damping=1.0, tol=tol)
-            bad += sum(r["status"] != 0 for r in reps)
+            ok[q0:q0 + b] = [r["status"] == 0 for r in reps]
             newton += [r["newton_iters"] for r in reps]
             X[q0:q0 + b] = net.prepare_input(f, g)
-            T[q0:q0 + b] = net.laplacian(torch.stack(psis))
+            T[q0:q0 + b] = net.target(torch.stack(psis), f, g)
             if (q0 // chunk) % 20 == 0:
                 log("generate: %d/%d pairs, %.1f s" % (q0 + b, npairs, time.time() - t0))
     plan.close()
     torch.cuda.synchronize()
-    return X, T, {"pairs": npairs, "unsolved": int(bad), "newton_mean": float(np.mean(newton)),
-                  "seconds": time.time() - t0}
+    return X, T, ok, {"pairs": npairs, "unsolved": int(np.sum(~ok)), "newton_mean": float(np.mean(newton)),
+                      "seconds": time.time() - t0}
 
 
-def train(net, X, T, epochs, batch, lr0, val_frac=0.05, seed=0, log=print):
+def train(net, X, T, ok, epochs, batch, lr0, val_frac=0.05, seed=0, log=print):
+    """Pairs the solver did not solve (ok False) are left out."""
     import torch
-    npairs = X.shape[0]
     g = torch.Generator().manual_seed(seed)
-    perm = torch.randperm(npairs, generator=g)
+    valid = torch.from_numpy(np.flatnonzero(ok))
+    npairs = len(valid)
+    perm = valid[torch.randperm(npairs, generator=g)]
     n_val = max(batch, int(npairs * val_frac)) // batch * batch
     val_idx, tr_idx = perm[:n_val].cuda(), perm[n_val:]
     steps_per_epoch = len(tr_idx) // batch
@@ -88,6 +91,12 @@ def train(net, X, T, epochs, batch, lr0, val_frac=0.05, seed=0, log=print):
     step = 0
     hist = []
     t0 = time.time()
+
+    def val_loss():
+        return float(np.mean([net.gradients(X[val_idx[s:s + batch]], T[val_idx[s:s + batch]])[1]
+                              for s in range(0, n_val, batch)]))
+
+    log("epoch 0: val %.4e" % val_loss())
     for ep in range(epochs):
         order = tr_idx[torch.randperm(len(tr_idx), generator=g)].cuda()
         for s in range(steps_per_epoch):
@@ -95,37 +104,41 @@ def train(net, X, T, epochs, batch, lr0, val_frac=0.05, seed=0, log=print):
             lr = 1e-5 + 0.5 * (lr0 - 1e-5) * (1 + math.cos(math.pi * step / total))
             net.train_step(X[idx], T[idx], lr)
             step += 1
-        vl = []
-        for s in range(0, n_val, batch):
-            idx = val_idx[s:s + batch]
-            vl.append(net.gradients(X[idx], T[idx])[1])
         tl = net.gradients(X[order[:batch]], T[order[:batch]])[1]
-        hist.append({"epoch": ep + 1, "train_loss": tl, "val_loss": float(np.mean(vl)),
-                     "seconds": time.time() - t0})
+        hist.append({"epoch": ep + 1, "train_loss": tl, "val_loss": val_loss(), "seconds": time.time() - t0})
         log("epoch %d: train %.4e  val %.4e  (%.1f s)" % (ep + 1, tl, hist[-1]["val_loss"], time.time() - t0))
     return hist
 
 
 def evaluate(maot, net, n, count=64, log=print):
-    """Newton iterations and wall time from zero and from the learned start (held-out pairs)."""
+    """Newton iterations and wall time on held-out pairs from zero, from the linearised
+    start (the network's output set to zero) and from the learned start, for both
+    symbols of the linear solve."""
     import torch
     pairs = [W.blobs(n, W.seed_for(TRAIN_CONFIG + 1, q)) for q in range(count)]
     f = [torch.from_numpy(a).cuda() for a, _ in pairs]
     g = [torch.from_numpy(b).cuda() for _, b in pairs]
-    plan = maot.Plan(n_max=n, batch_capacity=count, damping_policy="backtrack", gmres_tol=0.1, max_newton=300)
+    lin = maot.WarmStartNet(layers=net.layers, channels=net.channels, n_net=net.n_net, max_batch=net.max_batch)
+    lin.set_params(np.zeros(lin.count, dtype=np.float32))
     out = {}
-    for arm in ("zero", "learned"):
-        torch.cuda.synchronize()
-        t0 = time.time()
-        psi0 = net.warm_start(f, g) if arm == "learned" else None
-        _, _, reps = plan.solve_batched(f, g, damping=1.0, tol=1e-6, psi0s=psi0)
-        torch.cuda.synchronize()
-        out[arm] = {"seconds": time.time() - t0, "newton_mean": float(np.mean([r["newton_iters"] for r in reps])),
-                    "gmres_mean": float(np.mean([r["gmres_iters"] for r in reps])),
-                    "res0_mean": float(np.mean([r["res0_rms"] for r in reps])),
-                    "unsolved": int(sum(r["status"] != 0 for r in reps))}
-        log("eval %s: %s" % (arm, json.dumps(out[arm])))
-    plan.close()
+    for symbol in ("spectral", "fd4"):
+        plan = maot.Plan(n_max=n, batch_capacity=count, damping_policy="backtrack", gmres_tol=0.1, max_newton=300,
+                         symbol=symbol)
+        for arm, start in (("zero", None), ("linearised", lin), ("learned", net)):
+            torch.cuda.synchronize()
+            t0 = time.time()
+            psi0 = start.warm_start(f, g) if start is not None else None
+            _, _, reps = plan.solve_batched(f, g, damping=1.0, tol=1e-6, psi0s=psi0)
+            torch.cuda.synchronize()
+            key = "%s/%s" % (symbol, arm)
+            out[key] = {"seconds": time.time() - t0,
+                        "newton_mean": float(np.mean([r["newton_iters"] for r in reps])),
+                        "gmres_mean": float(np.mean([r["gmres_iters"] for r in reps])),
+                        "warm_accepted": int(sum(r["warm_steps"] for r in reps)),
+                        "unsolved": int(sum(r["status"] != 0 for r in reps))}
+            log("eval n=%d %s: %s" % (n, key, json.dumps(out[key])))
+        plan.close()
+    lin.close()
     return out
 
 
@@ -133,7 +146,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--pairs", type=int, default=20000)
     ap.add_argument("--n", type=int, default=256)
-    ap.add_argument("--epochs", type=int, default=12)
+    ap.add_argument("--epochs", type=int, default=16)
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--layers", type=int, default=8)
@@ -142,13 +155,17 @@ def main():
     ap.add_argument("--workers", type=int, default=16)
     ap.add_argument("--out", required=True)
     args = ap.parse_args()
+    import torch
     from . import maot
     log = lambda s: print(s, flush=True)  # noqa: E731
     net = maot.WarmStartNet(layers=args.layers, channels=args.channels, n_net=args.n, max_batch=args.batch)
     net.set_params(init_params(args.layers, args.channels, args.seed))
-    X, T, gen = generate(maot, net, args.pairs, args.n, workers=args.workers, log=log)
+    X, T, ok, gen = generate(maot, net, args.pairs, args.n, workers=args.workers, log=log)
     log("dataset: %s" % json.dumps(gen))
-    hist = train(net, X, T, args.epochs, args.batch, args.lr, seed=args.seed, log=log)
+    tq = T[torch.from_numpy(ok).cuda()]
+    log("target: mean square %.4e, max |t| %.4e" % (float((tq * tq).mean()), float(tq.abs().max())))
+    del tq
+    hist = train(net, X, T, ok, args.epochs, args.batch, args.lr, seed=args.seed, log=log)
     del X, T
     ev = evaluate(maot, net, args.n, log=log)
     ev512 = evaluate(maot, net, 2 * args.n, log=log)

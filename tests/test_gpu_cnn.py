@@ -121,15 +121,19 @@ def test_adam_steps_reduce_the_loss(maot):
         net.close()
 
 
-def test_laplacian_target_matches_oracle(maot):
+def test_training_target_matches_oracle(maot):
     net = maot.WarmStartNet(layers=2, channels=32, n_net=32, max_batch=1)
     try:
-        u = np.random.default_rng(4).standard_normal((2, 48, 48)) * 1e-3
-        out = net.laplacian(torch.from_numpy(u).cuda())
-        torch.cuda.synchronize()
-        out = out.cpu().numpy()
+        rng = np.random.default_rng(4)
+        u = rng.standard_normal((2, 48, 48)) * 1e-3
+        f = 0.2 + rng.random((2, 48, 48))
+        g = 0.5 + rng.random((2, 48, 48))
+        dev = lambda a: torch.from_numpy(a).cuda()  # noqa: E731
+        plain = net.target(dev(u)).cpu().numpy()
+        full = net.target(dev(u), dev(f), dev(g)).cpu().numpy()
         for k in range(2):
-            assert rel_l2(out[k], cnn.laplacian_fd4(u[k])) < 1e-6
+            assert rel_l2(plain[k], cnn.training_target(u[k])) < 1e-6
+            assert rel_l2(full[k], cnn.training_target(u[k], f[k], g[k])) < 1e-6
     finally:
         net.close()
 

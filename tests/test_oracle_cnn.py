@@ -193,3 +193,45 @@ def test_batched_gradient_normalisation():
     pp = [(Wp, b), params[1]]
     l_p = np.mean([cnn.mse(cnn.forward(x, pp)[0], t) for x, t in zip(xs, ts)])
     assert tot[0][0][1, 0, 1, 2] == pytest.approx((l_p - l_batch) / eps, rel=1e-4)
+
+
+def test_zero_network_gives_the_linearised_solution():
+    # For f = 1 + eps h, g = 1 the solution of the discrete equation satisfies
+    # Laplacian_h(psi) = log f + O(eps^2), so a network that outputs zero must give a
+    # start within O(eps^2) of the solver's answer; a wrong sign or a missing log ratio
+    # leaves an O(eps) error.
+    from oracle import ma
+    N = 32
+    x = np.arange(N) / N
+    X1, X2 = np.meshgrid(x, x, indexing="ij")
+    h = np.cos(2 * np.pi * X1) * np.sin(4 * np.pi * X2) + 0.5 * np.sin(2 * np.pi * (X1 + X2))
+    zero = [(np.zeros_like(W), np.zeros_like(b)) for W, b in cnn.init_params(channels=4, layers=2, seed=0)]
+    errs = []
+    for eps in (1e-2, 5e-3):
+        f, g = 1.0 + eps * h, np.ones((N, N))
+        psi, _, rep = ma.solve(f, g, tol=1e-13, max_newton=50)
+        assert rep.status == ma.OK
+        start = cnn.warm_start(f, g, zero, N, bf16=False)
+        errs.append(np.max(np.abs(start - psi)))
+        assert errs[-1] < 0.05 * np.max(np.abs(psi))
+    assert 3.5 < errs[0] / errs[1] < 4.5  # second order in eps
+
+
+def test_training_target_subtracts_the_log_ratio():
+    rng = np.random.default_rng(11)
+    psi = rng.standard_normal((16, 16)) * 1e-3
+    f = 1.0 + 0.3 * rng.random((16, 16))
+    g = 2.0 + rng.random((16, 16))
+    t = cnn.training_target(psi, f, g)
+    assert np.allclose(t, cnn.laplacian_fd4(psi) - np.log(f / f.mean()) + np.log(g / g.mean()), atol=1e-12)
+    assert np.array_equal(cnn.training_target(psi), cnn.laplacian_fd4(psi))
+
+
+def test_unflatten_inverts_the_flat_order():
+    params = cnn.init_params(channels=4, layers=3, seed=2)
+    flat = np.concatenate([np.concatenate([W.ravel(), b + 0.5]) for W, b in params])
+    back = cnn.unflatten_params(flat, 3, 4)
+    for (W, b), (W2, b2) in zip(params, back):
+        assert np.array_equal(W, W2) and np.array_equal(b + 0.5, b2)
+    with pytest.raises(ValueError):
+        cnn.unflatten_params(flat[:-1], 3, 4)
