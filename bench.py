@@ -25,6 +25,7 @@ import time
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
+TRAFFIC_FILE = "row_c_%d_batch64_hbm_traffic.md"  # written by paper_1009_6039_amd.rocprof_summary traffic
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 METRIC = "Newton-solved pairs/sec at 512^2 to residual 1e-6; learned-init vs plain"
 
@@ -113,6 +114,7 @@ def main():
         sys.exit(2)
     import torch
     from paper_1009_6039_amd import maot
+    from paper_1009_6039_amd.rocprof_summary import read_traffic_record
     from paper_1009_6039_amd import workloads as W
 
     N, B = args.n, args.batch
@@ -197,9 +199,15 @@ def main():
     for sym in symbols:
         if (sym, "zero") in arms and (sym, "learned") in arms:
             out["learned_vs_plain_" + sym] = round(arms[(sym, "zero")][0] / arms[(sym, "learned")][0], 4)
+    kname = {"row_c": "k_passC<%d>", "row_a": "k_passA<%d>", "column": "k_passB<%d>"}.get(args.profile_class, "")
+    kname = kname % N if kname else ""
+    rec = read_traffic_record(os.path.join(HERE, "profiles", TRAFFIC_FILE % N), kname) if kname else None
     out["roofline"] = {"bound": "hbm", "kernel": args.profile_class, "achieved": round(achieved, 1),
                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                       "traffic": None, "launches": prof["launches"],
+                       "traffic": round(rec["traffic_bytes_per_launch"]) if rec else None,
+                       "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-scaled; null when the "
+                                       "kernel sources differ from the profiled ones)",
+                       "launches": prof["launches"],
                        "avg_launch_us": round(1e3 * prof["ms"] / max(prof["launches"], 1), 3),
                        "bytes_per_launch": round(prof["bytes"] / max(prof["launches"], 1)),
                        "algorithmic_bytes_total": prof["bytes"]}
