@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--init", default="both", choices=("both", "zero", "learned"),
                     help="arms to time; value is the learned arm unless only zero is run")
     ap.add_argument("--weights", default=os.path.join(HERE, "paper_1009_6039_amd", "warmstart_256.npz"))
+    ap.add_argument("--tune-cache", default=os.path.join(HERE, "paper_1009_6039_amd", "tune_cache.json"),
+                    help="autotuner cache (JSON); 'none' skips the autotuner (default geometries)")
     ap.add_argument("--cpu-pairs", type=int, default=4, help="pairs in the oracle's timed sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -127,6 +129,12 @@ def main():
     plans = {sym: maot.Plan(n_max=N, batch_capacity=B, damping_policy=args.damping_policy,
                             gmres_tol=args.gmres_tol, max_newton=300, symbol=sym) for sym in symbols}
 
+    tuning = None
+    if args.tune_cache != "none":  # launch geometry chosen before the timed region
+        for sym in symbols:
+            tuning = plans[sym].autotune(N, B, args.tune_cache)
+        print("tuning %s" % json.dumps(tuning), file=sys.stderr, flush=True)
+
     net, params, meta = None, None, None
     if args.init != "zero":
         params, meta = load_weights(args.weights)
@@ -192,6 +200,11 @@ def main():
                    "gmres_tol": args.gmres_tol, "gmres_m": 10, "init": head[1], "symbol": head[0]},
     }
     out.update(summary(reps))
+    if tuning is not None:
+        out["tuning"] = {"n": N, "variant_row_a_column_row_c_residual": tuning["variant"],
+                         "from_cache": tuning["from_cache"],
+                         "us_per_launch": [round(x, 2) for x in tuning["us"]],
+                         "us_per_launch_default": [round(x, 2) for x in tuning["us_default"]]}
     out["arms"] = {}
     for (sym, init), (el, _, rp, _) in arms.items():
         out["arms"]["%s/%s" % (sym, init)] = dict(value=round(pairs / el, 3),
@@ -199,9 +212,14 @@ def main():
     for sym in symbols:
         if (sym, "zero") in arms and (sym, "learned") in arms:
             out["learned_vs_plain_" + sym] = round(arms[(sym, "zero")][0] / arms[(sym, "learned")][0], 4)
-    kname = {"row_c": "k_passC<%d>", "row_a": "k_passA<%d>", "column": "k_passB<%d>"}.get(args.profile_class, "")
-    kname = kname % N if kname else ""
+    cls = {"row_a": 0, "column": 1, "row_c": 2, "residual": 3}[args.profile_class]
+    var = plans[head[0]].get_tuning(N)[cls]
+    kname = {"row_c": "k_passC<%d, %d>", "row_a": "k_passA<%d, %d>", "column": "k_passB<%d, %d>"}.get(
+        args.profile_class, "")
+    kname = kname % (N, var) if kname else ""  # the kernel as rocprofv3 names it
     rec = read_traffic_record(os.path.join(HERE, "profiles", TRAFFIC_FILE % N), kname) if kname else None
+    if rec and rec.get("variant") != var:
+        rec = None  # counters taken with another launch geometry
     out["roofline"] = {"bound": "hbm", "kernel": args.profile_class, "achieved": round(achieved, 1),
                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                        "traffic": round(rec["traffic_bytes_per_launch"]) if rec else None,

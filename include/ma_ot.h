@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define MA_OT_ABI_VERSION 2
+#define MA_OT_ABI_VERSION 3
 
 /* return / status codes */
 #define MA_OK 0           /* converged: rms residual <= tol                           */
@@ -204,6 +204,47 @@ int ma_step_lbar_inverse(ma_plan* plan, int n, const float* sigma, const double*
 int ma_step_gmres(ma_plan* plan, int n, const float* h, const float* coef,
                   const double* abar, int m, double tol, int max_restarts, float* theta,
                   int* iters, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Autotuner (not in the paper): launch geometry per grid size.  Each of the four
+ * bandwidth-bound kernel classes (row pass A, column pass B, row pass C, residual
+ * stencil) has MA_TUNE_VARIANTS compiled geometries: 0 the default, 1 half as many
+ * rows / columns per workgroup (residual: half the tile width), 2 twice as many
+ * (residual: a quarter of the tile width), 3 the default tile with half the threads.
+ * A variant that coincides with a smaller index is skipped.
+ * ------------------------------------------------------------------------- */
+#define MA_TUNE_VARIANTS 4
+
+typedef struct ma_tuning {
+  int n;               /* grid side */
+  int npairs;          /* pairs per launch used for the timing */
+  int variant[4];      /* pass A, pass B, pass C, residual; 0 = default geometry */
+  int from_cache;      /* 1: read from the cache file, nothing timed */
+  int rejected;        /* variants whose output differed from the default's */
+  double us[4];        /* per-launch time of the chosen variants, microseconds (0 from the cache) */
+  double us_default[4];/* per-launch time of the default geometry */
+} ma_tuning;
+
+/* Times every distinct variant of each kernel class on `npairs` synthetic pairs of
+ * side n (smooth densities, coefficients near the Laplacian's, pseudo-random Krylov
+ * vectors), rejects a variant whose output differs from the default geometry's by
+ * more than FP32 reordering (fields 1e-6, folded partial sums 1e-5 of their
+ * magnitude), and makes the fastest the plan's choice for n.  If cache_path is not
+ * NULL and holds an entry for this device, library build, n, npairs and the plan's
+ * gmres_m, that entry is used instead; otherwise the result is added to the file
+ * (a small JSON document, one entry per line).  Uses the plan's workspace (any
+ * earlier solve's buffers are overwritten) and synchronises the stream. */
+int ma_plan_autotune(ma_plan* plan, int n, int npairs, const char* cache_path, ma_tuning* out,
+                     void* stream);
+/* Sets the plan's variants for t->n (t->variant[0..3]); MA_EINVAL if out of range. */
+int ma_plan_set_tuning(ma_plan* plan, const ma_tuning* t);
+/* The plan's variants for n (zeros if never tuned). */
+int ma_plan_get_tuning(const ma_plan* plan, int n, ma_tuning* out);
+/* Geometry of a variant: pass 0..3 (A, B, C, residual); per_block = row pairs (A, C),
+ * columns (B) or tile width (residual); threads per workgroup.  Returns the canonical
+ * variant index (smaller if a duplicate), or -1 for an unsupported n or variant.
+ * Host-only, no GPU needed. */
+int ma_tune_geometry(int pass, int n, int variant, int* per_block, int* threads);
 
 /* ---------------------------------------------------------------------------
  * Learned warm start (not in the paper): a periodic-padded 3x3 convolutional

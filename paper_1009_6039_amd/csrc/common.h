@@ -32,7 +32,6 @@ struct __align__(16) GS {
 struct PairDesc {
   int n;
   int cls;  // index of the size class this pair belongs to
-  int nblk_res, nblk_rows;
   // caller buffers
   const double* f_in;
   const double* g_in;
@@ -91,6 +90,7 @@ struct LaunchCtx {
   double gmres_tol;
   const float2* mt;  // per-wavenumber multipliers (Im d/dx, d^2/dx^2) of the selected symbol
   unsigned long long* prof_bytes;  // algorithmic-byte counter of the timed class, or null
+  int var[4];  // launch-geometry variants (pass A, pass B, pass C, residual), 0 = default
 };
 
 // adds one pair's algorithmic bytes for this launch (timed class only)

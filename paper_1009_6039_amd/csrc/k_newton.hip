@@ -403,9 +403,50 @@ __global__ __launch_bounds__(256) void k_summary(const PairState* st, const int*
   if (threadIdx.x < 8) out[threadIdx.x] = cnt[threadIdx.x];
 }
 
+// Synthetic fields for timing launch geometries: smooth positive densities, a small
+// potential, coefficients near those of the Laplacian and pseudo-random Krylov
+// vectors (a 32-bit integer hash of the pair, vector and point index).
+__global__ __launch_bounds__(MA_BLOCK) void k_tune_fill(LaunchCtx c) {
+  const int p = pair_of_block(c);
+  const PairDesc& d = c.desc[p];
+  const int n = d.n;
+  const long nn = (long)n * n;
+  const double tp = 6.283185307179586;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (long)gridDim.x * blockDim.x) {
+    const double x1 = (double)(e / n) / n, x2 = (double)(e % n) / n;
+    d.u[e] = 0.002 * sin(tp * x1) * sin(tp * x2);
+    d.f[e] = 1.0 + 0.3 * cos(tp * (x1 + 2.0 * x2));
+    const double ph = tp * (2.0 * x1 - x2);
+    GS gs;
+    gs.g = 1.0 + 0.2 * sin(ph);
+    gs.g1 = (float)(0.4 * tp * cos(ph));
+    gs.g2 = (float)(-0.2 * tp * cos(ph));
+    d.gs[e] = gs;
+    d.coef[e] = (float)(1.0 + 0.2 * sin(tp * x1));
+    d.coef[nn + e] = (float)(0.1 * cos(tp * x2));
+    d.coef[2 * nn + e] = (float)(1.0 + 0.2 * cos(tp * (x1 + x2)));
+    d.coef[3 * nn + e] = (float)(0.05 * sin(tp * x2));
+    d.coef[4 * nn + e] = (float)(0.05 * cos(tp * x1));
+    d.r[e] = 0.f;
+    d.x[e] = 0.f;
+    for (int l = 0; l <= c.m; ++l) {
+      unsigned h = (unsigned)e * 2654435761u ^ (unsigned)(l * 40503 + p * 977 + 17);
+      h ^= h >> 15;
+      h *= 2246822519u;
+      h ^= h >> 13;
+      d.V[(long)l * nn + e] = (float)((double)(h & 0xFFFFFF) / 8388608.0 - 1.0);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
+void launch_tune_fill(const LaunchCtx& c, int n, int npairs, hipStream_t st) {
+  long b = (long)n * n / (MA_BLOCK * 4);
+  const int nb = b < 1 ? 1 : (int)(b > 4096 ? 4096 : b);
+  hipLaunchKernelGGL(k_tune_fill, dim3(nb, npairs), dim3(MA_BLOCK), 0, st, c);
+}
 void launch_setup_fields(const LaunchCtx& c, int n, int npairs, hipStream_t st) {
   int nb2 = (int)((long)n * n / (MA_BLOCK * 4));
   nb2 = nb2 < 1 ? 1 : (nb2 > 4096 ? 4096 : nb2);
@@ -420,17 +461,36 @@ void launch_setup(const LaunchCtx& c, int n, int npairs, hipStream_t st) {
   launch_setup_fields(c, n, npairs, st);
 }
 
-int residual_tile_x(int n) { return (n % 64 == 0) ? 64 : ((n % 32 == 0) ? 32 : 16); }
+// tile width of the residual stencil: variant 0 the widest that divides n (64, 32 or
+// 16 columns), 1 half of it, 2 a quarter (never below 16), 3 the same as 0
+int residual_tile_x(int n, int v) {
+  const int t0 = (n % 64 == 0) ? 64 : ((n % 32 == 0) ? 32 : 16);
+  const int t = v == 1 ? t0 / 2 : (v == 2 ? t0 / 4 : t0);
+  return t < 16 ? 16 : t;
+}
 
-int residual_blocks(int n) { return (n / residual_tile_x(n)) * (n / MA_RES_TY); }
+int residual_geometry(int n, int v, int* tile_x, int* threads) {
+  if (v < 0 || v > 3 || n % 16) return -1;
+  *tile_x = residual_tile_x(n, v);
+  *threads = MA_BLOCK;
+  for (int u = 0; u < v; ++u)
+    if (residual_tile_x(n, u) == *tile_x) return u;
+  return v;
+}
 
-void launch_residual(const LaunchCtx& c, int n, int npairs, int step_mode, hipStream_t st, const TimedLaunch& ev) {
-  const int tx = residual_tile_x(n);
-  dim3 grid(residual_blocks(n), npairs);
+int residual_blocks(int n, int v) { return (n / residual_tile_x(n, v)) * (n / MA_RES_TY); }
+
+void launch_residual_only(const LaunchCtx& c, int n, int npairs, hipStream_t st, const TimedLaunch& ev) {
+  const int tx = residual_tile_x(n, c.var[3]);
+  dim3 grid(residual_blocks(n, c.var[3]), npairs);
   if (tx == 64) MA_LAUNCH(ev, k_residual<64>, grid, dim3(MA_BLOCK), st, c);
   else if (tx == 32) MA_LAUNCH(ev, k_residual<32>, grid, dim3(MA_BLOCK), st, c);
   else MA_LAUNCH(ev, k_residual<16>, grid, dim3(MA_BLOCK), st, c);
-  hipLaunchKernelGGL(k_residual_finalize, dim3(1, npairs), dim3(MA_BLOCK), 0, st, c, residual_blocks(n),
+}
+
+void launch_residual(const LaunchCtx& c, int n, int npairs, int step_mode, hipStream_t st, const TimedLaunch& ev) {
+  launch_residual_only(c, n, npairs, st, ev);
+  hipLaunchKernelGGL(k_residual_finalize, dim3(1, npairs), dim3(MA_BLOCK), 0, st, c, residual_blocks(n, c.var[3]),
                      step_mode);
 }
 

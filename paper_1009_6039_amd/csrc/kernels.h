@@ -30,19 +30,30 @@ enum : int { PC_MATVEC = 0, PC_RECOVER = 1, PC_THETA_ONLY = 2 };
 
 void launch_setup(const LaunchCtx& c, int n, int npairs, hipStream_t st);
 void launch_setup_fields(const LaunchCtx& c, int n, int npairs, hipStream_t st);
-int residual_tile_x(int n);
-int residual_blocks(int n);
+int residual_tile_x(int n, int v);
+int residual_blocks(int n, int v);
 void launch_residual(const LaunchCtx& c, int n, int npairs, int step_mode, hipStream_t st,
                      const TimedLaunch& ev = TimedLaunch());
+void launch_residual_only(const LaunchCtx& c, int n, int npairs, hipStream_t st,
+                          const TimedLaunch& ev = TimedLaunch());
 void launch_residual_shift(const LaunchCtx& c, int n, float* out, hipStream_t st);
 void launch_step_update(const LaunchCtx& c, int n, int npairs, hipStream_t st);
 void launch_outputs(const LaunchCtx& c, int n, int npairs, hipStream_t st);
 void launch_summary(const PairState* s, const int* ids, int npairs, int* out, hipStream_t st);
+void launch_tune_fill(const LaunchCtx& c, int n, int npairs, hipStream_t st);
 
 // FFT passes and GMRES kernels; `tw` is the length-n twiddle table
 bool fft_size_supported(int n);
-int passA_blocks(int n);
-int passC_blocks(int n);
+// launch-geometry variants 0..MA_NVARIANTS-1 of each pass (0 = default); the geometry
+// functions return the variant's canonical index (a duplicate returns 0) or -1
+constexpr int MA_NVARIANTS = 4;
+int passA_geometry(int n, int v, int* row_pairs, int* threads);
+int passB_geometry(int n, int v, int* columns, int* threads);
+int passC_geometry(int n, int v, int* row_pairs, int* threads);
+int residual_geometry(int n, int v, int* tile_x, int* threads);
+int passA_blocks(int n, int v);
+int passB_blocks(int n, int v);
+int passC_blocks(int n, int v);
 void launch_passA(const LaunchCtx& c, int n, int npairs, int mode, int jn, const float2* tw, hipStream_t st,
                   const TimedLaunch& ev = TimedLaunch());
 void launch_passA_only(const LaunchCtx& c, int n, int npairs, int mode, int jn, const float2* tw, hipStream_t st,

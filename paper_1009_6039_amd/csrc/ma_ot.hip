@@ -25,6 +25,10 @@ namespace {
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+struct Tune {
+  int v[4] = {0, 0, 0, 0};  // pass A, pass B, pass C, residual
+};
+
 struct Class {
   int n;
   std::vector<int> ids;
@@ -48,6 +52,7 @@ struct ma_plan {
   int* h_summary = nullptr;
   std::map<int, float2*> tw;
   std::map<std::pair<int, int>, float2*> mt;  // (n, symbol) -> derivative multipliers
+  std::map<int, Tune> tune;                   // n -> launch-geometry variants (absent: defaults)
   std::vector<PairDesc> h_desc;
   std::vector<PairState> h_state;
   // timing hook
@@ -61,12 +66,15 @@ struct ma_plan {
 
 namespace {
 
+// partial-sum slots per pair: the largest need over all launch-geometry variants
 size_t part_doubles(int n) {
-  size_t a = (size_t)residual_blocks(n) * MA_NPART_RES;
-  size_t b = (size_t)passC_blocks(n) * (MA_MMAX + 1);
-  size_t c = (size_t)passA_blocks(n) + 16;
-  size_t d = 256 * 4;
-  return std::max(std::max(a, b), std::max(c, d));
+  size_t need = 256 * 4;
+  for (int v = 0; v < MA_NVARIANTS; ++v) {
+    need = std::max(need, (size_t)residual_blocks(n, v) * MA_NPART_RES);
+    need = std::max(need, (size_t)passC_blocks(n, v) * (MA_MMAX + 1));
+    need = std::max(need, (size_t)passA_blocks(n, v) + 16);
+  }
+  return need;
 }
 
 size_t pair_bytes(int n, int m) {
@@ -103,8 +111,6 @@ void carve(PairDesc& d, char*& p, int n, int m) {
   d.H = (float2*)take(4 * nn);
   d.T = (float2*)take(12 * nn);
   d.part = (double*)take(8 * part_doubles(n));
-  d.nblk_res = residual_blocks(n);
-  d.nblk_rows = passA_blocks(n);
 }
 
 bool n_ok(int n) { return n >= 16 && n <= 2048 && n % 16 == 0 && fft_size_supported(n); }
@@ -221,6 +227,8 @@ LaunchCtx make_ctx(const ma_plan* P, const Class& cl, int kind = MA_PROF_NONE) {
   c.interp = P->opt.interp;
   c.op_mode = P->opt.op_mode;
   c.gmres_tol = P->opt.gmres_tol;
+  auto t = P->tune.find(cl.n);
+  for (int k = 0; k < 4; ++k) c.var[k] = t == P->tune.end() ? 0 : t->second.v[k];
   return c;
 }
 
@@ -508,6 +516,83 @@ void ma_plan_destroy(ma_plan* P) {
 int ma_plan_set_options(ma_plan* P, const ma_options* opt) {
   if (!P || !opt || validate_options(*opt)) return MA_EINVAL;
   P->opt = *opt;
+  return MA_OK;
+}
+
+int ma_plan_autotune(ma_plan* P, int n, int npairs, const char* cache_path, ma_tuning* out, void* stream) {
+  if (!P || !out || npairs < 1 || !n_ok(n)) return MA_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  ma_tuning t;
+  std::memset(&t, 0, sizeof(t));
+  t.n = n;
+  t.npairs = npairs;
+  if (tune_cache_lookup(cache_path, n, npairs, P->opt.gmres_m, &t)) {
+    int u = 0, th = 0;
+    bool ok = true;
+    for (int k = 0; k < 4; ++k) {
+      if (t.variant[k] < 0 || t.variant[k] >= MA_TUNE_VARIANTS) ok = false;
+      if (ok && ma_tune_geometry(k, n, t.variant[k], &u, &th) != t.variant[k]) ok = false;
+    }
+    if (ok) {
+      t.from_cache = 1;
+      Tune tu;
+      for (int k = 0; k < 4; ++k) tu.v[k] = t.variant[k];
+      P->tune[n] = tu;
+      *out = t;
+      return MA_OK;
+    }
+    std::memset(t.variant, 0, sizeof(t.variant));
+  }
+  std::vector<int> ns(npairs, n);
+  int e = ensure_workspace(P, ns);
+  if (e) return e;
+  std::vector<Class> cls;
+  e = build_classes(P, ns, cls, st);
+  if (e) return e;
+  HIP_TRY(hipMemcpyAsync(P->d_desc, P->h_desc.data(), sizeof(PairDesc) * npairs, hipMemcpyHostToDevice, st));
+  const double lap[5] = {1.0, 0.0, 1.0, 0.0, 0.0};
+  PairState s = step_state(lap);
+  for (int l = 0; l <= MA_MMAX; ++l) s.vscale[l] = 1.0;
+  P->h_state.assign(npairs, s);
+  HIP_TRY(hipMemcpyAsync(P->d_state, P->h_state.data(), sizeof(PairState) * npairs, hipMemcpyHostToDevice, st));
+  TunerView tv;
+  tv.ctx = make_ctx(P, cls[0]);
+  for (int k = 0; k < 4; ++k) tv.ctx.var[k] = 0;
+  tv.n = n;
+  tv.npairs = npairs;
+  tv.tw = cls[0].tw;
+  tv.desc0 = P->h_desc[0];
+  launch_tune_fill(tv.ctx, n, npairs, st);
+  e = tune_passes(tv, &t, st);
+  if (e) return e;
+  Tune tu;
+  for (int k = 0; k < 4; ++k) tu.v[k] = t.variant[k];
+  P->tune[n] = tu;
+  tune_cache_store(cache_path, n, npairs, P->opt.gmres_m, t);
+  *out = t;
+  return MA_OK;
+}
+
+int ma_plan_set_tuning(ma_plan* P, const ma_tuning* t) {
+  if (!P || !t || !n_ok(t->n)) return MA_EINVAL;
+  Tune tu;
+  for (int k = 0; k < 4; ++k) {
+    int u = 0, th = 0;
+    if (t->variant[k] < 0 || t->variant[k] >= MA_TUNE_VARIANTS || ma_tune_geometry(k, t->n, t->variant[k], &u, &th) < 0)
+      return MA_EINVAL;
+    tu.v[k] = t->variant[k];
+  }
+  P->tune[t->n] = tu;
+  return MA_OK;
+}
+
+int ma_plan_get_tuning(const ma_plan* P, int n, ma_tuning* out) {
+  if (!P || !out) return MA_EINVAL;
+  std::memset(out, 0, sizeof(*out));
+  out->n = n;
+  auto it = P->tune.find(n);
+  if (it != P->tune.end())
+    for (int k = 0; k < 4; ++k) out->variant[k] = it->second.v[k];
   return MA_OK;
 }
 

@@ -1,0 +1,432 @@
+// Strain's FFT operator (Section 4.2 of Saumier, Agueh, Khouider): the kernels of
+// the three passes over the grid per operator application, templated on the grid
+// size and a launch-geometry variant; instantiated by k_pass_a/b/c.hip:
+//
+//   pass A  row pass: builds the Krylov vector on the fly (right-hand side,
+//           Gram-Schmidt update, or solution recovery), then a length-N FFT of two
+//           real rows packed as one complex row, split into two half spectra.
+//           Half-spectrum layout H[i][s], s < N/2: slot 0 packs the real DC and
+//           Nyquist coefficients of row i as (Re X_i[0], Re X_i[N/2]).
+//   pass B  column pass: FFT along x1 of each slot, multiply by rhobar(k) (and the
+//           Krylov scale, and 1/N^2), then inverse FFTs of rhobar*sigmahat times
+//           1, 2 pi i k1 and -(2 pi k1)^2 (three outputs T0, T1, T2).
+//   pass C  row pass: five real inverse transforms along x2 taken as complex pairs
+//           (alpha11 + i beta1, alpha12 + i beta2 per row, alpha22 of two rows),
+//           the pointwise combination w = a11 alpha11 + 2 a12 alpha12 + a22 alpha22
+//           + b1 beta1 + b2 beta2, and the Arnoldi inner products <w, v_l>.
+//
+// Wavenumber conventions (reading P8): k in -N/2 .. N/2-1; the first-derivative
+// multiplier 2 pi i k is zero at k = -N/2, the second-derivative multiplier
+// -(2 pi k)^2 is used for every k; rhobar(0) = 0.
+#pragma once
+#include "common.h"
+#include "fft.h"
+#include "kernels.h"
+#include "ma_ot.h"
+
+namespace {
+
+__host__ __device__ constexpr int pow2_div(int limit, int m) {
+  int p = 1;
+  while (p * 2 <= limit && m % (p * 2) == 0) p *= 2;
+  return p;
+}
+__host__ __device__ constexpr int round_block(int t, int cap = 256) {
+  int b = ((t + 63) / 64) * 64;
+  return b < 64 ? 64 : (b > cap ? cap : b);
+}
+
+// Launch geometry per grid size N and variant V (the autotuner's choices):
+//   V = 0  the default: rows (pass A, C) or columns (pass B) per block as below,
+//          about one radix-8 butterfly per thread
+//   V = 1  half as many rows / columns per block (more, smaller blocks)
+//   V = 2  twice as many (fewer, larger blocks; only if the LDS tile stays within 64 KiB)
+//   V = 3  the default tile with half the threads (two butterflies per thread)
+// A variant that does not change the geometry is reported as a duplicate of V = 0.
+__host__ __device__ constexpr int vary_units(int base, int V, int limit, int bytes_per_unit) {
+  return V == 1 ? (base >= 2 ? base / 2 : base)
+                : (V == 2 ? ((limit % (2 * base) == 0 && 2 * base * bytes_per_unit <= 65536) ? 2 * base : base)
+                          : base);
+}
+__host__ __device__ constexpr int vary_block(int block, int V) {
+  return V == 3 ? (block / 2 >= 64 ? ((block / 2 + 63) / 64) * 64 : 64) : block;
+}
+
+template <int N, int V>
+struct Cfg {
+  static constexpr int NH = N / 2;
+  static constexpr int A0 = pow2_div(1024 / N > 0 ? 1024 / N : 1, NH);  // default row pairs per block
+  static constexpr int B0 = pow2_div(4096 / N > 0 ? 4096 / N : 1, NH);  // default columns per block
+  static constexpr int C0 = pow2_div(512 / N > 0 ? 512 / N : 1, NH);    // default row pairs per block
+  static constexpr int A_PPB = vary_units(A0, V, NH, 8 * N);
+  static constexpr int A_BLOCK = vary_block(round_block(A_PPB * N / 8, V == 2 ? 512 : 256), V);
+  static constexpr int B_CPB = vary_units(B0, V, NH, 16 * N);
+  static constexpr int B_BLOCK = vary_block(round_block(B_CPB * N / 8, V == 2 ? 512 : 256), V);
+  static constexpr int C_PPB = vary_units(C0, V, NH, 40 * N);
+  static constexpr int C_BLOCK = vary_block(round_block(5 * C_PPB * N / 8, V == 2 ? 640 : 320), V);
+  static_assert((N * B_CPB) % B_BLOCK == 0, "column pass: whole elements per thread");
+  static_assert(B_BLOCK % B_CPB == 0, "column pass: fixed column per thread");
+};
+
+// the smallest variant index with the same geometry (duplicates share one kernel)
+template <int N, int V>
+struct Canon {
+  static constexpr int A = (V > 0 && Cfg<N, V>::A_PPB == Cfg<N, 0>::A_PPB && Cfg<N, V>::A_BLOCK == Cfg<N, 0>::A_BLOCK) ? 0 : V;
+  static constexpr int B = (V > 0 && Cfg<N, V>::B_CPB == Cfg<N, 0>::B_CPB && Cfg<N, V>::B_BLOCK == Cfg<N, 0>::B_BLOCK) ? 0 : V;
+  static constexpr int C = (V > 0 && Cfg<N, V>::C_PPB == Cfg<N, 0>::C_PPB && Cfg<N, V>::C_BLOCK == Cfg<N, 0>::C_BLOCK) ? 0 : V;
+};
+
+// rhobar(k): inverse symbol of the averaged operator (Section 4.2), zero at k = 0.
+// q: FFT index of k1; q2: FFT index of k2 (N/2 for the Nyquist column).
+// mt[q] = (Im of the first-derivative multiplier, second-derivative multiplier).
+template <int N>
+__device__ __forceinline__ float2 rhobar(int q, int q2, const float (&ab)[5], const float2* __restrict__ mt) {
+  if (q == 0 && q2 == 0) return make_float2(0.f, 0.f);
+  const float2 m1 = mt[q], m2 = mt[q2];
+  // S = a11 d2(k1) + 2 a12 (i d1(k1))(i d1(k2)) + a22 d2(k2) + i (b1 d1(k1) + b2 d1(k2))
+  const float re = ab[0] * m1.y + ab[2] * m2.y - 2.f * ab[1] * m1.x * m2.x;
+  const float im = ab[3] * m1.x + ab[4] * m2.x;
+  const float den = re * re + im * im;
+  return make_float2(re / den, -im / den);
+}
+
+// Z[k] = A + iB and Z[N-k] = conj(A) + i conj(B): the full spectrum of the complex
+// signal whose real / imaginary parts have half spectra A / B
+template <int N>
+__device__ __forceinline__ void put_pair(float2* L, int k, float2 A, float2 B) {
+  L[k] = make_float2(A.x - B.y, A.y + B.x);
+  L[N - k] = make_float2(A.x + B.y, B.x - A.y);
+}
+__device__ __forceinline__ float2 times_i(float s, float2 a) { return make_float2(-s * a.y, s * a.x); }
+
+// ---------------------------------------------------------------------------
+// pass A
+// ---------------------------------------------------------------------------
+template <int N, int G>
+__global__ __launch_bounds__((Cfg<N, G>::A_BLOCK)) void k_passA(LaunchCtx c, int mode, int jn,
+                                                           const float2* __restrict__ tw) {
+  constexpr int PPB = Cfg<N, G>::A_PPB, BLOCK = Cfg<N, G>::A_BLOCK, NH = N / 2;
+  constexpr long NN = (long)N * N;
+  const int p = pair_of_block(c);
+  const PairDesc& d = c.desc[p];
+  PairState& s = c.st[p];
+  bool run;
+  if (mode == PA_INIT) run = s.phase == PH_SOLVE && s.gm_running && s.gm_cycle == 0;
+  else if (mode == PA_PLAIN) run = s.phase == PH_SOLVE && s.gm_restart;
+  else if (mode == PA_ARNOLDI) run = s.phase == PH_SOLVE && s.gm_running;
+  else if (mode == PA_RECOVER) run = s.phase == PH_SOLVE;
+  else run = true;
+  if (!run) return;
+
+  __shared__ float2 lds[PPB * N];
+  __shared__ float cf[MA_MMAX + 1];
+  __shared__ double scratch[BLOCK / 64];
+  int nv = 0;
+  bool usex = false;
+  if (mode == PA_ARNOLDI) nv = jn;
+  else if (mode == PA_RECOVER) { nv = s.gm_k; usex = s.gm_cycle > 0; }
+  if (threadIdx.x < nv) {
+    const int l = threadIdx.x;
+    cf[l] = mode == PA_ARNOLDI ? (float)(s.Hm[(jn - 1) * (MA_MMAX + 1) + l] * s.vscale[l]) : (float)s.y[l];
+  }
+  const float cst = (float)s.mass_c, inv_tau = (float)(1.0 / s.tau);
+  {  // algorithmic bytes per point: vectors read, Krylov vector written, half spectrum written
+    const bool fft = !(mode == PA_ARNOLDI && jn >= c.m);
+    double b = fft ? 4.0 : 0.0;
+    if (mode == PA_INIT) b += 8.0;
+    else if (mode == PA_PLAIN || mode == PA_STEP) b += 4.0;
+    else if (mode == PA_ARNOLDI) b += 4.0 * (jn + 1) + 4.0;
+    else b += 4.0 * (nv + (usex ? 1 : 0));
+    count_bytes(c, b, N);
+  }
+  __syncthreads();
+
+  const int row0 = 2 * blockIdx.x * PPB;
+  float* V = d.V;
+  float* Vj = V + (long)jn * NN;
+  float nrm = 0.f;
+  for (int e = threadIdx.x; e < PPB * N; e += BLOCK) {
+    const int pp = e / N, jj = e % N;
+    const long ea = (long)(row0 + 2 * pp) * N + jj, eb = ea + N;
+    float va, vb;
+    if (mode == PA_INIT) {
+      va = (d.r[ea] + cst) * inv_tau;
+      vb = (d.r[eb] + cst) * inv_tau;
+      V[ea] = va;
+      V[eb] = vb;
+    } else if (mode == PA_PLAIN || mode == PA_STEP) {
+      va = V[ea];
+      vb = V[eb];
+    } else if (mode == PA_ARNOLDI) {
+      va = Vj[ea];
+      vb = Vj[eb];
+      for (int l = 0; l < nv; ++l) {
+        const float* Vl = V + (long)l * NN;
+        va -= cf[l] * Vl[ea];
+        vb -= cf[l] * Vl[eb];
+      }
+      Vj[ea] = va;
+      Vj[eb] = vb;
+      nrm += va * va + vb * vb;
+    } else {  // PA_RECOVER
+      va = usex ? d.x[ea] : 0.f;
+      vb = usex ? d.x[eb] : 0.f;
+      for (int l = 0; l < nv; ++l) {
+        const float* Vl = V + (long)l * NN;
+        va += cf[l] * Vl[ea];
+        vb += cf[l] * Vl[eb];
+      }
+    }
+    lds[pp * N + jj] = make_float2(va, vb);
+  }
+
+  if (!(mode == PA_ARNOLDI && jn >= c.m)) {
+    __syncthreads();
+    fft_lds<N, PPB, BLOCK, false, LAYOUT_ROWS>(lds, tw);
+    for (int e = threadIdx.x; e < PPB * NH; e += BLOCK) {
+      const int pp = e / NH, k = e % NH;
+      const long ia = (long)(row0 + 2 * pp) * NH + k, ib = ia + NH;
+      const float2 zk = lds[pp * N + k];
+      float2 oa, ob;
+      if (k == 0) {
+        const float2 zn = lds[pp * N + NH];
+        oa = make_float2(zk.x, zn.x);
+        ob = make_float2(zk.y, zn.y);
+      } else {
+        const float2 zm = lds[pp * N + N - k];
+        oa = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+        ob = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
+      }
+      d.H[ia] = oa;
+      d.H[ib] = ob;
+    }
+  }
+
+  if (mode == PA_ARNOLDI) {  // partial ||w'||^2, folded by k_arnoldi_finalize
+    double v[1] = {(double)nrm};
+    const int kinds[1] = {0};
+    block_reduce<1>(v, kinds, scratch);
+    if (threadIdx.x == 0) d.part[blockIdx.x] = v[0];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// pass B (columns)
+// ---------------------------------------------------------------------------
+template <int N, int G>
+__global__ __launch_bounds__((Cfg<N, G>::B_BLOCK)) void k_passB(LaunchCtx c, int mode, int j,
+                                                           const float2* __restrict__ tw) {
+  constexpr int CPB = Cfg<N, G>::B_CPB, BLOCK = Cfg<N, G>::B_BLOCK, NH = N / 2;
+  const int p = pair_of_block(c);
+  const PairDesc& d = c.desc[p];
+  const PairState& s = c.st[p];
+  bool run;
+  if (mode == PB_MATVEC) run = s.phase == PH_SOLVE && s.gm_running;
+  else if (mode == PB_RECOVER) run = s.phase == PH_SOLVE;
+  else run = true;
+  if (!run) return;
+  count_bytes(c, mode == PB_MATVEC ? 16.0 : 8.0, N);  // half spectrum in, one or three out
+
+  // S: the column spectra, then rhobar * sigmahat; W: work buffer for derived spectra.
+  // Element (row or wavenumber e, column cc) sits at e * CPB + cc.
+  __shared__ float2 S[N * CPB];
+  __shared__ float2 Wb[N * CPB];
+  const int s0 = blockIdx.x * CPB;
+  for (int e = threadIdx.x; e < N * CPB; e += BLOCK) {
+    const int i = e / CPB, cc = e % CPB;
+    S[e] = d.H[(long)i * NH + s0 + cc];
+  }
+  __syncthreads();
+  fft_lds<N, CPB, BLOCK, false, LAYOUT_COLS>(S, tw);
+  if (mode == PB_FORWARD) {
+    for (int e = threadIdx.x; e < N * CPB; e += BLOCK) {
+      const int i = e / CPB, cc = e % CPB;
+      d.T[(long)i * NH + s0 + cc] = S[e];
+    }
+    return;
+  }
+  const float scale = (float)((mode == PB_MATVEC ? s.vscale[j] : 1.0) / ((double)N * (double)N));
+  float ab[5];
+  for (int k = 0; k < 5; ++k) ab[k] = (float)s.abar[k];
+  // wavenumbers q and N - q together: slot 0 packs the DC and Nyquist columns of the
+  // rows, which separate with the partner coefficient; every later multiplier m(q)
+  // then acts on the packed value P = sA + i sB directly
+  for (int it = threadIdx.x; it < (NH + 1) * CPB; it += BLOCK) {
+    const int q = it / CPB, cc = it % CPB;
+    const int qm = (N - q) % N;
+    const int slot = s0 + cc;
+    const float2 z = S[q * CPB + cc], zm = S[qm * CPB + cc];
+    float2 vq, vm;
+    if (slot != 0) {
+      vq = cscale(cmul(rhobar<N>(q, slot, ab, c.mt), z), scale);
+      vm = cscale(cmul(rhobar<N>(qm, slot, ab, c.mt), zm), scale);
+    } else {
+      const float2 A = make_float2(0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y));
+      const float2 B = make_float2(0.5f * (z.y + zm.y), -0.5f * (z.x - zm.x));
+      const float2 aq = cmul(rhobar<N>(q, 0, ab, c.mt), A), bq = cmul(rhobar<N>(q, NH, ab, c.mt), B);
+      const float2 am = cmul(rhobar<N>(qm, 0, ab, c.mt), cconj(A));
+      const float2 bm = cmul(rhobar<N>(qm, NH, ab, c.mt), cconj(B));
+      vq = cscale(make_float2(aq.x - bq.y, aq.y + bq.x), scale);
+      vm = cscale(make_float2(am.x - bm.y, am.y + bm.x), scale);
+    }
+    S[q * CPB + cc] = vq;
+    if (qm != q) S[qm * CPB + cc] = vm;
+  }
+  __syncthreads();
+  // derived spectra 2 pi i k1 and -(2 pi k1)^2 (matvec only), then the plain one in place
+  const int nout = mode == PB_MATVEC ? 3 : 1;
+  for (int oo = 0; oo < nout; ++oo) {
+    const int o = (oo + 1) % 3 == 0 || nout == 1 ? 0 : oo + 1;  // order 1, 2, 0
+    float2* L = (o == 0) ? S : Wb;
+    if (o != 0) {
+      for (int e = threadIdx.x; e < N * CPB; e += BLOCK) {
+        const int q = e / CPB;
+        const float2 m = c.mt[q];
+        const float2 v = S[e];
+        Wb[e] = (o == 1) ? times_i(m.x, v) : cscale(v, m.y);
+      }
+      __syncthreads();
+    }
+    fft_lds<N, CPB, BLOCK, true, LAYOUT_COLS>(L, tw);
+    float2* To = d.T + (long)o * N * NH;
+    for (int e = threadIdx.x; e < N * CPB; e += BLOCK) {
+      const int i = e / CPB, c2 = e % CPB;
+      To[(long)i * NH + s0 + c2] = L[e];
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// pass C (rows)
+// ---------------------------------------------------------------------------
+template <int N, int G>
+__global__ __launch_bounds__((Cfg<N, G>::C_BLOCK)) void k_passC(LaunchCtx c, int mode, int j,
+                                                           const float2* __restrict__ tw) {
+  constexpr int PPB = Cfg<N, G>::C_PPB, BLOCK = Cfg<N, G>::C_BLOCK, NH = N / 2;
+  constexpr long NN = (long)N * N;
+  const int p = pair_of_block(c);
+  const PairDesc& d = c.desc[p];
+  PairState& s = c.st[p];
+  const bool run = mode == PC_MATVEC ? (s.phase == PH_SOLVE && s.gm_running) : (s.phase == PH_SOLVE);
+  if (!run) return;
+
+  // three half spectra 12, coefficients 20, Krylov vectors for the dots, w 4 (matvec);
+  // one half spectrum 4, theta 8, u read and written 16 (recovery)
+  count_bytes(c, mode == PC_MATVEC ? 36.0 + 4.0 * (j + 1) : (mode == PC_RECOVER ? 28.0 : 8.0), N);
+  __shared__ float2 lds[5 * PPB * N];
+  __shared__ double red[(BLOCK / 64) * (MA_MMAX + 1)];
+  const int row0 = 2 * blockIdx.x * PPB;
+  const float2* T0 = d.T;
+  const float2* T1 = d.T + NN / 2;
+  const float2* T2 = d.T + NN;
+
+  if (mode != PC_MATVEC) {
+    // theta = Lbar^{-1} sigma: one complex inverse transform per row pair
+    for (int e = threadIdx.x; e < PPB * NH; e += BLOCK) {
+      const int pp = e / NH, k = e % NH;
+      const long ia = (long)(row0 + 2 * pp) * NH + k;
+      const float2 a = T0[ia], b = T0[ia + NH];
+      float2* L = lds + pp * N;
+      if (k == 0) {
+        L[0] = make_float2(a.x, b.x);
+        L[NH] = make_float2(a.y, b.y);
+      } else {
+        put_pair<N>(L, k, a, b);
+      }
+    }
+    __syncthreads();
+    fft_lds<N, PPB, BLOCK, true, LAYOUT_ROWS>(lds, tw);
+    for (int e = threadIdx.x; e < PPB * N; e += BLOCK) {
+      const int pp = e / N, jj = e % N;
+      const long ea = (long)(row0 + 2 * pp) * N + jj, eb = ea + N;
+      const float2 z = lds[pp * N + jj];
+      if (mode == PC_RECOVER) {  // FP64 correction kept for step halving; u in FP64
+        d.theta[ea] = (double)z.x;
+        d.theta[eb] = (double)z.y;
+        d.u[ea] += (double)z.x;
+        d.u[eb] += (double)z.y;
+      } else {  // single-step use: FP32 result in the x buffer
+        d.x[ea] = z.x;
+        d.x[eb] = z.y;
+      }
+    }
+    return;
+  }
+
+  // five complex inverse transforms per row pair
+  for (int e = threadIdx.x; e < PPB * NH; e += BLOCK) {
+    const int pp = e / NH, k = e % NH;
+    const long ia = (long)(row0 + 2 * pp) * NH + k, ib = ia + NH;
+    const float2 t0a = T0[ia], t1a = T1[ia], t2a = T2[ia];
+    const float2 t0b = T0[ib], t1b = T1[ib], t2b = T2[ib];
+    float2* L = lds + 5 * pp * N;
+    if (k == 0) {
+      // DC (.x) and Nyquist (.y) are real; the first-derivative multiplier vanishes at
+      // both, the second-derivative one at DC
+      const float d2n = c.mt[NH].y;
+      L[0] = make_float2(t2a.x, t1a.x);
+      L[NH] = make_float2(t2a.y, t1a.y);
+      L[N] = make_float2(0.f, 0.f);
+      L[N + NH] = make_float2(0.f, 0.f);
+      L[2 * N] = make_float2(t2b.x, t1b.x);
+      L[2 * N + NH] = make_float2(t2b.y, t1b.y);
+      L[3 * N] = make_float2(0.f, 0.f);
+      L[3 * N + NH] = make_float2(0.f, 0.f);
+      L[4 * N] = make_float2(0.f, 0.f);
+      L[4 * N + NH] = make_float2(d2n * t0a.y, d2n * t0b.y);
+    } else {
+      const float2 m = c.mt[k];
+      put_pair<N>(L, k, t2a, t1a);
+      put_pair<N>(L + N, k, times_i(m.x, t1a), times_i(m.x, t0a));
+      put_pair<N>(L + 2 * N, k, t2b, t1b);
+      put_pair<N>(L + 3 * N, k, times_i(m.x, t1b), times_i(m.x, t0b));
+      put_pair<N>(L + 4 * N, k, cscale(t0a, m.y), cscale(t0b, m.y));
+    }
+  }
+  __syncthreads();
+  fft_lds<N, 5 * PPB, BLOCK, true, LAYOUT_ROWS>(lds, tw);
+
+  float* W = d.V + (long)(j + 1) * NN;
+  const float* coef = d.coef;
+  float dots[MA_MMAX + 1];
+#pragma unroll
+  for (int l = 0; l <= MA_MMAX; ++l) dots[l] = 0.f;
+  for (int e = threadIdx.x; e < PPB * N; e += BLOCK) {
+    const int pp = e / N, jj = e % N;
+    const long ea = (long)(row0 + 2 * pp) * N + jj, eb = ea + N;
+    const float2* L = lds + 5 * pp * N + jj;
+    const float2 z0 = L[0], z1 = L[N], z2 = L[2 * N], z3 = L[3 * N], z4 = L[4 * N];
+    const float wa = coef[ea] * z0.x + 2.f * coef[NN + ea] * z1.x + coef[2 * NN + ea] * z4.x +
+                     coef[3 * NN + ea] * z0.y + coef[4 * NN + ea] * z1.y;
+    const float wb = coef[eb] * z2.x + 2.f * coef[NN + eb] * z3.x + coef[2 * NN + eb] * z4.y +
+                     coef[3 * NN + eb] * z2.y + coef[4 * NN + eb] * z3.y;
+    W[ea] = wa;
+    W[eb] = wb;
+#pragma unroll
+    for (int l = 0; l <= MA_MMAX; ++l)
+      if (l <= j) {
+        const float* Vl = d.V + (long)l * NN;
+        dots[l] += wa * Vl[ea] + wb * Vl[eb];
+      }
+  }
+  // block reduction of the j+1 inner products (fixed order); folded by k_dots_finalize
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int l = 0; l <= MA_MMAX; ++l)
+    if (l <= j) {
+      double v = wave_sum((double)dots[l]);
+      if (lane == 0) red[wid * (MA_MMAX + 1) + l] = v;
+    }
+  __syncthreads();
+  if (threadIdx.x <= j) {
+    double t = 0.0;
+    for (int w = 0; w < BLOCK / 64; ++w) t += red[w * (MA_MMAX + 1) + threadIdx.x];
+    d.part[(long)blockIdx.x * (MA_MMAX + 1) + threadIdx.x] = t;
+  }
+}
+
+}  // namespace
+
+#define MA_FOR_EACH_N(X) \
+  X(16) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024) X(1536) X(2048)

@@ -26,6 +26,7 @@ PROF = {"none": 0, "residual": 1, "row_a": 2, "column": 3, "row_c": 4}
 EXPORTED = ("ma_abi_version", "ma_options_default", "ma_strerror", "ma_plan_create",
             "ma_plan_destroy", "ma_plan_set_options", "ma_solve", "ma_solve_batched",
             "ma_plan_profile", "ma_plan_profile_read",
+            "ma_plan_autotune", "ma_plan_set_tuning", "ma_plan_get_tuning", "ma_tune_geometry",
             "ma_step_residual", "ma_step_fft2", "ma_step_strain_apply",
             "ma_step_lbar_inverse", "ma_step_gmres",
             "ma_cnn_create", "ma_cnn_destroy", "ma_cnn_param_count", "ma_cnn_set_params",
@@ -39,6 +40,28 @@ class Options(ctypes.Structure):
                 ("interp", ctypes.c_int), ("op_mode", ctypes.c_int),
                 ("damping_policy", ctypes.c_int), ("max_backtrack", ctypes.c_int),
                 ("symbol", ctypes.c_int)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("npairs", ctypes.c_int), ("variant", ctypes.c_int * 4),
+                ("from_cache", ctypes.c_int), ("rejected", ctypes.c_int),
+                ("us", ctypes.c_double * 4), ("us_default", ctypes.c_double * 4)]
+
+    def as_dict(self):
+        return {"n": self.n, "npairs": self.npairs, "variant": list(self.variant),
+                "from_cache": bool(self.from_cache), "rejected": self.rejected,
+                "us": list(self.us), "us_default": list(self.us_default)}
+
+
+TUNE_PASSES = ("row_a", "column", "row_c", "residual")
+
+
+def tune_geometry(kernel_class, n, variant):
+    """(canonical variant or -1, rows/columns/tile width per workgroup, threads); host only."""
+    u, t = ctypes.c_int(), ctypes.c_int()
+    k = TUNE_PASSES.index(kernel_class) if isinstance(kernel_class, str) else int(kernel_class)
+    c = load().ma_tune_geometry(k, n, variant, ctypes.byref(u), ctypes.byref(t))
+    return c, u.value, t.value
 
 
 class Report(ctypes.Structure):
@@ -81,6 +104,10 @@ def load():
     lib.ma_plan_profile.argtypes = [P, I]
     lib.ma_plan_profile_read.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_longlong),
                                          ctypes.POINTER(D)]
+    lib.ma_plan_autotune.argtypes = [P, I, I, ctypes.c_char_p, ctypes.POINTER(Tuning), P]
+    lib.ma_plan_set_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
+    lib.ma_plan_get_tuning.argtypes = [P, I, ctypes.POINTER(Tuning)]
+    lib.ma_tune_geometry.argtypes = [I, I, I, ctypes.POINTER(I), ctypes.POINTER(I)]
     lib.ma_step_residual.argtypes = [P, I, P, P, P, P, P, ctypes.POINTER(D), P]
     lib.ma_step_fft2.argtypes = [P, I, P, P, P]
     lib.ma_step_strain_apply.argtypes = [P, I, P, P, ctypes.POINTER(D), P, P]
@@ -195,6 +222,27 @@ class Plan:
         _check(load().ma_plan_profile_read(self._h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b)),
                "ma_plan_profile_read")
         return {"ms": ms.value, "launches": n.value, "bytes": b.value}
+
+    # -- autotuner -----------------------------------------------------------------
+    def autotune(self, n, npairs, cache=None):
+        """Chooses the launch geometry for size n from timed, output-checked variants;
+        cache: JSON file path (read if it holds an entry, else written)."""
+        t = Tuning()
+        _check(load().ma_plan_autotune(self._h, int(n), int(npairs), cache.encode() if cache else None,
+                                       ctypes.byref(t), _stream()), "ma_plan_autotune")
+        return t.as_dict()
+
+    def set_tuning(self, n, variant):
+        t = Tuning()
+        t.n = int(n)
+        for k in range(4):
+            t.variant[k] = int(variant[k])
+        _check(load().ma_plan_set_tuning(self._h, ctypes.byref(t)), "ma_plan_set_tuning")
+
+    def get_tuning(self, n):
+        t = Tuning()
+        _check(load().ma_plan_get_tuning(self._h, int(n), ctypes.byref(t)), "ma_plan_get_tuning")
+        return list(t.variant)
 
     # -- full solves ------------------------------------------------------------
     def solve(self, f, g, damping=1.0, tol=1e-6, psi0=None, want_map=True):

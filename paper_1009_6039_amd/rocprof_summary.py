@@ -25,8 +25,9 @@ import os
 import re
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-# the translation unit of the Strain passes (row A, column B, row C) and what it includes
-KERNEL_SOURCES = ["csrc/k_strain.hip", "csrc/fft.h", "csrc/common.h", "csrc/kernels.h"]
+# the translation units of the Strain passes (row A, column B, row C) and what they include
+KERNEL_SOURCES = ["csrc/strain.h", "csrc/k_pass_a.hip", "csrc/k_pass_b.hip", "csrc/k_pass_c.hip",
+                  "csrc/k_strain.hip", "csrc/fft.h", "csrc/common.h", "csrc/kernels.h"]
 
 
 def kernel_source_hash():
@@ -129,7 +130,7 @@ def traffic(args):
         rec = {"kernel": args.kernel, "dispatches": d, "read_bytes_per_launch": k["read"][1] / d,
                "write_bytes_per_launch": k["write"][1] / d,
                "traffic_bytes_per_launch": (k["read"][1] + k["write"][1]) / d,
-               "source_sha256": kernel_source_hash()}
+               "source_sha256": kernel_source_hash(), "variant": args.variant}
         if args.algorithmic_bytes_per_launch:
             rec["algorithmic_bytes_per_launch"] = args.algorithmic_bytes_per_launch
             rec["traffic_over_algorithmic"] = rec["traffic_bytes_per_launch"] / args.algorithmic_bytes_per_launch
@@ -172,6 +173,7 @@ def main():
     t.add_argument("--command", action="append", required=True)
     t.add_argument("--note", default="")
     t.add_argument("--algorithmic-bytes-per-launch", type=float, default=0.0)
+    t.add_argument("--variant", type=int, default=0, help="launch-geometry variant of the kernel profiled")
     t.add_argument("--top", type=int, default=12)
     a = ap.parse_args()
     stats(a) if a.cmd == "stats" else traffic(a)

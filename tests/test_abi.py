@@ -71,3 +71,37 @@ def test_plan_create_rejects_bad_options(lib):
                 dict(damping_policy=3), dict(max_backtrack=-1)):
         o = maot.make_options(**bad)
         assert lib.ma_plan_create(64, 1, ctypes.byref(o), ctypes.byref(h)) == -1
+
+
+SIZES = (16, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048)
+
+
+@pytest.mark.parametrize("n", SIZES)
+def test_tune_geometry_table_is_consistent(n):
+    # every variant of every kernel class tiles the grid exactly with whole
+    # wavefronts; duplicates point at a smaller index with the same geometry
+    from paper_1009_6039_amd import maot
+    for k in maot.TUNE_PASSES:
+        seen = {}
+        for v in range(4):
+            canon, units, threads = maot.tune_geometry(k, n, v)
+            assert 0 <= canon <= v and units >= 1 and threads % 64 == 0 and 64 <= threads <= 1024
+            if k in ("row_a", "row_c"):
+                assert (n // 2) % units == 0
+            elif k == "column":
+                assert (n // 2) % units == 0 and (n * units) % threads == 0 and threads % units == 0
+            else:
+                assert n % units == 0 and units >= 16
+            if canon < v:
+                assert seen[canon] == (units, threads)
+            else:
+                assert (units, threads) not in seen.values()
+            seen[v] = (units, threads)
+
+
+def test_tune_geometry_rejects_bad_arguments():
+    from paper_1009_6039_amd import maot
+    assert maot.tune_geometry("row_c", 500, 0)[0] == -1
+    assert maot.tune_geometry("row_c", 512, 4)[0] == -1
+    assert maot.tune_geometry("row_c", 512, -1)[0] == -1
+    assert maot.tune_geometry(7, 512, 0)[0] == -1

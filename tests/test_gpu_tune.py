@@ -1,0 +1,108 @@
+"""GPU: the autotuner's launch-geometry variants.
+
+Every variant of every kernel class must give the solver the same converged
+potential (the oracle's, within the 1e-6 * max|psi| parity bar), the autotuner must
+only choose verified variants, and its JSON cache must round-trip.
+"""
+
+import json
+
+import numpy as np
+import pytest
+
+from oracle import ma
+from paper_1009_6039_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def maot():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1009_6039_amd import maot as m
+    m.load()
+    return m
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.fixture(scope="module")
+def blob128():
+    f, g = W.blobs(128, W.seed_for(1, 3))
+    psi, _, rep = ma.solve(f, g, tol=1e-10, damping_policy="backtrack", gmres_tol=0.1, max_newton=300)
+    assert rep.status == ma.OK
+    return f, g, psi
+
+
+@pytest.mark.parametrize("v", [0, 1, 2, 3])
+def test_every_variant_reaches_the_oracle_solution(maot, blob128, v):
+    f, g, psi_ref = blob128
+    n = f.shape[0]
+    variant = [v if maot.tune_geometry(k, n, v)[0] == v else 0 for k in maot.TUNE_PASSES]
+    p = maot.Plan(n_max=n, batch_capacity=2, damping_policy="backtrack", gmres_tol=0.1, max_newton=300)
+    try:
+        p.set_tuning(n, variant)
+        assert p.get_tuning(n) == variant
+        psis, _, reps = p.solve_batched([dev(f), dev(f)], [dev(g), dev(g)], damping=1.0, tol=1e-9, want_map=False)
+        for psi, rep in zip(psis, reps):
+            assert rep["status"] == 0 and rep["res_rms"] <= 1e-9
+            err = np.max(np.abs(psi.cpu().numpy() - psi_ref)) / np.max(np.abs(psi_ref))
+            assert err <= 1e-6, (variant, err)
+    finally:
+        p.close()
+
+
+@pytest.mark.parametrize("n,npairs", [(128, 4), (512, 8)])
+def test_autotune_chooses_verified_variants_and_caches(maot, tmp_path, n, npairs):
+    cache = str(tmp_path / "tune.json")
+    p = maot.Plan(n_max=n, batch_capacity=npairs)
+    try:
+        t = p.autotune(n, npairs, cache)
+        print("autotune", n, npairs, t)
+        assert not t["from_cache"] and t["rejected"] == 0
+        for k, name in enumerate(maot.TUNE_PASSES):
+            assert maot.tune_geometry(name, n, t["variant"][k])[0] == t["variant"][k]
+            assert 0 < t["us"][k] <= t["us_default"][k] * 1.0001
+        assert p.get_tuning(n) == t["variant"]
+        doc = json.load(open(cache))
+        assert len(doc["entries"]) == 1 and doc["entries"][0]["n"] == n
+        assert doc["entries"][0]["v"] == t["variant"]
+    finally:
+        p.close()
+    q = maot.Plan(n_max=n, batch_capacity=npairs)
+    try:
+        t2 = q.autotune(n, npairs, cache)
+        assert t2["from_cache"] and t2["variant"] == t["variant"]
+        assert q.get_tuning(n) == t["variant"]
+        # another batch size is another entry
+        t3 = q.autotune(n, 1, cache)
+        assert not t3["from_cache"]
+        assert len(json.load(open(cache))["entries"]) == 2
+    finally:
+        q.close()
+
+
+def test_tuned_batched_solve_matches_untuned(maot):
+    n = 256
+    pairs = [W.blobs(n, W.seed_for(1, q)) for q in range(3)]
+    fs = [dev(a) for a, _ in pairs]
+    gs = [dev(b) for _, b in pairs]
+    base = maot.Plan(n_max=n, batch_capacity=3, damping_policy="backtrack", gmres_tol=0.1, max_newton=300,
+                     symbol="fd4")
+    tuned = maot.Plan(n_max=n, batch_capacity=3, damping_policy="backtrack", gmres_tol=0.1, max_newton=300,
+                      symbol="fd4")
+    try:
+        tuned.autotune(n, 3)
+        a, _, ra = base.solve_batched(fs, gs, damping=1.0, tol=1e-8, want_map=False)
+        b, _, rb = tuned.solve_batched(fs, gs, damping=1.0, tol=1e-8, want_map=False)
+        for x, y, r1, r2 in zip(a, b, ra, rb):
+            assert r1["status"] == 0 and r2["status"] == 0
+            x, y = x.cpu().numpy(), y.cpu().numpy()
+            assert np.max(np.abs(x - y)) <= 1e-6 * np.max(np.abs(x))
+    finally:
+        base.close()
+        tuned.close()
