@@ -33,6 +33,9 @@ METRIC = "Newton-solved pairs/sec at 512^2 to residual 1e-6; learned-init vs pla
 def parse():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", default="blobs", choices=("blobs", "mixed"),
+                    help="blobs: B pairs of side n (the metric's workload); mixed: B pairs with sides drawn "
+                         "from {128, 256, 384, 512} (zero init only)")
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=64)
@@ -119,9 +122,17 @@ def main():
     from paper_1009_6039_amd.rocprof_summary import read_traffic_record
     from paper_1009_6039_amd import workloads as W
 
-    N, B = args.n, args.batch
-    seeds = [W.seed_for(1, q) for q in range(B)]
-    host_pairs = [W.blobs(N, s) for s in seeds]
+    B = args.batch
+    if args.workload == "mixed":
+        if args.init != "zero":
+            args.init = "zero"  # the network takes sides 256 and 512 only
+        sizes = W.mixed_sizes(B, W.seed_for(3, 0))
+        seeds = [W.seed_for(3, q) for q in range(B)]
+    else:
+        sizes = [args.n] * B
+        seeds = [W.seed_for(1, q) for q in range(B)]
+    N = max(sizes)
+    host_pairs = [W.blobs(n, s) for n, s in zip(sizes, seeds)]
     fs = [torch.from_numpy(f).cuda() for f, _ in host_pairs]
     gs = [torch.from_numpy(g).cuda() for _, g in host_pairs]
     symbols = args.symbols.split(",")
@@ -130,9 +141,11 @@ def main():
                             gmres_tol=args.gmres_tol, max_newton=300, symbol=sym) for sym in symbols}
 
     tuning = None
-    if args.tune_cache != "none":  # launch geometry chosen before the timed region
+    if args.tune_cache != "none":  # launch geometry chosen before the timed region, per size class
         for sym in symbols:
-            tuning = plans[sym].autotune(N, B, args.tune_cache)
+            for n in sorted(set(sizes)):
+                t = plans[sym].autotune(n, sizes.count(n), args.tune_cache)
+                tuning = t if n == N else tuning
         print("tuning %s" % json.dumps(tuning), file=sys.stderr, flush=True)
 
     net, params, meta = None, None, None
@@ -193,10 +206,14 @@ def main():
         "vs_baseline": None,
         "dtype": "f32/f64",
         "data": "synthetic",
-        "config": {"workload": "blob-density pairs %dx%d (8 periodic Gaussian blobs, 0.1 floor), "
-                               "batch %d per step, rms residual %.0e, %s, %s symbols"
-                               % (N, N, B, args.tol, init_txt, head[0]),
-                   "n": N, "batch": B, "tol": args.tol, "damping_policy": args.damping_policy,
+        "config": {"workload": ("blob-density pairs %dx%d (8 periodic Gaussian blobs, 0.1 floor), "
+                                "batch %d per step, rms residual %.0e, %s, %s symbols"
+                                % (N, N, B, args.tol, init_txt, head[0])) if args.workload == "blobs" else
+                               ("mixed-size blob-density pairs, sides drawn from {128, 256, 384, 512} "
+                                "(%s), batch %d per step, rms residual %.0e, %s, %s symbols"
+                                % (", ".join("%d x %d" % (n, sizes.count(n)) for n in sorted(set(sizes))), B,
+                                   args.tol, init_txt, head[0])),
+                   "n": N if args.workload == "blobs" else sorted(set(sizes)), "batch": B, "tol": args.tol, "damping_policy": args.damping_policy,
                    "gmres_tol": args.gmres_tol, "gmres_m": 10, "init": head[1], "symbol": head[0]},
     }
     out.update(summary(reps))
@@ -216,7 +233,7 @@ def main():
     var = plans[head[0]].get_tuning(N)[cls]
     kname = {"row_c": "k_passC<%d, %d>", "row_a": "k_passA<%d, %d>", "column": "k_passB<%d, %d>"}.get(
         args.profile_class, "")
-    kname = kname % (N, var) if kname else ""  # the kernel as rocprofv3 names it
+    kname = kname % (N, var) if kname and args.workload == "blobs" else ""  # the kernel as rocprofv3 names it
     rec = read_traffic_record(os.path.join(HERE, "profiles", TRAFFIC_FILE % N), kname) if kname else None
     if rec and rec.get("variant") != var:
         rec = None  # counters taken with another launch geometry
@@ -230,14 +247,20 @@ def main():
                        "bytes_per_launch": round(prof["bytes"] / max(prof["launches"], 1)),
                        "algorithmic_bytes_total": prof["bytes"]}
     if not args.no_cpu_baseline:
-        k = min(args.cpu_pairs, B)
-        refs, dt = cpu_baseline(host_pairs[:k], args, params if head[1] == "learned" else None, meta)
-        err = max(float(np.max(np.abs(psis[q].cpu().numpy() - refs[q])) / np.max(np.abs(refs[q])))
-                  for q in range(k))
+        if args.workload == "mixed":  # one pair of each size: the mix's mean cost per pair
+            idx = [sizes.index(n) for n in sorted(set(sizes))]
+        else:
+            idx = list(range(min(args.cpu_pairs, B)))
+        k = len(idx)
+        refs, dt = cpu_baseline([host_pairs[q] for q in idx], args, params if head[1] == "learned" else None,
+                                meta)
+        err = max(float(np.max(np.abs(psis[q].cpu().numpy() - refs[i])) / np.max(np.abs(refs[i])))
+                  for i, q in enumerate(idx))
         out["cpu_baseline"] = {"value": round(k / dt, 5), "unit": "pairs/s", "cores": 1, "kind": "oracle",
-                               "sample": "%d pairs (seeds %d..%d) of the same workload (%s, %s symbols), FP64 "
-                                         "NumPy oracle, one thread, %.1f s"
-                                         % (k, seeds[0], seeds[k - 1], init_txt, head[0], dt)}
+                               "sample": "%d pairs (seeds %s, sides %s) of the same workload (%s, %s symbols), "
+                                         "FP64 NumPy oracle, one thread, %.1f s"
+                                         % (k, ",".join(str(seeds[q]) for q in idx),
+                                            ",".join(str(sizes[q]) for q in idx), init_txt, head[0], dt)}
         out["err_vs_oracle_max"] = err
     print(json.dumps(out), flush=True)
     if net is not None:

@@ -328,3 +328,60 @@ def test_batched_mixed_sizes_match_oracle(maot):
             assert np.max(np.abs(host(psis[q]) - ref)) <= 1e-6 * np.max(np.abs(ref))
     finally:
         p.close()
+
+
+def test_c2_noise_pair_2048_properties(maot):
+    # 2048^2 smooth-noise pair (exp(z/2), filtered white noise, the literal reading of
+    # the recipe), fixed tau = 1: the full-size case is checked through properties the
+    # oracle can evaluate at this size: its own FP64 residual of the GPU potential,
+    # convexity, mean zero, and agreement with a solve along another path (fd4
+    # symbols, tighter tolerance) to the same discrete fixed point.
+    N = 2048
+    f, g = W.smooth_noise(N, W.seed_for(2, 0))
+    print("C2 2048 pair seed %d" % W.seed_for(2, 0), flush=True)
+    p = maot.Plan(n_max=N, batch_capacity=1, gmres_tol=1e-2)
+    q = maot.Plan(n_max=N, batch_capacity=1, gmres_tol=1e-2, symbol="fd4")
+    try:
+        psi, mp, rep = p.solve(dev(f), dev(g), damping=1.0, tol=1e-6)
+        psi = host(psi)
+        print("C2 2048: newton %d gmres %d res %.3e" % (rep["newton_iters"], rep["gmres_iters"], rep["res_rms"]))
+        assert rep["status"] == 0 and rep["res_rms"] <= 1e-6 and rep["min_det"] > 0
+        ev = ma.evaluate(psi, ma.Problem(f, g))
+        assert ev.res_rms <= 1.0001e-6 and ev.convex
+        assert abs(psi.mean()) <= 1e-12
+        psi2, _, rep2 = q.solve(dev(f), dev(g), damping=1.0, tol=1e-9)
+        assert rep2["status"] == 0
+        err = np.max(np.abs(host(psi2) - psi)) / np.max(np.abs(psi))
+        print("C2 2048: spectral tol 1e-6 vs fd4 tol 1e-9: %.3e" % err)
+        assert err <= 2e-6
+    finally:
+        p.close()
+        q.close()
+
+
+def test_c3_mixed_batch_256_pairs(maot):
+    # the mixed-size batch at full size: 256 blob pairs with sides drawn from
+    # {128, 256, 384, 512}, one batched call with autotuned geometry (as bench.py
+    # --workload mixed times it); every pair must converge, and one pair of each size
+    # is compared with the oracle
+    sizes = W.mixed_sizes(256, W.seed_for(3, 0))
+    pairs = [W.blobs(n, W.seed_for(3, q)) for q, n in enumerate(sizes)]
+    p = maot.Plan(n_max=512, batch_capacity=256, damping_policy="backtrack", gmres_tol=0.1, max_newton=300,
+                  symbol="fd4")
+    try:
+        for n in sorted(set(sizes)):
+            p.autotune(n, sizes.count(n))
+        psis, _, reps = p.solve_batched([dev(a) for a, _ in pairs], [dev(b) for _, b in pairs],
+                                        damping=1.0, tol=1e-6)
+        assert all(r["status"] == 0 and r["res_rms"] <= 1e-6 for r in reps)
+        for n in sorted(set(sizes)):
+            qi = sizes.index(n)
+            a, b = pairs[qi]
+            print("C3 sample pair %d (n = %d)" % (qi, n), flush=True)
+            ref, _, rr = ma.solve(a, b, tau=1.0, tol=1e-10, damping_policy="backtrack", gmres_tol=0.1,
+                                  max_newton=300, symbol="fd4")
+            assert rr.status == ma.OK
+            err = np.max(np.abs(host(psis[qi]) - ref)) / np.max(np.abs(ref))
+            assert err <= 2e-6, (n, err)
+    finally:
+        p.close()
