@@ -91,7 +91,7 @@ def cpu_baseline(pairs, args, params=None, meta=None):
             psi0 = None
             if params is not None:
                 shaped = cnn.unflatten_params(params, meta["layers"], meta["channels"])
-                psi0 = cnn.warm_start(f, g, shaped, meta["n_net"])
+                psi0 = cnn.warm_start(f, g, shaped, meta["n_net"], dilations=meta.get("dilations"))
             psi, _, _ = ma.solve(f, g, tau=1.0, tol=args.tol, damping_policy=args.damping_policy,
                                  gmres_tol=args.gmres_tol, max_newton=300, symbol=args.symbol0, psi0=psi0)
             psis.append(psi)
@@ -152,7 +152,7 @@ def main():
     if args.init != "zero":
         params, meta = load_weights(args.weights)
         net = maot.WarmStartNet(layers=meta["layers"], channels=meta["channels"], n_net=meta["n_net"],
-                                max_batch=B)
+                                max_batch=B, dilations=meta.get("dilations"))
         net.set_params(params)
 
     def step(plan, learned):
@@ -191,8 +191,9 @@ def main():
     pairs = B * args.steps
     value = pairs / elapsed
     achieved = prof["bytes"] / (prof["ms"] * 1e-3) / 1e9 if prof["ms"] > 0 else 0.0
-    init_txt = ("learned start (8-layer 32-channel network at 256^2, checked)" if head[1] == "learned"
-                else "zero init")
+    init_txt = ("learned start (8-layer 32-channel %s3x3 network at 256^2, checked)"
+                % ("dilated " if meta and any(d > 1 for d in meta.get("dilations", [1])) else "")
+                if head[1] == "learned" else "zero init")
     out = {
         "metric": METRIC,
         "value": round(value, 3),

@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define MA_OT_ABI_VERSION 3
+#define MA_OT_ABI_VERSION 4
 
 /* return / status codes */
 #define MA_OK 0           /* converged: rms residual <= tol                           */
@@ -257,14 +257,17 @@ int ma_tune_geometry(int pass, int n, int variant, int* per_block, int* threads)
  * psi0 as a checked start (ma_solve), so zero-init Newton stays the fallback.
  *
  * Parameters are FP32 masters in the order W_0, b_0, W_1, b_1, ... with
- * W_l[co][ci][3][3], 2 input channels, `channels` hidden, 1 output channel.
+ * W_l[co][ci][3][3], 2 input channels, `channels` hidden, 1 output channel.  Layer l
+ * computes z(x) = b + sum W[co][ci][a][c] h[ci](x + d_l (a - 1, c - 1)), periodic.
  * Network inputs are BF16 tensors [batch][n_net][n_net][8] (channels 0 and 1 are
  * log(f/mean f) and log(g/mean g), the rest zero), made by ma_cnn_prepare_input.
  * ------------------------------------------------------------------------- */
 typedef struct ma_cnn ma_cnn;
 
-/* layers >= 2, channels == 32, n_net a multiple of 32, max_batch >= 1. */
-int ma_cnn_create(int layers, int channels, int n_net, int max_batch, ma_cnn** out);
+/* layers >= 2, channels == 32, max_batch >= 1; dilations: host array of `layers`
+ * dilation factors d_l >= 1 (the 3x3 taps of layer l are d_l pixels apart), or NULL
+ * for all 1; n_net must be a multiple of 16 d_l for every layer. */
+int ma_cnn_create(int layers, int channels, int n_net, int max_batch, const int* dilations, ma_cnn** out);
 void ma_cnn_destroy(ma_cnn* net);
 long ma_cnn_param_count(const ma_cnn* net);
 /* host FP32 arrays of ma_cnn_param_count values; set also resets the Adam state */

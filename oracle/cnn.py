@@ -12,7 +12,8 @@ and the initial guess is psi0 = (discrete Laplacian)^{-1} (c + log f - log g) wi
 zero mean (the head, applied outside the network).
 
 Convolution convention: out[co, i, j] = b[co] + sum_{ci, a, b} W[co, ci, a, b] *
-x[ci, (i + a - 1) mod H, (j + b - 1) mod W], a, b in {0, 1, 2}.
+x[ci, (i + d(a - 1)) mod H, (j + d(b - 1)) mod W], a, b in {0, 1, 2}, with the
+layer's dilation d (1 unless given).
 
 Optional BF16 emulation (`bf16=True`): the GPU kernels store inputs, weights and
 inter-layer activations in BF16 (round to nearest even) and accumulate in FP32;
@@ -39,19 +40,21 @@ def bf16_round(x):
     return out
 
 
-def conv3x3(x, W, b):
-    """Periodic 3x3 convolution of x (C_in, H, W) with W (C_out, C_in, 3, 3) plus bias."""
+def conv3x3(x, W, b, d=1):
+    """Periodic 3x3 convolution of x (C_in, H, W) with W (C_out, C_in, 3, 3) plus bias,
+    taps d pixels apart (dilation d)."""
     C_out = W.shape[0]
     H, Wd = x.shape[1], x.shape[2]
     out = np.zeros((C_out, H, Wd))
     for a in range(3):
         for c in range(3):
-            xs = np.roll(np.roll(x, -(a - 1), axis=1), -(c - 1), axis=2)  # xs[:, i, j] = x[:, i+a-1, j+c-1]
+            # xs[:, i, j] = x[:, i + d(a-1), j + d(c-1)]
+            xs = np.roll(np.roll(x, -d * (a - 1), axis=1), -d * (c - 1), axis=2)
             out += np.tensordot(W[:, :, a, c], xs, axes=([1], [0]))
     return out + b[:, None, None]
 
 
-def conv3x3_input_grad(dz, W):
+def conv3x3_input_grad(dz, W, d=1):
     """d(sum dz * conv(x))/dx: the correlation with the flipped kernel."""
     C_in = W.shape[1]
     H, Wd = dz.shape[1], dz.shape[2]
@@ -59,17 +62,17 @@ def conv3x3_input_grad(dz, W):
     for a in range(3):
         for c in range(3):
             t = np.tensordot(W[:, :, a, c], dz, axes=([0], [0]))  # (C_in, H, W) at output positions
-            dx += np.roll(np.roll(t, a - 1, axis=1), c - 1, axis=2)
+            dx += np.roll(np.roll(t, d * (a - 1), axis=1), d * (c - 1), axis=2)
     return dx
 
 
-def conv3x3_weight_grad(dz, x):
+def conv3x3_weight_grad(dz, x, d=1):
     """d(sum dz * conv(x))/dW and /db."""
     C_out, C_in = dz.shape[0], x.shape[0]
     dW = np.zeros((C_out, C_in, 3, 3))
     for a in range(3):
         for c in range(3):
-            xs = np.roll(np.roll(x, -(a - 1), axis=1), -(c - 1), axis=2)
+            xs = np.roll(np.roll(x, -d * (a - 1), axis=1), -d * (c - 1), axis=2)
             dW[:, :, a, c] = np.tensordot(dz, xs, axes=([1, 2], [1, 2]))
     return dW, dz.sum(axis=(1, 2))
 
@@ -104,14 +107,15 @@ def unflatten_params(flat, layers, channels, c_in=2, c_out=1):
     return out
 
 
-def forward(x, params, bf16=False):
+def forward(x, params, bf16=False, dilations=None):
     """Returns (output c, cache of layer inputs and pre-activations)."""
     r = bf16_round if bf16 else (lambda v: v)
     h = r(x)
     cache = []
     L = len(params)
+    dil = dilations or [1] * L
     for l, (W, b) in enumerate(params):
-        z = conv3x3(h, r(W), b)
+        z = conv3x3(h, r(W), b, dil[l])
         cache.append((h, z))
         if l < L - 1:
             h = r(np.maximum(z, 0.0))
@@ -124,7 +128,7 @@ def mse(c, t):
     return float(np.mean((c - t) ** 2))
 
 
-def backward(c, t, cache, params, bf16=False, count=None):
+def backward(c, t, cache, params, bf16=False, count=None, dilations=None):
     """Gradients of mse(c, t) with respect to every (W, b).
 
     With bf16=True the gradients flowing between layers are rounded to BF16, as the
@@ -133,14 +137,15 @@ def backward(c, t, cache, params, bf16=False, count=None):
     dh = 2.0 * (c - t) / (c.size if count is None else count)
     grads = [None] * len(params)
     L = len(params)
+    dil = dilations or [1] * L
     for l in range(L - 1, -1, -1):
         h, z = cache[l]
         dz = r(dh if l == L - 1 else dh * (z > 0))
         W = r(params[l][0])
-        dW, db = conv3x3_weight_grad(dz, h)
+        dW, db = conv3x3_weight_grad(dz, h, dil[l])
         grads[l] = (dW, db)
         if l > 0:
-            dh = conv3x3_input_grad(dz, W)
+            dh = conv3x3_input_grad(dz, W, dil[l])
     return grads
 
 
@@ -211,12 +216,12 @@ def training_target(psi, f=None, g=None):
     return t if f is None else t - log_ratio(f, g)
 
 
-def warm_start(f, g, params, n_net, bf16=True):
+def warm_start(f, g, params, n_net, bf16=True, dilations=None):
     """psi0 for one pair: restrict if needed, run the network, prolong, add the log
     ratio at full resolution, invert the Laplacian."""
     n = f.shape[0]
     fr, gr = (restrict_full_weighting(f), restrict_full_weighting(g)) if n == 2 * n_net else (f, g)
-    c, _ = forward(network_input(fr, gr), params, bf16=bf16)
+    c, _ = forward(network_input(fr, gr), params, bf16=bf16, dilations=dilations)
     c = c[0]
     if n == 2 * n_net:
         c = prolong_bilinear(c)

@@ -6,10 +6,11 @@
 
 enum : int { CV_FWD_RELU = 0, CV_FWD_LAST = 1, CV_BWD_DATA = 2 };
 
+// dil: dilation of the 3x3 taps (H and W multiples of 16 * dil)
 void cnn_conv(int cin, int cout_pad, int mode, const void* in, const void* wp, const float* bias, const void* mask,
-              void* out_bf, float* out_f, int batch, int H, int W, hipStream_t st);
-void cnn_wgrad(int cin, int cout, const void* h, const void* dz, int batch, int H, int W, int cout_real, int cin_real,
-               float* part, float* partb, int nblk, float* gw, float* gb, hipStream_t st);
+              void* out_bf, float* out_f, int batch, int H, int W, int dil, hipStream_t st);
+void cnn_wgrad(int cin, int cout, const void* h, const void* dz, int batch, int H, int W, int dil, int cout_real,
+               int cin_real, float* part, float* partb, int nblk, float* gw, float* gb, hipStream_t st);
 void cnn_pack(const float* Wm, int Co, int Ci, int flip, int cin_store, int cout_pad, void* out, hipStream_t st);
 constexpr int CNN_MEAN_PARTS = 64;  // partial sums per field in the mean reductions
 void cnn_means(const double* f, const double* g, int batch, int n, double* part, double* means, hipStream_t st);

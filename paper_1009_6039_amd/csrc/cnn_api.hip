@@ -39,6 +39,7 @@ struct ma_cnn {
   int L = 0, C = 0, n = 0, max_batch = 0;
   std::vector<long> w_off, b_off;  // offsets of W_l and b_l in the flat parameter array
   std::vector<int> cin, cout;      // real channel counts per layer
+  std::vector<int> dil;            // dilation of each layer's taps
   long count = 0;
   float *params = nullptr, *grads = nullptr, *m = nullptr, *v = nullptr;
   long step = 0;
@@ -95,9 +96,11 @@ void forward(ma_cnn* N, const void* x, int batch, hipStream_t st) {
     const void* in = (l == 0) ? x : N->act[l - 1].p;
     const float* bias = N->params + N->b_off[l];
     if (l < N->L - 1)
-      cnn_conv(l == 0 ? 8 : 32, 32, CV_FWD_RELU, in, N->wfwd[l].p, bias, nullptr, N->act[l].p, nullptr, batch, n, n, st);
+      cnn_conv(l == 0 ? 8 : 32, 32, CV_FWD_RELU, in, N->wfwd[l].p, bias, nullptr, N->act[l].p, nullptr, batch, n, n,
+               N->dil[l], st);
     else
-      cnn_conv(32, 16, CV_FWD_LAST, in, N->wfwd[l].p, bias, nullptr, nullptr, (float*)N->c.p, batch, n, n, st);
+      cnn_conv(32, 16, CV_FWD_LAST, in, N->wfwd[l].p, bias, nullptr, nullptr, (float*)N->c.p, batch, n, n,
+               N->dil[l], st);
   }
 }
 
@@ -111,11 +114,12 @@ void backward(ma_cnn* N, const void* x, const float* target, int batch, hipStrea
   for (int l = N->L - 1; l >= 0; --l) {
     const void* h = (l == 0) ? x : N->act[l - 1].p;
     const int cin_store = (l == 0) ? 8 : 32, dz_store = (l == N->L - 1) ? 8 : 32;
-    cnn_wgrad(cin_store, dz_store, h, dz, batch, n, n, N->cout[l], N->cin[l], (float*)N->part.p,
+    cnn_wgrad(cin_store, dz_store, h, dz, batch, n, n, N->dil[l], N->cout[l], N->cin[l], (float*)N->part.p,
               (float*)N->partb.p, WGRAD_BLOCKS, N->grads + N->w_off[l], N->grads + N->b_off[l], st);
     if (l > 0) {
       void* out = outs[l & 1]->p;
-      cnn_conv(dz_store, 32, CV_BWD_DATA, dz, N->wbwd[l].p, nullptr, N->act[l - 1].p, out, nullptr, batch, n, n, st);
+      cnn_conv(dz_store, 32, CV_BWD_DATA, dz, N->wbwd[l].p, nullptr, N->act[l - 1].p, out, nullptr, batch, n, n,
+               N->dil[l], st);
       dz = out;
     }
   }
@@ -125,11 +129,15 @@ void backward(ma_cnn* N, const void* x, const float* target, int batch, hipStrea
 
 extern "C" {
 
-int ma_cnn_create(int layers, int channels, int n_net, int max_batch, ma_cnn** out) {
+int ma_cnn_create(int layers, int channels, int n_net, int max_batch, const int* dilations, ma_cnn** out) {
   if (!out) return MA_EINVAL;
   *out = nullptr;
-  if (layers < 2 || channels != 32 || n_net < 32 || n_net % 32 || max_batch < 1) return MA_EINVAL;
+  if (layers < 2 || channels != 32 || n_net < 16 || n_net % 16 || max_batch < 1) return MA_EINVAL;
+  for (int l = 0; dilations && l < layers; ++l)
+    if (dilations[l] < 1 || n_net % (16 * dilations[l])) return MA_EINVAL;
   ma_cnn* N = new ma_cnn();
+  N->dil.assign(layers, 1);
+  for (int l = 0; dilations && l < layers; ++l) N->dil[l] = dilations[l];
   N->L = layers;
   N->C = channels;
   N->n = n_net;

@@ -4,6 +4,9 @@
 // Activations are BF16, channels last ([sample][row][column][channel]); the
 // network input has 8 stored channels (log f, log g of the mean-one densities, six
 // zeros), hidden layers 32.
+// A layer may be dilated by d (taps d pixels apart): a block then works on a 16 x 16
+// tile of one of the d^2 interleaved subgrids (pixels with the same row and column
+// residues mod d), where the taps are nearest neighbours, periodic with side n/d.
 // A convolution is an implicit GEMM per 16-pixel strip: D[co][pixel] =
 // sum_k A[co][k] B[k][pixel] with k = tap * C_in + ci, computed by
 // v_mfma_f32_16x16x32_bf16 (lane l holds A[l%16][8(l/16)..+7], B[8(l/16)..+7][l%16]
@@ -30,20 +33,24 @@ __device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >=
 template <int CIN, int COUT_PAD, int MODE>
 __global__ __launch_bounds__(256) void k_conv(const bf16* __restrict__ in, const bf16x8* __restrict__ wp,
                                               const float* __restrict__ bias, const bf16* __restrict__ mask,
-                                              bf16* __restrict__ out_bf, float* __restrict__ out_f, int H, int W) {
+                                              bf16* __restrict__ out_bf, float* __restrict__ out_f, int H, int W,
+                                              int dil) {
   constexpr int KB = (9 * CIN + 31) / 32;  // k blocks of 32
   constexpr int MB = COUT_PAD / 16;        // 16-channel output blocks
   constexpr int TW = 16, TH = 16, LW = TW + 2, LH = TH + 2;
   constexpr int CH8 = CIN / 8;             // 16-byte channel chunks per pixel
   __shared__ bf16x8 tile[LH * LW * CH8];
   const int b = blockIdx.z;
-  const int tiles_x = W / TW;
-  const int ty0 = (blockIdx.x / tiles_x) * TH, tx0 = (blockIdx.x % tiles_x) * TW;
+  const int Hd = H / dil, Wd = W / dil;  // subgrid sides
+  const int res = blockIdx.x % (dil * dil), t = blockIdx.x / (dil * dil);
+  const int ry = res / dil, rx = res % dil;
+  const int tiles_x = Wd / TW;
+  const int ty0 = (t / tiles_x) * TH, tx0 = (t % tiles_x) * TW;
   const bf16x8* inb = reinterpret_cast<const bf16x8*>(in) + (size_t)b * H * W * CH8;
   for (int e = threadIdx.x; e < LH * LW * CH8; e += 256) {
     const int chunk = e % CH8, pix = e / CH8;
     const int ly = pix / LW, lx = pix % LW;
-    const int gy = wrap(ty0 + ly - 1, H), gx = wrap(tx0 + lx - 1, W);
+    const int gy = wrap(ty0 + ly - 1, Hd) * dil + ry, gx = wrap(tx0 + lx - 1, Wd) * dil + rx;
     tile[e] = inb[((size_t)gy * W + gx) * CH8 + chunk];
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -72,7 +79,7 @@ __global__ __launch_bounds__(256) void k_conv(const bf16* __restrict__ in, const
       for (int cb = 0; cb < MB; ++cb)
         acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wreg[cb][kb], bop, acc[cb], 0, 0, 0);
     }
-    const size_t pixel = ((size_t)b * H + ty0 + row) * W + tx0 + px;
+    const size_t pixel = ((size_t)b * H + (ty0 + row) * dil + ry) * W + (tx0 + px) * dil + rx;
     if constexpr (MODE == CV_FWD_LAST) {
       if (kq == 0) out_f[pixel] = acc[0][0] + bias[0];
     } else {
@@ -94,43 +101,49 @@ __global__ __launch_bounds__(256) void k_conv(const bf16* __restrict__ in, const
 }
 
 // ---------------------------------------------------------------------------
-// weight gradient: D[co][ci] += sum over a 32-pixel row segment of dz[p][co] h[p+off][ci]
+// weight gradient: D[co][ci] += sum over 32 pixels (two 16-pixel rows of a tile) of
+// dz[p][co] h[p+off][ci]
 // ---------------------------------------------------------------------------
 template <int CIN, int COUT>
 __global__ __launch_bounds__(256) void k_conv_wgrad(const bf16* __restrict__ h, const bf16* __restrict__ dz, int B,
-                                                    int H, int W, int cout_real, int cin_real,
+                                                    int H, int W, int dil, int cout_real, int cin_real,
                                                     float* __restrict__ part, float* __restrict__ partb) {
-  constexpr int TR = 8, TC = 32, LW = TC + 2, LH = TR + 2;
+  constexpr int TR = 16, TC = 16, LW = TC + 2, LH = TR + 2;
+  constexpr int RPK = 32 / TC;  // tile rows per MFMA k block
   constexpr int MB = (COUT + 15) / 16, NB = (CIN + 15) / 16;
   constexpr int NCOMBO = 9 * MB * NB, PERW = (NCOMBO + 3) / 4;
   __shared__ __attribute__((aligned(16))) bf16 dzT[COUT * TR * TC];  // [co][r][c]
   __shared__ bf16 hT[CIN * LH * LW];                                  // [ci][ly][lx]
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int kq = lane >> 4, l16 = lane & 15;
-  const int tiles_y = H / TR, tiles_x = W / TC;
-  const int ntiles = B * tiles_y * tiles_x;
+  const int Hd = H / dil, Wd = W / dil;  // subgrid sides
+  const int tiles_y = Hd / TR, tiles_x = Wd / TC;
+  const int per_sample = dil * dil * tiles_y * tiles_x;
+  const int ntiles = B * per_sample;
   f32x4 acc[PERW];
 #pragma unroll
   for (int i = 0; i < PERW; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
   float bsum = 0.f;
   const bf16x8 zero8 = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const int s = t / (tiles_y * tiles_x), rem = t % (tiles_y * tiles_x);
-    const int y0 = (rem / tiles_x) * TR, x0 = (rem % tiles_x) * TC;
+    const int s = t / per_sample, rem = t % per_sample;
+    const int res = rem % (dil * dil), tt = rem / (dil * dil);
+    const int ry = res / dil, rx = res % dil;
+    const int y0 = (tt / tiles_x) * TR, x0 = (tt % tiles_x) * TC;
     const bf16x8* dz8 = reinterpret_cast<const bf16x8*>(dz) + (size_t)s * H * W * (COUT / 8);
     const bf16x8* h8 = reinterpret_cast<const bf16x8*>(h) + (size_t)s * H * W * (CIN / 8);
     __syncthreads();  // the previous tile is no longer read
     for (int e = threadIdx.x; e < TR * TC * (COUT / 8); e += 256) {
       const int chunk = e % (COUT / 8), pix = e / (COUT / 8);
       const int r = pix / TC, c = pix % TC;
-      const bf16x8 v = dz8[((size_t)(y0 + r) * W + x0 + c) * (COUT / 8) + chunk];
+      const bf16x8 v = dz8[((size_t)((y0 + r) * dil + ry) * W + (x0 + c) * dil + rx) * (COUT / 8) + chunk];
 #pragma unroll
       for (int k = 0; k < 8; ++k) dzT[((chunk * 8 + k) * TR + r) * TC + c] = v[k];
     }
     for (int e = threadIdx.x; e < LH * LW * (CIN / 8); e += 256) {
       const int chunk = e % (CIN / 8), pix = e / (CIN / 8);
       const int ly = pix / LW, lx = pix % LW;
-      const int gy = wrap(y0 + ly - 1, H), gx = wrap(x0 + lx - 1, W);
+      const int gy = wrap(y0 + ly - 1, Hd) * dil + ry, gx = wrap(x0 + lx - 1, Wd) * dil + rx;
       const bf16x8 v = h8[((size_t)gy * W + gx) * (CIN / 8) + chunk];
 #pragma unroll
       for (int k = 0; k < 8; ++k) hT[((chunk * 8 + k) * LH + ly) * LW + lx] = v[k];
@@ -145,12 +158,15 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const bf16* __restrict__ h, 
         const int tap = combo / (MB * NB), cb = (combo / NB) % MB, nb = combo % NB;
         const int dy = tap / 3, dx = tap % 3;
         const int co = cb * 16 + l16, ci = nb * 16 + l16;
+        // lane group kq takes 8 consecutive pixels: row r, columns c0..c0+7
+        const int rq = kq / (TC / 8), c0 = 8 * (kq % (TC / 8));
 #pragma unroll 1
-        for (int r = 0; r < TR; ++r) {
+        for (int rb = 0; rb < TR / RPK; ++rb) {
+          const int r = rb * RPK + rq;
           bf16x8 aop = zero8, bop = zero8;
-          if (co < COUT) aop = *reinterpret_cast<const bf16x8*>(&dzT[(co * TR + r) * TC + 8 * kq]);
+          if (co < COUT) aop = *reinterpret_cast<const bf16x8*>(&dzT[(co * TR + r) * TC + c0]);
           if (ci < CIN) {
-            const bf16* src = &hT[(ci * LH + r + dy) * LW + 8 * kq + dx];
+            const bf16* src = &hT[(ci * LH + r + dy) * LW + c0 + dx];
 #pragma unroll
             for (int k = 0; k < 8; ++k) bop[k] = src[k];
           }
@@ -362,36 +378,36 @@ inline unsigned nblocks(size_t count, int bs) { return (unsigned)((count + bs - 
 // launchers
 // ---------------------------------------------------------------------------
 void cnn_conv(int cin, int cout_pad, int mode, const void* in, const void* wp, const float* bias, const void* mask,
-              void* out_bf, float* out_f, int batch, int H, int W, hipStream_t st) {
+              void* out_bf, float* out_f, int batch, int H, int W, int dil, hipStream_t st) {
   dim3 grid((H / 16) * (W / 16), 1, batch), block(256);
   const bf16* i = (const bf16*)in;
   const bf16x8* w = (const bf16x8*)wp;
   const bf16* mk = (const bf16*)mask;
   bf16* ob = (bf16*)out_bf;
   if (cin == 8 && cout_pad == 32 && mode == CV_FWD_RELU)
-    hipLaunchKernelGGL((k_conv<8, 32, CV_FWD_RELU>), grid, block, 0, st, i, w, bias, mk, ob, out_f, H, W);
+    hipLaunchKernelGGL((k_conv<8, 32, CV_FWD_RELU>), grid, block, 0, st, i, w, bias, mk, ob, out_f, H, W, dil);
   else if (cin == 32 && cout_pad == 32 && mode == CV_FWD_RELU)
-    hipLaunchKernelGGL((k_conv<32, 32, CV_FWD_RELU>), grid, block, 0, st, i, w, bias, mk, ob, out_f, H, W);
+    hipLaunchKernelGGL((k_conv<32, 32, CV_FWD_RELU>), grid, block, 0, st, i, w, bias, mk, ob, out_f, H, W, dil);
   else if (cin == 32 && cout_pad == 16 && mode == CV_FWD_LAST)
-    hipLaunchKernelGGL((k_conv<32, 16, CV_FWD_LAST>), grid, block, 0, st, i, w, bias, mk, ob, out_f, H, W);
+    hipLaunchKernelGGL((k_conv<32, 16, CV_FWD_LAST>), grid, block, 0, st, i, w, bias, mk, ob, out_f, H, W, dil);
   else if (cin == 8 && cout_pad == 32 && mode == CV_BWD_DATA)
-    hipLaunchKernelGGL((k_conv<8, 32, CV_BWD_DATA>), grid, block, 0, st, i, w, bias, mk, ob, out_f, H, W);
+    hipLaunchKernelGGL((k_conv<8, 32, CV_BWD_DATA>), grid, block, 0, st, i, w, bias, mk, ob, out_f, H, W, dil);
   else if (cin == 32 && cout_pad == 32 && mode == CV_BWD_DATA)
-    hipLaunchKernelGGL((k_conv<32, 32, CV_BWD_DATA>), grid, block, 0, st, i, w, bias, mk, ob, out_f, H, W);
+    hipLaunchKernelGGL((k_conv<32, 32, CV_BWD_DATA>), grid, block, 0, st, i, w, bias, mk, ob, out_f, H, W, dil);
 }
 
-void cnn_wgrad(int cin, int cout, const void* h, const void* dz, int batch, int H, int W, int cout_real, int cin_real,
-               float* part, float* partb, int nblk, float* gw, float* gb, hipStream_t st) {
+void cnn_wgrad(int cin, int cout, const void* h, const void* dz, int batch, int H, int W, int dil, int cout_real,
+               int cin_real, float* part, float* partb, int nblk, float* gw, float* gb, hipStream_t st) {
   const bf16* hh = (const bf16*)h;
   const bf16* dd = (const bf16*)dz;
   if (cin == 8 && cout == 32)
-    hipLaunchKernelGGL((k_conv_wgrad<8, 32>), dim3(nblk), dim3(256), 0, st, hh, dd, batch, H, W, cout_real, cin_real,
+    hipLaunchKernelGGL((k_conv_wgrad<8, 32>), dim3(nblk), dim3(256), 0, st, hh, dd, batch, H, W, dil, cout_real, cin_real,
                        part, partb);
   else if (cin == 32 && cout == 32)
-    hipLaunchKernelGGL((k_conv_wgrad<32, 32>), dim3(nblk), dim3(256), 0, st, hh, dd, batch, H, W, cout_real, cin_real,
+    hipLaunchKernelGGL((k_conv_wgrad<32, 32>), dim3(nblk), dim3(256), 0, st, hh, dd, batch, H, W, dil, cout_real, cin_real,
                        part, partb);
   else if (cin == 32 && cout == 8)
-    hipLaunchKernelGGL((k_conv_wgrad<32, 8>), dim3(nblk), dim3(256), 0, st, hh, dd, batch, H, W, cout_real, cin_real,
+    hipLaunchKernelGGL((k_conv_wgrad<32, 8>), dim3(nblk), dim3(256), 0, st, hh, dd, batch, H, W, dil, cout_real, cin_real,
                        part, partb);
   const int nw = cout_real * cin_real * 9;
   hipLaunchKernelGGL(k_wgrad_reduce, dim3(nblocks(nw + cout_real, 256)), dim3(256), 0, st, part, partb, nblk, nw,

@@ -114,7 +114,7 @@ def load():
     lib.ma_step_lbar_inverse.argtypes = [P, I, P, ctypes.POINTER(D), P, P]
     lib.ma_step_gmres.argtypes = [P, I, P, P, ctypes.POINTER(D), I, D, I, P, ctypes.POINTER(I), P]
     F, L = ctypes.c_float, ctypes.c_long
-    lib.ma_cnn_create.argtypes = [I, I, I, I, ctypes.POINTER(P)]
+    lib.ma_cnn_create.argtypes = [I, I, I, I, ctypes.POINTER(I), ctypes.POINTER(P)]
     lib.ma_cnn_destroy.argtypes = [P]
     lib.ma_cnn_param_count.argtypes = [P]
     lib.ma_cnn_param_count.restype = L
@@ -334,12 +334,18 @@ class Plan:
 class WarmStartNet:
     """The warm-start network (ma_cnn): BF16 MFMA convolutions with FP32 masters."""
 
-    def __init__(self, layers=8, channels=32, n_net=256, max_batch=16):
+    def __init__(self, layers=8, channels=32, n_net=256, max_batch=16, dilations=None):
         lib = load()
         h = ctypes.c_void_p()
-        _check(lib.ma_cnn_create(layers, channels, n_net, max_batch, ctypes.byref(h)), "ma_cnn_create")
+        dil = None
+        if dilations is not None:
+            if len(dilations) != layers:
+                raise ValueError("one dilation per layer")
+            dil = (ctypes.c_int * layers)(*[int(d) for d in dilations])
+        _check(lib.ma_cnn_create(layers, channels, n_net, max_batch, dil, ctypes.byref(h)), "ma_cnn_create")
         self._h = h
         self.layers, self.channels, self.n_net, self.max_batch = layers, channels, n_net, max_batch
+        self.dilations = list(dilations) if dilations is not None else [1] * layers
         self.count = int(lib.ma_cnn_param_count(h))
 
     def close(self):

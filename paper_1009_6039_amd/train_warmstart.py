@@ -118,7 +118,8 @@ def evaluate(maot, net, n, count=64, log=print):
     pairs = [W.blobs(n, W.seed_for(TRAIN_CONFIG + 1, q)) for q in range(count)]
     f = [torch.from_numpy(a).cuda() for a, _ in pairs]
     g = [torch.from_numpy(b).cuda() for _, b in pairs]
-    lin = maot.WarmStartNet(layers=net.layers, channels=net.channels, n_net=net.n_net, max_batch=net.max_batch)
+    lin = maot.WarmStartNet(layers=net.layers, channels=net.channels, n_net=net.n_net, max_batch=net.max_batch,
+                            dilations=net.dilations)
     lin.set_params(np.zeros(lin.count, dtype=np.float32))
     out = {}
     for symbol in ("spectral", "fd4"):
@@ -151,6 +152,8 @@ def main():
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--layers", type=int, default=8)
     ap.add_argument("--channels", type=int, default=32)
+    ap.add_argument("--dilations", default="1,2,4,8,16,16,16,1",
+                    help="per-layer dilation of the 3x3 taps (comma list, one per layer)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--workers", type=int, default=16)
     ap.add_argument("--out", required=True)
@@ -158,7 +161,9 @@ def main():
     import torch
     from . import maot
     log = lambda s: print(s, flush=True)  # noqa: E731
-    net = maot.WarmStartNet(layers=args.layers, channels=args.channels, n_net=args.n, max_batch=args.batch)
+    dil = [int(v) for v in args.dilations.split(",")]
+    net = maot.WarmStartNet(layers=args.layers, channels=args.channels, n_net=args.n, max_batch=args.batch,
+                            dilations=dil)
     net.set_params(init_params(args.layers, args.channels, args.seed))
     X, T, ok, gen = generate(maot, net, args.pairs, args.n, workers=args.workers, log=log)
     log("dataset: %s" % json.dumps(gen))
@@ -169,7 +174,7 @@ def main():
     del X, T
     ev = evaluate(maot, net, args.n, log=log)
     ev512 = evaluate(maot, net, 2 * args.n, log=log)
-    meta = {"layers": args.layers, "channels": args.channels, "n_net": args.n, "pairs": args.pairs,
+    meta = {"layers": args.layers, "channels": args.channels, "dilations": dil, "n_net": args.n, "pairs": args.pairs,
             "epochs": args.epochs, "batch": args.batch, "lr": args.lr, "seed": args.seed,
             "dataset": gen, "history": hist, "eval_n_net": ev, "eval_2n_net": ev512}
     np.savez(args.out, params=net.get_params(), meta=np.array(json.dumps(meta)))

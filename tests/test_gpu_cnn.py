@@ -48,10 +48,14 @@ def inputs(n, batch, seed):
     return f, g
 
 
-def test_forward_matches_oracle(maot):
-    n, B = 32, 2
+DILATED = [(32, None), (64, (1, 2, 4, 2, 1, 4, 2, 1)), (48, (1, 3, 1, 1, 3, 1, 1, 1))]
+
+
+@pytest.mark.parametrize("n,dil", DILATED)
+def test_forward_matches_oracle(maot, n, dil):
+    B = 2
     params = f32_params(1)
-    net = maot.WarmStartNet(layers=8, channels=32, n_net=n, max_batch=B)
+    net = maot.WarmStartNet(layers=8, channels=32, n_net=n, max_batch=B, dilations=dil)
     try:
         net.set_params(flat(params))
         f, g = inputs(n, B, 0)
@@ -60,7 +64,7 @@ def test_forward_matches_oracle(maot):
         torch.cuda.synchronize()
         c = c.cpu().numpy().astype(np.float64)
         for k in range(B):
-            ref, _ = cnn.forward(cnn.network_input(f[k], g[k]), params, bf16=True)
+            ref, _ = cnn.forward(cnn.network_input(f[k], g[k]), params, bf16=True, dilations=dil)
             assert rel_l2(c[k], ref[0]) < 2e-3, k
         # the prepared input is the BF16 rounding of (log(f/mean), log(g/mean)); the device
         # logarithm may differ from NumPy's in the last FP32 bit, which moves rare roundings
@@ -73,10 +77,11 @@ def test_forward_matches_oracle(maot):
         net.close()
 
 
-def test_gradients_match_oracle(maot):
-    n, B = 32, 2
+@pytest.mark.parametrize("n,dil", DILATED)
+def test_gradients_match_oracle(maot, n, dil):
+    B = 2
     params = f32_params(2)
-    net = maot.WarmStartNet(layers=8, channels=32, n_net=n, max_batch=B)
+    net = maot.WarmStartNet(layers=8, channels=32, n_net=n, max_batch=B, dilations=dil)
     try:
         net.set_params(flat(params))
         f, g = inputs(n, B, 10)
@@ -87,8 +92,9 @@ def test_gradients_match_oracle(maot):
         grads = grads.cpu().numpy().astype(np.float64)
         tot, lref = None, 0.0
         for k in range(B):
-            c, cache = cnn.forward(cnn.network_input(f[k], g[k]), params, bf16=True)
-            gk = cnn.backward(c, t[k:k + 1].astype(np.float64), cache, params, bf16=True, count=B * n * n)
+            c, cache = cnn.forward(cnn.network_input(f[k], g[k]), params, bf16=True, dilations=dil)
+            gk = cnn.backward(c, t[k:k + 1].astype(np.float64), cache, params, bf16=True, count=B * n * n,
+                              dilations=dil)
             lref += np.sum((c - t[k]) ** 2) / (B * n * n)
             tot = gk if tot is None else [(a[0] + b[0], a[1] + b[1]) for a, b in zip(tot, gk)]
         assert loss == pytest.approx(lref, rel=1e-3)
@@ -124,6 +130,8 @@ def test_adam_steps_reduce_the_loss(maot):
 def test_training_target_matches_oracle(maot):
     net = maot.WarmStartNet(layers=2, channels=32, n_net=32, max_batch=1)
     try:
+        with pytest.raises(maot.MAError):  # a dilation the grid cannot tile
+            maot.WarmStartNet(layers=2, channels=32, n_net=32, max_batch=1, dilations=(1, 4))
         rng = np.random.default_rng(4)
         u = rng.standard_normal((2, 48, 48)) * 1e-3
         f = 0.2 + rng.random((2, 48, 48))
@@ -138,18 +146,18 @@ def test_training_target_matches_oracle(maot):
         net.close()
 
 
-@pytest.mark.parametrize("n", [32, 64])
-def test_warm_start_matches_oracle(maot, n):
+@pytest.mark.parametrize("n,dil", [(32, None), (64, None), (64, (1, 2, 1, 2, 1, 2, 1, 1))])
+def test_warm_start_matches_oracle(maot, n, dil):
     n_net = 32
     params = f32_params(5)
-    net = maot.WarmStartNet(layers=8, channels=32, n_net=n_net, max_batch=2)
+    net = maot.WarmStartNet(layers=8, channels=32, n_net=n_net, max_batch=2, dilations=dil)
     try:
         net.set_params(flat(params))
         f, g = inputs(n, 3, 30)
         psis = net.warm_start([torch.from_numpy(a).cuda() for a in f], [torch.from_numpy(b).cuda() for b in g])
         torch.cuda.synchronize()
         for k in range(3):
-            ref = cnn.warm_start(f[k], g[k], params, n_net)
+            ref = cnn.warm_start(f[k], g[k], params, n_net, dilations=dil)
             got = psis[k].cpu().numpy()
             assert rel_l2(got, ref) < 3e-3, k
             assert abs(got.mean()) < 1e-6 * np.max(np.abs(ref))

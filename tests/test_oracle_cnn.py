@@ -235,3 +235,65 @@ def test_unflatten_inverts_the_flat_order():
         assert np.array_equal(W, W2) and np.array_equal(b + 0.5, b2)
     with pytest.raises(ValueError):
         cnn.unflatten_params(flat[:-1], 3, 4)
+
+
+def brute_conv_dilated(x, W, b, d):
+    C_out, C_in = W.shape[:2]
+    H, Wd = x.shape[1:]
+    out = np.zeros((C_out, H, Wd))
+    for co in range(C_out):
+        for i in range(H):
+            for j in range(Wd):
+                s = b[co]
+                for ci in range(C_in):
+                    for a in range(3):
+                        for c in range(3):
+                            s += W[co, ci, a, c] * x[ci, (i + d * (a - 1)) % H, (j + d * (c - 1)) % Wd]
+                out[co, i, j] = s
+    return out
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_dilated_convolution_matches_brute_force(d):
+    rng = np.random.default_rng(20 + d)
+    x = rng.standard_normal((2, 6, 9))
+    W = rng.standard_normal((3, 2, 3, 3))
+    b = rng.standard_normal(3)
+    assert np.allclose(cnn.conv3x3(x, W, b, d), brute_conv_dilated(x, W, b, d), atol=1e-12)
+
+
+def test_dilated_convolution_acts_on_interleaved_subgrids():
+    # dilation d on an n x n grid = the undilated convolution on each of the d^2
+    # subgrids of pixels with equal residues mod d (what the GPU tiles rely on)
+    rng = np.random.default_rng(30)
+    x = rng.standard_normal((2, 12, 12))
+    W = rng.standard_normal((2, 2, 3, 3))
+    b = rng.standard_normal(2)
+    full = cnn.conv3x3(x, W, b, 3)
+    for ry in range(3):
+        for rx in range(3):
+            assert np.allclose(full[:, ry::3, rx::3], cnn.conv3x3(x[:, ry::3, rx::3], W, b), atol=1e-12)
+
+
+def test_dilated_gradients_match_central_differences():
+    rng = np.random.default_rng(31)
+    params = cnn.init_params(channels=4, layers=3, c_in=2, c_out=1, seed=5)
+    params = [(W, rng.standard_normal(b.shape) * 0.1) for W, b in params]
+    dil = [1, 2, 4]
+    x = rng.standard_normal((2, 8, 8))
+    t = rng.standard_normal((1, 8, 8))
+    c, cache = cnn.forward(x, params, dilations=dil)
+    grads = cnn.backward(c, t, cache, params, dilations=dil)
+    eps = 1e-6
+    for l in range(3):
+        W, b = params[l]
+        for idx in [tuple(rng.integers(0, s) for s in W.shape) for _ in range(4)]:
+            Wp, Wm = W.copy(), W.copy()
+            Wp[idx] += eps
+            Wm[idx] -= eps
+            pp = list(params)
+            pp[l] = (Wp, b)
+            lp = cnn.mse(cnn.forward(x, pp, dilations=dil)[0], t)
+            pp[l] = (Wm, b)
+            lm = cnn.mse(cnn.forward(x, pp, dilations=dil)[0], t)
+            assert grads[l][0][idx] == pytest.approx((lp - lm) / (2 * eps), rel=1e-5, abs=1e-9)
