@@ -14,7 +14,7 @@ memory and gathers minibatches):
   5. an evaluation: Newton iterations from zero and from the learned start on
      held-out pairs.
 
-  python -m paper_1009_6039_amd.train_warmstart --pairs 20000 --epochs 8 \
+  python -m paper_1009_6039_amd.train_warmstart --pairs 20000 \
       --out paper_1009_6039_amd/warmstart_256.npz
 """
 
@@ -147,9 +147,9 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--pairs", type=int, default=20000)
     ap.add_argument("--n", type=int, default=256)
-    ap.add_argument("--epochs", type=int, default=16)
+    ap.add_argument("--epochs", type=int, default=32)
     ap.add_argument("--batch", type=int, default=16)
-    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--layers", type=int, default=8)
     ap.add_argument("--channels", type=int, default=32)
     ap.add_argument("--dilations", default="1,2,4,8,16,16,16,1",
