@@ -238,11 +238,14 @@ def main():
     rec = read_traffic_record(os.path.join(HERE, "profiles", TRAFFIC_FILE % N), kname) if kname else None
     if rec and rec.get("variant") != var:
         rec = None  # counters taken with another launch geometry
+    bpl = prof["bytes"] / max(prof["launches"], 1)
+    if rec and abs(rec.get("algorithmic_bytes_per_launch", 0.0) - bpl) > 1e-3 * bpl:
+        rec = None  # counters taken on another launch mix (workload, start or iteration path)
     out["roofline"] = {"bound": "hbm", "kernel": args.profile_class, "achieved": round(achieved, 1),
                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                        "traffic": round(rec["traffic_bytes_per_launch"]) if rec else None,
-                       "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-scaled; null when the "
-                                       "kernel sources differ from the profiled ones)",
+                       "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-scaled; null unless the "
+                                       "kernel sources, geometry and launch mix are the profiled ones)",
                        "launches": prof["launches"],
                        "avg_launch_us": round(1e3 * prof["ms"] / max(prof["launches"], 1), 3),
                        "bytes_per_launch": round(prof["bytes"] / max(prof["launches"], 1)),
