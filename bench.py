@@ -5,15 +5,18 @@ One step solves a batch of blob-density pairs (8 periodic Gaussian blobs on a 0.
 floor, seeded) of size 512 x 512 with the damped Newton / Strain-GMRES method to
 an rms residual of 1e-6, all pairs in one batched call.  Arms: the plain method
 (Newton from zero) and the learned start (the warm-start network's guess for every
-pair, computed inside the timed region, then Newton from it), each with the linear
-solve's symbols taken from the fourth-order differences (fd4: the Jacobian of the
-discrete residual, the same fixed point in fewer iterations) and with the paper's
-spectral symbols.  `value` is the first symbol's learned-start throughput; every arm
-is reported beside it.  The inputs are resident in device memory before the timed
-region.  Prints one JSON line.
+pair, computed inside the timed region, then Newton from it), each with two ways of
+solving the linear equation:
+  fast   symbols of the fourth-order differences (the Jacobian of the discrete
+         residual) and GMRES on the system scaled by the relative trace of the
+         coefficients: the same fixed point in fewer iterations;
+  paper  the paper's spectral symbols, unscaled.
+`value` is the first method's learned-start throughput; every arm is reported
+beside it.  The inputs are resident in device memory before the timed region.
+Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--batch B] [--gpus 1] [--init both|zero|learned]
-                  [--symbols fd4,spectral]
+                  [--methods fast,paper]
 """
 
 import argparse
@@ -28,6 +31,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 TRAFFIC_FILE = "row_c_%d_batch64_hbm_traffic.md"  # written by paper_1009_6039_amd.rocprof_summary traffic
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 METRIC = "Newton-solved pairs/sec at 512^2 to residual 1e-6; learned-init vs plain"
+# linear-solve method -> plan options (symbols of the derivatives, left scaling)
+METHODS = {"fast": {"symbol": "fd4", "precond": "diag"}, "fd4": {"symbol": "fd4", "precond": "none"},
+           "paper": {"symbol": "spectral", "precond": "none"},
+           "spectral-diag": {"symbol": "spectral", "precond": "diag"}}
 
 
 def parse():
@@ -43,8 +50,9 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--gmres-tol", type=float, default=0.1)
     ap.add_argument("--damping-policy", default="backtrack")
-    ap.add_argument("--symbols", default="fd4,spectral",
-                    help="comma list of linear-solve symbols; the first is the headline")
+    ap.add_argument("--methods", default="fast,paper",
+                    help="comma list of linear-solve methods (%s); the first is the headline"
+                         % ", ".join(sorted(METHODS)))
     ap.add_argument("--profile-class", default="row_c",
                     help="kernel class timed for the roofline: residual, row_a, column, row_c")
     ap.add_argument("--init", default="both", choices=("both", "zero", "learned"),
@@ -93,7 +101,7 @@ def cpu_baseline(pairs, args, params=None, meta=None):
                 shaped = cnn.unflatten_params(params, meta["layers"], meta["channels"])
                 psi0 = cnn.warm_start(f, g, shaped, meta["n_net"], dilations=meta.get("dilations"))
             psi, _, _ = ma.solve(f, g, tau=1.0, tol=args.tol, damping_policy=args.damping_policy,
-                                 gmres_tol=args.gmres_tol, max_newton=300, symbol=args.symbol0, psi0=psi0)
+                                 gmres_tol=args.gmres_tol, max_newton=300, psi0=psi0, **METHODS[args.method0])
             psis.append(psi)
         dt = time.perf_counter() - t0
     return psis, dt
@@ -135,10 +143,13 @@ def main():
     host_pairs = [W.blobs(n, s) for n, s in zip(sizes, seeds)]
     fs = [torch.from_numpy(f).cuda() for f, _ in host_pairs]
     gs = [torch.from_numpy(g).cuda() for _, g in host_pairs]
-    symbols = args.symbols.split(",")
-    args.symbol0 = symbols[0]
+    symbols = args.methods.split(",")
+    for sym in symbols:
+        if sym not in METHODS:
+            raise SystemExit("unknown method %r" % sym)
+    args.method0 = symbols[0]
     plans = {sym: maot.Plan(n_max=N, batch_capacity=B, damping_policy=args.damping_policy,
-                            gmres_tol=args.gmres_tol, max_newton=300, symbol=sym) for sym in symbols}
+                            gmres_tol=args.gmres_tol, max_newton=300, **METHODS[sym]) for sym in symbols}
 
     tuning = None
     if args.tune_cache != "none":  # launch geometry chosen before the timed region, per size class
@@ -208,14 +219,15 @@ def main():
         "dtype": "f32/f64",
         "data": "synthetic",
         "config": {"workload": ("blob-density pairs %dx%d (8 periodic Gaussian blobs, 0.1 floor), "
-                                "batch %d per step, rms residual %.0e, %s, %s symbols"
+                                "batch %d per step, rms residual %.0e, %s, %s linear solve"
                                 % (N, N, B, args.tol, init_txt, head[0])) if args.workload == "blobs" else
                                ("mixed-size blob-density pairs, sides drawn from {128, 256, 384, 512} "
-                                "(%s), batch %d per step, rms residual %.0e, %s, %s symbols"
+                                "(%s), batch %d per step, rms residual %.0e, %s, %s linear solve"
                                 % (", ".join("%d x %d" % (n, sizes.count(n)) for n in sorted(set(sizes))), B,
                                    args.tol, init_txt, head[0])),
                    "n": N if args.workload == "blobs" else sorted(set(sizes)), "batch": B, "tol": args.tol, "damping_policy": args.damping_policy,
-                   "gmres_tol": args.gmres_tol, "gmres_m": 10, "init": head[1], "symbol": head[0]},
+                   "gmres_tol": args.gmres_tol, "gmres_m": 10, "init": head[1], "method": head[0],
+                   "symbol": METHODS[head[0]]["symbol"], "precond": METHODS[head[0]]["precond"]},
     }
     out.update(summary(reps))
     if tuning is not None:
@@ -261,7 +273,7 @@ def main():
         err = max(float(np.max(np.abs(psis[q].cpu().numpy() - refs[i])) / np.max(np.abs(refs[i])))
                   for i, q in enumerate(idx))
         out["cpu_baseline"] = {"value": round(k / dt, 5), "unit": "pairs/s", "cores": 1, "kind": "oracle",
-                               "sample": "%d pairs (seeds %s, sides %s) of the same workload (%s, %s symbols), "
+                               "sample": "%d pairs (seeds %s, sides %s) of the same workload (%s, %s linear solve), "
                                          "FP64 NumPy oracle, one thread, %.1f s"
                                          % (k, ",".join(str(seeds[q]) for q in idx),
                                             ",".join(str(sizes[q]) for q in idx), init_txt, head[0], dt)}

@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define MA_OT_ABI_VERSION 4
+#define MA_OT_ABI_VERSION 5
 
 /* return / status codes */
 #define MA_OK 0           /* converged: rms residual <= tol                           */
@@ -59,6 +59,12 @@ extern "C" {
  * residual; the fixed point is unchanged) */
 #define MA_SYMBOL_SPECTRAL 0
 #define MA_SYMBOL_FD4 1
+/* GMRES on L Lbar^{-1} sigma = h as in Section 4.2, or (an option) on the system
+ * scaled on the left by D(x) = (a11 + a22)(x) / (abar11 + abar22), the trace of the
+ * coefficient matrix relative to the averaged operator's: the same direction when
+ * solved exactly, fewer iterations at a loose tolerance; the fixed point is unchanged */
+#define MA_PRECOND_NONE 0
+#define MA_PRECOND_DIAG 1
 
 typedef struct ma_options {
   int max_newton;          /* Newton iterations before MA_ENOCONV (100)              */
@@ -70,6 +76,10 @@ typedef struct ma_options {
   int damping_policy;      /* MA_DAMP_*                                              */
   int max_backtrack;       /* step halvings per Newton step before failing (12)      */
   int symbol;              /* MA_SYMBOL_* (MA_SYMBOL_SPECTRAL)                       */
+  int precond;             /* MA_PRECOND_* (MA_PRECOND_NONE)                         */
+  double boundary_frac;    /* MA_DAMP_BACKTRACK: a step is also halved while min det  */
+                           /* (I + D^2 u) would fall below this fraction of its       */
+                           /* current value, 0 <= . < 1 (0.1; 0 = off)                */
 } ma_options;
 
 typedef struct ma_report {
@@ -164,6 +174,7 @@ int ma_plan_profile_read(ma_plan* plan, double* ms, long long* launches, double*
  * Single steps of the hot path, for verification and profiling.  They run the
  * same kernels as the solver on one pair, using the plan's workspace, and are
  * stream-ordered (no host synchronisation unless a host output is requested).
+ * They apply the operator of Section 4.2 whatever the plan's `precond` option.
  * ------------------------------------------------------------------------- */
 
 /* Section 4 + eq. (ma2), (translation), (linearmaeq): fourth-order derivatives of u,

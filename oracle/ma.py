@@ -17,6 +17,11 @@ What the paper fixes, and where:
 * Section 4: fourth-order differences for the derivatives of u_n (oracle.fd),
   interpolation of g (oracle.interp), and the normalisation of eq. (translation)
   f~_n = f_n - mean(f_n) + 1.
+* Option precond = "diag" (not in the paper): GMRES on the system scaled on the left
+  by D(x) = trace of the coefficient matrix over that of the averaged one; the same
+  Newton direction when GMRES is run to convergence, fewer iterations at a loose
+  tolerance.  Pins: identical to the plain solve when D = 1, the same direction
+  at a tight GMRES tolerance, the same converged potential.
 * Section 4.2: Strain's method.  Solve L Lbar^{-1} sigma = h by GMRES(m), then
   theta = Lbar^{-1} sigma, where Lbar has the Simpson averages of the coefficients,
   rhobar(k) = 1 / (sum abar_ij (2 pi i k_i)(2 pi i k_j) + sum bbar_i 2 pi i k_i), zero where
@@ -292,26 +297,49 @@ class Report(dict):
     __getattr__ = dict.__getitem__
 
 
+def diag_scale(coef, abar):
+    """D(x) = (a11 + a22)(x) / (abar11 + abar22): the operator's trace relative to that
+    of the averaged operator (positive wherever the iterate is convex)."""
+    return (coef[0] + coef[2]) / (abar[0] + abar[2])
+
+
 def newton_direction(ev, prob, rhs_scale, op_mode, gmres_m, gmres_tol, gmres_max_restarts,
-                     symbol_kind="spectral"):
-    """theta solving D M theta = r * rhs_scale by Strain's method; returns (theta, its)."""
+                     symbol_kind="spectral", precond="none"):
+    """theta solving D M theta = r * rhs_scale by Strain's method; returns (theta, its).
+
+    precond = "diag" (not in the paper) runs GMRES on the left-scaled system
+    D^{-1} L Lbar^{-1} sigma = D^{-1} h with D from diag_scale: the same sigma when
+    solved exactly, a different Krylov space and stopping norm otherwise."""
     coef = coefficients(ev, op_mode)
     abar = averaged(coef)
     rho = symbol(abar, prob.N, symbol_kind)
     rhs = ev.r * rhs_scale
-    sigma, its, _ = gmres(lambda v: strain_apply(v, coef, rho, symbol_kind), rhs,
-                          m=gmres_m, tol=gmres_tol, max_restarts=gmres_max_restarts)
+    if precond == "diag":
+        D = diag_scale(coef, abar)
+        op = lambda v: strain_apply(v, coef, rho, symbol_kind) / D  # noqa: E731
+        rhs = rhs / D
+    elif precond == "none":
+        op = lambda v: strain_apply(v, coef, rho, symbol_kind)  # noqa: E731
+    else:
+        raise ValueError("precond must be 'none' or 'diag'")
+    sigma, its, _ = gmres(op, rhs, m=gmres_m, tol=gmres_tol, max_restarts=gmres_max_restarts)
     return lbar_inverse(sigma, rho), its
 
 
 def solve(f, g, tau=1.0, tol=1e-6, psi0=None, max_newton=100, gmres_m=10,
           gmres_tol=1e-4, gmres_max_restarts=20, interp="bilinear", op_mode=0,
           damping_policy="fixed", max_backtrack=12, g_analytic=None, history=False,
-          symbol="spectral"):
+          symbol="spectral", precond="none", boundary_frac=0.1):
     """Damped Newton (eq. linma) with Strain's linear solver (Section 4.2).
 
     psi0, if given, is tried as a first step from u = 0 (accepted if convex and the
     residual drops, halved otherwise, abandoned after max_backtrack halvings).
+
+    With damping_policy "backtrack" a Newton step is accepted only if the iterate
+    stays convex, the residual drops, and min det(I + D^2 u) does not fall below
+    boundary_frac times its current value (a fraction-to-the-boundary rule: without
+    it an iterate can land next to the boundary of convexity, where every later
+    direction leaves it and the halving stalls).
 
     Returns (psi, map, report): psi is the mean-zero potential u on the grid, map is
     x + D_h u as a (2, N, N) array (unwrapped: the additive map of Theorem CE1),
@@ -358,7 +386,7 @@ def solve(f, g, tau=1.0, tol=1e-6, psi0=None, max_newton=100, gmres_m=10,
             status = ENOCONV
             break
         theta, its = newton_direction(ev, prob, 1.0 / tau_cur, op_mode, gmres_m,
-                                      gmres_tol, gmres_max_restarts, symbol)
+                                      gmres_tol, gmres_max_restarts, symbol, precond)
         gm_total += its
         n += 1
         if damping_policy == "fixed":
@@ -370,7 +398,8 @@ def solve(f, g, tau=1.0, tol=1e-6, psi0=None, max_newton=100, gmres_m=10,
             for _ in range(max_backtrack + 1):
                 u_try = u + theta * (tau_solve / tau_cur)
                 ev_try = evaluate(u_try, prob)
-                if ev_try.convex and ev_try.res_rms < ev.res_rms:
+                if (ev_try.convex and ev_try.res_rms < ev.res_rms
+                        and ev_try.min_det >= boundary_frac * ev.min_det):
                     accepted = True
                     break
                 tau_cur *= 2.0

@@ -91,6 +91,8 @@ struct LaunchCtx {
   const float2* mt;  // per-wavenumber multipliers (Im d/dx, d^2/dx^2) of the selected symbol
   unsigned long long* prof_bytes;  // algorithmic-byte counter of the timed class, or null
   int var[4];  // launch-geometry variants (pass A, pass B, pass C, residual), 0 = default
+  int precond;  // MA_PRECOND_*: left scaling of the GMRES system by the relative trace
+  double boundary_frac;  // step halving: smallest allowed ratio of min det to its current value
 };
 
 // adds one pair's algorithmic bytes for this launch (timed class only)

@@ -114,7 +114,10 @@ __device__ static void newton_decide(PairState& s, const LaunchCtx& c, int n, co
   }
   const bool trial = (ph == PH_SOLVE || ph == PH_BACKTRACK);
   if (trial && (c.damping_policy == MA_DAMP_BACKTRACK || s.warm_trial)) {
-    const bool accept = convex && res < s.res_prev;
+    // a Newton step must also keep min det(I + D^2 u) above a fraction of its value at
+    // the current iterate (fraction to the boundary of convexity); the checked start
+    // is measured against u = 0 and only needs convexity and a lower residual
+    const bool accept = convex && res < s.res_prev && (s.warm_trial || tot[10] >= c.boundary_frac * s.min_det);
     if (!accept) {
       s.bt_step++;
       if (!s.warm_trial) {

@@ -104,6 +104,27 @@ __global__ __launch_bounds__(256) void k_arnoldi_finalize(LaunchCtx c, int jn, i
   if (threadIdx.x == 0) arnoldi_close(s, c, jn, t[0]);
 }
 
+// the scaled right-hand side's norm (option MA_PRECOND_DIAG) from the pass-A partials:
+// the GMRES start values that the residual's fold set for the unscaled system
+__global__ __launch_bounds__(256) void k_rhs_finalize(LaunchCtx c, int nblk) {
+  const int p = pair_of_block(c);
+  const PairDesc& d = c.desc[p];
+  PairState& s = c.st[p];
+  if (!(s.phase == PH_SOLVE && s.gm_running && s.gm_cycle == 0)) return;
+  __shared__ double scratch[4];
+  const int kinds[1] = {0};
+  double t[1];
+  fold_partials<1>(d.part, nblk, kinds, t, scratch);
+  if (threadIdx.x == 0) {
+    const double bn = sqrt(fmax(t[0], 0.0));
+    s.bnorm = bn;
+    s.gm_target = c.gmres_tol * bn;
+    s.gm_running = bn > 0.0;
+    s.vscale[0] = bn > 0.0 ? 1.0 / bn : 0.0;
+    s.gv[0] = bn;
+  }
+}
+
 // a restarted cycle begins: its first vector has been transformed by pass A
 __global__ void k_cycle_begin(LaunchCtx c) {
   const int p = pair_of_block(c);
@@ -160,6 +181,8 @@ void launch_passA(const LaunchCtx& c, int n, int npairs, int mode, int jn, const
   launch_passA_only(c, n, npairs, mode, jn, tw, st, ev);
   if (mode == PA_ARNOLDI)
     hipLaunchKernelGGL(k_arnoldi_finalize, dim3(1, npairs), dim3(256), 0, st, c, jn, passA_blocks(n, c.var[0]));
+  else if (mode == PA_INIT && c.precond == MA_PRECOND_DIAG)
+    hipLaunchKernelGGL(k_rhs_finalize, dim3(1, npairs), dim3(256), 0, st, c, passA_blocks(n, c.var[0]));
   else if (mode == PA_PLAIN)
     hipLaunchKernelGGL(k_cycle_begin, dim3(1, npairs), dim3(64), 0, st, c);
 }

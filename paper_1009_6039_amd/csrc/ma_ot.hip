@@ -120,7 +120,9 @@ int validate_options(const ma_options& o) {
       !(o.gmres_tol > 0.0) || (o.interp != MA_INTERP_BILINEAR && o.interp != MA_INTERP_NEAREST) ||
       (o.op_mode != MA_OP_FULL && o.op_mode != MA_OP_NO_DRIFT) ||
       (o.damping_policy != MA_DAMP_FIXED && o.damping_policy != MA_DAMP_BACKTRACK) || o.max_backtrack < 0 ||
-      (o.symbol != MA_SYMBOL_SPECTRAL && o.symbol != MA_SYMBOL_FD4))
+      (o.symbol != MA_SYMBOL_SPECTRAL && o.symbol != MA_SYMBOL_FD4) ||
+      (o.precond != MA_PRECOND_NONE && o.precond != MA_PRECOND_DIAG) ||
+      !(o.boundary_frac >= 0.0 && o.boundary_frac < 1.0))
     return MA_EINVAL;
   return MA_OK;
 }
@@ -227,6 +229,8 @@ LaunchCtx make_ctx(const ma_plan* P, const Class& cl, int kind = MA_PROF_NONE) {
   c.interp = P->opt.interp;
   c.op_mode = P->opt.op_mode;
   c.gmres_tol = P->opt.gmres_tol;
+  c.precond = P->opt.precond;
+  c.boundary_frac = P->opt.boundary_frac;
   auto t = P->tune.find(cl.n);
   for (int k = 0; k < 4; ++k) c.var[k] = t == P->tune.end() ? 0 : t->second.v[k];
   return c;
@@ -453,6 +457,8 @@ void ma_options_default(ma_options* o) {
   o->damping_policy = MA_DAMP_FIXED;
   o->max_backtrack = 12;
   o->symbol = MA_SYMBOL_SPECTRAL;
+  o->precond = MA_PRECOND_NONE;
+  o->boundary_frac = 0.1;
 }
 
 const char* ma_strerror(int code) {
@@ -675,6 +681,7 @@ int ma_step_residual(ma_plan* P, int n, const double* u, const double* f, const 
   d.psi0_in = u;  // u0 = u - 0: the state's means are 1 and 0, so f and g are used as given
   HIP_TRY(hipMemcpyAsync(P->d_desc, P->h_desc.data(), sizeof(PairDesc), hipMemcpyHostToDevice, st));
   LaunchCtx x = make_ctx(P, c);
+  x.precond = MA_PRECOND_NONE;  // the step entry points apply the operator of Section 4.2
   launch_setup_fields(x, n, 1, st);
   launch_residual(x, n, 1, 1, st);
   if (r) launch_residual_shift(x, n, r, st);
@@ -699,6 +706,7 @@ int ma_step_fft2(ma_plan* P, int n, const float* v, float* spec, void* stream) {
   const PairDesc& d = P->h_desc[0];
   HIP_TRY(hipMemcpyAsync(d.V, v, 4 * (size_t)n * n, hipMemcpyDeviceToDevice, st));
   LaunchCtx x = make_ctx(P, c);
+  x.precond = MA_PRECOND_NONE;  // the step entry points apply the operator of Section 4.2
   launch_passA(x, n, 1, PA_STEP, 0, c.tw, st);
   launch_passB(x, n, 1, PB_FORWARD, 0, c.tw, st);
   HIP_TRY(hipMemcpyAsync(spec, d.T, 4 * (size_t)n * n, hipMemcpyDeviceToDevice, st));
@@ -717,6 +725,7 @@ int ma_step_strain_apply(ma_plan* P, int n, const float* v, const float* coef, c
   HIP_TRY(hipMemcpyAsync(d.V, v, 4 * nn, hipMemcpyDeviceToDevice, st));
   HIP_TRY(hipMemcpyAsync(d.coef, coef, 20 * nn, hipMemcpyDeviceToDevice, st));
   LaunchCtx x = make_ctx(P, c);
+  x.precond = MA_PRECOND_NONE;  // the step entry points apply the operator of Section 4.2
   launch_passA(x, n, 1, PA_STEP, 0, c.tw, st);
   launch_passB(x, n, 1, PB_MATVEC, 0, c.tw, st);
   launch_passC(x, n, 1, PC_MATVEC, 0, c.tw, st);
@@ -735,6 +744,7 @@ int ma_step_lbar_inverse(ma_plan* P, int n, const float* sigma, const double* ab
   const size_t nn = (size_t)n * n;
   HIP_TRY(hipMemcpyAsync(d.V, sigma, 4 * nn, hipMemcpyDeviceToDevice, st));
   LaunchCtx x = make_ctx(P, c);
+  x.precond = MA_PRECOND_NONE;  // the step entry points apply the operator of Section 4.2
   launch_passA(x, n, 1, PA_STEP, 0, c.tw, st);
   launch_passB(x, n, 1, PB_RECOVER, 0, c.tw, st);
   launch_passC(x, n, 1, PC_THETA_ONLY, 0, c.tw, st);
@@ -782,6 +792,7 @@ int ma_step_gmres(ma_plan* P, int n, const float* h, const float* coef, const do
       break;
     }
     LaunchCtx x = make_ctx(P, c);
+    x.precond = MA_PRECOND_NONE;  // the step entry points apply the operator of Section 4.2
     launch_passA(x, n, 1, PA_INIT, 0, c.tw, st);
     launch_cycle_body(P, cls, st);
     for (int cyc = 0; cyc < max_restarts; ++cyc) {

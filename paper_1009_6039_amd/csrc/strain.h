@@ -130,10 +130,13 @@ __global__ __launch_bounds__((Cfg<N, G>::A_BLOCK)) void k_passA(LaunchCtx c, int
     cf[l] = mode == PA_ARNOLDI ? (float)(s.Hm[(jn - 1) * (MA_MMAX + 1) + l] * s.vscale[l]) : (float)s.y[l];
   }
   const float cst = (float)s.mass_c, inv_tau = (float)(1.0 / s.tau);
+  // left scaling of the GMRES system (option): h / D with D = (a11 + a22) / (abar11 + abar22)
+  const bool scaled = mode == PA_INIT && c.precond == MA_PRECOND_DIAG;
+  const float trbar = (float)(s.abar[0] + s.abar[2]);
   {  // algorithmic bytes per point: vectors read, Krylov vector written, half spectrum written
     const bool fft = !(mode == PA_ARNOLDI && jn >= c.m);
     double b = fft ? 4.0 : 0.0;
-    if (mode == PA_INIT) b += 8.0;
+    if (mode == PA_INIT) b += scaled ? 16.0 : 8.0;
     else if (mode == PA_PLAIN || mode == PA_STEP) b += 4.0;
     else if (mode == PA_ARNOLDI) b += 4.0 * (jn + 1) + 4.0;
     else b += 4.0 * (nv + (usex ? 1 : 0));
@@ -152,6 +155,11 @@ __global__ __launch_bounds__((Cfg<N, G>::A_BLOCK)) void k_passA(LaunchCtx c, int
     if (mode == PA_INIT) {
       va = (d.r[ea] + cst) * inv_tau;
       vb = (d.r[eb] + cst) * inv_tau;
+      if (scaled) {
+        va *= trbar / (d.coef[ea] + d.coef[2 * NN + ea]);
+        vb *= trbar / (d.coef[eb] + d.coef[2 * NN + eb]);
+        nrm += va * va + vb * vb;
+      }
       V[ea] = va;
       V[eb] = vb;
     } else if (mode == PA_PLAIN || mode == PA_STEP) {
@@ -202,7 +210,7 @@ __global__ __launch_bounds__((Cfg<N, G>::A_BLOCK)) void k_passA(LaunchCtx c, int
     }
   }
 
-  if (mode == PA_ARNOLDI) {  // partial ||w'||^2, folded by k_arnoldi_finalize
+  if (mode == PA_ARNOLDI || scaled) {  // partial ||w'||^2 (or ||h / D||^2), folded per pair
     double v[1] = {(double)nrm};
     const int kinds[1] = {0};
     block_reduce<1>(v, kinds, scratch);
@@ -389,6 +397,8 @@ __global__ __launch_bounds__((Cfg<N, G>::C_BLOCK)) void k_passC(LaunchCtx c, int
 
   float* W = d.V + (long)(j + 1) * NN;
   const float* coef = d.coef;
+  const bool scaled = c.precond == MA_PRECOND_DIAG;
+  const float trbar = (float)(s.abar[0] + s.abar[2]);
   float dots[MA_MMAX + 1];
 #pragma unroll
   for (int l = 0; l <= MA_MMAX; ++l) dots[l] = 0.f;
@@ -397,10 +407,14 @@ __global__ __launch_bounds__((Cfg<N, G>::C_BLOCK)) void k_passC(LaunchCtx c, int
     const long ea = (long)(row0 + 2 * pp) * N + jj, eb = ea + N;
     const float2* L = lds + 5 * pp * N + jj;
     const float2 z0 = L[0], z1 = L[N], z2 = L[2 * N], z3 = L[3 * N], z4 = L[4 * N];
-    const float wa = coef[ea] * z0.x + 2.f * coef[NN + ea] * z1.x + coef[2 * NN + ea] * z4.x +
-                     coef[3 * NN + ea] * z0.y + coef[4 * NN + ea] * z1.y;
-    const float wb = coef[eb] * z2.x + 2.f * coef[NN + eb] * z3.x + coef[2 * NN + eb] * z4.y +
-                     coef[3 * NN + eb] * z2.y + coef[4 * NN + eb] * z3.y;
+    float wa = coef[ea] * z0.x + 2.f * coef[NN + ea] * z1.x + coef[2 * NN + ea] * z4.x +
+               coef[3 * NN + ea] * z0.y + coef[4 * NN + ea] * z1.y;
+    float wb = coef[eb] * z2.x + 2.f * coef[NN + eb] * z3.x + coef[2 * NN + eb] * z4.y +
+               coef[3 * NN + eb] * z2.y + coef[4 * NN + eb] * z3.y;
+    if (scaled) {  // left scaling by 1 / D(x), D = (a11 + a22) / (abar11 + abar22)
+      wa *= trbar / (coef[ea] + coef[2 * NN + ea]);
+      wb *= trbar / (coef[eb] + coef[2 * NN + eb]);
+    }
     W[ea] = wa;
     W[eb] = wb;
 #pragma unroll

@@ -5,7 +5,8 @@ memory and gathers minibatches):
   1. blob-density pairs at n_net x n_net (seeds 20265203 + q, disjoint from the
      benchmark's), drawn on the host by the shared input generator;
   2. solved on the GPU to rms residual 1e-8 (step-halving damping, fourth-order
-     symbol: the same fixed point, fewer iterations);
+     symbols and the diagonally scaled GMRES system: the same fixed point, fewer
+     iterations);
   3. network input (log f, log g of the mean-one densities) in BF16 and target = the fourth-order
      difference Laplacian of the solution minus log f + log g (what the linearised
      equation misses), both kept on the device;
@@ -55,7 +56,7 @@ def generate(maot, net, npairs, n, chunk=128, workers=16, tol=1e-8, log=print):
     X = torch.empty((npairs, n, n, 8), dtype=torch.bfloat16, device="cuda")
     T = torch.empty((npairs, n, n), dtype=torch.float32, device="cuda")
     plan = maot.Plan(n_max=n, batch_capacity=chunk, damping_policy="backtrack", gmres_tol=0.1,
-                     max_newton=300, symbol="fd4")
+                     max_newton=300, symbol="fd4", precond="diag")
     t0 = time.time()
     newton = []
     ok = np.zeros(npairs, dtype=bool)
@@ -113,7 +114,8 @@ def train(net, X, T, ok, epochs, batch, lr0, val_frac=0.05, seed=0, log=print):
 def evaluate(maot, net, n, count=64, log=print):
     """Newton iterations and wall time on held-out pairs from zero, from the linearised
     start (the network's output set to zero) and from the learned start, for both
-    symbols of the linear solve."""
+    ways of solving the linear equation (fd4 symbols with diagonal scaling, and the
+    paper's spectral symbols)."""
     import torch
     pairs = [W.blobs(n, W.seed_for(TRAIN_CONFIG + 1, q)) for q in range(count)]
     f = [torch.from_numpy(a).cuda() for a, _ in pairs]
@@ -122,9 +124,9 @@ def evaluate(maot, net, n, count=64, log=print):
                             dilations=net.dilations)
     lin.set_params(np.zeros(lin.count, dtype=np.float32))
     out = {}
-    for symbol in ("spectral", "fd4"):
+    for symbol, opts in (("paper", {"symbol": "spectral"}), ("fast", {"symbol": "fd4", "precond": "diag"})):
         plan = maot.Plan(n_max=n, batch_capacity=count, damping_policy="backtrack", gmres_tol=0.1, max_newton=300,
-                         symbol=symbol)
+                         **opts)
         for arm, start in (("zero", None), ("linearised", lin), ("learned", net)):
             torch.cuda.synchronize()
             t0 = time.time()

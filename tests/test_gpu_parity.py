@@ -385,3 +385,35 @@ def test_c3_mixed_batch_256_pairs(maot):
             assert err <= 2e-6, (n, err)
     finally:
         p.close()
+
+
+@pytest.mark.parametrize("symbol", ["fd4", "spectral"])
+def test_diag_scaled_solve_matches_oracle(maot, symbol):
+    # option precond = diag: the same converged potential as the oracle with the same
+    # option and as the unscaled oracle (the fixed point does not depend on it)
+    N = 128
+    f, g = W.blobs(N, W.seed_for(1, 5))
+    kw = dict(tau=1.0, damping_policy="backtrack", gmres_tol=0.1, max_newton=300, symbol=symbol)
+    ref, _, rr = ma.solve(f, g, tol=1e-10, precond="diag", **kw)
+    ref0, _, rr0 = ma.solve(f, g, tol=1e-10, **kw)
+    assert rr.status == ma.OK and rr0.status == ma.OK
+    p = maot.Plan(n_max=N, batch_capacity=2, damping_policy="backtrack", gmres_tol=0.1, max_newton=300,
+                  symbol=symbol, precond="diag")
+    q = maot.Plan(n_max=N, batch_capacity=1, damping_policy="backtrack", gmres_tol=0.1, max_newton=300,
+                  symbol=symbol)
+    try:
+        psi, _, rep = p.solve(dev(f), dev(g), damping=1.0, tol=1e-9)
+        _, _, rep0 = q.solve(dev(f), dev(g), damping=1.0, tol=1e-9)
+        psi = host(psi)
+        print("%s: diag gmres %d newton %d (oracle %d / %d); plain gmres %d" % (
+            symbol, rep["gmres_iters"], rep["newton_iters"], rr.gmres_iters, rr.newton_iters, rep0["gmres_iters"]))
+        assert rep["status"] == 0 and rep["res_rms"] <= 1e-9
+        for r in (ref, ref0):
+            assert np.max(np.abs(psi - r)) <= 1e-6 * np.max(np.abs(r))
+        assert rep["gmres_iters"] < 0.85 * rep0["gmres_iters"]
+        # batched == single, bitwise, with the option on
+        psis, _, reps = p.solve_batched([dev(f), dev(f)], [dev(g), dev(g)], damping=1.0, tol=1e-9)
+        assert np.array_equal(host(psis[0]), psi) and np.array_equal(host(psis[1]), psi)
+    finally:
+        p.close()
+        q.close()

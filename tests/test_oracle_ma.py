@@ -360,3 +360,71 @@ def test_checked_start_accepts_a_good_guess_and_survives_a_bad_one():
     bad = 3.0 * np.sin(2 * np.pi * np.arange(N) / N)[:, None] * np.ones((1, N))
     out, _, rb = ma.solve(f, g, tol=1e-10, psi0=bad)
     assert rb.status == ma.OK and np.max(np.abs(out - ref)) < 1e-9
+
+
+# --- option precond = "diag": left scaling by the relative trace of the coefficients ---
+
+def _blob_eval(N, seed):
+    from paper_1009_6039_amd import workloads as W
+    f, g = W.blobs(N, W.seed_for(1, seed))
+    prob = ma.Problem(f, g)
+    x = np.arange(N) / N
+    X1, X2 = np.meshgrid(x, x, indexing="ij")
+    u = 0.004 * np.sin(2 * np.pi * X1 + 0.3) * np.cos(2 * np.pi * X2)
+    return prob, ma.evaluate(u, prob)
+
+
+def test_diag_scale_is_one_for_the_laplacian():
+    N = 16
+    prob = ma.Problem(np.ones((N, N)) + 0.1 * np.cos(2 * np.pi * np.arange(N) / N)[:, None], np.ones((N, N)))
+    ev = ma.evaluate(np.zeros((N, N)), prob)
+    coef = ma.coefficients(ev, 0)
+    assert np.allclose(ma.diag_scale(coef, ma.averaged(coef)), 1.0, atol=1e-14)
+    t1, i1 = ma.newton_direction(ev, prob, 1.0, 0, 10, 1e-8, 20, "spectral", "none")
+    t2, i2 = ma.newton_direction(ev, prob, 1.0, 0, 10, 1e-8, 20, "spectral", "diag")
+    assert i1 == i2 and np.allclose(t1, t2, atol=1e-12 * np.max(np.abs(t1)))
+
+
+@pytest.mark.parametrize("symbol", ["spectral", "fd4"])
+def test_diag_scaled_direction_equals_plain_direction_when_solved_exactly(symbol):
+    # D^{-1} A sigma = D^{-1} h has the solution of A sigma = h: scaling only one side
+    # (or using a different D on the two sides) breaks this.  The right-hand side is
+    # taken in the range of A (h = A v), where both systems are solvable exactly.
+    import copy
+    prob, ev = _blob_eval(32, 2)
+    coef = ma.coefficients(ev, 0)
+    rho = ma.symbol(ma.averaged(coef), 32, symbol)
+    v = np.random.default_rng(7).standard_normal((32, 32))
+    ev2 = copy.copy(ev)
+    ev2.r = ma.strain_apply(v, coef, rho, symbol)
+    expect = ma.lbar_inverse(v, rho)
+    for pc in ("none", "diag"):
+        t, _ = ma.newton_direction(ev2, prob, 1.0, 0, 40, 1e-11, 40, symbol, pc)
+        assert np.max(np.abs(t - expect)) <= 1e-8 * np.max(np.abs(expect)), pc
+
+
+def test_diag_scaled_solve_reaches_the_same_potential_with_fewer_iterations():
+    from paper_1009_6039_amd import workloads as W
+    f, g = W.blobs(64, W.seed_for(1, 4))
+    kw = dict(tol=1e-10, damping_policy="backtrack", gmres_tol=0.1, max_newton=300, symbol="fd4")
+    p1, _, r1 = ma.solve(f, g, **kw)
+    p2, _, r2 = ma.solve(f, g, precond="diag", **kw)
+    assert r1.status == ma.OK and r2.status == ma.OK
+    assert np.max(np.abs(p1 - p2)) <= 1e-8 * np.max(np.abs(p1))
+    assert r2.gmres_iters < 0.8 * r1.gmres_iters, (r1.gmres_iters, r2.gmres_iters)
+    with pytest.raises(ValueError):
+        ma.solve(f, g, precond="jacobi")
+
+
+def test_boundary_fraction_keeps_the_fixed_point():
+    # the fraction-to-the-boundary rule only changes which steps are accepted: a strict
+    # fraction halves more often and reaches the same potential; 0 is the plain rule
+    from paper_1009_6039_amd import workloads as W
+    f, g = W.blobs(64, W.seed_for(1, 6))
+    kw = dict(tol=1e-10, damping_policy="backtrack", gmres_tol=0.1, max_newton=300, symbol="fd4")
+    results = [ma.solve(f, g, boundary_frac=b, **kw) for b in (0.0, 0.1, 0.8)]
+    assert all(r.status == ma.OK for _, _, r in results)
+    ref = results[0][0]
+    for psi, _, _ in results[1:]:
+        assert np.max(np.abs(psi - ref)) <= 1e-8 * np.max(np.abs(ref))
+    assert results[2][2].backtracks >= results[0][2].backtracks
