@@ -21,8 +21,11 @@ void cnn_adam(float* p, const float* g, float* m, float* v, int count, float lr,
               float eps, hipStream_t st);
 void cnn_target(const double* u, const double* f, const double* g, int batch, int n, double* part, double* means,
                 float* out, hipStream_t st);
-void cnn_add_log_ratio(const float* c, const double* f, const double* g, int n, double* part, double* means,
-                       float* out, hipStream_t st);
-void cnn_restrict(const double* x, int n_coarse, double* y, hipStream_t st);
-void cnn_prolong(const float* x, int n_coarse, float* y, hipStream_t st);
-void cnn_to_double(const float* x, size_t count, double* y, hipStream_t st);
+// warm start of a batch: f, g, out are device arrays of the pairs' device pointers
+void cnn_gather_inputs(const double* const* f, const double* const* g, int batch, int n, int nr, double* fx,
+                       double* gx, hipStream_t st);
+void cnn_full_means(const double* const* f, const double* const* g, int batch, int n, double* part, double* means,
+                    hipStream_t st);
+void cnn_head_input(const float* c, const double* const* f, const double* const* g, const double* means, int batch,
+                    int n, int nr, float* out, hipStream_t st);
+void cnn_scatter_double(const float* x, int batch, size_t nn, double* const* out, hipStream_t st);

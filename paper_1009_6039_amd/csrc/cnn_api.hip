@@ -45,7 +45,7 @@ struct ma_cnn {
   long step = 0;
   std::vector<Buf> wfwd, wbwd;     // packed BF16 weights per layer
   std::vector<Buf> act;            // h_1 .. h_{L-1}, BF16 32 channels
-  Buf c, dz_last, dzA, dzB, part, partb, lpart, loss, means, mpart, fx, gx, cbuf, cup, clin, theta;
+  Buf c, dz_last, dzA, dzB, part, partb, lpart, loss, means, mpart, fx, gx, cbuf, clin, theta, ptrs;
   ma_plan* head = nullptr;         // fourth-order inverse Laplacian for the warm-start head
   int head_n = 0;
 };
@@ -199,7 +199,7 @@ void ma_cnn_destroy(ma_cnn* N) {
   for (auto& b : N->wbwd) b.release();
   for (auto& b : N->act) b.release();
   for (Buf* b : {&N->c, &N->dz_last, &N->dzA, &N->dzB, &N->part, &N->partb, &N->lpart, &N->loss, &N->means, &N->mpart, &N->fx,
-                 &N->gx, &N->cbuf, &N->cup, &N->clin, &N->theta})
+                 &N->gx, &N->cbuf, &N->clin, &N->theta, &N->ptrs})
     b->release();
   if (N->head) ma_plan_destroy(N->head);
   delete N;
@@ -300,47 +300,43 @@ int ma_cnn_warm_start(ma_cnn* N, int npairs, int n, const double* const* f, cons
   }
   const int B = N->max_batch;
   const size_t pr = (size_t)nr * nr, pn = (size_t)n * n;
+  const int nbatch = (npairs + B - 1) / B;
   TRY(N->fx.ensure((size_t)B * pr * 8));
   TRY(N->gx.ensure((size_t)B * pr * 8));
   TRY(N->cbuf.ensure((size_t)B * pr * 2 * 8));  // network input (8 BF16 channels = 16 bytes per pixel)
-  TRY(N->cup.ensure(pn * 4));
   TRY(N->clin.ensure((size_t)B * pn * 4));
   TRY(N->theta.ensure((size_t)B * pn * 4));
   TRY(N->means.ensure((size_t)2 * B * 8));
   TRY(N->mpart.ensure((size_t)2 * B * CNN_MEAN_PARTS * 8));
+  TRY(N->ptrs.ensure((size_t)nbatch * 3 * B * sizeof(void*)));  // one region per batch: no reuse in a call
   const double lap[5] = {1.0, 0.0, 1.0, 0.0, 0.0};  // averaged operator = the Laplacian
+  std::vector<const void*> hp((size_t)nbatch * 3 * B, nullptr);
+  for (int q = 0; q < npairs; ++q) {
+    const size_t base = (size_t)(q / B) * 3 * B, k = q % B;
+    hp[base + k] = f[q];
+    hp[base + B + k] = g[q];
+    hp[base + 2 * B + k] = psi0[q];
+  }
+  HIPTRY(hipMemcpyAsync(N->ptrs.p, hp.data(), hp.size() * sizeof(void*), hipMemcpyHostToDevice, st));
   std::vector<const float*> sig(B);
   std::vector<float*> th(B);
   for (int q0 = 0; q0 < npairs; q0 += B) {
     const int b = (npairs - q0 < B) ? npairs - q0 : B;
-    for (int k = 0; k < b; ++k) {
-      double* fd = (double*)N->fx.p + (size_t)k * pr;
-      double* gd = (double*)N->gx.p + (size_t)k * pr;
-      if (n == nr) {
-        HIPTRY(hipMemcpyAsync(fd, f[q0 + k], pr * 8, hipMemcpyDeviceToDevice, st));
-        HIPTRY(hipMemcpyAsync(gd, g[q0 + k], pr * 8, hipMemcpyDeviceToDevice, st));
-      } else {
-        cnn_restrict(f[q0 + k], nr, fd, st);
-        cnn_restrict(g[q0 + k], nr, gd, st);
-      }
-    }
+    const void* const* pb = (const void* const*)N->ptrs.p + (size_t)(q0 / B) * 3 * B;
+    const double* const* fp = (const double* const*)pb;
+    const double* const* gp = (const double* const*)(pb + B);
+    double* const* op = (double* const*)(pb + 2 * B);
+    cnn_gather_inputs(fp, gp, b, n, nr, (double*)N->fx.p, (double*)N->gx.p, st);
     TRY(ma_cnn_prepare_input(N, (const double*)N->fx.p, (const double*)N->gx.p, b, N->cbuf.p, stream));
     forward(N, N->cbuf.p, b, st);
+    cnn_full_means(fp, gp, b, n, (double*)N->mpart.p, (double*)N->means.p, st);
+    cnn_head_input((const float*)N->c.p, fp, gp, (const double*)N->means.p, b, n, nr, (float*)N->clin.p, st);
     for (int k = 0; k < b; ++k) {
-      const float* ck = (const float*)N->c.p + (size_t)k * pr;
-      const float* src = ck;
-      if (n != nr) {
-        cnn_prolong(ck, nr, (float*)N->cup.p, st);
-        src = (const float*)N->cup.p;
-      }
-      float* lk = (float*)N->clin.p + (size_t)k * pn;
-      cnn_add_log_ratio(src, f[q0 + k], g[q0 + k], n, (double*)N->mpart.p + (size_t)2 * k * CNN_MEAN_PARTS,
-                        (double*)N->means.p + 2 * k, lk, st);
-      sig[k] = lk;
+      sig[k] = (const float*)N->clin.p + (size_t)k * pn;
       th[k] = (float*)N->theta.p + (size_t)k * pn;
     }
     TRY(plan_lbar_inverse_many(N->head, n, b, sig.data(), lap, th.data(), st));
-    for (int k = 0; k < b; ++k) cnn_to_double(th[k], pn, psi0[q0 + k], st);
+    cnn_scatter_double((const float*)N->theta.p, b, pn, op, st);
   }
   return hipGetLastError() == hipSuccess ? MA_OK : MA_EHIP;
 }

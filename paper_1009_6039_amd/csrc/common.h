@@ -13,6 +13,7 @@
 #define MA_RES_TY 16      // residual-kernel tile height (rows)
 #define MA_NPART_RES 16   // partial sums per residual block
 #define MA_BLOCK 256
+#define MA_SUMMARY_INTS 16  // host-loop counters written by the summary kernel
 
 // per-pair phase of the Newton loop
 enum : int {

@@ -236,11 +236,9 @@ __global__ void k_pack(const float* __restrict__ Wm, int Co, int Ci, int flip, i
 // means of f and g per sample: MEAN_BLOCKS partial sums per field (each a contiguous
 // chunk, coalesced), then a fixed-order fold, so the result does not depend on timing
 constexpr int MEAN_BLOCKS = CNN_MEAN_PARTS;
-__global__ void k_mean_partials(const double* __restrict__ f, const double* __restrict__ g, int n,
-                                double* __restrict__ part) {
-  const int field = blockIdx.y, s = field >> 1;
-  const double* x = ((field & 1) ? g : f) + (size_t)s * n * n;
-  const size_t total = (size_t)n * n, chunk = (total + MEAN_BLOCKS - 1) / MEAN_BLOCKS;
+// sum of chunk blockIdx.x of x[0..total) (256 threads; thread 0 holds the result)
+__device__ double chunk_sum(const double* __restrict__ x, size_t total) {
+  const size_t chunk = (total + MEAN_BLOCKS - 1) / MEAN_BLOCKS;
   const size_t lo = blockIdx.x * chunk, hi = lo + chunk < total ? lo + chunk : total;
   __shared__ double red[256];
   double a = 0.0;
@@ -251,7 +249,15 @@ __global__ void k_mean_partials(const double* __restrict__ f, const double* __re
     if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) part[(size_t)field * MEAN_BLOCKS + blockIdx.x] = red[0];
+  return red[0];
+}
+
+__global__ void k_mean_partials(const double* __restrict__ f, const double* __restrict__ g, int n,
+                                double* __restrict__ part) {
+  const int field = blockIdx.y, s = field >> 1;
+  const double* x = ((field & 1) ? g : f) + (size_t)s * n * n;
+  const double v = chunk_sum(x, (size_t)n * n);
+  if (threadIdx.x == 0) part[(size_t)field * MEAN_BLOCKS + blockIdx.x] = v;
 }
 
 __global__ void k_mean_fold(const double* __restrict__ part, int nfields, double inv_count,
@@ -334,40 +340,64 @@ __global__ void k_target(const double* __restrict__ u, const double* __restrict_
   out[i] = (float)t;
 }
 
-// c + log(f / mean f) - log(g / mean g) for one pair (the linearised part of the warm start)
-__global__ void k_add_log_ratio(const float* __restrict__ c, const double* __restrict__ f,
-                                const double* __restrict__ g, const double* __restrict__ means, int n,
-                                float* __restrict__ out) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (size_t)n * n) return;
-  out[i] = (float)((double)c[i] + log(f[i] / means[0]) - log(g[i] / means[1]));
-}
+// The warm start of a batch of pairs, every launch covering all of them
+// (blockIdx.y = pair; the pairs' buffers come as device arrays of pointers).
 
-// full-weighting restriction 2n -> n (node-centred: fine node 2a maps to coarse node a)
-__global__ void k_restrict(const double* __restrict__ x, int n, double* __restrict__ y) {
+// densities at the network's resolution: copied (n = n_net) or restricted by full
+// weighting (n = 2 n_net; fine node 2a maps to coarse node a); blockIdx.z = 0 f, 1 g
+__global__ void k_gather_inputs(const double* const* __restrict__ f, const double* const* __restrict__ g, int n,
+                                int nr, double* __restrict__ fx, double* __restrict__ gx) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n * n) return;
-  const int a = i / n, b = i % n, m = 2 * n;
+  if (i >= nr * nr) return;
+  const int k = blockIdx.y;
+  const double* x = (blockIdx.z ? g : f)[k];
+  double* y = (blockIdx.z ? gx : fx) + (size_t)k * nr * nr;
+  if (n == nr) {
+    y[i] = x[i];
+    return;
+  }
+  const int a = i / nr, b = i % nr;
   const double w[3] = {0.25, 0.5, 0.25};
   double s = 0.0;
   for (int p = -1; p <= 1; ++p)
-    for (int q = -1; q <= 1; ++q) s += w[p + 1] * w[q + 1] * x[(size_t)wrap(2 * a + p, m) * m + wrap(2 * b + q, m)];
+    for (int q = -1; q <= 1; ++q) s += w[p + 1] * w[q + 1] * x[(size_t)wrap(2 * a + p, n) * n + wrap(2 * b + q, n)];
   y[i] = s;
 }
 
-// bilinear prolongation n -> 2n (periodic)
-__global__ void k_prolong(const float* __restrict__ x, int n, float* __restrict__ y) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int m = 2 * n;
-  if (i >= m * m) return;
-  const int r = i / m, c = i % m;
-  const int a0 = r >> 1, b0 = c >> 1, a1 = wrap(a0 + (r & 1), n), b1 = wrap(b0 + (c & 1), n);
-  y[i] = 0.25f * (x[a0 * n + b0] + x[a1 * n + b0] + x[a0 * n + b1] + x[a1 * n + b1]);
+// partial sums of the full-resolution densities (folded by k_mean_fold)
+__global__ void k_mean_partials_ptr(const double* const* __restrict__ f, const double* const* __restrict__ g, int n,
+                                    double* __restrict__ part) {
+  const int field = blockIdx.y;
+  const double* x = ((field & 1) ? g : f)[field >> 1];
+  const double v = chunk_sum(x, (size_t)n * n);
+  if (threadIdx.x == 0) part[(size_t)field * MEAN_BLOCKS + blockIdx.x] = v;
 }
 
-__global__ void k_to_double(const float* __restrict__ x, size_t count, double* __restrict__ y) {
+// the head's input at full resolution: c (prolonged bilinearly, periodic, if n = 2 n_net)
+// plus log(f / mean f) - log(g / mean g)
+__global__ void k_head_input(const float* __restrict__ c, const double* const* __restrict__ f,
+                             const double* const* __restrict__ g, const double* __restrict__ means, int n, int nr,
+                             float* __restrict__ out) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count) y[i] = (double)x[i];
+  if (i >= (size_t)n * n) return;
+  const int k = blockIdx.y;
+  const float* ck = c + (size_t)k * nr * nr;
+  float cv;
+  if (n == nr) {
+    cv = ck[i];
+  } else {
+    const int r = (int)(i / n), col = (int)(i % n);
+    const int a0 = r >> 1, b0 = col >> 1, a1 = wrap(a0 + (r & 1), nr), b1 = wrap(b0 + (col & 1), nr);
+    cv = 0.25f * (ck[a0 * nr + b0] + ck[a1 * nr + b0] + ck[a0 * nr + b1] + ck[a1 * nr + b1]);
+  }
+  out[(size_t)k * n * n + i] =
+      (float)((double)cv + log(f[k][i] / means[2 * k]) - log(g[k][i] / means[2 * k + 1]));
+}
+
+// the pairs' potentials (contiguous FP32) into the callers' FP64 outputs
+__global__ void k_scatter_double(const float* __restrict__ x, size_t nn, double* const* __restrict__ out) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nn) out[blockIdx.y][i] = (double)x[(size_t)blockIdx.y * nn + i];
 }
 
 inline unsigned nblocks(size_t count, int bs) { return (unsigned)((count + bs - 1) / bs); }
@@ -451,21 +481,25 @@ void cnn_target(const double* u, const double* f, const double* g, int batch, in
                      out);
 }
 
-void cnn_add_log_ratio(const float* c, const double* f, const double* g, int n, double* part, double* means,
-                       float* out, hipStream_t st) {
-  cnn_means(f, g, 1, n, part, means, st);
-  hipLaunchKernelGGL(k_add_log_ratio, dim3(nblocks((size_t)n * n, 256)), dim3(256), 0, st, c, f, g, means, n, out);
+void cnn_gather_inputs(const double* const* f, const double* const* g, int batch, int n, int nr, double* fx,
+                       double* gx, hipStream_t st) {
+  hipLaunchKernelGGL(k_gather_inputs, dim3(nblocks((size_t)nr * nr, 256), batch, 2), dim3(256), 0, st, f, g, n, nr,
+                     fx, gx);
 }
 
-void cnn_restrict(const double* x, int n_coarse, double* y, hipStream_t st) {
-  hipLaunchKernelGGL(k_restrict, dim3(nblocks((size_t)n_coarse * n_coarse, 256)), dim3(256), 0, st, x, n_coarse, y);
+void cnn_full_means(const double* const* f, const double* const* g, int batch, int n, double* part, double* means,
+                    hipStream_t st) {
+  hipLaunchKernelGGL(k_mean_partials_ptr, dim3(MEAN_BLOCKS, 2 * batch), dim3(256), 0, st, f, g, n, part);
+  hipLaunchKernelGGL(k_mean_fold, dim3(nblocks(2 * batch, 64)), dim3(64), 0, st, part, 2 * batch,
+                     1.0 / ((double)n * n), means);
 }
 
-void cnn_prolong(const float* x, int n_coarse, float* y, hipStream_t st) {
-  const size_t m = 2 * (size_t)n_coarse;
-  hipLaunchKernelGGL(k_prolong, dim3(nblocks(m * m, 256)), dim3(256), 0, st, x, n_coarse, y);
+void cnn_head_input(const float* c, const double* const* f, const double* const* g, const double* means, int batch,
+                    int n, int nr, float* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_head_input, dim3(nblocks((size_t)n * n, 256), batch), dim3(256), 0, st, c, f, g, means, n, nr,
+                     out);
 }
 
-void cnn_to_double(const float* x, size_t count, double* y, hipStream_t st) {
-  hipLaunchKernelGGL(k_to_double, dim3(nblocks(count, 256)), dim3(256), 0, st, x, count, y);
+void cnn_scatter_double(const float* x, int batch, size_t nn, double* const* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_scatter_double, dim3(nblocks(nn, 256), batch), dim3(256), 0, st, x, nn, out);
 }

@@ -392,18 +392,21 @@ __global__ __launch_bounds__(MA_BLOCK) void k_outputs(LaunchCtx c) {
 }
 
 // counts pairs per phase, pending restarts and invalid inputs for the host loop
+// counts for the host loop: [0..5] pairs per phase, [6] pairs to restart GMRES,
+// [7] invalid inputs, [8] pairs inside a GMRES cycle (16 slots written)
 __global__ __launch_bounds__(256) void k_summary(const PairState* st, const int* ids, int npairs, int* out) {
-  __shared__ int cnt[8];
-  if (threadIdx.x < 8) cnt[threadIdx.x] = 0;
+  __shared__ int cnt[MA_SUMMARY_INTS];
+  if (threadIdx.x < MA_SUMMARY_INTS) cnt[threadIdx.x] = 0;
   __syncthreads();
   for (int q = threadIdx.x; q < npairs; q += blockDim.x) {
     const PairState& s = st[ids[q]];
     atomicAdd(&cnt[s.phase], 1);  // phases are 0..5
     if (s.phase == PH_SOLVE && s.gm_restart) atomicAdd(&cnt[6], 1);
     if (!s.valid) atomicAdd(&cnt[7], 1);
+    if (s.phase == PH_SOLVE && s.gm_running) atomicAdd(&cnt[8], 1);
   }
   __syncthreads();
-  if (threadIdx.x < 8) out[threadIdx.x] = cnt[threadIdx.x];
+  if (threadIdx.x < MA_SUMMARY_INTS) out[threadIdx.x] = cnt[threadIdx.x];
 }
 
 // Synthetic fields for timing launch geometries: smooth positive densities, a small

@@ -48,8 +48,11 @@ struct ma_plan {
   PairState* d_state = nullptr;
   int* d_ids = nullptr;
   int pairs_cap = 0;
-  int* d_summary = nullptr;
+  // host-loop counters: 4 slots of MA_SUMMARY_INTS (the synchronous read, then a ring
+  // of 3) in coherent pinned host memory that the summary kernel writes directly
   int* h_summary = nullptr;
+  int* d_summary = nullptr;  // the device's address of h_summary
+  hipEvent_t ring_ev[3] = {nullptr, nullptr, nullptr};
   std::map<int, float2*> tw;
   std::map<std::pair<int, int>, float2*> mt;  // (n, symbol) -> derivative multipliers
   std::map<int, Tune> tune;                   // n -> launch-geometry variants (absent: defaults)
@@ -311,20 +314,36 @@ void L_C(ma_plan* P, const Class& c, int mode, int j, hipStream_t st) {
 
 int read_summary(ma_plan* P, int npairs, hipStream_t st) {
   launch_summary(P->d_state, P->d_ids, npairs, P->d_summary, st);
-  HIP_TRY(hipMemcpyAsync(P->h_summary, P->d_summary, sizeof(int) * 8, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   prof_flush(P);
   return MA_OK;
 }
 
-void launch_cycle_body(ma_plan* P, const std::vector<Class>& cls, hipStream_t st) {
+// The iterations of one GMRES cycle.  From the third on, a summary of the state is
+// queued after each iteration, and the host reads the one queued two iterations
+// earlier (so the device queue never drains while the host waits): once no pair is
+// inside the cycle, the remaining iterations, which would all exit at once, are not
+// launched.  At most two such iterations are queued.
+int launch_cycle_body(ma_plan* P, const std::vector<Class>& cls, int npairs, hipStream_t st) {
   const int m = P->opt.gmres_m;
-  for (int j = 0; j < m; ++j)
+  constexpr int LAG = 2, FIRST = 2;
+  for (int j = 0; j < m; ++j) {
     for (const Class& c : cls) {
       L_B(P, c, PB_MATVEC, j, st);
       L_C(P, c, PC_MATVEC, j, st);
       L_A(P, c, PA_ARNOLDI, j + 1, st);
     }
+    if (j + 1 >= m || j < FIRST) continue;
+    const int slot = j % (LAG + 1);
+    launch_summary(P->d_state, P->d_ids, npairs, P->d_summary + MA_SUMMARY_INTS * (1 + slot), st);
+    HIP_TRY(hipEventRecord(P->ring_ev[slot], st));
+    if (j >= FIRST + LAG) {
+      const int old = (j - LAG) % (LAG + 1);
+      HIP_TRY(hipEventSynchronize(P->ring_ev[old]));
+      if (P->h_summary[MA_SUMMARY_INTS * (1 + old) + 8] == 0) break;
+    }
+  }
+  return MA_OK;
 }
 
 // the whole damped Newton loop for the pairs already described in P->h_desc
@@ -348,7 +367,8 @@ int run_solver(ma_plan* P, int npairs, double damping, double tol, hipStream_t s
     if (n_solve == 0 && n_update == 0) break;  // every pair is done
     if (n_solve > 0) {
       for (const Class& c : cls) L_A(P, c, PA_INIT, 0, st);
-      launch_cycle_body(P, cls, st);
+      e = launch_cycle_body(P, cls, npairs, st);
+      if (e) return e;
       for (int cyc = 0; cyc < P->opt.gmres_max_restarts; ++cyc) {
         e = read_summary(P, npairs, st);
         if (e) return e;
@@ -357,7 +377,8 @@ int run_solver(ma_plan* P, int npairs, double damping, double tol, hipStream_t s
           launch_restart(make_ctx(P, c), c.n, (int)c.ids.size(), st);
           L_A(P, c, PA_PLAIN, 0, st);
         }
-        launch_cycle_body(P, cls, st);
+        e = launch_cycle_body(P, cls, npairs, st);
+      if (e) return e;
       }
       for (const Class& c : cls) {
         L_A(P, c, PA_RECOVER, 0, st);
@@ -489,8 +510,12 @@ int ma_plan_create(int n_max, int batch_capacity, const ma_options* opt, ma_plan
   P->cap = batch_capacity;
   if (hipMalloc(&P->d_prof, sizeof(unsigned long long)) != hipSuccess ||
       hipMemset(P->d_prof, 0, sizeof(unsigned long long)) != hipSuccess ||
-      hipMalloc(&P->d_summary, sizeof(int) * 8) != hipSuccess ||
-      hipHostMalloc(&P->h_summary, sizeof(int) * 8, hipHostMallocDefault) != hipSuccess) {
+      hipHostMalloc(&P->h_summary, sizeof(int) * 4 * MA_SUMMARY_INTS,
+                    hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+      hipHostGetDevicePointer((void**)&P->d_summary, P->h_summary, 0) != hipSuccess ||
+      hipEventCreateWithFlags(&P->ring_ev[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&P->ring_ev[1], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&P->ring_ev[2], hipEventDisableTiming) != hipSuccess) {
     ma_plan_destroy(P);
     return MA_ENOMEM;
   }
@@ -510,8 +535,9 @@ void ma_plan_destroy(ma_plan* P) {
   if (P->d_desc) hipFree(P->d_desc);
   if (P->d_state) hipFree(P->d_state);
   if (P->d_ids) hipFree(P->d_ids);
-  if (P->d_summary) hipFree(P->d_summary);
   if (P->h_summary) hipHostFree(P->h_summary);
+  for (hipEvent_t e : P->ring_ev)
+    if (e) hipEventDestroy(e);
   for (auto& kv : P->tw) hipFree(kv.second);
   for (auto& kv : P->mt) hipFree(kv.second);
   for (hipEvent_t e : P->ev) hipEventDestroy(e);
@@ -769,6 +795,7 @@ int ma_step_gmres(ma_plan* P, int n, const float* h, const float* coef, const do
   P->opt.gmres_m = m;
   P->opt.gmres_max_restarts = max_restarts;
   P->opt.gmres_tol = tol;
+  P->opt.precond = MA_PRECOND_NONE;  // the operator of Section 4.2
   PairState s = step_state(abar);
   s.bnorm = bn;
   s.gm_target = tol * bn;
@@ -794,13 +821,13 @@ int ma_step_gmres(ma_plan* P, int n, const float* h, const float* coef, const do
     LaunchCtx x = make_ctx(P, c);
     x.precond = MA_PRECOND_NONE;  // the step entry points apply the operator of Section 4.2
     launch_passA(x, n, 1, PA_INIT, 0, c.tw, st);
-    launch_cycle_body(P, cls, st);
+    if ((rc = launch_cycle_body(P, cls, 1, st))) break;
     for (int cyc = 0; cyc < max_restarts; ++cyc) {
       if ((rc = read_summary(P, 1, st))) break;
       if (P->h_summary[6] == 0) break;
       launch_restart(x, n, 1, st);
       launch_passA(x, n, 1, PA_PLAIN, 0, c.tw, st);
-      launch_cycle_body(P, cls, st);
+      if ((rc = launch_cycle_body(P, cls, 1, st))) break;
     }
     if (rc) break;
     launch_passA(x, n, 1, PA_RECOVER, 0, c.tw, st);
