@@ -147,45 +147,78 @@ __global__ __launch_bounds__((Cfg<N, G>::A_BLOCK)) void k_passA(LaunchCtx c, int
   const int row0 = 2 * blockIdx.x * PPB;
   float* V = d.V;
   float* Vj = V + (long)jn * NN;
+  // The thread's points first (their values in registers), then the Krylov vectors
+  // one at a time with all of the thread's loads of that vector in flight together.
+  constexpr int PER = (PPB * N + BLOCK - 1) / BLOCK;
+  constexpr bool FULL = (PPB * N) % BLOCK == 0;
+  float va[PER], vb[PER];
+  int ea_[PER];  // offset of the first row's point (n * n < 2^31); a point past the end
+                 // reads the block's first point (in bounds) and is never stored
   float nrm = 0.f;
-  for (int e = threadIdx.x; e < PPB * N; e += BLOCK) {
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = threadIdx.x + q * BLOCK;
+    va[q] = vb[q] = 0.f;
+    ea_[q] = row0 * N;
+    if (!FULL && e >= PPB * N) continue;
     const int pp = e / N, jj = e % N;
-    const long ea = (long)(row0 + 2 * pp) * N + jj, eb = ea + N;
-    float va, vb;
+    const int ea = (row0 + 2 * pp) * N + jj, eb = ea + N;
+    ea_[q] = ea;
     if (mode == PA_INIT) {
-      va = (d.r[ea] + cst) * inv_tau;
-      vb = (d.r[eb] + cst) * inv_tau;
+      va[q] = (d.r[ea] + cst) * inv_tau;
+      vb[q] = (d.r[eb] + cst) * inv_tau;
       if (scaled) {
-        va *= trbar / (d.coef[ea] + d.coef[2 * NN + ea]);
-        vb *= trbar / (d.coef[eb] + d.coef[2 * NN + eb]);
-        nrm += va * va + vb * vb;
+        va[q] *= trbar / (d.coef[ea] + d.coef[2 * NN + ea]);
+        vb[q] *= trbar / (d.coef[eb] + d.coef[2 * NN + eb]);
       }
-      V[ea] = va;
-      V[eb] = vb;
     } else if (mode == PA_PLAIN || mode == PA_STEP) {
-      va = V[ea];
-      vb = V[eb];
+      va[q] = V[ea];
+      vb[q] = V[eb];
     } else if (mode == PA_ARNOLDI) {
-      va = Vj[ea];
-      vb = Vj[eb];
-      for (int l = 0; l < nv; ++l) {
-        const float* Vl = V + (long)l * NN;
-        va -= cf[l] * Vl[ea];
-        vb -= cf[l] * Vl[eb];
-      }
-      Vj[ea] = va;
-      Vj[eb] = vb;
-      nrm += va * va + vb * vb;
+      va[q] = Vj[ea];
+      vb[q] = Vj[eb];
     } else {  // PA_RECOVER
-      va = usex ? d.x[ea] : 0.f;
-      vb = usex ? d.x[eb] : 0.f;
-      for (int l = 0; l < nv; ++l) {
-        const float* Vl = V + (long)l * NN;
-        va += cf[l] * Vl[ea];
-        vb += cf[l] * Vl[eb];
+      va[q] = usex ? d.x[ea] : 0.f;
+      vb[q] = usex ? d.x[eb] : 0.f;
+    }
+  }
+  if (mode == PA_ARNOLDI) {
+    for (int l = 0; l < nv; ++l) {
+      const float* Vl = V + (long)l * NN;
+      const float cl = cf[l];
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        va[q] -= cl * Vl[ea_[q]];
+        vb[q] -= cl * Vl[ea_[q] + N];
       }
     }
-    lds[pp * N + jj] = make_float2(va, vb);
+  } else if (mode == PA_RECOVER) {
+    for (int l = 0; l < nv; ++l) {
+      const float* Vl = V + (long)l * NN;
+      const float cl = cf[l];
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        va[q] += cl * Vl[ea_[q]];
+        vb[q] += cl * Vl[ea_[q] + N];
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = threadIdx.x + q * BLOCK;
+    if (!FULL && e >= PPB * N) continue;
+    const int pp = e / N, jj = e % N;
+    const int ea = ea_[q], eb = ea + N;
+    if (mode == PA_INIT) {
+      if (scaled) nrm += va[q] * va[q] + vb[q] * vb[q];
+      V[ea] = va[q];
+      V[eb] = vb[q];
+    } else if (mode == PA_ARNOLDI) {
+      Vj[ea] = va[q];
+      Vj[eb] = vb[q];
+      nrm += va[q] * va[q] + vb[q] * vb[q];
+    }
+    lds[pp * N + jj] = make_float2(va[q], vb[q]);
   }
 
   if (!(mode == PA_ARNOLDI && jn >= c.m)) {
@@ -399,39 +432,47 @@ __global__ __launch_bounds__((Cfg<N, G>::C_BLOCK)) void k_passC(LaunchCtx c, int
   const float* coef = d.coef;
   const bool scaled = c.precond == MA_PRECOND_DIAG;
   const float trbar = (float)(s.abar[0] + s.abar[2]);
-  float dots[MA_MMAX + 1];
+  // w at the thread's points, then the inner products <w, v_l> one Krylov vector at a
+  // time with all of the thread's loads of v_l in flight together
+  constexpr int PER = (PPB * N + BLOCK - 1) / BLOCK;
+  constexpr bool FULL = (PPB * N) % BLOCK == 0;
+  float wa[PER], wb[PER];
+  int ea_[PER];  // offset of the first row's point; a point past the end reads the
+                 // block's first point (in bounds) with weight zero
 #pragma unroll
-  for (int l = 0; l <= MA_MMAX; ++l) dots[l] = 0.f;
-  for (int e = threadIdx.x; e < PPB * N; e += BLOCK) {
+  for (int q = 0; q < PER; ++q) {
+    const int e = threadIdx.x + q * BLOCK;
+    ea_[q] = row0 * N;
+    wa[q] = wb[q] = 0.f;
+    if (!FULL && e >= PPB * N) continue;
     const int pp = e / N, jj = e % N;
-    const long ea = (long)(row0 + 2 * pp) * N + jj, eb = ea + N;
+    const int ea = (row0 + 2 * pp) * N + jj, eb = ea + N;
+    ea_[q] = ea;
     const float2* L = lds + 5 * pp * N + jj;
     const float2 z0 = L[0], z1 = L[N], z2 = L[2 * N], z3 = L[3 * N], z4 = L[4 * N];
-    float wa = coef[ea] * z0.x + 2.f * coef[NN + ea] * z1.x + coef[2 * NN + ea] * z4.x +
-               coef[3 * NN + ea] * z0.y + coef[4 * NN + ea] * z1.y;
-    float wb = coef[eb] * z2.x + 2.f * coef[NN + eb] * z3.x + coef[2 * NN + eb] * z4.y +
-               coef[3 * NN + eb] * z2.y + coef[4 * NN + eb] * z3.y;
+    float a = coef[ea] * z0.x + 2.f * coef[NN + ea] * z1.x + coef[2 * NN + ea] * z4.x +
+              coef[3 * NN + ea] * z0.y + coef[4 * NN + ea] * z1.y;
+    float b = coef[eb] * z2.x + 2.f * coef[NN + eb] * z3.x + coef[2 * NN + eb] * z4.y +
+              coef[3 * NN + eb] * z2.y + coef[4 * NN + eb] * z3.y;
     if (scaled) {  // left scaling by 1 / D(x), D = (a11 + a22) / (abar11 + abar22)
-      wa *= trbar / (coef[ea] + coef[2 * NN + ea]);
-      wb *= trbar / (coef[eb] + coef[2 * NN + eb]);
+      a *= trbar / (coef[ea] + coef[2 * NN + ea]);
+      b *= trbar / (coef[eb] + coef[2 * NN + eb]);
     }
-    W[ea] = wa;
-    W[eb] = wb;
-#pragma unroll
-    for (int l = 0; l <= MA_MMAX; ++l)
-      if (l <= j) {
-        const float* Vl = d.V + (long)l * NN;
-        dots[l] += wa * Vl[ea] + wb * Vl[eb];
-      }
+    W[ea] = a;
+    W[eb] = b;
+    wa[q] = a;
+    wb[q] = b;
   }
   // block reduction of the j+1 inner products (fixed order); folded by k_dots_finalize
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int l = 0; l <= j; ++l) {
+    const float* Vl = d.V + (long)l * NN;
+    float acc = 0.f;
 #pragma unroll
-  for (int l = 0; l <= MA_MMAX; ++l)
-    if (l <= j) {
-      double v = wave_sum((double)dots[l]);
-      if (lane == 0) red[wid * (MA_MMAX + 1) + l] = v;
-    }
+    for (int q = 0; q < PER; ++q) acc += wa[q] * Vl[ea_[q]] + wb[q] * Vl[ea_[q] + N];
+    const double v = wave_sum((double)acc);
+    if (lane == 0) red[wid * (MA_MMAX + 1) + l] = v;
+  }
   __syncthreads();
   if (threadIdx.x <= j) {
     double t = 0.0;
