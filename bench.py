@@ -180,38 +180,43 @@ def main():
                                 max_batch=B, dilations=meta.get("dilations"))
         net.set_params(params)
 
-    def step(plan, learned):
+    def step(plan, learned, strict):
+        """One batched solve; an unsolved pair aborts the headline arm (strict) and is
+        counted, not credited, in the others."""
         psi0 = net.warm_start(fs, gs) if learned else None
         psis, _, reps = plan.solve_batched(fs, gs, damping=1.0, tol=args.tol, psi0s=psi0)
         bad = [r for r in reps if r["status"] != 0 or r["res_rms"] > args.tol]
-        if bad:
+        if bad and strict:
             raise RuntimeError("unsolved pairs: %d (first: %s)" % (len(bad), bad[0]))
-        return psis, reps
+        return psis, reps, len(bad)
 
-    def timed(plan, learned, profile):
+    def timed(plan, learned, profile, strict):
         for _ in range(args.warmup):
-            step(plan, learned)
+            step(plan, learned, strict)
         torch.cuda.synchronize()
         if profile:
             plan.profile(args.profile_class)
+        unsolved = 0
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            psis, reps = step(plan, learned)
+            psis, reps, nbad = step(plan, learned, strict)
+            unsolved += nbad
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
         prof = plan.profile_read() if profile else None
         plan.profile("none")
-        return elapsed, psis, reps, prof
+        return elapsed, psis, reps, prof, unsolved
 
     inits = {"both": ("zero", "learned"), "zero": ("zero",), "learned": ("learned",)}[args.init]
     head = (symbols[0], inits[-1])
     arms = {}
     for sym in reversed(symbols):  # the headline arm runs last: its launches end the kernel trace
         for init in inits:
-            arms[(sym, init)] = timed(plans[sym], init == "learned", (sym, init) == head)
-            print("arm %s/%s: %.3f pairs/s" % (sym, init, B * args.steps / arms[(sym, init)][0]),
-                  file=sys.stderr, flush=True)
-    elapsed, psis, reps, prof = arms[head]
+            arms[(sym, init)] = timed(plans[sym], init == "learned", (sym, init) == head, (sym, init) == head)
+            el, _, _, _, nbad = arms[(sym, init)]
+            print("arm %s/%s: %.3f pairs/s%s" % (sym, init, (B * args.steps - nbad) / el,
+                                                 " (%d unsolved)" % nbad if nbad else ""), file=sys.stderr, flush=True)
+    elapsed, psis, reps, prof, _ = arms[head]
 
     pairs = B * args.steps
     value = pairs / elapsed
@@ -249,12 +254,13 @@ def main():
                          "us_per_launch": [round(x, 2) for x in tuning["us"]],
                          "us_per_launch_default": [round(x, 2) for x in tuning["us_default"]]}
     out["arms"] = {}
-    for (sym, init), (el, _, rp, _) in arms.items():
-        out["arms"]["%s/%s" % (sym, init)] = dict(value=round(pairs / el, 3),
+    for (sym, init), (el, _, rp, _, nbad) in arms.items():
+        out["arms"]["%s/%s" % (sym, init)] = dict(value=round((pairs - nbad) / el, 3), unsolved=nbad,
                                                   ms_per_step=round(1e3 * el / args.steps, 3), **summary(rp))
     for sym in symbols:
         if (sym, "zero") in arms and (sym, "learned") in arms:
-            out["learned_vs_plain_" + sym] = round(arms[(sym, "zero")][0] / arms[(sym, "learned")][0], 4)
+            out["learned_vs_plain_" + sym] = round(out["arms"][sym + "/learned"]["value"] /
+                                                   out["arms"][sym + "/zero"]["value"], 4)
     cls = {"row_a": 0, "column": 1, "row_c": 2, "residual": 3}[args.profile_class]
     var = plans[head[0]].get_tuning(N)[cls]
     kname = {"row_c": "k_passC<%d, %d>", "row_a": "k_passA<%d, %d>", "column": "k_passB<%d, %d>"}.get(

@@ -105,3 +105,11 @@ def test_tune_geometry_rejects_bad_arguments():
     assert maot.tune_geometry("row_c", 512, 4)[0] == -1
     assert maot.tune_geometry("row_c", 512, -1)[0] == -1
     assert maot.tune_geometry(7, 512, 0)[0] == -1
+
+
+def test_bench_refuses_several_gpus():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
