@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define MA_OT_ABI_VERSION 5
+#define MA_OT_ABI_VERSION 6
 
 /* return / status codes */
 #define MA_OK 0           /* converged: rms residual <= tol                           */
@@ -65,6 +65,12 @@ extern "C" {
  * solved exactly, fewer iterations at a loose tolerance; the fixed point is unchanged */
 #define MA_PRECOND_NONE 0
 #define MA_PRECOND_DIAG 1
+/* GMRES tolerance of each Newton direction: gmres_tol throughout (the paper), or (an
+ * option, with MA_DAMP_BACKTRACK) per pair: after a step that had to be halved three
+ * times or more, the next direction is solved 2x tighter (down to min(gmres_tol, 1e-3)),
+ * after a full step 2x looser again (up to gmres_tol) */
+#define MA_FORCING_FIXED 0
+#define MA_FORCING_ADAPTIVE 1
 
 typedef struct ma_options {
   int max_newton;          /* Newton iterations before MA_ENOCONV (100)              */
@@ -80,6 +86,7 @@ typedef struct ma_options {
   double boundary_frac;    /* MA_DAMP_BACKTRACK: a step is also halved while min det  */
                            /* (I + D^2 u) would fall below this fraction of its       */
                            /* current value, 0 <= . < 1 (0.1; 0 = off)                */
+  int forcing;             /* MA_FORCING_* (MA_FORCING_FIXED)                        */
 } ma_options;
 
 typedef struct ma_report {

@@ -297,6 +297,13 @@ class Report(dict):
     __getattr__ = dict.__getitem__
 
 
+# adaptive forcing: halvings that trigger a tighter next direction, the tightening
+# factor, and the relaxation factor after a full step
+_FORCING_HALVINGS = 3
+_FORCING_TIGHTEN = 2.0
+_FORCING_RELAX = 2.0
+
+
 def diag_scale(coef, abar):
     """D(x) = (a11 + a22)(x) / (abar11 + abar22): the operator's trace relative to that
     of the averaged operator (positive wherever the iterate is convex)."""
@@ -329,7 +336,7 @@ def newton_direction(ev, prob, rhs_scale, op_mode, gmres_m, gmres_tol, gmres_max
 def solve(f, g, tau=1.0, tol=1e-6, psi0=None, max_newton=100, gmres_m=10,
           gmres_tol=1e-4, gmres_max_restarts=20, interp="bilinear", op_mode=0,
           damping_policy="fixed", max_backtrack=12, g_analytic=None, history=False,
-          symbol="spectral", precond="none", boundary_frac=0.1):
+          symbol="spectral", precond="none", boundary_frac=0.1, forcing="fixed"):
     """Damped Newton (eq. linma) with Strain's linear solver (Section 4.2).
 
     psi0, if given, is tried as a first step from u = 0 (accepted if convex and the
@@ -359,6 +366,9 @@ def solve(f, g, tau=1.0, tol=1e-6, psi0=None, max_newton=100, gmres_m=10,
     warm_steps = 0
     tau_cur = float(tau)
     status = None
+    if forcing not in ("fixed", "adaptive"):
+        raise ValueError("forcing must be 'fixed' or 'adaptive'")
+    eta, eta_min = gmres_tol, min(gmres_tol, 1e-3)  # GMRES tolerance of the next direction
     if psi0 is not None and ev.finite and ev.res_rms > tol:
         # checked start (not in the paper): psi0 is tried as a first step from u = 0 and
         # halved while the trial is non-convex or does not lower the residual; after
@@ -386,7 +396,7 @@ def solve(f, g, tau=1.0, tol=1e-6, psi0=None, max_newton=100, gmres_m=10,
             status = ENOCONV
             break
         theta, its = newton_direction(ev, prob, 1.0 / tau_cur, op_mode, gmres_m,
-                                      gmres_tol, gmres_max_restarts, symbol, precond)
+                                      eta, gmres_max_restarts, symbol, precond)
         gm_total += its
         n += 1
         if damping_policy == "fixed":
@@ -395,6 +405,7 @@ def solve(f, g, tau=1.0, tol=1e-6, psi0=None, max_newton=100, gmres_m=10,
         elif damping_policy == "backtrack":
             tau_solve = tau_cur
             accepted = False
+            halvings = 0
             for _ in range(max_backtrack + 1):
                 u_try = u + theta * (tau_solve / tau_cur)
                 ev_try = evaluate(u_try, prob)
@@ -404,11 +415,20 @@ def solve(f, g, tau=1.0, tol=1e-6, psi0=None, max_newton=100, gmres_m=10,
                     break
                 tau_cur *= 2.0
                 backtracks += 1
+                halvings += 1
             if not accepted:
                 status = ENOCONV
                 break
             u, ev = u_try, ev_try
             tau_cur = max(float(tau), tau_cur / 2.0)
+            if forcing == "adaptive":
+                # a step that had to be halved three times or more came from a direction
+                # solved too loosely for the distance to the solution: solve the next one
+                # 2x tighter; relax again after full steps
+                if halvings >= _FORCING_HALVINGS:
+                    eta = max(eta / _FORCING_TIGHTEN, eta_min)
+                elif halvings == 0:
+                    eta = min(gmres_tol, _FORCING_RELAX * eta)
         else:
             raise ValueError("damping_policy must be 'fixed' or 'backtrack'")
         hist.append(ev.res_rms)

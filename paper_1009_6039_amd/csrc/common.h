@@ -76,6 +76,7 @@ struct PairState {
   int gm_cycle;         // restarts done in this solve
   int gm_k;             // basis size at the end of the cycle
   double bnorm, gm_target;
+  double eta;  // adaptive forcing: GMRES tolerance of the next direction (0 = gmres_tol)
   double vscale[MA_MMAX + 1];       // v_l = vscale[l] * V[l]
   double Hm[(MA_MMAX + 1) * MA_MMAX];  // Hessenberg, column-major: Hm[j*(MMAX+1)+i]
   double cs[MA_MMAX], sn[MA_MMAX], gv[MA_MMAX + 1], y[MA_MMAX + 1], q[MA_MMAX + 1];
@@ -94,7 +95,13 @@ struct LaunchCtx {
   int var[4];  // launch-geometry variants (pass A, pass B, pass C, residual), 0 = default
   int precond;  // MA_PRECOND_*: left scaling of the GMRES system by the relative trace
   double boundary_frac;  // step halving: smallest allowed ratio of min det to its current value
+  int forcing;           // MA_FORCING_*: fixed or adaptive GMRES tolerance per Newton direction
 };
+
+// GMRES tolerance of the pair's next Newton direction (eta 0: not adapted yet)
+__host__ __device__ inline double pair_eta(const PairState& s, const LaunchCtx& c) {
+  return s.eta > 0.0 ? s.eta : c.gmres_tol;
+}
 
 // adds one pair's algorithmic bytes for this launch (timed class only)
 __device__ inline void count_bytes(const LaunchCtx& c, double bytes_per_point, int n) {

@@ -145,6 +145,13 @@ __device__ static void newton_decide(PairState& s, const LaunchCtx& c, int n, co
       s.warm_steps = 1;
     } else if (c.damping_policy == MA_DAMP_BACKTRACK) {
       s.tau = fmax(s.tau0, 0.5 * s.tau);
+      if (c.forcing == MA_FORCING_ADAPTIVE) {
+        // a direction that needed three or more halvings was solved too loosely for the
+        // distance to the solution: the next one 2x tighter, full steps relax it again
+        const double eta = pair_eta(s, c), eta_min = fmin(c.gmres_tol, 1e-3);
+        if (s.bt_step >= 3) s.eta = fmax(0.5 * eta, eta_min);
+        else if (s.bt_step == 0) s.eta = fmin(c.gmres_tol, 2.0 * eta);
+      }
     }
   }
   // the evaluation is accepted: record it
@@ -187,7 +194,7 @@ __device__ static void newton_decide(PairState& s, const LaunchCtx& c, int n, co
     s.bt_step = 0;
     s.step = 1.0;
     s.bnorm = sqrt(fmax(ss, 0.0)) / s.tau;
-    s.gm_target = c.gmres_tol * s.bnorm;
+    s.gm_target = pair_eta(s, c) * s.bnorm;
     s.gm_running = s.bnorm > 0.0;
     s.gm_restart = 0;
     s.gm_cycle = 0;

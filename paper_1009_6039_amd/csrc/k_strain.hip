@@ -118,7 +118,7 @@ __global__ __launch_bounds__(256) void k_rhs_finalize(LaunchCtx c, int nblk) {
   if (threadIdx.x == 0) {
     const double bn = sqrt(fmax(t[0], 0.0));
     s.bnorm = bn;
-    s.gm_target = c.gmres_tol * bn;
+    s.gm_target = pair_eta(s, c) * bn;
     s.gm_running = bn > 0.0;
     s.vscale[0] = bn > 0.0 ? 1.0 / bn : 0.0;
     s.gv[0] = bn;

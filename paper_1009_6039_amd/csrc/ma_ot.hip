@@ -125,7 +125,8 @@ int validate_options(const ma_options& o) {
       (o.damping_policy != MA_DAMP_FIXED && o.damping_policy != MA_DAMP_BACKTRACK) || o.max_backtrack < 0 ||
       (o.symbol != MA_SYMBOL_SPECTRAL && o.symbol != MA_SYMBOL_FD4) ||
       (o.precond != MA_PRECOND_NONE && o.precond != MA_PRECOND_DIAG) ||
-      !(o.boundary_frac >= 0.0 && o.boundary_frac < 1.0))
+      !(o.boundary_frac >= 0.0 && o.boundary_frac < 1.0) ||
+      (o.forcing != MA_FORCING_FIXED && o.forcing != MA_FORCING_ADAPTIVE))
     return MA_EINVAL;
   return MA_OK;
 }
@@ -234,6 +235,7 @@ LaunchCtx make_ctx(const ma_plan* P, const Class& cl, int kind = MA_PROF_NONE) {
   c.gmres_tol = P->opt.gmres_tol;
   c.precond = P->opt.precond;
   c.boundary_frac = P->opt.boundary_frac;
+  c.forcing = P->opt.forcing;
   auto t = P->tune.find(cl.n);
   for (int k = 0; k < 4; ++k) c.var[k] = t == P->tune.end() ? 0 : t->second.v[k];
   return c;
@@ -480,6 +482,7 @@ void ma_options_default(ma_options* o) {
   o->symbol = MA_SYMBOL_SPECTRAL;
   o->precond = MA_PRECOND_NONE;
   o->boundary_frac = 0.1;
+  o->forcing = MA_FORCING_FIXED;
 }
 
 const char* ma_strerror(int code) {

@@ -21,6 +21,7 @@ OP_MODE = {"full": 0, "no_drift": 1}
 DAMPING = {"fixed": 0, "backtrack": 1}
 SYMBOL = {"spectral": 0, "fd4": 1}
 PRECOND = {"none": 0, "diag": 1}
+FORCING = {"fixed": 0, "adaptive": 1}
 
 PROF = {"none": 0, "residual": 1, "row_a": 2, "column": 3, "row_c": 4}
 
@@ -40,7 +41,8 @@ class Options(ctypes.Structure):
                 ("gmres_max_restarts", ctypes.c_int), ("gmres_tol", ctypes.c_double),
                 ("interp", ctypes.c_int), ("op_mode", ctypes.c_int),
                 ("damping_policy", ctypes.c_int), ("max_backtrack", ctypes.c_int),
-                ("symbol", ctypes.c_int), ("precond", ctypes.c_int), ("boundary_frac", ctypes.c_double)]
+                ("symbol", ctypes.c_int), ("precond", ctypes.c_int), ("boundary_frac", ctypes.c_double),
+                ("forcing", ctypes.c_int)]
 
 
 class Tuning(ctypes.Structure):
@@ -166,6 +168,8 @@ def make_options(**kw):
             v = SYMBOL[v] if isinstance(v, str) else v
         elif k == "precond":
             v = PRECOND[v] if isinstance(v, str) else v
+        elif k == "forcing":
+            v = FORCING[v] if isinstance(v, str) else v
         if not hasattr(o, k):
             raise TypeError("unknown option %r" % k)
         setattr(o, k, v)

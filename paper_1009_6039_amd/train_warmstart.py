@@ -111,11 +111,15 @@ def train(net, X, T, ok, epochs, batch, lr0, val_frac=0.05, seed=0, log=print):
     return hist
 
 
+# the two ways of solving the linear equation that bench.py times
+METHODS = (("paper", {"symbol": "spectral", "gmres_tol": 0.01}),
+           ("fast", {"symbol": "fd4", "precond": "diag", "gmres_tol": 0.2, "forcing": "adaptive"}))
+
+
 def evaluate(maot, net, n, count=64, log=print):
     """Newton iterations and wall time on held-out pairs from zero, from the linearised
-    start (the network's output set to zero) and from the learned start, for both
-    ways of solving the linear equation (fd4 symbols with diagonal scaling, and the
-    paper's spectral symbols)."""
+    start (the network's output set to zero) and from the learned start, for the
+    paper's linear solve and the fast one."""
     import torch
     pairs = [W.blobs(n, W.seed_for(TRAIN_CONFIG + 1, q)) for q in range(count)]
     f = [torch.from_numpy(a).cuda() for a, _ in pairs]
@@ -124,22 +128,23 @@ def evaluate(maot, net, n, count=64, log=print):
                             dilations=net.dilations)
     lin.set_params(np.zeros(lin.count, dtype=np.float32))
     out = {}
-    for symbol, opts in (("paper", {"symbol": "spectral"}), ("fast", {"symbol": "fd4", "precond": "diag"})):
-        plan = maot.Plan(n_max=n, batch_capacity=count, damping_policy="backtrack", gmres_tol=0.1, max_newton=300,
-                         **opts)
+    for method, opts in METHODS:
+        plan = maot.Plan(n_max=n, batch_capacity=count, damping_policy="backtrack", max_newton=500, **opts)
+        plan.autotune(n, count)
         for arm, start in (("zero", None), ("linearised", lin), ("learned", net)):
-            torch.cuda.synchronize()
-            t0 = time.time()
-            psi0 = start.warm_start(f, g) if start is not None else None
-            _, _, reps = plan.solve_batched(f, g, damping=1.0, tol=1e-6, psi0s=psi0)
-            torch.cuda.synchronize()
-            key = "%s/%s" % (symbol, arm)
+            for rep_i in range(2):  # the first run of an arm warms up
+                torch.cuda.synchronize()
+                t0 = time.time()
+                psi0 = start.warm_start(f, g) if start is not None else None
+                _, _, reps = plan.solve_batched(f, g, damping=1.0, tol=1e-6, psi0s=psi0)
+                torch.cuda.synchronize()
+            key = "%s/%s" % (method, arm)
             out[key] = {"seconds": time.time() - t0,
                         "newton_mean": float(np.mean([r["newton_iters"] for r in reps])),
                         "gmres_mean": float(np.mean([r["gmres_iters"] for r in reps])),
                         "warm_accepted": int(sum(r["warm_steps"] for r in reps)),
                         "unsolved": int(sum(r["status"] != 0 for r in reps))}
-            log("eval n=%d %s: %s" % (n, key, json.dumps(out[key])))
+            log("eval n=%d pairs=%d %s: %s" % (n, count, key, json.dumps(out[key])))
         plan.close()
     lin.close()
     return out
@@ -158,11 +163,27 @@ def main():
                     help="per-layer dilation of the 3x3 taps (comma list, one per layer)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--workers", type=int, default=16)
-    ap.add_argument("--out", required=True)
+    ap.add_argument("--out", help="where to save the trained parameters (npz)")
+    ap.add_argument("--eval-only", metavar="NPZ", help="evaluate saved parameters instead of training")
+    ap.add_argument("--eval-pairs", default="256,64", help="held-out pairs at n_net and at 2 n_net")
     args = ap.parse_args()
     import torch
     from . import maot
     log = lambda s: print(s, flush=True)  # noqa: E731
+    cnt = [int(v) for v in args.eval_pairs.split(",")]
+    if args.eval_only:
+        d = np.load(args.eval_only, allow_pickle=False)
+        meta = json.loads(str(d["meta"]))
+        net = maot.WarmStartNet(layers=meta["layers"], channels=meta["channels"], n_net=meta["n_net"],
+                                max_batch=max(cnt), dilations=meta.get("dilations"))
+        net.set_params(d["params"].astype(np.float32))
+        res = {"n_net": evaluate(maot, net, meta["n_net"], cnt[0], log=log),
+               "2n_net": evaluate(maot, net, 2 * meta["n_net"], cnt[1], log=log)}
+        log("evaluation: " + json.dumps(res))
+        net.close()
+        return
+    if not args.out:
+        ap.error("--out is required for training")
     dil = [int(v) for v in args.dilations.split(",")]
     net = maot.WarmStartNet(layers=args.layers, channels=args.channels, n_net=args.n, max_batch=args.batch,
                             dilations=dil)
@@ -174,8 +195,8 @@ def main():
     del tq
     hist = train(net, X, T, ok, args.epochs, args.batch, args.lr, seed=args.seed, log=log)
     del X, T
-    ev = evaluate(maot, net, args.n, log=log)
-    ev512 = evaluate(maot, net, 2 * args.n, log=log)
+    ev = evaluate(maot, net, args.n, cnt[0], log=log)
+    ev512 = evaluate(maot, net, 2 * args.n, cnt[1], log=log)
     meta = {"layers": args.layers, "channels": args.channels, "dilations": dil, "n_net": args.n, "pairs": args.pairs,
             "epochs": args.epochs, "batch": args.batch, "lr": args.lr, "seed": args.seed,
             "dataset": gen, "history": hist, "eval_n_net": ev, "eval_2n_net": ev512}

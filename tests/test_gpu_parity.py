@@ -417,3 +417,25 @@ def test_diag_scaled_solve_matches_oracle(maot, symbol):
     finally:
         p.close()
         q.close()
+
+
+def test_adaptive_forcing_solves_the_pair_that_stalls_with_fixed_forcing(maot):
+    # held-out blob pair 192 at 256^2: with the fast linear solve at a fixed GMRES
+    # tolerance 0.2 its iterates run into the boundary of convexity (min det 1e-13, the
+    # oracle stalls at residual 0.73); solving the direction after a hard step more
+    # accurately avoids that.  GPU against the oracle with the same options.
+    N = 256
+    f, g = W.blobs(N, W.seed_for(5, 192))
+    opts = dict(damping_policy="backtrack", gmres_tol=0.2, max_newton=300, symbol="fd4", precond="diag",
+                forcing="adaptive")
+    ref, _, rr = ma.solve(f, g, tau=1.0, tol=1e-10, **opts)
+    assert rr.status == ma.OK
+    p = maot.Plan(n_max=N, batch_capacity=1, **opts)
+    try:
+        psi, _, rep = p.solve(dev(f), dev(g), damping=1.0, tol=1e-9)
+        print("adaptive forcing: newton %d (oracle %d), gmres %d, halvings %d" % (
+            rep["newton_iters"], rr.newton_iters, rep["gmres_iters"], rep["backtracks"]))
+        assert rep["status"] == 0 and rep["res_rms"] <= 1e-9
+        assert np.max(np.abs(host(psi) - ref)) <= 1e-6 * np.max(np.abs(ref))
+    finally:
+        p.close()

@@ -428,3 +428,16 @@ def test_boundary_fraction_keeps_the_fixed_point():
     for psi, _, _ in results[1:]:
         assert np.max(np.abs(psi - ref)) <= 1e-8 * np.max(np.abs(ref))
     assert results[2][2].backtracks >= results[0][2].backtracks
+
+
+def test_adaptive_forcing_keeps_the_fixed_point():
+    # adaptive forcing only changes how accurately each direction is solved
+    from paper_1009_6039_amd import workloads as W
+    f, g = W.blobs(64, W.seed_for(1, 7))
+    kw = dict(tol=1e-10, damping_policy="backtrack", gmres_tol=0.2, max_newton=300, symbol="fd4", precond="diag")
+    p1, _, r1 = ma.solve(f, g, **kw)
+    p2, _, r2 = ma.solve(f, g, forcing="adaptive", **kw)
+    assert r1.status == ma.OK and r2.status == ma.OK
+    assert np.max(np.abs(p1 - p2)) <= 1e-8 * np.max(np.abs(p1))
+    with pytest.raises(ValueError):
+        ma.solve(f, g, forcing="ew", **kw)
