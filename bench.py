@@ -36,9 +36,10 @@ METRIC = "Newton-solved pairs/sec at 512^2 to residual 1e-6; learned-init vs pla
 # and GMRES tolerance.  The paper's method runs at its 1e-2 (Section 5.2): at 1e-1 its
 # iteration count on some blob pairs depends on FP32 summation order (35 to 330
 # Newton steps on one benchmark pair), at 1e-2 it does not.  The fast method runs at
-# 2e-1 with adaptive forcing (a direction after a step halved three times or more is solved
-# 2x tighter): fewer passes in total than at 1e-1, and no pair stalls near the boundary
-# of convexity (without it one of 256 held-out pairs did).
+# 2e-1 with adaptive forcing (the direction after a step, other than the first, that
+# was halved twice or more is solved 4x tighter): fewer passes in total than at 1e-1,
+# and no held-out pair drifts into the boundary of convexity from the zero start
+# (with a fixed 2e-1 some do).
 METHODS = {"fast": {"symbol": "fd4", "precond": "diag", "gmres_tol": 0.2, "forcing": "adaptive"},
            "fd4": {"symbol": "fd4", "precond": "none", "gmres_tol": 0.1},
            "paper": {"symbol": "spectral", "precond": "none", "gmres_tol": 0.01},

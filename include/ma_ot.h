@@ -66,9 +66,9 @@ extern "C" {
 #define MA_PRECOND_NONE 0
 #define MA_PRECOND_DIAG 1
 /* GMRES tolerance of each Newton direction: gmres_tol throughout (the paper), or (an
- * option, with MA_DAMP_BACKTRACK) per pair: after a step that had to be halved three
- * times or more, the next direction is solved 2x tighter (down to min(gmres_tol, 1e-3)),
- * after a full step 2x looser again (up to gmres_tol) */
+ * option, with MA_DAMP_BACKTRACK) per pair: after a step other than the first that had
+ * to be halved twice or more, the next direction is solved 4x tighter (down to
+ * min(gmres_tol, 1e-3)), after a full step 4x looser again (up to gmres_tol) */
 #define MA_FORCING_FIXED 0
 #define MA_FORCING_ADAPTIVE 1
 

@@ -297,11 +297,11 @@ class Report(dict):
     __getattr__ = dict.__getitem__
 
 
-# adaptive forcing: halvings that trigger a tighter next direction, the tightening
-# factor, and the relaxation factor after a full step
-_FORCING_HALVINGS = 3
-_FORCING_TIGHTEN = 2.0
-_FORCING_RELAX = 2.0
+# adaptive forcing: halvings that trigger a tighter next direction (the first Newton
+# direction exempt), the tightening factor, and the relaxation factor after a full step
+_FORCING_HALVINGS = 2
+_FORCING_TIGHTEN = 4.0
+_FORCING_RELAX = 4.0
 
 
 def diag_scale(coef, abar):
@@ -422,10 +422,11 @@ def solve(f, g, tau=1.0, tol=1e-6, psi0=None, max_newton=100, gmres_m=10,
             u, ev = u_try, ev_try
             tau_cur = max(float(tau), tau_cur / 2.0)
             if forcing == "adaptive":
-                # a step that had to be halved three times or more came from a direction
-                # solved too loosely for the distance to the solution: solve the next one
-                # 2x tighter; relax again after full steps
-                if halvings >= _FORCING_HALVINGS:
+                # a step (after the first) that had to be halved twice or more came from a
+                # direction solved too loosely for the distance to the solution: solve the
+                # next one more tightly; relax again after a full step.  The first direction
+                # is exempt: from u = 0 it is halved for its linearisation, not its accuracy
+                if halvings >= _FORCING_HALVINGS and n > 1:
                     eta = max(eta / _FORCING_TIGHTEN, eta_min)
                 elif halvings == 0:
                     eta = min(gmres_tol, _FORCING_RELAX * eta)

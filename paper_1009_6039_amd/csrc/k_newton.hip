@@ -146,11 +146,12 @@ __device__ static void newton_decide(PairState& s, const LaunchCtx& c, int n, co
     } else if (c.damping_policy == MA_DAMP_BACKTRACK) {
       s.tau = fmax(s.tau0, 0.5 * s.tau);
       if (c.forcing == MA_FORCING_ADAPTIVE) {
-        // a direction that needed three or more halvings was solved too loosely for the
-        // distance to the solution: the next one 2x tighter, full steps relax it again
+        // a direction (after the first) that needed two or more halvings was solved too
+        // loosely for the distance to the solution: the next one 4x tighter; a full step
+        // relaxes it 4x again
         const double eta = pair_eta(s, c), eta_min = fmin(c.gmres_tol, 1e-3);
-        if (s.bt_step >= 3) s.eta = fmax(0.5 * eta, eta_min);
-        else if (s.bt_step == 0) s.eta = fmin(c.gmres_tol, 2.0 * eta);
+        if (s.bt_step >= 2 && s.newton_iters > 1) s.eta = fmax(0.25 * eta, eta_min);
+        else if (s.bt_step == 0) s.eta = fmin(c.gmres_tol, 4.0 * eta);
       }
     }
   }

@@ -143,7 +143,9 @@ def evaluate(maot, net, n, count=64, log=print):
                         "newton_mean": float(np.mean([r["newton_iters"] for r in reps])),
                         "gmres_mean": float(np.mean([r["gmres_iters"] for r in reps])),
                         "warm_accepted": int(sum(r["warm_steps"] for r in reps)),
-                        "unsolved": int(sum(r["status"] != 0 for r in reps))}
+                        "unsolved": int(sum(r["status"] != 0 for r in reps)),
+                        "unsolved_pairs": [[q, int(r["status"]), int(r["newton_iters"]), float(r["res_rms"])]
+                                           for q, r in enumerate(reps) if r["status"] != 0]}
             log("eval n=%d pairs=%d %s: %s" % (n, count, key, json.dumps(out[key])))
         plan.close()
     lin.close()
