@@ -65,6 +65,9 @@ def parse():
                          % ", ".join(sorted(METHODS)))
     ap.add_argument("--profile-class", default="row_c",
                     help="kernel class timed for the roofline: residual, row_a, column, row_c")
+    ap.add_argument("--profile-every", type=int, default=7,
+                    help="time every k-th launch of that class with HIP events (events add a few "
+                         "microseconds of queue time per timed launch)")
     ap.add_argument("--init", default="both", choices=("both", "zero", "learned"),
                     help="arms to time; value is the learned arm unless only zero is run")
     ap.add_argument("--weights", default=os.path.join(HERE, "paper_1009_6039_amd", "warmstart_256.npz"))
@@ -198,7 +201,7 @@ def main():
             step(plan, learned, strict)
         torch.cuda.synchronize()
         if profile:
-            plan.profile(args.profile_class)
+            plan.profile(args.profile_class, args.profile_every)
         unsolved = 0
         t0 = time.perf_counter()
         for _ in range(args.steps):
@@ -272,7 +275,7 @@ def main():
     rec = read_traffic_record(os.path.join(HERE, "profiles", TRAFFIC_FILE % N), kname) if kname else None
     if rec and rec.get("variant") != var:
         rec = None  # counters taken with another launch geometry
-    bpl = prof["bytes"] / max(prof["launches"], 1)
+    bpl = prof["all_bytes"] / max(prof["all_launches"], 1)  # over every launch, as the counters are
     if rec and abs(rec.get("algorithmic_bytes_per_launch", 0.0) - bpl) > 1e-3 * bpl:
         rec = None  # counters taken on another launch mix (workload, start or iteration path)
     out["roofline"] = {"bound": "hbm", "kernel": args.profile_class, "achieved": round(achieved, 1),
@@ -280,10 +283,12 @@ def main():
                        "traffic": round(rec["traffic_bytes_per_launch"]) if rec else None,
                        "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-scaled; null unless the "
                                        "kernel sources, geometry and launch mix are the profiled ones)",
-                       "launches": prof["launches"],
+                       "launches": prof["launches"], "timed_every": args.profile_every,
+                       "launches_all": prof["all_launches"],
                        "avg_launch_us": round(1e3 * prof["ms"] / max(prof["launches"], 1), 3),
                        "bytes_per_launch": round(prof["bytes"] / max(prof["launches"], 1)),
-                       "algorithmic_bytes_total": prof["bytes"]}
+                       "bytes_per_launch_all": round(bpl),
+                       "algorithmic_bytes_timed": prof["bytes"]}
     if not args.no_cpu_baseline:
         if args.workload == "mixed":  # one pair of each size: the mix's mean cost per pair
             idx = [sizes.index(n) for n in sorted(set(sizes))]

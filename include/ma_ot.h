@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define MA_OT_ABI_VERSION 6
+#define MA_OT_ABI_VERSION 7
 
 /* return / status codes */
 #define MA_OK 0           /* converged: rms residual <= tol                           */
@@ -158,10 +158,13 @@ int ma_solve_batched(ma_plan* plan, int npairs, const int* n, const double* cons
 
 /* ---------------------------------------------------------------------------
  * Timing hook for one kernel class, used by the benchmark to report a roofline.
- * While enabled, every launch of that class inside ma_solve / ma_solve_batched is
- * bracketed by HIP events on the caller's stream, and each launch adds the
- * algorithmic bytes of the pairs it actually serves (inputs read once, outputs
- * written once; pairs that skip the launch add nothing) to a device counter.
+ * While enabled, every `every`-th launch of that class inside ma_solve /
+ * ma_solve_batched (counting from the first after the call) is bracketed by HIP
+ * events on the caller's stream, and adds the algorithmic bytes of the pairs it
+ * actually serves (inputs read once, outputs written once; pairs that skip the
+ * launch add nothing) to a device counter.  Events cost a few microseconds of
+ * queue time around each timed launch: a stride above 1 keeps that overhead out of
+ * the surrounding throughput while the average stays a live measurement.
  * ------------------------------------------------------------------------- */
 #define MA_PROF_NONE 0
 #define MA_PROF_RESIDUAL 1   /* fused residual / coefficient kernel             */
@@ -169,13 +172,17 @@ int ma_solve_batched(ma_plan* plan, int npairs, const int* n, const double* cons
 #define MA_PROF_COLUMN 3     /* column pass B with the spectral multiply        */
 #define MA_PROF_ROW_C 4      /* row pass C: inverse rows + combine + dots       */
 
-/* Selects the class to time (MA_PROF_NONE disables) and clears the counters. */
-int ma_plan_profile(ma_plan* plan, int kernel_class);
+/* Selects the class to time (MA_PROF_NONE disables) and the sampling stride
+ * (every >= 1; 1 = every launch), and clears the counters.  MA_EINVAL for an
+ * unknown class or every < 1. */
+int ma_plan_profile(ma_plan* plan, int kernel_class, int every);
 
-/* Totals since ma_plan_profile: summed event time (ms), launches, algorithmic
- * bytes.  Any pointer may be NULL.  Synchronises nothing (counters are final once
+/* Totals since ma_plan_profile: over the timed launches, summed event time (ms),
+ * their number and their algorithmic bytes; over all launches of the class, their
+ * number and algorithmic bytes.  Any pointer may be NULL.  Synchronises nothing (counters are final once
  * the solve call has returned). */
-int ma_plan_profile_read(ma_plan* plan, double* ms, long long* launches, double* bytes);
+int ma_plan_profile_read(ma_plan* plan, double* ms, long long* launches, double* bytes,
+                         long long* all_launches, double* all_bytes);
 
 /* ---------------------------------------------------------------------------
  * Single steps of the hot path, for verification and profiling.  They run the

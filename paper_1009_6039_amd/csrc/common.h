@@ -14,6 +14,7 @@
 #define MA_NPART_RES 16   // partial sums per residual block
 #define MA_BLOCK 256
 #define MA_SUMMARY_INTS 16  // host-loop counters written by the summary kernel
+#define MA_SUMMARY_TAG 15   // slot of the sequence number the summary kernel writes last
 
 // per-pair phase of the Newton loop
 enum : int {

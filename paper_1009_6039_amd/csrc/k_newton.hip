@@ -205,6 +205,15 @@ __device__ static void newton_decide(PairState& s, const LaunchCtx& c, int n, co
   }
 }
 
+// f mod n for an integer-valued f with |f| < 2^50, in [0, n): the quotient is rounded,
+// so the FP64 remainder (exact: integers below 2^53) lies in [-n, 2n) and one fold
+// finishes it.  Replaces a 64-bit integer division.
+__device__ inline int wrap_index(double f, int n, double N) {
+  int a = (int)(f - N * floor(f / N));
+  a += a < 0 ? n : (a >= n ? -n : 0);
+  return a;
+}
+
 // ---------------------------------------------------------------------------
 // Fused residual + coefficient kernel (one Newton evaluation).
 // Tile: TX columns x MA_RES_TY rows per block, halo 2 staged in LDS (FP64).
@@ -226,7 +235,9 @@ __global__ __launch_bounds__(MA_BLOCK) void k_residual(LaunchCtx c) {
   const double* __restrict__ u = d.u;
   for (int e = threadIdx.x; e < (TY + 4) * LW; e += MA_BLOCK) {
     const int li = e / LW, lj = e % LW;
-    const int gi = (i0 + li - 2 + n) % n, gj = (j0 + lj - 2 + n) % n;
+    int gi = i0 + li - 2, gj = j0 + lj - 2;  // within [-2, n + 2): one periodic fold
+    gi += gi < 0 ? n : (gi >= n ? -n : 0);
+    gj += gj < 0 ? n : (gj >= n ? -n : 0);
     tile[e] = u[(long)gi * n + gj];
   }
   __syncthreads();
@@ -267,17 +278,13 @@ __global__ __launch_bounds__(MA_BLOCK) void k_residual(LaunchCtx c) {
     if (!(fabs(t2) < 1e15)) t2 = 0.0;
     double gy, gy1, gy2;
     if (c.interp == MA_INTERP_NEAREST) {
-      long a = (long)floor(t1 + 0.5), b = (long)floor(t2 + 0.5);
-      a %= n; if (a < 0) a += n;
-      b %= n; if (b < 0) b += n;
+      const long a = wrap_index(floor(t1 + 0.5), n, N), b = wrap_index(floor(t2 + 0.5), n, N);
       GS v = gs[a * n + b];
       gy = v.g; gy1 = v.g1; gy2 = v.g2;
     } else {
       const double f1 = floor(t1), f2 = floor(t2);
       const double wa = t1 - f1, wb = t2 - f2;
-      long a = (long)f1 % n, b = (long)f2 % n;
-      if (a < 0) a += n;
-      if (b < 0) b += n;
+      const long a = wrap_index(f1, n, N), b = wrap_index(f2, n, N);
       const long a1 = (a + 1 == n) ? 0 : a + 1, b1 = (b + 1 == n) ? 0 : b + 1;
       const GS v00 = gs[a * n + b], v10 = gs[a1 * n + b], v01 = gs[a * n + b1], v11 = gs[a1 * n + b1];
       const double w00 = (1 - wa) * (1 - wb), w10 = wa * (1 - wb), w01 = (1 - wa) * wb, w11 = wa * wb;
@@ -402,7 +409,11 @@ __global__ __launch_bounds__(MA_BLOCK) void k_outputs(LaunchCtx c) {
 // counts pairs per phase, pending restarts and invalid inputs for the host loop
 // counts for the host loop: [0..5] pairs per phase, [6] pairs to restart GMRES,
 // [7] invalid inputs, [8] pairs inside a GMRES cycle (16 slots written)
-__global__ __launch_bounds__(256) void k_summary(const PairState* st, const int* ids, int npairs, int* out) {
+// Counts of the pairs per phase and flag, written to host-visible memory; the
+// sequence number goes last, after a system-scope fence, so that a host that sees it
+// also sees the counts.
+__global__ __launch_bounds__(256) void k_summary(const PairState* st, const int* ids, int npairs, int* out,
+                                                 int seq) {
   __shared__ int cnt[MA_SUMMARY_INTS];
   if (threadIdx.x < MA_SUMMARY_INTS) cnt[threadIdx.x] = 0;
   __syncthreads();
@@ -414,7 +425,11 @@ __global__ __launch_bounds__(256) void k_summary(const PairState* st, const int*
     if (s.phase == PH_SOLVE && s.gm_running) atomicAdd(&cnt[8], 1);
   }
   __syncthreads();
-  if (threadIdx.x < MA_SUMMARY_INTS) out[threadIdx.x] = cnt[threadIdx.x];
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < MA_SUMMARY_TAG; ++k) out[k] = cnt[k];
+    __threadfence_system();
+    out[MA_SUMMARY_TAG] = seq;
+  }
 }
 
 // Synthetic fields for timing launch geometries: smooth positive densities, a small
@@ -525,6 +540,6 @@ void launch_outputs(const LaunchCtx& c, int n, int npairs, hipStream_t st) {
   hipLaunchKernelGGL(k_outputs, dim3(elementwise_blocks(n), npairs), dim3(MA_BLOCK), 0, st, c);
 }
 
-void launch_summary(const PairState* s, const int* ids, int npairs, int* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_summary, dim3(1), dim3(256), 0, st, s, ids, npairs, out);
+void launch_summary(const PairState* s, const int* ids, int npairs, int* out, int seq, hipStream_t st) {
+  hipLaunchKernelGGL(k_summary, dim3(1), dim3(256), 0, st, s, ids, npairs, out, seq);
 }

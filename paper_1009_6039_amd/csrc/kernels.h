@@ -39,7 +39,7 @@ void launch_residual_only(const LaunchCtx& c, int n, int npairs, hipStream_t st,
 void launch_residual_shift(const LaunchCtx& c, int n, float* out, hipStream_t st);
 void launch_step_update(const LaunchCtx& c, int n, int npairs, hipStream_t st);
 void launch_outputs(const LaunchCtx& c, int n, int npairs, hipStream_t st);
-void launch_summary(const PairState* s, const int* ids, int npairs, int* out, hipStream_t st);
+void launch_summary(const PairState* s, const int* ids, int npairs, int* out, int seq, hipStream_t st);
 void launch_tune_fill(const LaunchCtx& c, int n, int npairs, hipStream_t st);
 
 // FFT passes and GMRES kernels; `tw` is the length-n twiddle table

@@ -49,10 +49,12 @@ struct ma_plan {
   int* d_ids = nullptr;
   int pairs_cap = 0;
   // host-loop counters: 4 slots of MA_SUMMARY_INTS (the synchronous read, then a ring
-  // of 3) in coherent pinned host memory that the summary kernel writes directly
+  // of 3) in coherent pinned host memory that the summary kernel writes directly,
+  // each ending with the sequence number of the launch that wrote it
   int* h_summary = nullptr;
   int* d_summary = nullptr;  // the device's address of h_summary
-  hipEvent_t ring_ev[3] = {nullptr, nullptr, nullptr};
+  int sum_seq = 0;           // sequence number of the last summary launched
+  int ring_seq[3] = {0, 0, 0};
   std::map<int, float2*> tw;
   std::map<std::pair<int, int>, float2*> mt;  // (n, symbol) -> derivative multipliers
   std::map<int, Tune> tune;                   // n -> launch-geometry variants (absent: defaults)
@@ -65,6 +67,8 @@ struct ma_plan {
   int ev_used = 0;
   double prof_ms = 0.0;
   long long prof_launches = 0;
+  int prof_every = 1;       // time every prof_every-th launch of the class
+  long long prof_seq = 0;   // launches of the class seen since ma_plan_profile
 };
 
 namespace {
@@ -218,9 +222,10 @@ int ensure_workspace(ma_plan* P, const std::vector<int>& ns) {
   return MA_OK;
 }
 
-LaunchCtx make_ctx(const ma_plan* P, const Class& cl, int kind = MA_PROF_NONE) {
+LaunchCtx make_ctx(const ma_plan* P, const Class& cl, int kind = MA_PROF_NONE, bool timed = false) {
   LaunchCtx c;
-  c.prof_bytes = (kind != MA_PROF_NONE && kind == P->prof_kind) ? P->d_prof : nullptr;
+  // counter 0: the class's untimed launches, counter 1: its timed ones
+  c.prof_bytes = (kind != MA_PROF_NONE && kind == P->prof_kind) ? P->d_prof + (timed ? 1 : 0) : nullptr;
   c.desc = P->d_desc;
   c.st = P->d_state;
   c.pair_ids = cl.d_ids;
@@ -297,28 +302,63 @@ void prof_flush(ma_plan* P) {
   P->ev_used = 0;
 }
 
+// whether this launch of class `kind` is timed (it is the timed class and its turn in
+// the sampling stride): decided once, so that the timed byte counter and the events
+// cover the same launches
+bool prof_pick(ma_plan* P, int kind) {
+  if (kind != P->prof_kind || kind == MA_PROF_NONE) return false;
+  return (P->prof_seq++ % P->prof_every) == 0;
+}
+
 void L_res(ma_plan* P, const Class& c, int step_mode, hipStream_t st) {
-  launch_residual(make_ctx(P, c, MA_PROF_RESIDUAL), c.n, (int)c.ids.size(), step_mode, st,
-                  prof_events(P, MA_PROF_RESIDUAL));
+  const bool t = prof_pick(P, MA_PROF_RESIDUAL);
+  launch_residual(make_ctx(P, c, MA_PROF_RESIDUAL, t), c.n, (int)c.ids.size(), step_mode, st,
+                  prof_events(P, t ? MA_PROF_RESIDUAL : MA_PROF_NONE));
 }
 void L_A(ma_plan* P, const Class& c, int mode, int jn, hipStream_t st) {
-  launch_passA(make_ctx(P, c, MA_PROF_ROW_A), c.n, (int)c.ids.size(), mode, jn, c.tw, st,
-               prof_events(P, MA_PROF_ROW_A));
+  const bool t = prof_pick(P, MA_PROF_ROW_A);
+  launch_passA(make_ctx(P, c, MA_PROF_ROW_A, t), c.n, (int)c.ids.size(), mode, jn, c.tw, st,
+               prof_events(P, t ? MA_PROF_ROW_A : MA_PROF_NONE));
 }
 void L_B(ma_plan* P, const Class& c, int mode, int j, hipStream_t st) {
-  launch_passB(make_ctx(P, c, MA_PROF_COLUMN), c.n, (int)c.ids.size(), mode, j, c.tw, st,
-               prof_events(P, MA_PROF_COLUMN));
+  const bool t = prof_pick(P, MA_PROF_COLUMN);
+  launch_passB(make_ctx(P, c, MA_PROF_COLUMN, t), c.n, (int)c.ids.size(), mode, j, c.tw, st,
+               prof_events(P, t ? MA_PROF_COLUMN : MA_PROF_NONE));
 }
 void L_C(ma_plan* P, const Class& c, int mode, int j, hipStream_t st) {
-  launch_passC(make_ctx(P, c, MA_PROF_ROW_C), c.n, (int)c.ids.size(), mode, j, c.tw, st,
-               prof_events(P, MA_PROF_ROW_C));
+  const bool t = prof_pick(P, MA_PROF_ROW_C);
+  launch_passC(make_ctx(P, c, MA_PROF_ROW_C, t), c.n, (int)c.ids.size(), mode, j, c.tw, st,
+               prof_events(P, t ? MA_PROF_ROW_C : MA_PROF_NONE));
+}
+
+// Waits until slot `slot` of the summary holds the counts of the launch numbered
+// `seq` by polling its tag in host memory (no stream synchronisation: the host
+// resumes as soon as the kernel's fenced write lands).  Every 256 polls the stream
+// is queried, so that a failed or drained stream ends the wait with MA_EHIP.
+int wait_summary(ma_plan* P, int slot, int seq, hipStream_t st) {
+  int* tag = P->h_summary + MA_SUMMARY_INTS * slot + MA_SUMMARY_TAG;
+  for (unsigned spin = 1;; ++spin) {
+    if (__atomic_load_n(tag, __ATOMIC_ACQUIRE) == seq) return MA_OK;
+    if ((spin & 255) == 0) {
+      const hipError_t q = hipStreamQuery(st);
+      if (q == hipSuccess) return __atomic_load_n(tag, __ATOMIC_ACQUIRE) == seq ? MA_OK : MA_EHIP;
+      if (q != hipErrorNotReady) return MA_EHIP;
+    }
+    __builtin_ia32_pause();
+  }
+}
+
+// the next summary sequence number (1 .. INT_MAX, then 1 again: a slot always holds a
+// recent number, so a restarted count cannot meet a stale tag)
+int next_seq(ma_plan* P) {
+  P->sum_seq = P->sum_seq == 2147483647 ? 1 : P->sum_seq + 1;
+  return P->sum_seq;
 }
 
 int read_summary(ma_plan* P, int npairs, hipStream_t st) {
-  launch_summary(P->d_state, P->d_ids, npairs, P->d_summary, st);
-  HIP_TRY(hipStreamSynchronize(st));
-  prof_flush(P);
-  return MA_OK;
+  const int seq = next_seq(P);
+  launch_summary(P->d_state, P->d_ids, npairs, P->d_summary, seq, st);
+  return wait_summary(P, 0, seq, st);
 }
 
 // The iterations of one GMRES cycle.  From the third on, a summary of the state is
@@ -337,11 +377,13 @@ int launch_cycle_body(ma_plan* P, const std::vector<Class>& cls, int npairs, hip
     }
     if (j + 1 >= m || j < FIRST) continue;
     const int slot = j % (LAG + 1);
-    launch_summary(P->d_state, P->d_ids, npairs, P->d_summary + MA_SUMMARY_INTS * (1 + slot), st);
-    HIP_TRY(hipEventRecord(P->ring_ev[slot], st));
+    P->ring_seq[slot] = next_seq(P);
+    launch_summary(P->d_state, P->d_ids, npairs, P->d_summary + MA_SUMMARY_INTS * (1 + slot), P->ring_seq[slot],
+                   st);
     if (j >= FIRST + LAG) {
       const int old = (j - LAG) % (LAG + 1);
-      HIP_TRY(hipEventSynchronize(P->ring_ev[old]));
+      const int e = wait_summary(P, 1 + old, P->ring_seq[old], st);
+      if (e) return e;
       if (P->h_summary[MA_SUMMARY_INTS * (1 + old) + 8] == 0) break;
     }
   }
@@ -511,17 +553,15 @@ int ma_plan_create(int n_max, int batch_capacity, const ma_options* opt, ma_plan
   }
   P->n_max = n_max;
   P->cap = batch_capacity;
-  if (hipMalloc(&P->d_prof, sizeof(unsigned long long)) != hipSuccess ||
-      hipMemset(P->d_prof, 0, sizeof(unsigned long long)) != hipSuccess ||
+  if (hipMalloc(&P->d_prof, 2 * sizeof(unsigned long long)) != hipSuccess ||
+      hipMemset(P->d_prof, 0, 2 * sizeof(unsigned long long)) != hipSuccess ||
       hipHostMalloc(&P->h_summary, sizeof(int) * 4 * MA_SUMMARY_INTS,
                     hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
-      hipHostGetDevicePointer((void**)&P->d_summary, P->h_summary, 0) != hipSuccess ||
-      hipEventCreateWithFlags(&P->ring_ev[0], hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&P->ring_ev[1], hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&P->ring_ev[2], hipEventDisableTiming) != hipSuccess) {
+      hipHostGetDevicePointer((void**)&P->d_summary, P->h_summary, 0) != hipSuccess) {
     ma_plan_destroy(P);
     return MA_ENOMEM;
   }
+  std::memset(P->h_summary, 0, sizeof(int) * 4 * MA_SUMMARY_INTS);  // no tag matches a launch (they start at 1)
   std::vector<int> ns(batch_capacity, n_max);
   int e = ensure_workspace(P, ns);
   if (e) {
@@ -539,8 +579,6 @@ void ma_plan_destroy(ma_plan* P) {
   if (P->d_state) hipFree(P->d_state);
   if (P->d_ids) hipFree(P->d_ids);
   if (P->h_summary) hipHostFree(P->h_summary);
-  for (hipEvent_t e : P->ring_ev)
-    if (e) hipEventDestroy(e);
   for (auto& kv : P->tw) hipFree(kv.second);
   for (auto& kv : P->mt) hipFree(kv.second);
   for (hipEvent_t e : P->ev) hipEventDestroy(e);
@@ -631,24 +669,29 @@ int ma_plan_get_tuning(const ma_plan* P, int n, ma_tuning* out) {
   return MA_OK;
 }
 
-int ma_plan_profile(ma_plan* P, int kind) {
-  if (!P || kind < MA_PROF_NONE || kind > MA_PROF_ROW_C) return MA_EINVAL;
+int ma_plan_profile(ma_plan* P, int kind, int every) {
+  if (!P || kind < MA_PROF_NONE || kind > MA_PROF_ROW_C || every < 1) return MA_EINVAL;
   HIP_TRY(hipDeviceSynchronize());
   P->prof_kind = kind;
+  P->prof_every = every;
+  P->prof_seq = 0;
   P->prof_ms = 0.0;
   P->prof_launches = 0;
   P->ev_used = 0;
-  HIP_TRY(hipMemset(P->d_prof, 0, sizeof(unsigned long long)));
+  HIP_TRY(hipMemset(P->d_prof, 0, 2 * sizeof(unsigned long long)));
   return MA_OK;
 }
 
-int ma_plan_profile_read(ma_plan* P, double* ms, long long* launches, double* bytes) {
+int ma_plan_profile_read(ma_plan* P, double* ms, long long* launches, double* bytes, long long* all_launches,
+                         double* all_bytes) {
   if (!P) return MA_EINVAL;
-  unsigned long long b = 0;
-  HIP_TRY(hipMemcpy(&b, P->d_prof, sizeof(b), hipMemcpyDeviceToHost));
+  unsigned long long b[2] = {0, 0};
+  HIP_TRY(hipMemcpy(b, P->d_prof, sizeof(b), hipMemcpyDeviceToHost));
   if (ms) *ms = P->prof_ms;
   if (launches) *launches = P->prof_launches;
-  if (bytes) *bytes = (double)b;
+  if (bytes) *bytes = (double)b[1];
+  if (all_launches) *all_launches = P->prof_seq;
+  if (all_bytes) *all_bytes = (double)b[0] + (double)b[1];
   return MA_OK;
 }
 

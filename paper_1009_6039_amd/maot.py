@@ -104,8 +104,9 @@ def load():
     lib.ma_solve_batched.argtypes = [P, I, ctypes.POINTER(I), ctypes.POINTER(P), ctypes.POINTER(P),
                                      ctypes.POINTER(P), D, D, ctypes.POINTER(P), ctypes.POINTER(P),
                                      ctypes.POINTER(Report), P]
-    lib.ma_plan_profile.argtypes = [P, I]
+    lib.ma_plan_profile.argtypes = [P, I, I]
     lib.ma_plan_profile_read.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_longlong),
+                                         ctypes.POINTER(D), ctypes.POINTER(ctypes.c_longlong),
                                          ctypes.POINTER(D)]
     lib.ma_plan_autotune.argtypes = [P, I, I, ctypes.c_char_p, ctypes.POINTER(Tuning), P]
     lib.ma_plan_set_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
@@ -219,16 +220,21 @@ class Plan:
         _check(load().ma_plan_set_options(self._h, ctypes.byref(self.options)), "ma_plan_set_options")
 
     # -- timing hook -------------------------------------------------------------
-    def profile(self, kernel_class):
-        """Times every launch of one kernel class ("residual", "row_a", "column", "row_c")."""
+    def profile(self, kernel_class, every=1):
+        """Times every `every`-th launch of one kernel class ("residual", "row_a",
+        "column", "row_c")."""
         k = PROF[kernel_class] if isinstance(kernel_class, str) else int(kernel_class)
-        _check(load().ma_plan_profile(self._h, k), "ma_plan_profile")
+        _check(load().ma_plan_profile(self._h, k, int(every)), "ma_plan_profile")
 
     def profile_read(self):
+        """Timed launches: summed event time, count, algorithmic bytes; all launches of
+        the class: count and algorithmic bytes."""
         ms, n, b = ctypes.c_double(), ctypes.c_longlong(), ctypes.c_double()
-        _check(load().ma_plan_profile_read(self._h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b)),
-               "ma_plan_profile_read")
-        return {"ms": ms.value, "launches": n.value, "bytes": b.value}
+        na, ba = ctypes.c_longlong(), ctypes.c_double()
+        _check(load().ma_plan_profile_read(self._h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b),
+                                           ctypes.byref(na), ctypes.byref(ba)), "ma_plan_profile_read")
+        return {"ms": ms.value, "launches": n.value, "bytes": b.value, "all_launches": na.value,
+                "all_bytes": ba.value}
 
     # -- autotuner -----------------------------------------------------------------
     def autotune(self, n, npairs, cache=None):
