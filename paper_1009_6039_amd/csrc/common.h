@@ -99,6 +99,21 @@ struct LaunchCtx {
   int forcing;           // MA_FORCING_*: fixed or adaptive GMRES tolerance per Newton direction
 };
 
+// Global-address-space view of a device buffer.  Accesses through it compile to
+// global_* instructions, which count only against the vector-memory counter; the
+// flat_* ones that generic pointers get count against the LDS counter as well, so
+// every LDS or cross-lane wait would also wait for loads still in flight.  (The
+// host pass, which only parses device code, keeps the plain pointer.)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define MA_GLOBAL_AS __attribute__((address_space(1)))
+#else
+#define MA_GLOBAL_AS
+#endif
+template <class T>
+__device__ __forceinline__ MA_GLOBAL_AS T* gmem(T* p) {
+  return (MA_GLOBAL_AS T*)p;
+}
+
 // GMRES tolerance of the pair's next Newton direction (eta 0: not adapted yet)
 __host__ __device__ inline double pair_eta(const PairState& s, const LaunchCtx& c) {
   return s.eta > 0.0 ? s.eta : c.gmres_tol;

@@ -145,10 +145,14 @@ __global__ __launch_bounds__((Cfg<N, G>::A_BLOCK)) void k_passA(LaunchCtx c, int
   __syncthreads();
 
   const int row0 = 2 * blockIdx.x * PPB;
-  float* V = d.V;
-  float* Vj = V + (long)jn * NN;
+  const auto V = gmem<float>(d.V);
+  const auto Vj = V + (long)jn * NN;
+  const auto R = gmem<const float>(d.r);
+  const auto coef = gmem<const float>(d.coef);
+  const auto X = gmem<const float>(d.x);
   // The thread's points first (their values in registers), then the Krylov vectors
-  // one at a time with all of the thread's loads of that vector in flight together.
+  // one at a time with all of the thread's loads of that vector in flight together,
+  // and those of the next vector issued before the current one is used.
   constexpr int PER = (PPB * N + BLOCK - 1) / BLOCK;
   constexpr bool FULL = (PPB * N) % BLOCK == 0;
   float va[PER], vb[PER];
@@ -165,11 +169,11 @@ __global__ __launch_bounds__((Cfg<N, G>::A_BLOCK)) void k_passA(LaunchCtx c, int
     const int ea = (row0 + 2 * pp) * N + jj, eb = ea + N;
     ea_[q] = ea;
     if (mode == PA_INIT) {
-      va[q] = (d.r[ea] + cst) * inv_tau;
-      vb[q] = (d.r[eb] + cst) * inv_tau;
+      va[q] = (R[ea] + cst) * inv_tau;
+      vb[q] = (R[eb] + cst) * inv_tau;
       if (scaled) {
-        va[q] *= trbar / (d.coef[ea] + d.coef[2 * NN + ea]);
-        vb[q] *= trbar / (d.coef[eb] + d.coef[2 * NN + eb]);
+        va[q] *= trbar / (coef[ea] + coef[2 * NN + ea]);
+        vb[q] *= trbar / (coef[eb] + coef[2 * NN + eb]);
       }
     } else if (mode == PA_PLAIN || mode == PA_STEP) {
       va[q] = V[ea];
@@ -178,28 +182,43 @@ __global__ __launch_bounds__((Cfg<N, G>::A_BLOCK)) void k_passA(LaunchCtx c, int
       va[q] = Vj[ea];
       vb[q] = Vj[eb];
     } else {  // PA_RECOVER
-      va[q] = usex ? d.x[ea] : 0.f;
-      vb[q] = usex ? d.x[eb] : 0.f;
+      va[q] = usex ? X[ea] : 0.f;
+      vb[q] = usex ? X[eb] : 0.f;
     }
   }
-  if (mode == PA_ARNOLDI) {
-    for (int l = 0; l < nv; ++l) {
-      const float* Vl = V + (long)l * NN;
-      const float cl = cf[l];
+  if (mode == PA_ARNOLDI || mode == PA_RECOVER) {
+    // v -= sum_l c_l V_l (Arnoldi) or x += sum_l y_l V_l (recovery), l in order
+    const float sg = mode == PA_ARNOLDI ? -1.f : 1.f;
+    float la[PER], lb[PER];
+    if (nv > 0) {
 #pragma unroll
       for (int q = 0; q < PER; ++q) {
-        va[q] -= cl * Vl[ea_[q]];
-        vb[q] -= cl * Vl[ea_[q] + N];
+        la[q] = V[ea_[q]];
+        lb[q] = V[ea_[q] + N];
       }
     }
-  } else if (mode == PA_RECOVER) {
     for (int l = 0; l < nv; ++l) {
-      const float* Vl = V + (long)l * NN;
-      const float cl = cf[l];
+      float na[PER], nb[PER];
+      if (l + 1 < nv) {
+        const auto Vn = V + (long)(l + 1) * NN;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+          na[q] = Vn[ea_[q]];
+          nb[q] = Vn[ea_[q] + N];
+        }
+      }
+      const float cl = sg * cf[l];
 #pragma unroll
       for (int q = 0; q < PER; ++q) {
-        va[q] += cl * Vl[ea_[q]];
-        vb[q] += cl * Vl[ea_[q] + N];
+        va[q] += cl * la[q];
+        vb[q] += cl * lb[q];
+      }
+      if (l + 1 < nv) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+          la[q] = na[q];
+          lb[q] = nb[q];
+        }
       }
     }
   }
@@ -224,6 +243,7 @@ __global__ __launch_bounds__((Cfg<N, G>::A_BLOCK)) void k_passA(LaunchCtx c, int
   if (!(mode == PA_ARNOLDI && jn >= c.m)) {
     __syncthreads();
     fft_lds<N, PPB, BLOCK, false, LAYOUT_ROWS>(lds, tw);
+    const auto H = gmem<float2>(d.H);
     for (int e = threadIdx.x; e < PPB * NH; e += BLOCK) {
       const int pp = e / NH, k = e % NH;
       const long ia = (long)(row0 + 2 * pp) * NH + k, ib = ia + NH;
@@ -238,8 +258,8 @@ __global__ __launch_bounds__((Cfg<N, G>::A_BLOCK)) void k_passA(LaunchCtx c, int
         oa = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
         ob = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
       }
-      d.H[ia] = oa;
-      d.H[ib] = ob;
+      H[ia] = oa;
+      H[ib] = ob;
     }
   }
 
@@ -273,16 +293,25 @@ __global__ __launch_bounds__((Cfg<N, G>::B_BLOCK)) void k_passB(LaunchCtx c, int
   __shared__ float2 S[N * CPB];
   __shared__ float2 Wb[N * CPB];
   const int s0 = blockIdx.x * CPB;
-  for (int e = threadIdx.x; e < N * CPB; e += BLOCK) {
-    const int i = e / CPB, cc = e % CPB;
-    S[e] = d.H[(long)i * NH + s0 + cc];
+  const auto H = gmem<const float2>(d.H);
+  const auto T = gmem<float2>(d.T);
+  {  // every column load of the thread in flight before the first LDS write
+    constexpr int PER = N * CPB / BLOCK;  // whole (static_assert in Cfg)
+    float2 h[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = threadIdx.x + q * BLOCK;
+      h[q] = H[(long)(e / CPB) * NH + s0 + e % CPB];
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) S[threadIdx.x + q * BLOCK] = h[q];
   }
   __syncthreads();
   fft_lds<N, CPB, BLOCK, false, LAYOUT_COLS>(S, tw);
   if (mode == PB_FORWARD) {
     for (int e = threadIdx.x; e < N * CPB; e += BLOCK) {
       const int i = e / CPB, cc = e % CPB;
-      d.T[(long)i * NH + s0 + cc] = S[e];
+      T[(long)i * NH + s0 + cc] = S[e];
     }
     return;
   }
@@ -329,7 +358,7 @@ __global__ __launch_bounds__((Cfg<N, G>::B_BLOCK)) void k_passB(LaunchCtx c, int
       __syncthreads();
     }
     fft_lds<N, CPB, BLOCK, true, LAYOUT_COLS>(L, tw);
-    float2* To = d.T + (long)o * N * NH;
+    const auto To = T + (long)o * N * NH;
     for (int e = threadIdx.x; e < N * CPB; e += BLOCK) {
       const int i = e / CPB, c2 = e % CPB;
       To[(long)i * NH + s0 + c2] = L[e];
@@ -358,9 +387,9 @@ __global__ __launch_bounds__((Cfg<N, G>::C_BLOCK)) void k_passC(LaunchCtx c, int
   __shared__ float2 lds[5 * PPB * N];
   __shared__ double red[(BLOCK / 64) * (MA_MMAX + 1)];
   const int row0 = 2 * blockIdx.x * PPB;
-  const float2* T0 = d.T;
-  const float2* T1 = d.T + NN / 2;
-  const float2* T2 = d.T + NN;
+  const auto T0 = gmem<const float2>(d.T);
+  const auto T1 = T0 + NN / 2;
+  const auto T2 = T0 + NN;
 
   if (mode != PC_MATVEC) {
     // theta = Lbar^{-1} sigma: one complex inverse transform per row pair
@@ -395,12 +424,31 @@ __global__ __launch_bounds__((Cfg<N, G>::C_BLOCK)) void k_passC(LaunchCtx c, int
     return;
   }
 
-  // five complex inverse transforms per row pair
-  for (int e = threadIdx.x; e < PPB * NH; e += BLOCK) {
+  // five complex inverse transforms per row pair; every spectrum load of the thread
+  // is issued before the first LDS write
+  constexpr int IT1 = (PPB * NH + BLOCK - 1) / BLOCK;
+  constexpr bool FULL1 = (PPB * NH) % BLOCK == 0;
+  float2 tl[IT1][6];
+#pragma unroll
+  for (int q = 0; q < IT1; ++q) {
+    const int e = threadIdx.x + q * BLOCK;
+    if (!FULL1 && e >= PPB * NH) continue;
     const int pp = e / NH, k = e % NH;
     const long ia = (long)(row0 + 2 * pp) * NH + k, ib = ia + NH;
-    const float2 t0a = T0[ia], t1a = T1[ia], t2a = T2[ia];
-    const float2 t0b = T0[ib], t1b = T1[ib], t2b = T2[ib];
+    tl[q][0] = T0[ia];
+    tl[q][1] = T1[ia];
+    tl[q][2] = T2[ia];
+    tl[q][3] = T0[ib];
+    tl[q][4] = T1[ib];
+    tl[q][5] = T2[ib];
+  }
+#pragma unroll
+  for (int q = 0; q < IT1; ++q) {
+    const int e = threadIdx.x + q * BLOCK;
+    if (!FULL1 && e >= PPB * NH) continue;
+    const int pp = e / NH, k = e % NH;
+    const float2 t0a = tl[q][0], t1a = tl[q][1], t2a = tl[q][2];
+    const float2 t0b = tl[q][3], t1b = tl[q][4], t2b = tl[q][5];
     float2* L = lds + 5 * pp * N;
     if (k == 0) {
       // DC (.x) and Nyquist (.y) are real; the first-derivative multiplier vanishes at
@@ -428,50 +476,83 @@ __global__ __launch_bounds__((Cfg<N, G>::C_BLOCK)) void k_passC(LaunchCtx c, int
   __syncthreads();
   fft_lds<N, 5 * PPB, BLOCK, true, LAYOUT_ROWS>(lds, tw);
 
-  float* W = d.V + (long)(j + 1) * NN;
-  const float* coef = d.coef;
+  const auto V = gmem<float>(d.V);
+  const auto W = V + (long)(j + 1) * NN;
+  const auto coef = gmem<const float>(d.coef);
   const bool scaled = c.precond == MA_PRECOND_DIAG;
   const float trbar = (float)(s.abar[0] + s.abar[2]);
-  // w at the thread's points, then the inner products <w, v_l> one Krylov vector at a
-  // time with all of the thread's loads of v_l in flight together
+  // w at the thread's points, then the inner products <w, v_l>
   constexpr int PER = (PPB * N + BLOCK - 1) / BLOCK;
   constexpr bool FULL = (PPB * N) % BLOCK == 0;
   float wa[PER], wb[PER];
   int ea_[PER];  // offset of the first row's point; a point past the end reads the
                  // block's first point (in bounds) with weight zero
+  // the coefficients at all of the thread's points are loaded before the first is used
+  float ca[PER][5], cb[PER][5];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int e = threadIdx.x + q * BLOCK;
     ea_[q] = row0 * N;
+    if (!FULL && e >= PPB * N) continue;
+    const int pp = e / N, jj = e % N;
+    ea_[q] = (row0 + 2 * pp) * N + jj;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      ca[q][k] = coef[k * NN + ea_[q]];
+      cb[q][k] = coef[k * NN + ea_[q] + N];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = threadIdx.x + q * BLOCK;
     wa[q] = wb[q] = 0.f;
     if (!FULL && e >= PPB * N) continue;
     const int pp = e / N, jj = e % N;
-    const int ea = (row0 + 2 * pp) * N + jj, eb = ea + N;
-    ea_[q] = ea;
+    const int ea = ea_[q], eb = ea + N;
     const float2* L = lds + 5 * pp * N + jj;
     const float2 z0 = L[0], z1 = L[N], z2 = L[2 * N], z3 = L[3 * N], z4 = L[4 * N];
-    float a = coef[ea] * z0.x + 2.f * coef[NN + ea] * z1.x + coef[2 * NN + ea] * z4.x +
-              coef[3 * NN + ea] * z0.y + coef[4 * NN + ea] * z1.y;
-    float b = coef[eb] * z2.x + 2.f * coef[NN + eb] * z3.x + coef[2 * NN + eb] * z4.y +
-              coef[3 * NN + eb] * z2.y + coef[4 * NN + eb] * z3.y;
+    float a = ca[q][0] * z0.x + 2.f * ca[q][1] * z1.x + ca[q][2] * z4.x + ca[q][3] * z0.y + ca[q][4] * z1.y;
+    float b = cb[q][0] * z2.x + 2.f * cb[q][1] * z3.x + cb[q][2] * z4.y + cb[q][3] * z2.y + cb[q][4] * z3.y;
     if (scaled) {  // left scaling by 1 / D(x), D = (a11 + a22) / (abar11 + abar22)
-      a *= trbar / (coef[ea] + coef[2 * NN + ea]);
-      b *= trbar / (coef[eb] + coef[2 * NN + eb]);
+      a *= trbar / (ca[q][0] + ca[q][2]);
+      b *= trbar / (cb[q][0] + cb[q][2]);
     }
     W[ea] = a;
     W[eb] = b;
     wa[q] = a;
     wb[q] = b;
   }
-  // block reduction of the j+1 inner products (fixed order); folded by k_dots_finalize
+  // block reduction of the j+1 inner products (fixed order); folded by k_dots_finalize.
+  // The loads of v_{l+1} are issued before the reduction of <w, v_l>.
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  float va[PER], vb[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    va[q] = V[ea_[q]];
+    vb[q] = V[ea_[q] + N];
+  }
   for (int l = 0; l <= j; ++l) {
-    const float* Vl = d.V + (long)l * NN;
+    float na[PER], nb[PER];
+    if (l < j) {
+      const auto Vn = V + (long)(l + 1) * NN;
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        na[q] = Vn[ea_[q]];
+        nb[q] = Vn[ea_[q] + N];
+      }
+    }
     float acc = 0.f;
 #pragma unroll
-    for (int q = 0; q < PER; ++q) acc += wa[q] * Vl[ea_[q]] + wb[q] * Vl[ea_[q] + N];
+    for (int q = 0; q < PER; ++q) acc += wa[q] * va[q] + wb[q] * vb[q];
     const double v = wave_sum((double)acc);
     if (lane == 0) red[wid * (MA_MMAX + 1) + l] = v;
+    if (l < j) {
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        va[q] = na[q];
+        vb[q] = nb[q];
+      }
+    }
   }
   __syncthreads();
   if (threadIdx.x <= j) {
