@@ -232,7 +232,7 @@ __global__ __launch_bounds__(MA_BLOCK) void k_residual(LaunchCtx c) {
   const int n = d.n;
   const int nbx = n / TX;
   const int i0 = (blockIdx.x / nbx) * TY, j0 = (blockIdx.x % nbx) * TX;
-  const double* __restrict__ u = d.u;
+  const auto u = gmem<const double>(d.u);
   for (int e = threadIdx.x; e < (TY + 4) * LW; e += MA_BLOCK) {
     const int li = e / LW, lj = e % LW;
     int gi = i0 + li - 2, gj = j0 + lj - 2;  // within [-2, n + 2): one periodic fold
@@ -253,7 +253,10 @@ __global__ __launch_bounds__(MA_BLOCK) void k_residual(LaunchCtx c) {
   acc[13] = 1e300;   // min r
   acc[14] = 0.0;     // non-finite count
   acc[15] = 0.0;
-  const GS* __restrict__ gs = d.gs;
+  const auto gs = gmem<const GS>(d.gs);
+  const auto F = gmem<const double>(d.f);
+  const auto R = gmem<float>(d.r);
+  const auto coef = gmem<float>(d.coef);
   const long nn = (long)n * n;
   constexpr int TROWS = MA_BLOCK / TX;
   const int tx = threadIdx.x % TX, ty0 = threadIdx.x / TX;
@@ -295,17 +298,17 @@ __global__ __launch_bounds__(MA_BLOCK) void k_residual(LaunchCtx c) {
     const double det = (1.0 + u11) * (1.0 + u22) - u12 * u12;
     const double fn = gy * det;
     const long e = (long)i * n + j;
-    const double fv = d.f[e];
+    const double fv = F[e];
     const double rr = fv - fn;
     const double a11 = gy * (1.0 + u22), a22 = gy * (1.0 + u11), a12 = -gy * u12;
     const double b1 = c.op_mode == MA_OP_NO_DRIFT ? 0.0 : det * gy1;
     const double b2 = c.op_mode == MA_OP_NO_DRIFT ? 0.0 : det * gy2;
-    d.r[e] = (float)rr;
-    d.coef[e] = (float)a11;
-    d.coef[nn + e] = (float)a12;
-    d.coef[2 * nn + e] = (float)a22;
-    d.coef[3 * nn + e] = (float)b1;
-    d.coef[4 * nn + e] = (float)b2;
+    R[e] = (float)rr;
+    coef[e] = (float)a11;
+    coef[nn + e] = (float)a12;
+    coef[2 * nn + e] = (float)a22;
+    coef[3 * nn + e] = (float)b1;
+    coef[4 * nn + e] = (float)b2;
     // periodic Simpson weights (reading P7): 2h/3 at even nodes, 4h/3 at odd ones
     const double w = (double)((i & 1) ? 4 : 2) * (double)((j & 1) ? 4 : 2) * wnorm;
     acc[0] += fn;
