@@ -106,3 +106,29 @@ def test_tuned_batched_solve_matches_untuned(maot):
     finally:
         base.close()
         tuned.close()
+
+
+@pytest.mark.parametrize("every", [1, 3])
+def test_timing_hook_times_every_kth_launch(maot, blob128, every):
+    # the timing hook of one kernel class: every `every`-th launch is event-timed and
+    # counted in the timed bytes; the byte counter over all launches is the same for
+    # any stride (the same solve), and a timed launch carries bytes and time
+    f, g, _ = blob128
+    n = f.shape[0]
+    p = maot.Plan(n_max=n, batch_capacity=2, damping_policy="backtrack", gmres_tol=0.1, max_newton=300)
+    try:
+        totals = []
+        for stride in (1, every):
+            p.profile("row_c", stride)
+            p.solve_batched([dev(f), dev(f)], [dev(g), dev(g)], damping=1.0, tol=1e-9, want_map=False)
+            r = p.profile_read()
+            p.profile("none")
+            assert r["all_launches"] > 0
+            assert r["launches"] == -(-r["all_launches"] // stride)  # launches 0, k, 2k, ...
+            assert 0.0 < r["bytes"] <= r["all_bytes"] and r["ms"] > 0.0
+            totals.append((r["all_launches"], r["all_bytes"]))
+        assert totals[0] == totals[1]
+        with pytest.raises(maot.MAError):
+            p.profile("row_c", 0)
+    finally:
+        p.close()
