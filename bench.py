@@ -29,7 +29,7 @@ import time
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-TRAFFIC_FILE = "row_c_%d_batch64_hbm_traffic.md"  # written by paper_1009_6039_amd.rocprof_summary traffic
+TRAFFIC_FILE = "row_c_%d_batch%d_hbm_traffic.md"  # written by paper_1009_6039_amd.rocprof_summary traffic
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 METRIC = "Newton-solved pairs/sec at 512^2 to residual 1e-6; learned-init vs plain"
 # linear-solve method -> plan options (symbols of the derivatives, left scaling)
@@ -55,7 +55,9 @@ def parse():
                          "from {128, 256, 384, 512} (zero init only)")
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--batch", type=int, default=256,
+                    help="pairs per batched solve (one step); a larger batch spreads the last, nearly "
+                         "empty ticks of the slowest pairs over more pairs")
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--gmres-tol", type=float, default=None, help="overrides every method's GMRES tolerance")
@@ -65,9 +67,10 @@ def parse():
                          % ", ".join(sorted(METHODS)))
     ap.add_argument("--profile-class", default="row_c",
                     help="kernel class timed for the roofline: residual, row_a, column, row_c")
-    ap.add_argument("--profile-every", type=int, default=7,
+    ap.add_argument("--profile-every", type=int, default=1,
                     help="time every k-th launch of that class with HIP events (events add a few "
-                         "microseconds of queue time per timed launch)")
+                         "microseconds of queue time per timed launch; launch durations vary tenfold "
+                         "over a solve, so a sampled average can be off by 20%%)")
     ap.add_argument("--init", default="both", choices=("both", "zero", "learned"),
                     help="arms to time; value is the learned arm unless only zero is run")
     ap.add_argument("--weights", default=os.path.join(HERE, "paper_1009_6039_amd", "warmstart_256.npz"))
@@ -272,7 +275,7 @@ def main():
     kname = {"row_c": "k_passC<%d, %d>", "row_a": "k_passA<%d, %d>", "column": "k_passB<%d, %d>"}.get(
         args.profile_class, "")
     kname = kname % (N, var) if kname and args.workload == "blobs" else ""  # the kernel as rocprofv3 names it
-    rec = read_traffic_record(os.path.join(HERE, "profiles", TRAFFIC_FILE % N), kname) if kname else None
+    rec = read_traffic_record(os.path.join(HERE, "profiles", TRAFFIC_FILE % (N, B)), kname) if kname else None
     if rec and rec.get("variant") != var:
         rec = None  # counters taken with another launch geometry
     bpl = prof["all_bytes"] / max(prof["all_launches"], 1)  # over every launch, as the counters are
