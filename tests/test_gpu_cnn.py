@@ -163,3 +163,44 @@ def test_warm_start_matches_oracle(maot, n, dil):
             assert abs(got.mean()) < 1e-6 * np.max(np.abs(ref))
     finally:
         net.close()
+
+
+def test_benchmark_configuration_learned_start_matches_oracle(maot):
+    # the configuration bench.py times: 256 blob pairs at 512^2 in one batched call,
+    # learned start from the committed network, the fast linear solve (fd4 symbols,
+    # scaled system, tolerance 0.2 with adaptive forcing), residual 1e-6.  Every pair
+    # must converge; two sampled pairs are compared with the oracle, solved from the
+    # oracle's own network start (BF16 emulation) to 1e-10.
+    import json
+    import os
+    from oracle import ma
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    d = np.load(os.path.join(root, "paper_1009_6039_amd", "warmstart_256.npz"), allow_pickle=False)
+    meta = json.loads(str(d["meta"]))
+    B, N = 256, 512
+    pairs = [W.blobs(N, W.seed_for(1, q)) for q in range(B)]
+    opts = dict(damping_policy="backtrack", symbol="fd4", precond="diag", gmres_tol=0.2, forcing="adaptive")
+    net = maot.WarmStartNet(layers=meta["layers"], channels=meta["channels"], n_net=meta["n_net"], max_batch=B,
+                            dilations=meta["dilations"])
+    p = maot.Plan(n_max=N, batch_capacity=B, max_newton=500, **opts)
+    try:
+        net.set_params(d["params"].astype(np.float32))
+        fs = [torch.from_numpy(a).cuda() for a, _ in pairs]
+        gs = [torch.from_numpy(b).cuda() for _, b in pairs]
+        psi0 = net.warm_start(fs, gs)
+        psis, _, reps = p.solve_batched(fs, gs, damping=1.0, tol=1e-6, psi0s=psi0)
+        assert all(r["status"] == 0 and r["res_rms"] <= 1e-6 for r in reps)
+        assert sum(r["warm_steps"] for r in reps) == B
+        shaped = cnn.unflatten_params(d["params"], meta["layers"], meta["channels"])
+        for q in (0, 137):
+            print("benchmark configuration: sample pair %d" % q, flush=True)
+            f, g = pairs[q]
+            start = cnn.warm_start(f, g, shaped, meta["n_net"], dilations=meta["dilations"])
+            ref, _, rr = ma.solve(f, g, tau=1.0, tol=1e-10, max_newton=500, psi0=start, **opts)
+            assert rr.status == ma.OK
+            err = np.max(np.abs(psis[q].cpu().numpy() - ref)) / np.max(np.abs(ref))
+            print("pair %d: newton %d, max|psi - psi_oracle| / max|psi| = %.2e" % (q, reps[q]["newton_iters"], err))
+            assert err <= 1e-6
+    finally:
+        p.close()
+        net.close()
