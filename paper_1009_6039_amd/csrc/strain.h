@@ -288,10 +288,9 @@ __global__ __launch_bounds__((Cfg<N, G>::B_BLOCK)) void k_passB(LaunchCtx c, int
   if (!run) return;
   count_bytes(c, mode == PB_MATVEC ? 16.0 : 8.0, N);  // half spectrum in, one or three out
 
-  // S: the column spectra, then rhobar * sigmahat; W: work buffer for derived spectra.
+  // S: the column spectra, then rhobar * sigmahat, then each output spectrum in turn.
   // Element (row or wavenumber e, column cc) sits at e * CPB + cc.
   __shared__ float2 S[N * CPB];
-  __shared__ float2 Wb[N * CPB];
   const int s0 = blockIdx.x * CPB;
   const auto H = gmem<const float2>(d.H);
   const auto T = gmem<float2>(d.T);
@@ -343,25 +342,31 @@ __global__ __launch_bounds__((Cfg<N, G>::B_BLOCK)) void k_passB(LaunchCtx c, int
     if (qm != q) S[qm * CPB + cc] = vm;
   }
   __syncthreads();
-  // derived spectra 2 pi i k1 and -(2 pi k1)^2 (matvec only), then the plain one in place
+  // derived spectra 2 pi i k1 and -(2 pi k1)^2 (matvec only), then the plain one.  The
+  // multiplied spectrum stays in registers (each thread's own elements), and every
+  // output is written back into S from them and transformed in place: one LDS buffer
+  // per block instead of two, so twice the blocks fit on a CU.
+  constexpr int PER = N * CPB / BLOCK;  // whole (static_assert in Cfg)
+  float2 sv[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) sv[k] = S[threadIdx.x + k * BLOCK];
   const int nout = mode == PB_MATVEC ? 3 : 1;
   for (int oo = 0; oo < nout; ++oo) {
     const int o = (oo + 1) % 3 == 0 || nout == 1 ? 0 : oo + 1;  // order 1, 2, 0
-    float2* L = (o == 0) ? S : Wb;
-    if (o != 0) {
-      for (int e = threadIdx.x; e < N * CPB; e += BLOCK) {
-        const int q = e / CPB;
-        const float2 m = c.mt[q];
-        const float2 v = S[e];
-        Wb[e] = (o == 1) ? times_i(m.x, v) : cscale(v, m.y);
+    if (oo > 0 || o != 0) {  // S still holds the plain spectrum for a lone output 0
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        const int e = threadIdx.x + k * BLOCK;
+        const float2 m = c.mt[e / CPB];
+        S[e] = o == 0 ? sv[k] : ((o == 1) ? times_i(m.x, sv[k]) : cscale(sv[k], m.y));
       }
       __syncthreads();
     }
-    fft_lds<N, CPB, BLOCK, true, LAYOUT_COLS>(L, tw);
+    fft_lds<N, CPB, BLOCK, true, LAYOUT_COLS>(S, tw);
     const auto To = T + (long)o * N * NH;
     for (int e = threadIdx.x; e < N * CPB; e += BLOCK) {
       const int i = e / CPB, c2 = e % CPB;
-      To[(long)i * NH + s0 + c2] = L[e];
+      To[(long)i * NH + s0 + c2] = S[e];
     }
     __syncthreads();
   }
