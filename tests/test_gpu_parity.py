@@ -440,3 +440,40 @@ def test_adaptive_forcing_solves_pairs_that_stall_with_fixed_forcing(maot, q):
         assert np.max(np.abs(host(psi) - ref)) <= 1e-6 * np.max(np.abs(ref))
     finally:
         p.close()
+
+
+def test_bad_arguments_are_rejected_and_a_larger_batch_grows_the_workspace(maot):
+    # hard failures (code -1, nothing solved): damping < 1, tol <= 0, an empty batch,
+    # a grid side the transforms do not support.  A batch beyond the plan's capacity,
+    # with a grid larger than its n_max, grows the workspace; each pair's result is
+    # bitwise the one it gets alone.
+    N = 64
+    opts = dict(damping_policy="backtrack", gmres_tol=0.1, max_newton=300)
+    f, g = W.blobs(N, W.seed_for(1, 11))
+    f2, g2 = W.blobs(2 * N, W.seed_for(1, 12))
+    p = maot.Plan(n_max=N, batch_capacity=1, **opts)
+    q = maot.Plan(n_max=2 * N, batch_capacity=1, **opts)
+    try:
+        for kw in (dict(damping=0.5), dict(tol=0.0), dict(tol=-1e-6)):
+            args = dict(damping=1.0, tol=1e-8)
+            args.update(kw)
+            with pytest.raises(maot.MAError) as e:
+                p.solve_batched([dev(f)], [dev(g)], **args)
+            assert e.value.code == -1
+        with pytest.raises(maot.MAError) as e:
+            p.solve_batched([], [])
+        assert e.value.code == -1
+        bad = np.ones((72, 72))  # not a multiple of 16
+        with pytest.raises(maot.MAError) as e:
+            p.solve_batched([dev(bad)], [dev(bad)])
+        assert e.value.code == -1
+        alone, _, _ = p.solve_batched([dev(f)], [dev(g)], damping=1.0, tol=1e-8)
+        alone2, _, _ = q.solve_batched([dev(f2)], [dev(g2)], damping=1.0, tol=1e-8)
+        psis, _, reps = p.solve_batched([dev(f), dev(f2), dev(f)], [dev(g), dev(g2), dev(g)], damping=1.0,
+                                        tol=1e-8)
+        assert all(r["status"] == 0 and r["res_rms"] <= 1e-8 for r in reps)
+        assert np.array_equal(host(psis[0]), host(alone[0])) and np.array_equal(host(psis[2]), host(alone[0]))
+        assert np.array_equal(host(psis[1]), host(alone2[0]))
+    finally:
+        p.close()
+        q.close()
