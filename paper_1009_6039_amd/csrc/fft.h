@@ -164,6 +164,26 @@ __device__ __forceinline__ void fft_stages(float2* lds, const float2* __restrict
   }
 }
 
+// Column transforms whose first stage starts from registers.  Valid when every thread
+// runs exactly one butterfly of the first stage (BLOCK = NF * N / R0, R0 the first
+// radix) and holds its inputs: x[r] = element j + r N/R0 of column t, with
+// t = threadIdx.x % NF and j = threadIdx.x / NF (the element order e * NF + t read
+// with stride BLOCK).  The first stage has no twiddles; its outputs go to LDS in the
+// Stockham order and the later stages run in LDS as in fft_lds.  The caller makes
+// sure no thread still reads `lds` before the call; the routine ends with a barrier.
+template <int N, int NF, int BLOCK, bool INV>
+__device__ __forceinline__ void fft_cols_from_regs(float2* lds, const float2* __restrict__ tw,
+                                                   float2 (&x)[pick_radix(N)]) {
+  constexpr int R0 = pick_radix(N);
+  static_assert(BLOCK == NF * (N / R0), "one first-stage butterfly per thread");
+  const int t = threadIdx.x % NF, j = threadIdx.x / NF;
+  dft<R0, INV>(x);
+#pragma unroll
+  for (int r = 0; r < R0; ++r) lds[lds_index<N, NF, LAYOUT_COLS>(t, j * R0 + r)] = x[r];
+  __syncthreads();
+  fft_stages<N, R0, NF, BLOCK, INV, LAYOUT_COLS>(lds, tw);
+}
+
 // In-place transforms of NF sequences in LDS.  Caller synchronises before (data
 // written) — the routine ends with a barrier so results are visible on return.
 template <int N, int NF, int BLOCK, bool INV, int LAYOUT>

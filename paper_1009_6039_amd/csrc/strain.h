@@ -294,6 +294,12 @@ __global__ __launch_bounds__((Cfg<N, G>::B_BLOCK)) void k_passB(LaunchCtx c, int
   const int s0 = blockIdx.x * CPB;
   const auto H = gmem<const float2>(d.H);
   const auto T = gmem<float2>(d.T);
+  // With one first-stage butterfly per thread, the thread's elements (rows e / CPB
+  // for e = threadIdx.x + q BLOCK of column threadIdx.x % CPB) are that butterfly's
+  // inputs: every transform starts from registers (one LDS pass and two barriers
+  // fewer each); other geometries stage everything through LDS.
+  constexpr int R0 = pick_radix(N);
+  constexpr bool REG1 = BLOCK == CPB * (N / R0);
   {  // every column load of the thread in flight before the first LDS write
     constexpr int PER = N * CPB / BLOCK;  // whole (static_assert in Cfg)
     float2 h[PER];
@@ -302,11 +308,15 @@ __global__ __launch_bounds__((Cfg<N, G>::B_BLOCK)) void k_passB(LaunchCtx c, int
       const int e = threadIdx.x + q * BLOCK;
       h[q] = H[(long)(e / CPB) * NH + s0 + e % CPB];
     }
+    if constexpr (REG1) {
+      fft_cols_from_regs<N, CPB, BLOCK, false>(S, tw, h);
+    } else {
 #pragma unroll
-    for (int q = 0; q < PER; ++q) S[threadIdx.x + q * BLOCK] = h[q];
+      for (int q = 0; q < PER; ++q) S[threadIdx.x + q * BLOCK] = h[q];
+      __syncthreads();
+      fft_lds<N, CPB, BLOCK, false, LAYOUT_COLS>(S, tw);
+    }
   }
-  __syncthreads();
-  fft_lds<N, CPB, BLOCK, false, LAYOUT_COLS>(S, tw);
   if (mode == PB_FORWARD) {
     for (int e = threadIdx.x; e < N * CPB; e += BLOCK) {
       const int i = e / CPB, cc = e % CPB;
@@ -350,19 +360,31 @@ __global__ __launch_bounds__((Cfg<N, G>::B_BLOCK)) void k_passB(LaunchCtx c, int
   float2 sv[PER];
 #pragma unroll
   for (int k = 0; k < PER; ++k) sv[k] = S[threadIdx.x + k * BLOCK];
+  // the register path writes elements other threads are still reading here
+  if constexpr (REG1) __syncthreads();
   const int nout = mode == PB_MATVEC ? 3 : 1;
   for (int oo = 0; oo < nout; ++oo) {
     const int o = (oo + 1) % 3 == 0 || nout == 1 ? 0 : oo + 1;  // order 1, 2, 0
-    if (oo > 0 || o != 0) {  // S still holds the plain spectrum for a lone output 0
+    if constexpr (REG1) {
+      float2 x[PER];
 #pragma unroll
       for (int k = 0; k < PER; ++k) {
-        const int e = threadIdx.x + k * BLOCK;
-        const float2 m = c.mt[e / CPB];
-        S[e] = o == 0 ? sv[k] : ((o == 1) ? times_i(m.x, sv[k]) : cscale(sv[k], m.y));
+        const float2 m = c.mt[(threadIdx.x + k * BLOCK) / CPB];
+        x[k] = o == 0 ? sv[k] : ((o == 1) ? times_i(m.x, sv[k]) : cscale(sv[k], m.y));
       }
-      __syncthreads();
+      fft_cols_from_regs<N, CPB, BLOCK, true>(S, tw, x);
+    } else {
+      if (oo > 0 || o != 0) {  // S still holds the plain spectrum for a lone output 0
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+          const int e = threadIdx.x + k * BLOCK;
+          const float2 m = c.mt[e / CPB];
+          S[e] = o == 0 ? sv[k] : ((o == 1) ? times_i(m.x, sv[k]) : cscale(sv[k], m.y));
+        }
+        __syncthreads();
+      }
+      fft_lds<N, CPB, BLOCK, true, LAYOUT_COLS>(S, tw);
     }
-    fft_lds<N, CPB, BLOCK, true, LAYOUT_COLS>(S, tw);
     const auto To = T + (long)o * N * NH;
     for (int e = threadIdx.x; e < N * CPB; e += BLOCK) {
       const int i = e / CPB, c2 = e % CPB;
