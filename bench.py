@@ -76,7 +76,12 @@ def parse():
     ap.add_argument("--weights", default=os.path.join(HERE, "paper_1009_6039_amd", "warmstart_256.npz"))
     ap.add_argument("--tune-cache", default=os.path.join(HERE, "paper_1009_6039_amd", "tune_cache.json"),
                     help="autotuner cache (JSON); 'none' skips the autotuner (default geometries)")
-    ap.add_argument("--cpu-pairs", type=int, default=4, help="pairs in the oracle's timed sample")
+    ap.add_argument("--cpu-pairs", type=int, default=0,
+                    help="pairs in the oracle's timed sample (0: one per worker)")
+    ap.add_argument("--cpu-workers", type=int, default=min(16, os.cpu_count() or 1),
+                    help="single-threaded oracle processes (the host cores used)")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the mixed-size batch and the 2048^2 pair reported beside the headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB mebibytes (scales HBM byte counters)")
@@ -109,25 +114,110 @@ def load_weights(path):
     return d["params"].astype(np.float32), meta
 
 
-def cpu_baseline(pairs, args, params=None, meta=None):
-    """The FP64 oracle on a sample of pairs of the same workload, pinned to one thread:
-    the network's start (BF16 emulation) when params are given, then the solve."""
+def _oracle_worker(job):
+    """One pair in a worker process pinned to one thread: (seconds, psi)."""
+    f, g, opts, params, meta = job
     from threadpoolctl import threadpool_limits
     sys.path.insert(0, HERE)
     from oracle import cnn, ma
-    psis = []
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        for f, g in pairs:
-            psi0 = None
-            if params is not None:
-                shaped = cnn.unflatten_params(params, meta["layers"], meta["channels"])
-                psi0 = cnn.warm_start(f, g, shaped, meta["n_net"], dilations=meta.get("dilations"))
-            psi, _, _ = ma.solve(f, g, tau=1.0, tol=args.tol, damping_policy=args.damping_policy,
-                                 max_newton=MAX_NEWTON, psi0=psi0, **method_options(args.method0, args))
-            psis.append(psi)
-        dt = time.perf_counter() - t0
-    return psis, dt
+        psi0 = None
+        if params is not None:
+            shaped = cnn.unflatten_params(params, meta["layers"], meta["channels"])
+            psi0 = cnn.warm_start(f, g, shaped, meta["n_net"], dilations=meta.get("dilations"))
+        psi, _, _ = ma.solve(f, g, psi0=psi0, **opts)
+        return os.getpid(), time.perf_counter() - t0, psi
+
+
+def cpu_baseline(pairs, args, params=None, meta=None):
+    """The FP64 oracle on a sample of pairs of the same workload, one single-threaded
+    process per host core (the network's start, BF16-emulated, when params are given,
+    then the solve).  Returns (psis, pairs/s summed over the workers, workers, CPU seconds)."""
+    import multiprocessing as mp
+    opts = dict(tau=1.0, tol=args.tol, damping_policy=args.damping_policy, max_newton=MAX_NEWTON,
+                **method_options(args.method0, args))
+    jobs = [(f, g, opts, params, meta) for f, g in pairs]
+    workers = min(len(jobs), args.cpu_workers)
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[k] = "1"
+    with mp.get_context("spawn").Pool(workers) as pool:
+        out = pool.map(_oracle_worker, jobs, chunksize=1)
+    # each process solves its pairs one after another: its rate is pairs / its busy time
+    per = {}
+    for pid, dt, _ in out:
+        per.setdefault(pid, []).append(dt)
+    rate = sum(len(v) / sum(v) for v in per.values())
+    return [psi for _, _, psi in out], rate, workers, sum(dt for _, dt, _ in out)
+
+
+def extra_configs(args, maot, W, method, tuning_cache):
+    """The other full-size configurations, timed beside the headline (not part of
+    `value`): a batch of 256 blob pairs with sides drawn from {128, 256, 384, 512}
+    (zero start, the headline's linear solve, one batched call), and one 2048^2
+    smooth-noise pair with the paper's method (spectral symbols, fixed tau = 1, GMRES
+    tolerance 1e-2) and with the headline's, its potential compared with the oracle's
+    stored solution at every 16th node (tests/golden/c2_noise_2048_reference.npz)."""
+    import torch
+    res = {}
+    cache = None if tuning_cache == "none" else tuning_cache
+    # mixed-size batch
+    sizes = W.mixed_sizes(256, W.seed_for(3, 0))
+    pairs = [W.blobs(n, W.seed_for(3, q)) for q, n in enumerate(sizes)]
+    fs = [torch.from_numpy(f).cuda() for f, _ in pairs]
+    gs = [torch.from_numpy(g).cuda() for _, g in pairs]
+    plan = maot.Plan(n_max=512, batch_capacity=256, damping_policy=args.damping_policy, max_newton=MAX_NEWTON,
+                     **method_options(method, args))
+    for n in sorted(set(sizes)):
+        plan.autotune(n, sizes.count(n), cache)
+    plan.solve_batched(fs, gs, damping=1.0, tol=args.tol, want_map=True)  # warm-up
+    reps_all, t = [], []
+    for _ in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, reps = plan.solve_batched(fs, gs, damping=1.0, tol=args.tol, want_map=True)
+        torch.cuda.synchronize()
+        t.append(time.perf_counter() - t0)
+        reps_all += reps
+    plan.close()
+    bad = sum(r["status"] != 0 or r["res_rms"] > args.tol for r in reps_all)
+    res["mixed_256"] = {"workload": "256 blob pairs, sides %s, zero start, %s linear solve, rms residual %.0e"
+                                    % (", ".join("%d x %d" % (n, sizes.count(n)) for n in sorted(set(sizes))),
+                                       method, args.tol),
+                        "value": round((len(reps_all) - bad) / sum(t), 3), "unit": "pairs/s", "unsolved": bad,
+                        "ms_per_batch": round(1e3 * sum(t) / len(t), 3), **summary(reps_all)}
+    del fs, gs
+    # one 2048^2 pair
+    N = 2048
+    f, g = W.smooth_noise(N, W.seed_for(2, 0))
+    fd, gd = torch.from_numpy(f).cuda(), torch.from_numpy(g).cuda()
+    ref_path = os.path.join(HERE, "tests", "golden", "c2_noise_2048_reference.npz")
+    ref = np.load(ref_path, allow_pickle=False) if os.path.exists(ref_path) else None
+    for name, opts in (("paper", dict(damping_policy="fixed", symbol="spectral", gmres_tol=1e-2)),
+                       (method, dict(damping_policy=args.damping_policy, **method_options(method, args)))):
+        plan = maot.Plan(n_max=N, batch_capacity=1, max_newton=MAX_NEWTON, **opts)
+        if cache:
+            plan.autotune(N, 1, cache)
+        plan.solve(fd, gd, damping=1.0, tol=args.tol)  # warm-up
+        t = []
+        for _ in range(5):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            psi, _, rep = plan.solve(fd, gd, damping=1.0, tol=args.tol)
+            torch.cuda.synchronize()
+            t.append(time.perf_counter() - t0)
+        plan.close()
+        err = None
+        if ref is not None:
+            st = int(ref["stride"])
+            err = float(np.max(np.abs(psi.cpu().numpy()[::st, ::st] - ref["psi"])) / float(ref["psi_absmax"]))
+        res["noise_2048_" + name] = {
+            "workload": "one 2048 x 2048 smooth-noise pair (exp(z/2), z filtered white noise, 4 px), %s linear "
+                        "solve, rms residual %.0e" % (name, args.tol),
+            "ms_per_solve": round(1e3 * float(np.median(t)), 3), "status": rep["status"],
+            "newton_iters": rep["newton_iters"], "gmres_iters": rep["gmres_iters"], "res_rms": rep["res_rms"],
+            "err_vs_oracle_sampled": err}
+    return res
 
 
 def summary(reps):
@@ -193,7 +283,7 @@ def main():
         """One batched solve; an unsolved pair aborts the headline arm (strict) and is
         counted, not credited, in the others."""
         psi0 = net.warm_start(fs, gs) if learned else None
-        psis, _, reps = plan.solve_batched(fs, gs, damping=1.0, tol=args.tol, psi0s=psi0)
+        psis, _, reps = plan.solve_batched(fs, gs, damping=1.0, tol=args.tol, psi0s=psi0, want_map=True)
         bad = [r for r in reps if r["status"] != 0 or r["res_rms"] > args.tol]
         if bad and strict:
             raise RuntimeError("unsolved pairs: %d (first: %s)" % (len(bad), bad[0]))
@@ -292,22 +382,23 @@ def main():
                        "bytes_per_launch": round(prof["bytes"] / max(prof["launches"], 1)),
                        "bytes_per_launch_all": round(bpl),
                        "algorithmic_bytes_timed": prof["bytes"]}
+    if not args.no_configs and args.workload == "blobs":
+        out["configs"] = extra_configs(args, maot, W, head[0], tuning_cache=args.tune_cache)
     if not args.no_cpu_baseline:
-        if args.workload == "mixed":  # one pair of each size: the mix's mean cost per pair
-            idx = [sizes.index(n) for n in sorted(set(sizes))]
-        else:
-            idx = list(range(min(args.cpu_pairs, B)))
+        idx = list(range(min(args.cpu_pairs or args.cpu_workers, B)))  # the front of the batch
         k = len(idx)
-        refs, dt = cpu_baseline([host_pairs[q] for q in idx], args, params if head[1] == "learned" else None,
-                                meta)
+        refs, rate, workers, busy = cpu_baseline([host_pairs[q] for q in idx], args,
+                                                 params if head[1] == "learned" else None, meta)
         err = max(float(np.max(np.abs(psis[q].cpu().numpy() - refs[i])) / np.max(np.abs(refs[i])))
                   for i, q in enumerate(idx))
-        out["cpu_baseline"] = {"value": round(k / dt, 5), "unit": "pairs/s", "cores": 1, "kind": "oracle",
-                               "sample": "%d pairs (seeds %s, sides %s) of the same workload (%s, %s linear solve), "
-                                         "FP64 NumPy oracle, one thread, %.1f s"
-                                         % (k, ",".join(str(seeds[q]) for q in idx),
-                                            ",".join(str(sizes[q]) for q in idx), init_txt, head[0], dt)}
+        out["cpu_baseline"] = {"value": round(rate, 5), "unit": "pairs/s", "cores": workers, "kind": "oracle",
+                               "sample": "%d pairs (seeds %s..%s, sides %s) of the same workload (%s, %s linear "
+                                         "solve), FP64 NumPy oracle, %d single-threaded processes, %.1f s of "
+                                         "CPU time in all" % (k, seeds[idx[0]], seeds[idx[-1]],
+                                                              ",".join(sorted({str(sizes[q]) for q in idx})),
+                                                              init_txt, head[0], workers, busy)}
         out["err_vs_oracle_max"] = err
+        out["err_vs_oracle_pairs"] = k
     print(json.dumps(out), flush=True)
     if net is not None:
         net.close()

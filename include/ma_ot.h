@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define MA_OT_ABI_VERSION 7
+#define MA_OT_ABI_VERSION 8
 
 /* return / status codes */
 #define MA_OK 0           /* converged: rms residual <= tol                           */
@@ -87,6 +87,12 @@ typedef struct ma_options {
                            /* (I + D^2 u) would fall below this fraction of its       */
                            /* current value, 0 <= . < 1 (0.1; 0 = off)                */
   int forcing;             /* MA_FORCING_* (MA_FORCING_FIXED)                        */
+  double wait_limit_s;     /* longest host wait for one device summary, in seconds  */
+                           /* (> 0; 600).  A solve whose device work does not reach  */
+                           /* the summary within it returns MA_EHIP; the work        */
+                           /* already queued on the stream still runs to its end,    */
+                           /* so the caller synchronises the stream before reusing   */
+                           /* its buffers or the plan                                */
 } ma_options;
 
 typedef struct ma_report {

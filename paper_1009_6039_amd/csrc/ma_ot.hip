@@ -31,10 +31,18 @@ struct Tune {
 
 struct Class {
   int n;
-  std::vector<int> ids;
+  int count = 0;         // pairs of this size
   int* d_ids = nullptr;  // slice of the plan's id buffer
   const float2* tw = nullptr;
   const float2* mt = nullptr;
+};
+
+// the size classes of one solve, iterable with a range-for
+struct ClassList {
+  const Class* p;
+  int n;
+  const Class* begin() const { return p; }
+  const Class* end() const { return p + n; }
 };
 
 }  // namespace
@@ -130,18 +138,23 @@ int validate_options(const ma_options& o) {
       (o.symbol != MA_SYMBOL_SPECTRAL && o.symbol != MA_SYMBOL_FD4) ||
       (o.precond != MA_PRECOND_NONE && o.precond != MA_PRECOND_DIAG) ||
       !(o.boundary_frac >= 0.0 && o.boundary_frac < 1.0) ||
-      (o.forcing != MA_FORCING_FIXED && o.forcing != MA_FORCING_ADAPTIVE))
+      (o.forcing != MA_FORCING_FIXED && o.forcing != MA_FORCING_ADAPTIVE) || !(o.wait_limit_s > 0.0))
     return MA_EINVAL;
   return MA_OK;
+}
+
+// tw[m] = exp(-2 pi i m / n), computed in FP64 and stored in FP32
+void fill_twiddles(float2* h, int n) {
+  for (int m = 0; m < n; ++m) {
+    const double a = -2.0 * M_PI * (double)m / (double)n;
+    h[m] = make_float2((float)std::cos(a), (float)std::sin(a));
+  }
 }
 
 int ensure_twiddles(ma_plan* P, int n) {
   if (P->tw.count(n)) return MA_OK;
   std::vector<float2> h(n);
-  for (int m = 0; m < n; ++m) {
-    const double a = -2.0 * M_PI * (double)m / (double)n;
-    h[m] = make_float2((float)std::cos(a), (float)std::sin(a));
-  }
+  fill_twiddles(h.data(), n);
   float2* d = nullptr;
   if (hipMalloc(&d, sizeof(float2) * n) != hipSuccess) return MA_ENOMEM;
   if (hipMemcpy(d, h.data(), sizeof(float2) * n, hipMemcpyHostToDevice) != hipSuccess) {
@@ -156,10 +169,7 @@ int ensure_twiddles(ma_plan* P, int n) {
 // computed in FP64: 2 pi i k, -(2 pi k)^2 (Section 4.2), or the fourth-order
 // difference symbols i (8 sin t - sin 2t)/(6h), (-64 sin^2(t/2) + 4 sin^2 t)/(12 h^2),
 // t = 2 pi k h; the first-derivative multiplier is zero at k = -N/2 in both.
-int ensure_multipliers(ma_plan* P, int n, int symbol) {
-  const auto key = std::make_pair(n, symbol);
-  if (P->mt.count(key)) return MA_OK;
-  std::vector<float2> h(n);
+void fill_multipliers(float2* h, int n, int symbol) {
   for (int q = 0; q < n; ++q) {
     const double ks = q < n / 2 ? q : q - n;
     double d1, d2;
@@ -175,6 +185,13 @@ int ensure_multipliers(ma_plan* P, int n, int symbol) {
     if (q == n / 2) d1 = 0.0;
     h[q] = make_float2((float)d1, (float)d2);
   }
+}
+
+int ensure_multipliers(ma_plan* P, int n, int symbol) {
+  const auto key = std::make_pair(n, symbol);
+  if (P->mt.count(key)) return MA_OK;
+  std::vector<float2> h(n);
+  fill_multipliers(h.data(), n, symbol);
   float2* d = nullptr;
   if (hipMalloc(&d, sizeof(float2) * n) != hipSuccess) return MA_ENOMEM;
   if (hipMemcpy(d, h.data(), sizeof(float2) * n, hipMemcpyHostToDevice) != hipSuccess) {
@@ -267,7 +284,7 @@ int build_classes(ma_plan* P, const std::vector<int>& ns, std::vector<Class>& cl
   for (auto& kv : by) {
     Class c;
     c.n = kv.first;
-    c.ids = kv.second;
+    c.count = (int)kv.second.size();
     c.tw = P->tw[c.n];
     c.mt = P->mt[std::make_pair(c.n, P->opt.symbol)];
     c.d_ids = P->d_ids + flat.size();
@@ -312,33 +329,39 @@ bool prof_pick(ma_plan* P, int kind) {
 
 void L_res(ma_plan* P, const Class& c, int step_mode, hipStream_t st) {
   const bool t = prof_pick(P, MA_PROF_RESIDUAL);
-  launch_residual(make_ctx(P, c, MA_PROF_RESIDUAL, t), c.n, (int)c.ids.size(), step_mode, st,
+  launch_residual(make_ctx(P, c, MA_PROF_RESIDUAL, t), c.n, c.count, step_mode, st,
                   prof_events(P, t ? MA_PROF_RESIDUAL : MA_PROF_NONE));
 }
 void L_A(ma_plan* P, const Class& c, int mode, int jn, hipStream_t st) {
   const bool t = prof_pick(P, MA_PROF_ROW_A);
-  launch_passA(make_ctx(P, c, MA_PROF_ROW_A, t), c.n, (int)c.ids.size(), mode, jn, c.tw, st,
+  launch_passA(make_ctx(P, c, MA_PROF_ROW_A, t), c.n, c.count, mode, jn, c.tw, st,
                prof_events(P, t ? MA_PROF_ROW_A : MA_PROF_NONE));
 }
 void L_B(ma_plan* P, const Class& c, int mode, int j, hipStream_t st) {
   const bool t = prof_pick(P, MA_PROF_COLUMN);
-  launch_passB(make_ctx(P, c, MA_PROF_COLUMN, t), c.n, (int)c.ids.size(), mode, j, c.tw, st,
+  launch_passB(make_ctx(P, c, MA_PROF_COLUMN, t), c.n, c.count, mode, j, c.tw, st,
                prof_events(P, t ? MA_PROF_COLUMN : MA_PROF_NONE));
 }
 void L_C(ma_plan* P, const Class& c, int mode, int j, hipStream_t st) {
   const bool t = prof_pick(P, MA_PROF_ROW_C);
-  launch_passC(make_ctx(P, c, MA_PROF_ROW_C, t), c.n, (int)c.ids.size(), mode, j, c.tw, st,
+  launch_passC(make_ctx(P, c, MA_PROF_ROW_C, t), c.n, c.count, mode, j, c.tw, st,
                prof_events(P, t ? MA_PROF_ROW_C : MA_PROF_NONE));
 }
 
 // Waits until slot `slot` of the summary holds the counts of the launch numbered
 // `seq` by polling its tag in host memory (no stream synchronisation: the host
-// resumes as soon as the kernel's fenced write lands).  Every 256 polls the stream
-// is queried, so that a failed or drained stream ends the wait with MA_EHIP.
+// resumes as soon as the kernel's fenced write lands).  Every 64 polls the wall
+// clock is read and every 256 the stream is queried, so that a failed or drained
+// stream, or a wait longer than the plan's wait_limit_s, ends the wait with MA_EHIP
+// (the queued work is not cancelled: it runs on to its end).
 int wait_summary(ma_plan* P, int slot, int seq, hipStream_t st) {
   int* tag = P->h_summary + MA_SUMMARY_INTS * slot + MA_SUMMARY_TAG;
+  const auto t0 = std::chrono::steady_clock::now();
   for (unsigned spin = 1;; ++spin) {
     if (__atomic_load_n(tag, __ATOMIC_ACQUIRE) == seq) return MA_OK;
+    if ((spin & 63) == 0 &&
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() > P->opt.wait_limit_s)
+      return MA_EHIP;
     if ((spin & 255) == 0) {
       const hipError_t q = hipStreamQuery(st);
       if (q == hipSuccess) return __atomic_load_n(tag, __ATOMIC_ACQUIRE) == seq ? MA_OK : MA_EHIP;
@@ -366,7 +389,7 @@ int read_summary(ma_plan* P, int npairs, hipStream_t st) {
 // earlier (so the device queue never drains while the host waits): once no pair is
 // inside the cycle, the remaining iterations, which would all exit at once, are not
 // launched.  At most two such iterations are queued.
-int launch_cycle_body(ma_plan* P, const std::vector<Class>& cls, int npairs, hipStream_t st) {
+int launch_cycle_body(ma_plan* P, ClassList cls, int npairs, hipStream_t st) {
   const int m = P->opt.gmres_m;
   constexpr int LAG = 2, FIRST = 2;
   for (int j = 0; j < m; ++j) {
@@ -391,12 +414,12 @@ int launch_cycle_body(ma_plan* P, const std::vector<Class>& cls, int npairs, hip
 }
 
 // the whole damped Newton loop for the pairs already described in P->h_desc
-int run_solver(ma_plan* P, int npairs, double damping, double tol, hipStream_t st, std::vector<Class>& cls) {
+int run_solver(ma_plan* P, int npairs, double damping, double tol, hipStream_t st, ClassList cls) {
   HIP_TRY(hipMemcpyAsync(P->d_desc, P->h_desc.data(), sizeof(PairDesc) * npairs, hipMemcpyHostToDevice, st));
   P->h_state.assign(npairs, fresh_state(damping, tol));
   for (int q = 0; q < npairs; ++q) P->h_state[q].warm = P->h_desc[q].psi0_in != nullptr;
   HIP_TRY(hipMemcpyAsync(P->d_state, P->h_state.data(), sizeof(PairState) * npairs, hipMemcpyHostToDevice, st));
-  for (const Class& c : cls) launch_setup(make_ctx(P, c), c.n, (int)c.ids.size(), st);
+  for (const Class& c : cls) launch_setup(make_ctx(P, c), c.n, c.count, st);
   int e = read_summary(P, npairs, st);
   if (e) return e;
   if (P->h_summary[7] > 0) return MA_EINVAL;
@@ -418,7 +441,7 @@ int run_solver(ma_plan* P, int npairs, double damping, double tol, hipStream_t s
         if (e) return e;
         if (P->h_summary[6] == 0) break;
         for (const Class& c : cls) {
-          launch_restart(make_ctx(P, c), c.n, (int)c.ids.size(), st);
+          launch_restart(make_ctx(P, c), c.n, c.count, st);
           L_A(P, c, PA_PLAIN, 0, st);
         }
         e = launch_cycle_body(P, cls, npairs, st);
@@ -431,9 +454,9 @@ int run_solver(ma_plan* P, int npairs, double damping, double tol, hipStream_t s
       }
     }
     if (n_update > 0)
-      for (const Class& c : cls) launch_step_update(make_ctx(P, c), c.n, (int)c.ids.size(), st);
+      for (const Class& c : cls) launch_step_update(make_ctx(P, c), c.n, c.count, st);
   }
-  for (const Class& c : cls) launch_outputs(make_ctx(P, c), c.n, (int)c.ids.size(), st);
+  for (const Class& c : cls) launch_outputs(make_ctx(P, c), c.n, c.count, st);
   HIP_TRY(hipMemcpyAsync(P->h_state.data(), P->d_state, sizeof(PairState) * npairs, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   prof_flush(P);
@@ -525,6 +548,7 @@ void ma_options_default(ma_options* o) {
   o->precond = MA_PRECOND_NONE;
   o->boundary_frac = 0.1;
   o->forcing = MA_FORCING_FIXED;
+  o->wait_limit_s = 600.0;
 }
 
 const char* ma_strerror(int code) {
@@ -717,7 +741,7 @@ int ma_solve_batched(ma_plan* P, int npairs, const int* n, const double* const* 
   std::vector<Class> cls;
   e = build_classes(P, ns, cls, st);
   if (e) return e;
-  e = run_solver(P, npairs, damping, tol, st, cls);
+  e = run_solver(P, npairs, damping, tol, st, ClassList{cls.data(), (int)cls.size()});
   if (e) return e;
   const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   int worst = MA_OK;
@@ -867,13 +891,13 @@ int ma_step_gmres(ma_plan* P, int n, const float* h, const float* coef, const do
     LaunchCtx x = make_ctx(P, c);
     x.precond = MA_PRECOND_NONE;  // the step entry points apply the operator of Section 4.2
     launch_passA(x, n, 1, PA_INIT, 0, c.tw, st);
-    if ((rc = launch_cycle_body(P, cls, 1, st))) break;
+    if ((rc = launch_cycle_body(P, ClassList{cls.data(), 1}, 1, st))) break;
     for (int cyc = 0; cyc < max_restarts; ++cyc) {
       if ((rc = read_summary(P, 1, st))) break;
       if (P->h_summary[6] == 0) break;
       launch_restart(x, n, 1, st);
       launch_passA(x, n, 1, PA_PLAIN, 0, c.tw, st);
-      if ((rc = launch_cycle_body(P, cls, 1, st))) break;
+      if ((rc = launch_cycle_body(P, ClassList{cls.data(), 1}, 1, st))) break;
     }
     if (rc) break;
     launch_passA(x, n, 1, PA_RECOVER, 0, c.tw, st);
@@ -890,5 +914,4 @@ int ma_step_gmres(ma_plan* P, int n, const float* h, const float* coef, const do
   P->opt = saved;
   return rc;
 }
-
 }  // extern "C"

@@ -42,7 +42,7 @@ class Options(ctypes.Structure):
                 ("interp", ctypes.c_int), ("op_mode", ctypes.c_int),
                 ("damping_policy", ctypes.c_int), ("max_backtrack", ctypes.c_int),
                 ("symbol", ctypes.c_int), ("precond", ctypes.c_int), ("boundary_frac", ctypes.c_double),
-                ("forcing", ctypes.c_int)]
+                ("forcing", ctypes.c_int), ("wait_limit_s", ctypes.c_double)]
 
 
 class Tuning(ctypes.Structure):

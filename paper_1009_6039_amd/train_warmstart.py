@@ -2,8 +2,9 @@
 
 Pipeline (every numerical step runs in libmaot.so kernels; torch only holds device
 memory and gathers minibatches):
-  1. blob-density pairs at n_net x n_net (seeds 20265203 + q, disjoint from the
-     benchmark's), drawn on the host by the shared input generator;
+  1. blob-density pairs at n_net x n_net (seeds workloads.seed_for(4, q), disjoint
+     from the held-out pairs seed_for(5, q) and the benchmark's seed_for(1, q)), drawn
+     on the host by the shared input generator;
   2. solved on the GPU to rms residual 1e-8 (step-halving damping, fourth-order
      symbols and the diagonally scaled GMRES system: the same fixed point, fewer
      iterations);

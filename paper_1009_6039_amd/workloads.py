@@ -27,11 +27,25 @@ Grid convention everywhere: F[i, j] is the value at (x1, x2) = (i/N, j/N).
 import numpy as np
 
 SEED_BASE = 20261203
+SEED_CONFIGS = 100        # configs 0 .. 99
+SEED_INDICES = 10 ** 7    # pair indices 0 .. 10^7 - 1 per config
+_SEED_HIGH = 10 ** 9      # offset of the seeds of pair indices >= 1000
 
 
 def seed_for(config, index):
-    """Documented seed schedule: one seed per (config, pair index)."""
-    return SEED_BASE + 1000 * int(config) + int(index)
+    """Seed of pair `index` of input config `config`; distinct (config, index) never share one.
+
+    The first thousand pairs of each config take SEED_BASE + 1000 config + index; pair
+    indices from 1000 on take SEED_BASE + 10^9 + 10^7 config + index, a range above every
+    seed of the first kind.  Both maps are injective and their ranges are disjoint, so
+    training, held-out and benchmark pairs drawn from different configs never coincide.
+    """
+    config, index = int(config), int(index)
+    if not (0 <= config < SEED_CONFIGS and 0 <= index < SEED_INDICES):
+        raise ValueError("seed_for: config must lie in [0, %d) and index in [0, %d)" % (SEED_CONFIGS, SEED_INDICES))
+    if index < 1000:
+        return SEED_BASE + 1000 * config + index
+    return SEED_BASE + _SEED_HIGH + SEED_INDICES * config + index
 
 
 def grid(N):

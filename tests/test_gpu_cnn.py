@@ -65,6 +65,7 @@ def test_forward_matches_oracle(maot, n, dil):
         c = c.cpu().numpy().astype(np.float64)
         for k in range(B):
             ref, _ = cnn.forward(cnn.network_input(f[k], g[k]), params, bf16=True, dilations=dil)
+            print("forward n=%d dil=%s sample %d: rel L2 %.3e" % (n, dil, k, rel_l2(c[k], ref[0])))
             assert rel_l2(c[k], ref[0]) < 2e-3, k
         # the prepared input is the BF16 rounding of (log(f/mean), log(g/mean)); the device
         # logarithm may differ from NumPy's in the last FP32 bit, which moves rare roundings
@@ -99,6 +100,15 @@ def test_gradients_match_oracle(maot, n, dil):
             tot = gk if tot is None else [(a[0] + b[0], a[1] + b[1]) for a, b in zip(tot, gk)]
         assert loss == pytest.approx(lref, rel=1e-3)
         ref = flat(tot).astype(np.float64)
+        off = 0
+        errs = []
+        for l, (Wl, bl) in enumerate(params):
+            nw, nb = Wl.size, bl.size
+            errs.append((rel_l2(grads[off:off + nw], ref[off:off + nw]),
+                         rel_l2(grads[off + nw:off + nw + nb], ref[off + nw:off + nw + nb])))
+            off += nw + nb
+        print("gradients n=%d dil=%s: rel L2 per layer (W, b): %s" % (
+            n, dil, " ".join("%.2e/%.2e" % e for e in errs)))
         off = 0
         for l, (Wl, bl) in enumerate(params):
             nw, nb = Wl.size, bl.size
@@ -159,6 +169,7 @@ def test_warm_start_matches_oracle(maot, n, dil):
         for k in range(3):
             ref = cnn.warm_start(f[k], g[k], params, n_net, dilations=dil)
             got = psis[k].cpu().numpy()
+            print("warm start n=%d dil=%s sample %d: rel L2 %.3e" % (n, dil, k, rel_l2(got, ref)))
             assert rel_l2(got, ref) < 3e-3, k
             assert abs(got.mean()) < 1e-6 * np.max(np.abs(ref))
     finally:
@@ -201,6 +212,62 @@ def test_benchmark_configuration_learned_start_matches_oracle(maot):
             err = np.max(np.abs(psis[q].cpu().numpy() - ref)) / np.max(np.abs(ref))
             print("pair %d: newton %d, max|psi - psi_oracle| / max|psi| = %.2e" % (q, reps[q]["newton_iters"], err))
             assert err <= 1e-6
+    finally:
+        p.close()
+        net.close()
+
+
+def test_learned_start_saves_newton_steps_and_wall_time_on_held_out_pairs(maot):
+    # What the trained network gains over the method without it: 128 held-out blob pairs
+    # at 256^2 (seeds seed_for(5, q), disjoint from the training pairs seed_for(4, q)),
+    # the fast linear solve at residual 1e-6, one batched call per arm.  Every pair must
+    # be solved from both starts; the learned start (network inference and head inside
+    # the timing) must need fewer Newton steps on average and less wall time than the
+    # zero start.  Each arm is timed three times after a warm-up; the fastest counts.
+    import json
+    import os
+    import time
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    d = np.load(os.path.join(root, "paper_1009_6039_amd", "warmstart_256.npz"), allow_pickle=False)
+    meta = json.loads(str(d["meta"]))
+    B, N = 128, 256
+    pairs = [W.blobs(N, W.seed_for(5, 300 + q)) for q in range(B)]
+    opts = dict(damping_policy="backtrack", symbol="fd4", precond="diag", gmres_tol=0.2, forcing="adaptive")
+    net = maot.WarmStartNet(layers=meta["layers"], channels=meta["channels"], n_net=meta["n_net"], max_batch=B,
+                            dilations=meta["dilations"])
+    p = maot.Plan(n_max=N, batch_capacity=B, max_newton=500, **opts)
+    try:
+        net.set_params(d["params"].astype(np.float32))
+        p.autotune(N, B)
+        fs = [torch.from_numpy(a).cuda() for a, _ in pairs]
+        gs = [torch.from_numpy(b).cuda() for _, b in pairs]
+
+        def run(arm):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            psi0 = net.warm_start(fs, gs) if arm == "learned" else None
+            _, _, reps = p.solve_batched(fs, gs, damping=1.0, tol=1e-6, psi0s=psi0)
+            torch.cuda.synchronize()
+            return time.perf_counter() - t0, reps
+
+        for arm in ("zero", "learned"):  # warm-up
+            run(arm)
+        times, last = {"zero": [], "learned": []}, {}
+        for _ in range(3):  # interleaved, so that clock drift hits both arms alike
+            for arm in ("zero", "learned"):
+                dt, last[arm] = run(arm)
+                times[arm].append(dt)
+        res = {}
+        for arm, reps in last.items():
+            assert all(r["status"] == 0 and r["res_rms"] <= 1e-6 for r in reps), arm
+            res[arm] = (float(np.mean([r["newton_iters"] for r in reps])), min(times[arm]),
+                        float(np.mean([r["gmres_iters"] for r in reps])))
+        print("held-out 256^2 x %d: zero start newton %.2f gmres %.1f %.2f ms; learned start newton %.2f "
+              "gmres %.1f %.2f ms (x%.3f)" % (B, res["zero"][0], res["zero"][2], 1e3 * res["zero"][1],
+                                              res["learned"][0], res["learned"][2], 1e3 * res["learned"][1],
+                                              res["zero"][1] / res["learned"][1]))
+        assert res["learned"][0] < res["zero"][0]
+        assert res["learned"][1] < res["zero"][1]
     finally:
         p.close()
         net.close()

@@ -197,6 +197,83 @@ def test_manufactured_solution_64(maot):
     assert math.sqrt(np.mean((psi - ps) ** 2)) < 1e-8
 
 
+def test_asymmetric_potential_map_matches_oracle(maot):
+    # psi* = A sin(2 pi x1) sin(4 pi x2) + B cos(2 pi x1), g = 1: d1 psi* != d2 psi*, so the
+    # map's components are told apart (x1 + d1 psi in map[0], x2 + d2 psi in map[1])
+    N = 64
+    x = np.arange(N) / N
+    X1, X2 = np.meshgrid(x, x, indexing="ij")
+    A, B = 0.004, 0.003
+    s1, c1, s4, c4 = np.sin(2 * np.pi * X1), np.cos(2 * np.pi * X1), np.sin(4 * np.pi * X2), np.cos(4 * np.pi * X2)
+    p11 = -4 * np.pi ** 2 * (A * s1 * s4 + B * c1)
+    p22 = -16 * np.pi ** 2 * A * s1 * s4
+    p12 = 8 * np.pi ** 2 * A * c1 * c4
+    f = (1 + p11) * (1 + p22) - p12 ** 2
+    g = np.ones((N, N))
+    psi_ref, map_ref, rep_ref = ma.solve(f, g, tau=1.0, tol=1e-11)
+    assert rep_ref.status == ma.OK
+    psi, mp, rep = maot.solve(dev(f), dev(g), damping=1.0, tol=1e-10)
+    psi, mp = host(psi), host(mp)
+    assert rep["status"] == 0 and rep["res_rms"] <= 1e-10
+    assert np.max(np.abs(psi - psi_ref)) <= 1e-6 * np.max(np.abs(psi_ref))
+    disp = np.max(np.abs(map_ref - np.stack([X1, X2])))
+    assert np.max(np.abs(mp - map_ref)) <= 1e-6 * disp
+    assert rep["w2sq"] == pytest.approx(rep_ref.w2sq, rel=1e-9)
+
+
+def mild_pair(N):
+    """A mild-contrast smooth pair (grad g != 0) on which the simplified operator converges."""
+    x = np.arange(N) / N
+    X1, X2 = np.meshgrid(x, x, indexing="ij")
+    f = 1 + 0.3 * np.cos(2 * np.pi * X1) * np.sin(2 * np.pi * X2) + 0.1 * np.sin(4 * np.pi * X1)
+    g = 1 + 0.4 * np.sin(2 * np.pi * (X1 + 0.2)) + 0.2 * np.cos(2 * np.pi * X2)
+    return f, g
+
+
+def test_no_drift_residual_kernel_zeroes_b(maot):
+    # op_mode no_drift (Remarks of Section 3.3): the residual kernel writes b = 0 and the
+    # same a_ij as the full operator
+    N = 64
+    f, g = mild_pair(N)
+    prob = ma.Problem(f, g)
+    x = np.arange(N) / N
+    X1, X2 = np.meshgrid(x, x, indexing="ij")
+    u = 0.01 * np.cos(2 * np.pi * X1) * np.sin(2 * np.pi * X2)
+    ev = ma.evaluate(u, prob)
+    p = maot.Plan(n_max=N, batch_capacity=1, op_mode="no_drift")
+    try:
+        r, coef, sc = p.step_residual(dev(u), dev(prob.f), dev(prob.g))
+        coef = host(coef)
+        ref = np.stack(ma.coefficients(ev, 1))
+        for k in range(3):
+            assert relerr(coef[k], ref[k]) < 1e-6
+        assert np.all(coef[3] == 0) and np.all(coef[4] == 0)
+        assert sc["bbar1"] == 0.0 and sc["bbar2"] == 0.0
+    finally:
+        p.close()
+
+
+@pytest.mark.parametrize("N", [32, 128])
+def test_no_drift_solve_matches_oracle(maot, N):
+    # the simplified Newton operator, GPU against the oracle with op_mode = 1 and against
+    # the full operator's solution (the same fixed point)
+    f, g = mild_pair(N)
+    ref1, _, r1 = ma.solve(f, g, tau=1.0, tol=1e-11, op_mode=1)
+    ref0, _, r0 = ma.solve(f, g, tau=1.0, tol=1e-11)
+    assert r1.status == ma.OK and r0.status == ma.OK
+    p = maot.Plan(n_max=N, batch_capacity=1, op_mode="no_drift")
+    try:
+        psi, _, rep = p.solve(dev(f), dev(g), damping=1.0, tol=1e-10)
+        psi = host(psi)
+        print("no drift %d: newton %d (oracle %d), gmres %d (oracle %d)" % (
+            N, rep["newton_iters"], r1.newton_iters, rep["gmres_iters"], r1.gmres_iters))
+        assert rep["status"] == 0 and rep["res_rms"] <= 1e-10
+        for r in (ref1, ref0):
+            assert np.max(np.abs(psi - r)) <= 1e-6 * np.max(np.abs(r))
+    finally:
+        p.close()
+
+
 def test_equal_densities_take_no_step(maot):
     f, _ = W.blobs(64, 3)
     psi, mp, rep = maot.solve(dev(f), dev(f.copy()), damping=1.0, tol=1e-9)
@@ -245,10 +322,16 @@ def test_c1_pair_512_to_residual_1e6(maot):
         ev = ma.evaluate(psi, ma.Problem(f, g))
         assert ev.res_rms <= 1.0001e-6
         err = np.max(np.abs(psi - psi_ref)) / np.max(np.abs(psi_ref))
-        print("C1 512 tol 1e-6: rel err %.3e, newton %d" % (err, rep["newton_iters"]))
+        x = np.arange(N) / N
+        disp = np.max(np.abs(map_ref - np.stack([np.broadcast_to(x[:, None], (N, N)),
+                                                 np.broadcast_to(x[None, :], (N, N))])))
+        err_map = np.max(np.abs(mp - map_ref)) / disp
+        print("C1 512 tol 1e-6: rel err psi %.3e, map %.3e (of max |grad psi| %.3e), newton %d"
+              % (err, err_map, disp, rep["newton_iters"]))
         # residual 1e-6 bounds the potential error near 0.03 * 1e-6 (Section 5.1 spectral radius)
-        assert err <= 2e-6, err
-        assert np.max(np.abs(mp - map_ref)) < 1e-4
+        assert err <= 1e-6, err
+        # the map's displacement grad psi to the same relative bar
+        assert err_map <= 1e-6, err_map
         # a tighter residual meets the 1e-6 relative parity bar
         psi2, _, rep2 = p.solve(dev(f), dev(g), damping=1.0, tol=1e-8)
         err2 = np.max(np.abs(host(psi2) - psi_ref)) / np.max(np.abs(psi_ref))
@@ -330,30 +413,51 @@ def test_batched_mixed_sizes_match_oracle(maot):
         p.close()
 
 
-def test_c2_noise_pair_2048_properties(maot):
+def c2_reference():
+    """The oracle's solution of the 2048^2 noise pair at every 16th node (written by
+    tests/golden/make_c2_reference.py, which calls only the oracle)."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c2_noise_2048_reference.npz")
+    return np.load(path, allow_pickle=False)
+
+
+def test_c2_noise_pair_2048_matches_oracle(maot):
     # 2048^2 smooth-noise pair (exp(z/2), filtered white noise, the literal reading of
-    # the recipe), fixed tau = 1: the full-size case is checked through properties the
-    # oracle can evaluate at this size: its own FP64 residual of the GPU potential,
-    # convexity, mean zero, and agreement with a solve along another path (fd4
-    # symbols, tighter tolerance) to the same discrete fixed point.
+    # the recipe), the paper's method (spectral symbols, fixed tau = 1): the potential at
+    # the 128 x 128 stored nodes against the oracle's, run to its residual floor 1e-12,
+    # to the 1e-6 relative bar; then properties at every node: the oracle's own FP64
+    # residual of the GPU potential, convexity, mean zero, and agreement with a solve
+    # along another path (fd4 symbols, tighter tolerance) to the same fixed point.
     N = 2048
+    ref = c2_reference()
     f, g = W.smooth_noise(N, W.seed_for(2, 0))
+    assert int(ref["seed"]) == W.seed_for(2, 0) and int(ref["n"]) == N
+    st = int(ref["stride"])
     print("C2 2048 pair seed %d" % W.seed_for(2, 0), flush=True)
     p = maot.Plan(n_max=N, batch_capacity=1, gmres_tol=1e-2)
     q = maot.Plan(n_max=N, batch_capacity=1, gmres_tol=1e-2, symbol="fd4")
     try:
         psi, mp, rep = p.solve(dev(f), dev(g), damping=1.0, tol=1e-6)
-        psi = host(psi)
+        psi, mp = host(psi), host(mp)
         print("C2 2048: newton %d gmres %d res %.3e" % (rep["newton_iters"], rep["gmres_iters"], rep["res_rms"]))
         assert rep["status"] == 0 and rep["res_rms"] <= 1e-6 and rep["min_det"] > 0
+        amax = float(ref["psi_absmax"])
+        err = np.max(np.abs(psi[::st, ::st] - ref["psi"])) / amax
+        x = np.arange(0, N, st) / N
+        base = np.stack([np.broadcast_to(x[:, None], (N // st, N // st)), np.broadcast_to(x[None, :], (N // st, N // st))])
+        disp = np.max(np.abs(ref["map"] - base))
+        err_map = np.max(np.abs(mp[:, ::st, ::st] - ref["map"])) / disp
+        print("C2 2048 vs oracle at %d sampled nodes: psi %.3e, map %.3e (max|psi| %.3e)"
+              % (ref["psi"].size, err, err_map, amax), flush=True)
+        assert err <= 1e-6 and err_map <= 1e-6
         ev = ma.evaluate(psi, ma.Problem(f, g))
         assert ev.res_rms <= 1.0001e-6 and ev.convex
         assert abs(psi.mean()) <= 1e-12
         psi2, _, rep2 = q.solve(dev(f), dev(g), damping=1.0, tol=1e-9)
         assert rep2["status"] == 0
-        err = np.max(np.abs(host(psi2) - psi)) / np.max(np.abs(psi))
-        print("C2 2048: spectral tol 1e-6 vs fd4 tol 1e-9: %.3e" % err)
-        assert err <= 2e-6
+        err2 = np.max(np.abs(host(psi2) - psi)) / np.max(np.abs(psi))
+        print("C2 2048: spectral tol 1e-6 vs fd4 tol 1e-9: %.3e" % err2)
+        assert err2 <= 1e-6
     finally:
         p.close()
         q.close()
@@ -382,7 +486,8 @@ def test_c3_mixed_batch_256_pairs(maot):
                                   max_newton=300, symbol="fd4")
             assert rr.status == ma.OK
             err = np.max(np.abs(host(psis[qi]) - ref)) / np.max(np.abs(ref))
-            assert err <= 2e-6, (n, err)
+            print("C3 pair %d (n = %d): rel err %.3e" % (qi, n, err), flush=True)
+            assert err <= 1e-6, (n, err)
     finally:
         p.close()
 
@@ -477,3 +582,25 @@ def test_bad_arguments_are_rejected_and_a_larger_batch_grows_the_workspace(maot)
     finally:
         p.close()
         q.close()
+
+
+def test_host_wait_limit_returns_an_error_and_the_plan_recovers(maot):
+    # a wait limit of 1 microsecond is shorter than any device round trip: the solve
+    # returns MA_EHIP while its queued kernels run on to their normal end; after a
+    # stream synchronisation the same plan, with the default limit, solves correctly
+    N = 64
+    f, g = W.blobs(N, W.seed_for(1, 13))
+    opts = dict(damping_policy="backtrack", gmres_tol=0.1, max_newton=300)
+    p = maot.Plan(n_max=N, batch_capacity=1, wait_limit_s=1e-6, **opts)
+    try:
+        with pytest.raises(maot.MAError) as e:
+            p.solve(dev(f), dev(g), damping=1.0, tol=1e-9)
+        assert e.value.code == maot.EHIP
+        torch.cuda.synchronize()
+        p.set_options(**opts)
+        psi, _, rep = p.solve(dev(f), dev(g), damping=1.0, tol=1e-9)
+        ref, _, rr = ma.solve(f, g, tau=1.0, tol=1e-11, **opts)
+        assert rep["status"] == 0 and rr.status == ma.OK
+        assert np.max(np.abs(host(psi) - ref)) <= 1e-6 * np.max(np.abs(ref))
+    finally:
+        p.close()

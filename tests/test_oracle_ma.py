@@ -451,3 +451,109 @@ def test_adaptive_forcing_keeps_the_fixed_point():
     assert np.max(np.abs(p1 - p2)) <= 1e-8 * np.max(np.abs(p1))
     with pytest.raises(ValueError):
         ma.solve(f, g, forcing="ew", **kw)
+
+
+# --- orientation of the map: an asymmetric potential (Section 5.2 distance, Theorem CE1) ---
+
+def asymmetric_manufactured(N, A=0.004, B=0.003):
+    """psi* = A sin(2 pi x1) sin(4 pi x2) + B cos(2 pi x1), g = 1, f = det(I + D^2 psi*) in
+    closed form (mean exactly one: det(I + H) - 1 - tr H is a divergence).  Returns the
+    grid, psi*, its analytic gradient and f; d1 psi* and d2 psi* differ, so a map with
+    its components exchanged (or built from the wrong axis) is far off."""
+    x = np.arange(N) / N
+    X1, X2 = np.meshgrid(x, x, indexing="ij")
+    s1, c1 = np.sin(2 * np.pi * X1), np.cos(2 * np.pi * X1)
+    s4, c4 = np.sin(4 * np.pi * X2), np.cos(4 * np.pi * X2)
+    ps = A * s1 * s4 + B * c1
+    p1 = 2 * np.pi * A * c1 * s4 - 2 * np.pi * B * s1
+    p2 = 4 * np.pi * A * s1 * c4
+    p11 = -4 * np.pi ** 2 * A * s1 * s4 - 4 * np.pi ** 2 * B * c1
+    p22 = -16 * np.pi ** 2 * A * s1 * s4
+    p12 = 8 * np.pi ** 2 * A * c1 * c4
+    f = (1 + p11) * (1 + p22) - p12 ** 2
+    return X1, X2, ps, p1, p2, f
+
+
+def test_map_components_follow_the_axes_for_an_asymmetric_potential():
+    # T(x) = x + grad psi (Theorem CE1; Section 5.2): map[0] is x1 + d psi / d x1 and map[1]
+    # is x2 + d psi / d x2, each to fourth order in h against the analytic gradient
+    errs = []
+    for N in (32, 64):
+        X1, X2, ps, p1, p2, f = asymmetric_manufactured(N)
+        psi, mp, rep = ma.solve(f, np.ones((N, N)), tau=1.0, tol=1e-11)
+        assert rep.status == ma.OK
+        e0 = np.max(np.abs(mp[0] - (X1 + p1)))
+        e1 = np.max(np.abs(mp[1] - (X2 + p2)))
+        errs.append(max(e0, e1))
+        # exchanged components are off by the size of the gradient difference
+        assert np.max(np.abs(mp[0] - (X1 + p2))) > 0.05 and np.max(np.abs(mp[1] - (X2 + p1))) > 0.05
+        assert np.max(np.abs(mp[0] - (X2 + p1))) > 0.5  # wrong base coordinate
+    assert errs[1] < 5e-6
+    assert errs[0] / errs[1] > 12.0  # fourth order: 16 per halving of h
+
+
+def test_w2_of_an_asymmetric_potential_against_quadrature():
+    # d(f, g) = int |grad psi*|^2 f (Section 5.2) by the trapezoid rule on a fine grid (spectrally
+    # accurate for smooth periodic integrands), independent of the solver's differences
+    _, _, _, q1, q2, ff = asymmetric_manufactured(512)
+    w2 = float(np.mean((q1 ** 2 + q2 ** 2) * ff))
+    _, _, _, _, _, f = asymmetric_manufactured(64)
+    _, _, rep = ma.solve(f, np.ones((64, 64)), tau=1.0, tol=1e-11)
+    assert rep.w2sq == pytest.approx(w2, rel=1e-4)
+
+
+# --- the simplified operator without the b . grad theta term (Remarks of Section 3.3) ---
+
+def _nodrift_setup(N):
+    x = np.arange(N) / N
+    X1, X2 = np.meshgrid(x, x, indexing="ij")
+    f = 1 + 0.3 * np.cos(2 * np.pi * X1) * np.sin(2 * np.pi * X2)
+    g = 1 + 0.4 * np.sin(2 * np.pi * (X1 + 0.2)) + 0.2 * np.cos(2 * np.pi * X2)  # grad g != 0: b != 0
+    prob = ma.Problem(f, g)
+    u = 0.01 * np.cos(2 * np.pi * X1) * np.sin(2 * np.pi * X2) + 0.004 * np.sin(2 * np.pi * (X1 - X2))
+    return prob, ma.evaluate(u, prob), X1, X2
+
+
+def test_no_drift_coefficients_drop_only_b():
+    prob, ev, _, _ = _nodrift_setup(16)
+    full = ma.coefficients(ev, 0)
+    nd = ma.coefficients(ev, 1)
+    for k in range(3):
+        assert np.array_equal(full[k], nd[k])
+    assert np.all(nd[3] == 0) and np.all(nd[4] == 0)
+    assert np.max(np.abs(full[3])) > 0.1 and np.max(np.abs(full[4])) > 0.1
+
+
+def test_no_drift_direction_solves_the_dense_operator_without_b():
+    # op_mode 1: the Newton direction theta solves g Tr(Adj(I + D^2 u) D^2 theta) = h (no b term).
+    # Dense spectral collocation (Trefethen's closed-form matrices) gives that operator
+    # independently; h is taken in its range, h = L_nd theta_true with theta_true of mean zero.
+    import copy
+    N = 12
+    prob, ev, X1, X2 = _nodrift_setup(N)
+    a11, a12, a22, _, _ = ma.coefficients(ev, 1)
+    Lnd = dense_operator((a11, a12, a22, 0.0, 0.0), N)
+    theta_true = np.sin(2 * np.pi * X1 + 0.4) * np.cos(4 * np.pi * X2) + 0.3 * np.cos(2 * np.pi * X2)
+    theta_true -= theta_true.mean()
+    ev2 = copy.copy(ev)
+    ev2.r = (Lnd @ theta_true.ravel()).reshape(N, N)
+    th, its = ma.newton_direction(ev2, prob, 1.0, 1, N * N, 1e-12, 5)
+    assert np.max(np.abs(th - theta_true)) < 1e-9 * np.max(np.abs(theta_true))
+    # the full operator (with b . grad theta) gives another direction on the same h
+    th_full, _ = ma.newton_direction(ev2, prob, 1.0, 0, N * N, 1e-12, 5)
+    assert np.max(np.abs(th_full - theta_true)) > 1e-2 * np.max(np.abs(theta_true))
+
+
+def test_no_drift_newton_reaches_the_same_fixed_point():
+    # the simplified operator changes the path, not the discrete solution F(u) = 0.  The
+    # paper only says it gives good results in practice; on a mild-contrast pair it does
+    # (on the high-contrast blob pairs, density ratio about 20, its directions stall)
+    N = 32
+    prob, _, X1, X2 = _nodrift_setup(N)
+    f = 1 + 0.3 * np.cos(2 * np.pi * X1) * np.sin(2 * np.pi * X2) + 0.1 * np.sin(4 * np.pi * X1)
+    g = prob.g
+    a, _, ra = ma.solve(f, g, tau=1.0, tol=1e-11)
+    b, _, rb = ma.solve(f, g, tau=1.0, tol=1e-11, op_mode=1)
+    assert ra.status == ma.OK and rb.status == ma.OK
+    assert np.max(np.abs(a - b)) <= 1e-9 * np.max(np.abs(a))
+    assert rb.gmres_iters > ra.gmres_iters  # the dropped term makes each direction cruder
