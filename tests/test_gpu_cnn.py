@@ -3,7 +3,11 @@
 The GPU stores inputs, weights, activations and inter-layer gradients in BF16 and
 accumulates in FP32; the oracle rounds the same tensors to BF16 and accumulates in
 FP64.  FP32-vs-FP64 accumulation order can flip a rare BF16 rounding of an
-intermediate value, so tensors are compared by relative L2 error.
+intermediate value, so tensors are compared by relative L2 error, to 1e-3 per
+tensor (measured on MI355X: forward at most 6.6e-4, weight and bias gradients at
+most 9.0e-4; the kernels are deterministic, so these do not vary between runs) and
+1e-4 for the warm start, whose FP64 head dilutes the network's share (measured at
+most 4.1e-5).
 """
 
 import numpy as np
@@ -66,7 +70,7 @@ def test_forward_matches_oracle(maot, n, dil):
         for k in range(B):
             ref, _ = cnn.forward(cnn.network_input(f[k], g[k]), params, bf16=True, dilations=dil)
             print("forward n=%d dil=%s sample %d: rel L2 %.3e" % (n, dil, k, rel_l2(c[k], ref[0])))
-            assert rel_l2(c[k], ref[0]) < 2e-3, k
+            assert rel_l2(c[k], ref[0]) < 1e-3, k
         # the prepared input is the BF16 rounding of (log(f/mean), log(g/mean)); the device
         # logarithm may differ from NumPy's in the last FP32 bit, which moves rare roundings
         xin = x.float().cpu().numpy()
@@ -112,8 +116,8 @@ def test_gradients_match_oracle(maot, n, dil):
         off = 0
         for l, (Wl, bl) in enumerate(params):
             nw, nb = Wl.size, bl.size
-            assert rel_l2(grads[off:off + nw], ref[off:off + nw]) < 2e-2, ("W", l)
-            assert rel_l2(grads[off + nw:off + nw + nb], ref[off + nw:off + nw + nb]) < 2e-2, ("b", l)
+            assert rel_l2(grads[off:off + nw], ref[off:off + nw]) < 1e-3, ("W", l)
+            assert rel_l2(grads[off + nw:off + nw + nb], ref[off + nw:off + nw + nb]) < 1e-3, ("b", l)
             off += nw + nb
     finally:
         net.close()
@@ -170,7 +174,7 @@ def test_warm_start_matches_oracle(maot, n, dil):
             ref = cnn.warm_start(f[k], g[k], params, n_net, dilations=dil)
             got = psis[k].cpu().numpy()
             print("warm start n=%d dil=%s sample %d: rel L2 %.3e" % (n, dil, k, rel_l2(got, ref)))
-            assert rel_l2(got, ref) < 3e-3, k
+            assert rel_l2(got, ref) < 1e-4, k
             assert abs(got.mean()) < 1e-6 * np.max(np.abs(ref))
     finally:
         net.close()
