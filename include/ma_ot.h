@@ -162,6 +162,26 @@ int ma_solve_batched(ma_plan* plan, int npairs, const int* n, const double* cons
                      double tol, double* const* psi, double* const* map, ma_report* reps,
                      void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): ma_solve for one pair
+ * without a plan and without any allocation.  The options are passed directly
+ * (ma_options_default fills the defaults).  Every device buffer the solve needs
+ * (the pair's workspace, descriptor, state, transform tables, the host-loop
+ * summary) is carved from a fixed 48 MiB device array that the library holds on
+ * each GPU it runs on until the process ends; no hipMalloc, hipFree or other
+ * allocating routine is called.  Limit: n <= 512 and the pair's workspace within
+ * that array (at n = 512: gmres_m <= 24); larger requests return MA_EINVAL.  Every
+ * call on one GPU shares that GPU's array and leaves its contents there: calls
+ * that overlap on one GPU (two streams, two host threads) race and must be
+ * serialised by the caller.  The GMRES cycles are not cut short by the host (no
+ * mapped summary), so the launch sequence differs from ma_solve; the arithmetic
+ * and the result do not.  Arguments, outputs and return codes as ma_solve with the
+ * launch geometry of a plan that has not been autotuned; the default wait limit
+ * applies to each host wait. */
+int ma_solve_noalloc(const ma_options* opt, const double* f, const double* g, int n,
+                     double damping, double tol, const double* psi0, double* psi, double* map,
+                     ma_report* rep, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Timing hook for one kernel class, used by the benchmark to report a roofline.
  * While enabled, every `every`-th launch of that class inside ma_solve /

@@ -77,6 +77,11 @@ struct ma_plan {
   long long prof_launches = 0;
   int prof_every = 1;       // time every prof_every-th launch of the class
   long long prof_seq = 0;   // launches of the class seen since ma_plan_profile
+  // no-allocation mode (ma_solve_noalloc): every device buffer is carved from the
+  // library's static scratch array, the summary lives in device memory and is copied
+  // back after each launch that the host waits on
+  bool no_alloc = false;
+  int h_summary_buf[MA_SUMMARY_INTS] = {};
 };
 
 namespace {
@@ -381,7 +386,19 @@ int next_seq(ma_plan* P) {
 int read_summary(ma_plan* P, int npairs, hipStream_t st) {
   const int seq = next_seq(P);
   launch_summary(P->d_state, P->d_ids, npairs, P->d_summary, seq, st);
-  return wait_summary(P, 0, seq, st);
+  if (!P->no_alloc) return wait_summary(P, 0, seq, st);
+  // device-memory summary: copy it back and wait for the stream, within wait_limit_s
+  HIP_TRY(hipMemcpyAsync(P->h_summary, P->d_summary, sizeof(int) * MA_SUMMARY_INTS, hipMemcpyDeviceToHost, st));
+  const auto t0 = std::chrono::steady_clock::now();
+  for (;;) {
+    const hipError_t q = hipStreamQuery(st);
+    if (q == hipSuccess) break;
+    if (q != hipErrorNotReady ||
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() > P->opt.wait_limit_s)
+      return MA_EHIP;
+    __builtin_ia32_pause();
+  }
+  return P->h_summary[MA_SUMMARY_TAG] == seq ? MA_OK : MA_EHIP;
 }
 
 // The iterations of one GMRES cycle.  From the third on, a summary of the state is
@@ -398,7 +415,9 @@ int launch_cycle_body(ma_plan* P, ClassList cls, int npairs, hipStream_t st) {
       L_C(P, c, PC_MATVEC, j, st);
       L_A(P, c, PA_ARNOLDI, j + 1, st);
     }
-    if (j + 1 >= m || j < FIRST) continue;
+    // (the no-allocation mode has no mapped summary: every iteration is launched, and
+    // those after a pair's convergence exit at once)
+    if (j + 1 >= m || j < FIRST || P->no_alloc) continue;
     const int slot = j % (LAG + 1);
     P->ring_seq[slot] = next_seq(P);
     launch_summary(P->d_state, P->d_ids, npairs, P->d_summary + MA_SUMMARY_INTS * (1 + slot), P->ring_seq[slot],
@@ -529,6 +548,64 @@ int plan_lbar_inverse_many(ma_plan* P, int n, int count, const float* const* sig
   launch_passC(x, n, count, PC_THETA_ONLY, 0, cls[0].tw, st);
   return hipGetLastError() == hipSuccess ? MA_OK : MA_EHIP;
 }
+
+// ---------------------------------------------------------------------------
+// No-allocation solves (ma_solve_noalloc): one pair, all device memory carved from
+// `scratch`, a file-scope device array of MA_NOALLOC_BYTES that each GPU holds from
+// the library's load to the end of the process.  In host code `scratch` names a
+// host-side stand-in; its device address comes from hipGetSymbolAddress, once per
+// device, with that device current, and only that address is used.
+// ---------------------------------------------------------------------------
+constexpr size_t MA_NOALLOC_BYTES = (size_t)48 << 20;
+constexpr int MA_NOALLOC_DEVICES = 64;
+constexpr int MA_NOALLOC_NMAX = 512;
+
+static __device__ __align__(256) char scratch[MA_NOALLOC_BYTES];
+
+namespace {
+
+struct NoAllocSlot {
+  char* base = nullptr;  // device address of this GPU's `scratch`
+  float2* d_tw = nullptr;
+  float2* d_mt = nullptr;
+  float2 h_tw[MA_NOALLOC_NMAX], h_mt[MA_NOALLOC_NMAX];  // host sources of the last upload
+  int h_zero = 0;
+};
+NoAllocSlot g_noalloc[MA_NOALLOC_DEVICES];
+ma_plan g_noalloc_plan[MA_NOALLOC_DEVICES];
+
+// first call on device `dev`: the address of its scratch array and the carving of the
+// fixed regions (pair descriptor, state, id, summary, tables, then the pair's arena)
+int noalloc_setup(int dev) {
+  NoAllocSlot& S = g_noalloc[dev];
+  if (S.base) return MA_OK;
+  char* ptr = nullptr;
+  if (hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return MA_EHIP;
+  ma_plan* P = &g_noalloc_plan[dev];
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* q = ptr + off;
+    off += align256(bytes);
+    return q;
+  };
+  P->d_desc = (PairDesc*)take(sizeof(PairDesc));
+  P->d_state = (PairState*)take(sizeof(PairState));
+  P->d_ids = (int*)take(sizeof(int));
+  P->d_summary = (int*)take(sizeof(int) * MA_SUMMARY_INTS);
+  S.d_tw = (float2*)take(sizeof(float2) * MA_NOALLOC_NMAX);
+  S.d_mt = (float2*)take(sizeof(float2) * MA_NOALLOC_NMAX);
+  P->arena = ptr + off;
+  P->arena_bytes = MA_NOALLOC_BYTES - off;
+  P->h_summary = P->h_summary_buf;
+  P->pairs_cap = 1;
+  P->no_alloc = true;
+  P->h_desc.assign(1, PairDesc{});  // host vectors of one entry, sized once here
+  P->h_state.assign(1, PairState{});
+  S.base = ptr;
+  return MA_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -914,4 +991,49 @@ int ma_step_gmres(ma_plan* P, int n, const float* h, const float* coef, const do
   P->opt = saved;
   return rc;
 }
+
+int ma_solve_noalloc(const ma_options* opt, const double* f, const double* g, int n, double damping, double tol,
+                     const double* psi0, double* psi, double* map, ma_report* rep, void* stream) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!opt || !f || !g || !psi || !(damping >= 1.0) || !(tol > 0.0) || validate_options(*opt)) return MA_EINVAL;
+  if (!n_ok(n) || n > MA_NOALLOC_NMAX) return MA_EINVAL;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MA_NOALLOC_DEVICES) return MA_EHIP;
+  int e = noalloc_setup(dev);
+  if (e) return e;
+  NoAllocSlot& S = g_noalloc[dev];
+  ma_plan* P = &g_noalloc_plan[dev];
+  if (pair_bytes(n, opt->gmres_m) > P->arena_bytes) return MA_EINVAL;  // beyond the scratch array
+  P->opt = *opt;
+  hipStream_t st = (hipStream_t)stream;
+  PairDesc& d = P->h_desc[0];
+  d = PairDesc{};
+  char* p = P->arena;
+  carve(d, p, n, P->opt.gmres_m);
+  d.cls = 0;
+  d.f_in = f;
+  d.g_in = g;
+  d.psi0_in = psi0;
+  d.psi_out = psi;
+  d.map_out = map;
+  fill_twiddles(S.h_tw, n);
+  fill_multipliers(S.h_mt, n, P->opt.symbol);
+  HIP_TRY(hipMemcpyAsync(S.d_tw, S.h_tw, sizeof(float2) * n, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(S.d_mt, S.h_mt, sizeof(float2) * n, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(P->d_ids, &S.h_zero, sizeof(int), hipMemcpyHostToDevice, st));
+  Class c;
+  c.n = n;
+  c.count = 1;
+  c.d_ids = P->d_ids;
+  c.tw = S.d_tw;
+  c.mt = S.d_mt;
+  e = run_solver(P, 1, damping, tol, st, ClassList{&c, 1});
+  if (e) return e;
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  ma_report r;
+  fill_report(P->h_state[0], &r, ms);
+  if (rep) *rep = r;
+  return r.status;
+}
+
 }  // extern "C"

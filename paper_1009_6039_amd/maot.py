@@ -26,7 +26,7 @@ FORCING = {"fixed": 0, "adaptive": 1}
 PROF = {"none": 0, "residual": 1, "row_a": 2, "column": 3, "row_c": 4}
 
 EXPORTED = ("ma_abi_version", "ma_options_default", "ma_strerror", "ma_plan_create",
-            "ma_plan_destroy", "ma_plan_set_options", "ma_solve", "ma_solve_batched",
+            "ma_plan_destroy", "ma_plan_set_options", "ma_solve", "ma_solve_batched", "ma_solve_noalloc",
             "ma_plan_profile", "ma_plan_profile_read",
             "ma_plan_autotune", "ma_plan_set_tuning", "ma_plan_get_tuning", "ma_tune_geometry",
             "ma_step_residual", "ma_step_fft2", "ma_step_strain_apply",
@@ -104,6 +104,7 @@ def load():
     lib.ma_solve_batched.argtypes = [P, I, ctypes.POINTER(I), ctypes.POINTER(P), ctypes.POINTER(P),
                                      ctypes.POINTER(P), D, D, ctypes.POINTER(P), ctypes.POINTER(P),
                                      ctypes.POINTER(Report), P]
+    lib.ma_solve_noalloc.argtypes = [ctypes.POINTER(Options), P, P, I, D, D, P, P, P, ctypes.POINTER(Report), P]
     lib.ma_plan_profile.argtypes = [P, I, I]
     lib.ma_plan_profile_read.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_longlong),
                                          ctypes.POINTER(D), ctypes.POINTER(ctypes.c_longlong),
@@ -444,6 +445,24 @@ class WarmStartNet:
         pa = arr(*[t.data_ptr() for t in psis])
         _check(load().ma_cnn_warm_start(self._h, npairs, n, fa, ga, pa, _stream()), "ma_cnn_warm_start")
         return psis
+
+
+def solve_noalloc(f, g, damping=1.0, tol=1e-6, psi0=None, psi=None, map=None, **opts):
+    """ma_solve_noalloc: one pair with no device allocation inside the library; the
+    outputs psi (and map, if given) are caller-owned CUDA float64 tensors (allocated
+    here when None).  Returns (psi, map, report)."""
+    f = _dev(f, torch.float64)
+    g = _dev(g, torch.float64)
+    psi0 = _dev(psi0, torch.float64)
+    n = f.shape[0]
+    psi = _dev(psi, torch.float64) if psi is not None else torch.empty_like(f)
+    mp = _dev(map, torch.float64) if map is not None else None
+    o = make_options(**opts)
+    rep = Report()
+    code = load().ma_solve_noalloc(ctypes.byref(o), _ptr(f), _ptr(g), n, float(damping), float(tol), _ptr(psi0),
+                                   _ptr(psi), _ptr(mp), ctypes.byref(rep), _stream())
+    _check(code, "ma_solve_noalloc")
+    return psi, mp, rep.as_dict()
 
 
 def solve(f, g, damping=1.0, tol=1e-6, psi0=None, **opts):
