@@ -59,6 +59,9 @@ def parse():
                     help="pairs per batched solve (one step); a larger batch spreads the last, nearly "
                          "empty ticks of the slowest pairs over more pairs")
     ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--max-active", type=int, default=0,
+                    help="continuous batching: at most this many pairs in flight per call, finished "
+                         "slots refilled with the batch's pending pairs (0: every pair at once)")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--gmres-tol", type=float, default=None, help="overrides every method's GMRES tolerance")
     ap.add_argument("--damping-policy", default="backtrack")
@@ -261,8 +264,9 @@ def main():
         if sym not in METHODS:
             raise SystemExit("unknown method %r" % sym)
     args.method0 = symbols[0]
-    plans = {sym: maot.Plan(n_max=N, batch_capacity=B, damping_policy=args.damping_policy,
-                            max_newton=MAX_NEWTON, **method_options(sym, args)) for sym in symbols}
+    plans = {sym: maot.Plan(n_max=N, batch_capacity=args.max_active or B, damping_policy=args.damping_policy,
+                            max_newton=MAX_NEWTON, max_active=args.max_active, **method_options(sym, args))
+             for sym in symbols}
 
     tuning = None
     if args.tune_cache != "none":  # launch geometry chosen before the timed region, per size class
@@ -344,7 +348,8 @@ def main():
                                 % (", ".join("%d x %d" % (n, sizes.count(n)) for n in sorted(set(sizes))), B,
                                    args.tol, init_txt, head[0])),
                    "n": N if args.workload == "blobs" else sorted(set(sizes)), "batch": B, "tol": args.tol, "damping_policy": args.damping_policy,
-                   "gmres_m": 10, "init": head[1], "method": head[0], **method_options(head[0], args)},
+                   "gmres_m": 10, "init": head[1], "method": head[0], "max_active": args.max_active,
+                   **method_options(head[0], args)},
     }
     out.update(summary(reps))
     if tuning is not None:

@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define MA_OT_ABI_VERSION 8
+#define MA_OT_ABI_VERSION 9
 
 /* return / status codes */
 #define MA_OK 0           /* converged: rms residual <= tol                           */
@@ -93,6 +93,9 @@ typedef struct ma_options {
                            /* already queued on the stream still runs to its end,    */
                            /* so the caller synchronises the stream before reusing   */
                            /* its buffers or the plan                                */
+  int max_active;          /* ma_solve_batched: at most this many pairs in flight; a  */
+                           /* finished pair's slot takes the next pending pair of its */
+                           /* size within the same call (0: every pair at once)       */
 } ma_options;
 
 typedef struct ma_report {
@@ -256,15 +259,31 @@ int ma_step_gmres(ma_plan* plan, int n, const float* h, const float* coef,
                   const double* abar, int m, double tol, int max_restarts, float* theta,
                   int* iters, void* stream);
 
+/* Spectral radius of the inverse of the linearised operator by the power method
+ * (Section 5.1, stability paragraph after Table 1): from b_0 (N*N FP32 device, not
+ * written) with its mean removed and normalised, `iters` steps b_{k+1} = A^{-1} b_k /
+ * ||A^{-1} b_k||_2, each product A^{-1} b_k computed by Section 4.2's method (GMRES(m)
+ * on L Lbar^{-1} sigma = b_k to gmres_tol, then theta = Lbar^{-1} sigma) for the
+ * operator with coefficients coef (5*N*N FP32 device: a11, a12, a22, b1, b2) and
+ * averages abar (host[5]).  rho (host[iters]) receives ||A^{-1} b_k||_2 (for the unit
+ * b_k), gmres_iters (host[iters], may be NULL) the GMRES iterations of each product.
+ * Uses the plan's workspace and synchronises the stream; MA_EINVAL for bad sizes. */
+int ma_power_inverse(ma_plan* plan, int n, const float* coef, const double* abar,
+                     const float* b0, int iters, double gmres_tol, int gmres_m,
+                     int max_restarts, double* rho, int* gmres_iters, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Autotuner (not in the paper): launch geometry per grid size.  Each of the four
  * bandwidth-bound kernel classes (row pass A, column pass B, row pass C, residual
  * stencil) has MA_TUNE_VARIANTS compiled geometries: 0 the default, 1 half as many
  * rows / columns per workgroup (residual: half the tile width), 2 twice as many
- * (residual: a quarter of the tile width), 3 the default tile with half the threads.
- * A variant that coincides with a smaller index is skipped.
+ * (residual: a quarter of the tile width), 3 the default tile with half the threads
+ * (residual: the streaming kernel, where n is a multiple of 64: a wave walks down
+ * 64 columns with the stencil rows in registers and no LDS tile).  A variant that
+ * coincides with a smaller index is skipped.
  * ------------------------------------------------------------------------- */
 #define MA_TUNE_VARIANTS 4
+#define MA_TUNE_SLOTS 8  /* room for the per-variant times below */
 
 typedef struct ma_tuning {
   int n;               /* grid side */
@@ -274,6 +293,9 @@ typedef struct ma_tuning {
   int rejected;        /* variants whose output differed from the default's */
   double us[4];        /* per-launch time of the chosen variants, microseconds (0 from the cache) */
   double us_default[4];/* per-launch time of the default geometry */
+  double us_variant[4][MA_TUNE_SLOTS]; /* per-launch time of every variant timed, -1 where a
+                                          variant was skipped (duplicate, rejected, absent);
+                                          zeros when read from the cache */
 } ma_tuning;
 
 /* Times every distinct variant of each kernel class on `npairs` synthetic pairs of

@@ -229,6 +229,8 @@ int tune_passes(const TunerView& view, ma_tuning* t, hipStream_t st) {
   TRY_HIP(hipEventCreate(&e0));
   TRY_HIP(hipEventCreate(&e1));
   int err = MA_OK;
+  for (int k = 0; k < 4; ++k)
+    for (int v = 0; v < MA_TUNE_SLOTS; ++v) t->us_variant[k][v] = -1.0;
   // the residual first: it writes the coefficients that pass C reads
   const int order[4] = {3, 0, 1, 2};
   for (int oi = 0; oi < 4 && !err; ++oi) {
@@ -263,6 +265,7 @@ int tune_passes(const TunerView& view, ma_tuning* t, hipStream_t st) {
         break;
       }
       const double us = 1e3 * ms / reps;
+      t->us_variant[pass][v] = us;
       if (v == 0) t->us_default[pass] = us;
       if (v == 0 || us < 0.98 * best) {  // a variant must win by 2% to displace an earlier one
         best = us;

@@ -12,6 +12,8 @@
 #define MA_RES_TX_MAX 64  // residual-kernel tile width (columns)
 #define MA_RES_TY 16      // residual-kernel tile height (rows)
 #define MA_NPART_RES 16   // partial sums per residual block
+#define MA_RES_STREAM_BLOCK 128  // streaming residual kernel: threads per block (2 waves)
+#define MA_RES_STREAM_ROWS 32    // streaming residual kernel: rows per wave
 #define MA_BLOCK 256
 #define MA_SUMMARY_INTS 16  // host-loop counters written by the summary kernel
 #define MA_SUMMARY_TAG 15   // slot of the sequence number the summary kernel writes last
@@ -33,7 +35,9 @@ struct __align__(16) GS {
 
 struct PairDesc {
   int n;
-  int cls;  // index of the size class this pair belongs to
+  int cls;   // index of the size class this pair belongs to
+  int pair;  // the caller's index of the pair in this slot (continuous batching)
+  int pad0;
   // caller buffers
   const double* f_in;
   const double* g_in;
@@ -71,6 +75,7 @@ struct PairState {
   double res_rms, res_max, res0, res_prev, mass_c, min_det, min_tr, w2, mean_u;
   double abar[5];
   double mean_f, mean_g, mean_psi0;
+  double aux[2];        // power iteration: mean of b_0, then the current scale factor
   // --- GMRES ----------------------------------------------------------------
   int gm_running;       // an Arnoldi cycle is in progress
   int gm_restart;       // the cycle ended short of the tolerance: restart
@@ -81,6 +86,15 @@ struct PairState {
   double vscale[MA_MMAX + 1];       // v_l = vscale[l] * V[l]
   double Hm[(MA_MMAX + 1) * MA_MMAX];  // Hessenberg, column-major: Hm[j*(MMAX+1)+i]
   double cs[MA_MMAX], sn[MA_MMAX], gv[MA_MMAX + 1], y[MA_MMAX + 1], q[MA_MMAX + 1];
+};
+
+// one slot refilled with a new pair (continuous batching): written by the host into a
+// staging buffer, scattered into the slot's descriptor and state by k_refill
+struct RefillRecord {
+  PairDesc desc;
+  PairState state;
+  int slot;
+  int pad[3];
 };
 
 // parameters common to one launch (passed by value)

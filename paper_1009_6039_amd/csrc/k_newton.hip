@@ -205,20 +205,102 @@ __device__ static void newton_decide(PairState& s, const LaunchCtx& c, int n, co
   }
 }
 
-// f mod n for an integer-valued f with |f| < 2^50, in [0, n): the quotient is rounded,
-// so the FP64 remainder (exact: integers below 2^53) lies in [-n, 2n) and one fold
-// finishes it.  Replaces a 64-bit integer division.
-__device__ inline int wrap_index(double f, int n, double N) {
-  int a = (int)(f - N * floor(f / N));
+// f mod n for an integer-valued f with |f| < 2^50, in [0, n).  The quotient
+// floor(f * (1/N)) differs from floor(f / N) by at most one (1/N is rounded, f * (1/N)
+// too), so the FP64 remainder f - N q (exact: integers below 2^53) lies in [-n, 2n)
+// and one fold finishes it.  Replaces a division and a 64-bit integer remainder.
+__device__ inline int wrap_index(double f, int n, double N, double invN) {
+  int a = (int)(f - N * floor(f * invN));
   a += a < 0 ? n : (a >= n ? -n : 0);
   return a;
 }
 
 // ---------------------------------------------------------------------------
 // Fused residual + coefficient kernel (one Newton evaluation).
-// Tile: TX columns x MA_RES_TY rows per block, halo 2 staged in LDS (FP64).
 // ---------------------------------------------------------------------------
-template <int TX>
+// The part after the derivatives, for one grid point (i, j): g and grad g at
+// y = x + grad u (Section 4, periodic), det(I + D^2 u), f_n, r = f - f_n, the
+// coefficients of eq. (linearmaeq) (stored FP32), and this point's share of the
+// block's partial sums (acc, layout as k_residual_finalize reads it).
+struct ResidualViews {
+  MA_GLOBAL_AS const GS* gs;
+  MA_GLOBAL_AS const double* F;
+  MA_GLOBAL_AS float* R;
+  MA_GLOBAL_AS float* coef;
+};
+
+__device__ __forceinline__ void residual_acc_init(double (&acc)[MA_NPART_RES]) {
+  for (int k = 0; k < 10; ++k) acc[k] = 0.0;
+  acc[10] = 1e300;   // min det
+  acc[11] = 1e300;   // min trace
+  acc[12] = -1e300;  // max r
+  acc[13] = 1e300;   // min r
+  acc[14] = 0.0;     // non-finite count
+  acc[15] = 0.0;
+}
+
+template <int INTERP>
+__device__ __forceinline__ void residual_point(const LaunchCtx& c, const ResidualViews& v, int n, int i, int j,
+                                               double uc, double u1, double u2, double u11, double u22,
+                                               double u12, double fv, double (&acc)[MA_NPART_RES]) {
+  const double N = (double)n, invN = 1.0 / N;
+  const int nn = n * n;  // n * n < 2^31
+  // a diverging iterate must not produce a wild gather index (it is flagged below)
+  double t1 = (double)i + N * u1, t2 = (double)j + N * u2;
+  if (!(fabs(t1) < 1e15)) t1 = 0.0;
+  if (!(fabs(t2) < 1e15)) t2 = 0.0;
+  double gy, gy1, gy2;
+  if constexpr (INTERP == MA_INTERP_NEAREST) {
+    const int a = wrap_index(floor(t1 + 0.5), n, N, invN), b = wrap_index(floor(t2 + 0.5), n, N, invN);
+    GS w = v.gs[a * n + b];
+    gy = w.g; gy1 = w.g1; gy2 = w.g2;
+  } else {
+    const double f1 = floor(t1), f2 = floor(t2);
+    const double wa = t1 - f1, wb = t2 - f2;
+    const int a = wrap_index(f1, n, N, invN), b = wrap_index(f2, n, N, invN);
+    const int a1 = (a + 1 == n) ? 0 : a + 1, b1 = (b + 1 == n) ? 0 : b + 1;
+    const GS v00 = v.gs[a * n + b], v10 = v.gs[a1 * n + b], v01 = v.gs[a * n + b1], v11 = v.gs[a1 * n + b1];
+    const double w00 = (1 - wa) * (1 - wb), w10 = wa * (1 - wb), w01 = (1 - wa) * wb, w11 = wa * wb;
+    gy = w00 * v00.g + w10 * v10.g + w01 * v01.g + w11 * v11.g;
+    gy1 = w00 * v00.g1 + w10 * v10.g1 + w01 * v01.g1 + w11 * v11.g1;
+    gy2 = w00 * v00.g2 + w10 * v10.g2 + w01 * v01.g2 + w11 * v11.g2;
+  }
+  const double det = (1.0 + u11) * (1.0 + u22) - u12 * u12;
+  const double fn = gy * det;
+  const int e = i * n + j;
+  const double rr = fv - fn;
+  const double a11 = gy * (1.0 + u22), a22 = gy * (1.0 + u11), a12 = -gy * u12;
+  const double b1 = c.op_mode == MA_OP_NO_DRIFT ? 0.0 : det * gy1;
+  const double b2 = c.op_mode == MA_OP_NO_DRIFT ? 0.0 : det * gy2;
+  v.R[e] = (float)rr;
+  v.coef[e] = (float)a11;
+  v.coef[nn + e] = (float)a12;
+  v.coef[2 * nn + e] = (float)a22;
+  v.coef[3 * nn + e] = (float)b1;
+  v.coef[4 * nn + e] = (float)b2;
+  // periodic Simpson weights (reading P7): 2h/3 at even nodes, 4h/3 at odd ones
+  const double w = (double)((i & 1) ? 4 : 2) * (double)((j & 1) ? 4 : 2) * (1.0 / (9.0 * N * N));
+  acc[0] += fn;
+  acc[1] += rr;
+  acc[2] += rr * rr;
+  acc[3] += w * a11;
+  acc[4] += w * a12;
+  acc[5] += w * a22;
+  acc[6] += w * b1;
+  acc[7] += w * b2;
+  acc[8] += (u1 * u1 + u2 * u2) * fv;
+  acc[9] += uc;
+  acc[10] = fmin(acc[10], det);
+  acc[11] = fmin(acc[11], 2.0 + u11 + u22);
+  acc[12] = fmax(acc[12], rr);
+  acc[13] = fmin(acc[13], rr);
+  if (!isfinite(rr) || !isfinite(det)) acc[14] += 1.0;
+}
+
+constexpr int RES_KINDS[MA_NPART_RES] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 2, 1, 0, 0};
+
+// Tile: TX columns x MA_RES_TY rows per block, halo 2 staged in LDS (FP64).
+template <int TX, int INTERP>
 __global__ __launch_bounds__(MA_BLOCK) void k_residual(LaunchCtx c) {
   const int p = pair_of_block(c);
   const PairDesc& d = c.desc[p];
@@ -244,25 +326,13 @@ __global__ __launch_bounds__(MA_BLOCK) void k_residual(LaunchCtx c) {
 
   const double N = (double)n;
   const double i12h = N / 12.0, i12h2 = N * N / 12.0, i144h2 = N * N / 144.0;
-  const double wnorm = 1.0 / (9.0 * N * N);
   double acc[MA_NPART_RES];
-  for (int k = 0; k < 10; ++k) acc[k] = 0.0;
-  acc[10] = 1e300;   // min det
-  acc[11] = 1e300;   // min trace
-  acc[12] = -1e300;  // max r
-  acc[13] = 1e300;   // min r
-  acc[14] = 0.0;     // non-finite count
-  acc[15] = 0.0;
-  const auto gs = gmem<const GS>(d.gs);
-  const auto F = gmem<const double>(d.f);
-  const auto R = gmem<float>(d.r);
-  const auto coef = gmem<float>(d.coef);
-  const long nn = (long)n * n;
+  residual_acc_init(acc);
+  const ResidualViews views{gmem<const GS>(d.gs), gmem<const double>(d.f), gmem<float>(d.r), gmem<float>(d.coef)};
   constexpr int TROWS = MA_BLOCK / TX;
   const int tx = threadIdx.x % TX, ty0 = threadIdx.x / TX;
   for (int ty = ty0; ty < TY; ty += TROWS) {
     const int li = ty + 2, lj = tx + 2;
-    const int i = i0 + ty, j = j0 + tx;
 #define U(a, b) tile[(li + (a)) * LW + lj + (b)]
     const double u1 = (U(-2, 0) - 8.0 * U(-1, 0) + 8.0 * U(1, 0) - U(2, 0)) * i12h;
     const double u2 = (U(0, -2) - 8.0 * U(0, -1) + 8.0 * U(0, 1) - U(0, 2)) * i12h;
@@ -273,62 +343,120 @@ __global__ __launch_bounds__(MA_BLOCK) void k_residual(LaunchCtx c) {
     for (int a = -2; a <= 2; ++a)
       q[a + 2] = (a == 0) ? 0.0 : (U(a, -2) - 8.0 * U(a, -1) + 8.0 * U(a, 1) - U(a, 2));
     const double u12 = (q[0] - 8.0 * q[1] + 8.0 * q[3] - q[4]) * i144h2;
+    residual_point<INTERP>(c, views, n, i0 + ty, j0 + tx, U(0, 0), u1, u2, u11, u22, u12,
+                           views.F[(i0 + ty) * n + j0 + tx], acc);
 #undef U
-    // g and grad g at y = x + grad u (Section 4), periodic
-    // a diverging iterate must not produce a wild gather index (it is flagged below)
-    double t1 = (double)i + N * u1, t2 = (double)j + N * u2;
-    if (!(fabs(t1) < 1e15)) t1 = 0.0;
-    if (!(fabs(t2) < 1e15)) t2 = 0.0;
-    double gy, gy1, gy2;
-    if (c.interp == MA_INTERP_NEAREST) {
-      const long a = wrap_index(floor(t1 + 0.5), n, N), b = wrap_index(floor(t2 + 0.5), n, N);
-      GS v = gs[a * n + b];
-      gy = v.g; gy1 = v.g1; gy2 = v.g2;
-    } else {
-      const double f1 = floor(t1), f2 = floor(t2);
-      const double wa = t1 - f1, wb = t2 - f2;
-      const long a = wrap_index(f1, n, N), b = wrap_index(f2, n, N);
-      const long a1 = (a + 1 == n) ? 0 : a + 1, b1 = (b + 1 == n) ? 0 : b + 1;
-      const GS v00 = gs[a * n + b], v10 = gs[a1 * n + b], v01 = gs[a * n + b1], v11 = gs[a1 * n + b1];
-      const double w00 = (1 - wa) * (1 - wb), w10 = wa * (1 - wb), w01 = (1 - wa) * wb, w11 = wa * wb;
-      gy = w00 * v00.g + w10 * v10.g + w01 * v01.g + w11 * v11.g;
-      gy1 = w00 * v00.g1 + w10 * v10.g1 + w01 * v01.g1 + w11 * v11.g1;
-      gy2 = w00 * v00.g2 + w10 * v10.g2 + w01 * v01.g2 + w11 * v11.g2;
-    }
-    const double det = (1.0 + u11) * (1.0 + u22) - u12 * u12;
-    const double fn = gy * det;
-    const long e = (long)i * n + j;
-    const double fv = F[e];
-    const double rr = fv - fn;
-    const double a11 = gy * (1.0 + u22), a22 = gy * (1.0 + u11), a12 = -gy * u12;
-    const double b1 = c.op_mode == MA_OP_NO_DRIFT ? 0.0 : det * gy1;
-    const double b2 = c.op_mode == MA_OP_NO_DRIFT ? 0.0 : det * gy2;
-    R[e] = (float)rr;
-    coef[e] = (float)a11;
-    coef[nn + e] = (float)a12;
-    coef[2 * nn + e] = (float)a22;
-    coef[3 * nn + e] = (float)b1;
-    coef[4 * nn + e] = (float)b2;
-    // periodic Simpson weights (reading P7): 2h/3 at even nodes, 4h/3 at odd ones
-    const double w = (double)((i & 1) ? 4 : 2) * (double)((j & 1) ? 4 : 2) * wnorm;
-    acc[0] += fn;
-    acc[1] += rr;
-    acc[2] += rr * rr;
-    acc[3] += w * a11;
-    acc[4] += w * a12;
-    acc[5] += w * a22;
-    acc[6] += w * b1;
-    acc[7] += w * b2;
-    acc[8] += (u1 * u1 + u2 * u2) * fv;
-    acc[9] += tile[li * LW + lj];
-    acc[10] = fmin(acc[10], det);
-    acc[11] = fmin(acc[11], 2.0 + u11 + u22);
-    acc[12] = fmax(acc[12], rr);
-    acc[13] = fmin(acc[13], rr);
-    if (!isfinite(rr) || !isfinite(det)) acc[14] += 1.0;
   }
-  const int kinds[MA_NPART_RES] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 2, 1, 0, 0};
-  block_reduce<MA_NPART_RES>(acc, kinds, scratch);
+  block_reduce<MA_NPART_RES>(acc, RES_KINDS, scratch);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < MA_NPART_RES; ++k) d.part[(long)blockIdx.x * MA_NPART_RES + k] = acc[k];
+}
+
+// a double of lane l, read by every lane (two 32-bit lane reads)
+__device__ __forceinline__ double lane_read(double x, int l) {
+  const long long b = __double_as_longlong(x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffLL), l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)((unsigned long long)b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Streaming variant: a wave takes 64 consecutive columns j0 .. j0+63 and walks down
+// RPW rows.  The five rows of u around the current row sit in registers (a sliding
+// window, the x1 stencils), the x2 stencils take the neighbouring columns from the
+// neighbouring lanes (cross-lane reads; the wave's edge lanes take columns j0-2,
+// j0-1, j0+64, j0+65, which lanes 0..3 load besides their own), and the next row of
+// u is loaded before the current one is evaluated.  No LDS tile, no barrier before
+// the block's final reduction; the arithmetic of each point is that of k_residual.
+// Needs n % 64 == 0; a block of MA_RES_STREAM_BLOCK threads covers 64 columns and
+// (MA_RES_STREAM_BLOCK / 64) * RPW rows.
+template <int RPW, int INTERP>
+__global__ __launch_bounds__(MA_RES_STREAM_BLOCK) void k_residual_stream(LaunchCtx c) {
+  const int p = pair_of_block(c);
+  const PairDesc& d = c.desc[p];
+  PairState& s = c.st[p];
+  if (s.phase == PH_DONE) return;
+  count_bytes(c, 56.0, d.n);
+  constexpr int WPB = MA_RES_STREAM_BLOCK / 64;
+  __shared__ double scratch[WPB * MA_NPART_RES];
+  const int n = d.n;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int nbx = n / 64;
+  const int j0 = (blockIdx.x % nbx) * 64;
+  const int i0 = (blockIdx.x / nbx) * (WPB * RPW) + wv * RPW;
+  const int j = j0 + lane;
+  int jh = lane < 2 ? j0 - 2 + lane : j0 + 62 + lane;  // lanes 0..3: j0-2, j0-1, j0+64, j0+65
+  jh += jh < 0 ? n : (jh >= n ? -n : 0);
+  if (lane >= 4) jh = j;  // read but unused
+  const auto u = gmem<const double>(d.u);
+  auto row = [&](int i) {  // offset of row i (within [-2, n + 3)), periodic
+    i += i < 0 ? n : (i >= n ? -n : 0);
+    return i * n;  // n * n < 2^31
+  };
+  const double N = (double)n;
+  const double i12h = N / 12.0, i12h2 = N * N / 12.0, i144h2 = N * N / 144.0;
+  // x2 stencils of one row: q = the first-difference combination (unscaled), d2 the
+  // second derivative
+  auto across = [&](double v, double hv, double& q, double& d2) {
+    const double h0 = lane_read(hv, 0), h1 = lane_read(hv, 1), h2 = lane_read(hv, 2), h3 = lane_read(hv, 3);
+    double vm1 = __shfl(v, lane - 1, 64), vm2 = __shfl(v, lane - 2, 64);
+    double vp1 = __shfl(v, lane + 1, 64), vp2 = __shfl(v, lane + 2, 64);
+    vm1 = lane >= 1 ? vm1 : h1;
+    vm2 = lane >= 2 ? vm2 : (lane == 1 ? h1 : h0);
+    vp1 = lane <= 62 ? vp1 : h2;
+    vp2 = lane <= 61 ? vp2 : (lane == 62 ? h2 : h3);
+    q = vm2 - 8.0 * vm1 + 8.0 * vp1 - vp2;
+    d2 = (-vm2 + 16.0 * vm1 - 30.0 * v + 16.0 * vp1 - vp2) * i12h2;
+  };
+  // window: rows i-2 .. i+2 of u and q; d2 of rows i .. i+2
+  double wu[5], wq[5], wd[3];
+  {
+    double v[5], hv[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      const int o = row(i0 - 2 + k);
+      v[k] = u[o + j];
+      hv[k] = u[o + jh];
+    }
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      double dd;
+      wu[k] = v[k];
+      across(v[k], hv[k], wq[k], dd);
+      if (k >= 2) wd[k - 2] = dd;
+    }
+  }
+  double acc[MA_NPART_RES];
+  residual_acc_init(acc);
+  const ResidualViews views{gmem<const GS>(d.gs), gmem<const double>(d.f), gmem<float>(d.r), gmem<float>(d.coef)};
+#pragma unroll 1
+  for (int k = 0; k < RPW; ++k) {
+    const int i = i0 + k;
+    const double fv = views.F[i * n + j];  // issued with the next row's u, before the gathers
+    double nv = 0.0, nhv = 0.0;
+    if (k + 1 < RPW) {  // row i + 3, for the next window
+      const int o = row(i + 3);
+      nv = u[o + j];
+      nhv = u[o + jh];
+    }
+    const double u1 = (wu[0] - 8.0 * wu[1] + 8.0 * wu[3] - wu[4]) * i12h;
+    const double u2 = wq[2] * i12h;
+    const double u11 = (-wu[0] + 16.0 * wu[1] - 30.0 * wu[2] + 16.0 * wu[3] - wu[4]) * i12h2;
+    const double u22 = wd[0];
+    const double u12 = (wq[0] - 8.0 * wq[1] + 8.0 * wq[3] - wq[4]) * i144h2;
+    residual_point<INTERP>(c, views, n, i, j, wu[2], u1, u2, u11, u22, u12, fv, acc);
+    if (k + 1 < RPW) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        wu[m] = wu[m + 1];
+        wq[m] = wq[m + 1];
+      }
+      wd[0] = wd[1];
+      wd[1] = wd[2];
+      wu[4] = nv;
+      across(nv, nhv, wq[4], wd[2]);
+    }
+  }
+  block_reduce<MA_NPART_RES>(acc, RES_KINDS, scratch);
   if (threadIdx.x == 0)
     for (int k = 0; k < MA_NPART_RES; ++k) d.part[(long)blockIdx.x * MA_NPART_RES + k] = acc[k];
 }
@@ -340,9 +468,8 @@ __global__ __launch_bounds__(MA_BLOCK) void k_residual_finalize(LaunchCtx c, int
   PairState& s = c.st[p];
   if (s.phase == PH_DONE) return;
   __shared__ double scratch[(MA_BLOCK / 64) * MA_NPART_RES];
-  const int kinds[MA_NPART_RES] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 2, 1, 0, 0};
   double t[MA_NPART_RES];
-  fold_partials<MA_NPART_RES>(d.part, nblk, kinds, t, scratch);
+  fold_partials<MA_NPART_RES>(d.part, nblk, RES_KINDS, t, scratch);
   if (threadIdx.x != 0) return;
   const int n = d.n;
   if (step_mode) {  // single-step use: record the evaluation only
@@ -409,14 +536,12 @@ __global__ __launch_bounds__(MA_BLOCK) void k_outputs(LaunchCtx c) {
   }
 }
 
-// counts pairs per phase, pending restarts and invalid inputs for the host loop
-// counts for the host loop: [0..5] pairs per phase, [6] pairs to restart GMRES,
-// [7] invalid inputs, [8] pairs inside a GMRES cycle (16 slots written)
-// Counts of the pairs per phase and flag, written to host-visible memory; the
-// sequence number goes last, after a system-scope fence, so that a host that sees it
-// also sees the counts.
+// Counts of the pairs per phase and flag, written to host-visible memory: [0..5] pairs
+// per phase, [6] pairs to restart GMRES, [7] invalid inputs, [8] pairs inside a GMRES
+// cycle; with `phases`, each slot's phase as well.  The sequence number goes last,
+// after a system-scope fence, so that a host that sees it also sees the rest.
 __global__ __launch_bounds__(256) void k_summary(const PairState* st, const int* ids, int npairs, int* out,
-                                                 int seq) {
+                                                 int seq, int* phases) {
   __shared__ int cnt[MA_SUMMARY_INTS];
   if (threadIdx.x < MA_SUMMARY_INTS) cnt[threadIdx.x] = 0;
   __syncthreads();
@@ -426,13 +551,77 @@ __global__ __launch_bounds__(256) void k_summary(const PairState* st, const int*
     if (s.phase == PH_SOLVE && s.gm_restart) atomicAdd(&cnt[6], 1);
     if (!s.valid) atomicAdd(&cnt[7], 1);
     if (s.phase == PH_SOLVE && s.gm_running) atomicAdd(&cnt[8], 1);
+    if (phases) phases[q] = s.phase;
   }
+  if (phases) __threadfence_system();
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int k = 0; k < MA_SUMMARY_TAG; ++k) out[k] = cnt[k];
     __threadfence_system();
     out[MA_SUMMARY_TAG] = seq;
   }
+}
+
+// Continuous batching.  k_retire: for the slots in the launch's id list (pairs that
+// finished), the outputs of k_outputs and the final state into final[pair].
+__global__ __launch_bounds__(MA_BLOCK) void k_retire(LaunchCtx c, PairState* final_state) {
+  const int p = pair_of_block(c);
+  const PairDesc& d = c.desc[p];
+  const PairState& s = c.st[p];
+  const int n = d.n;
+  const long nn = (long)n * n;
+  const double mu = s.mean_u, i12h = (double)n / 12.0, h = 1.0 / (double)n;
+  const double* u = d.u;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (long)gridDim.x * blockDim.x) {
+    const int i = (int)(e / n), j = (int)(e % n);
+    d.psi_out[e] = u[e] - mu;
+    if (d.map_out) {
+      const int im1 = (i + n - 1) % n, im2 = (i + n - 2) % n, ip1 = (i + 1) % n, ip2 = (i + 2) % n;
+      const int jm1 = (j + n - 1) % n, jm2 = (j + n - 2) % n, jp1 = (j + 1) % n, jp2 = (j + 2) % n;
+      const double u1 = (u[(long)im2 * n + j] - 8.0 * u[(long)im1 * n + j] + 8.0 * u[(long)ip1 * n + j] -
+                         u[(long)ip2 * n + j]) * i12h;
+      const double u2 = (u[(long)i * n + jm2] - 8.0 * u[(long)i * n + jm1] + 8.0 * u[(long)i * n + jp1] -
+                         u[(long)i * n + jp2]) * i12h;
+      d.map_out[e] = (double)i * h + u1;
+      d.map_out[nn + e] = (double)j * h + u2;
+    }
+  }
+  if (blockIdx.x == 0) {  // the state, copied word by word by the block
+    const int* src = reinterpret_cast<const int*>(&s);
+    int* dst = reinterpret_cast<int*>(&final_state[d.pair]);
+    for (int w = threadIdx.x; w < (int)(sizeof(PairState) / sizeof(int)); w += blockDim.x) dst[w] = src[w];
+  }
+}
+
+// k_refill: record r's descriptor and fresh state into its slot
+__global__ __launch_bounds__(256) void k_refill(PairDesc* desc, PairState* st, const RefillRecord* rec) {
+  const RefillRecord& r = rec[blockIdx.x];
+  {
+    const int* src = reinterpret_cast<const int*>(&r.desc);
+    int* dst = reinterpret_cast<int*>(&desc[r.slot]);
+    for (int w = threadIdx.x; w < (int)(sizeof(PairDesc) / sizeof(int)); w += blockDim.x) dst[w] = src[w];
+  }
+  const int* src = reinterpret_cast<const int*>(&r.state);
+  int* dst = reinterpret_cast<int*>(&st[r.slot]);
+  for (int w = threadIdx.x; w < (int)(sizeof(PairState) / sizeof(int)); w += blockDim.x) dst[w] = src[w];
+}
+
+// k_validate: counts the pairs whose densities are not finite and positive (or whose
+// initial potential is not finite) before any of them is solved; one block row per pair
+__global__ __launch_bounds__(MA_BLOCK) void k_validate(const double* const* f, const double* const* g,
+                                                       const double* const* psi0, const int* n, int* bad) {
+  const int q = blockIdx.y;
+  const long nn = (long)n[q] * n[q];
+  const double* fq = f[q];
+  const double* gq = g[q];
+  const double* pq = psi0 ? psi0[q] : nullptr;
+  int b = 0;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (long)gridDim.x * blockDim.x) {
+    const double fv = fq[e], gv = gq[e];
+    if (!(fv > 0.0) || !(gv > 0.0) || !isfinite(fv) || !isfinite(gv)) b = 1;
+    if (pq && !isfinite(pq[e])) b = 1;
+  }
+  if (__syncthreads_or(b) && threadIdx.x == 0) atomicAdd(bad, 1);
 }
 
 // Synthetic fields for timing launch geometries: smooth positive densities, a small
@@ -494,30 +683,53 @@ void launch_setup(const LaunchCtx& c, int n, int npairs, hipStream_t st) {
 }
 
 // tile width of the residual stencil: variant 0 the widest that divides n (64, 32 or
-// 16 columns), 1 half of it, 2 a quarter (never below 16), 3 the same as 0
+// 16 columns), 1 half of it, 2 a quarter (never below 16), 3 the streaming kernel
+// (64 columns per wave, MA_RES_STREAM_ROWS rows per wave) where n % 64 == 0, else the
+// same as 0
 int residual_tile_x(int n, int v) {
   const int t0 = (n % 64 == 0) ? 64 : ((n % 32 == 0) ? 32 : 16);
   const int t = v == 1 ? t0 / 2 : (v == 2 ? t0 / 4 : t0);
   return t < 16 ? 16 : t;
 }
 
+bool residual_streams(int n, int v) { return v == 3 && n % 64 == 0; }
+
 int residual_geometry(int n, int v, int* tile_x, int* threads) {
   if (v < 0 || v > 3 || n % 16) return -1;
   *tile_x = residual_tile_x(n, v);
-  *threads = MA_BLOCK;
+  *threads = residual_streams(n, v) ? MA_RES_STREAM_BLOCK : MA_BLOCK;
+  if (residual_streams(n, v)) return v;
   for (int u = 0; u < v; ++u)
     if (residual_tile_x(n, u) == *tile_x) return u;
   return v;
 }
 
-int residual_blocks(int n, int v) { return (n / residual_tile_x(n, v)) * (n / MA_RES_TY); }
+int residual_blocks(int n, int v) {
+  if (residual_streams(n, v)) return (n / 64) * (n / (MA_RES_STREAM_BLOCK / 64 * MA_RES_STREAM_ROWS));
+  return (n / residual_tile_x(n, v)) * (n / MA_RES_TY);
+}
 
 void launch_residual_only(const LaunchCtx& c, int n, int npairs, hipStream_t st, const TimedLaunch& ev) {
-  const int tx = residual_tile_x(n, c.var[3]);
   dim3 grid(residual_blocks(n, c.var[3]), npairs);
-  if (tx == 64) MA_LAUNCH(ev, k_residual<64>, grid, dim3(MA_BLOCK), st, c);
-  else if (tx == 32) MA_LAUNCH(ev, k_residual<32>, grid, dim3(MA_BLOCK), st, c);
-  else MA_LAUNCH(ev, k_residual<16>, grid, dim3(MA_BLOCK), st, c);
+  const bool nearest = c.interp == MA_INTERP_NEAREST;
+  if (residual_streams(n, c.var[3])) {
+    if (nearest)
+      MA_LAUNCH(ev, (k_residual_stream<MA_RES_STREAM_ROWS, MA_INTERP_NEAREST>), grid, dim3(MA_RES_STREAM_BLOCK), st, c);
+    else
+      MA_LAUNCH(ev, (k_residual_stream<MA_RES_STREAM_ROWS, MA_INTERP_BILINEAR>), grid, dim3(MA_RES_STREAM_BLOCK), st,
+                c);
+    return;
+  }
+  const int tx = residual_tile_x(n, c.var[3]);
+  if (nearest) {
+    if (tx == 64) MA_LAUNCH(ev, (k_residual<64, MA_INTERP_NEAREST>), grid, dim3(MA_BLOCK), st, c);
+    else if (tx == 32) MA_LAUNCH(ev, (k_residual<32, MA_INTERP_NEAREST>), grid, dim3(MA_BLOCK), st, c);
+    else MA_LAUNCH(ev, (k_residual<16, MA_INTERP_NEAREST>), grid, dim3(MA_BLOCK), st, c);
+  } else {
+    if (tx == 64) MA_LAUNCH(ev, (k_residual<64, MA_INTERP_BILINEAR>), grid, dim3(MA_BLOCK), st, c);
+    else if (tx == 32) MA_LAUNCH(ev, (k_residual<32, MA_INTERP_BILINEAR>), grid, dim3(MA_BLOCK), st, c);
+    else MA_LAUNCH(ev, (k_residual<16, MA_INTERP_BILINEAR>), grid, dim3(MA_BLOCK), st, c);
+  }
 }
 
 void launch_residual(const LaunchCtx& c, int n, int npairs, int step_mode, hipStream_t st, const TimedLaunch& ev) {
@@ -543,6 +755,20 @@ void launch_outputs(const LaunchCtx& c, int n, int npairs, hipStream_t st) {
   hipLaunchKernelGGL(k_outputs, dim3(elementwise_blocks(n), npairs), dim3(MA_BLOCK), 0, st, c);
 }
 
-void launch_summary(const PairState* s, const int* ids, int npairs, int* out, int seq, hipStream_t st) {
-  hipLaunchKernelGGL(k_summary, dim3(1), dim3(256), 0, st, s, ids, npairs, out, seq);
+void launch_summary(const PairState* s, const int* ids, int npairs, int* out, int seq, hipStream_t st,
+                    int* phases) {
+  hipLaunchKernelGGL(k_summary, dim3(1), dim3(256), 0, st, s, ids, npairs, out, seq, phases);
+}
+
+void launch_retire(const LaunchCtx& c, int n, int count, PairState* final_state, hipStream_t st) {
+  hipLaunchKernelGGL(k_retire, dim3(elementwise_blocks(n), count), dim3(MA_BLOCK), 0, st, c, final_state);
+}
+
+void launch_refill(PairDesc* desc, PairState* state, const RefillRecord* rec, int count, hipStream_t st) {
+  hipLaunchKernelGGL(k_refill, dim3(count), dim3(256), 0, st, desc, state, rec);
+}
+
+void launch_validate(const double* const* f, const double* const* g, const double* const* psi0, const int* n,
+                     int npairs, int nmax, int* bad, hipStream_t st) {
+  hipLaunchKernelGGL(k_validate, dim3(elementwise_blocks(nmax), npairs), dim3(MA_BLOCK), 0, st, f, g, psi0, n, bad);
 }

@@ -163,7 +163,91 @@ __global__ __launch_bounds__(MA_BLOCK) void k_restart(LaunchCtx c) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Power iteration on the inverse operator (Section 5.1): the vector steps and their
+// per-pair folds.  The right-hand side of the next solve lives in r, the solution
+// theta = A^{-1} b of the last one in x.
+// ---------------------------------------------------------------------------
+// elementwise step, with per-block partial sums (FP64) of the value it writes (or reads)
+__global__ __launch_bounds__(MA_BLOCK) void k_power_vec(LaunchCtx c, int mode, const float* b0) {
+  const int p = pair_of_block(c);
+  const PairDesc& d = c.desc[p];
+  const PairState& s = c.st[p];
+  const long nn = (long)d.n * d.n;
+  double acc = 0.0;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (long)gridDim.x * blockDim.x) {
+    if (mode == PW_SUM_B0) {
+      acc += (double)b0[e];
+    } else if (mode == PW_CENTER) {  // b = b_0 - mean(b_0)
+      const float v = (float)((double)b0[e] - s.aux[0]);
+      d.r[e] = v;
+      acc += (double)v * v;
+    } else if (mode == PW_SCALE) {  // b *= 1 / ||b|| (first vector)
+      const float v = (float)((double)d.r[e] * s.aux[1]);
+      d.r[e] = v;
+      acc += (double)v * v;
+    } else if (mode == PW_THETA) {  // ||theta||^2
+      acc += (double)d.x[e] * d.x[e];
+    } else {  // PW_NEXT: b = theta / ||theta||
+      const float v = (float)((double)d.x[e] * s.aux[1]);
+      d.r[e] = v;
+      acc += (double)v * v;
+    }
+  }
+  __shared__ double scratch[MA_BLOCK / 64];
+  double v[1] = {acc};
+  const int kinds[1] = {0};
+  block_reduce<1>(v, kinds, scratch);
+  if (threadIdx.x == 0) d.part[blockIdx.x] = v[0];
+}
+
+// one block per pair: folds the partial sums of the preceding k_power_vec launch
+__global__ __launch_bounds__(256) void k_power_fold(LaunchCtx c, int mode, int nblk, int k, double* out) {
+  const int p = pair_of_block(c);
+  const PairDesc& d = c.desc[p];
+  PairState& s = c.st[p];
+  __shared__ double scratch[4];
+  const int kinds[1] = {0};
+  double t[1];
+  fold_partials<1>(d.part, nblk, kinds, t, scratch);
+  if (threadIdx.x != 0) return;
+  const double nn = (double)d.n * d.n;
+  if (mode == PW_SUM_B0) {
+    s.aux[0] = t[0] / nn;
+  } else if (mode == PW_CENTER) {
+    const double nb = sqrt(fmax(t[0], 0.0));
+    s.aux[1] = nb > 0.0 ? 1.0 / nb : 0.0;
+  } else if (mode == PW_THETA) {  // rho_k = ||A^{-1} b_k|| for the unit b_k; the next b scales by 1 / rho_k
+    const double rho = sqrt(fmax(t[0], 0.0));
+    out[2 * k] = rho;
+    out[2 * k + 1] = (double)s.gmres_iters;
+    s.aux[1] = rho > 0.0 ? 1.0 / rho : 0.0;
+  } else {  // PW_SCALE, PW_NEXT: a GMRES solve of A sigma = b starts from sigma = 0
+    const double bn = sqrt(fmax(t[0], 0.0));
+    s.phase = PH_SOLVE;
+    s.bnorm = bn;
+    s.gm_target = c.gmres_tol * bn;
+    s.gm_running = bn > 0.0;
+    s.gm_restart = 0;
+    s.gm_cycle = 0;
+    s.gm_k = 0;
+    s.vscale[0] = bn > 0.0 ? 1.0 / bn : 0.0;
+    s.gv[0] = bn;
+  }
+}
+
 }  // namespace
+
+void launch_power_vec(const LaunchCtx& c, int n, int mode, const float* b0, double* out, int k, hipStream_t st) {
+  const int nb = power_blocks(n);
+  hipLaunchKernelGGL(k_power_vec, dim3(nb, 1), dim3(MA_BLOCK), 0, st, c, mode, b0);
+  hipLaunchKernelGGL(k_power_fold, dim3(1, 1), dim3(256), 0, st, c, mode, nb, k, out);
+}
+
+int power_blocks(int n) {
+  long b = (long)n * n / (MA_BLOCK * 4);
+  return b < 1 ? 1 : (int)(b > 1024 ? 1024 : b);
+}
 
 bool fft_size_supported(int n) {
   switch (n) {

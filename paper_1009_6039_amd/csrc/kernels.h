@@ -27,6 +27,8 @@ enum : int {
 };
 enum : int { PB_MATVEC = 0, PB_RECOVER = 1, PB_FORWARD = 2 };
 enum : int { PC_MATVEC = 0, PC_RECOVER = 1, PC_THETA_ONLY = 2 };
+// power iteration steps (k_power_vec / k_power_fold)
+enum : int { PW_SUM_B0 = 0, PW_CENTER = 1, PW_SCALE = 2, PW_THETA = 3, PW_NEXT = 4 };
 
 void launch_setup(const LaunchCtx& c, int n, int npairs, hipStream_t st);
 void launch_setup_fields(const LaunchCtx& c, int n, int npairs, hipStream_t st);
@@ -39,7 +41,14 @@ void launch_residual_only(const LaunchCtx& c, int n, int npairs, hipStream_t st,
 void launch_residual_shift(const LaunchCtx& c, int n, float* out, hipStream_t st);
 void launch_step_update(const LaunchCtx& c, int n, int npairs, hipStream_t st);
 void launch_outputs(const LaunchCtx& c, int n, int npairs, hipStream_t st);
-void launch_summary(const PairState* s, const int* ids, int npairs, int* out, int seq, hipStream_t st);
+void launch_summary(const PairState* s, const int* ids, int npairs, int* out, int seq, hipStream_t st,
+                    int* phases = nullptr);
+// continuous batching: outputs and final states of finished slots (ids in the context),
+// refill records scattered into their slots, validation of every pair's inputs
+void launch_retire(const LaunchCtx& c, int n, int count, PairState* final_state, hipStream_t st);
+void launch_refill(PairDesc* desc, PairState* state, const RefillRecord* rec, int count, hipStream_t st);
+void launch_validate(const double* const* f, const double* const* g, const double* const* psi0, const int* n,
+                     int npairs, int nmax, int* bad, hipStream_t st);
 void launch_tune_fill(const LaunchCtx& c, int n, int npairs, hipStream_t st);
 
 // FFT passes and GMRES kernels; `tw` is the length-n twiddle table
@@ -65,3 +74,7 @@ void launch_passC(const LaunchCtx& c, int n, int npairs, int mode, int j, const 
 void launch_passC_only(const LaunchCtx& c, int n, int npairs, int mode, int j, const float2* tw, hipStream_t st,
                   const TimedLaunch& ev = TimedLaunch());
 void launch_restart(const LaunchCtx& c, int n, int npairs, hipStream_t st);
+// one power-iteration step on pair 0 of the context and its fold; `out` receives
+// (rho_k, GMRES iterations so far) at index 2k, 2k+1 for mode PW_THETA
+int power_blocks(int n);
+void launch_power_vec(const LaunchCtx& c, int n, int mode, const float* b0, double* out, int k, hipStream_t st);

@@ -77,6 +77,16 @@ struct ma_plan {
   long long prof_launches = 0;
   int prof_every = 1;       // time every prof_every-th launch of the class
   long long prof_seq = 0;   // launches of the class seen since ma_plan_profile
+  // continuous batching: final states by pair, per-slot phases in mapped host memory,
+  // a pinned host staging buffer and its device copy (validation tables, refill records)
+  PairState* d_final = nullptr;
+  int final_cap = 0;
+  int* h_phase = nullptr;
+  int* d_phase = nullptr;
+  int phase_cap = 0;
+  char* h_stage = nullptr;
+  char* d_stage = nullptr;
+  size_t stage_cap = 0;
   // no-allocation mode (ma_solve_noalloc): every device buffer is carved from the
   // library's static scratch array, the summary lives in device memory and is copied
   // back after each launch that the host waits on
@@ -143,7 +153,8 @@ int validate_options(const ma_options& o) {
       (o.symbol != MA_SYMBOL_SPECTRAL && o.symbol != MA_SYMBOL_FD4) ||
       (o.precond != MA_PRECOND_NONE && o.precond != MA_PRECOND_DIAG) ||
       !(o.boundary_frac >= 0.0 && o.boundary_frac < 1.0) ||
-      (o.forcing != MA_FORCING_FIXED && o.forcing != MA_FORCING_ADAPTIVE) || !(o.wait_limit_s > 0.0))
+      (o.forcing != MA_FORCING_FIXED && o.forcing != MA_FORCING_ADAPTIVE) || !(o.wait_limit_s > 0.0) ||
+      o.max_active < 0)
     return MA_EINVAL;
   return MA_OK;
 }
@@ -383,9 +394,9 @@ int next_seq(ma_plan* P) {
   return P->sum_seq;
 }
 
-int read_summary(ma_plan* P, int npairs, hipStream_t st) {
+int read_summary(ma_plan* P, int npairs, hipStream_t st, int* phases = nullptr) {
   const int seq = next_seq(P);
-  launch_summary(P->d_state, P->d_ids, npairs, P->d_summary, seq, st);
+  launch_summary(P->d_state, P->d_ids, npairs, P->d_summary, seq, st, phases);
   if (!P->no_alloc) return wait_summary(P, 0, seq, st);
   // device-memory summary: copy it back and wait for the stream, within wait_limit_s
   HIP_TRY(hipMemcpyAsync(P->h_summary, P->d_summary, sizeof(int) * MA_SUMMARY_INTS, hipMemcpyDeviceToHost, st));
@@ -477,6 +488,252 @@ int run_solver(ma_plan* P, int npairs, double damping, double tol, hipStream_t s
   }
   for (const Class& c : cls) launch_outputs(make_ctx(P, c), c.n, c.count, st);
   HIP_TRY(hipMemcpyAsync(P->h_state.data(), P->d_state, sizeof(PairState) * npairs, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  prof_flush(P);
+  return MA_OK;
+}
+
+// buffers of the continuous mode, grown on demand
+int ensure_continuous(ma_plan* P, int npairs, int nslots, size_t stage_bytes) {
+  if (npairs > P->final_cap) {
+    if (P->d_final) (void)hipFree(P->d_final);
+    P->d_final = nullptr;
+    P->final_cap = 0;
+    if (hipMalloc(&P->d_final, sizeof(PairState) * npairs) != hipSuccess) return MA_ENOMEM;
+    P->final_cap = npairs;
+  }
+  if (nslots > P->phase_cap) {
+    if (P->h_phase) (void)hipHostFree(P->h_phase);
+    P->h_phase = P->d_phase = nullptr;
+    P->phase_cap = 0;
+    if (hipHostMalloc(&P->h_phase, sizeof(int) * nslots, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+        hipHostGetDevicePointer((void**)&P->d_phase, P->h_phase, 0) != hipSuccess)
+      return MA_ENOMEM;
+    P->phase_cap = nslots;
+  }
+  if (stage_bytes > P->stage_cap) {
+    if (P->h_stage) (void)hipHostFree(P->h_stage);
+    if (P->d_stage) (void)hipFree(P->d_stage);
+    P->h_stage = P->d_stage = nullptr;
+    P->stage_cap = 0;
+    if (hipHostMalloc(&P->h_stage, stage_bytes, hipHostMallocDefault) != hipSuccess ||
+        hipMalloc(&P->d_stage, stage_bytes) != hipSuccess)
+      return MA_ENOMEM;
+    P->stage_cap = stage_bytes;
+  }
+  return MA_OK;
+}
+
+// The caller's pair q in slot s: its buffers, a fresh state (the initial potential, if
+// any, as a checked start)
+void fill_slot(ma_plan* P, int s, int q, const double* const* f, const double* const* g, const double* const* psi0,
+               double* const* psi, double* const* map, double damping, double tol, PairDesc& d, PairState& st) {
+  d = P->h_desc[s];  // the slot's workspace
+  d.pair = q;
+  d.f_in = f[q];
+  d.g_in = g[q];
+  d.psi0_in = psi0 ? psi0[q] : nullptr;
+  d.psi_out = psi[q];
+  d.map_out = map ? map[q] : nullptr;
+  st = fresh_state(damping, tol);
+  st.warm = d.psi0_in != nullptr;
+}
+
+// Continuous batching (option max_active): at most max_active pairs are in flight, in
+// slots shared among the size classes in proportion to their pair counts; when the
+// summary after a residual shows a slot's pair finished, its outputs and final state
+// are written (k_retire) and the slot takes the next pending pair of its size
+// (k_refill, then the set-up kernels for those slots), which enters the next tick's
+// residual.  Each pair's arithmetic is that of run_solver.  All inputs are validated
+// first, so that an invalid density is a hard error before anything is written.
+int run_continuous(ma_plan* P, int npairs, const std::vector<int>& ns, const double* const* f,
+                   const double* const* g, const double* const* psi0, double* const* psi, double* const* map,
+                   double damping, double tol, hipStream_t st, std::vector<PairState>& final_states) {
+  struct Queue {
+    int n, first_slot, nslots;
+    std::vector<int> pairs;
+    size_t next = 0;
+  };
+  std::map<int, std::vector<int>> by;
+  for (int q = 0; q < npairs; ++q) by[ns[q]].push_back(q);
+  std::vector<int> slot_n;
+  std::vector<Queue> qs;
+  for (auto& kv : by) {
+    Queue q;
+    q.n = kv.first;
+    q.pairs = kv.second;
+    const long share = std::lround((double)P->opt.max_active * (double)kv.second.size() / (double)npairs);
+    q.nslots = (int)std::max(1L, std::min((long)kv.second.size(), share));
+    q.first_slot = (int)slot_n.size();
+    for (int k = 0; k < q.nslots; ++k) slot_n.push_back(q.n);
+    qs.push_back(q);
+  }
+  const int S = (int)slot_n.size();
+  int e = ensure_workspace(P, slot_n);
+  if (e) return e;
+  const size_t val_bytes = align256((size_t)npairs * (3 * sizeof(void*) + sizeof(int))) + 256;
+  const size_t tick_bytes = align256((size_t)S * 2 * sizeof(int)) + (size_t)S * sizeof(RefillRecord);
+  e = ensure_continuous(P, npairs, S, std::max(val_bytes, tick_bytes));
+  if (e) return e;
+  // 1. every pair's inputs
+  {
+    char* h = P->h_stage;
+    const void** hf = (const void**)h;
+    const void** hg = hf + npairs;
+    const void** hp = hg + npairs;
+    int* hn = (int*)(hp + npairs);
+    int* hbad = (int*)(h + val_bytes - 256);
+    for (int q = 0; q < npairs; ++q) {
+      hf[q] = f[q];
+      hg[q] = g[q];
+      hp[q] = psi0 ? psi0[q] : nullptr;
+      hn[q] = ns[q];
+    }
+    *hbad = 0;
+    HIP_TRY(hipMemcpyAsync(P->d_stage, h, val_bytes, hipMemcpyHostToDevice, st));
+    const double* const* df = (const double* const*)P->d_stage;
+    int nmax = 0;
+    for (int n : ns) nmax = std::max(nmax, n);
+    launch_validate(df, df + npairs, psi0 ? df + 2 * npairs : nullptr, (const int*)(df + 3 * npairs), npairs, nmax,
+                    (int*)(P->d_stage + val_bytes - 256), st);
+    int bad = 0;
+    HIP_TRY(hipMemcpyAsync(&bad, P->d_stage + val_bytes - 256, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (bad) return MA_EINVAL;
+  }
+  // 2. slots 0..S-1 in class order, filled with the first pairs of each class
+  std::vector<int> ids(S);
+  for (int s = 0; s < S; ++s) ids[s] = s;
+  HIP_TRY(hipMemcpyAsync(P->d_ids, ids.data(), sizeof(int) * S, hipMemcpyHostToDevice, st));
+  std::vector<Class> cls;
+  for (const Queue& q : qs) {
+    Class c;
+    c.n = q.n;
+    c.count = q.nslots;
+    c.d_ids = P->d_ids + q.first_slot;
+    c.tw = P->tw[q.n];
+    c.mt = P->mt[std::make_pair(q.n, P->opt.symbol)];
+    cls.push_back(c);
+  }
+  std::vector<int> slot_pair(S, -1);
+  std::vector<PairDesc> hd(S);
+  P->h_state.assign(S, PairState{});
+  for (Queue& q : qs)
+    for (int k = 0; k < q.nslots; ++k) {
+      const int s = q.first_slot + k, pr = q.pairs[q.next++];
+      fill_slot(P, s, pr, f, g, psi0, psi, map, damping, tol, hd[s], P->h_state[s]);
+      slot_pair[s] = pr;
+    }
+  HIP_TRY(hipMemcpyAsync(P->d_desc, hd.data(), sizeof(PairDesc) * S, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(P->d_state, P->h_state.data(), sizeof(PairState) * S, hipMemcpyHostToDevice, st));
+  for (const Class& c : cls) launch_setup(make_ctx(P, c), c.n, c.count, st);
+  // 3. ticks; a refilled slot enters the next tick's residual
+  const long per_pair = (long)(P->opt.max_newton + 1) * (P->opt.max_backtrack + 3) + 8;
+  const long max_ticks = per_pair * (long)((npairs + S - 1) / S + 1);
+  int retired = 0;
+  const ClassList cl{cls.data(), (int)cls.size()};
+  for (long tick = 0; tick < max_ticks && retired < npairs; ++tick) {
+    for (const Class& c : cls) L_res(P, c, 0, st);
+    e = read_summary(P, S, st, P->d_phase);
+    if (e) return e;
+    const int n_solve = P->h_summary[PH_SOLVE];
+    const int n_update = P->h_summary[PH_BACKTRACK] + P->h_summary[PH_REVERT];
+    // finished slots: retire their pairs and refill from the class's queue
+    int* rid = (int*)P->h_stage;
+    int* fid = rid + S;
+    RefillRecord* rec = (RefillRecord*)(P->h_stage + align256((size_t)S * 2 * sizeof(int)));
+    std::vector<int> nret(qs.size(), 0), nref(qs.size(), 0), ret_at(qs.size()), ref_at(qs.size());
+    int nr = 0, nf = 0;
+    for (size_t k = 0; k < qs.size(); ++k) {
+      Queue& q = qs[k];
+      ret_at[k] = nr;
+      for (int s = q.first_slot; s < q.first_slot + q.nslots; ++s)
+        if (slot_pair[s] >= 0 && P->h_phase[s] == PH_DONE) rid[nr++] = s;
+      nret[k] = nr - ret_at[k];
+      ref_at[k] = nf;
+      for (int r = ret_at[k]; r < nr; ++r) {
+        const int s = rid[r];
+        slot_pair[s] = -1;
+        ++retired;
+        if (q.next < q.pairs.size()) {
+          const int pr = q.pairs[q.next++];
+          rec[nf].slot = s;
+          fill_slot(P, s, pr, f, g, psi0, psi, map, damping, tol, rec[nf].desc, rec[nf].state);
+          fid[nf++] = s;
+          slot_pair[s] = pr;
+        }
+      }
+      nref[k] = nf - ref_at[k];
+    }
+    if (nr > 0) {
+      const size_t bytes = align256((size_t)S * 2 * sizeof(int)) + (size_t)nf * sizeof(RefillRecord);
+      HIP_TRY(hipMemcpyAsync(P->d_stage, P->h_stage, bytes, hipMemcpyHostToDevice, st));
+      const int* d_rid = (const int*)P->d_stage;
+      const int* d_fid = d_rid + S;
+      for (size_t k = 0; k < qs.size(); ++k)
+        if (nret[k]) {
+          LaunchCtx x = make_ctx(P, cls[k]);
+          x.pair_ids = d_rid + ret_at[k];
+          launch_retire(x, qs[k].n, nret[k], P->d_final, st);
+        }
+      if (nf) {
+        launch_refill(P->d_desc, P->d_state,
+                      (const RefillRecord*)(P->d_stage + align256((size_t)S * 2 * sizeof(int))), nf, st);
+        for (size_t k = 0; k < qs.size(); ++k)
+          if (nref[k]) {
+            LaunchCtx x = make_ctx(P, cls[k]);
+            x.pair_ids = d_fid + ref_at[k];
+            launch_setup(x, qs[k].n, nref[k], st);
+          }
+      }
+    }
+    if (n_solve > 0) {
+      for (const Class& c : cls) L_A(P, c, PA_INIT, 0, st);
+      e = launch_cycle_body(P, cl, S, st);
+      if (e) return e;
+      for (int cyc = 0; cyc < P->opt.gmres_max_restarts; ++cyc) {
+        e = read_summary(P, S, st);
+        if (e) return e;
+        if (P->h_summary[6] == 0) break;
+        for (const Class& c : cls) {
+          launch_restart(make_ctx(P, c), c.n, c.count, st);
+          L_A(P, c, PA_PLAIN, 0, st);
+        }
+        e = launch_cycle_body(P, cl, S, st);
+        if (e) return e;
+      }
+      for (const Class& c : cls) {
+        L_A(P, c, PA_RECOVER, 0, st);
+        L_B(P, c, PB_RECOVER, 0, st);
+        L_C(P, c, PC_RECOVER, 0, st);
+      }
+    }
+    if (n_update > 0)
+      for (const Class& c : cls) launch_step_update(make_ctx(P, c), c.n, c.count, st);
+  }
+  if (retired < npairs) {  // the tick limit: write what the unfinished slots hold
+    HIP_TRY(hipStreamSynchronize(st));  // the staging buffer's last copy has been read
+    int nr = 0;
+    int* rid = (int*)P->h_stage;
+    for (int s = 0; s < S; ++s)
+      if (slot_pair[s] >= 0) rid[nr++] = s;
+    HIP_TRY(hipMemcpyAsync(P->d_stage, P->h_stage, sizeof(int) * S, hipMemcpyHostToDevice, st));
+    for (size_t k = 0; k < qs.size(); ++k) {
+      int cnt = 0, at = -1;
+      for (int r = 0; r < nr; ++r)
+        if (slot_n[rid[r]] == qs[k].n) {
+          if (at < 0) at = r;
+          ++cnt;
+        }
+      if (cnt) {
+        LaunchCtx x = make_ctx(P, cls[k]);
+        x.pair_ids = (const int*)P->d_stage + at;
+        launch_retire(x, qs[k].n, cnt, P->d_final, st);
+      }
+    }
+  }
+  final_states.assign(npairs, PairState{});
+  HIP_TRY(hipMemcpyAsync(final_states.data(), P->d_final, sizeof(PairState) * npairs, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   prof_flush(P);
   return MA_OK;
@@ -626,6 +883,7 @@ void ma_options_default(ma_options* o) {
   o->boundary_frac = 0.1;
   o->forcing = MA_FORCING_FIXED;
   o->wait_limit_s = 600.0;
+  o->max_active = 0;
 }
 
 const char* ma_strerror(int code) {
@@ -680,6 +938,10 @@ void ma_plan_destroy(ma_plan* P) {
   if (P->d_state) hipFree(P->d_state);
   if (P->d_ids) hipFree(P->d_ids);
   if (P->h_summary) hipHostFree(P->h_summary);
+  if (P->d_final) (void)hipFree(P->d_final);
+  if (P->h_phase) (void)hipHostFree(P->h_phase);
+  if (P->h_stage) (void)hipHostFree(P->h_stage);
+  if (P->d_stage) (void)hipFree(P->d_stage);
   for (auto& kv : P->tw) hipFree(kv.second);
   for (auto& kv : P->mt) hipFree(kv.second);
   for (hipEvent_t e : P->ev) hipEventDestroy(e);
@@ -805,6 +1067,20 @@ int ma_solve_batched(ma_plan* P, int npairs, const int* n, const double* const* 
   for (int q = 0; q < npairs; ++q)
     if (!n_ok(ns[q]) || !f[q] || !g[q] || !psi[q]) return MA_EINVAL;
   hipStream_t st = (hipStream_t)stream;
+  if (P->opt.max_active > 0 && P->opt.max_active < npairs) {  // continuous batching
+    std::vector<PairState> fin;
+    int e = run_continuous(P, npairs, ns, f, g, psi0, psi, map, damping, tol, st, fin);
+    if (e) return e;
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    int worst = MA_OK;
+    for (int q = 0; q < npairs; ++q) {
+      ma_report r;
+      fill_report(fin[q], &r, ms);
+      if (reps) reps[q] = r;
+      worst = std::max(worst, r.status);
+    }
+    return worst;
+  }
   int e = ensure_workspace(P, ns);
   if (e) return e;
   for (int q = 0; q < npairs; ++q) {
@@ -989,6 +1265,73 @@ int ma_step_gmres(ma_plan* P, int n, const float* h, const float* coef, const do
     if (iters) *iters = P->h_state[0].gmres_iters;
   } while (0);
   P->opt = saved;
+  return rc;
+}
+
+int ma_power_inverse(ma_plan* P, int n, const float* coef, const double* abar, const float* b0, int iters,
+                     double gmres_tol, int gmres_m, int max_restarts, double* rho, int* gmres_iters, void* stream) {
+  if (!P || !coef || !abar || !b0 || !rho || iters < 1 || iters > 100000 || gmres_m < 1 || gmres_m > MA_MMAX ||
+      !(gmres_tol > 0.0) || max_restarts < 0 || !n_ok(n))
+    return MA_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  double* d_out = nullptr;
+  if (hipMalloc(&d_out, sizeof(double) * 2 * (size_t)iters) != hipSuccess) return MA_ENOMEM;
+  const ma_options saved = P->opt;
+  P->opt.gmres_m = gmres_m;
+  P->opt.gmres_max_restarts = max_restarts;
+  P->opt.gmres_tol = gmres_tol;
+  P->opt.precond = MA_PRECOND_NONE;  // the operator of Section 4.2
+  Class c;
+  int rc = step_prepare(P, n, step_state(abar), st, c);
+  std::vector<double> out(2 * (size_t)iters, 0.0);
+  while (rc == MA_OK) {
+    const PairDesc& d = P->h_desc[0];
+    if (hipMemcpyAsync(d.coef, coef, 20 * (size_t)n * n, hipMemcpyDeviceToDevice, st) != hipSuccess) {
+      rc = MA_EHIP;
+      break;
+    }
+    LaunchCtx x = make_ctx(P, c);
+    x.precond = MA_PRECOND_NONE;
+    std::vector<Class> cls(1, c);
+    // b_0 - mean(b_0), normalised; the first GMRES solve starts from it
+    launch_power_vec(x, n, PW_SUM_B0, b0, d_out, 0, st);
+    launch_power_vec(x, n, PW_CENTER, b0, d_out, 0, st);
+    launch_power_vec(x, n, PW_SCALE, b0, d_out, 0, st);
+    for (int k = 0; k < iters && rc == MA_OK; ++k) {
+      // theta = A^{-1} b_k: GMRES on L Lbar^{-1} sigma = b_k, theta = Lbar^{-1} sigma (Section 4.2)
+      launch_passA(x, n, 1, PA_INIT, 0, c.tw, st);
+      if ((rc = launch_cycle_body(P, ClassList{cls.data(), 1}, 1, st))) break;
+      for (int cyc = 0; cyc < max_restarts; ++cyc) {
+        if ((rc = read_summary(P, 1, st))) break;
+        if (P->h_summary[6] == 0) break;
+        launch_restart(x, n, 1, st);
+        launch_passA(x, n, 1, PA_PLAIN, 0, c.tw, st);
+        if ((rc = launch_cycle_body(P, ClassList{cls.data(), 1}, 1, st))) break;
+      }
+      if (rc) break;
+      launch_passA(x, n, 1, PA_RECOVER, 0, c.tw, st);
+      launch_passB(x, n, 1, PB_RECOVER, 0, c.tw, st);
+      launch_passC(x, n, 1, PC_THETA_ONLY, 0, c.tw, st);
+      // rho_k = ||theta||, b_{k+1} = theta / rho_k
+      launch_power_vec(x, n, PW_THETA, b0, d_out, k, st);
+      if (k + 1 < iters) launch_power_vec(x, n, PW_NEXT, b0, d_out, k, st);
+    }
+    if (rc) break;
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(out.data(), d_out, sizeof(double) * out.size(), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+      rc = MA_EHIP;
+      break;
+    }
+    for (int k = 0; k < iters; ++k) {
+      rho[k] = out[2 * k];
+      if (gmres_iters) gmres_iters[k] = (int)(out[2 * k + 1] - (k > 0 ? out[2 * k - 1] : 0.0));
+    }
+    break;
+  }
+  P->opt = saved;
+  if (hipStreamSynchronize(st) != hipSuccess) rc = rc ? rc : MA_EHIP;
+  (void)hipFree(d_out);
   return rc;
 }
 

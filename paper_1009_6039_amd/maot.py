@@ -30,7 +30,7 @@ EXPORTED = ("ma_abi_version", "ma_options_default", "ma_strerror", "ma_plan_crea
             "ma_plan_profile", "ma_plan_profile_read",
             "ma_plan_autotune", "ma_plan_set_tuning", "ma_plan_get_tuning", "ma_tune_geometry",
             "ma_step_residual", "ma_step_fft2", "ma_step_strain_apply",
-            "ma_step_lbar_inverse", "ma_step_gmres",
+            "ma_step_lbar_inverse", "ma_step_gmres", "ma_power_inverse",
             "ma_cnn_create", "ma_cnn_destroy", "ma_cnn_param_count", "ma_cnn_set_params",
             "ma_cnn_get_params", "ma_cnn_prepare_input", "ma_cnn_target", "ma_cnn_forward",
             "ma_cnn_gradients", "ma_cnn_train_step", "ma_cnn_warm_start")
@@ -42,18 +42,21 @@ class Options(ctypes.Structure):
                 ("interp", ctypes.c_int), ("op_mode", ctypes.c_int),
                 ("damping_policy", ctypes.c_int), ("max_backtrack", ctypes.c_int),
                 ("symbol", ctypes.c_int), ("precond", ctypes.c_int), ("boundary_frac", ctypes.c_double),
-                ("forcing", ctypes.c_int), ("wait_limit_s", ctypes.c_double)]
+                ("forcing", ctypes.c_int), ("wait_limit_s", ctypes.c_double), ("max_active", ctypes.c_int)]
 
 
 class Tuning(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("npairs", ctypes.c_int), ("variant", ctypes.c_int * 4),
                 ("from_cache", ctypes.c_int), ("rejected", ctypes.c_int),
-                ("us", ctypes.c_double * 4), ("us_default", ctypes.c_double * 4)]
+                ("us", ctypes.c_double * 4), ("us_default", ctypes.c_double * 4),
+                ("us_variant", (ctypes.c_double * 8) * 4)]
 
     def as_dict(self):
         return {"n": self.n, "npairs": self.npairs, "variant": list(self.variant),
                 "from_cache": bool(self.from_cache), "rejected": self.rejected,
-                "us": list(self.us), "us_default": list(self.us_default)}
+                "us": list(self.us), "us_default": list(self.us_default),
+                "us_variant": {name: [round(x, 2) for x in self.us_variant[k]]
+                               for k, name in enumerate(TUNE_PASSES)}}
 
 
 TUNE_PASSES = ("row_a", "column", "row_c", "residual")
@@ -118,6 +121,8 @@ def load():
     lib.ma_step_strain_apply.argtypes = [P, I, P, P, ctypes.POINTER(D), P, P]
     lib.ma_step_lbar_inverse.argtypes = [P, I, P, ctypes.POINTER(D), P, P]
     lib.ma_step_gmres.argtypes = [P, I, P, P, ctypes.POINTER(D), I, D, I, P, ctypes.POINTER(I), P]
+    lib.ma_power_inverse.argtypes = [P, I, P, ctypes.POINTER(D), P, I, D, I, I, ctypes.POINTER(D),
+                                     ctypes.POINTER(I), P]
     F, L = ctypes.c_float, ctypes.c_long
     lib.ma_cnn_create.argtypes = [I, I, I, I, ctypes.POINTER(I), ctypes.POINTER(P)]
     lib.ma_cnn_destroy.argtypes = [P]
@@ -343,6 +348,19 @@ class Plan:
                                     int(max_restarts), _ptr(theta), ctypes.byref(its), _stream()),
                "ma_step_gmres")
         return theta, its.value
+
+
+    def power_inverse(self, coef, abar, b0, iters=8, gmres_tol=1e-6, m=10, max_restarts=50):
+        """Power iteration on the inverse operator (Section 5.1): (rho_k, GMRES iterations per step)."""
+        coef = _dev(coef, torch.float32)
+        b0 = _dev(b0, torch.float32)
+        n = b0.shape[0]
+        ab = (ctypes.c_double * 5)(*[float(a) for a in abar])
+        rho = (ctypes.c_double * iters)()
+        its = (ctypes.c_int * iters)()
+        _check(load().ma_power_inverse(self._h, n, _ptr(coef), ab, _ptr(b0), int(iters), float(gmres_tol), int(m),
+                                       int(max_restarts), rho, its, _stream()), "ma_power_inverse")
+        return list(rho), list(its)
 
 
 class WarmStartNet:

@@ -604,3 +604,38 @@ def test_host_wait_limit_returns_an_error_and_the_plan_recovers(maot):
         assert np.max(np.abs(host(psi) - ref)) <= 1e-6 * np.max(np.abs(ref))
     finally:
         p.close()
+
+
+def test_continuous_batching_is_bitwise_the_batched_solve(maot):
+    # option max_active: at most 4 of 11 mixed-size pairs in flight, finished slots refilled
+    # within the call.  Every pair's potential, map and counts are bitwise those of the
+    # all-at-once batch (each pair's arithmetic does not depend on its slot or its
+    # neighbours), with and without initial potentials; an invalid density anywhere in the
+    # batch is refused before anything is solved.
+    sizes = [64, 128, 64, 64, 128, 64, 64, 128, 64, 64, 64]
+    pairs = [W.blobs(n, W.seed_for(3, 40 + q)) for q, n in enumerate(sizes)]
+    fs = [dev(a) for a, _ in pairs]
+    gs = [dev(b) for _, b in pairs]
+    x = [np.arange(n) / n for n in sizes]
+    psi0 = [dev(1e-3 * np.sin(2 * np.pi * xi)[:, None] * np.cos(2 * np.pi * xi)[None, :]) for xi in x]
+    opts = dict(damping_policy="backtrack", symbol="fd4", precond="diag", gmres_tol=0.2, forcing="adaptive",
+                max_newton=300)
+    p = maot.Plan(n_max=128, batch_capacity=len(sizes), **opts)
+    q = maot.Plan(n_max=128, batch_capacity=4, max_active=4, **opts)
+    try:
+        for start in (None, psi0):
+            a, ma_, ra = p.solve_batched(fs, gs, damping=1.0, tol=1e-8, psi0s=start, want_map=True)
+            b, mb, rb = q.solve_batched(fs, gs, damping=1.0, tol=1e-8, psi0s=start, want_map=True)
+            for k in range(len(sizes)):
+                assert ra[k]["status"] == 0 and rb[k]["status"] == 0
+                assert torch.equal(a[k], b[k]) and torch.equal(ma_[k], mb[k]), k
+                for key in ("newton_iters", "gmres_iters", "backtracks", "res_rms", "warm_steps"):
+                    assert ra[k][key] == rb[k][key], (k, key)
+        bad = [t.clone() for t in gs]
+        bad[7][3, 3] = -1.0
+        with pytest.raises(maot.MAError) as e:
+            q.solve_batched(fs, bad, damping=1.0, tol=1e-8)
+        assert e.value.code == -1
+    finally:
+        p.close()
+        q.close()
