@@ -279,10 +279,13 @@ int ma_power_inverse(ma_plan* plan, int n, const float* coef, const double* abar
  * rows / columns per workgroup (residual: half the tile width), 2 twice as many
  * (residual: a quarter of the tile width), 3 the default tile with half the threads
  * (residual: the streaming kernel, where n is a multiple of 64: a wave walks down
- * 64 columns with the stencil rows in registers and no LDS tile).  A variant that
- * coincides with a smaller index is skipped.
+ * 64 columns with the stencil rows in registers and no LDS tile); 4..7 the
+ * wave-owned transforms, where each wavefront runs whole transforms in a padded LDS
+ * region of its own with wave-level synchronisation only (row pass C: one or two row
+ * pairs per block, n >= 128).  A variant that coincides with a smaller index is
+ * skipped; its geometry query returns that index.
  * ------------------------------------------------------------------------- */
-#define MA_TUNE_VARIANTS 4
+#define MA_TUNE_VARIANTS 8
 #define MA_TUNE_SLOTS 8  /* room for the per-variant times below */
 
 typedef struct ma_tuning {

@@ -111,6 +111,10 @@ struct LaunchCtx {
   int precond;  // MA_PRECOND_*: left scaling of the GMRES system by the relative trace
   double boundary_frac;  // step halving: smallest allowed ratio of min det to its current value
   int forcing;           // MA_FORCING_*: fixed or adaptive GMRES tolerance per Newton direction
+  // compacted launches: when set, pair_ids is a device list of the pairs that take part
+  // and *active_n its length; blocks with blockIdx.y >= *active_n exit at once (the grid
+  // is sized by an upper bound the host knows)
+  const int* active_n;
 };
 
 // Global-address-space view of a device buffer.  Accesses through it compile to
@@ -139,7 +143,11 @@ __device__ inline void count_bytes(const LaunchCtx& c, double bytes_per_point, i
     atomicAdd(c.prof_bytes, (unsigned long long)(bytes_per_point * (double)n * (double)n));
 }
 
-__device__ inline int pair_of_block(const LaunchCtx& c) { return c.pair_ids[blockIdx.y]; }
+// the pair of this block, or -1 for a block beyond a compacted list (it exits)
+__device__ inline int pair_of_block(const LaunchCtx& c) {
+  if (c.active_n && (int)blockIdx.y >= *c.active_n) return -1;
+  return c.pair_ids[blockIdx.y];
+}
 
 // ---------------------------------------------------------------------------
 // Block reductions (FP64), deterministic order.

@@ -190,3 +190,84 @@ template <int N, int NF, int BLOCK, bool INV, int LAYOUT>
 __device__ __forceinline__ void fft_lds(float2* lds, const float2* __restrict__ tw) {
   fft_stages<N, 1, NF, BLOCK, INV, LAYOUT>(lds, tw);
 }
+
+// ---------------------------------------------------------------------------
+// Transforms owned by one wavefront.  The sequence sits in an LDS region private to
+// the wave, element e at wpad(e) = e + e / 8 (one pad word pair after every eight
+// elements: the strided writes of a radix-8 stage then spread over the banks), and a
+// stage synchronises only its own wave: a wave's LDS operations execute in order, so a
+// compiler barrier between a stage's writes and the next stage's reads is enough.
+// Lane l runs butterflies l, l + 64, ... of each stage (any N; lanes idle where a
+// stage has fewer than 64 butterflies).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int wpad(int e) { return e + (e >> 3); }
+template <int N>
+struct WaveBuf {
+  static constexpr int size = N + N / 8;
+};
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int N, int NS, int R, bool INV>
+__device__ __forceinline__ void wfft_stage(float2* L, const float2* __restrict__ tw, int lane) {
+  constexpr int NB = N / R;
+  constexpr int PER = (NB + 63) / 64;
+  constexpr int TWS = N / (NS * R);
+  float2 v[PER][R];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int j = lane + 64 * q;
+    if (NB % 64 == 0 || j < NB) {
+      const int k = j % NS;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = L[wpad(j + r * NB)];
+      if (NS > 1) {
+        float2 w[R];
+        w[1] = tw[k * TWS];
+        if constexpr (R >= 3) w[2] = tw[2 * k * TWS];
+        if constexpr (R == 4) w[3] = cmul(w[1], w[2]);
+        if constexpr (R == 8) {
+          w[4] = tw[4 * k * TWS];
+          w[3] = cmul(w[1], w[2]);
+          w[5] = cmul(w[4], w[1]);
+          w[6] = cmul(w[4], w[2]);
+          w[7] = cmul(w[4], w[3]);
+        }
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], INV ? cconj(w[r]) : w[r]);
+      }
+      dft<R, INV>(v[q]);
+    }
+  }
+  wave_sync();
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int j = lane + 64 * q;
+    if (NB % 64 == 0 || j < NB) {
+      const int k = j % NS;
+      const int base = (j / NS) * NS * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) L[wpad(base + r * NS)] = v[q][r];
+    }
+  }
+  wave_sync();
+}
+
+template <int N, int NS, bool INV>
+__device__ __forceinline__ void wfft_stages(float2* L, const float2* __restrict__ tw, int lane) {
+  if constexpr (NS < N) {
+    constexpr int R = pick_radix(N / NS);
+    wfft_stage<N, NS, R, INV>(L, tw, lane);
+    wfft_stages<N, NS * R, INV>(L, tw, lane);
+  }
+}
+
+// In-place transform of the wave's sequence (written by the wave before the call);
+// ends synchronised, the result in natural order at wpad(e).
+template <int N, bool INV>
+__device__ __forceinline__ void wfft(float2* L, const float2* __restrict__ tw, int lane) {
+  wfft_stages<N, 1, INV>(L, tw, lane);
+}

@@ -12,6 +12,7 @@
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(MA_BLOCK) void k_setup_sums(LaunchCtx c, int nblk) {
   const int p = pair_of_block(c);
+  if (p < 0) return;
   const PairDesc& d = c.desc[p];
   PairState& s = c.st[p];
   const long nn = (long)d.n * d.n;
@@ -37,6 +38,7 @@ __global__ __launch_bounds__(MA_BLOCK) void k_setup_sums(LaunchCtx c, int nblk) 
 
 __global__ __launch_bounds__(MA_BLOCK) void k_setup_finalize(LaunchCtx c, int nblk) {
   const int p = pair_of_block(c);
+  if (p < 0) return;
   const PairDesc& d = c.desc[p];
   PairState& s = c.st[p];
   __shared__ double scratch[(MA_BLOCK / 64) * 4];
@@ -56,6 +58,7 @@ __global__ __launch_bounds__(MA_BLOCK) void k_setup_finalize(LaunchCtx c, int nb
 // (reading P5) and the initial iterate u0 = psi0 - mean(psi0) or 0.
 __global__ __launch_bounds__(MA_BLOCK) void k_setup_fields(LaunchCtx c) {
   const int p = pair_of_block(c);
+  if (p < 0) return;
   const PairDesc& d = c.desc[p];
   const PairState& s = c.st[p];
   const int n = d.n;
@@ -303,6 +306,7 @@ constexpr int RES_KINDS[MA_NPART_RES] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 2, 
 template <int TX, int INTERP>
 __global__ __launch_bounds__(MA_BLOCK) void k_residual(LaunchCtx c) {
   const int p = pair_of_block(c);
+  if (p < 0) return;
   const PairDesc& d = c.desc[p];
   PairState& s = c.st[p];
   if (s.phase == PH_DONE) return;
@@ -372,6 +376,7 @@ __device__ __forceinline__ double lane_read(double x, int l) {
 template <int RPW, int INTERP>
 __global__ __launch_bounds__(MA_RES_STREAM_BLOCK) void k_residual_stream(LaunchCtx c) {
   const int p = pair_of_block(c);
+  if (p < 0) return;
   const PairDesc& d = c.desc[p];
   PairState& s = c.st[p];
   if (s.phase == PH_DONE) return;
@@ -464,6 +469,7 @@ __global__ __launch_bounds__(MA_RES_STREAM_BLOCK) void k_residual_stream(LaunchC
 // folds the residual partials of one pair and runs its Newton decisions
 __global__ __launch_bounds__(MA_BLOCK) void k_residual_finalize(LaunchCtx c, int nblk, int step_mode) {
   const int p = pair_of_block(c);
+  if (p < 0) return;
   const PairDesc& d = c.desc[p];
   PairState& s = c.st[p];
   if (s.phase == PH_DONE) return;
@@ -492,6 +498,7 @@ __global__ __launch_bounds__(MA_BLOCK) void k_residual_finalize(LaunchCtx c, int
 // r + translation constant, as FP32, for the single-step entry point
 __global__ __launch_bounds__(MA_BLOCK) void k_residual_shift(LaunchCtx c, float* out) {
   const int p = pair_of_block(c);
+  if (p < 0) return;
   const PairDesc& d = c.desc[p];
   const float cst = (float)c.st[p].mass_c;
   const long nn = (long)d.n * d.n;
@@ -502,6 +509,7 @@ __global__ __launch_bounds__(MA_BLOCK) void k_residual_shift(LaunchCtx c, float*
 // u += axpy * theta for pairs halving a rejected step or restoring the last iterate
 __global__ __launch_bounds__(MA_BLOCK) void k_step_update(LaunchCtx c) {
   const int p = pair_of_block(c);
+  if (p < 0) return;
   const PairDesc& d = c.desc[p];
   const PairState& s = c.st[p];
   if (s.phase != PH_BACKTRACK && s.phase != PH_REVERT) return;
@@ -514,6 +522,7 @@ __global__ __launch_bounds__(MA_BLOCK) void k_step_update(LaunchCtx c) {
 // psi = u - mean(u); map = x + D_h u (fourth-order differences), unwrapped
 __global__ __launch_bounds__(MA_BLOCK) void k_outputs(LaunchCtx c) {
   const int p = pair_of_block(c);
+  if (p < 0) return;
   const PairDesc& d = c.desc[p];
   const PairState& s = c.st[p];
   const int n = d.n;
@@ -562,10 +571,58 @@ __global__ __launch_bounds__(256) void k_summary(const PairState* st, const int*
   }
 }
 
+// Compaction of the launch lists (one block per size class): the class's pairs whose
+// phase is not done (for the residual and the step updates) and those solving (for the
+// GMRES launches), in the class's order, and their numbers.  cls[k] = (offset of the
+// class's slice in ids, count); lists and counts are written at the same offsets, the
+// counts at cnt[2k] (live) and cnt[2k + 1] (solving).
+__global__ __launch_bounds__(256) void k_compact(const PairState* st, const int* ids, const int2* cls, int* live,
+                                                 int* solving, int* cnt) {
+  const int2 cl = cls[blockIdx.x];
+  __shared__ int sl[256], ss[256];
+  __shared__ int base_l, base_s;
+  if (threadIdx.x == 0) base_l = base_s = 0;
+  __syncthreads();
+  for (int b = 0; b < cl.y; b += 256) {
+    const int q = b + threadIdx.x;
+    int id = 0, fl = 0, fs = 0;
+    if (q < cl.y) {
+      id = ids[cl.x + q];
+      const int ph = st[id].phase;
+      fl = ph != PH_DONE;
+      fs = ph == PH_SOLVE;
+    }
+    sl[threadIdx.x] = fl;
+    ss[threadIdx.x] = fs;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {  // inclusive scans
+      const int al = threadIdx.x >= o ? sl[threadIdx.x - o] : 0;
+      const int as = threadIdx.x >= o ? ss[threadIdx.x - o] : 0;
+      __syncthreads();
+      sl[threadIdx.x] += al;
+      ss[threadIdx.x] += as;
+      __syncthreads();
+    }
+    if (fl) live[cl.x + base_l + sl[threadIdx.x] - 1] = id;
+    if (fs) solving[cl.x + base_s + ss[threadIdx.x] - 1] = id;
+    __syncthreads();
+    if (threadIdx.x == 255) {
+      base_l += sl[255];
+      base_s += ss[255];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    cnt[2 * blockIdx.x] = base_l;
+    cnt[2 * blockIdx.x + 1] = base_s;
+  }
+}
+
 // Continuous batching.  k_retire: for the slots in the launch's id list (pairs that
 // finished), the outputs of k_outputs and the final state into final[pair].
 __global__ __launch_bounds__(MA_BLOCK) void k_retire(LaunchCtx c, PairState* final_state) {
   const int p = pair_of_block(c);
+  if (p < 0) return;
   const PairDesc& d = c.desc[p];
   const PairState& s = c.st[p];
   const int n = d.n;
@@ -629,6 +686,7 @@ __global__ __launch_bounds__(MA_BLOCK) void k_validate(const double* const* f, c
 // vectors (a 32-bit integer hash of the pair, vector and point index).
 __global__ __launch_bounds__(MA_BLOCK) void k_tune_fill(LaunchCtx c) {
   const int p = pair_of_block(c);
+  if (p < 0) return;
   const PairDesc& d = c.desc[p];
   const int n = d.n;
   const long nn = (long)n * n;
@@ -687,6 +745,7 @@ void launch_setup(const LaunchCtx& c, int n, int npairs, hipStream_t st) {
 // (64 columns per wave, MA_RES_STREAM_ROWS rows per wave) where n % 64 == 0, else the
 // same as 0
 int residual_tile_x(int n, int v) {
+  if (v >= 4) v = 0;
   const int t0 = (n % 64 == 0) ? 64 : ((n % 32 == 0) ? 32 : 16);
   const int t = v == 1 ? t0 / 2 : (v == 2 ? t0 / 4 : t0);
   return t < 16 ? 16 : t;
@@ -695,7 +754,8 @@ int residual_tile_x(int n, int v) {
 bool residual_streams(int n, int v) { return v == 3 && n % 64 == 0; }
 
 int residual_geometry(int n, int v, int* tile_x, int* threads) {
-  if (v < 0 || v > 3 || n % 16) return -1;
+  if (v < 0 || v >= MA_NVARIANTS || n % 16) return -1;
+  if (v >= 4) return residual_geometry(n, 0, tile_x, threads) < 0 ? -1 : 0;  // no wave-owned residual
   *tile_x = residual_tile_x(n, v);
   *threads = residual_streams(n, v) ? MA_RES_STREAM_BLOCK : MA_BLOCK;
   if (residual_streams(n, v)) return v;
@@ -758,6 +818,11 @@ void launch_outputs(const LaunchCtx& c, int n, int npairs, hipStream_t st) {
 void launch_summary(const PairState* s, const int* ids, int npairs, int* out, int seq, hipStream_t st,
                     int* phases) {
   hipLaunchKernelGGL(k_summary, dim3(1), dim3(256), 0, st, s, ids, npairs, out, seq, phases);
+}
+
+void launch_compact(const PairState* st_, const int* ids, const int2* cls, int ncls, int* live, int* solving, int* cnt,
+                    hipStream_t st) {
+  hipLaunchKernelGGL(k_compact, dim3(ncls), dim3(256), 0, st, st_, ids, cls, live, solving, cnt);
 }
 
 void launch_retire(const LaunchCtx& c, int n, int count, PairState* final_state, hipStream_t st) {

@@ -4,7 +4,32 @@
 
 #define MA_VARIANT_CASES(NV) X(NV, 0) X(NV, 1) X(NV, 2) X(NV, 3)
 
+namespace {
+// wave-owned row pass A: one row pair per wave, W waves per block
+constexpr bool waveA_fits(int n, int w) { return (long)w * (n + n / 8) * 8 + 512 <= 65536; }
+int waveA_w(int n, int v) {
+  if (n < 128 || v < 4 || v > 7) return 0;
+  const int w = v == 5 ? 2 : (v == 6 ? 8 : 4);
+  return ((n / 2) % w == 0 && waveA_fits(n, w)) ? w : 0;
+}
+template <int N, int W>
+void launch_waveA(const LaunchCtx& c, int npairs, int mode, int jn, const float2* tw, hipStream_t st,
+                  const TimedLaunch& ev) {
+  if constexpr (waveA_fits(N, W) && (N / 2) % W == 0)
+    MA_LAUNCH(ev, (k_passA_w<N, W>), dim3(N / 2 / W, npairs), dim3(64 * W), st, c, mode, jn, tw);
+}
+}  // namespace
+
+
 int passA_geometry(int n, int v, int* units, int* threads) {
+  if (v >= 4 && v < MA_NVARIANTS) {
+    if (!fft_size_supported(n)) return -1;
+    const int w = waveA_w(n, v);
+    if (w == 0) return passA_geometry(n, 0, units, threads) < 0 ? -1 : 0;
+    *units = w;
+    *threads = 64 * w;
+    return v == 7 ? 4 : v;
+  }
   switch (n * 4 + v) {
 #define X(NV, VV)                                           \
   case NV * 4 + VV:                                         \
@@ -28,7 +53,21 @@ int passA_blocks(int n, int v) {
 
 void launch_passA_only(const LaunchCtx& c, int n, int npairs, int mode, int jn, const float2* tw,
                  hipStream_t st, const TimedLaunch& ev) {
-  switch (n * 4 + c.var[0]) {
+  const int w = waveA_w(n, c.var[0]);
+  if (w > 0) {
+    switch (n * 16 + w) {
+#define X(NV)                                                            \
+  case NV * 16 + 2: launch_waveA<NV, 2>(c, npairs, mode, jn, tw, st, ev); break; \
+  case NV * 16 + 4: launch_waveA<NV, 4>(c, npairs, mode, jn, tw, st, ev); break; \
+  case NV * 16 + 8: launch_waveA<NV, 8>(c, npairs, mode, jn, tw, st, ev); break;
+      MA_FOR_EACH_N_WAVE(X)
+#undef X
+      default:
+        break;
+    }
+    return;
+  }
+  switch (n * 4 + (c.var[0] >= 4 ? 0 : c.var[0])) {
 #define X(NV, VV)                                                                                        \
   case NV * 4 + VV:                                                                                      \
     MA_LAUNCH(ev, (k_passA<NV, Canon<NV, VV>::A>), dim3(NV / 2 / Cfg<NV, VV>::A_PPB, npairs),            \

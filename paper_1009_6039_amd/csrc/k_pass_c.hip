@@ -1,10 +1,39 @@
 // Pass C of Strain's operator: instantiations for every grid size and launch-geometry
-// variant, the launcher and the geometry query used by the autotuner.
+// variant, the launcher and the geometry query used by the autotuner.  Variants 0..3
+// are the block-shared kernels (Cfg), 4 and 5 the wave-owned kernels with one and two
+// row pairs per block (n >= 128), 6 and 7 duplicates of 4.
 #include "strain.h"
 
 #define MA_VARIANT_CASES(NV) X(NV, 0) X(NV, 1) X(NV, 2) X(NV, 3)
 
+namespace {
+// LDS of the wave-owned kernel: five padded transforms per row pair
+constexpr bool wave_fits(int n, int ppb) { return 5L * ppb * (n + n / 8) * 8 <= 65536; }
+
+// row pairs per block of wave-owned variant v (4..7), 0 where it is not offered
+int wave_ppb(int n, int v) {
+  if (n < 128 || v < 4 || v > 7) return 0;
+  const int ppb = v == 5 ? 2 : 1;
+  return wave_fits(n, ppb) ? ppb : 0;
+}
+
+template <int N, int PPB>
+void launch_wave(const LaunchCtx& c, int npairs, int mode, int j, const float2* tw, hipStream_t st,
+                 const TimedLaunch& ev) {
+  if constexpr (wave_fits(N, PPB))
+    MA_LAUNCH(ev, (k_passC_w<N, PPB>), dim3(N / 2 / PPB, npairs), dim3(320 * PPB), st, c, mode, j, tw);
+}
+}  // namespace
+
 int passC_geometry(int n, int v, int* units, int* threads) {
+  if (v >= 4 && v < MA_NVARIANTS) {
+    if (!fft_size_supported(n)) return -1;
+    const int ppb = wave_ppb(n, v);
+    if (ppb == 0) return passC_geometry(n, 0, units, threads) < 0 ? -1 : 0;
+    *units = ppb;
+    *threads = 320 * ppb;
+    return (v == 6 || v == 7) ? 4 : v;
+  }
   switch (n * 4 + v) {
 #define X(NV, VV)                                           \
   case NV * 4 + VV:                                         \
@@ -28,7 +57,25 @@ int passC_blocks(int n, int v) {
 
 void launch_passC_only(const LaunchCtx& c, int n, int npairs, int mode, int j, const float2* tw,
                  hipStream_t st, const TimedLaunch& ev) {
-  switch (n * 4 + c.var[2]) {
+  const int ppb = wave_ppb(n, c.var[2]);
+  if (ppb > 0) {
+    switch (n * 2 + ppb) {
+#define X(NV)                                                   \
+  case NV * 2 + 1:                                              \
+    launch_wave<NV, 1>(c, npairs, mode, j, tw, st, ev);         \
+    break;                                                      \
+  case NV * 2 + 2:                                              \
+    launch_wave<NV, 2>(c, npairs, mode, j, tw, st, ev);         \
+    break;
+      MA_FOR_EACH_N_WAVE(X)
+#undef X
+      default:
+        break;
+    }
+    return;
+  }
+  const int v = c.var[2] >= 4 ? 0 : c.var[2];
+  switch (n * 4 + v) {
 #define X(NV, VV)                                                                                        \
   case NV * 4 + VV:                                                                                      \
     MA_LAUNCH(ev, (k_passC<NV, Canon<NV, VV>::C>), dim3(NV / 2 / Cfg<NV, VV>::C_PPB, npairs),            \

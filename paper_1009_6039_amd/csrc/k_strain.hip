@@ -64,6 +64,7 @@ __device__ void arnoldi_close(PairState& s, const LaunchCtx& c, int jn, double w
 // Lane l of group g sums blocks g, g + 8, ...; the loads are independent.
 __global__ __launch_bounds__(256) void k_dots_finalize(LaunchCtx c, int j, int nblk) {
   const int p = pair_of_block(c);
+  if (p < 0) return;
   const PairDesc& d = c.desc[p];
   PairState& s = c.st[p];
   if (!(s.phase == PH_SOLVE && s.gm_running)) return;
@@ -94,6 +95,7 @@ __global__ __launch_bounds__(256) void k_dots_finalize(LaunchCtx c, int j, int n
 // ||w'|| from the pass-A partials, then the rotations and the convergence test
 __global__ __launch_bounds__(256) void k_arnoldi_finalize(LaunchCtx c, int jn, int nblk) {
   const int p = pair_of_block(c);
+  if (p < 0) return;
   const PairDesc& d = c.desc[p];
   PairState& s = c.st[p];
   if (!(s.phase == PH_SOLVE && s.gm_running)) return;
@@ -108,6 +110,7 @@ __global__ __launch_bounds__(256) void k_arnoldi_finalize(LaunchCtx c, int jn, i
 // the GMRES start values that the residual's fold set for the unscaled system
 __global__ __launch_bounds__(256) void k_rhs_finalize(LaunchCtx c, int nblk) {
   const int p = pair_of_block(c);
+  if (p < 0) return;
   const PairDesc& d = c.desc[p];
   PairState& s = c.st[p];
   if (!(s.phase == PH_SOLVE && s.gm_running && s.gm_cycle == 0)) return;
@@ -128,6 +131,7 @@ __global__ __launch_bounds__(256) void k_rhs_finalize(LaunchCtx c, int nblk) {
 // a restarted cycle begins: its first vector has been transformed by pass A
 __global__ void k_cycle_begin(LaunchCtx c) {
   const int p = pair_of_block(c);
+  if (p < 0) return;
   PairState& s = c.st[p];
   if (threadIdx.x == 0 && s.phase == PH_SOLVE && s.gm_restart) {
     s.gm_running = 1;
@@ -139,6 +143,7 @@ __global__ void k_cycle_begin(LaunchCtx c) {
 // x += sum y_l v_l and V[0] = the cycle's residual, for a GMRES restart
 __global__ __launch_bounds__(MA_BLOCK) void k_restart(LaunchCtx c) {
   const int p = pair_of_block(c);
+  if (p < 0) return;
   const PairDesc& d = c.desc[p];
   const PairState& s = c.st[p];
   if (!(s.phase == PH_SOLVE && s.gm_restart)) return;
@@ -171,6 +176,7 @@ __global__ __launch_bounds__(MA_BLOCK) void k_restart(LaunchCtx c) {
 // elementwise step, with per-block partial sums (FP64) of the value it writes (or reads)
 __global__ __launch_bounds__(MA_BLOCK) void k_power_vec(LaunchCtx c, int mode, const float* b0) {
   const int p = pair_of_block(c);
+  if (p < 0) return;
   const PairDesc& d = c.desc[p];
   const PairState& s = c.st[p];
   const long nn = (long)d.n * d.n;
@@ -204,6 +210,7 @@ __global__ __launch_bounds__(MA_BLOCK) void k_power_vec(LaunchCtx c, int mode, c
 // one block per pair: folds the partial sums of the preceding k_power_vec launch
 __global__ __launch_bounds__(256) void k_power_fold(LaunchCtx c, int mode, int nblk, int k, double* out) {
   const int p = pair_of_block(c);
+  if (p < 0) return;
   const PairDesc& d = c.desc[p];
   PairState& s = c.st[p];
   __shared__ double scratch[4];

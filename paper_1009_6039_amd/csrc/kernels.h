@@ -43,6 +43,9 @@ void launch_step_update(const LaunchCtx& c, int n, int npairs, hipStream_t st);
 void launch_outputs(const LaunchCtx& c, int n, int npairs, hipStream_t st);
 void launch_summary(const PairState* s, const int* ids, int npairs, int* out, int seq, hipStream_t st,
                     int* phases = nullptr);
+// compacted launch lists per size class (live: not done; solving: in a Newton direction)
+void launch_compact(const PairState* state, const int* ids, const int2* cls, int ncls, int* live, int* solving,
+                    int* cnt, hipStream_t st);
 // continuous batching: outputs and final states of finished slots (ids in the context),
 // refill records scattered into their slots, validation of every pair's inputs
 void launch_retire(const LaunchCtx& c, int n, int count, PairState* final_state, hipStream_t st);
@@ -55,7 +58,7 @@ void launch_tune_fill(const LaunchCtx& c, int n, int npairs, hipStream_t st);
 bool fft_size_supported(int n);
 // launch-geometry variants 0..MA_NVARIANTS-1 of each pass (0 = default); the geometry
 // functions return the variant's canonical index (a duplicate returns 0) or -1
-constexpr int MA_NVARIANTS = 4;
+constexpr int MA_NVARIANTS = 8;
 int passA_geometry(int n, int v, int* row_pairs, int* threads);
 int passB_geometry(int n, int v, int* columns, int* threads);
 int passC_geometry(int n, int v, int* row_pairs, int* threads);

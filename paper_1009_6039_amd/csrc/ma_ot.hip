@@ -31,8 +31,9 @@ struct Tune {
 
 struct Class {
   int n;
-  int count = 0;         // pairs of this size
-  int* d_ids = nullptr;  // slice of the plan's id buffer
+  int count = 0;         // pairs of this size (of a compacted list: an upper bound)
+  int* d_ids = nullptr;  // slice of the plan's id buffer (or of a compacted list)
+  const int* active_n = nullptr;  // device length of a compacted list, else null
   const float2* tw = nullptr;
   const float2* mt = nullptr;
 };
@@ -55,6 +56,9 @@ struct ma_plan {
   PairDesc* d_desc = nullptr;
   PairState* d_state = nullptr;
   int* d_ids = nullptr;
+  // compacted lists: live ids, solving ids (pairs_cap each), then per class (offset,
+  // count) and the two counts
+  int* d_lists = nullptr;
   int pairs_cap = 0;
   // host-loop counters: 4 slots of MA_SUMMARY_INTS (the synchronous read, then a ring
   // of 3) in coherent pinned host memory that the summary kernel writes directly,
@@ -68,6 +72,7 @@ struct ma_plan {
   std::map<int, Tune> tune;                   // n -> launch-geometry variants (absent: defaults)
   std::vector<PairDesc> h_desc;
   std::vector<PairState> h_state;
+  std::vector<int2> h_ctab;  // class table staged for upload (lives as long as the plan)
   // timing hook
   int prof_kind = MA_PROF_NONE;
   unsigned long long* d_prof = nullptr;
@@ -235,13 +240,16 @@ int ensure_workspace(ma_plan* P, const std::vector<int>& ns) {
     if (P->d_desc) hipFree(P->d_desc);
     if (P->d_state) hipFree(P->d_state);
     if (P->d_ids) hipFree(P->d_ids);
+    if (P->d_lists) (void)hipFree(P->d_lists);
     P->d_desc = nullptr;
     P->d_state = nullptr;
     P->d_ids = nullptr;
+    P->d_lists = nullptr;
     P->pairs_cap = 0;
     if (hipMalloc(&P->d_desc, sizeof(PairDesc) * np) != hipSuccess) return MA_ENOMEM;
     if (hipMalloc(&P->d_state, sizeof(PairState) * np) != hipSuccess) return MA_ENOMEM;
     if (hipMalloc(&P->d_ids, sizeof(int) * np) != hipSuccess) return MA_ENOMEM;
+    if (hipMalloc(&P->d_lists, sizeof(int) * 6 * (size_t)np) != hipSuccess) return MA_ENOMEM;
     P->pairs_cap = np;
   }
   P->h_desc.assign(np, PairDesc{});
@@ -262,6 +270,7 @@ LaunchCtx make_ctx(const ma_plan* P, const Class& cl, int kind = MA_PROF_NONE, b
   c.desc = P->d_desc;
   c.st = P->d_state;
   c.pair_ids = cl.d_ids;
+  c.active_n = cl.active_n;
   c.mt = cl.mt;
   c.m = P->opt.gmres_m;
   c.max_newton = P->opt.max_newton;
@@ -412,6 +421,37 @@ int read_summary(ma_plan* P, int npairs, hipStream_t st, int* phases = nullptr) 
   return P->h_summary[MA_SUMMARY_TAG] == seq ? MA_OK : MA_EHIP;
 }
 
+// The class table of the compaction kernel: (offset of each class's id slice, count).
+int upload_class_table(ma_plan* P, ClassList cls, int npairs, hipStream_t st) {
+  std::vector<int2>& t = P->h_ctab;
+  if (t.size() < (size_t)cls.n) t.resize(cls.n);  // never in the no-allocation mode (one class)
+  for (int k = 0; k < cls.n; ++k) t[k] = make_int2((int)(cls.p[k].d_ids - P->d_ids), cls.p[k].count);
+  HIP_TRY(hipMemcpyAsync(P->d_lists + 2 * (size_t)P->pairs_cap, t.data(), sizeof(int2) * cls.n,
+                         hipMemcpyHostToDevice, st));
+  return MA_OK;
+}
+
+// After a summary: the live and solving lists of every class, and the views of the
+// classes that the next launches use (grids bounded by the totals the summary gave)
+void compact_views(ma_plan* P, ClassList cls, int n_live, int n_solve, std::vector<Class>& live,
+                   std::vector<Class>& solving, hipStream_t st) {
+  const size_t cap = P->pairs_cap;
+  int* lists = P->d_lists;
+  int* cnt = P->d_lists + 2 * cap + 2 * cap;  // after the (offset, count) table
+  launch_compact(P->d_state, P->d_ids, (const int2*)(P->d_lists + 2 * cap), cls.n, lists, lists + cap, cnt, st);
+  live.assign(cls.begin(), cls.end());
+  solving.assign(cls.begin(), cls.end());
+  for (int k = 0; k < cls.n; ++k) {
+    const size_t off = (size_t)(cls.p[k].d_ids - P->d_ids);
+    live[k].d_ids = lists + off;
+    live[k].active_n = cnt + 2 * k;
+    live[k].count = std::min(cls.p[k].count, n_live);
+    solving[k].d_ids = lists + cap + off;
+    solving[k].active_n = cnt + 2 * k + 1;
+    solving[k].count = std::min(cls.p[k].count, n_solve);
+  }
+}
+
 // The iterations of one GMRES cycle.  From the third on, a summary of the state is
 // queued after each iteration, and the host reads the one queued two iterations
 // earlier (so the device queue never drains while the host waits): once no pair is
@@ -453,38 +493,46 @@ int run_solver(ma_plan* P, int npairs, double damping, double tol, hipStream_t s
   int e = read_summary(P, npairs, st);
   if (e) return e;
   if (P->h_summary[7] > 0) return MA_EINVAL;
+  e = upload_class_table(P, cls, npairs, st);
+  if (e) return e;
 
+  // launches of each tick over the pairs that take part: the residual and the step
+  // updates over the live pairs, the GMRES kernels over the solving ones (compacted
+  // lists after every residual's summary; the first residual takes every pair)
+  std::vector<Class> vlive(cls.begin(), cls.end()), vsolve;
   const long max_ticks = (long)(P->opt.max_newton + 1) * (P->opt.max_backtrack + 3) + 8;
   for (long tick = 0; tick < max_ticks; ++tick) {
-    for (const Class& c : cls) L_res(P, c, 0, st);
+    for (const Class& c : vlive) L_res(P, c, 0, st);
     e = read_summary(P, npairs, st);
     if (e) return e;
     const int n_solve = P->h_summary[PH_SOLVE];
     const int n_update = P->h_summary[PH_BACKTRACK] + P->h_summary[PH_REVERT];
     if (n_solve == 0 && n_update == 0) break;  // every pair is done
+    compact_views(P, cls, npairs - P->h_summary[PH_DONE], n_solve, vlive, vsolve, st);
+    const ClassList sl{vsolve.data(), (int)vsolve.size()};
     if (n_solve > 0) {
-      for (const Class& c : cls) L_A(P, c, PA_INIT, 0, st);
-      e = launch_cycle_body(P, cls, npairs, st);
+      for (const Class& c : vsolve) L_A(P, c, PA_INIT, 0, st);
+      e = launch_cycle_body(P, sl, npairs, st);
       if (e) return e;
       for (int cyc = 0; cyc < P->opt.gmres_max_restarts; ++cyc) {
         e = read_summary(P, npairs, st);
         if (e) return e;
         if (P->h_summary[6] == 0) break;
-        for (const Class& c : cls) {
+        for (const Class& c : vsolve) {
           launch_restart(make_ctx(P, c), c.n, c.count, st);
           L_A(P, c, PA_PLAIN, 0, st);
         }
-        e = launch_cycle_body(P, cls, npairs, st);
-      if (e) return e;
+        e = launch_cycle_body(P, sl, npairs, st);
+        if (e) return e;
       }
-      for (const Class& c : cls) {
+      for (const Class& c : vsolve) {
         L_A(P, c, PA_RECOVER, 0, st);
         L_B(P, c, PB_RECOVER, 0, st);
         L_C(P, c, PC_RECOVER, 0, st);
       }
     }
     if (n_update > 0)
-      for (const Class& c : cls) launch_step_update(make_ctx(P, c), c.n, c.count, st);
+      for (const Class& c : vlive) launch_step_update(make_ctx(P, c), c.n, c.count, st);
   }
   for (const Class& c : cls) launch_outputs(make_ctx(P, c), c.n, c.count, st);
   HIP_TRY(hipMemcpyAsync(P->h_state.data(), P->d_state, sizeof(PairState) * npairs, hipMemcpyDeviceToHost, st));
@@ -627,13 +675,16 @@ int run_continuous(ma_plan* P, int npairs, const std::vector<int>& ns, const dou
   HIP_TRY(hipMemcpyAsync(P->d_desc, hd.data(), sizeof(PairDesc) * S, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(P->d_state, P->h_state.data(), sizeof(PairState) * S, hipMemcpyHostToDevice, st));
   for (const Class& c : cls) launch_setup(make_ctx(P, c), c.n, c.count, st);
+  e = upload_class_table(P, ClassList{cls.data(), (int)cls.size()}, S, st);
+  if (e) return e;
+  std::vector<Class> vlive(cls.begin(), cls.end()), vsolve;
   // 3. ticks; a refilled slot enters the next tick's residual
   const long per_pair = (long)(P->opt.max_newton + 1) * (P->opt.max_backtrack + 3) + 8;
   const long max_ticks = per_pair * (long)((npairs + S - 1) / S + 1);
   int retired = 0;
   const ClassList cl{cls.data(), (int)cls.size()};
   for (long tick = 0; tick < max_ticks && retired < npairs; ++tick) {
-    for (const Class& c : cls) L_res(P, c, 0, st);
+    for (const Class& c : vlive) L_res(P, c, 0, st);
     e = read_summary(P, S, st, P->d_phase);
     if (e) return e;
     const int n_solve = P->h_summary[PH_SOLVE];
@@ -687,29 +738,34 @@ int run_continuous(ma_plan* P, int npairs, const std::vector<int>& ns, const dou
           }
       }
     }
+    // after the refills: the live slots (a pair in them) and the solving ones
+    int n_live = 0;
+    for (int s = 0; s < S; ++s) n_live += slot_pair[s] >= 0;
+    compact_views(P, cl, n_live, n_solve, vlive, vsolve, st);
+    const ClassList sl{vsolve.data(), (int)vsolve.size()};
     if (n_solve > 0) {
-      for (const Class& c : cls) L_A(P, c, PA_INIT, 0, st);
-      e = launch_cycle_body(P, cl, S, st);
+      for (const Class& c : vsolve) L_A(P, c, PA_INIT, 0, st);
+      e = launch_cycle_body(P, sl, S, st);
       if (e) return e;
       for (int cyc = 0; cyc < P->opt.gmres_max_restarts; ++cyc) {
         e = read_summary(P, S, st);
         if (e) return e;
         if (P->h_summary[6] == 0) break;
-        for (const Class& c : cls) {
+        for (const Class& c : vsolve) {
           launch_restart(make_ctx(P, c), c.n, c.count, st);
           L_A(P, c, PA_PLAIN, 0, st);
         }
-        e = launch_cycle_body(P, cl, S, st);
+        e = launch_cycle_body(P, sl, S, st);
         if (e) return e;
       }
-      for (const Class& c : cls) {
+      for (const Class& c : vsolve) {
         L_A(P, c, PA_RECOVER, 0, st);
         L_B(P, c, PB_RECOVER, 0, st);
         L_C(P, c, PC_RECOVER, 0, st);
       }
     }
     if (n_update > 0)
-      for (const Class& c : cls) launch_step_update(make_ctx(P, c), c.n, c.count, st);
+      for (const Class& c : vlive) launch_step_update(make_ctx(P, c), c.n, c.count, st);
   }
   if (retired < npairs) {  // the tick limit: write what the unfinished slots hold
     HIP_TRY(hipStreamSynchronize(st));  // the staging buffer's last copy has been read
@@ -849,6 +905,7 @@ int noalloc_setup(int dev) {
   P->d_state = (PairState*)take(sizeof(PairState));
   P->d_ids = (int*)take(sizeof(int));
   P->d_summary = (int*)take(sizeof(int) * MA_SUMMARY_INTS);
+  P->d_lists = (int*)take(sizeof(int) * 6);  // the compaction lists of one pair
   S.d_tw = (float2*)take(sizeof(float2) * MA_NOALLOC_NMAX);
   S.d_mt = (float2*)take(sizeof(float2) * MA_NOALLOC_NMAX);
   P->arena = ptr + off;
@@ -858,6 +915,7 @@ int noalloc_setup(int dev) {
   P->no_alloc = true;
   P->h_desc.assign(1, PairDesc{});  // host vectors of one entry, sized once here
   P->h_state.assign(1, PairState{});
+  P->h_ctab.assign(1, int2{});
   S.base = ptr;
   return MA_OK;
 }
@@ -937,6 +995,7 @@ void ma_plan_destroy(ma_plan* P) {
   if (P->d_desc) hipFree(P->d_desc);
   if (P->d_state) hipFree(P->d_state);
   if (P->d_ids) hipFree(P->d_ids);
+  if (P->d_lists) (void)hipFree(P->d_lists);
   if (P->h_summary) hipHostFree(P->h_summary);
   if (P->d_final) (void)hipFree(P->d_final);
   if (P->h_phase) (void)hipHostFree(P->h_phase);

@@ -108,6 +108,7 @@ __global__ __launch_bounds__((Cfg<N, G>::A_BLOCK)) void k_passA(LaunchCtx c, int
   constexpr int PPB = Cfg<N, G>::A_PPB, BLOCK = Cfg<N, G>::A_BLOCK, NH = N / 2;
   constexpr long NN = (long)N * N;
   const int p = pair_of_block(c);
+  if (p < 0) return;
   const PairDesc& d = c.desc[p];
   PairState& s = c.st[p];
   bool run;
@@ -279,6 +280,7 @@ __global__ __launch_bounds__((Cfg<N, G>::B_BLOCK)) void k_passB(LaunchCtx c, int
                                                            const float2* __restrict__ tw) {
   constexpr int CPB = Cfg<N, G>::B_CPB, BLOCK = Cfg<N, G>::B_BLOCK, NH = N / 2;
   const int p = pair_of_block(c);
+  if (p < 0) return;
   const PairDesc& d = c.desc[p];
   const PairState& s = c.st[p];
   bool run;
@@ -394,6 +396,102 @@ __global__ __launch_bounds__((Cfg<N, G>::B_BLOCK)) void k_passB(LaunchCtx c, int
   }
 }
 
+// Pass C's epilogue: w = a11 alpha11 + 2 a12 alpha12 + a22 alpha22 + b1 beta1 + b2 beta2 at
+// the block's points (left-scaled if the option is on), stored as V[j+1], and the
+// block's partial inner products <w, v_l>, l <= j, for k_dots_finalize.  zat(pp, t, jj)
+// is element jj of derived transform t of the block's row pair pp: t = 0 alpha11 + i
+// beta1 of row a, 1 alpha12 + i beta2 of row a, 2 and 3 the same for row b, 4 alpha22 of
+// row a (.x) and row b (.y).  The caller synchronises the block before the call.
+template <int N, int PPB, int BLOCK, class ZAT>
+__device__ __forceinline__ void passC_combine(const LaunchCtx& c, const PairDesc& d, const PairState& s, int j,
+                                              int row0, double* red, ZAT zat) {
+  constexpr long NN = (long)N * N;
+  const auto V = gmem<float>(d.V);
+  const auto W = V + (long)(j + 1) * NN;
+  const auto coef = gmem<const float>(d.coef);
+  const bool scaled = c.precond == MA_PRECOND_DIAG;
+  const float trbar = (float)(s.abar[0] + s.abar[2]);
+  // w at the thread's points, then the inner products <w, v_l>
+  constexpr int PER = (PPB * N + BLOCK - 1) / BLOCK;
+  constexpr bool FULL = (PPB * N) % BLOCK == 0;
+  float wa[PER], wb[PER];
+  int ea_[PER];  // offset of the first row's point; a point past the end reads the
+                 // block's first point (in bounds) with weight zero
+  // the coefficients at all of the thread's points are loaded before the first is used
+  float ca[PER][5], cb[PER][5];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = threadIdx.x + q * BLOCK;
+    ea_[q] = row0 * N;
+    if (!FULL && e >= PPB * N) continue;
+    const int pp = e / N, jj = e % N;
+    ea_[q] = (row0 + 2 * pp) * N + jj;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      ca[q][k] = coef[k * NN + ea_[q]];
+      cb[q][k] = coef[k * NN + ea_[q] + N];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = threadIdx.x + q * BLOCK;
+    wa[q] = wb[q] = 0.f;
+    if (!FULL && e >= PPB * N) continue;
+    const int pp = e / N, jj = e % N;
+    const int ea = ea_[q], eb = ea + N;
+    const float2 z0 = zat(pp, 0, jj), z1 = zat(pp, 1, jj), z2 = zat(pp, 2, jj), z3 = zat(pp, 3, jj),
+                 z4 = zat(pp, 4, jj);
+    float a = ca[q][0] * z0.x + 2.f * ca[q][1] * z1.x + ca[q][2] * z4.x + ca[q][3] * z0.y + ca[q][4] * z1.y;
+    float b = cb[q][0] * z2.x + 2.f * cb[q][1] * z3.x + cb[q][2] * z4.y + cb[q][3] * z2.y + cb[q][4] * z3.y;
+    if (scaled) {  // left scaling by 1 / D(x), D = (a11 + a22) / (abar11 + abar22)
+      a *= trbar / (ca[q][0] + ca[q][2]);
+      b *= trbar / (cb[q][0] + cb[q][2]);
+    }
+    W[ea] = a;
+    W[eb] = b;
+    wa[q] = a;
+    wb[q] = b;
+  }
+  // block reduction of the j+1 inner products (fixed order); folded by k_dots_finalize.
+  // The loads of v_{l+1} are issued before the reduction of <w, v_l>.
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  float va[PER], vb[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    va[q] = V[ea_[q]];
+    vb[q] = V[ea_[q] + N];
+  }
+  for (int l = 0; l <= j; ++l) {
+    float na[PER], nb[PER];
+    if (l < j) {
+      const auto Vn = V + (long)(l + 1) * NN;
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        na[q] = Vn[ea_[q]];
+        nb[q] = Vn[ea_[q] + N];
+      }
+    }
+    float acc = 0.f;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) acc += wa[q] * va[q] + wb[q] * vb[q];
+    const double v = wave_sum((double)acc);
+    if (lane == 0) red[wid * (MA_MMAX + 1) + l] = v;
+    if (l < j) {
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        va[q] = na[q];
+        vb[q] = nb[q];
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x <= j) {
+    double t = 0.0;
+    for (int w = 0; w < BLOCK / 64; ++w) t += red[w * (MA_MMAX + 1) + threadIdx.x];
+    d.part[(long)blockIdx.x * (MA_MMAX + 1) + threadIdx.x] = t;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // pass C (rows)
 // ---------------------------------------------------------------------------
@@ -403,6 +501,7 @@ __global__ __launch_bounds__((Cfg<N, G>::C_BLOCK)) void k_passC(LaunchCtx c, int
   constexpr int PPB = Cfg<N, G>::C_PPB, BLOCK = Cfg<N, G>::C_BLOCK, NH = N / 2;
   constexpr long NN = (long)N * N;
   const int p = pair_of_block(c);
+  if (p < 0) return;
   const PairDesc& d = c.desc[p];
   PairState& s = c.st[p];
   const bool run = mode == PC_MATVEC ? (s.phase == PH_SOLVE && s.gm_running) : (s.phase == PH_SOLVE);
@@ -502,90 +601,385 @@ __global__ __launch_bounds__((Cfg<N, G>::C_BLOCK)) void k_passC(LaunchCtx c, int
   }
   __syncthreads();
   fft_lds<N, 5 * PPB, BLOCK, true, LAYOUT_ROWS>(lds, tw);
+  passC_combine<N, PPB, BLOCK>(c, d, s, j, row0, red,
+                               [&](int pp, int t, int jj) { return lds[(5 * pp + t) * N + jj]; });
+}
 
-  const auto V = gmem<float>(d.V);
-  const auto W = V + (long)(j + 1) * NN;
-  const auto coef = gmem<const float>(d.coef);
-  const bool scaled = c.precond == MA_PRECOND_DIAG;
-  const float trbar = (float)(s.abar[0] + s.abar[2]);
-  // w at the thread's points, then the inner products <w, v_l>
-  constexpr int PER = (PPB * N + BLOCK - 1) / BLOCK;
-  constexpr bool FULL = (PPB * N) % BLOCK == 0;
-  float wa[PER], wb[PER];
-  int ea_[PER];  // offset of the first row's point; a point past the end reads the
-                 // block's first point (in bounds) with weight zero
-  // the coefficients at all of the thread's points are loaded before the first is used
-  float ca[PER][5], cb[PER][5];
-#pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int e = threadIdx.x + q * BLOCK;
-    ea_[q] = row0 * N;
-    if (!FULL && e >= PPB * N) continue;
-    const int pp = e / N, jj = e % N;
-    ea_[q] = (row0 + 2 * pp) * N + jj;
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      ca[q][k] = coef[k * NN + ea_[q]];
-      cb[q][k] = coef[k * NN + ea_[q] + N];
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int e = threadIdx.x + q * BLOCK;
-    wa[q] = wb[q] = 0.f;
-    if (!FULL && e >= PPB * N) continue;
-    const int pp = e / N, jj = e % N;
-    const int ea = ea_[q], eb = ea + N;
-    const float2* L = lds + 5 * pp * N + jj;
-    const float2 z0 = L[0], z1 = L[N], z2 = L[2 * N], z3 = L[3 * N], z4 = L[4 * N];
-    float a = ca[q][0] * z0.x + 2.f * ca[q][1] * z1.x + ca[q][2] * z4.x + ca[q][3] * z0.y + ca[q][4] * z1.y;
-    float b = cb[q][0] * z2.x + 2.f * cb[q][1] * z3.x + cb[q][2] * z4.y + cb[q][3] * z2.y + cb[q][4] * z3.y;
-    if (scaled) {  // left scaling by 1 / D(x), D = (a11 + a22) / (abar11 + abar22)
-      a *= trbar / (ca[q][0] + ca[q][2]);
-      b *= trbar / (cb[q][0] + cb[q][2]);
-    }
-    W[ea] = a;
-    W[eb] = b;
-    wa[q] = a;
-    wb[q] = b;
-  }
-  // block reduction of the j+1 inner products (fixed order); folded by k_dots_finalize.
-  // The loads of v_{l+1} are issued before the reduction of <w, v_l>.
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  float va[PER], vb[PER];
-#pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    va[q] = V[ea_[q]];
-    vb[q] = V[ea_[q] + N];
-  }
-  for (int l = 0; l <= j; ++l) {
-    float na[PER], nb[PER];
-    if (l < j) {
-      const auto Vn = V + (long)(l + 1) * NN;
-#pragma unroll
-      for (int q = 0; q < PER; ++q) {
-        na[q] = Vn[ea_[q]];
-        nb[q] = Vn[ea_[q] + N];
+// Pass C with wave-owned transforms: 5 PPB waves per block, wave (pp, t) builds derived
+// transform t of row pair pp straight from the column pass's spectra and inverts it in
+// its private LDS region; one block barrier before the pointwise combination.  The
+// recovery modes use wave (pp, 0) only.
+template <int N, int PPB>
+__global__ __launch_bounds__(320 * PPB) void k_passC_w(LaunchCtx c, int mode, int j, const float2* tw) {
+  constexpr int NH = N / 2, WB = WaveBuf<N>::size, BLOCK = 320 * PPB;
+  constexpr long NN = (long)N * N;
+  const int p = pair_of_block(c);
+  if (p < 0) return;
+  const PairDesc& d = c.desc[p];
+  PairState& s = c.st[p];
+  const bool run = mode == PC_MATVEC ? (s.phase == PH_SOLVE && s.gm_running) : (s.phase == PH_SOLVE);
+  if (!run) return;
+  count_bytes(c, mode == PC_MATVEC ? 36.0 + 4.0 * (j + 1) : (mode == PC_RECOVER ? 28.0 : 8.0), N);
+  __shared__ float2 lds[5 * PPB * WB];
+  __shared__ double red[(BLOCK / 64) * (MA_MMAX + 1)];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int pp = wv / 5, t = wv % 5;
+  const int row0 = 2 * blockIdx.x * PPB;
+  float2* L = lds + wv * WB;
+  const auto T0 = gmem<const float2>(d.T);
+  const auto T1 = T0 + NN / 2;
+  const auto T2 = T0 + NN;
+  const long ra = (long)(row0 + 2 * pp) * NH;  // half-spectrum row a of this row pair; row b follows
+
+  if (mode != PC_MATVEC) {
+    if (t != 0) return;
+    // theta = Lbar^{-1} sigma: rows a and b as the real and imaginary parts of one transform
+    for (int k = lane; k < NH; k += 64) {
+      const float2 a = T0[ra + k], b = T0[ra + NH + k];
+      if (k == 0) {
+        L[wpad(0)] = make_float2(a.x, b.x);
+        L[wpad(NH)] = make_float2(a.y, b.y);
+      } else {
+        L[wpad(k)] = make_float2(a.x - b.y, a.y + b.x);
+        L[wpad(N - k)] = make_float2(a.x + b.y, b.x - a.y);
       }
     }
-    float acc = 0.f;
-#pragma unroll
-    for (int q = 0; q < PER; ++q) acc += wa[q] * va[q] + wb[q] * vb[q];
-    const double v = wave_sum((double)acc);
-    if (lane == 0) red[wid * (MA_MMAX + 1) + l] = v;
-    if (l < j) {
-#pragma unroll
-      for (int q = 0; q < PER; ++q) {
-        va[q] = na[q];
-        vb[q] = nb[q];
+    wave_sync();
+    wfft<N, true>(L, tw, lane);
+    for (int jj = lane; jj < N; jj += 64) {
+      const long ea = (long)(row0 + 2 * pp) * N + jj, eb = ea + N;
+      const float2 z = L[wpad(jj)];
+      if (mode == PC_RECOVER) {  // FP64 correction kept for step halving; u in FP64
+        d.theta[ea] = (double)z.x;
+        d.theta[eb] = (double)z.y;
+        d.u[ea] += (double)z.x;
+        d.u[eb] += (double)z.y;
+      } else {
+        d.x[ea] = z.x;
+        d.x[eb] = z.y;
       }
     }
+    return;
+  }
+
+  // derived transform t of this row pair: every spectrum load of the lane first
+  constexpr int IT = (NH + 63) / 64;
+  float2 A[IT], B[IT];
+#pragma unroll
+  for (int q = 0; q < IT; ++q) {
+    const int k = lane + 64 * q;
+    if (NH % 64 != 0 && k >= NH) continue;
+    const long ia = ra + k, ib = ia + NH;
+    if (t == 0) { A[q] = T2[ia]; B[q] = T1[ia]; }
+    else if (t == 1) { A[q] = T1[ia]; B[q] = T0[ia]; }
+    else if (t == 2) { A[q] = T2[ib]; B[q] = T1[ib]; }
+    else if (t == 3) { A[q] = T1[ib]; B[q] = T0[ib]; }
+    else { A[q] = T0[ia]; B[q] = T0[ib]; }
+  }
+#pragma unroll
+  for (int q = 0; q < IT; ++q) {
+    const int k = lane + 64 * q;
+    if (NH % 64 != 0 && k >= NH) continue;
+    if (k == 0) {
+      // DC (.x) and Nyquist (.y) are real; the first-derivative multiplier vanishes at
+      // both, the second-derivative one at DC
+      if (t == 0 || t == 2) {
+        L[wpad(0)] = make_float2(A[q].x, B[q].x);
+        L[wpad(NH)] = make_float2(A[q].y, B[q].y);
+      } else if (t == 4) {
+        const float d2n = c.mt[NH].y;
+        L[wpad(0)] = make_float2(0.f, 0.f);
+        L[wpad(NH)] = make_float2(d2n * A[q].y, d2n * B[q].y);
+      } else {
+        L[wpad(0)] = make_float2(0.f, 0.f);
+        L[wpad(NH)] = make_float2(0.f, 0.f);
+      }
+    } else {
+      const float2 m = c.mt[k];
+      float2 a = A[q], b = B[q];
+      if (t == 1 || t == 3) {
+        a = times_i(m.x, a);
+        b = times_i(m.x, b);
+      } else if (t == 4) {
+        a = cscale(a, m.y);
+        b = cscale(b, m.y);
+      }
+      L[wpad(k)] = make_float2(a.x - b.y, a.y + b.x);
+      L[wpad(N - k)] = make_float2(a.x + b.y, b.x - a.y);
+    }
+  }
+  wave_sync();
+  wfft<N, true>(L, tw, lane);
+  __syncthreads();
+  passC_combine<N, PPB, BLOCK>(c, d, s, j, row0, red,
+                               [&](int q, int tt, int jj) { return lds[(5 * q + tt) * WB + wpad(jj)]; });
+}
+
+// region stride of a block's wave-owned transforms: at least the padded length, and
+// 8 modulo 32 elements, so that the transposing accesses of eight regions at once
+// spread over the LDS banks
+template <int N>
+struct WaveRegion {
+  static constexpr int size = WaveBuf<N>::size + ((8 - WaveBuf<N>::size % 32) + 32) % 32;
+};
+
+// Pass B with wave-owned columns: a block of W waves takes W adjacent half-spectrum
+// columns; rows are read with coalesced loads and transposed into the waves' regions
+// (one block barrier), then each wave runs its column's forward transform, the
+// multiplication by rhobar and the inverse transforms in its own region with wave-level
+// synchronisation only; each output is stored with coalesced row writes (two block
+// barriers around the transposing read).
+template <int N, int W>
+__global__ __launch_bounds__(64 * W) void k_passB_w(LaunchCtx c, int mode, int j, const float2* tw) {
+  constexpr int NH = N / 2, RS = WaveRegion<N>::size, BLOCK = 64 * W;
+  constexpr int ROWS = BLOCK / W;      // rows per cooperative pass (64)
+  constexpr int PER = N / ROWS;        // cooperative passes over the rows
+  constexpr int OWN = (N + 63) / 64;   // elements per lane of a column
+  const int p = pair_of_block(c);
+  if (p < 0) return;
+  const PairDesc& d = c.desc[p];
+  const PairState& s = c.st[p];
+  bool run;
+  if (mode == PB_MATVEC) run = s.phase == PH_SOLVE && s.gm_running;
+  else if (mode == PB_RECOVER) run = s.phase == PH_SOLVE;
+  else run = true;
+  if (!run) return;
+  count_bytes(c, mode == PB_MATVEC ? 16.0 : 8.0, N);
+  __shared__ float2 lds[W * RS];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int tc = threadIdx.x % W, tr = threadIdx.x / W;  // cooperative role: column, first row
+  const int s0 = blockIdx.x * W;
+  float2* L = lds + wv * RS;  // this wave's column: slot s0 + wv
+  const auto H = gmem<const float2>(d.H);
+  const auto T = gmem<float2>(d.T);
+  {  // rows in, transposed into the regions
+    float2 h[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) h[q] = H[(long)(tr + ROWS * q) * NH + s0 + tc];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) lds[tc * RS + wpad(tr + ROWS * q)] = h[q];
   }
   __syncthreads();
-  if (threadIdx.x <= j) {
-    double t = 0.0;
-    for (int w = 0; w < BLOCK / 64; ++w) t += red[w * (MA_MMAX + 1) + threadIdx.x];
-    d.part[(long)blockIdx.x * (MA_MMAX + 1) + threadIdx.x] = t;
+  wfft<N, false>(L, tw, lane);
+  auto store = [&](int o) {  // the regions' columns out as rows of T_o
+    __syncthreads();
+    const auto To = T + (long)o * N * NH;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) To[(long)(tr + ROWS * q) * NH + s0 + tc] = lds[tc * RS + wpad(tr + ROWS * q)];
+    __syncthreads();
+  };
+  if (mode == PB_FORWARD) {
+    store(0);
+    return;
+  }
+  const float scale = (float)((mode == PB_MATVEC ? s.vscale[j] : 1.0) / ((double)N * (double)N));
+  float ab[5];
+  for (int k = 0; k < 5; ++k) ab[k] = (float)s.abar[k];
+  const int slot = s0 + wv;
+  // wavenumbers q and N - q together (slot 0 packs the DC and Nyquist columns of the rows)
+  for (int q = lane; q <= NH; q += 64) {
+    const int qm = (N - q) % N;
+    const float2 z = L[wpad(q)], zm = L[wpad(qm)];
+    float2 vq, vm;
+    if (slot != 0) {
+      vq = cscale(cmul(rhobar<N>(q, slot, ab, c.mt), z), scale);
+      vm = cscale(cmul(rhobar<N>(qm, slot, ab, c.mt), zm), scale);
+    } else {
+      const float2 A = make_float2(0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y));
+      const float2 B = make_float2(0.5f * (z.y + zm.y), -0.5f * (z.x - zm.x));
+      const float2 aq = cmul(rhobar<N>(q, 0, ab, c.mt), A), bq = cmul(rhobar<N>(q, NH, ab, c.mt), B);
+      const float2 am = cmul(rhobar<N>(qm, 0, ab, c.mt), cconj(A));
+      const float2 bm = cmul(rhobar<N>(qm, NH, ab, c.mt), cconj(B));
+      vq = cscale(make_float2(aq.x - bq.y, aq.y + bq.x), scale);
+      vm = cscale(make_float2(am.x - bm.y, am.y + bm.x), scale);
+    }
+    L[wpad(q)] = vq;
+    if (qm != q) L[wpad(qm)] = vm;
+  }
+  wave_sync();
+  // the multiplied spectrum stays in registers (the lane's elements e = lane + 64 r)
+  float2 sv[OWN];
+#pragma unroll
+  for (int r = 0; r < OWN; ++r) {
+    const int e = lane + 64 * r;
+    sv[r] = (N % 64 == 0 || e < N) ? L[wpad(e)] : make_float2(0.f, 0.f);
+  }
+  const int nout = mode == PB_MATVEC ? 3 : 1;
+  for (int oo = 0; oo < nout; ++oo) {
+    const int o = (oo + 1) % 3 == 0 || nout == 1 ? 0 : oo + 1;  // order 1, 2, 0
+    wave_sync();
+#pragma unroll
+    for (int r = 0; r < OWN; ++r) {
+      const int e = lane + 64 * r;
+      if (N % 64 != 0 && e >= N) continue;
+      const float2 m = c.mt[e];
+      L[wpad(e)] = o == 0 ? sv[r] : ((o == 1) ? times_i(m.x, sv[r]) : cscale(sv[r], m.y));
+    }
+    wave_sync();
+    wfft<N, true>(L, tw, lane);
+    store(o);
+  }
+}
+
+// Pass A with wave-owned row pairs: a block of W waves, wave w builds the Krylov vector
+// on row pair w of the block (lane l takes the columns l, l + 64, ...), packs the two
+// rows as one complex row in its region, transforms it and writes the two half
+// spectra; the only block barrier is the final reduction of ||w'||^2.
+template <int N, int W>
+__global__ __launch_bounds__(64 * W) void k_passA_w(LaunchCtx c, int mode, int jn, const float2* tw) {
+  constexpr int NH = N / 2, WB = WaveBuf<N>::size, BLOCK = 64 * W;
+  constexpr long NN = (long)N * N;
+  constexpr int OWN = (N + 63) / 64;
+  const int p = pair_of_block(c);
+  if (p < 0) return;
+  const PairDesc& d = c.desc[p];
+  PairState& s = c.st[p];
+  bool run;
+  if (mode == PA_INIT) run = s.phase == PH_SOLVE && s.gm_running && s.gm_cycle == 0;
+  else if (mode == PA_PLAIN) run = s.phase == PH_SOLVE && s.gm_restart;
+  else if (mode == PA_ARNOLDI) run = s.phase == PH_SOLVE && s.gm_running;
+  else if (mode == PA_RECOVER) run = s.phase == PH_SOLVE;
+  else run = true;
+  if (!run) return;
+  __shared__ float2 lds[W * WB];
+  __shared__ float cf[MA_MMAX + 1];
+  __shared__ double scratch[BLOCK / 64];
+  int nv = 0;
+  bool usex = false;
+  if (mode == PA_ARNOLDI) nv = jn;
+  else if (mode == PA_RECOVER) { nv = s.gm_k; usex = s.gm_cycle > 0; }
+  if (threadIdx.x < nv) {
+    const int l = threadIdx.x;
+    cf[l] = mode == PA_ARNOLDI ? (float)(s.Hm[(jn - 1) * (MA_MMAX + 1) + l] * s.vscale[l]) : (float)s.y[l];
+  }
+  const float cst = (float)s.mass_c, inv_tau = (float)(1.0 / s.tau);
+  const bool scaled = mode == PA_INIT && c.precond == MA_PRECOND_DIAG;
+  const float trbar = (float)(s.abar[0] + s.abar[2]);
+  {
+    const bool fft = !(mode == PA_ARNOLDI && jn >= c.m);
+    double b = fft ? 4.0 : 0.0;
+    if (mode == PA_INIT) b += scaled ? 16.0 : 8.0;
+    else if (mode == PA_PLAIN || mode == PA_STEP) b += 4.0;
+    else if (mode == PA_ARNOLDI) b += 4.0 * (jn + 1) + 4.0;
+    else b += 4.0 * (nv + (usex ? 1 : 0));
+    count_bytes(c, b, N);
+  }
+  __syncthreads();  // cf
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  float2* L = lds + wv * WB;
+  const int ra = 2 * (blockIdx.x * W + wv);  // the wave's row pair
+  const auto V = gmem<float>(d.V);
+  const auto Vj = V + (long)jn * NN;
+  const auto R = gmem<const float>(d.r);
+  const auto coef = gmem<const float>(d.coef);
+  const auto X = gmem<const float>(d.x);
+  float va[OWN], vb[OWN];
+  int ea_[OWN];
+  float nrm = 0.f;
+#pragma unroll
+  for (int q = 0; q < OWN; ++q) {
+    const int jj = lane + 64 * q;
+    va[q] = vb[q] = 0.f;
+    ea_[q] = ra * N;
+    if (N % 64 != 0 && jj >= N) continue;
+    const int ea = ra * N + jj, eb = ea + N;
+    ea_[q] = ea;
+    if (mode == PA_INIT) {
+      va[q] = (R[ea] + cst) * inv_tau;
+      vb[q] = (R[eb] + cst) * inv_tau;
+      if (scaled) {
+        va[q] *= trbar / (coef[ea] + coef[2 * NN + ea]);
+        vb[q] *= trbar / (coef[eb] + coef[2 * NN + eb]);
+      }
+    } else if (mode == PA_PLAIN || mode == PA_STEP) {
+      va[q] = V[ea];
+      vb[q] = V[eb];
+    } else if (mode == PA_ARNOLDI) {
+      va[q] = Vj[ea];
+      vb[q] = Vj[eb];
+    } else {
+      va[q] = usex ? X[ea] : 0.f;
+      vb[q] = usex ? X[eb] : 0.f;
+    }
+  }
+  if (mode == PA_ARNOLDI || mode == PA_RECOVER) {
+    // v -= sum_l c_l V_l (Arnoldi) or x += sum_l y_l V_l (recovery), l in order
+    const float sg = mode == PA_ARNOLDI ? -1.f : 1.f;
+    float la[OWN], lb[OWN];
+    if (nv > 0) {
+#pragma unroll
+      for (int q = 0; q < OWN; ++q) {
+        la[q] = V[ea_[q]];
+        lb[q] = V[ea_[q] + N];
+      }
+    }
+    for (int l = 0; l < nv; ++l) {
+      float na[OWN], nb[OWN];
+      if (l + 1 < nv) {
+        const auto Vn = V + (long)(l + 1) * NN;
+#pragma unroll
+        for (int q = 0; q < OWN; ++q) {
+          na[q] = Vn[ea_[q]];
+          nb[q] = Vn[ea_[q] + N];
+        }
+      }
+      const float cl = sg * cf[l];
+#pragma unroll
+      for (int q = 0; q < OWN; ++q) {
+        va[q] += cl * la[q];
+        vb[q] += cl * lb[q];
+      }
+      if (l + 1 < nv) {
+#pragma unroll
+        for (int q = 0; q < OWN; ++q) {
+          la[q] = na[q];
+          lb[q] = nb[q];
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < OWN; ++q) {
+    const int jj = lane + 64 * q;
+    if (N % 64 != 0 && jj >= N) continue;
+    const int ea = ea_[q], eb = ea + N;
+    if (mode == PA_INIT) {
+      if (scaled) nrm += va[q] * va[q] + vb[q] * vb[q];
+      V[ea] = va[q];
+      V[eb] = vb[q];
+    } else if (mode == PA_ARNOLDI) {
+      Vj[ea] = va[q];
+      Vj[eb] = vb[q];
+      nrm += va[q] * va[q] + vb[q] * vb[q];
+    }
+    L[wpad(jj)] = make_float2(va[q], vb[q]);
+  }
+  if (!(mode == PA_ARNOLDI && jn >= c.m)) {
+    wave_sync();
+    wfft<N, false>(L, tw, lane);
+    const auto Hs = gmem<float2>(d.H);
+    for (int k = lane; k < NH; k += 64) {
+      const long ia = (long)ra * NH + k, ib = ia + NH;
+      const float2 zk = L[wpad(k)];
+      float2 oa, ob;
+      if (k == 0) {
+        const float2 zn = L[wpad(NH)];
+        oa = make_float2(zk.x, zn.x);
+        ob = make_float2(zk.y, zn.y);
+      } else {
+        const float2 zm = L[wpad(N - k)];
+        oa = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+        ob = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
+      }
+      Hs[ia] = oa;
+      Hs[ib] = ob;
+    }
+  }
+  if (mode == PA_ARNOLDI || scaled) {  // partial ||w'||^2 (or ||h / D||^2), folded per pair
+    double v[1] = {(double)nrm};
+    const int kinds[1] = {0};
+    block_reduce<1>(v, kinds, scratch);
+    if (threadIdx.x == 0) d.part[blockIdx.x] = v[0];
   }
 }
 
@@ -593,3 +987,5 @@ __global__ __launch_bounds__((Cfg<N, G>::C_BLOCK)) void k_passC(LaunchCtx c, int
 
 #define MA_FOR_EACH_N(X) \
   X(16) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024) X(1536) X(2048)
+// the sizes with wave-owned variants
+#define MA_FOR_EACH_N_WAVE(X) X(128) X(192) X(256) X(384) X(512) X(768) X(1024) X(1536) X(2048)

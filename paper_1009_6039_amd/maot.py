@@ -60,6 +60,7 @@ class Tuning(ctypes.Structure):
 
 
 TUNE_PASSES = ("row_a", "column", "row_c", "residual")
+TUNE_VARIANTS = 8  # MA_TUNE_VARIANTS: 0..3 block-shared kernels, 4..7 wave-owned transforms
 
 
 def tune_geometry(kernel_class, n, variant):

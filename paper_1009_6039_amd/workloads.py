@@ -20,6 +20,8 @@ blobs(N, seed)
 smooth_noise(N, seed, sigma_px)
     f = exp(z / 2) with z white noise filtered by a unit-gain periodic Gaussian
     of width sigma_px grid cells; scaled to mean one.  Draws f, then g.
+e1_example(N, k, gamma, alpha, rho)
+    the Section 5.1 family u* = (1/k) cos sin, g = 1 + alpha cos cos, f from eq. ma2.
 
 Grid convention everywhere: F[i, j] is the value at (x1, x2) = (i/N, j/N).
 """
@@ -64,6 +66,28 @@ def manufactured(N, A=0.01):
     f = (1.0 - c * s1 * s2) ** 2 - (c * c1 * c2) ** 2
     g = np.ones((N, N))
     return f, g, psi
+
+
+def e1_example(N, k=100.0, gamma=1, alpha=0.3, rho=1):
+    """(f, g, u*) of the Section 5.1 example family with the parameters it leaves open:
+    u* = (1/k) cos(2 pi gamma x1) sin(2 pi gamma x2), g = 1 + alpha cos(2 pi rho x1)
+    cos(2 pi rho x2), f = g(x + grad u*) det(I + D^2 u*) in closed form (the paper's
+    procedure: pick u and g, compute f from eq. ma2).  Defaults: amplitude 0.01, one
+    period, alpha 0.3."""
+    X1, X2 = grid(N)
+    tp = 2.0 * np.pi
+    a, w = 1.0 / k, tp * gamma
+    s1, c1 = np.sin(w * X1), np.cos(w * X1)
+    s2, c2 = np.sin(w * X2), np.cos(w * X2)
+    u = a * c1 * s2
+    u1, u2 = -a * w * s1 * s2, a * w * c1 * c2
+    u11 = u22 = -a * w * w * c1 * s2
+    u12 = -a * w * w * s1 * c2
+    y1, y2 = X1 + u1, X2 + u2
+    gy = 1.0 + alpha * np.cos(tp * rho * y1) * np.cos(tp * rho * y2)
+    f = gy * ((1.0 + u11) * (1.0 + u22) - u12 * u12)
+    g = 1.0 + alpha * np.cos(tp * rho * X1) * np.cos(tp * rho * X2)
+    return f, g, u
 
 
 def _blob_density(N, rng):

@@ -80,11 +80,13 @@ SIZES = (16, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048)
 @pytest.mark.parametrize("n", SIZES)
 def test_tune_geometry_table_is_consistent(n):
     # every variant of every kernel class tiles the grid exactly with whole
-    # wavefronts; duplicates point at a smaller index with the same geometry
+    # wavefronts; duplicates point at a smaller index with the same geometry.
+    # Variants 0..3 are the block-shared kernels, 4..7 the wave-owned ones: a geometry
+    # is distinct within its family.
     from paper_1009_6039_amd import maot
     for k in maot.TUNE_PASSES:
         seen = {}
-        for v in range(4):
+        for v in range(maot.TUNE_VARIANTS):
             canon, units, threads = maot.tune_geometry(k, n, v)
             assert 0 <= canon <= v and units >= 1 and threads % 64 == 0 and 64 <= threads <= 1024
             if k in ("row_a", "row_c"):
@@ -93,17 +95,18 @@ def test_tune_geometry_table_is_consistent(n):
                 assert (n // 2) % units == 0 and (n * units) % threads == 0 and threads % units == 0
             else:
                 assert n % units == 0 and units >= 16
+            family = 0 if canon < 4 else 1
             if canon < v:
-                assert seen[canon] == (units, threads)
+                assert seen[canon][1:] == (units, threads)
             else:
-                assert (units, threads) not in seen.values()
-            seen[v] = (units, threads)
+                assert (family, units, threads) not in seen.values()
+            seen[v] = (family, units, threads)
 
 
 def test_tune_geometry_rejects_bad_arguments():
     from paper_1009_6039_amd import maot
     assert maot.tune_geometry("row_c", 500, 0)[0] == -1
-    assert maot.tune_geometry("row_c", 512, 4)[0] == -1
+    assert maot.tune_geometry("row_c", 512, maot.TUNE_VARIANTS)[0] == -1
     assert maot.tune_geometry("row_c", 512, -1)[0] == -1
     assert maot.tune_geometry(7, 512, 0)[0] == -1
 

@@ -48,3 +48,13 @@ def test_same_seed_same_pair():
     a = W.blobs(32, W.seed_for(1, 3))
     b = W.blobs(32, W.seed_for(1, 3))
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_e1_example_mass_is_that_of_g():
+    # f = g(T(x)) det DT(x) with T = x + grad u* a diffeomorphism of the torus: by change of
+    # variables int f = int g = 1 (the trapezoid rule is spectrally exact for these smooth
+    # periodic integrands)
+    for kw in ({}, dict(alpha=0.5, rho=2), dict(gamma=2, k=200.0)):
+        f, g, u = W.e1_example(64, **kw)
+        assert abs(np.mean(f) - 1.0) < 1e-12 and abs(np.mean(g) - 1.0) < 1e-12
+        assert np.all(f > 0)
