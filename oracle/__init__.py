@@ -14,6 +14,9 @@ fd       fourth-order centred periodic differences and Simpson weights (Section 
 interp   periodic nearest / bilinear interpolation of grid data (Section 4)
 ma       residual M(u) (eq. ma2), linearisation (eq. linearmaeq), Strain's
          FFT operator (Section 4.2), GMRES(m), the damped Newton loop (eq. linma)
+fd_bicg  the finite-difference linear step of Section 4.1 (nine-point matrix, the
+         augmented system of its Lemma, BiCG)
+stability the power method on the inverse of the linearised operator (Section 5.1)
 cnn      the warm-start network (forward, backward, Adam) in FP64
 
 Parity status per function is listed in each module header.  Every function
@@ -22,4 +25,4 @@ routine, brute force, or a value the paper prints, except where a module header
 says "parity unpinned".
 """
 
-from . import cnn, fd, interp, ma  # noqa: F401
+from . import cnn, fd, fd_bicg, interp, ma  # noqa: F401

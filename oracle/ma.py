@@ -52,6 +52,7 @@ import time
 import numpy as np
 
 from . import fd
+from . import fd_bicg
 from . import interp as _interp
 
 OK, ENOCONV, ENONCONVEX, ENAN = 0, 1, 2, 3
@@ -336,8 +337,12 @@ def newton_direction(ev, prob, rhs_scale, op_mode, gmres_m, gmres_tol, gmres_max
 def solve(f, g, tau=1.0, tol=1e-6, psi0=None, max_newton=100, gmres_m=10,
           gmres_tol=1e-4, gmres_max_restarts=20, interp="bilinear", op_mode=0,
           damping_policy="fixed", max_backtrack=12, g_analytic=None, history=False,
-          symbol="spectral", precond="none", boundary_frac=0.1, forcing="fixed"):
-    """Damped Newton (eq. linma) with Strain's linear solver (Section 4.2).
+          symbol="spectral", precond="none", boundary_frac=0.1, forcing="fixed",
+          linear="strain", bicg_max_iters=1000):
+    """Damped Newton (eq. linma) with Strain's linear solver (Section 4.2), or with
+    linear="fd_bicg" the finite-difference system of Section 4.1 solved by BiCG
+    (oracle.fd_bicg) to the tolerance gmres_tol and at most bicg_max_iters iterations
+    per Newton step; the report's gmres_iters then counts BiCG iterations.
 
     psi0, if given, is tried as a first step from u = 0 (accepted if convex and the
     residual drops, halved otherwise, abandoned after max_backtrack halvings).
@@ -368,6 +373,10 @@ def solve(f, g, tau=1.0, tol=1e-6, psi0=None, max_newton=100, gmres_m=10,
     status = None
     if forcing not in ("fixed", "adaptive"):
         raise ValueError("forcing must be 'fixed' or 'adaptive'")
+    if linear not in ("strain", "fd_bicg"):
+        raise ValueError("linear must be 'strain' or 'fd_bicg'")
+    if linear == "fd_bicg" and precond != "none":
+        raise ValueError("the BiCG step has no preconditioner (Section 4.1)")
     eta, eta_min = gmres_tol, min(gmres_tol, 1e-3)  # GMRES tolerance of the next direction
     if psi0 is not None and ev.finite and ev.res_rms > tol:
         # checked start (not in the paper): psi0 is tried as a first step from u = 0 and
@@ -395,8 +404,12 @@ def solve(f, g, tau=1.0, tol=1e-6, psi0=None, max_newton=100, gmres_m=10,
         if n >= max_newton:
             status = ENOCONV
             break
-        theta, its = newton_direction(ev, prob, 1.0 / tau_cur, op_mode, gmres_m,
-                                      eta, gmres_max_restarts, symbol, precond)
+        if linear == "fd_bicg":
+            theta, its = fd_bicg.newton_direction(coefficients(ev, op_mode), ev.r, 1.0 / tau_cur,
+                                                  eta, bicg_max_iters)
+        else:
+            theta, its = newton_direction(ev, prob, 1.0 / tau_cur, op_mode, gmres_m,
+                                          eta, gmres_max_restarts, symbol, precond)
         gm_total += its
         n += 1
         if damping_policy == "fixed":
@@ -433,7 +446,10 @@ def solve(f, g, tau=1.0, tol=1e-6, psi0=None, max_newton=100, gmres_m=10,
         else:
             raise ValueError("damping_policy must be 'fixed' or 'backtrack'")
         hist.append(ev.res_rms)
-    psi = u
+    # u is fixed up to a constant (Section 4.1 fixes it by a zero integral): the mean-zero
+    # representative is returned; the Strain step keeps u at mean zero by itself, the BiCG
+    # step moves the mean whenever the right-hand side is not in the range of A (F4)
+    psi = u - np.mean(u)
     mp = np.stack([prob.X1 + ev.u1, prob.X2 + ev.u2])
     rep = Report(status=status, newton_iters=n, gmres_iters=gm_total, res_rms=ev.res_rms,
                  res_max=ev.res_max, res0_rms=res0, mass_defect=ev.mass_defect,
