@@ -7,7 +7,8 @@
  * the Monge-Ampere equation g(x + grad u) det(I + D^2 u) = f  (Section 3.1, eq. ma2)
  * for the mean-zero periodic potential u with |x|^2/2 + u convex, by the damped
  * Newton iteration of eq. (linma), each linear step solved by Strain's FFT method
- * with restarted GMRES(m) (Section 4.2).  The optimal map is x + grad u
+ * with restarted GMRES(m) (Section 4.2) or, as an option, by the finite-difference
+ * system of Section 4.1 with BiCG.  The optimal map is x + grad u
  * (Theorem CE1 and Section 5.2).
  *
  * Conventions shared by every entry point
@@ -31,7 +32,7 @@
 extern "C" {
 #endif
 
-#define MA_OT_ABI_VERSION 9
+#define MA_OT_ABI_VERSION 10
 
 /* return / status codes */
 #define MA_OK 0           /* converged: rms residual <= tol                           */
@@ -71,6 +72,16 @@ extern "C" {
  * min(gmres_tol, 1e-3)), after a full step 4x looser again (up to gmres_tol) */
 #define MA_FORCING_FIXED 0
 #define MA_FORCING_ADAPTIVE 1
+/* The linear step of each Newton iteration: Strain's FFT method with GMRES(m)
+ * (Section 4.2), or the finite-difference system of Section 4.1: second-order centred
+ * differences for theta (a nine-point stencil), made nonsingular by the row of ones
+ * that its Lemma adds to every row (tilde A = A + 1 1^T), solved by BiCG without a
+ * preconditioner from a zero start with shadow residual r~0 = r0, until
+ * ||r_k||_2 <= gmres_tol ||b||_2 or bicg_max_iters iterations.  Vectors and
+ * reductions in FP64, coefficients in FP32.  Requires MA_PRECOND_NONE; gmres_m,
+ * gmres_max_restarts and symbol are not used. */
+#define MA_LINEAR_STRAIN_GMRES 0
+#define MA_LINEAR_FD_BICG 1
 
 typedef struct ma_options {
   int max_newton;          /* Newton iterations before MA_ENOCONV (100)              */
@@ -96,12 +107,17 @@ typedef struct ma_options {
   int max_active;          /* ma_solve_batched: at most this many pairs in flight; a  */
                            /* finished pair's slot takes the next pending pair of its */
                            /* size within the same call (0: every pair at once)       */
+  int linear_solver;       /* MA_LINEAR_* (MA_LINEAR_STRAIN_GMRES)                    */
+  int bicg_max_iters;      /* MA_LINEAR_FD_BICG: iterations per Newton step (1000,    */
+                           /* Section 5.1), >= 1                                      */
 } ma_options;
 
 typedef struct ma_report {
   int status;              /* MA_OK or a soft failure code                           */
   int newton_iters;        /* Newton directions computed                             */
-  int gmres_iters;         /* GMRES inner iterations (operator applications)         */
+  int gmres_iters;         /* inner iterations of the linear steps: GMRES operator  */
+                           /* applications, or BiCG iterations (one product with    */
+                           /* tilde A and one with its transpose each)               */
   int backtracks;          /* rejected trial steps (MA_DAMP_BACKTRACK)               */
   double res_rms;          /* sqrt(mean (f - f~_n)^2) at the returned iterate        */
   double res_max;          /* max |f - f~_n|                                         */
@@ -200,6 +216,7 @@ int ma_solve_noalloc(const ma_options* opt, const double* f, const double* g, in
 #define MA_PROF_ROW_A 2      /* row pass A: Krylov vector build + forward rows  */
 #define MA_PROF_COLUMN 3     /* column pass B with the spectral multiply        */
 #define MA_PROF_ROW_C 4      /* row pass C: inverse rows + combine + dots       */
+#define MA_PROF_BICG_MATVEC 5  /* BiCG: the products with tilde A and tilde A^T   */
 
 /* Selects the class to time (MA_PROF_NONE disables) and the sampling stride
  * (every >= 1; 1 = every launch), and clears the counters.  MA_EINVAL for an
@@ -271,6 +288,24 @@ int ma_step_gmres(ma_plan* plan, int n, const float* h, const float* coef,
 int ma_power_inverse(ma_plan* plan, int n, const float* coef, const double* abar,
                      const float* b0, int iters, double gmres_tol, int gmres_m,
                      int max_restarts, double* rho, int* gmres_iters, void* stream);
+
+/* The finite-difference operator of Section 4.1 and its transpose:
+ *   q  = tilde A p  = L_h p + (sum p) 1,
+ *   qt = tilde A^T pt = L_h^T pt + (sum pt) 1,
+ * with L_h p = a11 D11 p + 2 a12 D12 p + a22 D22 p + b1 D1 p + b2 D2 p (second-order
+ * centred periodic differences, D12 on the four diagonal neighbours over 4h^2) and
+ * L_h^T y = D11(a11 y) + 2 D12(a12 y) + D22(a22 y) - D1(b1 y) - D2(b2 y).
+ * p, pt, q, qt N*N FP64; coef 5*N*N FP32 (a11, a12, a22, b1, b2).  The sums are taken
+ * on the host in FP64 (this entry point copies p and pt there).  Synchronises. */
+int ma_step_fd_apply(ma_plan* plan, int n, const double* p, const double* pt, const float* coef,
+                     double* q, double* qt, void* stream);
+
+/* BiCG on tilde A x = h (Section 4.1): zero start, shadow residual r~0 = r0, stop at
+ * ||h - tilde A x||_2 <= tol ||h||_2 (the recurrence residual) or after max_iters
+ * iterations, or at a breakdown (a zero denominator).  h N*N FP32, coef 5*N*N FP32,
+ * x N*N FP64 out; iters host out (iterations done).  Synchronises. */
+int ma_step_bicg(ma_plan* plan, int n, const float* h, const float* coef, double tol, int max_iters,
+                 double* x, int* iters, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Autotuner (not in the paper): launch geometry per grid size.  Each of the four

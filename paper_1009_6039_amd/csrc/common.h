@@ -56,6 +56,7 @@ struct PairDesc {
   float2* H;       // n*(n/2) half spectrum after the row pass
   float2* T;       // 3*n*(n/2) column-pass outputs
   double* part;    // per-block partial sums
+  double* bv;      // 7*n*n BiCG vectors x, r, r~, p, p~, q, q~ (finite-difference step only)
 };
 
 struct PairState {
@@ -86,6 +87,11 @@ struct PairState {
   double vscale[MA_MMAX + 1];       // v_l = vscale[l] * V[l]
   double Hm[(MA_MMAX + 1) * MA_MMAX];  // Hessenberg, column-major: Hm[j*(MMAX+1)+i]
   double cs[MA_MMAX], sn[MA_MMAX], gv[MA_MMAX + 1], y[MA_MMAX + 1], q[MA_MMAX + 1];
+  // --- BiCG (finite-difference step; gm_running, gm_k, bnorm, gm_target are shared) --
+  double bi_rho, bi_alpha, bi_beta;  // r~ . r, and the current step coefficients
+  double bi_sum_p, bi_sum_pt;        // sum p, sum p~ (the row of ones of tilde A)
+  int bi_break;                      // a zero denominator: the iteration stops
+  int bi_pad;
 };
 
 // one slot refilled with a new pair (continuous batching): written by the host into a
@@ -115,6 +121,8 @@ struct LaunchCtx {
   // and *active_n its length; blocks with blockIdx.y >= *active_n exit at once (the grid
   // is sized by an upper bound the host knows)
   const int* active_n;
+  int bicg_max;  // BiCG iterations per Newton step (finite-difference step)
+  int bicg_pad;
 };
 
 // Global-address-space view of a device buffer.  Accesses through it compile to

@@ -104,6 +104,7 @@ namespace {
 // partial-sum slots per pair: the largest need over all launch-geometry variants
 size_t part_doubles(int n) {
   size_t need = 256 * 4;
+  need = std::max(need, (size_t)bicg_blocks(n) * 4);
   for (int v = 0; v < MA_NVARIANTS; ++v) {
     need = std::max(need, (size_t)residual_blocks(n, v) * MA_NPART_RES);
     need = std::max(need, (size_t)passC_blocks(n, v) * (MA_MMAX + 1));
@@ -112,7 +113,7 @@ size_t part_doubles(int n) {
   return need;
 }
 
-size_t pair_bytes(int n, int m) {
+size_t pair_bytes(int n, int m, bool bicg) {
   const size_t nn = (size_t)n * n;
   size_t b = 0;
   b += align256(8 * nn) * 2;              // u, f
@@ -124,10 +125,11 @@ size_t pair_bytes(int n, int m) {
   b += align256(4 * nn);                  // H
   b += align256(12 * nn);                 // T
   b += align256(8 * part_doubles(n));     // partials
+  if (bicg) b += align256(56 * nn);       // BiCG vectors
   return b;
 }
 
-void carve(PairDesc& d, char*& p, int n, int m) {
+void carve(PairDesc& d, char*& p, int n, int m, bool bicg) {
   const size_t nn = (size_t)n * n;
   auto take = [&](size_t bytes) {
     char* q = p;
@@ -146,7 +148,10 @@ void carve(PairDesc& d, char*& p, int n, int m) {
   d.H = (float2*)take(4 * nn);
   d.T = (float2*)take(12 * nn);
   d.part = (double*)take(8 * part_doubles(n));
+  d.bv = bicg ? (double*)take(56 * nn) : nullptr;
 }
+
+bool uses_bicg(const ma_options& o) { return o.linear_solver == MA_LINEAR_FD_BICG; }
 
 bool n_ok(int n) { return n >= 16 && n <= 2048 && n % 16 == 0 && fft_size_supported(n); }
 
@@ -159,7 +164,8 @@ int validate_options(const ma_options& o) {
       (o.precond != MA_PRECOND_NONE && o.precond != MA_PRECOND_DIAG) ||
       !(o.boundary_frac >= 0.0 && o.boundary_frac < 1.0) ||
       (o.forcing != MA_FORCING_FIXED && o.forcing != MA_FORCING_ADAPTIVE) || !(o.wait_limit_s > 0.0) ||
-      o.max_active < 0)
+      o.max_active < 0 || (o.linear_solver != MA_LINEAR_STRAIN_GMRES && o.linear_solver != MA_LINEAR_FD_BICG) ||
+      o.bicg_max_iters < 1 || (o.linear_solver == MA_LINEAR_FD_BICG && o.precond != MA_PRECOND_NONE))
     return MA_EINVAL;
   return MA_OK;
 }
@@ -227,7 +233,7 @@ int ensure_multipliers(ma_plan* P, int n, int symbol) {
 int ensure_workspace(ma_plan* P, const std::vector<int>& ns) {
   const int m = P->opt.gmres_m;
   size_t need = 0;
-  for (int n : ns) need += pair_bytes(n, m);
+  for (int n : ns) need += pair_bytes(n, m, uses_bicg(P->opt));
   if (need > P->arena_bytes) {
     if (P->arena) hipFree(P->arena);
     P->arena = nullptr;
@@ -254,7 +260,7 @@ int ensure_workspace(ma_plan* P, const std::vector<int>& ns) {
   }
   P->h_desc.assign(np, PairDesc{});
   char* p = P->arena;
-  for (int q = 0; q < np; ++q) carve(P->h_desc[q], p, ns[q], P->opt.gmres_m);
+  for (int q = 0; q < np; ++q) carve(P->h_desc[q], p, ns[q], P->opt.gmres_m, uses_bicg(P->opt));
   for (int n : ns) {
     int e = ensure_twiddles(P, n);
     if (!e) e = ensure_multipliers(P, n, P->opt.symbol);
@@ -283,6 +289,7 @@ LaunchCtx make_ctx(const ma_plan* P, const Class& cl, int kind = MA_PROF_NONE, b
   c.precond = P->opt.precond;
   c.boundary_frac = P->opt.boundary_frac;
   c.forcing = P->opt.forcing;
+  c.bicg_max = P->opt.bicg_max_iters;
   auto t = P->tune.find(cl.n);
   for (int k = 0; k < 4; ++k) c.var[k] = t == P->tune.end() ? 0 : t->second.v[k];
   return c;
@@ -371,6 +378,11 @@ void L_C(ma_plan* P, const Class& c, int mode, int j, hipStream_t st) {
   const bool t = prof_pick(P, MA_PROF_ROW_C);
   launch_passC(make_ctx(P, c, MA_PROF_ROW_C, t), c.n, c.count, mode, j, c.tw, st,
                prof_events(P, t ? MA_PROF_ROW_C : MA_PROF_NONE));
+}
+void L_bicg(ma_plan* P, const Class& c, int step, hipStream_t st) {
+  const bool t = step == BI_MATVEC && prof_pick(P, MA_PROF_BICG_MATVEC);
+  launch_bicg(make_ctx(P, c, step == BI_MATVEC ? MA_PROF_BICG_MATVEC : MA_PROF_NONE, t), c.n, c.count, step, st,
+              prof_events(P, t ? MA_PROF_BICG_MATVEC : MA_PROF_NONE));
 }
 
 // Waits until slot `slot` of the summary holds the counts of the launch numbered
@@ -483,6 +495,73 @@ int launch_cycle_body(ma_plan* P, ClassList cls, int npairs, hipStream_t st) {
   return MA_OK;
 }
 
+// BiCG iterations of the finite-difference step (Section 4.1).  As for GMRES, a summary
+// is queued after every iteration and the host reads the one queued two iterations
+// earlier; once no pair is still iterating, no further iteration is launched.  In the
+// no-allocation mode (no mapped summary) the stream is drained every 16 iterations.
+int launch_bicg_body(ma_plan* P, ClassList cls, int npairs, hipStream_t st) {
+  constexpr int LAG = 2, NOALLOC_PERIOD = 16;
+  for (int j = 0; j < P->opt.bicg_max_iters; ++j) {
+    for (const Class& c : cls) {
+      L_bicg(P, c, BI_MATVEC, st);
+      L_bicg(P, c, BI_ALPHA, st);
+      L_bicg(P, c, BI_UPDATE, st);
+      L_bicg(P, c, BI_BETA, st);
+      L_bicg(P, c, BI_DIRECTION, st);
+    }
+    if (P->no_alloc) {
+      if ((j + 1) % NOALLOC_PERIOD) continue;
+      const int e = read_summary(P, npairs, st);
+      if (e) return e;
+      if (P->h_summary[8] == 0) break;
+      continue;
+    }
+    const int slot = j % (LAG + 1);
+    P->ring_seq[slot] = next_seq(P);
+    launch_summary(P->d_state, P->d_ids, npairs, P->d_summary + MA_SUMMARY_INTS * (1 + slot), P->ring_seq[slot],
+                   st);
+    if (j >= LAG) {
+      const int old = (j - LAG) % (LAG + 1);
+      const int e = wait_summary(P, 1 + old, P->ring_seq[old], st);
+      if (e) return e;
+      if (P->h_summary[MA_SUMMARY_INTS * (1 + old) + 8] == 0) break;
+    }
+  }
+  return MA_OK;
+}
+
+// The linear step of one Newton iteration for the solving pairs: theta written, u += theta
+int linear_step(ma_plan* P, const std::vector<Class>& vsolve, int npairs, hipStream_t st) {
+  const ClassList sl{vsolve.data(), (int)vsolve.size()};
+  if (uses_bicg(P->opt)) {
+    for (const Class& c : vsolve) L_bicg(P, c, BI_INIT, st);
+    int e = launch_bicg_body(P, sl, npairs, st);
+    if (e) return e;
+    for (const Class& c : vsolve) L_bicg(P, c, BI_FINISH, st);
+    return MA_OK;
+  }
+  for (const Class& c : vsolve) L_A(P, c, PA_INIT, 0, st);
+  int e = launch_cycle_body(P, sl, npairs, st);
+  if (e) return e;
+  for (int cyc = 0; cyc < P->opt.gmres_max_restarts; ++cyc) {
+    e = read_summary(P, npairs, st);
+    if (e) return e;
+    if (P->h_summary[6] == 0) break;
+    for (const Class& c : vsolve) {
+      launch_restart(make_ctx(P, c), c.n, c.count, st);
+      L_A(P, c, PA_PLAIN, 0, st);
+    }
+    e = launch_cycle_body(P, sl, npairs, st);
+    if (e) return e;
+  }
+  for (const Class& c : vsolve) {
+    L_A(P, c, PA_RECOVER, 0, st);
+    L_B(P, c, PB_RECOVER, 0, st);
+    L_C(P, c, PC_RECOVER, 0, st);
+  }
+  return MA_OK;
+}
+
 // the whole damped Newton loop for the pairs already described in P->h_desc
 int run_solver(ma_plan* P, int npairs, double damping, double tol, hipStream_t st, ClassList cls) {
   HIP_TRY(hipMemcpyAsync(P->d_desc, P->h_desc.data(), sizeof(PairDesc) * npairs, hipMemcpyHostToDevice, st));
@@ -509,27 +588,9 @@ int run_solver(ma_plan* P, int npairs, double damping, double tol, hipStream_t s
     const int n_update = P->h_summary[PH_BACKTRACK] + P->h_summary[PH_REVERT];
     if (n_solve == 0 && n_update == 0) break;  // every pair is done
     compact_views(P, cls, npairs - P->h_summary[PH_DONE], n_solve, vlive, vsolve, st);
-    const ClassList sl{vsolve.data(), (int)vsolve.size()};
     if (n_solve > 0) {
-      for (const Class& c : vsolve) L_A(P, c, PA_INIT, 0, st);
-      e = launch_cycle_body(P, sl, npairs, st);
+      e = linear_step(P, vsolve, npairs, st);
       if (e) return e;
-      for (int cyc = 0; cyc < P->opt.gmres_max_restarts; ++cyc) {
-        e = read_summary(P, npairs, st);
-        if (e) return e;
-        if (P->h_summary[6] == 0) break;
-        for (const Class& c : vsolve) {
-          launch_restart(make_ctx(P, c), c.n, c.count, st);
-          L_A(P, c, PA_PLAIN, 0, st);
-        }
-        e = launch_cycle_body(P, sl, npairs, st);
-        if (e) return e;
-      }
-      for (const Class& c : vsolve) {
-        L_A(P, c, PA_RECOVER, 0, st);
-        L_B(P, c, PB_RECOVER, 0, st);
-        L_C(P, c, PC_RECOVER, 0, st);
-      }
     }
     if (n_update > 0)
       for (const Class& c : vlive) launch_step_update(make_ctx(P, c), c.n, c.count, st);
@@ -742,27 +803,9 @@ int run_continuous(ma_plan* P, int npairs, const std::vector<int>& ns, const dou
     int n_live = 0;
     for (int s = 0; s < S; ++s) n_live += slot_pair[s] >= 0;
     compact_views(P, cl, n_live, n_solve, vlive, vsolve, st);
-    const ClassList sl{vsolve.data(), (int)vsolve.size()};
     if (n_solve > 0) {
-      for (const Class& c : vsolve) L_A(P, c, PA_INIT, 0, st);
-      e = launch_cycle_body(P, sl, S, st);
+      e = linear_step(P, vsolve, S, st);
       if (e) return e;
-      for (int cyc = 0; cyc < P->opt.gmres_max_restarts; ++cyc) {
-        e = read_summary(P, S, st);
-        if (e) return e;
-        if (P->h_summary[6] == 0) break;
-        for (const Class& c : vsolve) {
-          launch_restart(make_ctx(P, c), c.n, c.count, st);
-          L_A(P, c, PA_PLAIN, 0, st);
-        }
-        e = launch_cycle_body(P, sl, S, st);
-        if (e) return e;
-      }
-      for (const Class& c : vsolve) {
-        L_A(P, c, PA_RECOVER, 0, st);
-        L_B(P, c, PB_RECOVER, 0, st);
-        L_C(P, c, PC_RECOVER, 0, st);
-      }
     }
     if (n_update > 0)
       for (const Class& c : vlive) launch_step_update(make_ctx(P, c), c.n, c.count, st);
@@ -942,6 +985,8 @@ void ma_options_default(ma_options* o) {
   o->forcing = MA_FORCING_FIXED;
   o->wait_limit_s = 600.0;
   o->max_active = 0;
+  o->linear_solver = MA_LINEAR_STRAIN_GMRES;
+  o->bicg_max_iters = 1000;
 }
 
 const char* ma_strerror(int code) {
@@ -1092,7 +1137,7 @@ int ma_plan_get_tuning(const ma_plan* P, int n, ma_tuning* out) {
 }
 
 int ma_plan_profile(ma_plan* P, int kind, int every) {
-  if (!P || kind < MA_PROF_NONE || kind > MA_PROF_ROW_C || every < 1) return MA_EINVAL;
+  if (!P || kind < MA_PROF_NONE || kind > MA_PROF_BICG_MATVEC || every < 1) return MA_EINVAL;
   HIP_TRY(hipDeviceSynchronize());
   P->prof_kind = kind;
   P->prof_every = every;
@@ -1327,6 +1372,83 @@ int ma_step_gmres(ma_plan* P, int n, const float* h, const float* coef, const do
   return rc;
 }
 
+int ma_step_fd_apply(ma_plan* P, int n, const double* p, const double* pt, const float* coef, double* q,
+                     double* qt, void* stream) {
+  if (!P || !p || !pt || !coef || !q || !qt || !n_ok(n)) return MA_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const size_t nn = (size_t)n * n;
+  std::vector<double> hp(nn), hpt(nn);
+  HIP_TRY(hipMemcpyAsync(hp.data(), p, 8 * nn, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(hpt.data(), pt, 8 * nn, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  double sp = 0.0, spt = 0.0;
+  for (size_t k = 0; k < nn; ++k) {
+    sp += hp[k];
+    spt += hpt[k];
+  }
+  const ma_options saved = P->opt;
+  P->opt.linear_solver = MA_LINEAR_FD_BICG;
+  P->opt.precond = MA_PRECOND_NONE;
+  PairState s = step_state(nullptr);
+  s.bi_sum_p = sp;
+  s.bi_sum_pt = spt;
+  Class c;
+  int rc = step_prepare(P, n, s, st, c);
+  if (!rc) {
+    const PairDesc& d = P->h_desc[0];
+    if (hipMemcpyAsync(d.bv + 3 * nn, p, 8 * nn, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(d.bv + 4 * nn, pt, 8 * nn, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(d.coef, coef, 20 * nn, hipMemcpyDeviceToDevice, st) != hipSuccess) {
+      rc = MA_EHIP;
+    } else {
+      launch_bicg(make_ctx(P, c), n, 1, BI_MATVEC, st);
+      if (hipGetLastError() != hipSuccess ||
+          hipMemcpyAsync(q, d.bv + 5 * nn, 8 * nn, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+          hipMemcpyAsync(qt, d.bv + 6 * nn, 8 * nn, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
+        rc = MA_EHIP;
+    }
+  }
+  P->opt = saved;
+  return rc;
+}
+
+int ma_step_bicg(ma_plan* P, int n, const float* h, const float* coef, double tol, int max_iters, double* x,
+                 int* iters, void* stream) {
+  if (!P || !h || !coef || !x || !(tol > 0.0) || max_iters < 1 || !n_ok(n)) return MA_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const size_t nn = (size_t)n * n;
+  const ma_options saved = P->opt;
+  P->opt.linear_solver = MA_LINEAR_FD_BICG;
+  P->opt.precond = MA_PRECOND_NONE;
+  P->opt.gmres_tol = tol;
+  P->opt.bicg_max_iters = max_iters;
+  PairState s = step_state(nullptr);  // tau = 1, no translation: b = h
+  s.mass_c = 0.0;
+  Class c;
+  int rc = step_prepare(P, n, s, st, c);
+  do {
+    if (rc) break;
+    const PairDesc& d = P->h_desc[0];
+    if (hipMemcpyAsync(d.r, h, 4 * nn, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(d.coef, coef, 20 * nn, hipMemcpyDeviceToDevice, st) != hipSuccess) {
+      rc = MA_EHIP;
+      break;
+    }
+    launch_bicg(make_ctx(P, c), n, 1, BI_INIT, st);
+    if ((rc = launch_bicg_body(P, ClassList{&c, 1}, 1, st))) break;
+    if (hipMemcpyAsync(x, d.bv, 8 * nn, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(P->h_state.data(), P->d_state, sizeof(PairState), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+      rc = MA_EHIP;
+      break;
+    }
+    if (iters) *iters = P->h_state[0].gm_k;
+  } while (0);
+  P->opt = saved;
+  return rc;
+}
+
 int ma_power_inverse(ma_plan* P, int n, const float* coef, const double* abar, const float* b0, int iters,
                      double gmres_tol, int gmres_m, int max_restarts, double* rho, int* gmres_iters, void* stream) {
   if (!P || !coef || !abar || !b0 || !rho || iters < 1 || iters > 100000 || gmres_m < 1 || gmres_m > MA_MMAX ||
@@ -1405,13 +1527,13 @@ int ma_solve_noalloc(const ma_options* opt, const double* f, const double* g, in
   if (e) return e;
   NoAllocSlot& S = g_noalloc[dev];
   ma_plan* P = &g_noalloc_plan[dev];
-  if (pair_bytes(n, opt->gmres_m) > P->arena_bytes) return MA_EINVAL;  // beyond the scratch array
+  if (pair_bytes(n, opt->gmres_m, uses_bicg(*opt)) > P->arena_bytes) return MA_EINVAL;  // beyond the scratch array
   P->opt = *opt;
   hipStream_t st = (hipStream_t)stream;
   PairDesc& d = P->h_desc[0];
   d = PairDesc{};
   char* p = P->arena;
-  carve(d, p, n, P->opt.gmres_m);
+  carve(d, p, n, P->opt.gmres_m, uses_bicg(P->opt));
   d.cls = 0;
   d.f_in = f;
   d.g_in = g;

@@ -22,15 +22,16 @@ DAMPING = {"fixed": 0, "backtrack": 1}
 SYMBOL = {"spectral": 0, "fd4": 1}
 PRECOND = {"none": 0, "diag": 1}
 FORCING = {"fixed": 0, "adaptive": 1}
+LINEAR = {"strain_gmres": 0, "fd_bicg": 1}
 
-PROF = {"none": 0, "residual": 1, "row_a": 2, "column": 3, "row_c": 4}
+PROF = {"none": 0, "residual": 1, "row_a": 2, "column": 3, "row_c": 4, "bicg_matvec": 5}
 
 EXPORTED = ("ma_abi_version", "ma_options_default", "ma_strerror", "ma_plan_create",
             "ma_plan_destroy", "ma_plan_set_options", "ma_solve", "ma_solve_batched", "ma_solve_noalloc",
             "ma_plan_profile", "ma_plan_profile_read",
             "ma_plan_autotune", "ma_plan_set_tuning", "ma_plan_get_tuning", "ma_tune_geometry",
             "ma_step_residual", "ma_step_fft2", "ma_step_strain_apply",
-            "ma_step_lbar_inverse", "ma_step_gmres", "ma_power_inverse",
+            "ma_step_lbar_inverse", "ma_step_gmres", "ma_power_inverse", "ma_step_fd_apply", "ma_step_bicg",
             "ma_cnn_create", "ma_cnn_destroy", "ma_cnn_param_count", "ma_cnn_set_params",
             "ma_cnn_get_params", "ma_cnn_prepare_input", "ma_cnn_target", "ma_cnn_forward",
             "ma_cnn_gradients", "ma_cnn_train_step", "ma_cnn_warm_start")
@@ -42,7 +43,8 @@ class Options(ctypes.Structure):
                 ("interp", ctypes.c_int), ("op_mode", ctypes.c_int),
                 ("damping_policy", ctypes.c_int), ("max_backtrack", ctypes.c_int),
                 ("symbol", ctypes.c_int), ("precond", ctypes.c_int), ("boundary_frac", ctypes.c_double),
-                ("forcing", ctypes.c_int), ("wait_limit_s", ctypes.c_double), ("max_active", ctypes.c_int)]
+                ("forcing", ctypes.c_int), ("wait_limit_s", ctypes.c_double), ("max_active", ctypes.c_int),
+                ("linear_solver", ctypes.c_int), ("bicg_max_iters", ctypes.c_int)]
 
 
 class Tuning(ctypes.Structure):
@@ -124,6 +126,8 @@ def load():
     lib.ma_step_gmres.argtypes = [P, I, P, P, ctypes.POINTER(D), I, D, I, P, ctypes.POINTER(I), P]
     lib.ma_power_inverse.argtypes = [P, I, P, ctypes.POINTER(D), P, I, D, I, I, ctypes.POINTER(D),
                                      ctypes.POINTER(I), P]
+    lib.ma_step_fd_apply.argtypes = [P, I, P, P, P, P, P, P]
+    lib.ma_step_bicg.argtypes = [P, I, P, P, D, I, P, ctypes.POINTER(I), P]
     F, L = ctypes.c_float, ctypes.c_long
     lib.ma_cnn_create.argtypes = [I, I, I, I, ctypes.POINTER(I), ctypes.POINTER(P)]
     lib.ma_cnn_destroy.argtypes = [P]
@@ -178,6 +182,8 @@ def make_options(**kw):
             v = PRECOND[v] if isinstance(v, str) else v
         elif k == "forcing":
             v = FORCING[v] if isinstance(v, str) else v
+        elif k == "linear_solver":
+            v = LINEAR[v] if isinstance(v, str) else v
         if not hasattr(o, k):
             raise TypeError("unknown option %r" % k)
         setattr(o, k, v)
@@ -350,6 +356,28 @@ class Plan:
                "ma_step_gmres")
         return theta, its.value
 
+    def step_fd_apply(self, p, pt, coef):
+        """The finite-difference operator of Section 4.1: (tilde A p, tilde A^T pt), FP64."""
+        p = _dev(p, torch.float64)
+        pt = _dev(pt, torch.float64)
+        coef = _dev(coef, torch.float32)
+        n = p.shape[0]
+        q = torch.empty_like(p)
+        qt = torch.empty_like(p)
+        _check(load().ma_step_fd_apply(self._h, n, _ptr(p), _ptr(pt), _ptr(coef), _ptr(q), _ptr(qt), _stream()),
+               "ma_step_fd_apply")
+        return q, qt
+
+    def step_bicg(self, h, coef, tol=1e-4, max_iters=1000):
+        """BiCG on tilde A x = h (Section 4.1): (x FP64, iterations)."""
+        h = _dev(h, torch.float32)
+        coef = _dev(coef, torch.float32)
+        n = h.shape[0]
+        x = torch.empty(h.shape, dtype=torch.float64, device=h.device)
+        its = ctypes.c_int(0)
+        _check(load().ma_step_bicg(self._h, n, _ptr(h), _ptr(coef), float(tol), int(max_iters), _ptr(x),
+                                   ctypes.byref(its), _stream()), "ma_step_bicg")
+        return x, its.value
 
     def power_inverse(self, coef, abar, b0, iters=8, gmres_tol=1e-6, m=10, max_restarts=50):
         """Power iteration on the inverse operator (Section 5.1): (rho_k, GMRES iterations per step)."""

@@ -51,6 +51,8 @@ def test_default_options_and_error_strings(lib):
     o = maot.make_options()
     assert (o.max_newton, o.gmres_m, o.gmres_max_restarts) == (100, 10, 20)
     assert o.gmres_tol == 1e-4 and o.max_backtrack == 12 and o.wait_limit_s == 600.0
+    # the linear step of Section 4.2 by default; BiCG capped at 1000 iterations (Section 5.1)
+    assert o.linear_solver == maot.LINEAR["strain_gmres"] and o.bicg_max_iters == 1000
     assert maot.strerror(0) == "converged"
     assert "invalid" in maot.strerror(-1)
 
@@ -69,7 +71,8 @@ def test_plan_create_rejects_bad_options(lib):
     h = ctypes.c_void_p()
     for bad in (dict(gmres_m=0), dict(gmres_m=31), dict(gmres_tol=0.0), dict(interp=7),
                 dict(damping_policy=3), dict(max_backtrack=-1), dict(wait_limit_s=0.0),
-                dict(wait_limit_s=-1.0)):
+                dict(wait_limit_s=-1.0), dict(linear_solver=2), dict(linear_solver="fd_bicg", bicg_max_iters=0),
+                dict(linear_solver="fd_bicg", precond="diag")):
         o = maot.make_options(**bad)
         assert lib.ma_plan_create(64, 1, ctypes.byref(o), ctypes.byref(h)) == -1
 
