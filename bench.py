@@ -220,6 +220,72 @@ def extra_configs(args, maot, W, method, tuning_cache):
             "ms_per_solve": round(1e3 * float(np.median(t)), 3), "status": rep["status"],
             "newton_iters": rep["newton_iters"], "gmres_iters": rep["gmres_iters"], "res_rms": rep["res_rms"],
             "err_vs_oracle_sampled": err}
+    del fd, gd
+    res.update(fd_bicg_configs(args, maot, W))
+    return res
+
+
+def fd_bicg_configs(args, maot, W):
+    """The finite-difference linear step of Section 4.1 (nine-point system, BiCG at
+    tolerance 1e-1, fixed tau = 1 as in Section 5.1) on the workload the paper runs it on:
+    a batch of 64 members of the Section 5.1 example family at 256^2 (seeded parameters),
+    solved to the headline's residual, with the event-timed bandwidth of the BiCG matvec
+    kernel; and Table 1's row N = 256 on the example itself (20 Newton steps at tolerance
+    1e-1, tau = 1) with both linear steps."""
+    import torch
+    res = {}
+    B, N = 64, 256
+    pairs = [W.e1_family(N, W.seed_for(4, q))[:2] for q in range(B)]
+    fs = [torch.from_numpy(f).cuda() for f, _ in pairs]
+    gs = [torch.from_numpy(g).cuda() for _, g in pairs]
+    plan = maot.Plan(n_max=N, batch_capacity=B, damping_policy="fixed", max_newton=MAX_NEWTON,
+                     linear_solver="fd_bicg", gmres_tol=0.1)
+    plan.solve_batched(fs, gs, damping=1.0, tol=args.tol)  # warm-up
+    torch.cuda.synchronize()
+    plan.profile("bicg_matvec", 4)  # every 4th matvec launch timed with events
+    t0 = time.perf_counter()
+    _, _, reps = plan.solve_batched(fs, gs, damping=1.0, tol=args.tol)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = plan.profile_read()
+    plan.profile("none")
+    plan.close()
+    bad = sum(r["status"] != 0 or r["res_rms"] > args.tol for r in reps)
+    ach = prof["bytes"] / (prof["ms"] * 1e-3) / 1e9 if prof["ms"] > 0 else 0.0
+    res["fd_bicg_256"] = {
+        "workload": "64 pairs 256 x 256 of the Section 5.1 example family (u* = cos sin / k, k in [80, 200]; "
+                    "g = 1 + alpha cos cos, alpha in [0.1, 0.5], rho in {1, 2, 3}), zero start, tau = 1, "
+                    "finite-difference step with BiCG (tolerance 1e-1), rms residual %.0e" % args.tol,
+        "value": round((B - bad) / el, 3), "unit": "pairs/s", "unsolved": bad, "ms_per_batch": round(1e3 * el, 3),
+        "bicg_iters_per_newton": round(float(np.sum([r["gmres_iters"] for r in reps]) /
+                                             max(1, np.sum([r["newton_iters"] for r in reps]))), 2),
+        **summary(reps),
+        "roofline_matvec": {"bound": "hbm", "kernel": "k_bicg_matvec<64>", "achieved": round(ach, 1),
+                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                            "launches": prof["launches"], "timed_every": 4,
+                            "avg_launch_us": round(1e3 * prof["ms"] / max(prof["launches"], 1), 3),
+                            "bytes_per_launch": round(prof["bytes"] / max(prof["launches"], 1))}}
+    del fs, gs
+    # Table 1, row N = 256: 20 Newton steps at tolerance 1e-1 on the Section 5.1 example
+    f, g, _ = W.e1_example(N)
+    fd, gd = torch.from_numpy(f).cuda(), torch.from_numpy(g).cuda()
+    row = {"workload": "Section 5.1 example 256 x 256 (u* = 0.01 cos sin, g = 1 + 0.3 cos cos), 20 Newton "
+                       "steps, tau = 1, linear tolerance 1e-1 (Table 1's setting)"}
+    for ls in ("strain_gmres", "fd_bicg"):
+        plan = maot.Plan(n_max=N, batch_capacity=1, linear_solver=ls, gmres_tol=0.1, max_newton=20)
+        plan.solve(fd, gd, damping=1.0, tol=1e-14)  # warm-up
+        t = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, _, rep = plan.solve(fd, gd, damping=1.0, tol=1e-14)
+            torch.cuda.synchronize()
+            t.append(time.perf_counter() - t0)
+        plan.close()
+        row[ls] = {"ms_20_newton": round(1e3 * float(np.median(t)), 3), "newton_iters": rep["newton_iters"],
+                   "inner_iters_per_newton": round(rep["gmres_iters"] / max(rep["newton_iters"], 1), 2),
+                   "res_rms": rep["res_rms"]}
+    res["table1_e1_256"] = row
     return res
 
 

@@ -56,7 +56,7 @@ struct PairDesc {
   float2* H;       // n*(n/2) half spectrum after the row pass
   float2* T;       // 3*n*(n/2) column-pass outputs
   double* part;    // per-block partial sums
-  double* bv;      // 7*n*n BiCG vectors x, r, r~, p, p~, q, q~ (finite-difference step only)
+  double* bv;      // 9*n*n BiCG vectors x, r, r~, q, q~, and p, p~ twice (finite-difference step only)
 };
 
 struct PairState {
@@ -88,9 +88,10 @@ struct PairState {
   double Hm[(MA_MMAX + 1) * MA_MMAX];  // Hessenberg, column-major: Hm[j*(MMAX+1)+i]
   double cs[MA_MMAX], sn[MA_MMAX], gv[MA_MMAX + 1], y[MA_MMAX + 1], q[MA_MMAX + 1];
   // --- BiCG (finite-difference step; gm_running, gm_k, bnorm, gm_target are shared) --
-  double bi_rho, bi_alpha, bi_beta;  // r~ . r, and the current step coefficients
-  double bi_sum_p, bi_sum_pt;        // sum p, sum p~ (the row of ones of tilde A)
-  int bi_break;                      // a zero denominator: the iteration stops
+  // rho = r~ . r and the sums of p, p~ (the row of ones of tilde A), by parity of the
+  // iteration: iteration j reads slot (j - 1) & 1 and writes slot j & 1
+  double bi_rho[2], bi_sum_p[2], bi_sum_pt[2];
+  int bi_break;  // a zero denominator: the iteration stops
   int bi_pad;
 };
 

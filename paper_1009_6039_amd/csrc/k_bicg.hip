@@ -6,18 +6,22 @@
 //   A^T y = D11(a11 y) + 2 D12(a12 y) + D22(a22 y) - D1(b1 y) - D2(b2 y),
 // since the centred second differences are symmetric and the first differences
 // antisymmetric on the periodic grid.  The row of ones adds sum(p) to every entry of
-// tilde A p; that sum is carried as a scalar (sum p_{k+1} = sum r_{k+1} + beta sum p_k).
+// tilde A p; that sum is carried as a scalar (sum p_j = sum r_j + beta_j sum p_{j-1}).
 //
-// One BiCG iteration over a batch is five launches:
-//   matvec     q = tilde A p, q~ = tilde A^T p~, partial sums of p~ . q      (HBM bound)
-//   alpha      one block per pair: alpha = rho / (p~ . q), breakdown if zero
-//   update     x += alpha p, r -= alpha q, r~ -= alpha q~; partials of r~.r, r.r,
-//              sum r, sum r~                                                 (HBM bound)
-//   beta       one block per pair: convergence test ||r|| <= tol ||b||, the
-//              iteration cap, beta = rho_new / rho, the sums of the new p, p~
-//   direction  p = r + beta p, p~ = r~ + beta p~                            (HBM bound)
-// Vectors and reductions are FP64; the partial sums are folded in a fixed order, so
-// the result does not depend on the batch or the launch order.
+// BiCG iteration j over a batch is two launches:
+//   direction+matvec  every block folds the previous update's partial sums (r~.r, r.r,
+//                     sum r, sum r~), takes the convergence test ||r|| <= tol ||b|| and
+//                     beta_j = rho_j / rho_{j-1}, forms p_j = r_j + beta_j p_{j-1} (and
+//                     p~_j) over its tile and halo in LDS, writes them, and applies
+//                     tilde A and tilde A^T; partial sums of p~_j . q_j   (HBM bound)
+//   update            every block folds the p~.q partials: alpha_j = rho_j / (p~.q)
+//                     (a zero denominator stops the iteration), x += alpha p,
+//                     r -= alpha q, r~ -= alpha q~; partial sums for the next test
+//                                                                         (HBM bound)
+// p and p~ alternate between two planes by the parity of j, so that no block
+// overwrites a value another block still reads; rho and sum p alternate in the pair
+// state in the same way.  Decisions taken by every block from the same fixed-order fold
+// agree; only block 0 writes them to the state.  Vectors and reductions are FP64.
 #include "common.h"
 #include "kernels.h"
 
@@ -25,14 +29,26 @@ namespace {
 
 constexpr int BI_TY = 16;  // tile rows; a block is BI_TY x TX points, 256 threads
 
-// BiCG vector planes inside PairDesc::bv
-enum : int { BV_X = 0, BV_R = 1, BV_RT = 2, BV_P = 3, BV_PT = 4, BV_Q = 5, BV_QT = 6 };
+// BiCG vector planes inside PairDesc::bv (p, p~ in two planes each, by parity)
+enum : int { BV_X = 0, BV_R = 1, BV_RT = 2, BV_Q = 3, BV_QT = 4, BV_P0 = 5, BV_PT0 = 6, BV_P1 = 7, BV_PT1 = 8 };
+__device__ inline int bv_p(int j) { return (j & 1) ? BV_P1 : BV_P0; }
+__device__ inline int bicg_blocks_dev(int n, int tx) { return n / BI_TY * (n / tx); }
+__device__ inline int bv_pt(int j) { return (j & 1) ? BV_PT1 : BV_PT0; }
 
-__device__ inline bool bicg_live(const PairState& s) {
-  return s.phase == PH_SOLVE && s.gm_running && !s.bi_break;
+// Sums of K partials per block over nblk blocks, in a fixed order, in every thread
+template <int K>
+__device__ inline void fold_all(const double* part, int nblk, double (&t)[K]) {
+  __shared__ double scratch[4 * K];
+  __shared__ double out[K];
+  const int kinds[K] = {};
+  fold_partials<K>(part, nblk, kinds, t, scratch);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < K; ++k) out[k] = t[k];
+  __syncthreads();
+  for (int k = 0; k < K; ++k) t[k] = out[k];
 }
 
-// b = (r + translation) / tau; x = 0; r = r~ = p = p~ = b; partials of b.b and sum b
+// b = (r + translation) / tau; x = 0; r = r~ = p_0 = p~_0 = b; partials of b.b and sum b
 template <int TX>
 __global__ __launch_bounds__(256) void k_bicg_init(LaunchCtx c) {
   const int p = pair_of_block(c);
@@ -41,6 +57,7 @@ __global__ __launch_bounds__(256) void k_bicg_init(LaunchCtx c) {
   if (s.phase != PH_SOLVE) return;
   const PairDesc& d = c.desc[p];
   const long nn = (long)d.n * d.n;
+  const int nb = bicg_blocks_dev(d.n, TX);
   const double cst = s.mass_c, inv_tau = 1.0 / s.tau;
   double* bv = d.bv;
   double v[2] = {0.0, 0.0};
@@ -51,8 +68,8 @@ __global__ __launch_bounds__(256) void k_bicg_init(LaunchCtx c) {
     bv[BV_X * nn + g] = 0.0;
     bv[BV_R * nn + g] = b;
     bv[BV_RT * nn + g] = b;
-    bv[BV_P * nn + g] = b;
-    bv[BV_PT * nn + g] = b;
+    bv[BV_P0 * nn + g] = b;
+    bv[BV_PT0 * nn + g] = b;
     v[0] += b * b;
     v[1] += b;
   }
@@ -60,12 +77,12 @@ __global__ __launch_bounds__(256) void k_bicg_init(LaunchCtx c) {
   const int kinds[2] = {0, 0};
   block_reduce<2>(v, kinds, scratch);
   if (threadIdx.x == 0) {
-    d.part[(long)blockIdx.x * 2] = v[0];
-    d.part[(long)blockIdx.x * 2 + 1] = v[1];
+    d.part[nb + (long)blockIdx.x * 2] = v[0];
+    d.part[nb + (long)blockIdx.x * 2 + 1] = v[1];
   }
 }
 
-// rho_0 = b.b, the sums of p_0 = p~_0 = b, the target tol ||b||
+// rho_0 = b.b, the sums of p_0 = p~_0 = b, the target tol ||b|| (one block per pair)
 __global__ __launch_bounds__(256) void k_bicg_start(LaunchCtx c, int nblk) {
   const int p = pair_of_block(c);
   if (p < 0) return;
@@ -75,12 +92,11 @@ __global__ __launch_bounds__(256) void k_bicg_start(LaunchCtx c, int nblk) {
   __shared__ double scratch[4 * 2];
   const int kinds[2] = {0, 0};
   double t[2];
-  fold_partials<2>(d.part, nblk, kinds, t, scratch);
+  fold_partials<2>(d.part + nblk, nblk, kinds, t, scratch);
   if (threadIdx.x == 0) {
-    s.bi_rho = t[0];
-    s.bi_sum_p = t[1];
-    s.bi_sum_pt = t[1];
-    s.bi_alpha = s.bi_beta = 0.0;
+    s.bi_rho[0] = t[0];
+    s.bi_sum_p[0] = t[1];
+    s.bi_sum_pt[0] = t[1];
     s.bi_break = 0;
     s.bnorm = sqrt(t[0]);
     s.gm_target = pair_eta(s, c) * s.bnorm;
@@ -89,40 +105,84 @@ __global__ __launch_bounds__(256) void k_bicg_start(LaunchCtx c, int nblk) {
   }
 }
 
+// Iteration j >= 1: the test on r_j and the new directions, then q = tilde A p_j and
+// q~ = tilde A^T p~_j.  j = 0 applies the operators to p_0 as stored (no test, no
+// direction): the first iteration of a solve and the step entry point.
 template <int TX>
-__global__ __launch_bounds__(256) void k_bicg_matvec(LaunchCtx c) {
+__global__ __launch_bounds__(256) void k_bicg_matvec(LaunchCtx c, int j) {
   const int p = pair_of_block(c);
   if (p < 0) return;
-  const PairState& s = c.st[p];
-  if (!bicg_live(s)) return;
+  PairState& s = c.st[p];
+  // the state flags are read once per block (block 0 of this launch may be writing
+  // them), so that every wave of a block takes the same branch
+  __shared__ int go;
+  if (threadIdx.x == 0) go = s.phase != PH_SOLVE || !s.gm_running ? 0 : (s.bi_break ? 2 : 1);
+  __syncthreads();
+  if (go == 0) return;
+  if (go == 2) {  // the last update met a zero denominator: stop with x as it is
+    if (blockIdx.x == 0 && threadIdx.x == 0) s.gm_running = 0;
+    return;
+  }
   const PairDesc& d = c.desc[p];
   const int n = d.n;
   const long nn = (long)n * n;
-  count_bytes(c, 52.0, n);  // p, p~ (FP64), five FP32 coefficients read; q, q~ written
+  const int nb = bicg_blocks_dev(n, TX);
+  const int cur = j & 1, prev = cur ^ 1;
+  double beta = 0.0, S, ST;
+  if (j == 0) {
+    S = s.bi_sum_p[0];
+    ST = s.bi_sum_pt[0];
+  } else {
+    double t[4];
+    fold_all<4>(d.part + nb, nb, t);  // r~.r, r.r, sum r, sum r~ after the last update
+    const double rho = t[0], rr = t[1];
+    if (sqrt(rr) <= s.gm_target || j >= c.bicg_max || rho == 0.0 || !isfinite(rho) || !isfinite(rr)) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) s.gm_running = 0;
+      return;
+    }
+    beta = rho / s.bi_rho[prev];
+    S = t[2] + beta * s.bi_sum_p[prev];
+    ST = t[3] + beta * s.bi_sum_pt[prev];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      s.bi_rho[cur] = rho;
+      s.bi_sum_p[cur] = S;
+      s.bi_sum_pt[cur] = ST;
+    }
+  }
+  // algorithmic bytes per point: r, p, r~, p~ (FP64) and five FP32 coefficients read,
+  // p, p~, q, q~ written; j = 0 reads only p, p~ and writes only q, q~
+  count_bytes(c, j > 0 ? 84.0 : 52.0, n);
   constexpr int W = TX + 2, H = BI_TY + 2;
   __shared__ double sp[H][W], spt[H][W];
   __shared__ float sc[5][H][W];
-  __shared__ double scratch[4];
   const int tpr = n / TX;
   const int i0 = (int)(blockIdx.x / tpr) * BI_TY, j0 = (int)(blockIdx.x % tpr) * TX;
-  const double* P_ = d.bv + BV_P * nn;
-  const double* PT = d.bv + BV_PT * nn;
+  const double* Pin = d.bv + (j > 0 ? bv_p(prev) : BV_P0) * nn;
+  const double* PTin = d.bv + (j > 0 ? bv_pt(prev) : BV_PT0) * nn;
+  const double* R = d.bv + BV_R * nn;
+  const double* RT = d.bv + BV_RT * nn;
   for (int e = threadIdx.x; e < H * W; e += 256) {
     const int a = e / W, b = e % W;
     int gi = i0 + a - 1, gj = j0 + b - 1;
     gi += gi < 0 ? n : (gi >= n ? -n : 0);
     gj += gj < 0 ? n : (gj >= n ? -n : 0);
     const long g = (long)gi * n + gj;
-    sp[a][b] = P_[g];
-    spt[a][b] = PT[g];
+    if (j > 0) {
+      sp[a][b] = R[g] + beta * Pin[g];
+      spt[a][b] = RT[g] + beta * PTin[g];
+    } else {
+      sp[a][b] = Pin[g];
+      spt[a][b] = PTin[g];
+    }
 #pragma unroll
     for (int k = 0; k < 5; ++k) sc[k][a][b] = d.coef[k * nn + g];
   }
   __syncthreads();
   const double ih = (double)n, ih2 = (double)n * (double)n, hih = 0.5 * ih, hih2 = 0.5 * ih2;
-  const double S = s.bi_sum_p, ST = s.bi_sum_pt;
   double* Q = d.bv + BV_Q * nn;
   double* QT = d.bv + BV_QT * nn;
+  double* Pout = d.bv + bv_p(cur) * nn;
+  double* PTout = d.bv + bv_pt(cur) * nn;
   double v[1] = {0.0};
   for (int e = threadIdx.x; e < BI_TY * TX; e += 256) {
     const int a = e / TX + 1, b = e % TX + 1;
@@ -138,48 +198,53 @@ __global__ __launch_bounds__(256) void k_bicg_matvec(LaunchCtx c) {
                        (w(2, a, b + 1) - 2.0 * w(2, a, b) + w(2, a, b - 1)) * ih2 -
                        (w(3, a + 1, b) - w(3, a - 1, b)) * hih - (w(4, a, b + 1) - w(4, a, b - 1)) * hih + ST;
     const long g = (long)(i0 + a - 1) * n + (j0 + b - 1);
+    if (j > 0) {
+      Pout[g] = pc;
+      PTout[g] = spt[a][b];
+    }
     Q[g] = ap;
     QT[g] = atp;
     v[0] += spt[a][b] * ap;
   }
+  __shared__ double scratch[4];
   const int kinds[1] = {0};
   block_reduce<1>(v, kinds, scratch);
   if (threadIdx.x == 0) d.part[blockIdx.x] = v[0];
 }
 
-__global__ __launch_bounds__(256) void k_bicg_alpha(LaunchCtx c, int nblk) {
+// alpha_j = rho_j / (p~_j . q_j); x += alpha p_j, r -= alpha q, r~ -= alpha q~
+template <int TX>
+__global__ __launch_bounds__(256) void k_bicg_update(LaunchCtx c, int j) {
   const int p = pair_of_block(c);
   if (p < 0) return;
   PairState& s = c.st[p];
-  if (!bicg_live(s)) return;
-  const PairDesc& d = c.desc[p];
-  __shared__ double scratch[4];
-  const int kinds[1] = {0};
-  double t[1];
-  fold_partials<1>(d.part, nblk, kinds, t, scratch);
-  if (threadIdx.x == 0) {
-    const double sigma = t[0];
-    if (sigma == 0.0 || !isfinite(sigma)) s.bi_break = 1;  // breakdown: keep x as it is
-    else s.bi_alpha = s.bi_rho / sigma;
-  }
-}
-
-template <int TX>
-__global__ __launch_bounds__(256) void k_bicg_update(LaunchCtx c) {
-  const int p = pair_of_block(c);
-  if (p < 0) return;
-  const PairState& s = c.st[p];
-  if (!bicg_live(s)) return;
+  __shared__ int go;  // read once per block, as in the matvec
+  if (threadIdx.x == 0) go = s.phase == PH_SOLVE && s.gm_running && !s.bi_break;
+  __syncthreads();
+  if (!go) return;
   const PairDesc& d = c.desc[p];
   const long nn = (long)d.n * d.n;
+  const int nb = bicg_blocks_dev(d.n, TX);
+  double t[1];
+  fold_all<1>(d.part, nb, t);
+  const double sigma = t[0];
+  if (sigma == 0.0 || !isfinite(sigma)) {  // breakdown: the next launch stops the pair
+    if (blockIdx.x == 0 && threadIdx.x == 0) s.bi_break = 1;
+    return;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    s.gm_k = j + 1;
+    s.gmres_iters++;
+  }
   count_bytes(c, 72.0, d.n);  // x, p, r, q, r~, q~ read; x, r, r~ written (FP64)
-  const double al = s.bi_alpha;
+  const double al = s.bi_rho[j & 1] / sigma;
   double* bv = d.bv;
+  const double* P_ = bv + bv_p(j) * nn;
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   const long base = (long)blockIdx.x * (BI_TY * TX);
   for (int e = threadIdx.x; e < BI_TY * TX; e += 256) {
     const long g = base + e;
-    bv[BV_X * nn + g] += al * bv[BV_P * nn + g];
+    bv[BV_X * nn + g] += al * P_[g];
     const double r = bv[BV_R * nn + g] - al * bv[BV_Q * nn + g];
     const double rt = bv[BV_RT * nn + g] - al * bv[BV_QT * nn + g];
     bv[BV_R * nn + g] = r;
@@ -193,57 +258,7 @@ __global__ __launch_bounds__(256) void k_bicg_update(LaunchCtx c) {
   const int kinds[4] = {0, 0, 0, 0};
   block_reduce<4>(v, kinds, scratch);
   if (threadIdx.x == 0)
-    for (int k = 0; k < 4; ++k) d.part[(long)blockIdx.x * 4 + k] = v[k];
-}
-
-__global__ __launch_bounds__(256) void k_bicg_beta(LaunchCtx c, int nblk) {
-  const int p = pair_of_block(c);
-  if (p < 0) return;
-  PairState& s = c.st[p];
-  if (s.phase != PH_SOLVE || !s.gm_running) return;
-  if (s.bi_break) {  // (every thread reads the flag before thread 0 clears gm_running)
-    __syncthreads();
-    if (threadIdx.x == 0) s.gm_running = 0;
-    return;
-  }
-  const PairDesc& d = c.desc[p];
-  __shared__ double scratch[4 * 4];
-  const int kinds[4] = {0, 0, 0, 0};
-  double t[4];
-  fold_partials<4>(d.part, nblk, kinds, t, scratch);
-  if (threadIdx.x == 0) {
-    s.gm_k++;
-    s.gmres_iters++;
-    const double rho = t[0], rr = t[1];
-    if (sqrt(rr) <= s.gm_target || s.gm_k >= c.bicg_max || rho == 0.0 || !isfinite(rho) || !isfinite(rr)) {
-      s.gm_running = 0;
-    } else {
-      const double beta = rho / s.bi_rho;
-      s.bi_beta = beta;
-      s.bi_rho = rho;
-      s.bi_sum_p = t[2] + beta * s.bi_sum_p;
-      s.bi_sum_pt = t[3] + beta * s.bi_sum_pt;
-    }
-  }
-}
-
-template <int TX>
-__global__ __launch_bounds__(256) void k_bicg_direction(LaunchCtx c) {
-  const int p = pair_of_block(c);
-  if (p < 0) return;
-  const PairState& s = c.st[p];
-  if (!bicg_live(s)) return;
-  const PairDesc& d = c.desc[p];
-  const long nn = (long)d.n * d.n;
-  count_bytes(c, 48.0, d.n);  // r, p, r~, p~ read; p, p~ written (FP64)
-  const double be = s.bi_beta;
-  double* bv = d.bv;
-  const long base = (long)blockIdx.x * (BI_TY * TX);
-  for (int e = threadIdx.x; e < BI_TY * TX; e += 256) {
-    const long g = base + e;
-    bv[BV_P * nn + g] = bv[BV_R * nn + g] + be * bv[BV_P * nn + g];
-    bv[BV_PT * nn + g] = bv[BV_RT * nn + g] + be * bv[BV_PT * nn + g];
-  }
+    for (int k = 0; k < 4; ++k) d.part[nb + (long)blockIdx.x * 4 + k] = v[k];
 }
 
 // theta = x (kept for step halving), u += x
@@ -269,31 +284,27 @@ __global__ __launch_bounds__(256) void k_bicg_finish(LaunchCtx c) {
 int bicg_tx(int n) { return n % 64 == 0 ? 64 : (n % 32 == 0 ? 32 : 16); }
 int bicg_blocks(int n) { return n / BI_TY * (n / bicg_tx(n)); }
 
-#define MA_BICG_DISPATCH(EV, KERNEL, ...)                                  \
-  do {                                                                     \
-    const dim3 grid(bicg_blocks(n), npairs);                               \
-    switch (bicg_tx(n)) {                                                  \
+#define MA_BICG_DISPATCH(EV, KERNEL, ...)                                           \
+  do {                                                                              \
+    const dim3 grid(bicg_blocks(n), npairs);                                        \
+    switch (bicg_tx(n)) {                                                           \
       case 64: MA_LAUNCH(EV, KERNEL<64>, grid, dim3(256), st, __VA_ARGS__); break; \
       case 32: MA_LAUNCH(EV, KERNEL<32>, grid, dim3(256), st, __VA_ARGS__); break; \
       default: MA_LAUNCH(EV, KERNEL<16>, grid, dim3(256), st, __VA_ARGS__); break; \
-    }                                                                      \
+    }                                                                               \
   } while (0)
 
-// one step of the BiCG sequence for the pairs of a class; ev times the matvec only
-void launch_bicg(const LaunchCtx& c, int n, int npairs, int step, hipStream_t st, const TimedLaunch& ev) {
-  const dim3 one(1, npairs);
-  const int nb = bicg_blocks(n);
+// one step of the BiCG sequence for the pairs of a class (j: the iteration); ev times
+// the direction+matvec launch only
+void launch_bicg(const LaunchCtx& c, int n, int npairs, int step, int j, hipStream_t st, const TimedLaunch& ev) {
   const TimedLaunch none;
   switch (step) {
     case BI_INIT:
       MA_BICG_DISPATCH(none, k_bicg_init, c);
-      hipLaunchKernelGGL(k_bicg_start, one, dim3(256), 0, st, c, nb);
+      hipLaunchKernelGGL(k_bicg_start, dim3(1, npairs), dim3(256), 0, st, c, bicg_blocks(n));
       break;
-    case BI_MATVEC: MA_BICG_DISPATCH(ev, k_bicg_matvec, c); break;
-    case BI_ALPHA: hipLaunchKernelGGL(k_bicg_alpha, one, dim3(256), 0, st, c, nb); break;
-    case BI_UPDATE: MA_BICG_DISPATCH(none, k_bicg_update, c); break;
-    case BI_BETA: hipLaunchKernelGGL(k_bicg_beta, one, dim3(256), 0, st, c, nb); break;
-    case BI_DIRECTION: MA_BICG_DISPATCH(none, k_bicg_direction, c); break;
+    case BI_MATVEC: MA_BICG_DISPATCH(ev, k_bicg_matvec, c, j); break;
+    case BI_UPDATE: MA_BICG_DISPATCH(none, k_bicg_update, c, j); break;
     case BI_FINISH: MA_BICG_DISPATCH(none, k_bicg_finish, c); break;
     default: break;
   }

@@ -82,9 +82,9 @@ void launch_restart(const LaunchCtx& c, int n, int npairs, hipStream_t st);
 int power_blocks(int n);
 
 // the finite-difference BiCG step (Section 4.1), one step of its launch sequence
-enum : int { BI_INIT = 0, BI_MATVEC = 1, BI_ALPHA = 2, BI_UPDATE = 3, BI_BETA = 4, BI_DIRECTION = 5, BI_FINISH = 6 };
+enum : int { BI_INIT = 0, BI_MATVEC = 1, BI_UPDATE = 2, BI_FINISH = 3 };
 int bicg_tx(int n);
 int bicg_blocks(int n);
-void launch_bicg(const LaunchCtx& c, int n, int npairs, int step, hipStream_t st,
+void launch_bicg(const LaunchCtx& c, int n, int npairs, int step, int j, hipStream_t st,
                  const TimedLaunch& ev = TimedLaunch());
 void launch_power_vec(const LaunchCtx& c, int n, int mode, const float* b0, double* out, int k, hipStream_t st);

@@ -104,7 +104,7 @@ namespace {
 // partial-sum slots per pair: the largest need over all launch-geometry variants
 size_t part_doubles(int n) {
   size_t need = 256 * 4;
-  need = std::max(need, (size_t)bicg_blocks(n) * 4);
+  need = std::max(need, (size_t)bicg_blocks(n) * 5);
   for (int v = 0; v < MA_NVARIANTS; ++v) {
     need = std::max(need, (size_t)residual_blocks(n, v) * MA_NPART_RES);
     need = std::max(need, (size_t)passC_blocks(n, v) * (MA_MMAX + 1));
@@ -125,7 +125,7 @@ size_t pair_bytes(int n, int m, bool bicg) {
   b += align256(4 * nn);                  // H
   b += align256(12 * nn);                 // T
   b += align256(8 * part_doubles(n));     // partials
-  if (bicg) b += align256(56 * nn);       // BiCG vectors
+  if (bicg) b += align256(72 * nn);       // BiCG vectors
   return b;
 }
 
@@ -148,7 +148,7 @@ void carve(PairDesc& d, char*& p, int n, int m, bool bicg) {
   d.H = (float2*)take(4 * nn);
   d.T = (float2*)take(12 * nn);
   d.part = (double*)take(8 * part_doubles(n));
-  d.bv = bicg ? (double*)take(56 * nn) : nullptr;
+  d.bv = bicg ? (double*)take(72 * nn) : nullptr;
 }
 
 bool uses_bicg(const ma_options& o) { return o.linear_solver == MA_LINEAR_FD_BICG; }
@@ -379,9 +379,9 @@ void L_C(ma_plan* P, const Class& c, int mode, int j, hipStream_t st) {
   launch_passC(make_ctx(P, c, MA_PROF_ROW_C, t), c.n, c.count, mode, j, c.tw, st,
                prof_events(P, t ? MA_PROF_ROW_C : MA_PROF_NONE));
 }
-void L_bicg(ma_plan* P, const Class& c, int step, hipStream_t st) {
+void L_bicg(ma_plan* P, const Class& c, int step, int j, hipStream_t st) {
   const bool t = step == BI_MATVEC && prof_pick(P, MA_PROF_BICG_MATVEC);
-  launch_bicg(make_ctx(P, c, step == BI_MATVEC ? MA_PROF_BICG_MATVEC : MA_PROF_NONE, t), c.n, c.count, step, st,
+  launch_bicg(make_ctx(P, c, step == BI_MATVEC ? MA_PROF_BICG_MATVEC : MA_PROF_NONE, t), c.n, c.count, step, j, st,
               prof_events(P, t ? MA_PROF_BICG_MATVEC : MA_PROF_NONE));
 }
 
@@ -503,11 +503,8 @@ int launch_bicg_body(ma_plan* P, ClassList cls, int npairs, hipStream_t st) {
   constexpr int LAG = 2, NOALLOC_PERIOD = 16;
   for (int j = 0; j < P->opt.bicg_max_iters; ++j) {
     for (const Class& c : cls) {
-      L_bicg(P, c, BI_MATVEC, st);
-      L_bicg(P, c, BI_ALPHA, st);
-      L_bicg(P, c, BI_UPDATE, st);
-      L_bicg(P, c, BI_BETA, st);
-      L_bicg(P, c, BI_DIRECTION, st);
+      L_bicg(P, c, BI_MATVEC, j, st);
+      L_bicg(P, c, BI_UPDATE, j, st);
     }
     if (P->no_alloc) {
       if ((j + 1) % NOALLOC_PERIOD) continue;
@@ -534,10 +531,10 @@ int launch_bicg_body(ma_plan* P, ClassList cls, int npairs, hipStream_t st) {
 int linear_step(ma_plan* P, const std::vector<Class>& vsolve, int npairs, hipStream_t st) {
   const ClassList sl{vsolve.data(), (int)vsolve.size()};
   if (uses_bicg(P->opt)) {
-    for (const Class& c : vsolve) L_bicg(P, c, BI_INIT, st);
+    for (const Class& c : vsolve) L_bicg(P, c, BI_INIT, 0, st);
     int e = launch_bicg_body(P, sl, npairs, st);
     if (e) return e;
-    for (const Class& c : vsolve) L_bicg(P, c, BI_FINISH, st);
+    for (const Class& c : vsolve) L_bicg(P, c, BI_FINISH, 0, st);
     return MA_OK;
   }
   for (const Class& c : vsolve) L_A(P, c, PA_INIT, 0, st);
@@ -1390,21 +1387,22 @@ int ma_step_fd_apply(ma_plan* P, int n, const double* p, const double* pt, const
   P->opt.linear_solver = MA_LINEAR_FD_BICG;
   P->opt.precond = MA_PRECOND_NONE;
   PairState s = step_state(nullptr);
-  s.bi_sum_p = sp;
-  s.bi_sum_pt = spt;
+  s.bi_sum_p[0] = sp;
+  s.bi_sum_pt[0] = spt;
   Class c;
   int rc = step_prepare(P, n, s, st, c);
   if (!rc) {
     const PairDesc& d = P->h_desc[0];
-    if (hipMemcpyAsync(d.bv + 3 * nn, p, 8 * nn, hipMemcpyDeviceToDevice, st) != hipSuccess ||
-        hipMemcpyAsync(d.bv + 4 * nn, pt, 8 * nn, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+    // planes of PairDesc::bv: p_0, p~_0 in 5, 6; q, q~ in 3, 4
+    if (hipMemcpyAsync(d.bv + 5 * nn, p, 8 * nn, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(d.bv + 6 * nn, pt, 8 * nn, hipMemcpyDeviceToDevice, st) != hipSuccess ||
         hipMemcpyAsync(d.coef, coef, 20 * nn, hipMemcpyDeviceToDevice, st) != hipSuccess) {
       rc = MA_EHIP;
     } else {
-      launch_bicg(make_ctx(P, c), n, 1, BI_MATVEC, st);
+      launch_bicg(make_ctx(P, c), n, 1, BI_MATVEC, 0, st);
       if (hipGetLastError() != hipSuccess ||
-          hipMemcpyAsync(q, d.bv + 5 * nn, 8 * nn, hipMemcpyDeviceToDevice, st) != hipSuccess ||
-          hipMemcpyAsync(qt, d.bv + 6 * nn, 8 * nn, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+          hipMemcpyAsync(q, d.bv + 3 * nn, 8 * nn, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+          hipMemcpyAsync(qt, d.bv + 4 * nn, 8 * nn, hipMemcpyDeviceToDevice, st) != hipSuccess ||
           hipStreamSynchronize(st) != hipSuccess)
         rc = MA_EHIP;
     }
@@ -1435,7 +1433,7 @@ int ma_step_bicg(ma_plan* P, int n, const float* h, const float* coef, double to
       rc = MA_EHIP;
       break;
     }
-    launch_bicg(make_ctx(P, c), n, 1, BI_INIT, st);
+    launch_bicg(make_ctx(P, c), n, 1, BI_INIT, 0, st);
     if ((rc = launch_bicg_body(P, ClassList{&c, 1}, 1, st))) break;
     if (hipMemcpyAsync(x, d.bv, 8 * nn, hipMemcpyDeviceToDevice, st) != hipSuccess ||
         hipMemcpyAsync(P->h_state.data(), P->d_state, sizeof(PairState), hipMemcpyDeviceToHost, st) != hipSuccess ||

@@ -90,6 +90,18 @@ def e1_example(N, k=100.0, gamma=1, alpha=0.3, rho=1):
     return f, g, u
 
 
+def e1_family(N, seed):
+    """One member of the Section 5.1 family with its open parameters drawn from a
+    seeded generator: k in [80, 200] (amplitude 1/k; with one period the Hessian of u*
+    stays below 4 pi^2 / 80 < 0.5, so |x|^2/2 + u* is uniformly convex), gamma = 1,
+    alpha in [0.1, 0.5], rho in {1, 2, 3}.  Returns (f, g, u*)."""
+    rng = np.random.default_rng(seed)
+    k = float(rng.uniform(80.0, 200.0))
+    alpha = float(rng.uniform(0.1, 0.5))
+    rho = int(rng.integers(1, 4))
+    return e1_example(N, k=k, gamma=1, alpha=alpha, rho=rho)
+
+
 def _blob_density(N, rng):
     x = np.arange(N, dtype=np.float64) / N
     centres = rng.uniform(0.0, 1.0, size=(8, 2))

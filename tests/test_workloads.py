@@ -58,3 +58,15 @@ def test_e1_example_mass_is_that_of_g():
         f, g, u = W.e1_example(64, **kw)
         assert abs(np.mean(f) - 1.0) < 1e-12 and abs(np.mean(g) - 1.0) < 1e-12
         assert np.all(f > 0)
+
+
+def test_e1_family_members_are_valid_and_seeded():
+    # positive densities of equal mass, a convex potential, different members per seed
+    a = W.e1_family(64, W.seed_for(4, 0))
+    b = W.e1_family(64, W.seed_for(4, 0))
+    c = W.e1_family(64, W.seed_for(4, 1))
+    assert all(np.array_equal(x, y) for x, y in zip(a, b))
+    assert not np.array_equal(a[0], c[0])
+    for f, g, u in (a, c):
+        assert f.min() > 0 and g.min() > 0
+        assert abs(f.mean() - g.mean()) < 1e-3 * g.mean()

@@ -52,6 +52,27 @@ def test_noalloc_solve_matches_plan_solve_on_two_calls(maot):
             assert rep_a[k] == rep_b[k], k
 
 
+def test_noalloc_fd_bicg_solve_matches_plan_solve_on_two_calls(maot):
+    # the finite-difference BiCG step (its vectors carved from the same static array;
+    # the host drains the stream every 16 BiCG iterations instead of polling a summary)
+    opts = dict(linear_solver="fd_bicg", damping_policy="backtrack", gmres_tol=0.1, max_newton=300)
+    for n, q in ((128, 2), (64, 3)):
+        f, g = W.blobs(n, W.seed_for(1, q))
+        print("noalloc fd-bicg: n = %d, pair seed %d" % (n, W.seed_for(1, q)), flush=True)
+        fd, gd = dev(f), dev(g)
+        psi_a, _, rep_a = maot.solve_noalloc(fd, gd, damping=1.0, tol=1e-8, **opts)
+        plan = maot.Plan(n_max=n, batch_capacity=1, **opts)
+        try:
+            psi_b, _, rep_b = plan.solve(fd, gd, damping=1.0, tol=1e-8)
+        finally:
+            plan.close()
+        torch.cuda.synchronize()
+        assert rep_a["status"] == 0 and rep_b["status"] == 0 and rep_a["res_rms"] <= 1e-8
+        assert torch.equal(psi_a, psi_b)
+        for k in ("newton_iters", "gmres_iters", "backtracks", "res_rms"):
+            assert rep_a[k] == rep_b[k], k
+
+
 def test_noalloc_rejects_sizes_beyond_its_array(maot):
     f = torch.ones((768, 768), dtype=torch.float64, device="cuda")
     with pytest.raises(maot.MAError) as e:
