@@ -95,6 +95,32 @@ __host__ __device__ constexpr int pick_radix(int rem) {
   return (rem % 3 == 0) ? 3 : (rem == 16 ? 4 : (rem % 8 == 0 ? 8 : (rem % 4 == 0 ? 4 : 2)));
 }
 
+// One more than the largest twiddle-table index a length-N transform reads: a stage
+// of radix R after sub-length NS > 1 reads tw[m k TWS], k < NS, TWS = N / (NS R), with
+// m up to 4 (R = 8), 2 (R = 4, 3) or 1 (R = 2).
+__host__ __device__ constexpr int tw_span(int n) {
+  int need = 1, ns = 1;
+  while (ns < n) {
+    const int r = pick_radix(n / ns);
+    if (ns > 1) {
+      const int top = r == 8 ? 4 : (r == 2 ? 1 : 2);
+      const int idx = top * (ns - 1) * (n / (ns * r)) + 1;
+      need = need > idx ? need : idx;
+    }
+    ns *= r;
+  }
+  return need;
+}
+
+// Copies the part of the twiddle table that a length-N transform reads into LDS, so
+// that the stages read twiddles without vector-memory loads (whose in-order counter
+// would also hold every other load in flight).  The caller's barrier before its first
+// transform makes the copy visible.
+template <int N, int BLOCK>
+__device__ __forceinline__ void stage_twiddles(float2* twl, const float2* __restrict__ tw) {
+  for (int e = threadIdx.x; e < tw_span(N); e += BLOCK) twl[e] = tw[e];
+}
+
 template <int N, int NF, int LAYOUT>
 __device__ __forceinline__ int lds_index(int t, int e) {
   if constexpr (LAYOUT == LAYOUT_ROWS) return t * N + e;

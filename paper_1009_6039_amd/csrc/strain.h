@@ -293,6 +293,7 @@ __global__ __launch_bounds__((Cfg<N, G>::B_BLOCK)) void k_passB(LaunchCtx c, int
   // S: the column spectra, then rhobar * sigmahat, then each output spectrum in turn.
   // Element (row or wavenumber e, column cc) sits at e * CPB + cc.
   __shared__ float2 S[N * CPB];
+  __shared__ float2 twl[tw_span(N)];
   const int s0 = blockIdx.x * CPB;
   const auto H = gmem<const float2>(d.H);
   const auto T = gmem<float2>(d.T);
@@ -310,13 +311,14 @@ __global__ __launch_bounds__((Cfg<N, G>::B_BLOCK)) void k_passB(LaunchCtx c, int
       const int e = threadIdx.x + q * BLOCK;
       h[q] = H[(long)(e / CPB) * NH + s0 + e % CPB];
     }
+    stage_twiddles<N, BLOCK>(twl, tw);  // issued after the column loads, used after them
     if constexpr (REG1) {
-      fft_cols_from_regs<N, CPB, BLOCK, false>(S, tw, h);
+      fft_cols_from_regs<N, CPB, BLOCK, false>(S, twl, h);
     } else {
 #pragma unroll
       for (int q = 0; q < PER; ++q) S[threadIdx.x + q * BLOCK] = h[q];
       __syncthreads();
-      fft_lds<N, CPB, BLOCK, false, LAYOUT_COLS>(S, tw);
+      fft_lds<N, CPB, BLOCK, false, LAYOUT_COLS>(S, twl);
     }
   }
   if (mode == PB_FORWARD) {
@@ -374,7 +376,7 @@ __global__ __launch_bounds__((Cfg<N, G>::B_BLOCK)) void k_passB(LaunchCtx c, int
         const float2 m = c.mt[(threadIdx.x + k * BLOCK) / CPB];
         x[k] = o == 0 ? sv[k] : ((o == 1) ? times_i(m.x, sv[k]) : cscale(sv[k], m.y));
       }
-      fft_cols_from_regs<N, CPB, BLOCK, true>(S, tw, x);
+      fft_cols_from_regs<N, CPB, BLOCK, true>(S, twl, x);
     } else {
       if (oo > 0 || o != 0) {  // S still holds the plain spectrum for a lone output 0
 #pragma unroll
@@ -385,7 +387,7 @@ __global__ __launch_bounds__((Cfg<N, G>::B_BLOCK)) void k_passB(LaunchCtx c, int
         }
         __syncthreads();
       }
-      fft_lds<N, CPB, BLOCK, true, LAYOUT_COLS>(S, tw);
+      fft_lds<N, CPB, BLOCK, true, LAYOUT_COLS>(S, twl);
     }
     const auto To = T + (long)o * N * NH;
     for (int e = threadIdx.x; e < N * CPB; e += BLOCK) {
