@@ -17,6 +17,8 @@ ma       residual M(u) (eq. ma2), linearisation (eq. linearmaeq), Strain's
 fd_bicg  the finite-difference linear step of Section 4.1 (nine-point matrix, the
          augmented system of its Lemma, BiCG)
 stability the power method on the inverse of the linearised operator (Section 5.1)
+ma3d     the same damped Newton method in three dimensions (cofactors of a 3 x 3 matrix,
+         trilinear interpolation, Strain's operator with nine derived transforms)
 cnn      the warm-start network (forward, backward, Adam) in FP64
 
 Parity status per function is listed in each module header.  Every function
@@ -25,4 +27,4 @@ routine, brute force, or a value the paper prints, except where a module header
 says "parity unpinned".
 """
 
-from . import cnn, fd, fd_bicg, interp, ma  # noqa: F401
+from . import cnn, fd, fd_bicg, interp, ma, ma3d  # noqa: F401

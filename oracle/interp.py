@@ -13,8 +13,12 @@ linear interpolation is better (Section 5.3).  Readings (P4):
 
 Grid value F[i, j] sits at (i/N, j/N).
 
+  trilinear the 3-D tensor-product form of bilinear (oracle.ma3d).
+
 Pins: tests/test_oracle_interp.py (exact at nodes; reproduces x1, x2 and x1*x2
-inside the fundamental cell; periodic in y; nearest picks the closest node).
+inside the fundamental cell; periodic in y; nearest picks the closest node);
+trilinear through tests/test_oracle_ma3d.py (x3-constant data reduce to bilinear,
+and a planted swap of its weights fails).
 """
 
 import numpy as np
@@ -43,3 +47,24 @@ def nearest(F, y1, y2):
     i = np.floor(np.asarray(y1, dtype=np.float64) * N + 0.5).astype(np.int64) % N
     j = np.floor(np.asarray(y2, dtype=np.float64) * N + 0.5).astype(np.int64) % N
     return F[i, j]
+
+
+def trilinear(F, y1, y2, y3):
+    """Periodic trilinear interpolant of the 3-D grid field F at points (y1, y2, y3):
+    the tensor product of the 1-D linear interpolants, the 3-D form of reading P4."""
+    N = F.shape[0]
+    lo, hi, frac = [], [], []
+    for y in (y1, y2, y3):
+        t = np.asarray(y, dtype=np.float64) * N
+        f = np.floor(t)
+        frac.append(t - f)
+        lo.append(f.astype(np.int64) % N)
+        hi.append((f.astype(np.int64) + 1) % N)
+    out = 0.0
+    for c1 in (0, 1):
+        for c2 in (0, 1):
+            for c3 in (0, 1):
+                w = ((frac[0] if c1 else 1 - frac[0]) * (frac[1] if c2 else 1 - frac[1])
+                     * (frac[2] if c3 else 1 - frac[2]))
+                out = out + w * F[hi[0] if c1 else lo[0], hi[1] if c2 else lo[1], hi[2] if c3 else lo[2]]
+    return out

@@ -20,8 +20,10 @@ blobs(N, seed)
 smooth_noise(N, seed, sigma_px)
     f = exp(z / 2) with z white noise filtered by a unit-gain periodic Gaussian
     of width sigma_px grid cells; scaled to mean one.  Draws f, then g.
-e1_example(N, k, gamma, alpha, rho)
+e1_example(N, k, gamma, alpha, rho), e1_family(N, seed)
     the Section 5.1 family u* = (1/k) cos sin, g = 1 + alpha cos cos, f from eq. ma2.
+e1_example3(N, k, alpha, rho), blobs3(N, seed)
+    the same construction on the 3-torus, and 3-D blob densities (N x N x N).
 
 Grid convention everywhere: F[i, j] is the value at (x1, x2) = (i/N, j/N).
 """
@@ -100,6 +102,59 @@ def e1_family(N, seed):
     alpha = float(rng.uniform(0.1, 0.5))
     rho = int(rng.integers(1, 4))
     return e1_example(N, k=k, gamma=1, alpha=alpha, rho=rho)
+
+
+def grid3(N):
+    x = np.arange(N, dtype=np.float64) / N
+    return np.meshgrid(x, x, x, indexing="ij")
+
+
+def e1_example3(N, k=100.0, alpha=0.3, rho=1):
+    """(f, g, u*) of the Section 5.1 construction in three dimensions (the method is
+    stated for any dimension): u* = (1/k) cos(2 pi x1) sin(2 pi x2) cos(2 pi x3),
+    g = 1 + alpha cos(2 pi rho x1) cos(2 pi rho x2) cos(2 pi rho x3), and
+    f = g(x + grad u*) det(I + D^2 u*) in closed form."""
+    X1, X2, X3 = grid3(N)
+    tp = 2.0 * np.pi
+    a, w = 1.0 / k, tp
+    s1, c1 = np.sin(w * X1), np.cos(w * X1)
+    s2, c2 = np.sin(w * X2), np.cos(w * X2)
+    s3, c3 = np.sin(w * X3), np.cos(w * X3)
+    u = a * c1 * s2 * c3
+    u1, u2, u3 = -a * w * s1 * s2 * c3, a * w * c1 * c2 * c3, -a * w * c1 * s2 * s3
+    d = -a * w * w * c1 * s2 * c3  # u11 = u22 = u33
+    u12 = -a * w * w * s1 * c2 * c3
+    u13 = a * w * w * s1 * s2 * s3
+    u23 = -a * w * w * c1 * c2 * s3
+    m11 = m22 = m33 = 1.0 + d
+    det = (m11 * (m22 * m33 - u23 * u23) - u12 * (u12 * m33 - u23 * u13) + u13 * (u12 * u23 - m22 * u13))
+    y1, y2, y3 = X1 + u1, X2 + u2, X3 + u3
+    gy = 1.0 + alpha * np.cos(tp * rho * y1) * np.cos(tp * rho * y2) * np.cos(tp * rho * y3)
+    g = 1.0 + alpha * np.cos(tp * rho * X1) * np.cos(tp * rho * X2) * np.cos(tp * rho * X3)
+    return gy * det, g, u
+
+
+def blobs3(N, seed, count=6):
+    """(f, g): independent 3-D densities, each a 0.2 floor plus `count` periodic
+    Gaussian blobs (centres uniform, widths 0.06..0.12, weights 0.5..1.5), scaled to
+    mean one; drawn from one generator, f first."""
+    rng = np.random.default_rng(seed)
+    x = np.arange(N, dtype=np.float64) / N
+
+    def one():
+        c = rng.uniform(0.0, 1.0, size=(count, 3))
+        sg = rng.uniform(0.06, 0.12, size=count)
+        wt = rng.uniform(0.5, 1.5, size=count)
+        d = np.full((N, N, N), 0.2)
+        for b in range(count):
+            s2 = 2.0 * sg[b] ** 2
+            e = [sum(np.exp(-(x - c[b, a] - p) ** 2 / s2) for p in (-1, 0, 1)) for a in range(3)]
+            d += wt[b] * np.einsum("i,j,k->ijk", e[0], e[1], e[2])
+        return d / d.mean()
+
+    f = one()
+    g = one()
+    return f, g
 
 
 def _blob_density(N, rng):
