@@ -308,6 +308,51 @@ int ma_step_bicg(ma_plan* plan, int n, const float* h, const float* coef, double
                  double* x, int* iters, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Three dimensions.  The method is stated for any dimension d (eq. (linearmaeq) with
+ * the cofactor matrix of the d x d matrix I + D^2 u; Section 4.2 counts d(d+1) inverse
+ * transforms per product).  One pair on an N x N x N grid, h = 1/N, arrays [i][j][k]
+ * row-major with k contiguous (i <-> x1, j <-> x2, k <-> x3), N in {16, 32, 48, 64,
+ * 96, 128, 192, 256}.  g and grad g are interpolated trilinearly at x + grad u; the
+ * iterate must keep the leading minors of I + D^2 u positive (else MA_ENONCONVEX).
+ * The linear step is Strain's method with nine derived transforms (alpha_ab, six, and
+ * beta_a, three) and GMRES(m).  Options as for the 2-D solver, except that nearest
+ * interpolation, MA_PRECOND_DIAG, MA_FORCING_ADAPTIVE and MA_LINEAR_FD_BICG are not
+ * available (MA_EINVAL).  Each call synchronises `stream`.
+ * ------------------------------------------------------------------------- */
+typedef struct ma3_plan ma3_plan;
+
+/* Plan for grids up to n_max (a supported N); opt may be NULL (defaults).  The device
+ * workspace (about (172 + 4 (gmres_m + 1)) bytes per point) is allocated by the first
+ * call that needs it and kept. */
+int ma3_plan_create(int n_max, const ma_options* opt, ma3_plan** out);
+void ma3_plan_destroy(ma3_plan* plan);
+
+/* Damped Newton (eq. linma) in 3-D from u = 0: f, g N^3 FP64 positive densities
+ * (scaled to mean one inside), damping tau >= 1, tol > 0 on the rms residual.
+ * psi N^3 FP64 out (mean zero); map 3 N^3 FP64 out (x_a + D_a u, planes a = 1, 2, 3)
+ * or NULL; rep host out or NULL.  Return codes as ma_solve; MA_EINVAL for an
+ * unsupported N, N > n_max, or a density that is not positive and finite. */
+int ma3_solve(ma3_plan* plan, const double* f, const double* g, int n, double damping, double tol,
+              double* psi, double* map, ma_report* rep, void* stream);
+
+/* One residual evaluation at a given iterate: u, f, g N^3 FP64 (f and g used as
+ * given); r N^3 FP32 out (f - f_n); coef 9 N^3 FP32 out (a11, a22, a33, a12, a13, a23,
+ * b1, b2, b3; op_mode applies); scalars host out, 17 doubles: res_rms, res_max,
+ * mass_defect, min det, min (I + D^2 u)_11, min of the leading 2 x 2 minor, the nine
+ * Simpson averages in coefficient order, mean(|grad u|^2 f), mean(u). */
+int ma3_step_residual(ma3_plan* plan, int n, const double* u, const double* f, const double* g, float* r,
+                      float* coef, double* scalars, void* stream);
+
+/* Strain's operator in 3-D: w = L Lbar^{-1} v, v and w N^3 FP32, coef 9 N^3 FP32,
+ * abar host[9] (the averages Lbar uses). */
+int ma3_step_strain_apply(ma3_plan* plan, int n, const float* v, const float* coef, const double* abar,
+                          float* w, void* stream);
+
+/* theta = Lbar^{-1} sigma in 3-D (mean zero), sigma and theta N^3 FP32, abar host[9]. */
+int ma3_step_lbar_inverse(ma3_plan* plan, int n, const float* sigma, const double* abar, float* theta,
+                          void* stream);
+
+/* ---------------------------------------------------------------------------
  * Autotuner (not in the paper): launch geometry per grid size.  Each of the four
  * bandwidth-bound kernel classes (row pass A, column pass B, row pass C, residual
  * stencil) has MA_TUNE_VARIANTS compiled geometries: 0 the default, 1 half as many

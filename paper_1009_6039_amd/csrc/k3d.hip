@@ -1,0 +1,746 @@
+// The damped Newton method in three dimensions (the method is stated for any dimension
+// d; Section 4.2 counts d(d+1) inverse transforms per product): the set-up, the FP64
+// residual and coefficient kernel, Strain's operator as five line-transform passes, the
+// Arnoldi steps and their per-pair folds.
+//
+// Operator passes for a product w = L Lbar^{-1} v (complex FP32 spectra, full length):
+//   P1  along x3 (contiguous): v (real) -> forward transform -> S
+//   P2  along x2: S -> forward transform -> S (in place)
+//   P3  along x1: S -> forward transform, times rhobar(k) (Section 4.2) and the Krylov
+//       scale / N^3, then inverse transforms of Z, i k1 Z and -k1^2 Z -> T0, T1, T2
+//   P4  along x2: inverse transforms of T2, T1, i k2 T1, T0, i k2 T0, -k2^2 T0 -> U_a..U_f
+//   P5  along x3: the nine real results alpha_ab, beta_a as five complex inverse
+//       transforms (two real signals per transform: X + iY -> x + iy), the combination
+//       w = sum a_aa alpha_aa + 2 sum a_ab alpha_ab + sum b_a beta_a, the inner products
+//       <w, V_l> (partial sums per block)
+// For theta = Lbar^{-1} x only Z -> T0 -> U_d -> theta is formed.
+#include "common.h"
+#include "fft.h"
+#include "k3d.h"
+
+namespace {
+
+constexpr int LINES_ELEMS = 2048;  // complex elements per block in the x3 passes (16 KB of LDS)
+constexpr int COLS = 16;           // lines per block in the x1 / x2 passes (128-byte row segments)
+
+// the largest power of two <= max(1, lim): lines per block of the x3 passes, a divisor of
+// N^2 (N is a multiple of 16), so that the blocks cover every line exactly once
+__host__ __device__ constexpr int pow2_floor(int lim) {
+  int p = 1;
+  while (2 * p <= lim) p *= 2;
+  return p;
+}
+template <int N>
+struct Lines3 {
+  static constexpr int P1 = pow2_floor(LINES_ELEMS / N);        // P1: one transform per line
+  static constexpr int P5 = pow2_floor((LINES_ELEMS / 2) / N);  // P5: five transforms per line
+  static_assert((N * N) % P1 == 0 && (N * N) % P5 == 0, "whole lines per block");
+};
+
+__device__ __forceinline__ int wrap3(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// periodic index of an integer-valued double (|f| < 2^50), in [0, n)
+__device__ __forceinline__ int wrapf(double f, int n, double invn) {
+  int a = (int)(f - (double)n * floor(f * invn));
+  return a < 0 ? a + n : (a >= n ? a - n : a);
+}
+
+// ---------------------------------------------------------------------------
+// set-up: means of f and g, then the scaled fields and the gradient of g
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(MA3_BLOCK) void k3_sums(Desc3 d) {
+  const long nn = (long)d.n * d.n * d.n;
+  double v[4] = {0.0, 0.0, 1e300, 0.0};
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (long)gridDim.x * blockDim.x) {
+    const double a = d.f_in[e], b = d.g_in[e];
+    v[0] += a;
+    v[1] += b;
+    v[2] = fmin(v[2], fmin(a, b));
+    v[3] += (isfinite(a) && isfinite(b)) ? 0.0 : 1.0;
+  }
+  __shared__ double scratch[4 * 4];
+  const int kinds[4] = {0, 0, 1, 0};
+  block_reduce<4>(v, kinds, scratch);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 4; ++k) d.part[(long)blockIdx.x * 4 + k] = v[k];
+}
+
+__global__ __launch_bounds__(256) void k3_sums_fold(Desc3 d, State3* s, int nblk) {
+  __shared__ double scratch[4 * 4];
+  const int kinds[4] = {0, 0, 1, 0};
+  double t[4];
+  fold_partials<4>(d.part, nblk, kinds, t, scratch);
+  if (threadIdx.x == 0) {
+    const double nn = (double)d.n * d.n * d.n;
+    s->mean_f = t[0] / nn;
+    s->mean_g = t[1] / nn;
+    s->sums[0] = t[2];  // smallest density value (positive required)
+    s->sums[1] = t[3];  // non-finite values
+  }
+}
+
+__global__ __launch_bounds__(MA3_BLOCK) void k3_fields(Desc3 d, const State3* s) {
+  const int n = d.n;
+  const long nn = (long)n * n * n;
+  const double ig = 1.0 / s->mean_g, i12h = (double)n / 12.0;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (long)gridDim.x * blockDim.x) {
+    const int i = (int)(e / ((long)n * n)), j = (int)((e / n) % n), k = (int)(e % n);
+    auto G = [&](int a, int b, int c) { return d.g_in[((long)wrap3(a, n) * n + wrap3(b, n)) * n + wrap3(c, n)]; };
+    const double g1 = (G(i - 2, j, k) - 8.0 * G(i - 1, j, k) + 8.0 * G(i + 1, j, k) - G(i + 2, j, k)) * i12h * ig;
+    const double g2 = (G(i, j - 2, k) - 8.0 * G(i, j - 1, k) + 8.0 * G(i, j + 1, k) - G(i, j + 2, k)) * i12h * ig;
+    const double g3 = (G(i, j, k - 2) - 8.0 * G(i, j, k - 1) + 8.0 * G(i, j, k + 1) - G(i, j, k + 2)) * i12h * ig;
+    d.gg[e] = make_float4((float)g1, (float)g2, (float)g3, 0.f);
+    d.g[e] = d.g_in[e] * ig;
+    d.f[e] = d.f_in[e] / s->mean_f;
+    d.u[e] = 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// residual and coefficients (eq. ma2, eq. linearmaeq in 3-D; Section 4)
+// ---------------------------------------------------------------------------
+__device__ constexpr double W1[5] = {1.0 / 12.0, -8.0 / 12.0, 0.0, 8.0 / 12.0, -1.0 / 12.0};
+
+__global__ __launch_bounds__(MA3_BLOCK) void k3_res(Desc3 d, int op_mode) {
+  const int n = d.n;
+  const long nn = (long)n * n * n;
+  const double N = (double)n, invn = 1.0 / N, h1 = N, h2 = N * N;
+  double acc[MA3_NPART];
+  for (int k = 0; k < 14; ++k) acc[k] = 0.0;
+  acc[14] = acc[15] = acc[16] = 1e300;
+  acc[17] = -1e300;
+  acc[18] = 1e300;
+  acc[19] = 0.0;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (long)gridDim.x * blockDim.x) {
+    const int i = (int)(e / ((long)n * n)), j = (int)((e / n) % n), k = (int)(e % n);
+    auto U = [&](int a, int b, int c) { return d.u[((long)wrap3(a, n) * n + wrap3(b, n)) * n + wrap3(c, n)]; };
+    const double u0 = d.u[e];
+    // first and second derivatives along each axis, fourth order
+    double g[3], s2[3];
+    for (int a = 0; a < 3; ++a) {
+      const int di = a == 0, dj = a == 1, dk = a == 2;
+      const double m2 = U(i - 2 * di, j - 2 * dj, k - 2 * dk), m1 = U(i - di, j - dj, k - dk);
+      const double p1 = U(i + di, j + dj, k + dk), p2 = U(i + 2 * di, j + 2 * dj, k + 2 * dk);
+      g[a] = (m2 - 8.0 * m1 + 8.0 * p1 - p2) * (h1 / 12.0);
+      s2[a] = (-m2 + 16.0 * m1 - 30.0 * u0 + 16.0 * p1 - p2) * (h2 / 12.0);
+    }
+    // mixed derivatives: the first-derivative formula along a applied to the one along b
+    double mx[3];
+    const int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2};
+    for (int q = 0; q < 3; ++q) {
+      double outer = 0.0;
+      for (int sa = -2; sa <= 2; ++sa) {
+        if (sa == 0) continue;
+        double inner = 0.0;
+        for (int sb = -2; sb <= 2; ++sb) {
+          if (sb == 0) continue;
+          int o[3] = {0, 0, 0};
+          o[pa[q]] = sa;
+          o[pb[q]] = sb;
+          inner += W1[sb + 2] * U(i + o[0], j + o[1], k + o[2]);
+        }
+        outer += W1[sa + 2] * (inner * h1);
+      }
+      mx[q] = outer * h1;
+    }
+    // g and grad g at y = x + grad u, trilinear and periodic
+    const double y[3] = {i * invn + g[0], j * invn + g[1], k * invn + g[2]};
+    int lo[3], hi[3];
+    double fr[3];
+    for (int a = 0; a < 3; ++a) {
+      const double t = y[a] * N, fl = floor(t);
+      fr[a] = t - fl;
+      lo[a] = wrapf(fl, n, invn);
+      hi[a] = lo[a] + 1 == n ? 0 : lo[a] + 1;
+    }
+    double gy = 0.0, gy1 = 0.0, gy2 = 0.0, gy3 = 0.0;
+    for (int c1 = 0; c1 < 2; ++c1)
+      for (int c2 = 0; c2 < 2; ++c2)
+        for (int c3 = 0; c3 < 2; ++c3) {
+          const double w = (c1 ? fr[0] : 1.0 - fr[0]) * (c2 ? fr[1] : 1.0 - fr[1]) * (c3 ? fr[2] : 1.0 - fr[2]);
+          const long idx = ((long)(c1 ? hi[0] : lo[0]) * n + (c2 ? hi[1] : lo[1])) * n + (c3 ? hi[2] : lo[2]);
+          const float4 gr = d.gg[idx];
+          gy = gy + w * d.g[idx];
+          gy1 = gy1 + w * (double)gr.x;
+          gy2 = gy2 + w * (double)gr.y;
+          gy3 = gy3 + w * (double)gr.z;
+        }
+    // det and cofactors of M = I + D^2 u
+    const double m11 = 1.0 + s2[0], m22 = 1.0 + s2[1], m33 = 1.0 + s2[2];
+    const double m12 = mx[0], m13 = mx[1], m23 = mx[2];
+    const double c11 = m22 * m33 - m23 * m23, c22 = m11 * m33 - m13 * m13, c33 = m11 * m22 - m12 * m12;
+    const double c12 = m13 * m23 - m12 * m33, c13 = m12 * m23 - m13 * m22, c23 = m12 * m13 - m11 * m23;
+    const double det = m11 * c11 + m12 * c12 + m13 * c13;
+    const double fn = gy * det;
+    const double rr = d.f[e] - fn;
+    d.r[e] = (float)rr;
+    double cf[9] = {gy * c11, gy * c22, gy * c33, gy * c12, gy * c13, gy * c23, 0.0, 0.0, 0.0};
+    if (op_mode == 0) {
+      cf[6] = det * gy1;
+      cf[7] = det * gy2;
+      cf[8] = det * gy3;
+    }
+    // periodic Simpson weights (2/3 at even, 4/3 at odd indices, times 1/N per axis)
+    const double ws = ((i & 1) ? 4.0 : 2.0) * ((j & 1) ? 4.0 : 2.0) * ((k & 1) ? 4.0 : 2.0) / (27.0 * N * N * N);
+    for (int q = 0; q < 9; ++q) {
+      d.coef[q * nn + e] = (float)cf[q];
+      acc[3 + q] += ws * cf[q];
+    }
+    acc[0] += fn;
+    acc[1] += rr;
+    acc[2] += rr * rr;
+    acc[12] += (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) * d.f[e];
+    acc[13] += u0;
+    acc[14] = fmin(acc[14], det);
+    acc[15] = fmin(acc[15], m11);
+    acc[16] = fmin(acc[16], m11 * m22 - m12 * m12);
+    acc[17] = fmax(acc[17], rr);
+    acc[18] = fmin(acc[18], rr);
+    acc[19] += isfinite(rr) ? 0.0 : 1.0;
+  }
+  __shared__ double scratch[4 * MA3_NPART];
+  const int kinds[MA3_NPART] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 2, 1, 0};
+  block_reduce<MA3_NPART>(acc, kinds, scratch);
+  if (threadIdx.x == 0)
+    for (int q = 0; q < MA3_NPART; ++q) d.part[(long)blockIdx.x * MA3_NPART + q] = acc[q];
+}
+
+__global__ __launch_bounds__(256) void k3_res_fold(Desc3 d, State3* s, int nblk) {
+  __shared__ double scratch[4 * MA3_NPART];
+  const int kinds[MA3_NPART] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 2, 1, 0};
+  double t[MA3_NPART];
+  fold_partials<MA3_NPART>(d.part, nblk, kinds, t, scratch);
+  if (threadIdx.x == 0) {
+    for (int q = 0; q < MA3_NPART; ++q) s->sums[q] = t[q];
+    for (int q = 0; q < 9; ++q) s->abar[q] = t[3 + q];
+    s->mass_c = t[0] / ((double)d.n * d.n * d.n) - 1.0;
+  }
+}
+
+__global__ __launch_bounds__(MA3_BLOCK) void k3_upd(Desc3 d, double a) {
+  const long nn = (long)d.n * d.n * d.n;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (long)gridDim.x * blockDim.x)
+    d.u[e] += a * d.theta[e];
+}
+
+// psi = u - mean(u); map = x + D_h u (fourth order), unwrapped
+__global__ __launch_bounds__(MA3_BLOCK) void k3_out(Desc3 d, const State3* s, double* psi, double* map) {
+  const int n = d.n;
+  const long nn = (long)n * n * n;
+  const double mu = s->sums[13] / (double)nn, i12h = (double)n / 12.0, h = 1.0 / n;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (long)gridDim.x * blockDim.x) {
+    const int i = (int)(e / ((long)n * n)), j = (int)((e / n) % n), k = (int)(e % n);
+    psi[e] = d.u[e] - mu;
+    if (map) {
+      auto U = [&](int a, int b, int c) { return d.u[((long)wrap3(a, n) * n + wrap3(b, n)) * n + wrap3(c, n)]; };
+      map[e] = i * h + (U(i - 2, j, k) - 8.0 * U(i - 1, j, k) + 8.0 * U(i + 1, j, k) - U(i + 2, j, k)) * i12h;
+      map[nn + e] = j * h + (U(i, j - 2, k) - 8.0 * U(i, j - 1, k) + 8.0 * U(i, j + 1, k) - U(i, j + 2, k)) * i12h;
+      map[2 * nn + e] = k * h + (U(i, j, k - 2) - 8.0 * U(i, j, k - 1) + 8.0 * U(i, j, k + 1) - U(i, j, k + 2)) * i12h;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Arnoldi bookkeeping (one thread): as in the 2-D solver's GMRES(m) with Givens
+// rotations, on the 3-D state
+// ---------------------------------------------------------------------------
+__device__ void arnoldi_close3(State3& s, int jn, double wnorm2) {
+  const int j = jn - 1;
+  double* col = &s.Hm[j * (MA3_MMAX + 1)];
+  const double hn = sqrt(fmax(wnorm2, 0.0));
+  col[jn] = hn;
+  s.vscale[jn] = hn > 0.0 ? 1.0 / hn : 0.0;
+  for (int i = 0; i < j; ++i) {
+    const double a = col[i], b = col[i + 1];
+    col[i] = s.cs[i] * a + s.sn[i] * b;
+    col[i + 1] = -s.sn[i] * a + s.cs[i] * b;
+  }
+  const double den = hypot(col[j], col[j + 1]);
+  s.cs[j] = den > 0.0 ? col[j] / den : 1.0;
+  s.sn[j] = den > 0.0 ? col[j + 1] / den : 0.0;
+  col[j] = den;
+  col[j + 1] = 0.0;
+  s.gv[jn] = -s.sn[j] * s.gv[j];
+  s.gv[j] = s.cs[j] * s.gv[j];
+  s.gmres_iters++;
+  const bool conv = fabs(s.gv[jn]) <= s.gm_target || hn == 0.0;
+  if (!(conv || jn >= s.m)) return;
+  const int k = jn;
+  for (int i = k - 1; i >= 0; --i) {
+    double t = s.gv[i];
+    for (int l = i + 1; l < k; ++l) t -= s.Hm[l * (MA3_MMAX + 1) + i] * s.y[l];
+    const double di = s.Hm[i * (MA3_MMAX + 1) + i];
+    s.y[i] = di != 0.0 ? t / di : 0.0;
+  }
+  s.gm_k = k;
+  s.gm_running = 0;
+  if (!conv && s.gm_cycle < s.max_restarts) {
+    for (int l = 0; l <= k; ++l) s.q[l] = 0.0;
+    s.q[k] = s.gv[k];
+    for (int i = k - 1; i >= 0; --i) {
+      const double a = s.q[i], b = s.q[i + 1];
+      s.q[i] = s.cs[i] * a - s.sn[i] * b;
+      s.q[i + 1] = s.sn[i] * a + s.cs[i] * b;
+    }
+    for (int l = 0; l <= k; ++l) s.q[l] *= s.vscale[l];
+    for (int l = 0; l < k; ++l) s.y[l] *= s.vscale[l];
+    const double beta = fabs(s.gv[k]);
+    s.gv[0] = beta;
+    s.vscale[0] = beta > 0.0 ? 1.0 / beta : 0.0;
+    s.gm_restart = 1;
+  } else {
+    for (int l = 0; l < k; ++l) s.y[l] *= s.vscale[l];
+    s.gm_restart = 0;
+  }
+}
+
+// Krylov vector build, with the per-block partial sums of its square
+__global__ __launch_bounds__(MA3_BLOCK) void k3_vec(Desc3 d, const State3* s, int mode, int jn) {
+  const bool run = mode == V3_INIT ? true : (mode == V3_ARNOLDI ? (bool)s->gm_running : true);
+  if (!run) return;
+  __shared__ float cf[MA3_MMAX + 1];
+  int nv = 0;
+  if (mode == V3_ARNOLDI) nv = jn;
+  else if (mode == V3_RECOVER) nv = s->gm_k;
+  if (threadIdx.x < nv)
+    cf[threadIdx.x] = mode == V3_ARNOLDI ? (float)(s->Hm[(jn - 1) * (MA3_MMAX + 1) + threadIdx.x] * s->vscale[threadIdx.x])
+                                         : (float)s->y[threadIdx.x];
+  __syncthreads();
+  const long nn = (long)d.n * d.n * d.n;
+  const float cst = (float)s->mass_c, itau = (float)(1.0 / s->tau);
+  const bool usex = mode == V3_RECOVER && s->gm_cycle > 0;
+  double acc = 0.0;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (long)gridDim.x * blockDim.x) {
+    float v;
+    if (mode == V3_INIT) {
+      v = (d.r[e] + cst) * itau;
+      d.V[e] = v;
+    } else if (mode == V3_ARNOLDI) {
+      v = d.V[(long)jn * nn + e];
+      for (int l = 0; l < nv; ++l) v -= cf[l] * d.V[(long)l * nn + e];
+      d.V[(long)jn * nn + e] = v;
+    } else {  // recovery: x = (x of earlier cycles) + sum y_l V_l
+      v = usex ? d.x[e] : 0.f;
+      for (int l = 0; l < nv; ++l) v += cf[l] * d.V[(long)l * nn + e];
+      d.x[e] = v;
+    }
+    acc += (double)v * v;
+  }
+  __shared__ double scratch[4];
+  double t[1] = {acc};
+  const int kinds[1] = {0};
+  block_reduce<1>(t, kinds, scratch);
+  if (threadIdx.x == 0) d.part[blockIdx.x] = t[0];
+}
+
+// the fold after k3_vec: the right-hand side's norm (init) or ||w'|| and the rotations
+__global__ __launch_bounds__(256) void k3_vec_fold(Desc3 d, State3* s, int mode, int jn, int nblk) {
+  if (mode == V3_ARNOLDI && !s->gm_running) return;
+  __shared__ double scratch[4];
+  const int kinds[1] = {0};
+  double t[1];
+  fold_partials<1>(d.part, nblk, kinds, t, scratch);
+  if (threadIdx.x != 0) return;
+  if (mode == V3_INIT) {
+    const double bn = sqrt(fmax(t[0], 0.0));
+    s->bnorm = bn;
+    s->gm_target = s->gmres_tol * bn;
+    s->gm_running = bn > 0.0;
+    s->gm_restart = 0;
+    s->gm_cycle = 0;
+    s->gm_k = 0;
+    s->vscale[0] = bn > 0.0 ? 1.0 / bn : 0.0;
+    s->gv[0] = bn;
+  } else if (mode == V3_ARNOLDI) {
+    arnoldi_close3(*s, jn, t[0]);
+  }
+}
+
+// x += sum y_l V_l and V0 = the cycle's residual; then the next cycle begins
+__global__ __launch_bounds__(MA3_BLOCK) void k3_rst(Desc3 d, const State3* s) {
+  __shared__ float cy[MA3_MMAX + 1], cq[MA3_MMAX + 1];
+  const int k = s->gm_k;
+  const bool usex = s->gm_cycle > 0;
+  if (threadIdx.x <= k) {
+    cy[threadIdx.x] = threadIdx.x < k ? (float)s->y[threadIdx.x] : 0.f;
+    cq[threadIdx.x] = (float)s->q[threadIdx.x];
+  }
+  __syncthreads();
+  const long nn = (long)d.n * d.n * d.n;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (long)gridDim.x * blockDim.x) {
+    float xs = usex ? d.x[e] : 0.f, r0 = 0.f;
+    for (int l = 0; l <= k; ++l) {
+      const float v = d.V[(long)l * nn + e];
+      xs += cy[l] * v;
+      r0 += cq[l] * v;
+    }
+    d.x[e] = xs;
+    d.V[e] = r0;
+  }
+}
+
+__global__ void k3_cycle_begin(State3* s) {
+  if (threadIdx.x == 0 && s->gm_restart) {
+    s->gm_running = 1;
+    s->gm_restart = 0;
+    s->gm_cycle++;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// line-transform passes
+// ---------------------------------------------------------------------------
+// P1: real input along x3 -> complex forward transform -> S.  Input: V[j] (matvec) or x.
+template <int N>
+__global__ __launch_bounds__(MA3_BLOCK) void k3_p1(Desc3 d, const State3* s, int mode, int j) {
+  if (mode == P3_MATVEC && !s->gm_running) return;
+  constexpr int R = Lines3<N>::P1;  // lines per block
+  __shared__ float2 L[R * N];
+  const long nn = (long)N * N * N;
+  const float* in = mode == P3_MATVEC ? d.V + (long)j * nn : d.x;
+  const long base = (long)blockIdx.x * R * N;
+  for (int e = threadIdx.x; e < R * N; e += MA3_BLOCK) L[e] = make_float2(in[base + e], 0.f);
+  __syncthreads();
+  fft_lds<N, R, MA3_BLOCK, false, LAYOUT_ROWS>(L, d.tw);
+  for (int e = threadIdx.x; e < R * N; e += MA3_BLOCK) d.S[base + e] = L[e];
+}
+
+// P2: forward transform along x2, in place; a block takes COLS consecutive x3 indices
+// of one x1 plane
+template <int N>
+__global__ __launch_bounds__(MA3_BLOCK) void k3_p2(Desc3 d, const State3* s, int mode) {
+  if (mode == P3_MATVEC && !s->gm_running) return;
+  constexpr int C = COLS < N ? COLS : N;
+  __shared__ float2 L[N * C];
+  const int i = blockIdx.x / (N / C), k0 = (blockIdx.x % (N / C)) * C;
+  for (int e = threadIdx.x; e < N * C; e += MA3_BLOCK) {
+    const int jj = e / C, t = e % C;
+    L[e] = d.S[((long)i * N + jj) * N + k0 + t];
+  }
+  __syncthreads();
+  fft_lds<N, C, MA3_BLOCK, false, LAYOUT_COLS>(L, d.tw);
+  for (int e = threadIdx.x; e < N * C; e += MA3_BLOCK) {
+    const int jj = e / C, t = e % C;
+    d.S[((long)i * N + jj) * N + k0 + t] = L[e];
+  }
+}
+
+// rhobar(k) for wavenumber indices (q1, q2, q3): the inverse symbol of the averaged
+// operator, zero where it vanishes (k = 0)
+__device__ __forceinline__ float2 rhobar3(int q1, int q2, int q3, const float (&ab)[9], const float2* mt) {
+  const float2 m1 = mt[q1], m2 = mt[q2], m3 = mt[q3];
+  // S = sum a_aa d2(k_a) + 2 sum_{a<b} a_ab (i d1(k_a))(i d1(k_b)) + i sum b_a d1(k_a)
+  const float re = ab[0] * m1.y + ab[1] * m2.y + ab[2] * m3.y -
+                   2.f * (ab[3] * m1.x * m2.x + ab[4] * m1.x * m3.x + ab[5] * m2.x * m3.x);
+  const float im = ab[6] * m1.x + ab[7] * m2.x + ab[8] * m3.x;
+  const float den = re * re + im * im;
+  if ((q1 == 0 && q2 == 0 && q3 == 0) || den == 0.f) return make_float2(0.f, 0.f);
+  return make_float2(re / den, -im / den);
+}
+
+// P3: forward transform along x1, times rhobar and the scale, inverse transforms of
+// Z, i k1 Z, -k1^2 Z -> T0, T1, T2 (theta: Z -> T0 only).  A block takes COLS
+// consecutive x3 indices of one x2 row.
+template <int N>
+__global__ __launch_bounds__(MA3_BLOCK) void k3_p3(Desc3 d, const State3* s, int mode, int j) {
+  if (mode == P3_MATVEC && !s->gm_running) return;
+  constexpr int C = COLS < N ? COLS : N;
+  constexpr long NN = (long)N * N * N;
+  __shared__ float2 L[N * C];
+  const int jj = blockIdx.x / (N / C), k0 = (blockIdx.x % (N / C)) * C;
+  for (int e = threadIdx.x; e < N * C; e += MA3_BLOCK) {
+    const int i = e / C, t = e % C;
+    L[e] = d.S[((long)i * N + jj) * N + k0 + t];
+  }
+  __syncthreads();
+  fft_lds<N, C, MA3_BLOCK, false, LAYOUT_COLS>(L, d.tw);
+  float ab[9];
+  for (int q = 0; q < 9; ++q) ab[q] = (float)s->abar[q];
+  const float scale = (float)((mode == P3_MATVEC ? s->vscale[j] : 1.0) / ((double)N * N * N));
+  // Z = rhobar * spectrum * scale, kept in registers (each thread its own elements)
+  constexpr int PER = (N * C + MA3_BLOCK - 1) / MA3_BLOCK;
+  float2 z[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = threadIdx.x + q * MA3_BLOCK;
+    z[q] = make_float2(0.f, 0.f);
+    if (e < N * C) {
+      const int i = e / C, t = e % C;
+      const float2 rb = rhobar3(i, jj, k0 + t, ab, d.mt);
+      z[q] = cscale(cmul(rb, L[e]), scale);
+    }
+  }
+  const int outs = mode == P3_MATVEC ? 3 : 1;
+  for (int o = 0; o < outs; ++o) {
+    __syncthreads();  // the previous transform's results have been stored
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = threadIdx.x + q * MA3_BLOCK;
+      if (e < N * C) {
+        const float2 m = d.mt[e / C];
+        // o = 0: Z; o = 1: i d1(k1) Z; o = 2: d2(k1) Z
+        L[e] = o == 0 ? z[q] : (o == 1 ? make_float2(-m.x * z[q].y, m.x * z[q].x) : cscale(z[q], m.y));
+      }
+    }
+    __syncthreads();
+    fft_lds<N, C, MA3_BLOCK, true, LAYOUT_COLS>(L, d.tw);
+    float2* T = d.T + (long)o * NN;
+    for (int e = threadIdx.x; e < N * C; e += MA3_BLOCK) {
+      const int i = e / C, t = e % C;
+      T[((long)i * N + jj) * N + k0 + t] = L[e];
+    }
+  }
+}
+
+// P4: inverse transforms along x2 of T2, T1, i k2 T1, T0, i k2 T0, -k2^2 T0 -> U_a..U_f
+// (theta: T0 -> U_d only).  A block takes COLS consecutive x3 indices of one x1 plane.
+template <int N>
+__global__ __launch_bounds__(MA3_BLOCK) void k3_p4(Desc3 d, const State3* s, int mode) {
+  if (mode == P3_MATVEC && !s->gm_running) return;
+  constexpr int C = COLS < N ? COLS : N;
+  constexpr long NN = (long)N * N * N;
+  __shared__ float2 L[N * C];
+  const int i = blockIdx.x / (N / C), k0 = (blockIdx.x % (N / C)) * C;
+  // (source T plane, multiplier: 0 one, 1 i d1(k2), 2 d2(k2), destination U plane)
+  const int plan[6][3] = {{2, 0, 0}, {1, 0, 1}, {1, 1, 2}, {0, 0, 3}, {0, 1, 4}, {0, 2, 5}};
+  const int first = mode == P3_MATVEC ? 0 : 3, last = mode == P3_MATVEC ? 6 : 4;
+  for (int o = first; o < last; ++o) {
+    const float2* T = d.T + (long)plan[o][0] * NN;
+    for (int e = threadIdx.x; e < N * C; e += MA3_BLOCK) {
+      const int jj = e / C, t = e % C;
+      const float2 v = T[((long)i * N + jj) * N + k0 + t];
+      const float2 m = d.mt[jj];
+      L[e] = plan[o][1] == 0 ? v : (plan[o][1] == 1 ? make_float2(-m.x * v.y, m.x * v.x) : cscale(v, m.y));
+    }
+    __syncthreads();
+    fft_lds<N, C, MA3_BLOCK, true, LAYOUT_COLS>(L, d.tw);
+    float2* Uo = d.U + (long)plan[o][2] * NN;
+    for (int e = threadIdx.x; e < N * C; e += MA3_BLOCK) {
+      const int jj = e / C, t = e % C;
+      Uo[((long)i * N + jj) * N + k0 + t] = L[e];
+    }
+    __syncthreads();  // the stores have read L before the next transform overwrites it
+  }
+}
+
+// P5: along x3, the nine real results as five complex inverse transforms, then the
+// combination and the inner products (matvec), or theta and u += theta.  A block takes
+// R5 whole x3 lines.
+template <int N>
+__global__ __launch_bounds__(MA3_BLOCK) void k3_p5(Desc3 d, const State3* s, int mode, int j) {
+  if (mode == P3_MATVEC && !s->gm_running) return;
+  constexpr long NN = (long)N * N * N;
+  constexpr int R5 = Lines3<N>::P5;  // lines per block
+  constexpr int NT = 5;              // transforms per line
+  __shared__ float2 L[NT * R5 * N];
+  __shared__ double red[(MA3_BLOCK / 64) * (MA3_MMAX + 1)];
+  const long base = (long)blockIdx.x * R5 * N;  // first element of the block's lines
+  if (mode != P3_MATVEC) {
+    const float2* Ud = d.U + 3 * NN;
+    for (int e = threadIdx.x; e < R5 * N; e += MA3_BLOCK) L[e] = Ud[base + e];
+    __syncthreads();
+    fft_lds<N, R5, MA3_BLOCK, true, LAYOUT_ROWS>(L, d.tw);
+    for (int e = threadIdx.x; e < R5 * N; e += MA3_BLOCK) {
+      const double th = (double)L[e].x;
+      if (mode == P3_THETA) {
+        d.theta[base + e] = th;
+        d.u[base + e] += th;
+      } else {
+        d.x[base + e] = L[e].x;
+      }
+    }
+    return;
+  }
+  // transform t of line l at L[(t * R5 + l) * N + k]:
+  //   0: U_a + i U_b        -> alpha11, beta1
+  //   1: U_c + i (i d1 U_b) -> alpha12, alpha13
+  //   2: U_f + i U_e        -> alpha22, beta2
+  //   3: i d1 U_e + i d2 U_d -> alpha23, alpha33
+  //   4: i d1 U_d           -> beta3
+  for (int e = threadIdx.x; e < R5 * N; e += MA3_BLOCK) {
+    const int l = e / N, k = e % N;
+    const long g = base + e;
+    const float2 ua = d.U[g], ub = d.U[NN + g], uc = d.U[2 * NN + g], ud = d.U[3 * NN + g];
+    const float2 ue = d.U[4 * NN + g], uf = d.U[5 * NN + g];
+    const float2 m = d.mt[k];
+    const float2 ib = make_float2(-m.x * ub.y, m.x * ub.x);  // i d1(k3) U_b
+    const float2 ie = make_float2(-m.x * ue.y, m.x * ue.x);
+    const float2 id = make_float2(-m.x * ud.y, m.x * ud.x);
+    const float2 qd = cscale(ud, m.y);
+    // X + i Y for spectra X, Y of real signals
+    L[(0 * R5 + l) * N + k] = make_float2(ua.x - ub.y, ua.y + ub.x);
+    L[(1 * R5 + l) * N + k] = make_float2(uc.x - ib.y, uc.y + ib.x);
+    L[(2 * R5 + l) * N + k] = make_float2(uf.x - ue.y, uf.y + ue.x);
+    L[(3 * R5 + l) * N + k] = make_float2(ie.x - qd.y, ie.y + qd.x);
+    L[(4 * R5 + l) * N + k] = id;
+  }
+  __syncthreads();
+  fft_lds<N, NT * R5, MA3_BLOCK, true, LAYOUT_ROWS>(L, d.tw);
+  float* W = d.V + (long)(j + 1) * NN;
+  constexpr int PER = (R5 * N + MA3_BLOCK - 1) / MA3_BLOCK;
+  float w[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = threadIdx.x + q * MA3_BLOCK;
+    w[q] = 0.f;
+    if (e >= R5 * N) continue;
+    const int l = e / N, k = e % N;
+    const long g = base + e;
+    const float2 z0 = L[(0 * R5 + l) * N + k], z1 = L[(1 * R5 + l) * N + k], z2 = L[(2 * R5 + l) * N + k];
+    const float2 z3 = L[(3 * R5 + l) * N + k], z4 = L[(4 * R5 + l) * N + k];
+    const float* cf = d.coef;
+    // a11 a11 + a22 a22 + a33 a33 + 2 (a12 a12 + a13 a13 + a23 a23) + b . beta
+    const float v = cf[g] * z0.x + cf[NN + g] * z2.x + cf[2 * NN + g] * z3.y +
+                    2.f * (cf[3 * NN + g] * z1.x + cf[4 * NN + g] * z1.y + cf[5 * NN + g] * z3.x) +
+                    cf[6 * NN + g] * z0.y + cf[7 * NN + g] * z2.y + cf[8 * NN + g] * z4.x;
+    W[g] = v;
+    w[q] = v;
+  }
+  // inner products <w, V_l>, l <= j, per block (fixed order); folded by k3_dots_fold
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int lv = 0; lv <= j; ++lv) {
+    const float* Vl = d.V + (long)lv * NN;
+    float acc = 0.f;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = threadIdx.x + q * MA3_BLOCK;
+      if (e < R5 * N) acc += w[q] * Vl[base + e];
+    }
+    const double v = wave_sum((double)acc);
+    if (lane == 0) red[wid * (MA3_MMAX + 1) + lv] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x <= j) {
+    double t = 0.0;
+    for (int ww = 0; ww < MA3_BLOCK / 64; ++ww) t += red[ww * (MA3_MMAX + 1) + threadIdx.x];
+    d.part[(long)blockIdx.x * (MA3_MMAX + 1) + threadIdx.x] = t;
+  }
+}
+
+// h[l][j] = <w, v_l> from the P5 partials (one block)
+__global__ __launch_bounds__(256) void k3_dots_fold(Desc3 d, State3* s, int j, int nblk) {
+  if (!s->gm_running) return;
+  __shared__ double red[8][32];
+  const int l = threadIdx.x & 31, grp = threadIdx.x >> 5;
+  double t = 0.0;
+  if (l <= j)
+    for (int b = grp; b < nblk; b += 8) t += d.part[(long)b * (MA3_MMAX + 1) + l];
+  red[grp][l] = t;
+  __syncthreads();
+  if (threadIdx.x <= j) {
+    double u = 0.0;
+    for (int g2 = 0; g2 < 8; ++g2) u += red[g2][threadIdx.x];
+    s->Hm[j * (MA3_MMAX + 1) + threadIdx.x] = u * s->vscale[threadIdx.x];
+  }
+}
+
+template <int N>
+void forward_rest_n(const Desc3& d, State3* s, int mode, hipStream_t st) {
+  constexpr int C = COLS < N ? COLS : N;
+  hipLaunchKernelGGL(k3_p2<N>, dim3(N * (N / C)), dim3(MA3_BLOCK), 0, st, d, s, mode);
+}
+
+template <int N>
+void first_pass_n(const Desc3& d, State3* s, int mode, int j, hipStream_t st) {
+  constexpr int R = Lines3<N>::P1;
+  hipLaunchKernelGGL(k3_p1<N>, dim3((N * N) / R), dim3(MA3_BLOCK), 0, st, d, s, mode, j);
+}
+
+template <int N>
+void inverse_n(const Desc3& d, State3* s, int mode, int j, hipStream_t st) {
+  constexpr int C = COLS < N ? COLS : N;
+  constexpr int R5 = Lines3<N>::P5;
+  hipLaunchKernelGGL(k3_p3<N>, dim3(N * (N / C)), dim3(MA3_BLOCK), 0, st, d, s, mode, j);
+  hipLaunchKernelGGL(k3_p4<N>, dim3(N * (N / C)), dim3(MA3_BLOCK), 0, st, d, s, mode);
+  hipLaunchKernelGGL(k3_p5<N>, dim3((N * N) / R5), dim3(MA3_BLOCK), 0, st, d, s, mode, j);
+  if (mode == P3_MATVEC)
+    hipLaunchKernelGGL(k3_dots_fold, dim3(1), dim3(256), 0, st, d, s, j, (N * N) / R5);
+}
+
+#define MA3_FOR_EACH_N(X) X(16) X(32) X(48) X(64) X(96) X(128) X(192) X(256)
+
+}  // namespace
+
+bool n3_supported(int n) {
+  switch (n) {
+#define X(NV) case NV:
+    MA3_FOR_EACH_N(X)
+#undef X
+    return true;
+    default:
+      return false;
+  }
+}
+
+int k3_blocks(int n) {
+  const long b = (long)n * n * n / (MA3_BLOCK * 4);
+  return b < 1 ? 1 : (int)(b > 8192 ? 8192 : b);
+}
+
+int k3_dot_blocks(int n) { return n * n / pow2_floor((LINES_ELEMS / 2) / n); }
+
+void k3_setup(const Desc3& d, State3* s, bool scale, hipStream_t st) {
+  const int nb = k3_blocks(d.n);
+  if (scale) {
+    hipLaunchKernelGGL(k3_sums, dim3(nb), dim3(MA3_BLOCK), 0, st, d);
+    hipLaunchKernelGGL(k3_sums_fold, dim3(1), dim3(256), 0, st, d, s, nb);
+  }
+  hipLaunchKernelGGL(k3_fields, dim3(nb), dim3(MA3_BLOCK), 0, st, d, s);
+}
+
+void k3_residual(const Desc3& d, State3* s, int op_mode, hipStream_t st) {
+  const int nb = k3_blocks(d.n);
+  hipLaunchKernelGGL(k3_res, dim3(nb), dim3(MA3_BLOCK), 0, st, d, op_mode);
+  hipLaunchKernelGGL(k3_res_fold, dim3(1), dim3(256), 0, st, d, s, nb);
+}
+
+void k3_update(const Desc3& d, double a, hipStream_t st) {
+  hipLaunchKernelGGL(k3_upd, dim3(k3_blocks(d.n)), dim3(MA3_BLOCK), 0, st, d, a);
+}
+
+void k3_outputs(const Desc3& d, const State3* s, double* psi, double* map, hipStream_t st) {
+  hipLaunchKernelGGL(k3_out, dim3(k3_blocks(d.n)), dim3(MA3_BLOCK), 0, st, d, s, psi, map);
+}
+
+void k3_vector(const Desc3& d, State3* s, int mode, int jn, hipStream_t st) {
+  const int nb = k3_blocks(d.n);
+  hipLaunchKernelGGL(k3_vec, dim3(nb), dim3(MA3_BLOCK), 0, st, d, s, mode, jn);
+  if (mode == V3_INIT || mode == V3_ARNOLDI)
+    hipLaunchKernelGGL(k3_vec_fold, dim3(1), dim3(256), 0, st, d, s, mode, jn, nb);
+}
+
+void k3_restart(const Desc3& d, State3* s, hipStream_t st) {
+  hipLaunchKernelGGL(k3_rst, dim3(k3_blocks(d.n)), dim3(MA3_BLOCK), 0, st, d, s);
+  hipLaunchKernelGGL(k3_cycle_begin, dim3(1), dim3(64), 0, st, s);
+}
+
+// the first pass: mode P3_* with the input V[j] (matvec) or x
+void k3_forward_rest(const Desc3& d, State3* s, int mode, hipStream_t st) {
+  switch (d.n) {
+#define X(NV) \
+  case NV: forward_rest_n<NV>(d, s, mode, st); break;
+    MA3_FOR_EACH_N(X)
+#undef X
+    default: break;
+  }
+}
+
+void k3_first_pass(const Desc3& d, State3* s, int mode, int j, hipStream_t st) {
+  switch (d.n) {
+#define X(NV) \
+  case NV: first_pass_n<NV>(d, s, mode, j, st); break;
+    MA3_FOR_EACH_N(X)
+#undef X
+    default: break;
+  }
+}
+
+void k3_inverse(const Desc3& d, State3* s, int mode, int j, hipStream_t st) {
+  switch (d.n) {
+#define X(NV) \
+  case NV: inverse_n<NV>(d, s, mode, j, st); break;
+    MA3_FOR_EACH_N(X)
+#undef X
+    default: break;
+  }
+}

@@ -32,6 +32,8 @@ EXPORTED = ("ma_abi_version", "ma_options_default", "ma_strerror", "ma_plan_crea
             "ma_plan_autotune", "ma_plan_set_tuning", "ma_plan_get_tuning", "ma_tune_geometry",
             "ma_step_residual", "ma_step_fft2", "ma_step_strain_apply",
             "ma_step_lbar_inverse", "ma_step_gmres", "ma_power_inverse", "ma_step_fd_apply", "ma_step_bicg",
+            "ma3_plan_create", "ma3_plan_destroy", "ma3_solve", "ma3_step_residual", "ma3_step_strain_apply",
+            "ma3_step_lbar_inverse",
             "ma_cnn_create", "ma_cnn_destroy", "ma_cnn_param_count", "ma_cnn_set_params",
             "ma_cnn_get_params", "ma_cnn_prepare_input", "ma_cnn_target", "ma_cnn_forward",
             "ma_cnn_gradients", "ma_cnn_train_step", "ma_cnn_warm_start")
@@ -128,6 +130,12 @@ def load():
                                      ctypes.POINTER(I), P]
     lib.ma_step_fd_apply.argtypes = [P, I, P, P, P, P, P, P]
     lib.ma_step_bicg.argtypes = [P, I, P, P, D, I, P, ctypes.POINTER(I), P]
+    lib.ma3_plan_create.argtypes = [I, ctypes.POINTER(Options), ctypes.POINTER(P)]
+    lib.ma3_plan_destroy.argtypes = [P]
+    lib.ma3_solve.argtypes = [P, P, P, I, D, D, P, P, ctypes.POINTER(Report), P]
+    lib.ma3_step_residual.argtypes = [P, I, P, P, P, P, P, ctypes.POINTER(D), P]
+    lib.ma3_step_strain_apply.argtypes = [P, I, P, P, ctypes.POINTER(D), P, P]
+    lib.ma3_step_lbar_inverse.argtypes = [P, I, P, ctypes.POINTER(D), P, P]
     F, L = ctypes.c_float, ctypes.c_long
     lib.ma_cnn_create.argtypes = [I, I, I, I, ctypes.POINTER(I), ctypes.POINTER(P)]
     lib.ma_cnn_destroy.argtypes = [P]
@@ -390,6 +398,68 @@ class Plan:
         _check(load().ma_power_inverse(self._h, n, _ptr(coef), ab, _ptr(b0), int(iters), float(gmres_tol), int(m),
                                        int(max_restarts), rho, its, _stream()), "ma_power_inverse")
         return list(rho), list(its)
+
+
+class Plan3:
+    """Owns one ma3_plan: the damped Newton solver on N x N x N grids."""
+
+    def __init__(self, n_max=64, **opts):
+        lib = load()
+        self.options = make_options(**opts)
+        h = ctypes.c_void_p()
+        _check(lib.ma3_plan_create(int(n_max), ctypes.byref(self.options), ctypes.byref(h)), "ma3_plan_create")
+        self._h = h
+
+    def close(self):
+        if self._h:
+            load().ma3_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, f, g, damping=1.0, tol=1e-6, want_map=True):
+        f = _dev(f, torch.float64)
+        g = _dev(g, torch.float64)
+        n = f.shape[0]
+        psi = torch.empty_like(f)
+        mp = torch.empty((3,) + tuple(f.shape), dtype=torch.float64, device=f.device) if want_map else None
+        rep = Report()
+        code = load().ma3_solve(self._h, _ptr(f), _ptr(g), n, float(damping), float(tol), _ptr(psi), _ptr(mp),
+                                ctypes.byref(rep), _stream())
+        if code < 0:
+            raise MAError(code, "ma3_solve")
+        return psi, mp, rep.as_dict()
+
+    def step_residual(self, u, f, g):
+        u, f, g = (_dev(t, torch.float64) for t in (u, f, g))
+        n = u.shape[0]
+        r = torch.empty(u.shape, dtype=torch.float32, device=u.device)
+        coef = torch.empty((9,) + tuple(u.shape), dtype=torch.float32, device=u.device)
+        sc = (ctypes.c_double * 17)()
+        _check(load().ma3_step_residual(self._h, n, _ptr(u), _ptr(f), _ptr(g), _ptr(r), _ptr(coef), sc, _stream()),
+               "ma3_step_residual")
+        return r, coef, list(sc)
+
+    def step_strain_apply(self, v, coef, abar):
+        v = _dev(v, torch.float32)
+        coef = _dev(coef, torch.float32)
+        w = torch.empty_like(v)
+        ab = (ctypes.c_double * 9)(*[float(a) for a in abar])
+        _check(load().ma3_step_strain_apply(self._h, v.shape[0], _ptr(v), _ptr(coef), ab, _ptr(w), _stream()),
+               "ma3_step_strain_apply")
+        return w
+
+    def step_lbar_inverse(self, sigma, abar):
+        sigma = _dev(sigma, torch.float32)
+        th = torch.empty_like(sigma)
+        ab = (ctypes.c_double * 9)(*[float(a) for a in abar])
+        _check(load().ma3_step_lbar_inverse(self._h, sigma.shape[0], _ptr(sigma), ab, _ptr(th), _stream()),
+               "ma3_step_lbar_inverse")
+        return th
 
 
 class WarmStartNet:

@@ -14,7 +14,7 @@ LIB = os.path.join(ROOT, "paper_1009_6039_amd", "libmaot.so")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(ma_[a-z0-9_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(ma3?_[a-z0-9_]+)\s*\(", text)))
 
 
 @pytest.fixture(scope="module")
