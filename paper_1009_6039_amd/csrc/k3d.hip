@@ -617,19 +617,31 @@ __global__ __launch_bounds__(MA3_BLOCK) void k3_p5(Desc3 d, const State3* s, int
   }
 }
 
-// h[l][j] = <w, v_l> from the P5 partials (one block)
-__global__ __launch_bounds__(256) void k3_dots_fold(Desc3 d, State3* s, int j, int nblk) {
+// h[l][j] = <w, v_l> from the P5 partials (one block of 1024 threads): lane l of group g
+// sums blocks g, g + 32, ... with four independent accumulators, then the groups are
+// summed in order (a fixed order throughout)
+__global__ __launch_bounds__(1024) void k3_dots_fold(Desc3 d, State3* s, int j, int nblk) {
   if (!s->gm_running) return;
-  __shared__ double red[8][32];
+  __shared__ double red[32][32];
   const int l = threadIdx.x & 31, grp = threadIdx.x >> 5;
   double t = 0.0;
-  if (l <= j)
-    for (int b = grp; b < nblk; b += 8) t += d.part[(long)b * (MA3_MMAX + 1) + l];
+  if (l <= j) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int b = grp;
+    for (; b + 96 < nblk; b += 128) {
+      a0 += d.part[(long)b * (MA3_MMAX + 1) + l];
+      a1 += d.part[(long)(b + 32) * (MA3_MMAX + 1) + l];
+      a2 += d.part[(long)(b + 64) * (MA3_MMAX + 1) + l];
+      a3 += d.part[(long)(b + 96) * (MA3_MMAX + 1) + l];
+    }
+    for (; b < nblk; b += 32) a0 += d.part[(long)b * (MA3_MMAX + 1) + l];
+    t = (a0 + a1) + (a2 + a3);
+  }
   red[grp][l] = t;
   __syncthreads();
   if (threadIdx.x <= j) {
     double u = 0.0;
-    for (int g2 = 0; g2 < 8; ++g2) u += red[g2][threadIdx.x];
+    for (int g2 = 0; g2 < 32; ++g2) u += red[g2][threadIdx.x];
     s->Hm[j * (MA3_MMAX + 1) + threadIdx.x] = u * s->vscale[threadIdx.x];
   }
 }
@@ -654,7 +666,7 @@ void inverse_n(const Desc3& d, State3* s, int mode, int j, hipStream_t st) {
   hipLaunchKernelGGL(k3_p4<N>, dim3(N * (N / C)), dim3(MA3_BLOCK), 0, st, d, s, mode);
   hipLaunchKernelGGL(k3_p5<N>, dim3((N * N) / R5), dim3(MA3_BLOCK), 0, st, d, s, mode, j);
   if (mode == P3_MATVEC)
-    hipLaunchKernelGGL(k3_dots_fold, dim3(1), dim3(256), 0, st, d, s, j, (N * N) / R5);
+    hipLaunchKernelGGL(k3_dots_fold, dim3(1), dim3(1024), 0, st, d, s, j, (N * N) / R5);
 }
 
 #define MA3_FOR_EACH_N(X) X(16) X(32) X(48) X(64) X(96) X(128) X(192) X(256)
