@@ -362,8 +362,10 @@ int ma3_step_lbar_inverse(ma3_plan* plan, int n, const float* sigma, const doubl
  * 64 columns with the stencil rows in registers and no LDS tile); 4..7 the
  * wave-owned transforms, where each wavefront runs whole transforms in a padded LDS
  * region of its own with wave-level synchronisation only (row pass C: one or two row
- * pairs per block, n >= 128).  A variant that coincides with a smaller index is
- * skipped; its geometry query returns that index.
+ * pairs per block, n >= 128; its variants 6 and 7 are instead the block geometries 0
+ * and 3 with the coefficient loads issued before the transforms and the twiddles read
+ * from LDS).  A variant that coincides with a smaller index is skipped; its geometry
+ * query returns that index.
  * ------------------------------------------------------------------------- */
 #define MA_TUNE_VARIANTS 8
 #define MA_TUNE_SLOTS 8  /* room for the per-variant times below */

@@ -1,7 +1,8 @@
 // Pass C of Strain's operator: instantiations for every grid size and launch-geometry
 // variant, the launcher and the geometry query used by the autotuner.  Variants 0..3
 // are the block-shared kernels (Cfg), 4 and 5 the wave-owned kernels with one and two
-// row pairs per block (n >= 128), 6 and 7 duplicates of 4.
+// row pairs per block (n >= 128), 6 and 7 the block-shared kernels of variants 0 and 3
+// that load the combination's coefficients before the transforms.
 #include "strain.h"
 
 #define MA_VARIANT_CASES(NV) X(NV, 0) X(NV, 1) X(NV, 2) X(NV, 3)
@@ -10,9 +11,9 @@ namespace {
 // LDS of the wave-owned kernel: five padded transforms per row pair
 constexpr bool wave_fits(int n, int ppb) { return 5L * ppb * (n + n / 8) * 8 <= 65536; }
 
-// row pairs per block of wave-owned variant v (4..7), 0 where it is not offered
+// row pairs per block of wave-owned variant v (4, 5), 0 where it is not offered
 int wave_ppb(int n, int v) {
-  if (n < 128 || v < 4 || v > 7) return 0;
+  if (n < 128 || v < 4 || v > 5) return 0;
   const int ppb = v == 5 ? 2 : 1;
   return wave_fits(n, ppb) ? ppb : 0;
 }
@@ -23,16 +24,24 @@ void launch_wave(const LaunchCtx& c, int npairs, int mode, int j, const float2* 
   if constexpr (wave_fits(N, PPB))
     MA_LAUNCH(ev, (k_passC_w<N, PPB>), dim3(N / 2 / PPB, npairs), dim3(320 * PPB), st, c, mode, j, tw);
 }
+
+// variants 6 and 7: block-shared geometry 0 or 3, coefficients loaded first
+int prefetch_base(int v) { return v == 6 ? 0 : 3; }
 }  // namespace
 
 int passC_geometry(int n, int v, int* units, int* threads) {
+  if (v == 6 || v == 7) {
+    const int c = passC_geometry(n, prefetch_base(v), units, threads);
+    if (c < 0) return -1;
+    return c == 0 ? 6 : v;  // variant 3 with the geometry of 0: a duplicate of 6
+  }
   if (v >= 4 && v < MA_NVARIANTS) {
     if (!fft_size_supported(n)) return -1;
     const int ppb = wave_ppb(n, v);
     if (ppb == 0) return passC_geometry(n, 0, units, threads) < 0 ? -1 : 0;
     *units = ppb;
     *threads = 320 * ppb;
-    return (v == 6 || v == 7) ? 4 : v;
+    return v;
   }
   switch (n * 4 + v) {
 #define X(NV, VV)                                           \
@@ -74,12 +83,18 @@ void launch_passC_only(const LaunchCtx& c, int n, int npairs, int mode, int j, c
     }
     return;
   }
-  const int v = c.var[2] >= 4 ? 0 : c.var[2];
+  const bool pf = c.var[2] == 6 || c.var[2] == 7;
+  const int v = pf ? prefetch_base(c.var[2]) : (c.var[2] >= 4 ? 0 : c.var[2]);
   switch (n * 4 + v) {
 #define X(NV, VV)                                                                                        \
   case NV * 4 + VV:                                                                                      \
-    MA_LAUNCH(ev, (k_passC<NV, Canon<NV, VV>::C>), dim3(NV / 2 / Cfg<NV, VV>::C_PPB, npairs),            \
-              dim3(Cfg<NV, VV>::C_BLOCK), st, c, mode, j, tw);                                    \
+    if (pf) {                                                                                            \
+      if constexpr (VV == 0 || VV == 3)                                                                  \
+        MA_LAUNCH(ev, (k_passC<NV, Canon<NV, VV>::C, true>), dim3(NV / 2 / Cfg<NV, VV>::C_PPB, npairs),  \
+                  dim3(Cfg<NV, VV>::C_BLOCK), st, c, mode, j, tw);                                \
+    } else                                                                                               \
+      MA_LAUNCH(ev, (k_passC<NV, Canon<NV, VV>::C>), dim3(NV / 2 / Cfg<NV, VV>::C_PPB, npairs),          \
+                dim3(Cfg<NV, VV>::C_BLOCK), st, c, mode, j, tw);                                  \
     break;
 #define Y(NV) MA_VARIANT_CASES(NV)
     MA_FOR_EACH_N(Y)

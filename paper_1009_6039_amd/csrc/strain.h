@@ -398,42 +398,58 @@ __global__ __launch_bounds__((Cfg<N, G>::B_BLOCK)) void k_passB(LaunchCtx c, int
   }
 }
 
+// The coefficients at the thread's points of the block's row pairs (all loads issued
+// together, with no branch) and the points' offsets; a point past the end takes the
+// block's first point (in bounds) and is never used.
+template <int N, int PPB, int BLOCK>
+struct PassCCoef {
+  static constexpr int PER = (PPB * N + BLOCK - 1) / BLOCK;
+  float ca[PER][5], cb[PER][5];
+  int ea[PER];
+};
+template <int N, int PPB, int BLOCK>
+__device__ __forceinline__ void passC_load_coef(const PairDesc& d, int row0, PassCCoef<N, PPB, BLOCK>& k5) {
+  constexpr long NN = (long)N * N;
+  constexpr int PER = PassCCoef<N, PPB, BLOCK>::PER;
+  constexpr bool FULL = (PPB * N) % BLOCK == 0;
+  const auto coef = gmem<const float>(d.coef);
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = threadIdx.x + q * BLOCK;
+    const bool in = FULL || e < PPB * N;
+    const int pp = in ? e / N : 0, jj = in ? e % N : 0;
+    k5.ea[q] = (row0 + 2 * pp) * N + jj;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      k5.ca[q][k] = coef[k * NN + k5.ea[q]];
+      k5.cb[q][k] = coef[k * NN + k5.ea[q] + N];
+    }
+  }
+}
+
 // Pass C's epilogue: w = a11 alpha11 + 2 a12 alpha12 + a22 alpha22 + b1 beta1 + b2 beta2 at
 // the block's points (left-scaled if the option is on), stored as V[j+1], and the
 // block's partial inner products <w, v_l>, l <= j, for k_dots_finalize.  zat(pp, t, jj)
 // is element jj of derived transform t of the block's row pair pp: t = 0 alpha11 + i
 // beta1 of row a, 1 alpha12 + i beta2 of row a, 2 and 3 the same for row b, 4 alpha22 of
 // row a (.x) and row b (.y).  The caller synchronises the block before the call.
+// k5: the coefficients at the thread's points (passC_load_coef).
 template <int N, int PPB, int BLOCK, class ZAT>
 __device__ __forceinline__ void passC_combine(const LaunchCtx& c, const PairDesc& d, const PairState& s, int j,
-                                              int row0, double* red, ZAT zat) {
+                                              int row0, double* red, ZAT zat,
+                                              const PassCCoef<N, PPB, BLOCK>& k5) {
   constexpr long NN = (long)N * N;
   const auto V = gmem<float>(d.V);
   const auto W = V + (long)(j + 1) * NN;
-  const auto coef = gmem<const float>(d.coef);
   const bool scaled = c.precond == MA_PRECOND_DIAG;
   const float trbar = (float)(s.abar[0] + s.abar[2]);
   // w at the thread's points, then the inner products <w, v_l>
-  constexpr int PER = (PPB * N + BLOCK - 1) / BLOCK;
+  constexpr int PER = PassCCoef<N, PPB, BLOCK>::PER;
   constexpr bool FULL = (PPB * N) % BLOCK == 0;
   float wa[PER], wb[PER];
-  int ea_[PER];  // offset of the first row's point; a point past the end reads the
-                 // block's first point (in bounds) with weight zero
-  // the coefficients at all of the thread's points are loaded before the first is used
-  float ca[PER][5], cb[PER][5];
-#pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int e = threadIdx.x + q * BLOCK;
-    ea_[q] = row0 * N;
-    if (!FULL && e >= PPB * N) continue;
-    const int pp = e / N, jj = e % N;
-    ea_[q] = (row0 + 2 * pp) * N + jj;
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      ca[q][k] = coef[k * NN + ea_[q]];
-      cb[q][k] = coef[k * NN + ea_[q] + N];
-    }
-  }
+  const auto& ca = k5.ca;
+  const auto& cb = k5.cb;
+  const auto& ea_ = k5.ea;
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int e = threadIdx.x + q * BLOCK;
@@ -497,7 +513,10 @@ __device__ __forceinline__ void passC_combine(const LaunchCtx& c, const PairDesc
 // ---------------------------------------------------------------------------
 // pass C (rows)
 // ---------------------------------------------------------------------------
-template <int N, int G>
+// PF: the coefficients of the combination are loaded right after the spectra, before
+// the transforms, and the transforms read their twiddles from an LDS copy (so that no
+// vector-memory wait inside them holds the coefficient loads back)
+template <int N, int G, bool PF = false>
 __global__ __launch_bounds__((Cfg<N, G>::C_BLOCK)) void k_passC(LaunchCtx c, int mode, int j,
                                                            const float2* __restrict__ tw) {
   constexpr int PPB = Cfg<N, G>::C_PPB, BLOCK = Cfg<N, G>::C_BLOCK, NH = N / 2;
@@ -554,15 +573,19 @@ __global__ __launch_bounds__((Cfg<N, G>::C_BLOCK)) void k_passC(LaunchCtx c, int
 
   // five complex inverse transforms per row pair; every spectrum load of the thread
   // is issued before the first LDS write
+  __shared__ float2 twl[PF ? tw_span(N) : 1];
+  if constexpr (PF) stage_twiddles<N, BLOCK>(twl, tw);
   constexpr int IT1 = (PPB * NH + BLOCK - 1) / BLOCK;
   constexpr bool FULL1 = (PPB * NH) % BLOCK == 0;
-  float2 tl[IT1][6];
+  float2 tl[IT1][7];  // three spectra of each row, the multipliers at k
+  const float d2n = c.mt[NH].y;
 #pragma unroll
   for (int q = 0; q < IT1; ++q) {
     const int e = threadIdx.x + q * BLOCK;
     if (!FULL1 && e >= PPB * NH) continue;
     const int pp = e / NH, k = e % NH;
     const long ia = (long)(row0 + 2 * pp) * NH + k, ib = ia + NH;
+    tl[q][6] = c.mt[k];
     tl[q][0] = T0[ia];
     tl[q][1] = T1[ia];
     tl[q][2] = T2[ia];
@@ -570,6 +593,8 @@ __global__ __launch_bounds__((Cfg<N, G>::C_BLOCK)) void k_passC(LaunchCtx c, int
     tl[q][4] = T1[ib];
     tl[q][5] = T2[ib];
   }
+  PassCCoef<N, PPB, BLOCK> pre;
+  if constexpr (PF) passC_load_coef<N, PPB, BLOCK>(d, row0, pre);
 #pragma unroll
   for (int q = 0; q < IT1; ++q) {
     const int e = threadIdx.x + q * BLOCK;
@@ -581,7 +606,6 @@ __global__ __launch_bounds__((Cfg<N, G>::C_BLOCK)) void k_passC(LaunchCtx c, int
     if (k == 0) {
       // DC (.x) and Nyquist (.y) are real; the first-derivative multiplier vanishes at
       // both, the second-derivative one at DC
-      const float d2n = c.mt[NH].y;
       L[0] = make_float2(t2a.x, t1a.x);
       L[NH] = make_float2(t2a.y, t1a.y);
       L[N] = make_float2(0.f, 0.f);
@@ -593,7 +617,7 @@ __global__ __launch_bounds__((Cfg<N, G>::C_BLOCK)) void k_passC(LaunchCtx c, int
       L[4 * N] = make_float2(0.f, 0.f);
       L[4 * N + NH] = make_float2(d2n * t0a.y, d2n * t0b.y);
     } else {
-      const float2 m = c.mt[k];
+      const float2 m = tl[q][6];
       put_pair<N>(L, k, t2a, t1a);
       put_pair<N>(L + N, k, times_i(m.x, t1a), times_i(m.x, t0a));
       put_pair<N>(L + 2 * N, k, t2b, t1b);
@@ -602,9 +626,11 @@ __global__ __launch_bounds__((Cfg<N, G>::C_BLOCK)) void k_passC(LaunchCtx c, int
     }
   }
   __syncthreads();
-  fft_lds<N, 5 * PPB, BLOCK, true, LAYOUT_ROWS>(lds, tw);
+  fft_lds<N, 5 * PPB, BLOCK, true, LAYOUT_ROWS>(lds, PF ? twl : tw);
+  // the coefficients at all of the thread's points are loaded before the first is used
+  if constexpr (!PF) passC_load_coef<N, PPB, BLOCK>(d, row0, pre);
   passC_combine<N, PPB, BLOCK>(c, d, s, j, row0, red,
-                               [&](int pp, int t, int jj) { return lds[(5 * pp + t) * N + jj]; });
+                               [&](int pp, int t, int jj) { return lds[(5 * pp + t) * N + jj]; }, pre);
 }
 
 // Pass C with wave-owned transforms: 5 PPB waves per block, wave (pp, t) builds derived
@@ -713,8 +739,10 @@ __global__ __launch_bounds__(320 * PPB) void k_passC_w(LaunchCtx c, int mode, in
   wave_sync();
   wfft<N, true>(L, tw, lane);
   __syncthreads();
+  PassCCoef<N, PPB, BLOCK> k5;
+  passC_load_coef<N, PPB, BLOCK>(d, row0, k5);
   passC_combine<N, PPB, BLOCK>(c, d, s, j, row0, red,
-                               [&](int q, int tt, int jj) { return lds[(5 * q + tt) * WB + wpad(jj)]; });
+                               [&](int q, int tt, int jj) { return lds[(5 * q + tt) * WB + wpad(jj)]; }, k5);
 }
 
 // region stride of a block's wave-owned transforms: at least the padded length, and

@@ -65,6 +65,7 @@ class Tuning(ctypes.Structure):
 
 TUNE_PASSES = ("row_a", "column", "row_c", "residual")
 TUNE_VARIANTS = 8  # MA_TUNE_VARIANTS: 0..3 block-shared kernels, 4..7 wave-owned transforms
+                   # (row pass C: 4, 5 wave-owned; 6, 7 block-shared with early coefficient loads)
 
 
 def tune_geometry(kernel_class, n, variant):
