@@ -28,6 +28,7 @@
 namespace {
 
 constexpr int BI_TY = 16;  // tile rows; a block is BI_TY x TX points, 256 threads
+static_assert(BI_TY * 16 % 256 == 0, "whole points per thread in the elementwise kernels");
 
 // BiCG vector planes inside PairDesc::bv (p, p~ in two planes each, by parity)
 enum : int { BV_X = 0, BV_R = 1, BV_RT = 2, BV_Q = 3, BV_QT = 4, BV_P0 = 5, BV_PT0 = 6, BV_P1 = 7, BV_PT1 = 8 };
@@ -128,6 +129,36 @@ __global__ __launch_bounds__(256) void k_bicg_matvec(LaunchCtx c, int j) {
   const long nn = (long)n * n;
   const int nb = bicg_blocks_dev(n, TX);
   const int cur = j & 1, prev = cur ^ 1;
+  constexpr int W = TX + 2, H = BI_TY + 2, NLD = (H * W + 255) / 256;
+  const int tpr = n / TX;
+  const int i0 = (int)(blockIdx.x / tpr) * BI_TY, j0 = (int)(blockIdx.x % tpr) * TX;
+  // every load of the tile and its halo is issued before the fold below (a slot past
+  // the tile reloads the tile's first point and is never stored; for j = 0 the r loads
+  // repeat the p loads)
+  const auto bv = gmem<double>(d.bv);
+  const auto coef = gmem<const float>(d.coef);
+  const auto Pin = bv + (j > 0 ? bv_p(prev) : BV_P0) * nn;
+  const auto PTin = bv + (j > 0 ? bv_pt(prev) : BV_PT0) * nn;
+  const auto R = j > 0 ? bv + BV_R * nn : Pin;
+  const auto RT = j > 0 ? bv + BV_RT * nn : PTin;
+  double lp[NLD], lpt[NLD], lr[NLD], lrt[NLD];
+  float lc[NLD][5];
+#pragma unroll
+  for (int q = 0; q < NLD; ++q) {
+    const int e0 = threadIdx.x + q * 256;
+    const int e = e0 < H * W ? e0 : 0;
+    const int a = e / W, b = e % W;
+    int gi = i0 + a - 1, gj = j0 + b - 1;
+    gi += gi < 0 ? n : (gi >= n ? -n : 0);
+    gj += gj < 0 ? n : (gj >= n ? -n : 0);
+    const long g = (long)gi * n + gj;
+    lp[q] = Pin[g];
+    lpt[q] = PTin[g];
+    lr[q] = R[g];
+    lrt[q] = RT[g];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) lc[q][k] = coef[k * nn + g];
+  }
   double beta = 0.0, S, ST;
   if (j == 0) {
     S = s.bi_sum_p[0];
@@ -152,37 +183,29 @@ __global__ __launch_bounds__(256) void k_bicg_matvec(LaunchCtx c, int j) {
   // algorithmic bytes per point: r, p, r~, p~ (FP64) and five FP32 coefficients read,
   // p, p~, q, q~ written; j = 0 reads only p, p~ and writes only q, q~
   count_bytes(c, j > 0 ? 84.0 : 52.0, n);
-  constexpr int W = TX + 2, H = BI_TY + 2;
   __shared__ double sp[H][W], spt[H][W];
   __shared__ float sc[5][H][W];
-  const int tpr = n / TX;
-  const int i0 = (int)(blockIdx.x / tpr) * BI_TY, j0 = (int)(blockIdx.x % tpr) * TX;
-  const double* Pin = d.bv + (j > 0 ? bv_p(prev) : BV_P0) * nn;
-  const double* PTin = d.bv + (j > 0 ? bv_pt(prev) : BV_PT0) * nn;
-  const double* R = d.bv + BV_R * nn;
-  const double* RT = d.bv + BV_RT * nn;
-  for (int e = threadIdx.x; e < H * W; e += 256) {
+#pragma unroll
+  for (int q = 0; q < NLD; ++q) {
+    const int e = threadIdx.x + q * 256;
+    if (e >= H * W) continue;
     const int a = e / W, b = e % W;
-    int gi = i0 + a - 1, gj = j0 + b - 1;
-    gi += gi < 0 ? n : (gi >= n ? -n : 0);
-    gj += gj < 0 ? n : (gj >= n ? -n : 0);
-    const long g = (long)gi * n + gj;
     if (j > 0) {
-      sp[a][b] = R[g] + beta * Pin[g];
-      spt[a][b] = RT[g] + beta * PTin[g];
+      sp[a][b] = lr[q] + beta * lp[q];
+      spt[a][b] = lrt[q] + beta * lpt[q];
     } else {
-      sp[a][b] = Pin[g];
-      spt[a][b] = PTin[g];
+      sp[a][b] = lp[q];
+      spt[a][b] = lpt[q];
     }
 #pragma unroll
-    for (int k = 0; k < 5; ++k) sc[k][a][b] = d.coef[k * nn + g];
+    for (int k = 0; k < 5; ++k) sc[k][a][b] = lc[q][k];
   }
   __syncthreads();
   const double ih = (double)n, ih2 = (double)n * (double)n, hih = 0.5 * ih, hih2 = 0.5 * ih2;
-  double* Q = d.bv + BV_Q * nn;
-  double* QT = d.bv + BV_QT * nn;
-  double* Pout = d.bv + bv_p(cur) * nn;
-  double* PTout = d.bv + bv_pt(cur) * nn;
+  const auto Q = bv + BV_Q * nn;
+  const auto QT = bv + BV_QT * nn;
+  const auto Pout = bv + bv_p(cur) * nn;
+  const auto PTout = bv + bv_pt(cur) * nn;
   double v[1] = {0.0};
   for (int e = threadIdx.x; e < BI_TY * TX; e += 256) {
     const int a = e / TX + 1, b = e % TX + 1;
@@ -225,6 +248,22 @@ __global__ __launch_bounds__(256) void k_bicg_update(LaunchCtx c, int j) {
   const PairDesc& d = c.desc[p];
   const long nn = (long)d.n * d.n;
   const int nb = bicg_blocks_dev(d.n, TX);
+  // the block's loads are issued before the fold of the p~.q partials
+  constexpr int PER = BI_TY * TX / 256;
+  const auto bv = gmem<double>(d.bv);
+  const auto P_ = bv + bv_p(j) * nn;
+  const long base = (long)blockIdx.x * (BI_TY * TX);
+  double lx[PER], lp[PER], lr[PER], lq[PER], lrt[PER], lqt[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const long g = base + threadIdx.x + q * 256;
+    lx[q] = bv[BV_X * nn + g];
+    lp[q] = P_[g];
+    lr[q] = bv[BV_R * nn + g];
+    lq[q] = bv[BV_Q * nn + g];
+    lrt[q] = bv[BV_RT * nn + g];
+    lqt[q] = bv[BV_QT * nn + g];
+  }
   double t[1];
   fold_all<1>(d.part, nb, t);
   const double sigma = t[0];
@@ -238,15 +277,13 @@ __global__ __launch_bounds__(256) void k_bicg_update(LaunchCtx c, int j) {
   }
   count_bytes(c, 72.0, d.n);  // x, p, r, q, r~, q~ read; x, r, r~ written (FP64)
   const double al = s.bi_rho[j & 1] / sigma;
-  double* bv = d.bv;
-  const double* P_ = bv + bv_p(j) * nn;
   double v[4] = {0.0, 0.0, 0.0, 0.0};
-  const long base = (long)blockIdx.x * (BI_TY * TX);
-  for (int e = threadIdx.x; e < BI_TY * TX; e += 256) {
-    const long g = base + e;
-    bv[BV_X * nn + g] += al * P_[g];
-    const double r = bv[BV_R * nn + g] - al * bv[BV_Q * nn + g];
-    const double rt = bv[BV_RT * nn + g] - al * bv[BV_QT * nn + g];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const long g = base + threadIdx.x + q * 256;
+    bv[BV_X * nn + g] = lx[q] + al * lp[q];
+    const double r = lr[q] - al * lq[q];
+    const double rt = lrt[q] - al * lqt[q];
     bv[BV_R * nn + g] = r;
     bv[BV_RT * nn + g] = rt;
     v[0] += rt * r;
