@@ -204,19 +204,85 @@ __device__ inline void block_reduce(double (&v)[K], const int (&kinds)[K], doubl
 }
 
 // Fixed-order fold of per-block partials (K values per block) inside a
-// one-block-per-pair finalize kernel: thread t takes blocks t, t + blockDim, ...,
-// then a block reduction.  Result valid in thread 0.
+// one-block-per-pair finalize kernel: thread t takes blocks t, t + blockDim, ... in
+// that order (the loads of four of them issued before the first is combined), then a
+// block reduction.  Result valid in thread 0.
 template <int K>
 __device__ inline void fold_partials(const double* part, int nblk, const int (&kinds)[K], double (&t)[K],
                                      double* scratch) {
+  constexpr int U = 4;
+  const auto P = gmem<const double>(part);
 #pragma unroll
   for (int k = 0; k < K; ++k) t[k] = kinds[k] == 1 ? 1e300 : (kinds[k] == 2 ? -1e300 : 0.0);
-  for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+  const int bd = blockDim.x;
+  for (int b = threadIdx.x; b < nblk; b += U * bd) {
+    double v[U][K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const double v = part[(long)b * K + k];
-      t[k] = kinds[k] == 0 ? t[k] + v : (kinds[k] == 1 ? fmin(t[k], v) : fmax(t[k], v));
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int k = 0; k < K; ++k) v[u][k] = b + u * bd < nblk ? P[(long)(b + u * bd) * K + k] : 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (b + u * bd >= nblk) break;
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+        t[k] = kinds[k] == 0 ? t[k] + v[u][k] : (kinds[k] == 1 ? fmin(t[k], v[u][k]) : fmax(t[k], v[u][k]));
     }
   }
   block_reduce<K>(t, kinds, scratch);
+}
+
+// A structure staged in LDS for one thread's serial bookkeeping: the block loads it
+// 8 bytes per lane (every load issued before the first use), stores it into LDS, and
+// after the bookkeeping writes it back.  Launch with BLOCK threads.
+template <class T, int BLOCK>
+struct StagedWords {
+  static_assert(sizeof(T) % 8 == 0, "whole 8-byte words");
+  static constexpr int WORDS = sizeof(T) / 8, PER = (WORDS + BLOCK - 1) / BLOCK;
+  unsigned long long v[PER];
+  __device__ void load(const T* src) {
+    const auto w = gmem<const unsigned long long>(reinterpret_cast<const unsigned long long*>(src));
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = threadIdx.x + q * BLOCK;
+      v[q] = e < WORDS ? w[e] : 0ull;
+    }
+  }
+  __device__ void to_lds(T* lds) const {
+    unsigned long long* w = reinterpret_cast<unsigned long long*>(lds);
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = threadIdx.x + q * BLOCK;
+      if (e < WORDS) w[e] = v[q];
+    }
+  }
+  static __device__ void write_back(const T* lds, T* dst) {
+    const unsigned long long* w = reinterpret_cast<const unsigned long long*>(lds);
+    const auto d = gmem<unsigned long long>(reinterpret_cast<unsigned long long*>(dst));
+    for (int e = threadIdx.x; e < WORDS; e += BLOCK) d[e] = w[e];
+  }
+};
+
+// Sum of part[b * stride + l] over b = first, first + step, ... < nblk in a fixed
+// order: U accumulators (block first + (r U + u) step goes to accumulator u), the U
+// loads of a round issued before its adds, then a pairwise sum of the accumulators.
+template <int U>
+__device__ inline double strided_sum(const double* part, long stride, int l, int first, int step, int nblk) {
+  static_assert((U & (U - 1)) == 0, "U: a power of two");
+  const auto P = gmem<const double>(part);
+  double a[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) a[u] = 0.0;
+  for (int b = first; b < nblk; b += U * step) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = b + u * step < nblk ? P[(long)(b + u * step) * stride + l] : 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) a[u] += v[u];
+  }
+#pragma unroll
+  for (int w = U / 2; w > 0; w >>= 1)
+#pragma unroll
+    for (int u = 0; u < w; ++u) a[u] += a[u + w];
+  return a[0];
 }

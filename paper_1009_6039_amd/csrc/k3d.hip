@@ -339,6 +339,18 @@ __global__ __launch_bounds__(256) void k3_vec_fold(Desc3 d, State3* s, int mode,
   __shared__ double scratch[4];
   const int kinds[1] = {0};
   double t[1];
+  if (mode == V3_ARNOLDI) {  // the rotations run on a copy of the state in LDS
+    __shared__ State3 ls;
+    StagedWords<State3, 256> sw;
+    sw.load(s);
+    fold_partials<1>(d.part, nblk, kinds, t, scratch);
+    sw.to_lds(&ls);
+    __syncthreads();
+    if (threadIdx.x == 0) arnoldi_close3(ls, jn, t[0]);
+    __syncthreads();
+    StagedWords<State3, 256>::write_back(&ls, s);
+    return;
+  }
   fold_partials<1>(d.part, nblk, kinds, t, scratch);
   if (threadIdx.x != 0) return;
   if (mode == V3_INIT) {
@@ -351,8 +363,6 @@ __global__ __launch_bounds__(256) void k3_vec_fold(Desc3 d, State3* s, int mode,
     s->gm_k = 0;
     s->vscale[0] = bn > 0.0 ? 1.0 / bn : 0.0;
     s->gv[0] = bn;
-  } else if (mode == V3_ARNOLDI) {
-    arnoldi_close3(*s, jn, t[0]);
   }
 }
 
@@ -618,25 +628,13 @@ __global__ __launch_bounds__(MA3_BLOCK) void k3_p5(Desc3 d, const State3* s, int
 }
 
 // h[l][j] = <w, v_l> from the P5 partials (one block of 1024 threads): lane l of group g
-// sums blocks g, g + 32, ... with four independent accumulators, then the groups are
+// sums blocks g, g + 32, ... with 16 loads in flight per round, then the groups are
 // summed in order (a fixed order throughout)
 __global__ __launch_bounds__(1024) void k3_dots_fold(Desc3 d, State3* s, int j, int nblk) {
   if (!s->gm_running) return;
   __shared__ double red[32][32];
   const int l = threadIdx.x & 31, grp = threadIdx.x >> 5;
-  double t = 0.0;
-  if (l <= j) {
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int b = grp;
-    for (; b + 96 < nblk; b += 128) {
-      a0 += d.part[(long)b * (MA3_MMAX + 1) + l];
-      a1 += d.part[(long)(b + 32) * (MA3_MMAX + 1) + l];
-      a2 += d.part[(long)(b + 64) * (MA3_MMAX + 1) + l];
-      a3 += d.part[(long)(b + 96) * (MA3_MMAX + 1) + l];
-    }
-    for (; b < nblk; b += 32) a0 += d.part[(long)b * (MA3_MMAX + 1) + l];
-    t = (a0 + a1) + (a2 + a3);
-  }
+  const double t = l <= j ? strided_sum<16>(d.part, MA3_MMAX + 1, l, grp, 32, nblk) : 0.0;
   red[grp][l] = t;
   __syncthreads();
   if (threadIdx.x <= j) {

@@ -61,7 +61,7 @@ __device__ void arnoldi_close(PairState& s, const LaunchCtx& c, int jn, double w
 }
 
 // h[l][j] = <w, v_l> for l <= j from the pass-C partials (one block per pair).
-// Lane l of group g sums blocks g, g + 8, ...; the loads are independent.
+// Lane l of group g sums blocks g, g + 8, ... (16 loads in flight per round).
 __global__ __launch_bounds__(256) void k_dots_finalize(LaunchCtx c, int j, int nblk) {
   const int p = pair_of_block(c);
   if (p < 0) return;
@@ -70,19 +70,7 @@ __global__ __launch_bounds__(256) void k_dots_finalize(LaunchCtx c, int j, int n
   if (!(s.phase == PH_SOLVE && s.gm_running)) return;
   __shared__ double red[8][32];
   const int l = threadIdx.x & 31, grp = threadIdx.x >> 5;
-  double t = 0.0;
-  if (l <= j) {
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int b = grp;
-    for (; b + 24 < nblk; b += 32) {
-      a0 += d.part[(long)b * (MA_MMAX + 1) + l];
-      a1 += d.part[(long)(b + 8) * (MA_MMAX + 1) + l];
-      a2 += d.part[(long)(b + 16) * (MA_MMAX + 1) + l];
-      a3 += d.part[(long)(b + 24) * (MA_MMAX + 1) + l];
-    }
-    for (; b < nblk; b += 8) a0 += d.part[(long)b * (MA_MMAX + 1) + l];
-    t = (a0 + a1) + (a2 + a3);
-  }
+  const double t = l <= j ? strided_sum<16>(d.part, MA_MMAX + 1, l, grp, 8, nblk) : 0.0;
   red[grp][l] = t;
   __syncthreads();
   if (threadIdx.x <= j) {
@@ -92,7 +80,8 @@ __global__ __launch_bounds__(256) void k_dots_finalize(LaunchCtx c, int j, int n
   }
 }
 
-// ||w'|| from the pass-A partials, then the rotations and the convergence test
+// ||w'|| from the pass-A partials, then the rotations and the convergence test (on a
+// copy of the pair's state in LDS, loaded together with the partials)
 __global__ __launch_bounds__(256) void k_arnoldi_finalize(LaunchCtx c, int jn, int nblk) {
   const int p = pair_of_block(c);
   if (p < 0) return;
@@ -100,10 +89,17 @@ __global__ __launch_bounds__(256) void k_arnoldi_finalize(LaunchCtx c, int jn, i
   PairState& s = c.st[p];
   if (!(s.phase == PH_SOLVE && s.gm_running)) return;
   __shared__ double scratch[4];
+  __shared__ PairState ls;
+  StagedWords<PairState, 256> sw;
+  sw.load(&s);
   const int kinds[1] = {0};
   double t[1];
   fold_partials<1>(d.part, nblk, kinds, t, scratch);
-  if (threadIdx.x == 0) arnoldi_close(s, c, jn, t[0]);
+  sw.to_lds(&ls);
+  __syncthreads();
+  if (threadIdx.x == 0) arnoldi_close(ls, c, jn, t[0]);
+  __syncthreads();
+  StagedWords<PairState, 256>::write_back(&ls, &s);
 }
 
 // the scaled right-hand side's norm (option MA_PRECOND_DIAG) from the pass-A partials:
