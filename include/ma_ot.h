@@ -32,7 +32,7 @@
 extern "C" {
 #endif
 
-#define MA_OT_ABI_VERSION 10
+#define MA_OT_ABI_VERSION 11
 
 /* return / status codes */
 #define MA_OK 0           /* converged: rms residual <= tol                           */
@@ -364,11 +364,15 @@ int ma3_step_lbar_inverse(ma3_plan* plan, int n, const float* sigma, const doubl
  * region of its own with wave-level synchronisation only (row pass C: one or two row
  * pairs per block, n >= 128; its variants 6 and 7 are instead the block geometries 0
  * and 3 with the coefficient loads issued before the transforms and the twiddles read
- * from LDS).  A variant that coincides with a smaller index is skipped; its geometry
- * query returns that index.
+ * from LDS); 8..11 the FFT radix plans of the three transform passes: 8 and 10 radix 4
+ * throughout (a factor 3 first, a last 8 or 2), 9 and 11 radix 16 where it saves a
+ * stage (512 = 16 8 4, 256 = 16 16, 384 = 3 16 8), at the default geometry (8, 9) or
+ * at geometry 2 (passes A, B) / 3 (pass C) (10, 11); the default plan takes a factor 3
+ * first, then eights (512 = 8 8 8, 384 = 3 8 4 4).  A variant that coincides with a
+ * smaller index is skipped; its geometry query returns that index.
  * ------------------------------------------------------------------------- */
-#define MA_TUNE_VARIANTS 8
-#define MA_TUNE_SLOTS 8  /* room for the per-variant times below */
+#define MA_TUNE_VARIANTS 12
+#define MA_TUNE_SLOTS 12  /* room for the per-variant times below */
 
 typedef struct ma_tuning {
   int n;               /* grid side */

@@ -1,4 +1,4 @@
-// Mixed-radix (2, 3, 4, 8) self-sorting Stockham FFT on data resident in LDS.
+// Mixed-radix (2, 3, 4, 8, 16) self-sorting Stockham FFT on data resident in LDS.
 //
 // A block runs NF independent length-N complex transforms that sit in LDS.
 // LAYOUT_ROWS:  element e of transform t at lds[t * N + e]   (row FFTs)
@@ -10,6 +10,8 @@
 // w = exp(-+2 pi i / (Ns R)), runs a length-R DFT and writes
 // x[(j / Ns) Ns R + (j mod Ns) + r Ns].  The output is in natural order.
 // Twiddles come from a table tw[m] = exp(-2 pi i m / N) built on the host in FP64.
+// The radix sequence (the plan) is a compile-time choice: plan 0 takes a factor 3
+// first, then eights; plan 1 fours; plan 2 sixteens where they save a stage.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -81,29 +83,88 @@ __device__ __forceinline__ void dft8(float2 (&v)[8]) {
   v[7] = csub(e3, o3);
 }
 
+// x * exp(-+ 2 pi i m / 16) for a fixed m in 1..9 (cos and sin of multiples of pi / 8)
+template <int M, bool INV>
+__device__ __forceinline__ float2 w16(float2 a) {
+  constexpr float c1 = 0.92387953251128675613f, s1 = 0.38268343236508977173f, r2 = 0.70710678118654752440f;
+  constexpr float cr = M == 1 ? c1 : M == 2 ? r2 : M == 3 ? s1 : M == 4 ? 0.f : M == 6 ? -r2 : -c1;
+  constexpr float si = M == 1 ? s1 : M == 2 ? r2 : M == 3 ? c1 : M == 4 ? 1.f : M == 6 ? r2 : -s1;
+  static_assert(M == 1 || M == 2 || M == 3 || M == 4 || M == 6 || M == 9, "twiddle index");
+  // w = cr - +i si (forward: minus)
+  const float sg = INV ? si : -si;
+  return make_float2(a.x * cr - a.y * sg, a.x * sg + a.y * cr);
+}
+
+// 16-point DFT as 4 x 4: element 4 n1 + n2; length-4 transforms over n1, the twiddles
+// w16^(n2 k1), length-4 transforms over n2; output k1 + 4 k2 in natural order
+template <bool INV>
+__device__ __forceinline__ void dft16(float2 (&v)[16]) {
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) dft4<INV>(v[n2], v[4 + n2], v[8 + n2], v[12 + n2]);
+  // v[4 k1 + n2] now holds y[n2][k1]
+  v[5] = w16<1, INV>(v[5]);
+  v[9] = w16<2, INV>(v[9]);
+  v[13] = w16<3, INV>(v[13]);
+  v[6] = w16<2, INV>(v[6]);
+  v[10] = w16<4, INV>(v[10]);
+  v[14] = w16<6, INV>(v[14]);
+  v[7] = w16<3, INV>(v[7]);
+  v[11] = w16<6, INV>(v[11]);
+  v[15] = w16<9, INV>(v[15]);
+  float2 o[16];
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    float2 a = v[4 * k1], b = v[4 * k1 + 1], c = v[4 * k1 + 2], d = v[4 * k1 + 3];
+    dft4<INV>(a, b, c, d);
+    o[k1] = a;
+    o[k1 + 4] = b;
+    o[k1 + 8] = c;
+    o[k1 + 12] = d;
+  }
+#pragma unroll
+  for (int k = 0; k < 16; ++k) v[k] = o[k];
+}
+
 template <int R, bool INV>
 __device__ __forceinline__ void dft(float2 (&v)[R]) {
   if constexpr (R == 2) dft2<INV>(v[0], v[1]);
   else if constexpr (R == 3) dft3<INV>(v[0], v[1], v[2]);
   else if constexpr (R == 4) dft4<INV>(v[0], v[1], v[2], v[3]);
-  else dft8<INV>(v);
+  else if constexpr (R == 8) dft8<INV>(v);
+  else dft16<INV>(v);
 }
 
-// radix used for the remaining length REM: a factor 3 first, then eights, with
-// sixteen split as 4 x 4 and leftovers as 4 or 2
-__host__ __device__ constexpr int pick_radix(int rem) {
-  return (rem % 3 == 0) ? 3 : (rem == 16 ? 4 : (rem % 8 == 0 ? 8 : (rem % 4 == 0 ? 4 : 2)));
+// radix used for the remaining length REM under a plan.  Plan 0: a factor 3 first,
+// then eights, with sixteen split as 4 x 4 and leftovers as 4 or 2.  Plan 1: a factor 3
+// first, then fours, with a last eight or two.  Plan 2: a factor 3 first, then sixteens
+// (thirty-two as 8 x 4), then 8, 4 or 2.
+__host__ __device__ constexpr int pick_radix(int rem, int plan = 0) {
+  if (rem % 3 == 0) return 3;
+  if (plan == 1) return rem == 8 ? 8 : (rem % 4 == 0 ? 4 : 2);
+  if (plan == 2 && rem % 16 == 0 && rem != 32) return 16;
+  return rem == 16 ? 4 : (rem % 8 == 0 ? 8 : (rem % 4 == 0 ? 4 : 2));
+}
+
+// whether a plan's radix sequence for length n differs from plan 0's
+__host__ __device__ constexpr bool plan_differs(int n, int plan) {
+  int ns = 1;
+  while (ns < n) {
+    const int r = pick_radix(n / ns, plan);
+    if (r != pick_radix(n / ns, 0)) return true;
+    ns *= r;
+  }
+  return false;
 }
 
 // One more than the largest twiddle-table index a length-N transform reads: a stage
 // of radix R after sub-length NS > 1 reads tw[m k TWS], k < NS, TWS = N / (NS R), with
-// m up to 4 (R = 8), 2 (R = 4, 3) or 1 (R = 2).
-__host__ __device__ constexpr int tw_span(int n) {
+// m up to 8 (R = 16), 4 (R = 8), 2 (R = 4, 3) or 1 (R = 2).
+__host__ __device__ constexpr int tw_span(int n, int plan = 0) {
   int need = 1, ns = 1;
   while (ns < n) {
-    const int r = pick_radix(n / ns);
+    const int r = pick_radix(n / ns, plan);
     if (ns > 1) {
-      const int top = r == 8 ? 4 : (r == 2 ? 1 : 2);
+      const int top = r == 16 ? 8 : (r == 8 ? 4 : (r == 2 ? 1 : 2));
       const int idx = top * (ns - 1) * (n / (ns * r)) + 1;
       need = need > idx ? need : idx;
     }
@@ -116,9 +177,9 @@ __host__ __device__ constexpr int tw_span(int n) {
 // that the stages read twiddles without vector-memory loads (whose in-order counter
 // would also hold every other load in flight).  The caller's barrier before its first
 // transform makes the copy visible.
-template <int N, int BLOCK>
+template <int N, int BLOCK, int PLAN = 0>
 __device__ __forceinline__ void stage_twiddles(float2* twl, const float2* __restrict__ tw) {
-  for (int e = threadIdx.x; e < tw_span(N); e += BLOCK) twl[e] = tw[e];
+  for (int e = threadIdx.x; e < tw_span(N, PLAN); e += BLOCK) twl[e] = tw[e];
 }
 
 template <int N, int NF, int LAYOUT>
@@ -151,12 +212,17 @@ __device__ __forceinline__ void fft_stage(float2* lds, const float2* __restrict_
         w[1] = tw[k * TWS];
         if constexpr (R >= 3) w[2] = tw[2 * k * TWS];
         if constexpr (R == 4) w[3] = cmul(w[1], w[2]);
-        if constexpr (R == 8) {
+        if constexpr (R >= 8) {
           w[4] = tw[4 * k * TWS];
           w[3] = cmul(w[1], w[2]);
           w[5] = cmul(w[4], w[1]);
           w[6] = cmul(w[4], w[2]);
           w[7] = cmul(w[4], w[3]);
+        }
+        if constexpr (R == 16) {  // w^8 from the table, the rest as w^8 w^(r - 8)
+          w[8] = tw[8 * k * TWS];
+#pragma unroll
+          for (int r = 9; r < 16; ++r) w[r] = cmul(w[8], w[r - 8]);
         }
 #pragma unroll
         for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], INV ? cconj(w[r]) : w[r]);
@@ -181,12 +247,12 @@ __device__ __forceinline__ void fft_stage(float2* lds, const float2* __restrict_
   __syncthreads();
 }
 
-template <int N, int NS, int NF, int BLOCK, bool INV, int LAYOUT>
+template <int N, int NS, int NF, int BLOCK, bool INV, int LAYOUT, int PLAN = 0>
 __device__ __forceinline__ void fft_stages(float2* lds, const float2* __restrict__ tw) {
   if constexpr (NS < N) {
-    constexpr int R = pick_radix(N / NS);
+    constexpr int R = pick_radix(N / NS, PLAN);
     fft_stage<N, NS, R, NF, BLOCK, INV, LAYOUT>(lds, tw);
-    fft_stages<N, NS * R, NF, BLOCK, INV, LAYOUT>(lds, tw);
+    fft_stages<N, NS * R, NF, BLOCK, INV, LAYOUT, PLAN>(lds, tw);
   }
 }
 
@@ -197,24 +263,24 @@ __device__ __forceinline__ void fft_stages(float2* lds, const float2* __restrict
 // with stride BLOCK).  The first stage has no twiddles; its outputs go to LDS in the
 // Stockham order and the later stages run in LDS as in fft_lds.  The caller makes
 // sure no thread still reads `lds` before the call; the routine ends with a barrier.
-template <int N, int NF, int BLOCK, bool INV>
+template <int N, int NF, int BLOCK, bool INV, int PLAN = 0>
 __device__ __forceinline__ void fft_cols_from_regs(float2* lds, const float2* __restrict__ tw,
-                                                   float2 (&x)[pick_radix(N)]) {
-  constexpr int R0 = pick_radix(N);
+                                                   float2 (&x)[pick_radix(N, PLAN)]) {
+  constexpr int R0 = pick_radix(N, PLAN);
   static_assert(BLOCK == NF * (N / R0), "one first-stage butterfly per thread");
   const int t = threadIdx.x % NF, j = threadIdx.x / NF;
   dft<R0, INV>(x);
 #pragma unroll
   for (int r = 0; r < R0; ++r) lds[lds_index<N, NF, LAYOUT_COLS>(t, j * R0 + r)] = x[r];
   __syncthreads();
-  fft_stages<N, R0, NF, BLOCK, INV, LAYOUT_COLS>(lds, tw);
+  fft_stages<N, R0, NF, BLOCK, INV, LAYOUT_COLS, PLAN>(lds, tw);
 }
 
 // In-place transforms of NF sequences in LDS.  Caller synchronises before (data
 // written) — the routine ends with a barrier so results are visible on return.
-template <int N, int NF, int BLOCK, bool INV, int LAYOUT>
+template <int N, int NF, int BLOCK, bool INV, int LAYOUT, int PLAN = 0>
 __device__ __forceinline__ void fft_lds(float2* lds, const float2* __restrict__ tw) {
-  fft_stages<N, 1, NF, BLOCK, INV, LAYOUT>(lds, tw);
+  fft_stages<N, 1, NF, BLOCK, INV, LAYOUT, PLAN>(lds, tw);
 }
 
 // ---------------------------------------------------------------------------

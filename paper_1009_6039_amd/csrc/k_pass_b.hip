@@ -1,5 +1,6 @@
 // Pass B of Strain's operator: instantiations for every grid size and launch-geometry
-// variant, the launcher and the geometry query used by the autotuner.
+// variant, the launcher and the geometry query used by the autotuner.  Variants 0..3
+// are the block-shared kernels (Cfg), 4..6 the wave-owned ones, 8..11 the radix plans.
 #include "strain.h"
 
 #define MA_VARIANT_CASES(NV) X(NV, 0) X(NV, 1) X(NV, 2) X(NV, 3)
@@ -22,10 +23,24 @@ void launch_waveB(const LaunchCtx& c, int npairs, int mode, int j, const float2*
   if constexpr (waveB_fits(N, W) && (N / 2) % W == 0 && N % 64 == 0)
     MA_LAUNCH(ev, (k_passB_w<N, W>), dim3(N / 2 / W, npairs), dim3(64 * W), st, c, mode, j, tw);
 }
+
+// block-shared kernel of geometry VV with radix plan P
+template <int N, int VV, int P>
+void launch_planB(const LaunchCtx& c, int npairs, int mode, int j, const float2* tw, hipStream_t st,
+                  const TimedLaunch& ev) {
+  constexpr int G = Canon<N, VV>::B;
+  constexpr int PL = plan_differs(N, P) ? P : 0;
+  MA_LAUNCH(ev, (k_passB<N, G, PL>), dim3(N / 2 / Cfg<N, VV>::B_CPB, npairs), dim3(Cfg<N, VV>::B_BLOCK), st, c,
+            mode, j, tw);
+}
 }  // namespace
 
-
 int passB_geometry(int n, int v, int* units, int* threads) {
+  if (is_plan_variant(v)) {
+    const int g = passB_geometry(n, plan_geometry(v, 2), units, threads);
+    if (g < 0 || !plan_differs(n, plan_of_variant(v))) return g;
+    return g == 0 ? (v < 10 ? v : v - 2) : v;
+  }
   if (v >= 4 && v < MA_NVARIANTS) {
     if (!fft_size_supported(n)) return -1;
     const int w = waveB_w(n, v);
@@ -57,6 +72,23 @@ int passB_blocks(int n, int v) {
 
 void launch_passB(const LaunchCtx& c, int n, int npairs, int mode, int j, const float2* tw,
                  hipStream_t st, const TimedLaunch& ev) {
+  if (is_plan_variant(c.var[1])) {
+    const bool p1 = plan_of_variant(c.var[1]) == 1;
+    switch (n * 4 + plan_geometry(c.var[1], 2)) {
+#define X(NV, VV)                                                       \
+  case NV * 4 + VV:                                                     \
+    if (p1) launch_planB<NV, VV, 1>(c, npairs, mode, j, tw, st, ev);    \
+    else launch_planB<NV, VV, 2>(c, npairs, mode, j, tw, st, ev);       \
+    break;
+#define Y(NV) X(NV, 0) X(NV, 2)
+      MA_FOR_EACH_N(Y)
+#undef Y
+#undef X
+      default:
+        break;
+    }
+    return;
+  }
   const int w = waveB_w(n, c.var[1]);
   if (w > 0) {
     switch (n * 16 + w) {

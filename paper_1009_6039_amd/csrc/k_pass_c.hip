@@ -2,7 +2,8 @@
 // variant, the launcher and the geometry query used by the autotuner.  Variants 0..3
 // are the block-shared kernels (Cfg), 4 and 5 the wave-owned kernels with one and two
 // row pairs per block (n >= 128), 6 and 7 the block-shared kernels of variants 0 and 3
-// that load the combination's coefficients before the transforms.
+// that load the combination's coefficients before the transforms, 8..11 the radix
+// plans.
 #include "strain.h"
 
 #define MA_VARIANT_CASES(NV) X(NV, 0) X(NV, 1) X(NV, 2) X(NV, 3)
@@ -27,9 +28,24 @@ void launch_wave(const LaunchCtx& c, int npairs, int mode, int j, const float2* 
 
 // variants 6 and 7: block-shared geometry 0 or 3, coefficients loaded first
 int prefetch_base(int v) { return v == 6 ? 0 : 3; }
+
+// block-shared kernel of geometry VV with radix plan P
+template <int N, int VV, int P>
+void launch_planC(const LaunchCtx& c, int npairs, int mode, int j, const float2* tw, hipStream_t st,
+                  const TimedLaunch& ev) {
+  constexpr int G = Canon<N, VV>::C;
+  constexpr int PL = plan_differs(N, P) ? P : 0;
+  MA_LAUNCH(ev, (k_passC<N, G, false, PL>), dim3(N / 2 / Cfg<N, VV>::C_PPB, npairs), dim3(Cfg<N, VV>::C_BLOCK),
+            st, c, mode, j, tw);
+}
 }  // namespace
 
 int passC_geometry(int n, int v, int* units, int* threads) {
+  if (is_plan_variant(v)) {
+    const int g = passC_geometry(n, plan_geometry(v, 3), units, threads);
+    if (g < 0 || !plan_differs(n, plan_of_variant(v))) return g;
+    return g == 0 ? (v < 10 ? v : v - 2) : v;
+  }
   if (v == 6 || v == 7) {
     const int c = passC_geometry(n, prefetch_base(v), units, threads);
     if (c < 0) return -1;
@@ -66,6 +82,23 @@ int passC_blocks(int n, int v) {
 
 void launch_passC_only(const LaunchCtx& c, int n, int npairs, int mode, int j, const float2* tw,
                  hipStream_t st, const TimedLaunch& ev) {
+  if (is_plan_variant(c.var[2])) {
+    const bool p1 = plan_of_variant(c.var[2]) == 1;
+    switch (n * 4 + plan_geometry(c.var[2], 3)) {
+#define X(NV, VV)                                                       \
+  case NV * 4 + VV:                                                     \
+    if (p1) launch_planC<NV, VV, 1>(c, npairs, mode, j, tw, st, ev);    \
+    else launch_planC<NV, VV, 2>(c, npairs, mode, j, tw, st, ev);       \
+    break;
+#define Y(NV) X(NV, 0) X(NV, 3)
+      MA_FOR_EACH_N(Y)
+#undef Y
+#undef X
+      default:
+        break;
+    }
+    return;
+  }
   const int ppb = wave_ppb(n, c.var[2]);
   if (ppb > 0) {
     switch (n * 2 + ppb) {

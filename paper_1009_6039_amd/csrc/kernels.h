@@ -58,7 +58,14 @@ void launch_tune_fill(const LaunchCtx& c, int n, int npairs, hipStream_t st);
 bool fft_size_supported(int n);
 // launch-geometry variants 0..MA_NVARIANTS-1 of each pass (0 = default); the geometry
 // functions return the variant's canonical index (a duplicate returns 0) or -1
-constexpr int MA_NVARIANTS = 8;
+constexpr int MA_NVARIANTS = 12;
+// Variants 8..11 of the transform passes change the radix plan of their FFTs (fft.h):
+// plan 1 (8, 10) or plan 2 (9, 11), at the default geometry (8, 9) or at the pass's
+// second geometry (10, 11: geometry 2 for passes A and B, 3 for pass C).  A plan that
+// equals plan 0 for the size leaves the kernel of that geometry.
+constexpr bool is_plan_variant(int v) { return v >= 8 && v < 12; }
+constexpr int plan_of_variant(int v) { return (v - 8) % 2 + 1; }
+constexpr int plan_geometry(int v, int second) { return v < 10 ? 0 : second; }
 int passA_geometry(int n, int v, int* row_pairs, int* threads);
 int passB_geometry(int n, int v, int* columns, int* threads);
 int passC_geometry(int n, int v, int* row_pairs, int* threads);

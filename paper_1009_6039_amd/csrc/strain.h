@@ -102,7 +102,8 @@ __device__ __forceinline__ float2 times_i(float s, float2 a) { return make_float
 // ---------------------------------------------------------------------------
 // pass A
 // ---------------------------------------------------------------------------
-template <int N, int G>
+// PL: the radix plan of the transforms (fft.h)
+template <int N, int G, int PL = 0>
 __global__ __launch_bounds__((Cfg<N, G>::A_BLOCK)) void k_passA(LaunchCtx c, int mode, int jn,
                                                            const float2* __restrict__ tw) {
   constexpr int PPB = Cfg<N, G>::A_PPB, BLOCK = Cfg<N, G>::A_BLOCK, NH = N / 2;
@@ -243,7 +244,7 @@ __global__ __launch_bounds__((Cfg<N, G>::A_BLOCK)) void k_passA(LaunchCtx c, int
 
   if (!(mode == PA_ARNOLDI && jn >= c.m)) {
     __syncthreads();
-    fft_lds<N, PPB, BLOCK, false, LAYOUT_ROWS>(lds, tw);
+    fft_lds<N, PPB, BLOCK, false, LAYOUT_ROWS, PL>(lds, tw);
     const auto H = gmem<float2>(d.H);
     for (int e = threadIdx.x; e < PPB * NH; e += BLOCK) {
       const int pp = e / NH, k = e % NH;
@@ -275,7 +276,7 @@ __global__ __launch_bounds__((Cfg<N, G>::A_BLOCK)) void k_passA(LaunchCtx c, int
 // ---------------------------------------------------------------------------
 // pass B (columns)
 // ---------------------------------------------------------------------------
-template <int N, int G>
+template <int N, int G, int PL = 0>
 __global__ __launch_bounds__((Cfg<N, G>::B_BLOCK)) void k_passB(LaunchCtx c, int mode, int j,
                                                            const float2* __restrict__ tw) {
   constexpr int CPB = Cfg<N, G>::B_CPB, BLOCK = Cfg<N, G>::B_BLOCK, NH = N / 2;
@@ -293,7 +294,7 @@ __global__ __launch_bounds__((Cfg<N, G>::B_BLOCK)) void k_passB(LaunchCtx c, int
   // S: the column spectra, then rhobar * sigmahat, then each output spectrum in turn.
   // Element (row or wavenumber e, column cc) sits at e * CPB + cc.
   __shared__ float2 S[N * CPB];
-  __shared__ float2 twl[tw_span(N)];
+  __shared__ float2 twl[tw_span(N, PL)];
   const int s0 = blockIdx.x * CPB;
   const auto H = gmem<const float2>(d.H);
   const auto T = gmem<float2>(d.T);
@@ -301,7 +302,7 @@ __global__ __launch_bounds__((Cfg<N, G>::B_BLOCK)) void k_passB(LaunchCtx c, int
   // for e = threadIdx.x + q BLOCK of column threadIdx.x % CPB) are that butterfly's
   // inputs: every transform starts from registers (one LDS pass and two barriers
   // fewer each); other geometries stage everything through LDS.
-  constexpr int R0 = pick_radix(N);
+  constexpr int R0 = pick_radix(N, PL);
   constexpr bool REG1 = BLOCK == CPB * (N / R0);
   {  // every column load of the thread in flight before the first LDS write
     constexpr int PER = N * CPB / BLOCK;  // whole (static_assert in Cfg)
@@ -311,14 +312,14 @@ __global__ __launch_bounds__((Cfg<N, G>::B_BLOCK)) void k_passB(LaunchCtx c, int
       const int e = threadIdx.x + q * BLOCK;
       h[q] = H[(long)(e / CPB) * NH + s0 + e % CPB];
     }
-    stage_twiddles<N, BLOCK>(twl, tw);  // issued after the column loads, used after them
+    stage_twiddles<N, BLOCK, PL>(twl, tw);  // issued after the column loads, used after them
     if constexpr (REG1) {
-      fft_cols_from_regs<N, CPB, BLOCK, false>(S, twl, h);
+      fft_cols_from_regs<N, CPB, BLOCK, false, PL>(S, twl, h);
     } else {
 #pragma unroll
       for (int q = 0; q < PER; ++q) S[threadIdx.x + q * BLOCK] = h[q];
       __syncthreads();
-      fft_lds<N, CPB, BLOCK, false, LAYOUT_COLS>(S, twl);
+      fft_lds<N, CPB, BLOCK, false, LAYOUT_COLS, PL>(S, twl);
     }
   }
   if (mode == PB_FORWARD) {
@@ -376,7 +377,7 @@ __global__ __launch_bounds__((Cfg<N, G>::B_BLOCK)) void k_passB(LaunchCtx c, int
         const float2 m = c.mt[(threadIdx.x + k * BLOCK) / CPB];
         x[k] = o == 0 ? sv[k] : ((o == 1) ? times_i(m.x, sv[k]) : cscale(sv[k], m.y));
       }
-      fft_cols_from_regs<N, CPB, BLOCK, true>(S, twl, x);
+      fft_cols_from_regs<N, CPB, BLOCK, true, PL>(S, twl, x);
     } else {
       if (oo > 0 || o != 0) {  // S still holds the plain spectrum for a lone output 0
 #pragma unroll
@@ -387,7 +388,7 @@ __global__ __launch_bounds__((Cfg<N, G>::B_BLOCK)) void k_passB(LaunchCtx c, int
         }
         __syncthreads();
       }
-      fft_lds<N, CPB, BLOCK, true, LAYOUT_COLS>(S, twl);
+      fft_lds<N, CPB, BLOCK, true, LAYOUT_COLS, PL>(S, twl);
     }
     const auto To = T + (long)o * N * NH;
     for (int e = threadIdx.x; e < N * CPB; e += BLOCK) {
@@ -516,7 +517,7 @@ __device__ __forceinline__ void passC_combine(const LaunchCtx& c, const PairDesc
 // PF: the coefficients of the combination are loaded right after the spectra, before
 // the transforms, and the transforms read their twiddles from an LDS copy (so that no
 // vector-memory wait inside them holds the coefficient loads back)
-template <int N, int G, bool PF = false>
+template <int N, int G, bool PF = false, int PL = 0>
 __global__ __launch_bounds__((Cfg<N, G>::C_BLOCK)) void k_passC(LaunchCtx c, int mode, int j,
                                                            const float2* __restrict__ tw) {
   constexpr int PPB = Cfg<N, G>::C_PPB, BLOCK = Cfg<N, G>::C_BLOCK, NH = N / 2;
@@ -553,7 +554,7 @@ __global__ __launch_bounds__((Cfg<N, G>::C_BLOCK)) void k_passC(LaunchCtx c, int
       }
     }
     __syncthreads();
-    fft_lds<N, PPB, BLOCK, true, LAYOUT_ROWS>(lds, tw);
+    fft_lds<N, PPB, BLOCK, true, LAYOUT_ROWS, PL>(lds, tw);
     for (int e = threadIdx.x; e < PPB * N; e += BLOCK) {
       const int pp = e / N, jj = e % N;
       const long ea = (long)(row0 + 2 * pp) * N + jj, eb = ea + N;
@@ -573,8 +574,8 @@ __global__ __launch_bounds__((Cfg<N, G>::C_BLOCK)) void k_passC(LaunchCtx c, int
 
   // five complex inverse transforms per row pair; every spectrum load of the thread
   // is issued before the first LDS write
-  __shared__ float2 twl[PF ? tw_span(N) : 1];
-  if constexpr (PF) stage_twiddles<N, BLOCK>(twl, tw);
+  __shared__ float2 twl[PF ? tw_span(N, PL) : 1];
+  if constexpr (PF) stage_twiddles<N, BLOCK, PL>(twl, tw);
   constexpr int IT1 = (PPB * NH + BLOCK - 1) / BLOCK;
   constexpr bool FULL1 = (PPB * NH) % BLOCK == 0;
   float2 tl[IT1][7];  // three spectra of each row, the multipliers at k
@@ -626,7 +627,7 @@ __global__ __launch_bounds__((Cfg<N, G>::C_BLOCK)) void k_passC(LaunchCtx c, int
     }
   }
   __syncthreads();
-  fft_lds<N, 5 * PPB, BLOCK, true, LAYOUT_ROWS>(lds, PF ? twl : tw);
+  fft_lds<N, 5 * PPB, BLOCK, true, LAYOUT_ROWS, PL>(lds, PF ? twl : tw);
   // the coefficients at all of the thread's points are loaded before the first is used
   if constexpr (!PF) passC_load_coef<N, PPB, BLOCK>(d, row0, pre);
   passC_combine<N, PPB, BLOCK>(c, d, s, j, row0, red,

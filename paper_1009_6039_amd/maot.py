@@ -53,7 +53,7 @@ class Tuning(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("npairs", ctypes.c_int), ("variant", ctypes.c_int * 4),
                 ("from_cache", ctypes.c_int), ("rejected", ctypes.c_int),
                 ("us", ctypes.c_double * 4), ("us_default", ctypes.c_double * 4),
-                ("us_variant", (ctypes.c_double * 8) * 4)]
+                ("us_variant", (ctypes.c_double * 12) * 4)]
 
     def as_dict(self):
         return {"n": self.n, "npairs": self.npairs, "variant": list(self.variant),
@@ -64,8 +64,9 @@ class Tuning(ctypes.Structure):
 
 
 TUNE_PASSES = ("row_a", "column", "row_c", "residual")
-TUNE_VARIANTS = 8  # MA_TUNE_VARIANTS: 0..3 block-shared kernels, 4..7 wave-owned transforms
-                   # (row pass C: 4, 5 wave-owned; 6, 7 block-shared with early coefficient loads)
+TUNE_VARIANTS = 12  # MA_TUNE_VARIANTS: 0..3 block-shared kernels, 4..7 wave-owned transforms
+                    # (row pass C: 4, 5 wave-owned; 6, 7 block-shared with early coefficient
+                    # loads), 8..11 FFT radix plans
 
 
 def tune_geometry(kernel_class, n, variant):

@@ -84,9 +84,10 @@ SIZES = (16, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048)
 def test_tune_geometry_table_is_consistent(n):
     # every variant of every kernel class tiles the grid exactly with whole
     # wavefronts; duplicates point at a smaller index with the same geometry.
-    # Variants 0..3 are the block-shared kernels, 4 and 5 the wave-owned ones, and 6, 7
-    # of row pass C the block-shared ones that load coefficients first: a geometry is
-    # distinct within its family.
+    # Variants 0..3 are the block-shared kernels, 4 and 5 the wave-owned ones, 6, 7
+    # of row pass C the block-shared ones that load coefficients first, and 8..11 the
+    # radix plans (8, 10 one plan, 9, 11 the other): a geometry is distinct within its
+    # family.
     from paper_1009_6039_amd import maot
     for k in maot.TUNE_PASSES:
         seen = {}
@@ -99,7 +100,10 @@ def test_tune_geometry_table_is_consistent(n):
                 assert (n // 2) % units == 0 and (n * units) % threads == 0 and threads % units == 0
             else:
                 assert n % units == 0 and units >= 16
-            family = 0 if canon < 4 else (1 if canon < 6 else 2)
+            if canon < 8:
+                family = 0 if canon < 4 else (1 if canon < 6 else 2)
+            else:
+                family = 3 + canon % 2
             if canon < v:
                 assert seen[canon][1:] == (units, threads)
             else:

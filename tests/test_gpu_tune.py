@@ -38,7 +38,7 @@ def blob128():
     return f, g, psi
 
 
-@pytest.mark.parametrize("v", list(range(8)))
+@pytest.mark.parametrize("v", list(range(12)))
 def test_every_variant_reaches_the_oracle_solution(maot, blob128, v):
     f, g, psi_ref = blob128
     n = f.shape[0]
