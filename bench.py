@@ -84,11 +84,14 @@ def parse():
     ap.add_argument("--cpu-workers", type=int, default=min(16, os.cpu_count() or 1),
                     help="single-threaded oracle processes (the host cores used)")
     ap.add_argument("--no-configs", action="store_true",
-                    help="skip the mixed-size batch and the 2048^2 pair reported beside the headline")
+                    help="skip the configurations reported beside the headline (single pairs, mixed-size batch, "
+                         "2048^2 pair, finite differences, 3-D)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fd-only", action="store_true",
                     help="run only the finite-difference configurations (fd_bicg_256, table1_e1_256) and print them")
     ap.add_argument("--only-3d", action="store_true", help="run only the three-dimensional configuration and print it")
+    ap.add_argument("--only-single", action="store_true",
+                    help="run only the single-pair configurations (64^2 manufactured, 512^2 blob pair) and print them")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB mebibytes (scales HBM byte counters)")
     return ap.parse_args()
@@ -157,16 +160,72 @@ def cpu_baseline(pairs, args, params=None, meta=None):
     return [psi for _, _, psi in out], rate, workers, sum(dt for _, dt, _ in out)
 
 
+def single_pair_configs(args, maot, W, method, cache):
+    """The single-pair configurations, each potential compared with the oracle's stored
+    solution (tests/golden/c0_c1_reference.npz): the manufactured 64^2 pair with the
+    paper's method (spectral symbols, fixed tau = 1, GMRES tolerance 1e-4) to rms
+    residual 1e-8, and one 512^2 blob pair to the headline's residual with the paper's
+    linear solve and with the headline's (step halving, zero start).  Median of five
+    solves after a warm-up."""
+    import torch
+    ref_path = os.path.join(HERE, "tests", "golden", "c0_c1_reference.npz")
+    ref = np.load(ref_path, allow_pickle=False) if os.path.exists(ref_path) else None
+    res = {}
+
+    def timed(plan, fd, gd, tol):
+        plan.solve(fd, gd, damping=1.0, tol=tol)  # warm-up
+        t = []
+        for _ in range(5):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            psi, _, rep = plan.solve(fd, gd, damping=1.0, tol=tol)
+            torch.cuda.synchronize()
+            t.append(time.perf_counter() - t0)
+        return psi.cpu().numpy(), rep, 1e3 * float(np.median(t))
+
+    f, g, _ = W.manufactured(64)
+    plan = maot.Plan(n_max=64, batch_capacity=1, damping_policy="fixed", symbol="spectral", gmres_tol=1e-4,
+                     max_newton=MAX_NEWTON)
+    psi, rep, ms = timed(plan, torch.from_numpy(f).cuda(), torch.from_numpy(g).cuda(), 1e-8)
+    plan.close()
+    err = None if ref is None else float(np.max(np.abs(psi - ref["c0_psi"])) / np.max(np.abs(ref["c0_psi"])))
+    res["c0_manufactured_64"] = {
+        "workload": "manufactured 64 x 64 pair (psi* = 0.01 sin sin, g = 1), paper linear solve, fixed tau = 1, "
+                    "rms residual 1e-08", "ms_per_solve": round(ms, 3), "status": rep["status"],
+        "newton_iters": rep["newton_iters"], "gmres_iters": rep["gmres_iters"], "res_rms": rep["res_rms"],
+        "err_vs_oracle": err}
+    f, g = W.blobs(512, W.seed_for(1, 0))
+    fd, gd = torch.from_numpy(f).cuda(), torch.from_numpy(g).cuda()
+    for name in ("paper", method):
+        plan = maot.Plan(n_max=512, batch_capacity=1, damping_policy=args.damping_policy, max_newton=MAX_NEWTON,
+                         **method_options(name, args))
+        if cache:
+            plan.autotune(512, 1, cache)
+        psi, rep, ms = timed(plan, fd, gd, args.tol)
+        plan.close()
+        err = None
+        if ref is not None:
+            st = int(ref["c1_stride"])
+            err = float(np.max(np.abs(psi[::st, ::st] - ref["c1_psi"])) / float(ref["c1_psi_absmax"]))
+        res["c1_single_512_" + name] = {
+            "workload": "one 512 x 512 blob pair, %s linear solve, step halving, zero start, rms residual %.0e"
+                        % (name, args.tol), "ms_per_solve": round(ms, 3), "status": rep["status"],
+            "newton_iters": rep["newton_iters"], "gmres_iters": rep["gmres_iters"], "res_rms": rep["res_rms"],
+            "err_vs_oracle_sampled": err}
+    return res
+
+
 def extra_configs(args, maot, W, method, tuning_cache):
     """The other full-size configurations, timed beside the headline (not part of
-    `value`): a batch of 256 blob pairs with sides drawn from {128, 256, 384, 512}
-    (zero start, the headline's linear solve, one batched call), and one 2048^2
-    smooth-noise pair with the paper's method (spectral symbols, fixed tau = 1, GMRES
-    tolerance 1e-2) and with the headline's, its potential compared with the oracle's
-    stored solution at every 16th node (tests/golden/c2_noise_2048_reference.npz)."""
+    `value`): the single-pair configurations (single_pair_configs), a batch of 256 blob
+    pairs with sides drawn from {128, 256, 384, 512} (zero start, the headline's linear
+    solve, one batched call), and one 2048^2 smooth-noise pair with the paper's method
+    (spectral symbols, fixed tau = 1, GMRES tolerance 1e-2) and with the headline's, its
+    potential compared with the oracle's stored solution at every 16th node
+    (tests/golden/c2_noise_2048_reference.npz)."""
     import torch
-    res = {}
     cache = None if tuning_cache == "none" else tuning_cache
+    res = single_pair_configs(args, maot, W, method, cache)
     # mixed-size batch
     sizes = W.mixed_sizes(256, W.seed_for(3, 0))
     pairs = [W.blobs(n, W.seed_for(3, q)) for q, n in enumerate(sizes)]
@@ -334,16 +393,23 @@ def main():
     if args.copy_probe:
         copy_probe(args.copy_probe)
         return
-    if args.fd_only or args.only_3d:
-        from paper_1009_6039_amd import maot
-        from paper_1009_6039_amd import workloads as W
-        print(json.dumps(fd_bicg_configs(args, maot, W) if args.fd_only else configs_3d(args, maot, W)), flush=True)
-        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this solver build runs on a single device "
               "(batches of pairs would shard across GPUs without communication)",
               file=sys.stderr)
         sys.exit(2)
+    if args.fd_only or args.only_3d or args.only_single:
+        from paper_1009_6039_amd import maot
+        from paper_1009_6039_amd import workloads as W
+        if args.fd_only:
+            out = fd_bicg_configs(args, maot, W)
+        elif args.only_3d:
+            out = configs_3d(args, maot, W)
+        else:
+            out = single_pair_configs(args, maot, W, args.methods.split(",")[0],
+                                      args.tune_cache if args.tune_cache != "none" else None)
+        print(json.dumps(out), flush=True)
+        return
     import torch
     from paper_1009_6039_amd import maot
     from paper_1009_6039_amd.rocprof_summary import read_traffic_record
@@ -470,9 +536,8 @@ def main():
                                                    out["arms"][sym + "/zero"]["value"], 4)
     cls = {"row_a": 0, "column": 1, "row_c": 2, "residual": 3}[args.profile_class]
     var = plans[head[0]].get_tuning(N)[cls]
-    kname = {"row_c": "k_passC<%d, %d>", "row_a": "k_passA<%d, %d>", "column": "k_passB<%d, %d>"}.get(
-        args.profile_class, "")
-    kname = kname % (N, var) if kname and args.workload == "blobs" else ""  # the kernel as rocprofv3 names it
+    # the kernel as rocprofv3 names it
+    kname = maot.pass_kernel_name(args.profile_class, N, var) if args.workload == "blobs" else None
     rec = read_traffic_record(os.path.join(HERE, "profiles", TRAFFIC_FILE % (N, B)), kname) if kname else None
     if rec and rec.get("variant") != var:
         rec = None  # counters taken with another launch geometry

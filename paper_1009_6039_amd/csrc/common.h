@@ -205,12 +205,13 @@ __device__ inline void block_reduce(double (&v)[K], const int (&kinds)[K], doubl
 
 // Fixed-order fold of per-block partials (K values per block) inside a
 // one-block-per-pair finalize kernel: thread t takes blocks t, t + blockDim, ... in
-// that order (the loads of four of them issued before the first is combined), then a
-// block reduction.  Result valid in thread 0.
+// that order (for K < 4 the loads of four blocks issued before the first is combined;
+// K >= 4 values of one block are already that many loads), then a block reduction.
+// Result valid in thread 0.
 template <int K>
 __device__ inline void fold_partials(const double* part, int nblk, const int (&kinds)[K], double (&t)[K],
                                      double* scratch) {
-  constexpr int U = 4;
+  constexpr int U = K < 4 ? 4 : 1;
   const auto P = gmem<const double>(part);
 #pragma unroll
   for (int k = 0; k < K; ++k) t[k] = kinds[k] == 1 ? 1e300 : (kinds[k] == 2 ? -1e300 : 0.0);
@@ -234,7 +235,7 @@ __device__ inline void fold_partials(const double* part, int nblk, const int (&k
 
 // A structure staged in LDS for one thread's serial bookkeeping: the block loads it
 // 8 bytes per lane (every load issued before the first use), stores it into LDS, and
-// after the bookkeeping writes it back.  Launch with BLOCK threads.
+// after the bookkeeping writes back the words that changed.  Launch with BLOCK threads.
 template <class T, int BLOCK>
 struct StagedWords {
   static_assert(sizeof(T) % 8 == 0, "whole 8-byte words");
@@ -256,10 +257,14 @@ struct StagedWords {
       if (e < WORDS) w[e] = v[q];
     }
   }
-  static __device__ void write_back(const T* lds, T* dst) {
+  __device__ void write_back(const T* lds, T* dst) const {
     const unsigned long long* w = reinterpret_cast<const unsigned long long*>(lds);
     const auto d = gmem<unsigned long long>(reinterpret_cast<unsigned long long*>(dst));
-    for (int e = threadIdx.x; e < WORDS; e += BLOCK) d[e] = w[e];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = threadIdx.x + q * BLOCK;
+      if (e < WORDS && w[e] != v[q]) d[e] = w[e];
+    }
   }
 };
 

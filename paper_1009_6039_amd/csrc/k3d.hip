@@ -111,35 +111,57 @@ __global__ __launch_bounds__(MA3_BLOCK) void k3_res(Desc3 d, int op_mode) {
   acc[17] = -1e300;
   acc[18] = 1e300;
   acc[19] = 0.0;
+  // n^3 (and 9 n^3) stay below 2^31 for the supported sizes: 32-bit offsets
+  const auto u = gmem<const double>(d.u);
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (long)gridDim.x * blockDim.x) {
-    const int i = (int)(e / ((long)n * n)), j = (int)((e / n) % n), k = (int)(e % n);
-    auto U = [&](int a, int b, int c) { return d.u[((long)wrap3(a, n) * n + wrap3(b, n)) * n + wrap3(c, n)]; };
-    const double u0 = d.u[e];
+    const int ei = (int)e, n2 = n * n;
+    const int i = ei / n2, j = (ei / n) % n, k = ei % n;
+    // wrapped offsets of the planes i - 2..i + 2, rows j - 2..j + 2, columns k - 2..k + 2
+    int oi[5], oj[5], ok[5];
+#pragma unroll
+    for (int t = 0; t < 5; ++t) {
+      oi[t] = wrap3(i + t - 2, n) * n2;
+      oj[t] = wrap3(j + t - 2, n) * n;
+      ok[t] = wrap3(k + t - 2, n);
+    }
+    // u at the offset (a, b, c) from the point, |a|, |b|, |c| <= 2
+    auto U = [&](int a, int b, int c) { return u[oi[a + 2] + oj[b + 2] + ok[c + 2]]; };
+    const double u0 = u[ei];
     // first and second derivatives along each axis, fourth order
     double g[3], s2[3];
+#pragma unroll
     for (int a = 0; a < 3; ++a) {
       const int di = a == 0, dj = a == 1, dk = a == 2;
-      const double m2 = U(i - 2 * di, j - 2 * dj, k - 2 * dk), m1 = U(i - di, j - dj, k - dk);
-      const double p1 = U(i + di, j + dj, k + dk), p2 = U(i + 2 * di, j + 2 * dj, k + 2 * dk);
+      const double m2 = U(-2 * di, -2 * dj, -2 * dk), m1 = U(-di, -dj, -dk);
+      const double p1 = U(di, dj, dk), p2 = U(2 * di, 2 * dj, 2 * dk);
       g[a] = (m2 - 8.0 * m1 + 8.0 * p1 - p2) * (h1 / 12.0);
       s2[a] = (-m2 + 16.0 * m1 - 30.0 * u0 + 16.0 * p1 - p2) * (h2 / 12.0);
     }
     // mixed derivatives: the first-derivative formula along a applied to the one along b
+    // (the sixteen values of each loaded before the first is used)
+    constexpr double w1[4] = {1.0 / 12.0, -8.0 / 12.0, 8.0 / 12.0, -1.0 / 12.0};  // offsets -2, -1, 1, 2
+    constexpr int off[4] = {-2, -1, 1, 2};
     double mx[3];
     const int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2};
+#pragma unroll
     for (int q = 0; q < 3; ++q) {
-      double outer = 0.0;
-      for (int sa = -2; sa <= 2; ++sa) {
-        if (sa == 0) continue;
-        double inner = 0.0;
-        for (int sb = -2; sb <= 2; ++sb) {
-          if (sb == 0) continue;
+      double v[4][4];
+#pragma unroll
+      for (int ia = 0; ia < 4; ++ia)
+#pragma unroll
+        for (int ib = 0; ib < 4; ++ib) {
           int o[3] = {0, 0, 0};
-          o[pa[q]] = sa;
-          o[pb[q]] = sb;
-          inner += W1[sb + 2] * U(i + o[0], j + o[1], k + o[2]);
+          o[pa[q]] = off[ia];
+          o[pb[q]] = off[ib];
+          v[ia][ib] = U(o[0], o[1], o[2]);
         }
-        outer += W1[sa + 2] * (inner * h1);
+      double outer = 0.0;
+#pragma unroll
+      for (int ia = 0; ia < 4; ++ia) {
+        double inner = 0.0;
+#pragma unroll
+        for (int ib = 0; ib < 4; ++ib) inner += w1[ib] * v[ia][ib];
+        outer += w1[ia] * (inner * h1);
       }
       mx[q] = outer * h1;
     }
@@ -154,17 +176,26 @@ __global__ __launch_bounds__(MA3_BLOCK) void k3_res(Desc3 d, int op_mode) {
       hi[a] = lo[a] + 1 == n ? 0 : lo[a] + 1;
     }
     double gy = 0.0, gy1 = 0.0, gy2 = 0.0, gy3 = 0.0;
-    for (int c1 = 0; c1 < 2; ++c1)
-      for (int c2 = 0; c2 < 2; ++c2)
-        for (int c3 = 0; c3 < 2; ++c3) {
-          const double w = (c1 ? fr[0] : 1.0 - fr[0]) * (c2 ? fr[1] : 1.0 - fr[1]) * (c3 ? fr[2] : 1.0 - fr[2]);
-          const long idx = ((long)(c1 ? hi[0] : lo[0]) * n + (c2 ? hi[1] : lo[1])) * n + (c3 ? hi[2] : lo[2]);
-          const float4 gr = d.gg[idx];
-          gy = gy + w * d.g[idx];
-          gy1 = gy1 + w * (double)gr.x;
-          gy2 = gy2 + w * (double)gr.y;
-          gy3 = gy3 + w * (double)gr.z;
-        }
+    const auto G = gmem<const double>(d.g);
+    const auto GG = gmem<const float4>(d.gg);
+    double gc[8];  // the eight corners' values, all loaded before the first is used
+    float4 gg[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int c1 = c >> 2, c2 = (c >> 1) & 1, c3 = c & 1;
+      const int idx = ((c1 ? hi[0] : lo[0]) * n + (c2 ? hi[1] : lo[1])) * n + (c3 ? hi[2] : lo[2]);
+      gc[c] = G[idx];
+      gg[c] = GG[idx];
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int c1 = c >> 2, c2 = (c >> 1) & 1, c3 = c & 1;
+      const double w = (c1 ? fr[0] : 1.0 - fr[0]) * (c2 ? fr[1] : 1.0 - fr[1]) * (c3 ? fr[2] : 1.0 - fr[2]);
+      gy = gy + w * gc[c];
+      gy1 = gy1 + w * (double)gg[c].x;
+      gy2 = gy2 + w * (double)gg[c].y;
+      gy3 = gy3 + w * (double)gg[c].z;
+    }
     // det and cofactors of M = I + D^2 u
     const double m11 = 1.0 + s2[0], m22 = 1.0 + s2[1], m33 = 1.0 + s2[2];
     const double m12 = mx[0], m13 = mx[1], m23 = mx[2];
@@ -172,8 +203,9 @@ __global__ __launch_bounds__(MA3_BLOCK) void k3_res(Desc3 d, int op_mode) {
     const double c12 = m13 * m23 - m12 * m33, c13 = m12 * m23 - m13 * m22, c23 = m12 * m13 - m11 * m23;
     const double det = m11 * c11 + m12 * c12 + m13 * c13;
     const double fn = gy * det;
-    const double rr = d.f[e] - fn;
-    d.r[e] = (float)rr;
+    const double fe = gmem<const double>(d.f)[ei];
+    const double rr = fe - fn;
+    gmem<float>(d.r)[ei] = (float)rr;
     double cf[9] = {gy * c11, gy * c22, gy * c33, gy * c12, gy * c13, gy * c23, 0.0, 0.0, 0.0};
     if (op_mode == 0) {
       cf[6] = det * gy1;
@@ -182,14 +214,15 @@ __global__ __launch_bounds__(MA3_BLOCK) void k3_res(Desc3 d, int op_mode) {
     }
     // periodic Simpson weights (2/3 at even, 4/3 at odd indices, times 1/N per axis)
     const double ws = ((i & 1) ? 4.0 : 2.0) * ((j & 1) ? 4.0 : 2.0) * ((k & 1) ? 4.0 : 2.0) / (27.0 * N * N * N);
+#pragma unroll
     for (int q = 0; q < 9; ++q) {
-      d.coef[q * nn + e] = (float)cf[q];
+      gmem<float>(d.coef)[q * (int)nn + ei] = (float)cf[q];
       acc[3 + q] += ws * cf[q];
     }
     acc[0] += fn;
     acc[1] += rr;
     acc[2] += rr * rr;
-    acc[12] += (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) * d.f[e];
+    acc[12] += (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) * fe;
     acc[13] += u0;
     acc[14] = fmin(acc[14], det);
     acc[15] = fmin(acc[15], m11);
@@ -348,7 +381,7 @@ __global__ __launch_bounds__(256) void k3_vec_fold(Desc3 d, State3* s, int mode,
     __syncthreads();
     if (threadIdx.x == 0) arnoldi_close3(ls, jn, t[0]);
     __syncthreads();
-    StagedWords<State3, 256>::write_back(&ls, s);
+    sw.write_back(&ls, s);
     return;
   }
   fold_partials<1>(d.part, nblk, kinds, t, scratch);

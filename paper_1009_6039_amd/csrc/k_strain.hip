@@ -99,7 +99,7 @@ __global__ __launch_bounds__(256) void k_arnoldi_finalize(LaunchCtx c, int jn, i
   __syncthreads();
   if (threadIdx.x == 0) arnoldi_close(ls, c, jn, t[0]);
   __syncthreads();
-  StagedWords<PairState, 256>::write_back(&ls, &s);
+  sw.write_back(&ls, &s);
 }
 
 // the scaled right-hand side's norm (option MA_PRECOND_DIAG) from the pass-A partials:

@@ -77,6 +77,31 @@ def tune_geometry(kernel_class, n, variant):
     return c, u.value, t.value
 
 
+def pass_kernel_name(kernel_class, n, variant):
+    """The kernel that `variant` of a transform pass launches at grid size n, as the
+    profilers name it ("k_passC<512, 3, false, 0>": size, block geometry, early
+    coefficient loads, radix plan; "k_passC_w<512, 1>": a wave-owned kernel), or None."""
+    canon, units, _ = tune_geometry(kernel_class, n, variant)
+    if canon < 0 or kernel_class not in ("row_a", "column", "row_c"):
+        return None
+    base = {"row_a": "k_passA", "column": "k_passB", "row_c": "k_passC"}[kernel_class]
+    second = 3 if kernel_class == "row_c" else 2
+    pf, plan = False, 0
+    if canon >= 8:  # radix plan at the default or the second geometry
+        plan = (canon - 8) % 2 + 1
+        g = tune_geometry(kernel_class, n, 0 if canon < 10 else second)[0]
+    elif kernel_class == "row_c" and canon in (6, 7):  # early coefficient loads
+        pf = True
+        g = tune_geometry(kernel_class, n, 0 if canon == 6 else 3)[0]
+    elif canon >= 4:
+        return "%s_w<%d, %d>" % (base, n, units)
+    else:
+        g = canon
+    if kernel_class == "row_c":
+        return "%s<%d, %d, %s, %d>" % (base, n, g, "true" if pf else "false", plan)
+    return "%s<%d, %d, %d>" % (base, n, g, plan)
+
+
 class Report(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("newton_iters", ctypes.c_int),
                 ("gmres_iters", ctypes.c_int), ("backtracks", ctypes.c_int),

@@ -125,3 +125,18 @@ def test_bench_refuses_several_gpus():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_pass_kernel_names_follow_the_variant_table():
+    # the names the profilers print for the kernels a variant launches (used to match
+    # rocprofv3 summaries to the tuned geometry)
+    from paper_1009_6039_amd import maot
+    assert maot.pass_kernel_name("row_c", 512, 3) == "k_passC<512, 3, false, 0>"
+    assert maot.pass_kernel_name("row_c", 512, 1) == "k_passC<512, 0, false, 0>"  # a duplicate of 0
+    assert maot.pass_kernel_name("row_c", 512, 7) == "k_passC<512, 3, true, 0>"
+    assert maot.pass_kernel_name("row_c", 512, 4) == "k_passC_w<512, 1>"
+    assert maot.pass_kernel_name("row_c", 384, 11) == "k_passC<384, 3, false, 2>"
+    assert maot.pass_kernel_name("row_a", 512, 2) == "k_passA<512, 2, 0>"
+    assert maot.pass_kernel_name("column", 1024, 9) == "k_passB<1024, 0, 2>"
+    assert maot.pass_kernel_name("residual", 512, 3) is None
+    assert maot.pass_kernel_name("row_c", 500, 0) is None
