@@ -132,3 +132,51 @@ def test_timing_hook_times_every_kth_launch(maot, blob128, every):
             p.profile("row_c", 0)
     finally:
         p.close()
+
+
+@pytest.mark.parametrize("N", [48, 96, 384, 512, 1024])
+def test_radix_plan_variants_match_numpy_and_the_oracle(maot, N):
+    # the FFT radix plans (variants 8..11: radix 4 throughout, radix 16 where it saves a
+    # stage) at sizes whose plans differ from the default: the 2-D transform against
+    # numpy, Strain's operator and Lbar^{-1} against the oracle
+    p = maot.Plan(n_max=N, batch_capacity=1)
+    try:
+        f, g = W.blobs(N, W.seed_for(1, 11))
+        prob = ma.Problem(f, g)
+        x = np.arange(N) / N
+        X1, X2 = np.meshgrid(x, x, indexing="ij")
+        u = 0.004 * np.sin(2 * np.pi * X1 + 0.3) * np.cos(2 * np.pi * X2) + 0.002 * np.sin(4 * np.pi * X2)
+        coef = np.stack(ma.coefficients(ma.evaluate(u, prob))).astype(np.float32).astype(np.float64)
+        abar = ma.averaged(tuple(coef))
+        rho = ma.symbol(abar, N)
+        v = np.random.default_rng(N).standard_normal((N, N)).astype(np.float32)
+        v64 = v.astype(np.float64)
+        X = np.fft.fft(v64, axis=1)
+        spec_ref = np.concatenate([np.fft.fft(X[:, 0] + 1j * X[:, N // 2])[:, None],
+                                   np.fft.fft2(v64)[:, 1:N // 2]], axis=1)
+        w_ref = ma.strain_apply(v64, tuple(coef), rho)
+        th_ref = ma.lbar_inverse(v64, rho)
+
+        def rel(a, b):
+            return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+        tested = 0
+        for var in range(8, 12):
+            variant = [var if maot.tune_geometry(k, N, var)[0] == var else 0 for k in maot.TUNE_PASSES]
+            if variant[:3] == [0, 0, 0]:
+                continue  # every plan of this variant equals the default one at N
+            p.set_tuning(N, variant)
+            spec = p.step_fft2(dev(v).float())
+            torch.cuda.synchronize()
+            got = spec.cpu().numpy().astype(np.complex128)
+            w = p.step_strain_apply(dev(v).float(), dev(coef).float(), abar).cpu().numpy()
+            th = p.step_lbar_inverse(dev(v).float(), abar).cpu().numpy()
+            e = (rel(got, spec_ref), rel(w, w_ref), rel(th, th_ref))
+            print("N %d variant %d (%s): fft %.2e, operator %.2e, Lbar^-1 %.2e"
+                  % (N, var, [maot.pass_kernel_name(k, N, variant[i]) for i, k in enumerate(maot.TUNE_PASSES[:3])],
+                     *e), flush=True)
+            assert e[0] < 2e-6 and e[1] < 1e-4 and e[2] < 1e-4, (var, e)
+            tested += 1
+        assert tested > 0
+    finally:
+        p.close()
