@@ -433,19 +433,37 @@ __global__ void k3_cycle_begin(State3* s) {
 // ---------------------------------------------------------------------------
 // line-transform passes
 // ---------------------------------------------------------------------------
+// The line passes below issue every global load of a phase before the phase's first
+// LDS write, and read their twiddles from an LDS copy of the table (so that no
+// in-order wait on a twiddle load holds back the other loads in flight).
+
 // P1: real input along x3 -> complex forward transform -> S.  Input: V[j] (matvec) or x.
 template <int N>
 __global__ __launch_bounds__(MA3_BLOCK) void k3_p1(Desc3 d, const State3* s, int mode, int j) {
   if (mode == P3_MATVEC && !s->gm_running) return;
   constexpr int R = Lines3<N>::P1;  // lines per block
+  constexpr int PER = R * N / MA3_BLOCK;
+  static_assert((R * N) % MA3_BLOCK == 0, "whole elements per thread");
   __shared__ float2 L[R * N];
+  __shared__ float2 twl[tw_span(N)];
   const long nn = (long)N * N * N;
   const float* in = mode == P3_MATVEC ? d.V + (long)j * nn : d.x;
   const long base = (long)blockIdx.x * R * N;
-  for (int e = threadIdx.x; e < R * N; e += MA3_BLOCK) L[e] = make_float2(in[base + e], 0.f);
+  float x[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) x[q] = in[base + threadIdx.x + q * MA3_BLOCK];
+  stage_twiddles<N, MA3_BLOCK>(twl, d.tw);
+#pragma unroll
+  for (int q = 0; q < PER; ++q) L[threadIdx.x + q * MA3_BLOCK] = make_float2(x[q], 0.f);
   __syncthreads();
-  fft_lds<N, R, MA3_BLOCK, false, LAYOUT_ROWS>(L, d.tw);
+  fft_lds<N, R, MA3_BLOCK, false, LAYOUT_ROWS>(L, twl);
   for (int e = threadIdx.x; e < R * N; e += MA3_BLOCK) d.S[base + e] = L[e];
+}
+
+// element e of a block's tile in the x1 / x2 passes: line e % C, position e / C along it
+template <int N, int C>
+__device__ __forceinline__ long col_index(long plane_or_row_base, long stride, int e) {
+  return plane_or_row_base + (long)(e / C) * stride + (e % C);
 }
 
 // P2: forward transform along x2, in place; a block takes COLS consecutive x3 indices
@@ -454,24 +472,27 @@ template <int N>
 __global__ __launch_bounds__(MA3_BLOCK) void k3_p2(Desc3 d, const State3* s, int mode) {
   if (mode == P3_MATVEC && !s->gm_running) return;
   constexpr int C = COLS < N ? COLS : N;
+  constexpr int PER = N * C / MA3_BLOCK;
+  static_assert((N * C) % MA3_BLOCK == 0, "whole elements per thread");
   __shared__ float2 L[N * C];
+  __shared__ float2 twl[tw_span(N)];
   const int i = blockIdx.x / (N / C), k0 = (blockIdx.x % (N / C)) * C;
-  for (int e = threadIdx.x; e < N * C; e += MA3_BLOCK) {
-    const int jj = e / C, t = e % C;
-    L[e] = d.S[((long)i * N + jj) * N + k0 + t];
-  }
+  const long b0 = (long)i * N * N + k0;  // element (i, jj, k0 + t) at b0 + jj N + t
+  float2 v[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) v[q] = d.S[col_index<N, C>(b0, N, threadIdx.x + q * MA3_BLOCK)];
+  stage_twiddles<N, MA3_BLOCK>(twl, d.tw);
+#pragma unroll
+  for (int q = 0; q < PER; ++q) L[threadIdx.x + q * MA3_BLOCK] = v[q];
   __syncthreads();
-  fft_lds<N, C, MA3_BLOCK, false, LAYOUT_COLS>(L, d.tw);
-  for (int e = threadIdx.x; e < N * C; e += MA3_BLOCK) {
-    const int jj = e / C, t = e % C;
-    d.S[((long)i * N + jj) * N + k0 + t] = L[e];
-  }
+  fft_lds<N, C, MA3_BLOCK, false, LAYOUT_COLS>(L, twl);
+  for (int e = threadIdx.x; e < N * C; e += MA3_BLOCK) d.S[col_index<N, C>(b0, N, e)] = L[e];
 }
 
-// rhobar(k) for wavenumber indices (q1, q2, q3): the inverse symbol of the averaged
-// operator, zero where it vanishes (k = 0)
-__device__ __forceinline__ float2 rhobar3(int q1, int q2, int q3, const float (&ab)[9], const float2* mt) {
-  const float2 m1 = mt[q1], m2 = mt[q2], m3 = mt[q3];
+// rhobar(k) from the multipliers of the wavenumber indices (q1, q2, q3): the inverse
+// symbol of the averaged operator, zero where it vanishes (k = 0)
+__device__ __forceinline__ float2 rhobar3(int q1, int q2, int q3, float2 m1, float2 m2, float2 m3,
+                                          const float (&ab)[9]) {
   // S = sum a_aa d2(k_a) + 2 sum_{a<b} a_ab (i d1(k_a))(i d1(k_b)) + i sum b_a d1(k_a)
   const float re = ab[0] * m1.y + ab[1] * m2.y + ab[2] * m3.y -
                    2.f * (ab[3] * m1.x * m2.x + ab[4] * m1.x * m3.x + ab[5] * m2.x * m3.x);
@@ -489,80 +510,101 @@ __global__ __launch_bounds__(MA3_BLOCK) void k3_p3(Desc3 d, const State3* s, int
   if (mode == P3_MATVEC && !s->gm_running) return;
   constexpr int C = COLS < N ? COLS : N;
   constexpr long NN = (long)N * N * N;
+  constexpr int PER = N * C / MA3_BLOCK;
+  static_assert((N * C) % MA3_BLOCK == 0, "whole elements per thread");
   __shared__ float2 L[N * C];
+  __shared__ float2 twl[tw_span(N)];
   const int jj = blockIdx.x / (N / C), k0 = (blockIdx.x % (N / C)) * C;
-  for (int e = threadIdx.x; e < N * C; e += MA3_BLOCK) {
-    const int i = e / C, t = e % C;
-    L[e] = d.S[((long)i * N + jj) * N + k0 + t];
-  }
-  __syncthreads();
-  fft_lds<N, C, MA3_BLOCK, false, LAYOUT_COLS>(L, d.tw);
+  const long b0 = (long)jj * N + k0;  // element (i, jj, k0 + t) at b0 + i N^2 + t
+  float2 v[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) v[q] = d.S[col_index<N, C>(b0, (long)N * N, threadIdx.x + q * MA3_BLOCK)];
+  float2 m[PER];  // multipliers at the thread's wavenumbers k1 = e / C
+#pragma unroll
+  for (int q = 0; q < PER; ++q) m[q] = d.mt[(threadIdx.x + q * MA3_BLOCK) / C];
+  const int t = threadIdx.x % C;  // the thread's x3 index k0 + t (the same for every q)
+  const float2 m2 = d.mt[jj], m3 = d.mt[k0 + t];
   float ab[9];
   for (int q = 0; q < 9; ++q) ab[q] = (float)s->abar[q];
   const float scale = (float)((mode == P3_MATVEC ? s->vscale[j] : 1.0) / ((double)N * N * N));
+  stage_twiddles<N, MA3_BLOCK>(twl, d.tw);
+#pragma unroll
+  for (int q = 0; q < PER; ++q) L[threadIdx.x + q * MA3_BLOCK] = v[q];
+  __syncthreads();
+  fft_lds<N, C, MA3_BLOCK, false, LAYOUT_COLS>(L, twl);
   // Z = rhobar * spectrum * scale, kept in registers (each thread its own elements)
-  constexpr int PER = (N * C + MA3_BLOCK - 1) / MA3_BLOCK;
   float2 z[PER];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int e = threadIdx.x + q * MA3_BLOCK;
-    z[q] = make_float2(0.f, 0.f);
-    if (e < N * C) {
-      const int i = e / C, t = e % C;
-      const float2 rb = rhobar3(i, jj, k0 + t, ab, d.mt);
-      z[q] = cscale(cmul(rb, L[e]), scale);
-    }
+    const float2 rb = rhobar3(e / C, jj, k0 + t, m[q], m2, m3, ab);
+    z[q] = cscale(cmul(rb, L[e]), scale);
   }
   const int outs = mode == P3_MATVEC ? 3 : 1;
   for (int o = 0; o < outs; ++o) {
     __syncthreads();  // the previous transform's results have been stored
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-      const int e = threadIdx.x + q * MA3_BLOCK;
-      if (e < N * C) {
-        const float2 m = d.mt[e / C];
-        // o = 0: Z; o = 1: i d1(k1) Z; o = 2: d2(k1) Z
-        L[e] = o == 0 ? z[q] : (o == 1 ? make_float2(-m.x * z[q].y, m.x * z[q].x) : cscale(z[q], m.y));
-      }
+      // o = 0: Z; o = 1: i d1(k1) Z; o = 2: d2(k1) Z
+      L[threadIdx.x + q * MA3_BLOCK] =
+          o == 0 ? z[q] : (o == 1 ? make_float2(-m[q].x * z[q].y, m[q].x * z[q].x) : cscale(z[q], m[q].y));
     }
     __syncthreads();
-    fft_lds<N, C, MA3_BLOCK, true, LAYOUT_COLS>(L, d.tw);
+    fft_lds<N, C, MA3_BLOCK, true, LAYOUT_COLS>(L, twl);
     float2* T = d.T + (long)o * NN;
-    for (int e = threadIdx.x; e < N * C; e += MA3_BLOCK) {
-      const int i = e / C, t = e % C;
-      T[((long)i * N + jj) * N + k0 + t] = L[e];
-    }
+    for (int e = threadIdx.x; e < N * C; e += MA3_BLOCK) T[col_index<N, C>(b0, (long)N * N, e)] = L[e];
   }
 }
 
 // P4: inverse transforms along x2 of T2, T1, i k2 T1, T0, i k2 T0, -k2^2 T0 -> U_a..U_f
 // (theta: T0 -> U_d only).  A block takes COLS consecutive x3 indices of one x1 plane.
+// Each source plane is loaded once (the next one's loads issued before the current
+// one's transforms) and every output derived from it is transformed in turn.
 template <int N>
 __global__ __launch_bounds__(MA3_BLOCK) void k3_p4(Desc3 d, const State3* s, int mode) {
   if (mode == P3_MATVEC && !s->gm_running) return;
   constexpr int C = COLS < N ? COLS : N;
   constexpr long NN = (long)N * N * N;
+  constexpr int PER = N * C / MA3_BLOCK;
+  static_assert((N * C) % MA3_BLOCK == 0, "whole elements per thread");
   __shared__ float2 L[N * C];
+  __shared__ float2 twl[tw_span(N)];
   const int i = blockIdx.x / (N / C), k0 = (blockIdx.x % (N / C)) * C;
-  // (source T plane, multiplier: 0 one, 1 i d1(k2), 2 d2(k2), destination U plane)
-  const int plan[6][3] = {{2, 0, 0}, {1, 0, 1}, {1, 1, 2}, {0, 0, 3}, {0, 1, 4}, {0, 2, 5}};
-  const int first = mode == P3_MATVEC ? 0 : 3, last = mode == P3_MATVEC ? 6 : 4;
-  for (int o = first; o < last; ++o) {
-    const float2* T = d.T + (long)plan[o][0] * NN;
-    for (int e = threadIdx.x; e < N * C; e += MA3_BLOCK) {
-      const int jj = e / C, t = e % C;
-      const float2 v = T[((long)i * N + jj) * N + k0 + t];
-      const float2 m = d.mt[jj];
-      L[e] = plan[o][1] == 0 ? v : (plan[o][1] == 1 ? make_float2(-m.x * v.y, m.x * v.x) : cscale(v, m.y));
+  const long b0 = (long)i * N * N + k0;
+  // sources in order (T plane, first output, outputs): T2 -> U_a; T1 -> U_b, U_c (i d1);
+  // T0 -> U_d, U_e (i d1), U_f (d2); theta: T0 -> U_d
+  const bool mv = mode == P3_MATVEC;
+  const int nsrc = mv ? 3 : 1;
+  auto src_plane = [&](int si) { return mv ? 2 - si : 0; };
+  float2 cur[PER], nxt[PER], m[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) cur[q] = d.T[src_plane(0) * NN + col_index<N, C>(b0, N, threadIdx.x + q * MA3_BLOCK)];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) m[q] = d.mt[(threadIdx.x + q * MA3_BLOCK) / C];
+  stage_twiddles<N, MA3_BLOCK>(twl, d.tw);
+  int out = mv ? 0 : 3;
+  for (int si = 0; si < nsrc; ++si) {
+    if (si + 1 < nsrc) {
+#pragma unroll
+      for (int q = 0; q < PER; ++q)
+        nxt[q] = d.T[src_plane(si + 1) * NN + col_index<N, C>(b0, N, threadIdx.x + q * MA3_BLOCK)];
     }
-    __syncthreads();
-    fft_lds<N, C, MA3_BLOCK, true, LAYOUT_COLS>(L, d.tw);
-    float2* Uo = d.U + (long)plan[o][2] * NN;
-    for (int e = threadIdx.x; e < N * C; e += MA3_BLOCK) {
-      const int jj = e / C, t = e % C;
-      Uo[((long)i * N + jj) * N + k0 + t] = L[e];
+    const int nmul = mv ? si + 1 : 1;  // multipliers 0 .. nmul - 1: one, i d1(k2), d2(k2)
+    for (int mu = 0; mu < nmul; ++mu, ++out) {
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const float2 v = cur[q];
+        L[threadIdx.x + q * MA3_BLOCK] =
+            mu == 0 ? v : (mu == 1 ? make_float2(-m[q].x * v.y, m[q].x * v.x) : cscale(v, m[q].y));
+      }
+      __syncthreads();
+      fft_lds<N, C, MA3_BLOCK, true, LAYOUT_COLS>(L, twl);
+      float2* Uo = d.U + (long)out * NN;
+      for (int e = threadIdx.x; e < N * C; e += MA3_BLOCK) Uo[col_index<N, C>(b0, N, e)] = L[e];
+      __syncthreads();  // the stores have read L before the next transform overwrites it
     }
-    __syncthreads();  // the stores have read L before the next transform overwrites it
+#pragma unroll
+    for (int q = 0; q < PER; ++q) cur[q] = nxt[q];
   }
 }
 
@@ -575,14 +617,22 @@ __global__ __launch_bounds__(MA3_BLOCK) void k3_p5(Desc3 d, const State3* s, int
   constexpr long NN = (long)N * N * N;
   constexpr int R5 = Lines3<N>::P5;  // lines per block
   constexpr int NT = 5;              // transforms per line
+  constexpr int PER = R5 * N / MA3_BLOCK;
+  static_assert((R5 * N) % MA3_BLOCK == 0, "whole elements per thread");
   __shared__ float2 L[NT * R5 * N];
+  __shared__ float2 twl[tw_span(N)];
   __shared__ double red[(MA3_BLOCK / 64) * (MA3_MMAX + 1)];
   const long base = (long)blockIdx.x * R5 * N;  // first element of the block's lines
   if (mode != P3_MATVEC) {
     const float2* Ud = d.U + 3 * NN;
-    for (int e = threadIdx.x; e < R5 * N; e += MA3_BLOCK) L[e] = Ud[base + e];
+    float2 v[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) v[q] = Ud[base + threadIdx.x + q * MA3_BLOCK];
+    stage_twiddles<N, MA3_BLOCK>(twl, d.tw);
+#pragma unroll
+    for (int q = 0; q < PER; ++q) L[threadIdx.x + q * MA3_BLOCK] = v[q];
     __syncthreads();
-    fft_lds<N, R5, MA3_BLOCK, true, LAYOUT_ROWS>(L, d.tw);
+    fft_lds<N, R5, MA3_BLOCK, true, LAYOUT_ROWS>(L, twl);
     for (int e = threadIdx.x; e < R5 * N; e += MA3_BLOCK) {
       const double th = (double)L[e].x;
       if (mode == P3_THETA) {
@@ -600,16 +650,25 @@ __global__ __launch_bounds__(MA3_BLOCK) void k3_p5(Desc3 d, const State3* s, int
   //   2: U_f + i U_e        -> alpha22, beta2
   //   3: i d1 U_e + i d2 U_d -> alpha23, alpha33
   //   4: i d1 U_d           -> beta3
-  for (int e = threadIdx.x; e < R5 * N; e += MA3_BLOCK) {
+  float2 uv[6][PER], m[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const long g = base + threadIdx.x + q * MA3_BLOCK;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) uv[c][q] = d.U[c * NN + g];
+    m[q] = d.mt[(threadIdx.x + q * MA3_BLOCK) % N];
+  }
+  stage_twiddles<N, MA3_BLOCK>(twl, d.tw);
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = threadIdx.x + q * MA3_BLOCK;
     const int l = e / N, k = e % N;
-    const long g = base + e;
-    const float2 ua = d.U[g], ub = d.U[NN + g], uc = d.U[2 * NN + g], ud = d.U[3 * NN + g];
-    const float2 ue = d.U[4 * NN + g], uf = d.U[5 * NN + g];
-    const float2 m = d.mt[k];
-    const float2 ib = make_float2(-m.x * ub.y, m.x * ub.x);  // i d1(k3) U_b
-    const float2 ie = make_float2(-m.x * ue.y, m.x * ue.x);
-    const float2 id = make_float2(-m.x * ud.y, m.x * ud.x);
-    const float2 qd = cscale(ud, m.y);
+    const float2 ua = uv[0][q], ub = uv[1][q], uc = uv[2][q], ud = uv[3][q], ue = uv[4][q], uf = uv[5][q];
+    const float2 mk = m[q];
+    const float2 ib = make_float2(-mk.x * ub.y, mk.x * ub.x);  // i d1(k3) U_b
+    const float2 ie = make_float2(-mk.x * ue.y, mk.x * ue.x);
+    const float2 id = make_float2(-mk.x * ud.y, mk.x * ud.x);
+    const float2 qd = cscale(ud, mk.y);
     // X + i Y for spectra X, Y of real signals
     L[(0 * R5 + l) * N + k] = make_float2(ua.x - ub.y, ua.y + ub.x);
     L[(1 * R5 + l) * N + k] = make_float2(uc.x - ib.y, uc.y + ib.x);
@@ -618,39 +677,50 @@ __global__ __launch_bounds__(MA3_BLOCK) void k3_p5(Desc3 d, const State3* s, int
     L[(4 * R5 + l) * N + k] = id;
   }
   __syncthreads();
-  fft_lds<N, NT * R5, MA3_BLOCK, true, LAYOUT_ROWS>(L, d.tw);
+  fft_lds<N, NT * R5, MA3_BLOCK, true, LAYOUT_ROWS>(L, twl);
   float* W = d.V + (long)(j + 1) * NN;
-  constexpr int PER = (R5 * N + MA3_BLOCK - 1) / MA3_BLOCK;
+  // the nine coefficients at all of the thread's points, loaded before the first is used
+  float cf[9][PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q)
+#pragma unroll
+    for (int c = 0; c < 9; ++c) cf[c][q] = d.coef[c * NN + base + threadIdx.x + q * MA3_BLOCK];
   float w[PER];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int e = threadIdx.x + q * MA3_BLOCK;
-    w[q] = 0.f;
-    if (e >= R5 * N) continue;
     const int l = e / N, k = e % N;
     const long g = base + e;
     const float2 z0 = L[(0 * R5 + l) * N + k], z1 = L[(1 * R5 + l) * N + k], z2 = L[(2 * R5 + l) * N + k];
     const float2 z3 = L[(3 * R5 + l) * N + k], z4 = L[(4 * R5 + l) * N + k];
-    const float* cf = d.coef;
     // a11 a11 + a22 a22 + a33 a33 + 2 (a12 a12 + a13 a13 + a23 a23) + b . beta
-    const float v = cf[g] * z0.x + cf[NN + g] * z2.x + cf[2 * NN + g] * z3.y +
-                    2.f * (cf[3 * NN + g] * z1.x + cf[4 * NN + g] * z1.y + cf[5 * NN + g] * z3.x) +
-                    cf[6 * NN + g] * z0.y + cf[7 * NN + g] * z2.y + cf[8 * NN + g] * z4.x;
+    const float v = cf[0][q] * z0.x + cf[1][q] * z2.x + cf[2][q] * z3.y +
+                    2.f * (cf[3][q] * z1.x + cf[4][q] * z1.y + cf[5][q] * z3.x) + cf[6][q] * z0.y +
+                    cf[7][q] * z2.y + cf[8][q] * z4.x;
     W[g] = v;
     w[q] = v;
   }
   // inner products <w, V_l>, l <= j, per block (fixed order); folded by k3_dots_fold
+  // (the loads of V_{l+1} issued before <w, V_l> is reduced)
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  float vl[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) vl[q] = d.V[base + threadIdx.x + q * MA3_BLOCK];
   for (int lv = 0; lv <= j; ++lv) {
-    const float* Vl = d.V + (long)lv * NN;
+    float vn[PER];
+    if (lv < j) {
+#pragma unroll
+      for (int q = 0; q < PER; ++q) vn[q] = d.V[(long)(lv + 1) * NN + base + threadIdx.x + q * MA3_BLOCK];
+    }
     float acc = 0.f;
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int e = threadIdx.x + q * MA3_BLOCK;
-      if (e < R5 * N) acc += w[q] * Vl[base + e];
-    }
+    for (int q = 0; q < PER; ++q) acc += w[q] * vl[q];
     const double v = wave_sum((double)acc);
     if (lane == 0) red[wid * (MA3_MMAX + 1) + lv] = v;
+    if (lv < j) {
+#pragma unroll
+      for (int q = 0; q < PER; ++q) vl[q] = vn[q];
+    }
   }
   __syncthreads();
   if (threadIdx.x <= j) {

@@ -61,7 +61,7 @@ __device__ void arnoldi_close(PairState& s, const LaunchCtx& c, int jn, double w
 }
 
 // h[l][j] = <w, v_l> for l <= j from the pass-C partials (one block per pair).
-// Lane l of group g sums blocks g, g + 8, ... (16 loads in flight per round).
+// Lane l of group g sums blocks g, g + 8, ... (32 loads in flight per round).
 __global__ __launch_bounds__(256) void k_dots_finalize(LaunchCtx c, int j, int nblk) {
   const int p = pair_of_block(c);
   if (p < 0) return;
@@ -70,7 +70,7 @@ __global__ __launch_bounds__(256) void k_dots_finalize(LaunchCtx c, int j, int n
   if (!(s.phase == PH_SOLVE && s.gm_running)) return;
   __shared__ double red[8][32];
   const int l = threadIdx.x & 31, grp = threadIdx.x >> 5;
-  const double t = l <= j ? strided_sum<16>(d.part, MA_MMAX + 1, l, grp, 8, nblk) : 0.0;
+  const double t = l <= j ? strided_sum<32>(d.part, MA_MMAX + 1, l, grp, 8, nblk) : 0.0;
   red[grp][l] = t;
   __syncthreads();
   if (threadIdx.x <= j) {
