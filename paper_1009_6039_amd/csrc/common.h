@@ -161,20 +161,62 @@ __device__ inline int pair_of_block(const LaunchCtx& c) {
 // ---------------------------------------------------------------------------
 // Block reductions (FP64), deterministic order.
 // ---------------------------------------------------------------------------
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+// Cross-lane moves of a double by DPP (VALU moves, no LDS traffic); lanes without a
+// source read 0.  CTRL: 0x110 + n, row shift right (lane i of a row of 16 reads lane
+// i - n of the row); 0x138, wave shift right (lane i reads lane i - 1); 0x130, wave
+// shift left (lane i reads lane i + 1).
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, true);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
+template <int SHIFT>
+__device__ __forceinline__ double row_shr(double v) {
+  static_assert(SHIFT >= 1 && SHIFT <= 15, "row shift");
+  return dpp_move<0x110 + SHIFT>(v);
+}
+// the same row shift, lanes without a source reading `fill`
+template <int SHIFT>
+__device__ __forceinline__ double row_shr_or(double v, double fill) {
+  static_assert(SHIFT >= 1 && SHIFT <= 15, "row shift");
+  const long long b = __double_as_longlong(v), f = __double_as_longlong(fill);
+  const int lo = __builtin_amdgcn_update_dpp((int)f, (int)b, 0x110 + SHIFT, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(f >> 32), (int)(b >> 32), 0x110 + SHIFT, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ double read_lane(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+// Sum over the 64 lanes (every lane active), the same in every lane, in a fixed order:
+// inclusive prefix sums within each row of 16 lanes by DPP row shifts of 1, 2, 4 and 8,
+// then the four row totals (lanes 15, 31, 47, 63) added pairwise.
+__device__ inline double wave_sum(double v) {
+  v += row_shr<1>(v);
+  v += row_shr<2>(v);
+  v += row_shr<4>(v);
+  v += row_shr<8>(v);
+  return (read_lane(v, 15) + read_lane(v, 31)) + (read_lane(v, 47) + read_lane(v, 63));
+}
+// minimum and maximum over the 64 lanes in the same pattern (shifted-in lanes read the
+// operation's identity)
 __device__ inline double wave_min(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-  return v;
+  v = fmin(v, row_shr_or<1>(v, INFINITY));
+  v = fmin(v, row_shr_or<2>(v, INFINITY));
+  v = fmin(v, row_shr_or<4>(v, INFINITY));
+  v = fmin(v, row_shr_or<8>(v, INFINITY));
+  return fmin(fmin(read_lane(v, 15), read_lane(v, 31)), fmin(read_lane(v, 47), read_lane(v, 63)));
 }
 __device__ inline double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
+  v = fmax(v, row_shr_or<1>(v, -INFINITY));
+  v = fmax(v, row_shr_or<2>(v, -INFINITY));
+  v = fmax(v, row_shr_or<4>(v, -INFINITY));
+  v = fmax(v, row_shr_or<8>(v, -INFINITY));
+  return fmax(fmax(read_lane(v, 15), read_lane(v, 31)), fmax(read_lane(v, 47), read_lane(v, 63)));
 }
 
 // Reduces K values per thread across the block; result valid in thread 0 only.

@@ -356,13 +356,6 @@ __global__ __launch_bounds__(MA_BLOCK) void k_residual(LaunchCtx c) {
     for (int k = 0; k < MA_NPART_RES; ++k) d.part[(long)blockIdx.x * MA_NPART_RES + k] = acc[k];
 }
 
-// a double of lane l, read by every lane (two 32-bit lane reads)
-__device__ __forceinline__ double lane_read(double x, int l) {
-  const long long b = __double_as_longlong(x);
-  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffLL), l);
-  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)((unsigned long long)b >> 32), l);
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
 
 // Streaming variant: a wave takes 64 consecutive columns j0 .. j0+63 and walks down
 // RPW rows.  The five rows of u around the current row sit in registers (a sliding
@@ -402,9 +395,10 @@ __global__ __launch_bounds__(MA_RES_STREAM_BLOCK) void k_residual_stream(LaunchC
   // x2 stencils of one row: q = the first-difference combination (unscaled), d2 the
   // second derivative
   auto across = [&](double v, double hv, double& q, double& d2) {
-    const double h0 = lane_read(hv, 0), h1 = lane_read(hv, 1), h2 = lane_read(hv, 2), h3 = lane_read(hv, 3);
-    double vm1 = __shfl(v, lane - 1, 64), vm2 = __shfl(v, lane - 2, 64);
-    double vp1 = __shfl(v, lane + 1, 64), vp2 = __shfl(v, lane + 2, 64);
+    const double h0 = read_lane(hv, 0), h1 = read_lane(hv, 1), h2 = read_lane(hv, 2), h3 = read_lane(hv, 3);
+    // neighbours by DPP wave shifts (lanes 0, 1, 62, 63 take the halo values below)
+    double vm1 = dpp_move<0x138>(v), vp1 = dpp_move<0x130>(v);
+    double vm2 = dpp_move<0x138>(vm1), vp2 = dpp_move<0x130>(vp1);
     vm1 = lane >= 1 ? vm1 : h1;
     vm2 = lane >= 2 ? vm2 : (lane == 1 ? h1 : h0);
     vp1 = lane <= 62 ? vp1 : h2;
