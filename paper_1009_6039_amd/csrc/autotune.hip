@@ -127,15 +127,6 @@ std::string arch_name() {
 }
 
 // one entry per line: {"arch": "...", "source": "...", "n": N, "pairs": P, "m": M, "v": [a, b, c, r], ...}
-bool field_str(const std::string& line, const char* key, std::string& out) {
-  const std::string k = std::string("\"") + key + "\": \"";
-  const size_t i = line.find(k);
-  if (i == std::string::npos) return false;
-  const size_t j = line.find('"', i + k.size());
-  if (j == std::string::npos) return false;
-  out = line.substr(i + k.size(), j - i - k.size());
-  return true;
-}
 bool field_ints(const std::string& line, const char* key, int* out, int count) {
   const std::string k = std::string("\"") + key + "\": ";
   size_t i = line.find(k);
@@ -276,8 +267,8 @@ int tune_passes(const TunerView& view, ma_tuning* t, hipStream_t st) {
     t->variant[pass] = best_v;
     t->us[pass] = best;
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   return err;
 }
 

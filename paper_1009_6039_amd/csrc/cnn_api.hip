@@ -17,7 +17,7 @@ struct Buf {
   size_t bytes = 0;
   int ensure(size_t b) {
     if (b <= bytes) return MA_OK;
-    if (p) hipFree(p);
+    if (p) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
     if (hipMalloc(&p, b) != hipSuccess) return MA_ENOMEM;
@@ -25,7 +25,7 @@ struct Buf {
     return MA_OK;
   }
   void release() {
-    if (p) hipFree(p);
+    if (p) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
   }
@@ -159,9 +159,11 @@ int ma_cnn_create(int layers, int channels, int n_net, int max_batch, const int*
     ma_cnn_destroy(N);
     return MA_ENOMEM;
   }
-  hipMemset(N->params, 0, pb);
-  hipMemset(N->m, 0, pb);
-  hipMemset(N->v, 0, pb);
+  if (hipMemset(N->params, 0, pb) != hipSuccess || hipMemset(N->m, 0, pb) != hipSuccess ||
+      hipMemset(N->v, 0, pb) != hipSuccess) {
+    ma_cnn_destroy(N);
+    return MA_EHIP;
+  }
   N->wfwd.resize(layers);
   N->wbwd.resize(layers);
   N->act.resize(layers - 1);
@@ -194,7 +196,7 @@ int ma_cnn_create(int layers, int channels, int n_net, int max_batch, const int*
 void ma_cnn_destroy(ma_cnn* N) {
   if (!N) return;
   for (float* p : {N->params, N->grads, N->m, N->v})
-    if (p) hipFree(p);
+    if (p) (void)hipFree(p);
   for (auto& b : N->wfwd) b.release();
   for (auto& b : N->wbwd) b.release();
   for (auto& b : N->act) b.release();

@@ -99,7 +99,6 @@ __global__ __launch_bounds__(MA3_BLOCK) void k3_fields(Desc3 d, const State3* s)
 // ---------------------------------------------------------------------------
 // residual and coefficients (eq. ma2, eq. linearmaeq in 3-D; Section 4)
 // ---------------------------------------------------------------------------
-__device__ constexpr double W1[5] = {1.0 / 12.0, -8.0 / 12.0, 0.0, 8.0 / 12.0, -1.0 / 12.0};
 
 __global__ __launch_bounds__(MA3_BLOCK) void k3_res(Desc3 d, int op_mode) {
   const int n = d.n;

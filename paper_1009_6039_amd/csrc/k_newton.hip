@@ -14,7 +14,6 @@ __global__ __launch_bounds__(MA_BLOCK) void k_setup_sums(LaunchCtx c, int nblk) 
   const int p = pair_of_block(c);
   if (p < 0) return;
   const PairDesc& d = c.desc[p];
-  PairState& s = c.st[p];
   const long nn = (long)d.n * d.n;
   double sf = 0, sg = 0, sp = 0, bad = 0;
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (long)nblk * blockDim.x) {

@@ -185,7 +185,7 @@ int ensure_twiddles(ma_plan* P, int n) {
   float2* d = nullptr;
   if (hipMalloc(&d, sizeof(float2) * n) != hipSuccess) return MA_ENOMEM;
   if (hipMemcpy(d, h.data(), sizeof(float2) * n, hipMemcpyHostToDevice) != hipSuccess) {
-    hipFree(d);
+    (void)hipFree(d);
     return MA_EHIP;
   }
   P->tw[n] = d;
@@ -222,7 +222,7 @@ int ensure_multipliers(ma_plan* P, int n, int symbol) {
   float2* d = nullptr;
   if (hipMalloc(&d, sizeof(float2) * n) != hipSuccess) return MA_ENOMEM;
   if (hipMemcpy(d, h.data(), sizeof(float2) * n, hipMemcpyHostToDevice) != hipSuccess) {
-    hipFree(d);
+    (void)hipFree(d);
     return MA_EHIP;
   }
   P->mt[key] = d;
@@ -235,7 +235,7 @@ int ensure_workspace(ma_plan* P, const std::vector<int>& ns) {
   size_t need = 0;
   for (int n : ns) need += pair_bytes(n, m, uses_bicg(P->opt));
   if (need > P->arena_bytes) {
-    if (P->arena) hipFree(P->arena);
+    if (P->arena) (void)hipFree(P->arena);
     P->arena = nullptr;
     P->arena_bytes = 0;
     if (hipMalloc(&P->arena, need) != hipSuccess) return MA_ENOMEM;
@@ -243,9 +243,9 @@ int ensure_workspace(ma_plan* P, const std::vector<int>& ns) {
   }
   const int np = (int)ns.size();
   if (np > P->pairs_cap) {
-    if (P->d_desc) hipFree(P->d_desc);
-    if (P->d_state) hipFree(P->d_state);
-    if (P->d_ids) hipFree(P->d_ids);
+    if (P->d_desc) (void)hipFree(P->d_desc);
+    if (P->d_state) (void)hipFree(P->d_state);
+    if (P->d_ids) (void)hipFree(P->d_ids);
     if (P->d_lists) (void)hipFree(P->d_lists);
     P->d_desc = nullptr;
     P->d_state = nullptr;
@@ -1033,20 +1033,20 @@ int ma_plan_create(int n_max, int batch_capacity, const ma_options* opt, ma_plan
 
 void ma_plan_destroy(ma_plan* P) {
   if (!P) return;
-  if (P->arena) hipFree(P->arena);
-  if (P->d_desc) hipFree(P->d_desc);
-  if (P->d_state) hipFree(P->d_state);
-  if (P->d_ids) hipFree(P->d_ids);
+  if (P->arena) (void)hipFree(P->arena);
+  if (P->d_desc) (void)hipFree(P->d_desc);
+  if (P->d_state) (void)hipFree(P->d_state);
+  if (P->d_ids) (void)hipFree(P->d_ids);
   if (P->d_lists) (void)hipFree(P->d_lists);
-  if (P->h_summary) hipHostFree(P->h_summary);
+  if (P->h_summary) (void)hipHostFree(P->h_summary);
   if (P->d_final) (void)hipFree(P->d_final);
   if (P->h_phase) (void)hipHostFree(P->h_phase);
   if (P->h_stage) (void)hipHostFree(P->h_stage);
   if (P->d_stage) (void)hipFree(P->d_stage);
-  for (auto& kv : P->tw) hipFree(kv.second);
-  for (auto& kv : P->mt) hipFree(kv.second);
-  for (hipEvent_t e : P->ev) hipEventDestroy(e);
-  if (P->d_prof) hipFree(P->d_prof);
+  for (auto& kv : P->tw) (void)hipFree(kv.second);
+  for (auto& kv : P->mt) (void)hipFree(kv.second);
+  for (hipEvent_t e : P->ev) (void)hipEventDestroy(e);
+  if (P->d_prof) (void)hipFree(P->d_prof);
   delete P;
 }
 
