@@ -100,16 +100,142 @@ __global__ __launch_bounds__(MA3_BLOCK) void k3_fields(Desc3 d, const State3* s)
 // residual and coefficients (eq. ma2, eq. linearmaeq in 3-D; Section 4)
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(MA3_BLOCK) void k3_res(Desc3 d, int op_mode) {
+// The residual and coefficients at point (i, j, k) (ei its offset) from u at offsets
+// |a|, |b|, |c| <= 2 (U(a, b, c)), accumulated into the block's partials
+template <class UF>
+__device__ __forceinline__ void res_point(const Desc3& d, int op_mode, int i, int j, int k, int ei, UF&& U,
+                                          double (&acc)[MA3_NPART]) {
   const int n = d.n;
   const long nn = (long)n * n * n;
   const double N = (double)n, invn = 1.0 / N, h1 = N, h2 = N * N;
-  double acc[MA3_NPART];
+  const double u0 = U(0, 0, 0);
+  // first and second derivatives along each axis, fourth order
+  double g[3], s2[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int di = a == 0, dj = a == 1, dk = a == 2;
+    const double m2 = U(-2 * di, -2 * dj, -2 * dk), m1 = U(-di, -dj, -dk);
+    const double p1 = U(di, dj, dk), p2 = U(2 * di, 2 * dj, 2 * dk);
+    g[a] = (m2 - 8.0 * m1 + 8.0 * p1 - p2) * (h1 / 12.0);
+    s2[a] = (-m2 + 16.0 * m1 - 30.0 * u0 + 16.0 * p1 - p2) * (h2 / 12.0);
+  }
+  // mixed derivatives: the first-derivative formula along a applied to the one along b
+  // (the sixteen values of each loaded before the first is used)
+  constexpr double w1[4] = {1.0 / 12.0, -8.0 / 12.0, 8.0 / 12.0, -1.0 / 12.0};  // offsets -2, -1, 1, 2
+  constexpr int off[4] = {-2, -1, 1, 2};
+  double mx[3];
+  const int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2};
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    double v[4][4];
+#pragma unroll
+    for (int ia = 0; ia < 4; ++ia)
+#pragma unroll
+      for (int ib = 0; ib < 4; ++ib) {
+        int o[3] = {0, 0, 0};
+        o[pa[q]] = off[ia];
+        o[pb[q]] = off[ib];
+        v[ia][ib] = U(o[0], o[1], o[2]);
+      }
+    double outer = 0.0;
+#pragma unroll
+    for (int ia = 0; ia < 4; ++ia) {
+      double inner = 0.0;
+#pragma unroll
+      for (int ib = 0; ib < 4; ++ib) inner += w1[ib] * v[ia][ib];
+      outer += w1[ia] * (inner * h1);
+    }
+    mx[q] = outer * h1;
+  }
+  // g and grad g at y = x + grad u, trilinear and periodic
+  const double y[3] = {i * invn + g[0], j * invn + g[1], k * invn + g[2]};
+  int lo[3], hi[3];
+  double fr[3];
+  for (int a = 0; a < 3; ++a) {
+    const double t = y[a] * N, fl = floor(t);
+    fr[a] = t - fl;
+    lo[a] = wrapf(fl, n, invn);
+    hi[a] = lo[a] + 1 == n ? 0 : lo[a] + 1;
+  }
+  double gy = 0.0, gy1 = 0.0, gy2 = 0.0, gy3 = 0.0;
+  const auto G = gmem<const double>(d.g);
+  const auto GG = gmem<const float4>(d.gg);
+  double gc[8];  // the eight corners' values, all loaded before the first is used
+  float4 gg[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int c1 = c >> 2, c2 = (c >> 1) & 1, c3 = c & 1;
+    const int idx = ((c1 ? hi[0] : lo[0]) * n + (c2 ? hi[1] : lo[1])) * n + (c3 ? hi[2] : lo[2]);
+    gc[c] = G[idx];
+    gg[c] = GG[idx];
+  }
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int c1 = c >> 2, c2 = (c >> 1) & 1, c3 = c & 1;
+    const double w = (c1 ? fr[0] : 1.0 - fr[0]) * (c2 ? fr[1] : 1.0 - fr[1]) * (c3 ? fr[2] : 1.0 - fr[2]);
+    gy = gy + w * gc[c];
+    gy1 = gy1 + w * (double)gg[c].x;
+    gy2 = gy2 + w * (double)gg[c].y;
+    gy3 = gy3 + w * (double)gg[c].z;
+  }
+  // det and cofactors of M = I + D^2 u
+  const double m11 = 1.0 + s2[0], m22 = 1.0 + s2[1], m33 = 1.0 + s2[2];
+  const double m12 = mx[0], m13 = mx[1], m23 = mx[2];
+  const double c11 = m22 * m33 - m23 * m23, c22 = m11 * m33 - m13 * m13, c33 = m11 * m22 - m12 * m12;
+  const double c12 = m13 * m23 - m12 * m33, c13 = m12 * m23 - m13 * m22, c23 = m12 * m13 - m11 * m23;
+  const double det = m11 * c11 + m12 * c12 + m13 * c13;
+  const double fn = gy * det;
+  const double fe = gmem<const double>(d.f)[ei];
+  const double rr = fe - fn;
+  gmem<float>(d.r)[ei] = (float)rr;
+  double cf[9] = {gy * c11, gy * c22, gy * c33, gy * c12, gy * c13, gy * c23, 0.0, 0.0, 0.0};
+  if (op_mode == 0) {
+    cf[6] = det * gy1;
+    cf[7] = det * gy2;
+    cf[8] = det * gy3;
+  }
+  // periodic Simpson weights (2/3 at even, 4/3 at odd indices, times 1/N per axis)
+  const double ws = ((i & 1) ? 4.0 : 2.0) * ((j & 1) ? 4.0 : 2.0) * ((k & 1) ? 4.0 : 2.0) / (27.0 * N * N * N);
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    gmem<float>(d.coef)[q * (int)nn + ei] = (float)cf[q];
+    acc[3 + q] += ws * cf[q];
+  }
+  acc[0] += fn;
+  acc[1] += rr;
+  acc[2] += rr * rr;
+  acc[12] += (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) * fe;
+  acc[13] += u0;
+  acc[14] = fmin(acc[14], det);
+  acc[15] = fmin(acc[15], m11);
+  acc[16] = fmin(acc[16], m11 * m22 - m12 * m12);
+  acc[17] = fmax(acc[17], rr);
+  acc[18] = fmin(acc[18], rr);
+  acc[19] += isfinite(rr) ? 0.0 : 1.0;
+}
+
+__device__ __forceinline__ void res_acc_init(double (&acc)[MA3_NPART]) {
   for (int k = 0; k < 14; ++k) acc[k] = 0.0;
   acc[14] = acc[15] = acc[16] = 1e300;
   acc[17] = -1e300;
   acc[18] = 1e300;
   acc[19] = 0.0;
+}
+
+__device__ __forceinline__ void res_acc_store(const Desc3& d, double (&acc)[MA3_NPART]) {
+  __shared__ double scratch[4 * MA3_NPART];
+  const int kinds[MA3_NPART] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 2, 1, 0};
+  block_reduce<MA3_NPART>(acc, kinds, scratch);
+  if (threadIdx.x == 0)
+    for (int q = 0; q < MA3_NPART; ++q) d.part[(long)blockIdx.x * MA3_NPART + q] = acc[q];
+}
+
+// u read directly (cached) at every stencil point: any n
+__global__ __launch_bounds__(MA3_BLOCK) void k3_res(Desc3 d, int op_mode) {
+  const int n = d.n;
+  const long nn = (long)n * n * n;
+  double acc[MA3_NPART];
+  res_acc_init(acc);
   // n^3 (and 9 n^3) stay below 2^31 for the supported sizes: 32-bit offsets
   const auto u = gmem<const double>(d.u);
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (long)gridDim.x * blockDim.x) {
@@ -123,119 +249,82 @@ __global__ __launch_bounds__(MA3_BLOCK) void k3_res(Desc3 d, int op_mode) {
       oj[t] = wrap3(j + t - 2, n) * n;
       ok[t] = wrap3(k + t - 2, n);
     }
-    // u at the offset (a, b, c) from the point, |a|, |b|, |c| <= 2
-    auto U = [&](int a, int b, int c) { return u[oi[a + 2] + oj[b + 2] + ok[c + 2]]; };
-    const double u0 = u[ei];
-    // first and second derivatives along each axis, fourth order
-    double g[3], s2[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const int di = a == 0, dj = a == 1, dk = a == 2;
-      const double m2 = U(-2 * di, -2 * dj, -2 * dk), m1 = U(-di, -dj, -dk);
-      const double p1 = U(di, dj, dk), p2 = U(2 * di, 2 * dj, 2 * dk);
-      g[a] = (m2 - 8.0 * m1 + 8.0 * p1 - p2) * (h1 / 12.0);
-      s2[a] = (-m2 + 16.0 * m1 - 30.0 * u0 + 16.0 * p1 - p2) * (h2 / 12.0);
-    }
-    // mixed derivatives: the first-derivative formula along a applied to the one along b
-    // (the sixteen values of each loaded before the first is used)
-    constexpr double w1[4] = {1.0 / 12.0, -8.0 / 12.0, 8.0 / 12.0, -1.0 / 12.0};  // offsets -2, -1, 1, 2
-    constexpr int off[4] = {-2, -1, 1, 2};
-    double mx[3];
-    const int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2};
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      double v[4][4];
-#pragma unroll
-      for (int ia = 0; ia < 4; ++ia)
-#pragma unroll
-        for (int ib = 0; ib < 4; ++ib) {
-          int o[3] = {0, 0, 0};
-          o[pa[q]] = off[ia];
-          o[pb[q]] = off[ib];
-          v[ia][ib] = U(o[0], o[1], o[2]);
-        }
-      double outer = 0.0;
-#pragma unroll
-      for (int ia = 0; ia < 4; ++ia) {
-        double inner = 0.0;
-#pragma unroll
-        for (int ib = 0; ib < 4; ++ib) inner += w1[ib] * v[ia][ib];
-        outer += w1[ia] * (inner * h1);
-      }
-      mx[q] = outer * h1;
-    }
-    // g and grad g at y = x + grad u, trilinear and periodic
-    const double y[3] = {i * invn + g[0], j * invn + g[1], k * invn + g[2]};
-    int lo[3], hi[3];
-    double fr[3];
-    for (int a = 0; a < 3; ++a) {
-      const double t = y[a] * N, fl = floor(t);
-      fr[a] = t - fl;
-      lo[a] = wrapf(fl, n, invn);
-      hi[a] = lo[a] + 1 == n ? 0 : lo[a] + 1;
-    }
-    double gy = 0.0, gy1 = 0.0, gy2 = 0.0, gy3 = 0.0;
-    const auto G = gmem<const double>(d.g);
-    const auto GG = gmem<const float4>(d.gg);
-    double gc[8];  // the eight corners' values, all loaded before the first is used
-    float4 gg[8];
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      const int c1 = c >> 2, c2 = (c >> 1) & 1, c3 = c & 1;
-      const int idx = ((c1 ? hi[0] : lo[0]) * n + (c2 ? hi[1] : lo[1])) * n + (c3 ? hi[2] : lo[2]);
-      gc[c] = G[idx];
-      gg[c] = GG[idx];
-    }
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      const int c1 = c >> 2, c2 = (c >> 1) & 1, c3 = c & 1;
-      const double w = (c1 ? fr[0] : 1.0 - fr[0]) * (c2 ? fr[1] : 1.0 - fr[1]) * (c3 ? fr[2] : 1.0 - fr[2]);
-      gy = gy + w * gc[c];
-      gy1 = gy1 + w * (double)gg[c].x;
-      gy2 = gy2 + w * (double)gg[c].y;
-      gy3 = gy3 + w * (double)gg[c].z;
-    }
-    // det and cofactors of M = I + D^2 u
-    const double m11 = 1.0 + s2[0], m22 = 1.0 + s2[1], m33 = 1.0 + s2[2];
-    const double m12 = mx[0], m13 = mx[1], m23 = mx[2];
-    const double c11 = m22 * m33 - m23 * m23, c22 = m11 * m33 - m13 * m13, c33 = m11 * m22 - m12 * m12;
-    const double c12 = m13 * m23 - m12 * m33, c13 = m12 * m23 - m13 * m22, c23 = m12 * m13 - m11 * m23;
-    const double det = m11 * c11 + m12 * c12 + m13 * c13;
-    const double fn = gy * det;
-    const double fe = gmem<const double>(d.f)[ei];
-    const double rr = fe - fn;
-    gmem<float>(d.r)[ei] = (float)rr;
-    double cf[9] = {gy * c11, gy * c22, gy * c33, gy * c12, gy * c13, gy * c23, 0.0, 0.0, 0.0};
-    if (op_mode == 0) {
-      cf[6] = det * gy1;
-      cf[7] = det * gy2;
-      cf[8] = det * gy3;
-    }
-    // periodic Simpson weights (2/3 at even, 4/3 at odd indices, times 1/N per axis)
-    const double ws = ((i & 1) ? 4.0 : 2.0) * ((j & 1) ? 4.0 : 2.0) * ((k & 1) ? 4.0 : 2.0) / (27.0 * N * N * N);
-#pragma unroll
-    for (int q = 0; q < 9; ++q) {
-      gmem<float>(d.coef)[q * (int)nn + ei] = (float)cf[q];
-      acc[3 + q] += ws * cf[q];
-    }
-    acc[0] += fn;
-    acc[1] += rr;
-    acc[2] += rr * rr;
-    acc[12] += (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) * fe;
-    acc[13] += u0;
-    acc[14] = fmin(acc[14], det);
-    acc[15] = fmin(acc[15], m11);
-    acc[16] = fmin(acc[16], m11 * m22 - m12 * m12);
-    acc[17] = fmax(acc[17], rr);
-    acc[18] = fmin(acc[18], rr);
-    acc[19] += isfinite(rr) ? 0.0 : 1.0;
+    res_point(d, op_mode, i, j, k, ei, [&](int a, int b, int c) { return u[oi[a + 2] + oj[b + 2] + ok[c + 2]]; },
+              acc);
   }
-  __shared__ double scratch[4 * MA3_NPART];
-  const int kinds[MA3_NPART] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 2, 1, 0};
-  block_reduce<MA3_NPART>(acc, kinds, scratch);
-  if (threadIdx.x == 0)
-    for (int q = 0; q < MA3_NPART; ++q) d.part[(long)blockIdx.x * MA3_NPART + q] = acc[q];
+  res_acc_store(d, acc);
 }
+
+// Streaming form (64 | n): a block takes a tile of R3_TJ rows x 64 columns of (j, k) and
+// walks R3_TI planes along i with the five planes i - 2 .. i + 2 of u (tile plus a halo
+// of two) in LDS; the next plane's loads are issued before the current plane is
+// computed.  Wave w takes row j0 + w, lane l column k0 + l.
+constexpr int R3_TJ = 4, R3_TI = 8, R3_W = 64 + 4, R3_H = R3_TJ + 4, R3_PLANE = R3_W * R3_H;
+constexpr int R3_PER = (R3_PLANE + MA3_BLOCK - 1) / MA3_BLOCK;
+static_assert(R3_TJ * 64 == MA3_BLOCK, "one point per thread and plane");
+
+__global__ __launch_bounds__(MA3_BLOCK) void k3_res_s(Desc3 d, int op_mode) {
+  const int n = d.n, n2 = n * n;
+  const int ntk = n / 64, ntj = n / R3_TJ;
+  const int b = blockIdx.x;
+  const int k0 = (b % ntk) * 64, j0 = ((b / ntk) % ntj) * R3_TJ, i0 = (b / (ntk * ntj)) * R3_TI;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __shared__ double L[5 * R3_PLANE];
+  const auto u = gmem<const double>(d.u);
+  // tile element e of plane i: row jt = e / R3_W (j = j0 - 2 + jt), column kt = e % R3_W
+  int toff[R3_PER];  // (j, k) offset of the thread's tile elements (elements past the tile: 0)
+#pragma unroll
+  for (int q = 0; q < R3_PER; ++q) {
+    const int e = threadIdx.x + q * MA3_BLOCK;
+    const int jt = e / R3_W, kt = e % R3_W;
+    toff[q] = e < R3_PLANE ? wrap3(j0 - 2 + jt, n) * n + wrap3(k0 - 2 + kt, n) : 0;
+  }
+  auto slot = [&](int i) { return ((i - i0 + 2) % 5) * R3_PLANE; };  // i >= i0 - 2
+  auto fetch = [&](int i, double (&v)[R3_PER]) {
+    const int po = wrap3(i, n) * n2;
+#pragma unroll
+    for (int q = 0; q < R3_PER; ++q) v[q] = u[po + toff[q]];
+  };
+  auto put = [&](int i, const double (&v)[R3_PER]) {
+#pragma unroll
+    for (int q = 0; q < R3_PER; ++q) {
+      const int e = threadIdx.x + q * MA3_BLOCK;
+      if (e < R3_PLANE) L[slot(i) + e] = v[q];
+    }
+  };
+  {  // planes i0 - 2 .. i0 + 2
+    double v[5][R3_PER];
+#pragma unroll
+    for (int t = 0; t < 5; ++t) fetch(i0 - 2 + t, v[t]);
+#pragma unroll
+    for (int t = 0; t < 5; ++t) put(i0 - 2 + t, v[t]);
+  }
+  __syncthreads();
+  double acc[MA3_NPART];
+  res_acc_init(acc);
+  const int j = j0 + w, k = k0 + lane;
+  const int cell = (w + 2) * R3_W + lane + 2;  // the point's position in a plane tile
+#pragma unroll 1
+  for (int s = 0; s < R3_TI; ++s) {
+    const int i = i0 + s;
+    double nv[R3_PER];
+    if (s + 1 < R3_TI) fetch(i + 3, nv);
+    int so[5];
+#pragma unroll
+    for (int t = 0; t < 5; ++t) so[t] = slot(i - 2 + t) + cell;
+    res_point(d, op_mode, i, j, k, (i * n + j) * n + k,
+              [&](int a, int bb, int c) { return L[so[a + 2] + bb * R3_W + c]; }, acc);
+    if (s + 1 < R3_TI) {
+      __syncthreads();  // every read of plane i - 2 is done
+      put(i + 3, nv);
+      __syncthreads();
+    }
+  }
+  res_acc_store(d, acc);
+}
+
+bool res_streams(int n) { return n % 64 == 0 && n % R3_TI == 0; }
+int res_blocks(int n) { return res_streams(n) ? (n / 64) * (n / R3_TJ) * (n / R3_TI) : k3_blocks(n); }
 
 __global__ __launch_bounds__(256) void k3_res_fold(Desc3 d, State3* s, int nblk) {
   __shared__ double scratch[4 * MA3_NPART];
@@ -801,8 +890,11 @@ void k3_setup(const Desc3& d, State3* s, bool scale, hipStream_t st) {
 }
 
 void k3_residual(const Desc3& d, State3* s, int op_mode, hipStream_t st) {
-  const int nb = k3_blocks(d.n);
-  hipLaunchKernelGGL(k3_res, dim3(nb), dim3(MA3_BLOCK), 0, st, d, op_mode);
+  const int nb = res_blocks(d.n);
+  if (res_streams(d.n))
+    hipLaunchKernelGGL(k3_res_s, dim3(nb), dim3(MA3_BLOCK), 0, st, d, op_mode);
+  else
+    hipLaunchKernelGGL(k3_res, dim3(nb), dim3(MA3_BLOCK), 0, st, d, op_mode);
   hipLaunchKernelGGL(k3_res_fold, dim3(1), dim3(256), 0, st, d, s, nb);
 }
 
