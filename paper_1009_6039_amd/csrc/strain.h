@@ -80,14 +80,18 @@ struct Canon {
 // q: FFT index of k1; q2: FFT index of k2 (N/2 for the Nyquist column).
 // mt[q] = (Im of the first-derivative multiplier, second-derivative multiplier).
 template <int N>
-__device__ __forceinline__ float2 rhobar(int q, int q2, const float (&ab)[5], const float2* __restrict__ mt) {
+__device__ __forceinline__ float2 rhobar_m(int q, int q2, float2 m1, float2 m2, const float (&ab)[5]) {
   if (q == 0 && q2 == 0) return make_float2(0.f, 0.f);
-  const float2 m1 = mt[q], m2 = mt[q2];
   // S = a11 d2(k1) + 2 a12 (i d1(k1))(i d1(k2)) + a22 d2(k2) + i (b1 d1(k1) + b2 d1(k2))
   const float re = ab[0] * m1.y + ab[2] * m2.y - 2.f * ab[1] * m1.x * m2.x;
   const float im = ab[3] * m1.x + ab[4] * m2.x;
   const float den = re * re + im * im;
   return make_float2(re / den, -im / den);
+}
+// the same with the multipliers read from the table mt
+template <int N>
+__device__ __forceinline__ float2 rhobar(int q, int q2, const float (&ab)[5], const float2* __restrict__ mt) {
+  return rhobar_m<N>(q, q2, mt[q], mt[q2], ab);
 }
 
 // Z[k] = A + iB and Z[N-k] = conj(A) + i conj(B): the full spectrum of the complex
@@ -304,14 +308,37 @@ __global__ __launch_bounds__((Cfg<N, G>::B_BLOCK)) void k_passB(LaunchCtx c, int
   // fewer each); other geometries stage everything through LDS.
   constexpr int R0 = pick_radix(N, PL);
   constexpr bool REG1 = BLOCK == CPB * (N / R0);
+  // the multipliers the thread uses below, loaded with its columns (so that no wait on
+  // a table load stalls the transforms): at the wavenumbers q and N - q of its rhobar
+  // items, at its column's wavenumber, and at the rows of its elements
+  constexpr int NI = ((NH + 1) * CPB + BLOCK - 1) / BLOCK;  // rhobar items per thread
+  constexpr int PER = N * CPB / BLOCK;                      // elements per thread (whole)
+  float2 mq[NI], mqm[NI], mo[PER];
+  const int cc0 = threadIdx.x % CPB;  // the thread's column (BLOCK is a multiple of CPB)
+  float2 mslot, m0, mnh;
+  // the scale and the averaged coefficients, read with the loads below
+  const float scale = (float)((mode == PB_MATVEC ? s.vscale[j] : 1.0) / ((double)N * (double)N));
+  float ab[5];
+  for (int k = 0; k < 5; ++k) ab[k] = (float)s.abar[k];
   {  // every column load of the thread in flight before the first LDS write
-    constexpr int PER = N * CPB / BLOCK;  // whole (static_assert in Cfg)
     float2 h[PER];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int e = threadIdx.x + q * BLOCK;
       h[q] = H[(long)(e / CPB) * NH + s0 + e % CPB];
     }
+#pragma unroll
+    for (int r = 0; r < NI; ++r) {
+      const int it = threadIdx.x + r * BLOCK;
+      const int q = it < (NH + 1) * CPB ? it / CPB : 0;
+      mq[r] = c.mt[q];
+      mqm[r] = c.mt[(N - q) % N];
+    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) mo[k] = c.mt[(threadIdx.x + k * BLOCK) / CPB];
+    mslot = c.mt[s0 + cc0];
+    m0 = c.mt[0];
+    mnh = c.mt[NH];
     stage_twiddles<N, BLOCK, PL>(twl, tw);  // issued after the column loads, used after them
     if constexpr (REG1) {
       fft_cols_from_regs<N, CPB, BLOCK, false, PL>(S, twl, h);
@@ -329,27 +356,27 @@ __global__ __launch_bounds__((Cfg<N, G>::B_BLOCK)) void k_passB(LaunchCtx c, int
     }
     return;
   }
-  const float scale = (float)((mode == PB_MATVEC ? s.vscale[j] : 1.0) / ((double)N * (double)N));
-  float ab[5];
-  for (int k = 0; k < 5; ++k) ab[k] = (float)s.abar[k];
   // wavenumbers q and N - q together: slot 0 packs the DC and Nyquist columns of the
   // rows, which separate with the partner coefficient; every later multiplier m(q)
   // then acts on the packed value P = sA + i sB directly
-  for (int it = threadIdx.x; it < (NH + 1) * CPB; it += BLOCK) {
-    const int q = it / CPB, cc = it % CPB;
+#pragma unroll
+  for (int r = 0; r < NI; ++r) {
+    const int it = threadIdx.x + r * BLOCK;
+    if (it >= (NH + 1) * CPB) break;
+    const int q = it / CPB, cc = cc0;
     const int qm = (N - q) % N;
     const int slot = s0 + cc;
     const float2 z = S[q * CPB + cc], zm = S[qm * CPB + cc];
     float2 vq, vm;
     if (slot != 0) {
-      vq = cscale(cmul(rhobar<N>(q, slot, ab, c.mt), z), scale);
-      vm = cscale(cmul(rhobar<N>(qm, slot, ab, c.mt), zm), scale);
+      vq = cscale(cmul(rhobar_m<N>(q, slot, mq[r], mslot, ab), z), scale);
+      vm = cscale(cmul(rhobar_m<N>(qm, slot, mqm[r], mslot, ab), zm), scale);
     } else {
       const float2 A = make_float2(0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y));
       const float2 B = make_float2(0.5f * (z.y + zm.y), -0.5f * (z.x - zm.x));
-      const float2 aq = cmul(rhobar<N>(q, 0, ab, c.mt), A), bq = cmul(rhobar<N>(q, NH, ab, c.mt), B);
-      const float2 am = cmul(rhobar<N>(qm, 0, ab, c.mt), cconj(A));
-      const float2 bm = cmul(rhobar<N>(qm, NH, ab, c.mt), cconj(B));
+      const float2 aq = cmul(rhobar_m<N>(q, 0, mq[r], m0, ab), A), bq = cmul(rhobar_m<N>(q, NH, mq[r], mnh, ab), B);
+      const float2 am = cmul(rhobar_m<N>(qm, 0, mqm[r], m0, ab), cconj(A));
+      const float2 bm = cmul(rhobar_m<N>(qm, NH, mqm[r], mnh, ab), cconj(B));
       vq = cscale(make_float2(aq.x - bq.y, aq.y + bq.x), scale);
       vm = cscale(make_float2(am.x - bm.y, am.y + bm.x), scale);
     }
@@ -361,7 +388,6 @@ __global__ __launch_bounds__((Cfg<N, G>::B_BLOCK)) void k_passB(LaunchCtx c, int
   // multiplied spectrum stays in registers (each thread's own elements), and every
   // output is written back into S from them and transformed in place: one LDS buffer
   // per block instead of two, so twice the blocks fit on a CU.
-  constexpr int PER = N * CPB / BLOCK;  // whole (static_assert in Cfg)
   float2 sv[PER];
 #pragma unroll
   for (int k = 0; k < PER; ++k) sv[k] = S[threadIdx.x + k * BLOCK];
@@ -374,7 +400,7 @@ __global__ __launch_bounds__((Cfg<N, G>::B_BLOCK)) void k_passB(LaunchCtx c, int
       float2 x[PER];
 #pragma unroll
       for (int k = 0; k < PER; ++k) {
-        const float2 m = c.mt[(threadIdx.x + k * BLOCK) / CPB];
+        const float2 m = mo[k];
         x[k] = o == 0 ? sv[k] : ((o == 1) ? times_i(m.x, sv[k]) : cscale(sv[k], m.y));
       }
       fft_cols_from_regs<N, CPB, BLOCK, true, PL>(S, twl, x);
@@ -383,7 +409,7 @@ __global__ __launch_bounds__((Cfg<N, G>::B_BLOCK)) void k_passB(LaunchCtx c, int
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
           const int e = threadIdx.x + k * BLOCK;
-          const float2 m = c.mt[e / CPB];
+          const float2 m = mo[k];
           S[e] = o == 0 ? sv[k] : ((o == 1) ? times_i(m.x, sv[k]) : cscale(sv[k], m.y));
         }
         __syncthreads();
