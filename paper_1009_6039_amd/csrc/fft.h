@@ -173,13 +173,37 @@ __host__ __device__ constexpr int tw_span(int n, int plan = 0) {
   return need;
 }
 
-// Copies the part of the twiddle table that a length-N transform reads into LDS, so
+// The part of the twiddle table that a length-N transform reads, copied into LDS so
 // that the stages read twiddles without vector-memory loads (whose in-order counter
-// would also hold every other load in flight).  The caller's barrier before its first
+// would also hold every other load in flight).  load() issues the thread's share of
+// the table into registers; a caller that issues it before its data loads can store()
+// the copy while those are still in flight.  The caller's barrier before its first
 // transform makes the copy visible.
 template <int N, int BLOCK, int PLAN = 0>
+struct TwiddleStage {
+  static constexpr int SPAN = tw_span(N, PLAN);
+  static constexpr int IT = (SPAN + BLOCK - 1) / BLOCK;
+  float2 v[IT];
+  __device__ __forceinline__ void load(const float2* __restrict__ tw) {
+#pragma unroll
+    for (int q = 0; q < IT; ++q) {
+      const int e = threadIdx.x + q * BLOCK;
+      if (SPAN % BLOCK == 0 || e < SPAN) v[q] = tw[e];
+    }
+  }
+  __device__ __forceinline__ void store(float2* twl) const {
+#pragma unroll
+    for (int q = 0; q < IT; ++q) {
+      const int e = threadIdx.x + q * BLOCK;
+      if (SPAN % BLOCK == 0 || e < SPAN) twl[e] = v[q];
+    }
+  }
+};
+template <int N, int BLOCK, int PLAN = 0>
 __device__ __forceinline__ void stage_twiddles(float2* twl, const float2* __restrict__ tw) {
-  for (int e = threadIdx.x; e < tw_span(N, PLAN); e += BLOCK) twl[e] = tw[e];
+  TwiddleStage<N, BLOCK, PLAN> t;
+  t.load(tw);
+  t.store(twl);
 }
 
 template <int N, int NF, int LAYOUT>

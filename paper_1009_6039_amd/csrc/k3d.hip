@@ -537,10 +537,12 @@ __global__ __launch_bounds__(MA3_BLOCK) void k3_p1(Desc3 d, const State3* s, int
   const long nn = (long)N * N * N;
   const float* in = mode == P3_MATVEC ? d.V + (long)j * nn : d.x;
   const long base = (long)blockIdx.x * R * N;
+  TwiddleStage<N, MA3_BLOCK> tws;  // issued before the data loads
+  tws.load(d.tw);
   float x[PER];
 #pragma unroll
   for (int q = 0; q < PER; ++q) x[q] = in[base + threadIdx.x + q * MA3_BLOCK];
-  stage_twiddles<N, MA3_BLOCK>(twl, d.tw);
+  tws.store(twl);
 #pragma unroll
   for (int q = 0; q < PER; ++q) L[threadIdx.x + q * MA3_BLOCK] = make_float2(x[q], 0.f);
   __syncthreads();
@@ -566,10 +568,12 @@ __global__ __launch_bounds__(MA3_BLOCK) void k3_p2(Desc3 d, const State3* s, int
   __shared__ float2 twl[tw_span(N)];
   const int i = blockIdx.x / (N / C), k0 = (blockIdx.x % (N / C)) * C;
   const long b0 = (long)i * N * N + k0;  // element (i, jj, k0 + t) at b0 + jj N + t
+  TwiddleStage<N, MA3_BLOCK> tws;  // issued before the data loads
+  tws.load(d.tw);
   float2 v[PER];
 #pragma unroll
   for (int q = 0; q < PER; ++q) v[q] = d.S[col_index<N, C>(b0, N, threadIdx.x + q * MA3_BLOCK)];
-  stage_twiddles<N, MA3_BLOCK>(twl, d.tw);
+  tws.store(twl);
 #pragma unroll
   for (int q = 0; q < PER; ++q) L[threadIdx.x + q * MA3_BLOCK] = v[q];
   __syncthreads();
@@ -604,6 +608,8 @@ __global__ __launch_bounds__(MA3_BLOCK) void k3_p3(Desc3 d, const State3* s, int
   __shared__ float2 twl[tw_span(N)];
   const int jj = blockIdx.x / (N / C), k0 = (blockIdx.x % (N / C)) * C;
   const long b0 = (long)jj * N + k0;  // element (i, jj, k0 + t) at b0 + i N^2 + t
+  TwiddleStage<N, MA3_BLOCK> tws;  // issued before the data loads
+  tws.load(d.tw);
   float2 v[PER];
 #pragma unroll
   for (int q = 0; q < PER; ++q) v[q] = d.S[col_index<N, C>(b0, (long)N * N, threadIdx.x + q * MA3_BLOCK)];
@@ -615,7 +621,7 @@ __global__ __launch_bounds__(MA3_BLOCK) void k3_p3(Desc3 d, const State3* s, int
   float ab[9];
   for (int q = 0; q < 9; ++q) ab[q] = (float)s->abar[q];
   const float scale = (float)((mode == P3_MATVEC ? s->vscale[j] : 1.0) / ((double)N * N * N));
-  stage_twiddles<N, MA3_BLOCK>(twl, d.tw);
+  tws.store(twl);
 #pragma unroll
   for (int q = 0; q < PER; ++q) L[threadIdx.x + q * MA3_BLOCK] = v[q];
   __syncthreads();
@@ -664,12 +670,14 @@ __global__ __launch_bounds__(MA3_BLOCK) void k3_p4(Desc3 d, const State3* s, int
   const bool mv = mode == P3_MATVEC;
   const int nsrc = mv ? 3 : 1;
   auto src_plane = [&](int si) { return mv ? 2 - si : 0; };
+  TwiddleStage<N, MA3_BLOCK> tws;  // issued before the data loads
+  tws.load(d.tw);
   float2 cur[PER], nxt[PER], m[PER];
 #pragma unroll
   for (int q = 0; q < PER; ++q) cur[q] = d.T[src_plane(0) * NN + col_index<N, C>(b0, N, threadIdx.x + q * MA3_BLOCK)];
 #pragma unroll
   for (int q = 0; q < PER; ++q) m[q] = d.mt[(threadIdx.x + q * MA3_BLOCK) / C];
-  stage_twiddles<N, MA3_BLOCK>(twl, d.tw);
+  tws.store(twl);
   int out = mv ? 0 : 3;
   for (int si = 0; si < nsrc; ++si) {
     if (si + 1 < nsrc) {
@@ -711,12 +719,14 @@ __global__ __launch_bounds__(MA3_BLOCK) void k3_p5(Desc3 d, const State3* s, int
   __shared__ float2 twl[tw_span(N)];
   __shared__ double red[(MA3_BLOCK / 64) * (MA3_MMAX + 1)];
   const long base = (long)blockIdx.x * R5 * N;  // first element of the block's lines
+  TwiddleStage<N, MA3_BLOCK> tws;  // issued before the data loads
+  tws.load(d.tw);
   if (mode != P3_MATVEC) {
     const float2* Ud = d.U + 3 * NN;
     float2 v[PER];
 #pragma unroll
     for (int q = 0; q < PER; ++q) v[q] = Ud[base + threadIdx.x + q * MA3_BLOCK];
-    stage_twiddles<N, MA3_BLOCK>(twl, d.tw);
+    tws.store(twl);
 #pragma unroll
     for (int q = 0; q < PER; ++q) L[threadIdx.x + q * MA3_BLOCK] = v[q];
     __syncthreads();
@@ -746,7 +756,7 @@ __global__ __launch_bounds__(MA3_BLOCK) void k3_p5(Desc3 d, const State3* s, int
     for (int c = 0; c < 6; ++c) uv[c][q] = d.U[c * NN + g];
     m[q] = d.mt[(threadIdx.x + q * MA3_BLOCK) % N];
   }
-  stage_twiddles<N, MA3_BLOCK>(twl, d.tw);
+  tws.store(twl);
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int e = threadIdx.x + q * MA3_BLOCK;

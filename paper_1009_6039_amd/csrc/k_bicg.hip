@@ -56,7 +56,7 @@ __global__ __launch_bounds__(256) void k_bicg_init(LaunchCtx c) {
   if (p < 0) return;
   const PairState& s = c.st[p];
   if (s.phase != PH_SOLVE) return;
-  const PairDesc& d = c.desc[p];
+  const PairDesc d = c.desc[p];
   const long nn = (long)d.n * d.n;
   const int nb = bicg_blocks_dev(d.n, TX);
   const double cst = s.mass_c, inv_tau = 1.0 / s.tau;
@@ -89,7 +89,7 @@ __global__ __launch_bounds__(256) void k_bicg_start(LaunchCtx c, int nblk) {
   if (p < 0) return;
   PairState& s = c.st[p];
   if (s.phase != PH_SOLVE) return;
-  const PairDesc& d = c.desc[p];
+  const PairDesc d = c.desc[p];
   __shared__ double scratch[4 * 2];
   const int kinds[2] = {0, 0};
   double t[2];
@@ -124,7 +124,7 @@ __global__ __launch_bounds__(256) void k_bicg_matvec(LaunchCtx c, int j) {
     if (blockIdx.x == 0 && threadIdx.x == 0) s.gm_running = 0;
     return;
   }
-  const PairDesc& d = c.desc[p];
+  const PairDesc d = c.desc[p];
   const int n = d.n;
   const long nn = (long)n * n;
   const int nb = bicg_blocks_dev(n, TX);
@@ -245,7 +245,7 @@ __global__ __launch_bounds__(256) void k_bicg_update(LaunchCtx c, int j) {
   if (threadIdx.x == 0) go = s.phase == PH_SOLVE && s.gm_running && !s.bi_break;
   __syncthreads();
   if (!go) return;
-  const PairDesc& d = c.desc[p];
+  const PairDesc d = c.desc[p];
   const long nn = (long)d.n * d.n;
   const int nb = bicg_blocks_dev(d.n, TX);
   // the block's loads are issued before the fold of the p~.q partials
@@ -305,7 +305,7 @@ __global__ __launch_bounds__(256) void k_bicg_finish(LaunchCtx c) {
   if (p < 0) return;
   const PairState& s = c.st[p];
   if (s.phase != PH_SOLVE) return;
-  const PairDesc& d = c.desc[p];
+  const PairDesc d = c.desc[p];
   const long base = (long)blockIdx.x * (BI_TY * TX);
   for (int e = threadIdx.x; e < BI_TY * TX; e += 256) {
     const long g = base + e;

@@ -13,7 +13,7 @@
 __global__ __launch_bounds__(MA_BLOCK) void k_setup_sums(LaunchCtx c, int nblk) {
   const int p = pair_of_block(c);
   if (p < 0) return;
-  const PairDesc& d = c.desc[p];
+  const PairDesc d = c.desc[p];
   const long nn = (long)d.n * d.n;
   double sf = 0, sg = 0, sp = 0, bad = 0;
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (long)nblk * blockDim.x) {
@@ -38,7 +38,7 @@ __global__ __launch_bounds__(MA_BLOCK) void k_setup_sums(LaunchCtx c, int nblk) 
 __global__ __launch_bounds__(MA_BLOCK) void k_setup_finalize(LaunchCtx c, int nblk) {
   const int p = pair_of_block(c);
   if (p < 0) return;
-  const PairDesc& d = c.desc[p];
+  const PairDesc d = c.desc[p];
   PairState& s = c.st[p];
   __shared__ double scratch[(MA_BLOCK / 64) * 4];
   const int kinds[4] = {0, 0, 0, 0};
@@ -58,7 +58,7 @@ __global__ __launch_bounds__(MA_BLOCK) void k_setup_finalize(LaunchCtx c, int nb
 __global__ __launch_bounds__(MA_BLOCK) void k_setup_fields(LaunchCtx c) {
   const int p = pair_of_block(c);
   if (p < 0) return;
-  const PairDesc& d = c.desc[p];
+  const PairDesc d = c.desc[p];
   const PairState& s = c.st[p];
   const int n = d.n;
   const long nn = (long)n * n;
@@ -306,7 +306,7 @@ template <int TX, int INTERP>
 __global__ __launch_bounds__(MA_BLOCK) void k_residual(LaunchCtx c) {
   const int p = pair_of_block(c);
   if (p < 0) return;
-  const PairDesc& d = c.desc[p];
+  const PairDesc d = c.desc[p];
   PairState& s = c.st[p];
   if (s.phase == PH_DONE) return;
   count_bytes(c, 56.0, d.n);  // u 8, f 8, g with gradient 16 (once), r 4, coefficients 20
@@ -369,7 +369,7 @@ template <int RPW, int INTERP>
 __global__ __launch_bounds__(MA_RES_STREAM_BLOCK) void k_residual_stream(LaunchCtx c) {
   const int p = pair_of_block(c);
   if (p < 0) return;
-  const PairDesc& d = c.desc[p];
+  const PairDesc d = c.desc[p];
   PairState& s = c.st[p];
   if (s.phase == PH_DONE) return;
   count_bytes(c, 56.0, d.n);
@@ -463,7 +463,7 @@ __global__ __launch_bounds__(MA_RES_STREAM_BLOCK) void k_residual_stream(LaunchC
 __global__ __launch_bounds__(MA_BLOCK) void k_residual_finalize(LaunchCtx c, int nblk, int step_mode) {
   const int p = pair_of_block(c);
   if (p < 0) return;
-  const PairDesc& d = c.desc[p];
+  const PairDesc d = c.desc[p];
   PairState& s = c.st[p];
   if (s.phase == PH_DONE) return;
   __shared__ double scratch[(MA_BLOCK / 64) * MA_NPART_RES];
@@ -492,7 +492,7 @@ __global__ __launch_bounds__(MA_BLOCK) void k_residual_finalize(LaunchCtx c, int
 __global__ __launch_bounds__(MA_BLOCK) void k_residual_shift(LaunchCtx c, float* out) {
   const int p = pair_of_block(c);
   if (p < 0) return;
-  const PairDesc& d = c.desc[p];
+  const PairDesc d = c.desc[p];
   const float cst = (float)c.st[p].mass_c;
   const long nn = (long)d.n * d.n;
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (long)gridDim.x * blockDim.x)
@@ -503,7 +503,7 @@ __global__ __launch_bounds__(MA_BLOCK) void k_residual_shift(LaunchCtx c, float*
 __global__ __launch_bounds__(MA_BLOCK) void k_step_update(LaunchCtx c) {
   const int p = pair_of_block(c);
   if (p < 0) return;
-  const PairDesc& d = c.desc[p];
+  const PairDesc d = c.desc[p];
   const PairState& s = c.st[p];
   if (s.phase != PH_BACKTRACK && s.phase != PH_REVERT) return;
   const double a = s.axpy;
@@ -516,7 +516,7 @@ __global__ __launch_bounds__(MA_BLOCK) void k_step_update(LaunchCtx c) {
 __global__ __launch_bounds__(MA_BLOCK) void k_outputs(LaunchCtx c) {
   const int p = pair_of_block(c);
   if (p < 0) return;
-  const PairDesc& d = c.desc[p];
+  const PairDesc d = c.desc[p];
   const PairState& s = c.st[p];
   const int n = d.n;
   const long nn = (long)n * n;
@@ -616,7 +616,7 @@ __global__ __launch_bounds__(256) void k_compact(const PairState* st, const int*
 __global__ __launch_bounds__(MA_BLOCK) void k_retire(LaunchCtx c, PairState* final_state) {
   const int p = pair_of_block(c);
   if (p < 0) return;
-  const PairDesc& d = c.desc[p];
+  const PairDesc d = c.desc[p];
   const PairState& s = c.st[p];
   const int n = d.n;
   const long nn = (long)n * n;
@@ -680,7 +680,7 @@ __global__ __launch_bounds__(MA_BLOCK) void k_validate(const double* const* f, c
 __global__ __launch_bounds__(MA_BLOCK) void k_tune_fill(LaunchCtx c) {
   const int p = pair_of_block(c);
   if (p < 0) return;
-  const PairDesc& d = c.desc[p];
+  const PairDesc d = c.desc[p];
   const int n = d.n;
   const long nn = (long)n * n;
   const double tp = 6.283185307179586;

@@ -65,7 +65,7 @@ __device__ void arnoldi_close(PairState& s, const LaunchCtx& c, int jn, double w
 __global__ __launch_bounds__(256) void k_dots_finalize(LaunchCtx c, int j, int nblk) {
   const int p = pair_of_block(c);
   if (p < 0) return;
-  const PairDesc& d = c.desc[p];
+  const PairDesc d = c.desc[p];
   PairState& s = c.st[p];
   if (!(s.phase == PH_SOLVE && s.gm_running)) return;
   __shared__ double red[8][32];
@@ -85,7 +85,7 @@ __global__ __launch_bounds__(256) void k_dots_finalize(LaunchCtx c, int j, int n
 __global__ __launch_bounds__(256) void k_arnoldi_finalize(LaunchCtx c, int jn, int nblk) {
   const int p = pair_of_block(c);
   if (p < 0) return;
-  const PairDesc& d = c.desc[p];
+  const PairDesc d = c.desc[p];
   PairState& s = c.st[p];
   if (!(s.phase == PH_SOLVE && s.gm_running)) return;
   __shared__ double scratch[4];
@@ -107,7 +107,7 @@ __global__ __launch_bounds__(256) void k_arnoldi_finalize(LaunchCtx c, int jn, i
 __global__ __launch_bounds__(256) void k_rhs_finalize(LaunchCtx c, int nblk) {
   const int p = pair_of_block(c);
   if (p < 0) return;
-  const PairDesc& d = c.desc[p];
+  const PairDesc d = c.desc[p];
   PairState& s = c.st[p];
   if (!(s.phase == PH_SOLVE && s.gm_running && s.gm_cycle == 0)) return;
   __shared__ double scratch[4];
@@ -140,7 +140,7 @@ __global__ void k_cycle_begin(LaunchCtx c) {
 __global__ __launch_bounds__(MA_BLOCK) void k_restart(LaunchCtx c) {
   const int p = pair_of_block(c);
   if (p < 0) return;
-  const PairDesc& d = c.desc[p];
+  const PairDesc d = c.desc[p];
   const PairState& s = c.st[p];
   if (!(s.phase == PH_SOLVE && s.gm_restart)) return;
   __shared__ float cy[MA_MMAX + 1], cq[MA_MMAX + 1];
@@ -173,7 +173,7 @@ __global__ __launch_bounds__(MA_BLOCK) void k_restart(LaunchCtx c) {
 __global__ __launch_bounds__(MA_BLOCK) void k_power_vec(LaunchCtx c, int mode, const float* b0) {
   const int p = pair_of_block(c);
   if (p < 0) return;
-  const PairDesc& d = c.desc[p];
+  const PairDesc d = c.desc[p];
   const PairState& s = c.st[p];
   const long nn = (long)d.n * d.n;
   double acc = 0.0;
@@ -207,7 +207,7 @@ __global__ __launch_bounds__(MA_BLOCK) void k_power_vec(LaunchCtx c, int mode, c
 __global__ __launch_bounds__(256) void k_power_fold(LaunchCtx c, int mode, int nblk, int k, double* out) {
   const int p = pair_of_block(c);
   if (p < 0) return;
-  const PairDesc& d = c.desc[p];
+  const PairDesc d = c.desc[p];
   PairState& s = c.st[p];
   __shared__ double scratch[4];
   const int kinds[1] = {0};

@@ -114,8 +114,8 @@ __global__ __launch_bounds__((Cfg<N, G>::A_BLOCK)) void k_passA(LaunchCtx c, int
   constexpr long NN = (long)N * N;
   const int p = pair_of_block(c);
   if (p < 0) return;
-  const PairDesc& d = c.desc[p];
-  PairState& s = c.st[p];
+  const PairDesc d = c.desc[p];
+  const PairState& s = c.st[p];
   bool run;
   if (mode == PA_INIT) run = s.phase == PH_SOLVE && s.gm_running && s.gm_cycle == 0;
   else if (mode == PA_PLAIN) run = s.phase == PH_SOLVE && s.gm_restart;
@@ -286,7 +286,7 @@ __global__ __launch_bounds__((Cfg<N, G>::B_BLOCK)) void k_passB(LaunchCtx c, int
   constexpr int CPB = Cfg<N, G>::B_CPB, BLOCK = Cfg<N, G>::B_BLOCK, NH = N / 2;
   const int p = pair_of_block(c);
   if (p < 0) return;
-  const PairDesc& d = c.desc[p];
+  const PairDesc d = c.desc[p];
   const PairState& s = c.st[p];
   bool run;
   if (mode == PB_MATVEC) run = s.phase == PH_SOLVE && s.gm_running;
@@ -316,11 +316,15 @@ __global__ __launch_bounds__((Cfg<N, G>::B_BLOCK)) void k_passB(LaunchCtx c, int
   float2 mq[NI], mqm[NI], mo[PER];
   const int cc0 = threadIdx.x % CPB;  // the thread's column (BLOCK is a multiple of CPB)
   float2 mslot, m0, mnh;
-  // the scale and the averaged coefficients, read with the loads below
-  const float scale = (float)((mode == PB_MATVEC ? s.vscale[j] : 1.0) / ((double)N * (double)N));
+  // the scale and the averaged coefficients, read with the loads below (the scale's
+  // load is unconditional so that no branch waits on it before the column loads)
+  const double vsj = s.vscale[mode == PB_MATVEC ? j : 0];
   float ab[5];
   for (int k = 0; k < 5; ++k) ab[k] = (float)s.abar[k];
-  {  // every column load of the thread in flight before the first LDS write
+  {  // every column load of the thread in flight before the first LDS write; the
+     // twiddles first, so that their copy into LDS waits for them alone
+    TwiddleStage<N, BLOCK, PL> tws;
+    tws.load(tw);
     float2 h[PER];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
@@ -339,7 +343,7 @@ __global__ __launch_bounds__((Cfg<N, G>::B_BLOCK)) void k_passB(LaunchCtx c, int
     mslot = c.mt[s0 + cc0];
     m0 = c.mt[0];
     mnh = c.mt[NH];
-    stage_twiddles<N, BLOCK, PL>(twl, tw);  // issued after the column loads, used after them
+    tws.store(twl);
     if constexpr (REG1) {
       fft_cols_from_regs<N, CPB, BLOCK, false, PL>(S, twl, h);
     } else {
@@ -349,6 +353,7 @@ __global__ __launch_bounds__((Cfg<N, G>::B_BLOCK)) void k_passB(LaunchCtx c, int
       fft_lds<N, CPB, BLOCK, false, LAYOUT_COLS, PL>(S, twl);
     }
   }
+  const float scale = (float)((mode == PB_MATVEC ? vsj : 1.0) / ((double)N * (double)N));
   if (mode == PB_FORWARD) {
     for (int e = threadIdx.x; e < N * CPB; e += BLOCK) {
       const int i = e / CPB, cc = e % CPB;
@@ -460,16 +465,17 @@ __device__ __forceinline__ void passC_load_coef(const PairDesc& d, int row0, Pas
 // is element jj of derived transform t of the block's row pair pp: t = 0 alpha11 + i
 // beta1 of row a, 1 alpha12 + i beta2 of row a, 2 and 3 the same for row b, 4 alpha22 of
 // row a (.x) and row b (.y).  The caller synchronises the block before the call.
-// k5: the coefficients at the thread's points (passC_load_coef).
+// k5: the coefficients at the thread's points (passC_load_coef); trbar = abar11 + abar22.
+// d is the caller's register copy of the pair's descriptor, so that no pointer is
+// reloaded from memory after the block barriers.
 template <int N, int PPB, int BLOCK, class ZAT>
-__device__ __forceinline__ void passC_combine(const LaunchCtx& c, const PairDesc& d, const PairState& s, int j,
+__device__ __forceinline__ void passC_combine(const LaunchCtx& c, const PairDesc& d, float trbar, int j,
                                               int row0, double* red, ZAT zat,
                                               const PassCCoef<N, PPB, BLOCK>& k5) {
   constexpr long NN = (long)N * N;
   const auto V = gmem<float>(d.V);
   const auto W = V + (long)(j + 1) * NN;
   const bool scaled = c.precond == MA_PRECOND_DIAG;
-  const float trbar = (float)(s.abar[0] + s.abar[2]);
   // w at the thread's points, then the inner products <w, v_l>
   constexpr int PER = PassCCoef<N, PPB, BLOCK>::PER;
   constexpr bool FULL = (PPB * N) % BLOCK == 0;
@@ -550,10 +556,11 @@ __global__ __launch_bounds__((Cfg<N, G>::C_BLOCK)) void k_passC(LaunchCtx c, int
   constexpr long NN = (long)N * N;
   const int p = pair_of_block(c);
   if (p < 0) return;
-  const PairDesc& d = c.desc[p];
-  PairState& s = c.st[p];
+  const PairDesc d = c.desc[p];
+  const PairState& s = c.st[p];
   const bool run = mode == PC_MATVEC ? (s.phase == PH_SOLVE && s.gm_running) : (s.phase == PH_SOLVE);
   if (!run) return;
+  const float trbar = (float)(s.abar[0] + s.abar[2]);
 
   // three half spectra 12, coefficients 20, Krylov vectors for the dots, w 4 (matvec);
   // one half spectrum 4, theta 8, u read and written 16 (recovery)
@@ -601,7 +608,8 @@ __global__ __launch_bounds__((Cfg<N, G>::C_BLOCK)) void k_passC(LaunchCtx c, int
   // five complex inverse transforms per row pair; every spectrum load of the thread
   // is issued before the first LDS write
   __shared__ float2 twl[PF ? tw_span(N, PL) : 1];
-  if constexpr (PF) stage_twiddles<N, BLOCK, PL>(twl, tw);
+  TwiddleStage<N, BLOCK, PL> tws;
+  if constexpr (PF) tws.load(tw);
   constexpr int IT1 = (PPB * NH + BLOCK - 1) / BLOCK;
   constexpr bool FULL1 = (PPB * NH) % BLOCK == 0;
   float2 tl[IT1][7];  // three spectra of each row, the multipliers at k
@@ -621,7 +629,10 @@ __global__ __launch_bounds__((Cfg<N, G>::C_BLOCK)) void k_passC(LaunchCtx c, int
     tl[q][5] = T2[ib];
   }
   PassCCoef<N, PPB, BLOCK> pre;
-  if constexpr (PF) passC_load_coef<N, PPB, BLOCK>(d, row0, pre);
+  if constexpr (PF) {
+    passC_load_coef<N, PPB, BLOCK>(d, row0, pre);
+    tws.store(twl);
+  }
 #pragma unroll
   for (int q = 0; q < IT1; ++q) {
     const int e = threadIdx.x + q * BLOCK;
@@ -656,7 +667,7 @@ __global__ __launch_bounds__((Cfg<N, G>::C_BLOCK)) void k_passC(LaunchCtx c, int
   fft_lds<N, 5 * PPB, BLOCK, true, LAYOUT_ROWS, PL>(lds, PF ? twl : tw);
   // the coefficients at all of the thread's points are loaded before the first is used
   if constexpr (!PF) passC_load_coef<N, PPB, BLOCK>(d, row0, pre);
-  passC_combine<N, PPB, BLOCK>(c, d, s, j, row0, red,
+  passC_combine<N, PPB, BLOCK>(c, d, trbar, j, row0, red,
                                [&](int pp, int t, int jj) { return lds[(5 * pp + t) * N + jj]; }, pre);
 }
 
@@ -670,10 +681,11 @@ __global__ __launch_bounds__(320 * PPB) void k_passC_w(LaunchCtx c, int mode, in
   constexpr long NN = (long)N * N;
   const int p = pair_of_block(c);
   if (p < 0) return;
-  const PairDesc& d = c.desc[p];
-  PairState& s = c.st[p];
+  const PairDesc d = c.desc[p];
+  const PairState& s = c.st[p];
   const bool run = mode == PC_MATVEC ? (s.phase == PH_SOLVE && s.gm_running) : (s.phase == PH_SOLVE);
   if (!run) return;
+  const float trbar = (float)(s.abar[0] + s.abar[2]);
   count_bytes(c, mode == PC_MATVEC ? 36.0 + 4.0 * (j + 1) : (mode == PC_RECOVER ? 28.0 : 8.0), N);
   __shared__ float2 lds[5 * PPB * WB];
   __shared__ double red[(BLOCK / 64) * (MA_MMAX + 1)];
@@ -768,7 +780,7 @@ __global__ __launch_bounds__(320 * PPB) void k_passC_w(LaunchCtx c, int mode, in
   __syncthreads();
   PassCCoef<N, PPB, BLOCK> k5;
   passC_load_coef<N, PPB, BLOCK>(d, row0, k5);
-  passC_combine<N, PPB, BLOCK>(c, d, s, j, row0, red,
+  passC_combine<N, PPB, BLOCK>(c, d, trbar, j, row0, red,
                                [&](int q, int tt, int jj) { return lds[(5 * q + tt) * WB + wpad(jj)]; }, k5);
 }
 
@@ -794,7 +806,7 @@ __global__ __launch_bounds__(64 * W) void k_passB_w(LaunchCtx c, int mode, int j
   constexpr int OWN = (N + 63) / 64;   // elements per lane of a column
   const int p = pair_of_block(c);
   if (p < 0) return;
-  const PairDesc& d = c.desc[p];
+  const PairDesc d = c.desc[p];
   const PairState& s = c.st[p];
   bool run;
   if (mode == PB_MATVEC) run = s.phase == PH_SOLVE && s.gm_running;
@@ -889,8 +901,8 @@ __global__ __launch_bounds__(64 * W) void k_passA_w(LaunchCtx c, int mode, int j
   constexpr int OWN = (N + 63) / 64;
   const int p = pair_of_block(c);
   if (p < 0) return;
-  const PairDesc& d = c.desc[p];
-  PairState& s = c.st[p];
+  const PairDesc d = c.desc[p];
+  const PairState& s = c.st[p];
   bool run;
   if (mode == PA_INIT) run = s.phase == PH_SOLVE && s.gm_running && s.gm_cycle == 0;
   else if (mode == PA_PLAIN) run = s.phase == PH_SOLVE && s.gm_restart;
