@@ -141,6 +141,38 @@ __device__ __forceinline__ MA_GLOBAL_AS T* gmem(T* p) {
   return (MA_GLOBAL_AS T*)p;
 }
 
+// Stops the instruction scheduler from moving any instruction across this point.
+__device__ __forceinline__ void sched_fence() {
+#if defined(__HIP_DEVICE_COMPILE__)
+  __builtin_amdgcn_sched_barrier(0);
+#endif
+}
+
+// Runs use(l, x) for l = 0, 1, ..., n - 1 in that order, x holding the thread's K
+// elements of vector l as load(l, x) reads them.  Two register sets take the vectors
+// in turn, so the loads of vector l + 1 are in flight while vector l is used and no
+// register copy waits on a load.  The look-ahead loads are unconditional (a branch
+// around a load makes the wait before the next use drain every load in flight): when
+// n is even the last one re-reads vector n - 1, which the thread has just read.  A
+// scheduling fence after each group of loads keeps the other set's use below it.
+template <int K, class LOAD, class USE>
+__device__ __forceinline__ void stream_vectors(int n, LOAD load, USE use) {
+  if (n <= 0) return;
+  float x0[K], x1[K];
+  load(0, x0);
+  sched_fence();
+  int l = 0;
+  for (; l + 2 <= n; l += 2) {
+    load(l + 1, x1);
+    sched_fence();
+    use(l, x0);
+    load(l + 2 < n ? l + 2 : n - 1, x0);
+    sched_fence();
+    use(l + 1, x1);
+  }
+  if (l < n) use(l, x0);
+}
+
 // GMRES tolerance of the pair's next Newton direction (eta 0: not adapted yet)
 __host__ __device__ inline double pair_eta(const PairState& s, const LaunchCtx& c) {
   return s.eta > 0.0 ? s.eta : c.gmres_tol;

@@ -799,27 +799,20 @@ __global__ __launch_bounds__(MA3_BLOCK) void k3_p5(Desc3 d, const State3* s, int
     w[q] = v;
   }
   // inner products <w, V_l>, l <= j, per block (fixed order); folded by k3_dots_fold
-  // (the loads of V_{l+1} issued before <w, V_l> is reduced)
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  float vl[PER];
+  stream_vectors<PER>(
+      j + 1,
+      [&](int lv, float* x) {
 #pragma unroll
-  for (int q = 0; q < PER; ++q) vl[q] = d.V[base + threadIdx.x + q * MA3_BLOCK];
-  for (int lv = 0; lv <= j; ++lv) {
-    float vn[PER];
-    if (lv < j) {
+        for (int q = 0; q < PER; ++q) x[q] = d.V[(long)lv * NN + base + threadIdx.x + q * MA3_BLOCK];
+      },
+      [&](int lv, const float* x) {
+        float acc = 0.f;
 #pragma unroll
-      for (int q = 0; q < PER; ++q) vn[q] = d.V[(long)(lv + 1) * NN + base + threadIdx.x + q * MA3_BLOCK];
-    }
-    float acc = 0.f;
-#pragma unroll
-    for (int q = 0; q < PER; ++q) acc += w[q] * vl[q];
-    const double v = wave_sum((double)acc);
-    if (lane == 0) red[wid * (MA3_MMAX + 1) + lv] = v;
-    if (lv < j) {
-#pragma unroll
-      for (int q = 0; q < PER; ++q) vl[q] = vn[q];
-    }
-  }
+        for (int q = 0; q < PER; ++q) acc += w[q] * x[q];
+        const double v = wave_sum((double)acc);
+        if (lane == 0) red[wid * (MA3_MMAX + 1) + lv] = v;
+      });
   __syncthreads();
   if (threadIdx.x <= j) {
     double t = 0.0;

@@ -195,38 +195,24 @@ __global__ __launch_bounds__((Cfg<N, G>::A_BLOCK)) void k_passA(LaunchCtx c, int
   if (mode == PA_ARNOLDI || mode == PA_RECOVER) {
     // v -= sum_l c_l V_l (Arnoldi) or x += sum_l y_l V_l (recovery), l in order
     const float sg = mode == PA_ARNOLDI ? -1.f : 1.f;
-    float la[PER], lb[PER];
-    if (nv > 0) {
+    stream_vectors<2 * PER>(
+        nv,
+        [&](int l, float* x) {
+          const auto Vl = V + (long)l * NN;
 #pragma unroll
-      for (int q = 0; q < PER; ++q) {
-        la[q] = V[ea_[q]];
-        lb[q] = V[ea_[q] + N];
-      }
-    }
-    for (int l = 0; l < nv; ++l) {
-      float na[PER], nb[PER];
-      if (l + 1 < nv) {
-        const auto Vn = V + (long)(l + 1) * NN;
+          for (int q = 0; q < PER; ++q) {
+            x[q] = Vl[ea_[q]];
+            x[PER + q] = Vl[ea_[q] + N];
+          }
+        },
+        [&](int l, const float* x) {
+          const float cl = sg * cf[l];
 #pragma unroll
-        for (int q = 0; q < PER; ++q) {
-          na[q] = Vn[ea_[q]];
-          nb[q] = Vn[ea_[q] + N];
-        }
-      }
-      const float cl = sg * cf[l];
-#pragma unroll
-      for (int q = 0; q < PER; ++q) {
-        va[q] += cl * la[q];
-        vb[q] += cl * lb[q];
-      }
-      if (l + 1 < nv) {
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-          la[q] = na[q];
-          lb[q] = nb[q];
-        }
-      }
-    }
+          for (int q = 0; q < PER; ++q) {
+            va[q] += cl * x[q];
+            vb[q] += cl * x[PER + q];
+          }
+        });
   }
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
@@ -503,38 +489,25 @@ __device__ __forceinline__ void passC_combine(const LaunchCtx& c, const PairDesc
     wa[q] = a;
     wb[q] = b;
   }
-  // block reduction of the j+1 inner products (fixed order); folded by k_dots_finalize.
-  // The loads of v_{l+1} are issued before the reduction of <w, v_l>.
+  // block reduction of the j+1 inner products (fixed order); folded by k_dots_finalize
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  float va[PER], vb[PER];
+  stream_vectors<2 * PER>(
+      j + 1,
+      [&](int l, float* x) {
+        const auto Vl = V + (long)l * NN;
 #pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    va[q] = V[ea_[q]];
-    vb[q] = V[ea_[q] + N];
-  }
-  for (int l = 0; l <= j; ++l) {
-    float na[PER], nb[PER];
-    if (l < j) {
-      const auto Vn = V + (long)(l + 1) * NN;
+        for (int q = 0; q < PER; ++q) {
+          x[q] = Vl[ea_[q]];
+          x[PER + q] = Vl[ea_[q] + N];
+        }
+      },
+      [&](int l, const float* x) {
+        float acc = 0.f;
 #pragma unroll
-      for (int q = 0; q < PER; ++q) {
-        na[q] = Vn[ea_[q]];
-        nb[q] = Vn[ea_[q] + N];
-      }
-    }
-    float acc = 0.f;
-#pragma unroll
-    for (int q = 0; q < PER; ++q) acc += wa[q] * va[q] + wb[q] * vb[q];
-    const double v = wave_sum((double)acc);
-    if (lane == 0) red[wid * (MA_MMAX + 1) + l] = v;
-    if (l < j) {
-#pragma unroll
-      for (int q = 0; q < PER; ++q) {
-        va[q] = na[q];
-        vb[q] = nb[q];
-      }
-    }
-  }
+        for (int q = 0; q < PER; ++q) acc += wa[q] * x[q] + wb[q] * x[PER + q];
+        const double v = wave_sum((double)acc);
+        if (lane == 0) red[wid * (MA_MMAX + 1) + l] = v;
+      });
   __syncthreads();
   if (threadIdx.x <= j) {
     double t = 0.0;
@@ -974,38 +947,24 @@ __global__ __launch_bounds__(64 * W) void k_passA_w(LaunchCtx c, int mode, int j
   if (mode == PA_ARNOLDI || mode == PA_RECOVER) {
     // v -= sum_l c_l V_l (Arnoldi) or x += sum_l y_l V_l (recovery), l in order
     const float sg = mode == PA_ARNOLDI ? -1.f : 1.f;
-    float la[OWN], lb[OWN];
-    if (nv > 0) {
+    stream_vectors<2 * OWN>(
+        nv,
+        [&](int l, float* x) {
+          const auto Vl = V + (long)l * NN;
 #pragma unroll
-      for (int q = 0; q < OWN; ++q) {
-        la[q] = V[ea_[q]];
-        lb[q] = V[ea_[q] + N];
-      }
-    }
-    for (int l = 0; l < nv; ++l) {
-      float na[OWN], nb[OWN];
-      if (l + 1 < nv) {
-        const auto Vn = V + (long)(l + 1) * NN;
+          for (int q = 0; q < OWN; ++q) {
+            x[q] = Vl[ea_[q]];
+            x[OWN + q] = Vl[ea_[q] + N];
+          }
+        },
+        [&](int l, const float* x) {
+          const float cl = sg * cf[l];
 #pragma unroll
-        for (int q = 0; q < OWN; ++q) {
-          na[q] = Vn[ea_[q]];
-          nb[q] = Vn[ea_[q] + N];
-        }
-      }
-      const float cl = sg * cf[l];
-#pragma unroll
-      for (int q = 0; q < OWN; ++q) {
-        va[q] += cl * la[q];
-        vb[q] += cl * lb[q];
-      }
-      if (l + 1 < nv) {
-#pragma unroll
-        for (int q = 0; q < OWN; ++q) {
-          la[q] = na[q];
-          lb[q] = nb[q];
-        }
-      }
-    }
+          for (int q = 0; q < OWN; ++q) {
+            va[q] += cl * x[q];
+            vb[q] += cl * x[OWN + q];
+          }
+        });
   }
 #pragma unroll
   for (int q = 0; q < OWN; ++q) {
