@@ -109,6 +109,26 @@ def copy_probe(mib):
     print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4}), flush=True)
 
 
+def copy_rate(mib=1024, reps=10):
+    """GB/s (bytes read + written) of a plain device-to-device copy of mib MiB, timed
+    with events over reps copies after one untimed: what a streaming copy reaches on
+    this part, a practical ceiling next to the published HBM peak."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1)
+    del src, dst
+    return 2.0 * n * 4 * reps / (ms * 1e-3) / 1e9
+
+
 def method_options(name, args):
     o = dict(METHODS[name])
     if args.gmres_tol is not None:
@@ -555,6 +575,9 @@ def main():
                        "bytes_per_launch": round(prof["bytes"] / max(prof["launches"], 1)),
                        "bytes_per_launch_all": round(bpl),
                        "algorithmic_bytes_timed": prof["bytes"]}
+    cr = copy_rate()  # after the timed region
+    out["roofline"]["copy_achieved"] = round(cr, 1)
+    out["roofline"]["frac_of_copy"] = round(achieved / cr, 4)
     if not args.no_configs and args.workload == "blobs":
         out["configs"] = extra_configs(args, maot, W, head[0], tuning_cache=args.tune_cache)
     if not args.no_cpu_baseline:
