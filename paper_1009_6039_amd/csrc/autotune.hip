@@ -258,7 +258,7 @@ int tune_passes(const TunerView& view, ma_tuning* t, hipStream_t st) {
       const double us = 1e3 * ms / reps;
       t->us_variant[pass][v] = us;
       if (v == 0) t->us_default[pass] = us;
-      if (v == 0 || us < 0.99 * best) {  // a variant must win by 1% to displace an earlier one
+      if (v == 0 || us < 0.98 * best) {  // a variant must win by 2% to displace an earlier one
         best = us;
         best_v = v;
       }

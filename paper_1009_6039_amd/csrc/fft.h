@@ -138,7 +138,14 @@ __device__ __forceinline__ void dft(float2 (&v)[R]) {
 // then eights, with sixteen split as 4 x 4 and leftovers as 4 or 2.  Plan 1: a factor 3
 // first, then fours, with a last eight or two.  Plan 2: a factor 3 first, then sixteens
 // (thirty-two as 8 x 4), then 8, 4 or 2.
+// Flag of a plan argument: the stages read every twiddle power w^r, r < R, from the
+// table (an LDS copy, so the extra reads cost no memory traffic) instead of forming the
+// higher powers as products of two or three table values, which saves their complex
+// multiplications.  The radix sequence is the plan's.
+constexpr int TW_FULL = 4;
+
 __host__ __device__ constexpr int pick_radix(int rem, int plan = 0) {
+  plan &= 3;
   if (rem % 3 == 0) return 3;
   if (plan == 1) return rem == 8 ? 8 : (rem % 4 == 0 ? 4 : 2);
   if (plan == 2 && rem % 16 == 0 && rem != 32) return 16;
@@ -158,13 +165,14 @@ __host__ __device__ constexpr bool plan_differs(int n, int plan) {
 
 // One more than the largest twiddle-table index a length-N transform reads: a stage
 // of radix R after sub-length NS > 1 reads tw[m k TWS], k < NS, TWS = N / (NS R), with
-// m up to 8 (R = 16), 4 (R = 8), 2 (R = 4, 3) or 1 (R = 2).
+// m up to 8 (R = 16), 4 (R = 8), 2 (R = 4, 3) or 1 (R = 2), or up to R - 1 under
+// TW_FULL.
 __host__ __device__ constexpr int tw_span(int n, int plan = 0) {
   int need = 1, ns = 1;
   while (ns < n) {
     const int r = pick_radix(n / ns, plan);
     if (ns > 1) {
-      const int top = r == 16 ? 8 : (r == 8 ? 4 : (r == 2 ? 1 : 2));
+      const int top = (plan & TW_FULL) ? r - 1 : (r == 16 ? 8 : (r == 8 ? 4 : (r == 2 ? 1 : 2)));
       const int idx = top * (ns - 1) * (n / (ns * r)) + 1;
       need = need > idx ? need : idx;
     }
@@ -212,7 +220,34 @@ __device__ __forceinline__ int lds_index(int t, int e) {
   else return e * NF + t;
 }
 
-template <int N, int NS, int R, int NF, int BLOCK, bool INV, int LAYOUT>
+// w[r] = tw[r k TWS] for 0 < r < R.  FULL: every power read from the table; otherwise
+// from at most three table entries (k r < NS R, so indices stay below N), products of
+// two table values keeping the error within a few ulp.
+template <int R, bool FULL>
+__device__ __forceinline__ void stage_powers(const float2* __restrict__ tw, int k, int TWS, float2 (&w)[R]) {
+  if constexpr (FULL) {
+#pragma unroll
+    for (int r = 1; r < R; ++r) w[r] = tw[r * k * TWS];
+  } else {
+    w[1] = tw[k * TWS];
+    if constexpr (R >= 3) w[2] = tw[2 * k * TWS];
+    if constexpr (R == 4) w[3] = cmul(w[1], w[2]);
+    if constexpr (R >= 8) {
+      w[4] = tw[4 * k * TWS];
+      w[3] = cmul(w[1], w[2]);
+      w[5] = cmul(w[4], w[1]);
+      w[6] = cmul(w[4], w[2]);
+      w[7] = cmul(w[4], w[3]);
+    }
+    if constexpr (R == 16) {  // w^8 from the table, the rest as w^8 w^(r - 8)
+      w[8] = tw[8 * k * TWS];
+#pragma unroll
+      for (int r = 9; r < 16; ++r) w[r] = cmul(w[8], w[r - 8]);
+    }
+  }
+}
+
+template <int N, int NS, int R, int NF, int BLOCK, bool INV, int LAYOUT, bool FULL = false>
 __device__ __forceinline__ void fft_stage(float2* lds, const float2* __restrict__ tw) {
   constexpr int NB = N / R;                  // butterflies per transform
   constexpr int ITEMS = NF * NB;
@@ -230,24 +265,8 @@ __device__ __forceinline__ void fft_stage(float2* lds, const float2* __restrict_
 #pragma unroll
       for (int r = 0; r < R; ++r) v[q][r] = lds[lds_index<N, NF, LAYOUT>(t, j + r * NB)];
       if (NS > 1) {
-        // w^r for r < R from at most three table entries (k r < NS R, so indices stay
-        // below N); products of two table values keep the error within a few ulp
         float2 w[R];
-        w[1] = tw[k * TWS];
-        if constexpr (R >= 3) w[2] = tw[2 * k * TWS];
-        if constexpr (R == 4) w[3] = cmul(w[1], w[2]);
-        if constexpr (R >= 8) {
-          w[4] = tw[4 * k * TWS];
-          w[3] = cmul(w[1], w[2]);
-          w[5] = cmul(w[4], w[1]);
-          w[6] = cmul(w[4], w[2]);
-          w[7] = cmul(w[4], w[3]);
-        }
-        if constexpr (R == 16) {  // w^8 from the table, the rest as w^8 w^(r - 8)
-          w[8] = tw[8 * k * TWS];
-#pragma unroll
-          for (int r = 9; r < 16; ++r) w[r] = cmul(w[8], w[r - 8]);
-        }
+        stage_powers<R, FULL>(tw, k, TWS, w);
 #pragma unroll
         for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], INV ? cconj(w[r]) : w[r]);
       }
@@ -275,8 +294,55 @@ template <int N, int NS, int NF, int BLOCK, bool INV, int LAYOUT, int PLAN = 0>
 __device__ __forceinline__ void fft_stages(float2* lds, const float2* __restrict__ tw) {
   if constexpr (NS < N) {
     constexpr int R = pick_radix(N / NS, PLAN);
-    fft_stage<N, NS, R, NF, BLOCK, INV, LAYOUT>(lds, tw);
+    fft_stage<N, NS, R, NF, BLOCK, INV, LAYOUT, (PLAN & TW_FULL) != 0>(lds, tw);
     fft_stages<N, NS * R, NF, BLOCK, INV, LAYOUT, PLAN>(lds, tw);
+  }
+}
+
+// The last stage of a transform (NS R = N) handing its outputs to out(t, e, value),
+// element e of sequence t, instead of writing them back to LDS: the caller's stores go
+// straight to memory.  It reads LDS and ends without a barrier, so the caller
+// synchronises before anything writes `lds` again.
+template <int N, int NS, int R, int NF, int BLOCK, bool INV, int LAYOUT, bool FULL, class OUT>
+__device__ __forceinline__ void fft_stage_out(const float2* lds, const float2* __restrict__ tw, OUT out) {
+  static_assert(NS * R == N, "the last stage");
+  constexpr int NB = N / R;
+  constexpr int ITEMS = NF * NB;
+  constexpr int PER = (ITEMS + BLOCK - 1) / BLOCK;
+  constexpr int TWS = N / (NS * R);
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int it = threadIdx.x + q * BLOCK;
+    if (ITEMS % BLOCK == 0 || it < ITEMS) {
+      int t, j;
+      if constexpr (LAYOUT == LAYOUT_ROWS) { t = it / NB; j = it % NB; }
+      else { t = it % NF; j = it / NF; }
+      const int k = j % NS;  // = j: the last stage has NB = NS butterflies per sequence
+      float2 v[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[r] = lds[lds_index<N, NF, LAYOUT>(t, j + r * NB)];
+      if (NS > 1) {
+        float2 w[R];
+        stage_powers<R, FULL>(tw, k, TWS, w);
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[r] = cmul(v[r], INV ? cconj(w[r]) : w[r]);
+      }
+      dft<R, INV>(v);
+#pragma unroll
+      for (int r = 0; r < R; ++r) out(t, k + r * NS, v[r]);
+    }
+  }
+}
+
+// All stages in LDS but the last, which hands its outputs to out (fft_stage_out)
+template <int N, int NS, int NF, int BLOCK, bool INV, int LAYOUT, int PLAN, class OUT>
+__device__ __forceinline__ void fft_stages_out(float2* lds, const float2* __restrict__ tw, OUT out) {
+  constexpr int R = pick_radix(N / NS, PLAN);
+  if constexpr (NS * R < N) {
+    fft_stage<N, NS, R, NF, BLOCK, INV, LAYOUT, (PLAN & TW_FULL) != 0>(lds, tw);
+    fft_stages_out<N, NS * R, NF, BLOCK, INV, LAYOUT, PLAN>(lds, tw, out);
+  } else {
+    fft_stage_out<N, NS, R, NF, BLOCK, INV, LAYOUT, (PLAN & TW_FULL) != 0>(lds, tw, out);
   }
 }
 
@@ -298,6 +364,26 @@ __device__ __forceinline__ void fft_cols_from_regs(float2* lds, const float2* __
   for (int r = 0; r < R0; ++r) lds[lds_index<N, NF, LAYOUT_COLS>(t, j * R0 + r)] = x[r];
   __syncthreads();
   fft_stages<N, R0, NF, BLOCK, INV, LAYOUT_COLS, PLAN>(lds, tw);
+}
+
+// fft_cols_from_regs whose last stage hands its outputs to out(t, e, value) (see
+// fft_stage_out); ends without a barrier.
+template <int N, int NF, int BLOCK, bool INV, int PLAN, class OUT>
+__device__ __forceinline__ void fft_cols_from_regs_out(float2* lds, const float2* __restrict__ tw,
+                                                       float2 (&x)[pick_radix(N, PLAN)], OUT out) {
+  constexpr int R0 = pick_radix(N, PLAN);
+  static_assert(BLOCK == NF * (N / R0), "one first-stage butterfly per thread");
+  const int t = threadIdx.x % NF, j = threadIdx.x / NF;
+  dft<R0, INV>(x);
+  if constexpr (R0 == N) {  // a single stage: the outputs are the thread's registers
+#pragma unroll
+    for (int r = 0; r < R0; ++r) out(t, r, x[r]);
+  } else {
+#pragma unroll
+    for (int r = 0; r < R0; ++r) lds[lds_index<N, NF, LAYOUT_COLS>(t, j * R0 + r)] = x[r];
+    __syncthreads();
+    fft_stages_out<N, R0, NF, BLOCK, INV, LAYOUT_COLS, PLAN>(lds, tw, out);
+  }
 }
 
 // In-place transforms of NF sequences in LDS.  Caller synchronises before (data

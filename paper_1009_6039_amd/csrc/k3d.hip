@@ -533,11 +533,11 @@ __global__ __launch_bounds__(MA3_BLOCK) void k3_p1(Desc3 d, const State3* s, int
   constexpr int PER = R * N / MA3_BLOCK;
   static_assert((R * N) % MA3_BLOCK == 0, "whole elements per thread");
   __shared__ float2 L[R * N];
-  __shared__ float2 twl[tw_span(N)];
+  __shared__ float2 twl[tw_span(N, TW_FULL)];
   const long nn = (long)N * N * N;
   const float* in = mode == P3_MATVEC ? d.V + (long)j * nn : d.x;
   const long base = (long)blockIdx.x * R * N;
-  TwiddleStage<N, MA3_BLOCK> tws;  // issued before the data loads
+  TwiddleStage<N, MA3_BLOCK, TW_FULL> tws;  // issued before the data loads
   tws.load(d.tw);
   float x[PER];
 #pragma unroll
@@ -546,7 +546,7 @@ __global__ __launch_bounds__(MA3_BLOCK) void k3_p1(Desc3 d, const State3* s, int
 #pragma unroll
   for (int q = 0; q < PER; ++q) L[threadIdx.x + q * MA3_BLOCK] = make_float2(x[q], 0.f);
   __syncthreads();
-  fft_lds<N, R, MA3_BLOCK, false, LAYOUT_ROWS>(L, twl);
+  fft_lds<N, R, MA3_BLOCK, false, LAYOUT_ROWS, TW_FULL>(L, twl);
   for (int e = threadIdx.x; e < R * N; e += MA3_BLOCK) d.S[base + e] = L[e];
 }
 
@@ -565,10 +565,10 @@ __global__ __launch_bounds__(MA3_BLOCK) void k3_p2(Desc3 d, const State3* s, int
   constexpr int PER = N * C / MA3_BLOCK;
   static_assert((N * C) % MA3_BLOCK == 0, "whole elements per thread");
   __shared__ float2 L[N * C];
-  __shared__ float2 twl[tw_span(N)];
+  __shared__ float2 twl[tw_span(N, TW_FULL)];
   const int i = blockIdx.x / (N / C), k0 = (blockIdx.x % (N / C)) * C;
   const long b0 = (long)i * N * N + k0;  // element (i, jj, k0 + t) at b0 + jj N + t
-  TwiddleStage<N, MA3_BLOCK> tws;  // issued before the data loads
+  TwiddleStage<N, MA3_BLOCK, TW_FULL> tws;  // issued before the data loads
   tws.load(d.tw);
   float2 v[PER];
 #pragma unroll
@@ -577,7 +577,7 @@ __global__ __launch_bounds__(MA3_BLOCK) void k3_p2(Desc3 d, const State3* s, int
 #pragma unroll
   for (int q = 0; q < PER; ++q) L[threadIdx.x + q * MA3_BLOCK] = v[q];
   __syncthreads();
-  fft_lds<N, C, MA3_BLOCK, false, LAYOUT_COLS>(L, twl);
+  fft_lds<N, C, MA3_BLOCK, false, LAYOUT_COLS, TW_FULL>(L, twl);
   for (int e = threadIdx.x; e < N * C; e += MA3_BLOCK) d.S[col_index<N, C>(b0, N, e)] = L[e];
 }
 
@@ -591,7 +591,8 @@ __device__ __forceinline__ float2 rhobar3(int q1, int q2, int q3, float2 m1, flo
   const float im = ab[6] * m1.x + ab[7] * m2.x + ab[8] * m3.x;
   const float den = re * re + im * im;
   if ((q1 == 0 && q2 == 0 && q3 == 0) || den == 0.f) return make_float2(0.f, 0.f);
-  return make_float2(re / den, -im / den);
+  const float inv = 1.f / den;  // one division for both parts
+  return make_float2(re * inv, -im * inv);
 }
 
 // P3: forward transform along x1, times rhobar and the scale, inverse transforms of
@@ -605,10 +606,10 @@ __global__ __launch_bounds__(MA3_BLOCK) void k3_p3(Desc3 d, const State3* s, int
   constexpr int PER = N * C / MA3_BLOCK;
   static_assert((N * C) % MA3_BLOCK == 0, "whole elements per thread");
   __shared__ float2 L[N * C];
-  __shared__ float2 twl[tw_span(N)];
+  __shared__ float2 twl[tw_span(N, TW_FULL)];
   const int jj = blockIdx.x / (N / C), k0 = (blockIdx.x % (N / C)) * C;
   const long b0 = (long)jj * N + k0;  // element (i, jj, k0 + t) at b0 + i N^2 + t
-  TwiddleStage<N, MA3_BLOCK> tws;  // issued before the data loads
+  TwiddleStage<N, MA3_BLOCK, TW_FULL> tws;  // issued before the data loads
   tws.load(d.tw);
   float2 v[PER];
 #pragma unroll
@@ -625,7 +626,7 @@ __global__ __launch_bounds__(MA3_BLOCK) void k3_p3(Desc3 d, const State3* s, int
 #pragma unroll
   for (int q = 0; q < PER; ++q) L[threadIdx.x + q * MA3_BLOCK] = v[q];
   __syncthreads();
-  fft_lds<N, C, MA3_BLOCK, false, LAYOUT_COLS>(L, twl);
+  fft_lds<N, C, MA3_BLOCK, false, LAYOUT_COLS, TW_FULL>(L, twl);
   // Z = rhobar * spectrum * scale, kept in registers (each thread its own elements)
   float2 z[PER];
 #pragma unroll
@@ -644,7 +645,7 @@ __global__ __launch_bounds__(MA3_BLOCK) void k3_p3(Desc3 d, const State3* s, int
           o == 0 ? z[q] : (o == 1 ? make_float2(-m[q].x * z[q].y, m[q].x * z[q].x) : cscale(z[q], m[q].y));
     }
     __syncthreads();
-    fft_lds<N, C, MA3_BLOCK, true, LAYOUT_COLS>(L, twl);
+    fft_lds<N, C, MA3_BLOCK, true, LAYOUT_COLS, TW_FULL>(L, twl);
     float2* T = d.T + (long)o * NN;
     for (int e = threadIdx.x; e < N * C; e += MA3_BLOCK) T[col_index<N, C>(b0, (long)N * N, e)] = L[e];
   }
@@ -662,7 +663,7 @@ __global__ __launch_bounds__(MA3_BLOCK) void k3_p4(Desc3 d, const State3* s, int
   constexpr int PER = N * C / MA3_BLOCK;
   static_assert((N * C) % MA3_BLOCK == 0, "whole elements per thread");
   __shared__ float2 L[N * C];
-  __shared__ float2 twl[tw_span(N)];
+  __shared__ float2 twl[tw_span(N, TW_FULL)];
   const int i = blockIdx.x / (N / C), k0 = (blockIdx.x % (N / C)) * C;
   const long b0 = (long)i * N * N + k0;
   // sources in order (T plane, first output, outputs): T2 -> U_a; T1 -> U_b, U_c (i d1);
@@ -670,7 +671,7 @@ __global__ __launch_bounds__(MA3_BLOCK) void k3_p4(Desc3 d, const State3* s, int
   const bool mv = mode == P3_MATVEC;
   const int nsrc = mv ? 3 : 1;
   auto src_plane = [&](int si) { return mv ? 2 - si : 0; };
-  TwiddleStage<N, MA3_BLOCK> tws;  // issued before the data loads
+  TwiddleStage<N, MA3_BLOCK, TW_FULL> tws;  // issued before the data loads
   tws.load(d.tw);
   float2 cur[PER], nxt[PER], m[PER];
 #pragma unroll
@@ -694,7 +695,7 @@ __global__ __launch_bounds__(MA3_BLOCK) void k3_p4(Desc3 d, const State3* s, int
             mu == 0 ? v : (mu == 1 ? make_float2(-m[q].x * v.y, m[q].x * v.x) : cscale(v, m[q].y));
       }
       __syncthreads();
-      fft_lds<N, C, MA3_BLOCK, true, LAYOUT_COLS>(L, twl);
+      fft_lds<N, C, MA3_BLOCK, true, LAYOUT_COLS, TW_FULL>(L, twl);
       float2* Uo = d.U + (long)out * NN;
       for (int e = threadIdx.x; e < N * C; e += MA3_BLOCK) Uo[col_index<N, C>(b0, N, e)] = L[e];
       __syncthreads();  // the stores have read L before the next transform overwrites it
@@ -716,10 +717,10 @@ __global__ __launch_bounds__(MA3_BLOCK) void k3_p5(Desc3 d, const State3* s, int
   constexpr int PER = R5 * N / MA3_BLOCK;
   static_assert((R5 * N) % MA3_BLOCK == 0, "whole elements per thread");
   __shared__ float2 L[NT * R5 * N];
-  __shared__ float2 twl[tw_span(N)];
+  __shared__ float2 twl[tw_span(N, TW_FULL)];
   __shared__ double red[(MA3_BLOCK / 64) * (MA3_MMAX + 1)];
   const long base = (long)blockIdx.x * R5 * N;  // first element of the block's lines
-  TwiddleStage<N, MA3_BLOCK> tws;  // issued before the data loads
+  TwiddleStage<N, MA3_BLOCK, TW_FULL> tws;  // issued before the data loads
   tws.load(d.tw);
   if (mode != P3_MATVEC) {
     const float2* Ud = d.U + 3 * NN;
@@ -730,7 +731,7 @@ __global__ __launch_bounds__(MA3_BLOCK) void k3_p5(Desc3 d, const State3* s, int
 #pragma unroll
     for (int q = 0; q < PER; ++q) L[threadIdx.x + q * MA3_BLOCK] = v[q];
     __syncthreads();
-    fft_lds<N, R5, MA3_BLOCK, true, LAYOUT_ROWS>(L, twl);
+    fft_lds<N, R5, MA3_BLOCK, true, LAYOUT_ROWS, TW_FULL>(L, twl);
     for (int e = threadIdx.x; e < R5 * N; e += MA3_BLOCK) {
       const double th = (double)L[e].x;
       if (mode == P3_THETA) {
@@ -775,7 +776,7 @@ __global__ __launch_bounds__(MA3_BLOCK) void k3_p5(Desc3 d, const State3* s, int
     L[(4 * R5 + l) * N + k] = id;
   }
   __syncthreads();
-  fft_lds<N, NT * R5, MA3_BLOCK, true, LAYOUT_ROWS>(L, twl);
+  fft_lds<N, NT * R5, MA3_BLOCK, true, LAYOUT_ROWS, TW_FULL>(L, twl);
   float* W = d.V + (long)(j + 1) * NN;
   // the nine coefficients at all of the thread's points, loaded before the first is used
   float cf[9][PER];

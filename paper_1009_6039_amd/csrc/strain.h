@@ -86,7 +86,8 @@ __device__ __forceinline__ float2 rhobar_m(int q, int q2, float2 m1, float2 m2, 
   const float re = ab[0] * m1.y + ab[2] * m2.y - 2.f * ab[1] * m1.x * m2.x;
   const float im = ab[3] * m1.x + ab[4] * m2.x;
   const float den = re * re + im * im;
-  return make_float2(re / den, -im / den);
+  const float inv = 1.f / den;  // one division for both parts
+  return make_float2(re * inv, -im * inv);
 }
 // the same with the multipliers read from the table mt
 template <int N>
@@ -284,7 +285,8 @@ __global__ __launch_bounds__((Cfg<N, G>::B_BLOCK)) void k_passB(LaunchCtx c, int
   // S: the column spectra, then rhobar * sigmahat, then each output spectrum in turn.
   // Element (row or wavenumber e, column cc) sits at e * CPB + cc.
   __shared__ float2 S[N * CPB];
-  __shared__ float2 twl[tw_span(N, PL)];
+  constexpr int PT = PL | TW_FULL;  // the transforms read every twiddle power from twl
+  __shared__ float2 twl[tw_span(N, PT)];
   const int s0 = blockIdx.x * CPB;
   const auto H = gmem<const float2>(d.H);
   const auto T = gmem<float2>(d.T);
@@ -309,7 +311,7 @@ __global__ __launch_bounds__((Cfg<N, G>::B_BLOCK)) void k_passB(LaunchCtx c, int
   for (int k = 0; k < 5; ++k) ab[k] = (float)s.abar[k];
   {  // every column load of the thread in flight before the first LDS write; the
      // twiddles first, so that their copy into LDS waits for them alone
-    TwiddleStage<N, BLOCK, PL> tws;
+    TwiddleStage<N, BLOCK, PT> tws;
     tws.load(tw);
     float2 h[PER];
 #pragma unroll
@@ -331,12 +333,12 @@ __global__ __launch_bounds__((Cfg<N, G>::B_BLOCK)) void k_passB(LaunchCtx c, int
     mnh = c.mt[NH];
     tws.store(twl);
     if constexpr (REG1) {
-      fft_cols_from_regs<N, CPB, BLOCK, false, PL>(S, twl, h);
+      fft_cols_from_regs<N, CPB, BLOCK, false, PT>(S, twl, h);
     } else {
 #pragma unroll
       for (int q = 0; q < PER; ++q) S[threadIdx.x + q * BLOCK] = h[q];
       __syncthreads();
-      fft_lds<N, CPB, BLOCK, false, LAYOUT_COLS, PL>(S, twl);
+      fft_lds<N, CPB, BLOCK, false, LAYOUT_COLS, PT>(S, twl);
     }
   }
   const float scale = (float)((mode == PB_MATVEC ? vsj : 1.0) / ((double)N * (double)N));
@@ -387,6 +389,9 @@ __global__ __launch_bounds__((Cfg<N, G>::B_BLOCK)) void k_passB(LaunchCtx c, int
   const int nout = mode == PB_MATVEC ? 3 : 1;
   for (int oo = 0; oo < nout; ++oo) {
     const int o = (oo + 1) % 3 == 0 || nout == 1 ? 0 : oo + 1;  // order 1, 2, 0
+    // the last radix stage stores its outputs (row e of column t) straight to memory
+    const auto To = T + (long)o * N * NH + s0;
+    auto store = [&](int t, int e, float2 v) { To[(long)e * NH + t] = v; };
     if constexpr (REG1) {
       float2 x[PER];
 #pragma unroll
@@ -394,7 +399,7 @@ __global__ __launch_bounds__((Cfg<N, G>::B_BLOCK)) void k_passB(LaunchCtx c, int
         const float2 m = mo[k];
         x[k] = o == 0 ? sv[k] : ((o == 1) ? times_i(m.x, sv[k]) : cscale(sv[k], m.y));
       }
-      fft_cols_from_regs<N, CPB, BLOCK, true, PL>(S, twl, x);
+      fft_cols_from_regs_out<N, CPB, BLOCK, true, PT>(S, twl, x, store);
     } else {
       if (oo > 0 || o != 0) {  // S still holds the plain spectrum for a lone output 0
 #pragma unroll
@@ -405,14 +410,9 @@ __global__ __launch_bounds__((Cfg<N, G>::B_BLOCK)) void k_passB(LaunchCtx c, int
         }
         __syncthreads();
       }
-      fft_lds<N, CPB, BLOCK, true, LAYOUT_COLS, PL>(S, twl);
+      fft_stages_out<N, 1, CPB, BLOCK, true, LAYOUT_COLS, PT>(S, twl, store);
     }
-    const auto To = T + (long)o * N * NH;
-    for (int e = threadIdx.x; e < N * CPB; e += BLOCK) {
-      const int i = e / CPB, c2 = e % CPB;
-      To[(long)i * NH + s0 + c2] = S[e];
-    }
-    __syncthreads();
+    __syncthreads();  // the last stage has read S before the next output overwrites it
   }
 }
 
@@ -580,8 +580,9 @@ __global__ __launch_bounds__((Cfg<N, G>::C_BLOCK)) void k_passC(LaunchCtx c, int
 
   // five complex inverse transforms per row pair; every spectrum load of the thread
   // is issued before the first LDS write
-  __shared__ float2 twl[PF ? tw_span(N, PL) : 1];
-  TwiddleStage<N, BLOCK, PL> tws;
+  constexpr int PT = PF ? (PL | TW_FULL) : PL;  // with the LDS copy, every twiddle power from it
+  __shared__ float2 twl[PF ? tw_span(N, PT) : 1];
+  TwiddleStage<N, BLOCK, PT> tws;
   if constexpr (PF) tws.load(tw);
   constexpr int IT1 = (PPB * NH + BLOCK - 1) / BLOCK;
   constexpr bool FULL1 = (PPB * NH) % BLOCK == 0;
@@ -637,7 +638,7 @@ __global__ __launch_bounds__((Cfg<N, G>::C_BLOCK)) void k_passC(LaunchCtx c, int
     }
   }
   __syncthreads();
-  fft_lds<N, 5 * PPB, BLOCK, true, LAYOUT_ROWS, PL>(lds, PF ? twl : tw);
+  fft_lds<N, 5 * PPB, BLOCK, true, LAYOUT_ROWS, PT>(lds, PF ? twl : tw);
   // the coefficients at all of the thread's points are loaded before the first is used
   if constexpr (!PF) passC_load_coef<N, PPB, BLOCK>(d, row0, pre);
   passC_combine<N, PPB, BLOCK>(c, d, trbar, j, row0, red,
