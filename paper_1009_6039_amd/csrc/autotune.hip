@@ -242,30 +242,44 @@ int tune_passes(const TunerView& view, ma_tuning* t, hipStream_t st) {
         t->rejected++;
         continue;
       }
-      const int reps = 20;
-      for (int w = 0; w < 2 && !err; ++w) err = run_pass(tv, pass, jn, st);
-      if (err || hipEventRecord(e0, st) != hipSuccess) {
-        err = err ? err : MA_EHIP;
-        break;
-      }
-      for (int r = 0; r < reps && !err; ++r) err = run_pass(tv, pass, jn, st);
-      float ms = 0.f;
-      if (err || hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-        err = err ? err : MA_EHIP;
-        break;
-      }
-      const double us = 1e3 * ms / reps;
+      // microseconds per launch of this pass over the view's pairs (2 untimed launches,
+      // then 20 timed)
+      auto time_pass = [&](const TunerView& view, double& us_out) {
+        const int reps = 20;
+        for (int w = 0; w < 2 && !err; ++w) err = run_pass(view, pass, jn, st);
+        if (err || hipEventRecord(e0, st) != hipSuccess) {
+          err = err ? err : MA_EHIP;
+          return;
+        }
+        for (int r = 0; r < reps && !err; ++r) err = run_pass(view, pass, jn, st);
+        float ms = 0.f;
+        if (err || hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+          err = err ? err : MA_EHIP;
+          return;
+        }
+        us_out = 1e3 * ms / reps;
+      };
+      // A solve's launches shrink as pairs finish their GMRES cycles and their Newton
+      // steps, so each variant is timed on the whole batch and on a sixteenth of it; the
+      // score adds the two per full batch of work.
+      double us = 0.0, us_part = 0.0;
+      time_pass(tv, us);
+      TunerView part = tv;
+      part.npairs = std::max(1, tv.npairs / 16);
+      if (!err && part.npairs < tv.npairs) time_pass(part, us_part);
+      if (err) break;
+      const double score = us + us_part * ((double)tv.npairs / part.npairs);
       t->us_variant[pass][v] = us;
       if (v == 0) t->us_default[pass] = us;
-      if (v == 0 || us < 0.98 * best) {  // a variant must win by 2% to displace an earlier one
-        best = us;
+      if (v == 0 || score < 0.98 * best) {  // a variant must win by 2% to displace an earlier one
+        best = score;
         best_v = v;
+        t->us[pass] = us;
       }
     }
     tv.ctx.var[pass] = best_v;  // later passes run on the chosen geometry of this one
     t->variant[pass] = best_v;
-    t->us[pass] = best;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
