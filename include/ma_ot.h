@@ -32,7 +32,7 @@
 extern "C" {
 #endif
 
-#define MA_OT_ABI_VERSION 11
+#define MA_OT_ABI_VERSION 12
 
 /* return / status codes */
 #define MA_OK 0           /* converged: rms residual <= tol                           */
@@ -385,13 +385,21 @@ typedef struct ma_tuning {
   double us_variant[4][MA_TUNE_SLOTS]; /* per-launch time of every variant timed, -1 where a
                                           variant was skipped (duplicate, rejected, absent);
                                           zeros when read from the cache */
+  int npairs_part;     /* pairs of the partial-batch timing: npairs / 16, at least 1 */
+  double us_part_variant[4][MA_TUNE_SLOTS]; /* per-launch time of every variant on the
+                                          first npairs_part pairs (0 where npairs_part equals
+                                          npairs); -1 and zeros as in us_variant.  A variant's
+                                          score is us_variant + us_part_variant * npairs /
+                                          npairs_part; the choice is the lowest score, an
+                                          earlier variant kept unless beaten by 2% */
 } ma_tuning;
 
 /* Times every distinct variant of each kernel class on `npairs` synthetic pairs of
  * side n (smooth densities, coefficients near the Laplacian's, pseudo-random Krylov
  * vectors), rejects a variant whose output differs from the default geometry's by
  * more than FP32 reordering (fields 1e-6, folded partial sums 1e-5 of their
- * magnitude), and makes the fastest the plan's choice for n.  If cache_path is not
+ * magnitude), times each on all npairs and on the first npairs / 16 (a solve's launches
+ * shrink as pairs finish), and makes the best score (ma_tuning) the plan's choice for n.  If cache_path is not
  * NULL and holds an entry for this device, library build, n, npairs and the plan's
  * gmres_m, that entry is used instead; otherwise the result is added to the file
  * (a small JSON document, one entry per line).  Uses the plan's workspace (any

@@ -220,8 +220,10 @@ int tune_passes(const TunerView& view, ma_tuning* t, hipStream_t st) {
   TRY_HIP(hipEventCreate(&e0));
   TRY_HIP(hipEventCreate(&e1));
   int err = MA_OK;
+  const int npart = std::max(1, tv.npairs / 16);
+  t->npairs_part = npart;
   for (int k = 0; k < 4; ++k)
-    for (int v = 0; v < MA_TUNE_SLOTS; ++v) t->us_variant[k][v] = -1.0;
+    for (int v = 0; v < MA_TUNE_SLOTS; ++v) t->us_variant[k][v] = t->us_part_variant[k][v] = -1.0;
   // the residual first: it writes the coefficients that pass C reads
   const int order[4] = {3, 0, 1, 2};
   for (int oi = 0; oi < 4 && !err; ++oi) {
@@ -266,11 +268,12 @@ int tune_passes(const TunerView& view, ma_tuning* t, hipStream_t st) {
       double us = 0.0, us_part = 0.0;
       time_pass(tv, us);
       TunerView part = tv;
-      part.npairs = std::max(1, tv.npairs / 16);
+      part.npairs = npart;
       if (!err && part.npairs < tv.npairs) time_pass(part, us_part);
       if (err) break;
       const double score = us + us_part * ((double)tv.npairs / part.npairs);
       t->us_variant[pass][v] = us;
+      t->us_part_variant[pass][v] = us_part;
       if (v == 0) t->us_default[pass] = us;
       if (v == 0 || score < 0.98 * best) {  // a variant must win by 2% to displace an earlier one
         best = score;

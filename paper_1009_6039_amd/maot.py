@@ -53,14 +53,18 @@ class Tuning(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("npairs", ctypes.c_int), ("variant", ctypes.c_int * 4),
                 ("from_cache", ctypes.c_int), ("rejected", ctypes.c_int),
                 ("us", ctypes.c_double * 4), ("us_default", ctypes.c_double * 4),
-                ("us_variant", (ctypes.c_double * 12) * 4)]
+                ("us_variant", (ctypes.c_double * 12) * 4), ("npairs_part", ctypes.c_int),
+                ("us_part_variant", (ctypes.c_double * 12) * 4)]
 
     def as_dict(self):
         return {"n": self.n, "npairs": self.npairs, "variant": list(self.variant),
                 "from_cache": bool(self.from_cache), "rejected": self.rejected,
                 "us": list(self.us), "us_default": list(self.us_default),
                 "us_variant": {name: [round(x, 2) for x in self.us_variant[k]]
-                               for k, name in enumerate(TUNE_PASSES)}}
+                               for k, name in enumerate(TUNE_PASSES)},
+                "npairs_part": self.npairs_part,
+                "us_part_variant": {name: [round(x, 3) for x in self.us_part_variant[k]]
+                                    for k, name in enumerate(TUNE_PASSES)}}
 
 
 TUNE_PASSES = ("row_a", "column", "row_c", "residual")

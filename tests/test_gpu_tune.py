@@ -64,9 +64,18 @@ def test_autotune_chooses_verified_variants_and_caches(maot, tmp_path, n, npairs
         t = p.autotune(n, npairs, cache)
         print("autotune", n, npairs, t)
         assert not t["from_cache"] and t["rejected"] == 0
+        assert t["npairs_part"] == max(1, npairs // 16)
+        scale = npairs / t["npairs_part"]
         for k, name in enumerate(maot.TUNE_PASSES):
-            assert maot.tune_geometry(name, n, t["variant"][k])[0] == t["variant"][k]
-            assert 0 < t["us"][k] <= t["us_default"][k] * 1.0001
+            v = t["variant"][k]
+            assert maot.tune_geometry(name, n, v)[0] == v
+            assert 0 < t["us"][k] and t["us"][k] == pytest.approx(t["us_variant"][name][v], rel=1e-3, abs=0.01)
+            # the choice: the default or a variant whose full-plus-partial score beats
+            # every earlier kept choice by 2%, so never worse than the default's score
+            score = [a + b * scale if a > 0 else None
+                     for a, b in zip(t["us_variant"][name], t["us_part_variant"][name])]
+            assert score[v] is not None and score[0] is not None
+            assert score[v] <= score[0] * 1.0001
         assert p.get_tuning(n) == t["variant"]
         doc = json.load(open(cache))
         assert len(doc["entries"]) == 1 and doc["entries"][0]["n"] == n
