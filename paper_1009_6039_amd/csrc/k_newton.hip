@@ -611,6 +611,39 @@ __global__ __launch_bounds__(256) void k_compact(const PairState* st, const int*
   }
 }
 
+// The pairs of one class's launch list (its first *in_n entries, or count where in_n is
+// null) that are inside a GMRES cycle, in list order, and their number: the launch
+// list of the cycle's later iterations once pairs have left it.
+__global__ __launch_bounds__(256) void k_compact_running(const PairState* st, const int* in, const int* in_n,
+                                                         int count, int* out, int* out_n) {
+  const int n = in_n ? min(*in_n, count) : count;
+  __shared__ int sr[256];
+  __shared__ int base;
+  if (threadIdx.x == 0) base = 0;
+  __syncthreads();
+  for (int b = 0; b < n; b += 256) {
+    const int q = b + threadIdx.x;
+    int id = 0, f = 0;
+    if (q < n) {
+      id = in[q];
+      f = st[id].phase == PH_SOLVE && st[id].gm_running;
+    }
+    sr[threadIdx.x] = f;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {  // inclusive scan
+      const int a = threadIdx.x >= o ? sr[threadIdx.x - o] : 0;
+      __syncthreads();
+      sr[threadIdx.x] += a;
+      __syncthreads();
+    }
+    if (f) out[base + sr[threadIdx.x] - 1] = id;
+    __syncthreads();
+    if (threadIdx.x == 255) base += sr[255];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out_n = base;
+}
+
 // Continuous batching.  k_retire: for the slots in the launch's id list (pairs that
 // finished), the outputs of k_outputs and the final state into final[pair].
 __global__ __launch_bounds__(MA_BLOCK) void k_retire(LaunchCtx c, PairState* final_state) {
@@ -816,6 +849,11 @@ void launch_summary(const PairState* s, const int* ids, int npairs, int* out, in
 void launch_compact(const PairState* st_, const int* ids, const int2* cls, int ncls, int* live, int* solving, int* cnt,
                     hipStream_t st) {
   hipLaunchKernelGGL(k_compact, dim3(ncls), dim3(256), 0, st, st_, ids, cls, live, solving, cnt);
+}
+
+void launch_compact_running(const PairState* st_, const int* in, const int* in_n, int count, int* out, int* out_n,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_compact_running, dim3(1), dim3(256), 0, st, st_, in, in_n, count, out, out_n);
 }
 
 void launch_retire(const LaunchCtx& c, int n, int count, PairState* final_state, hipStream_t st) {

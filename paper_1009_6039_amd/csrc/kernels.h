@@ -46,6 +46,9 @@ void launch_summary(const PairState* s, const int* ids, int npairs, int* out, in
 // compacted launch lists per size class (live: not done; solving: in a Newton direction)
 void launch_compact(const PairState* state, const int* ids, const int2* cls, int ncls, int* live, int* solving,
                     int* cnt, hipStream_t st);
+// the pairs of a launch list still inside their GMRES cycle (order kept) and their number
+void launch_compact_running(const PairState* state, const int* in, const int* in_n, int count, int* out,
+                            int* out_n, hipStream_t st);
 // continuous batching: outputs and final states of finished slots (ids in the context),
 // refill records scattered into their slots, validation of every pair's inputs
 void launch_retire(const LaunchCtx& c, int n, int count, PairState* final_state, hipStream_t st);

@@ -57,7 +57,8 @@ struct ma_plan {
   PairState* d_state = nullptr;
   int* d_ids = nullptr;
   // compacted lists: live ids, solving ids (pairs_cap each), then per class (offset,
-  // count) and the two counts
+  // count) and the two counts, then the GMRES cycle's running ids and their counts
+  // (not in the no-allocation mode, whose lists hold the first six only)
   int* d_lists = nullptr;
   int pairs_cap = 0;
   // host-loop counters: 4 slots of MA_SUMMARY_INTS (the synchronous read, then a ring
@@ -255,7 +256,8 @@ int ensure_workspace(ma_plan* P, const std::vector<int>& ns) {
     if (hipMalloc(&P->d_desc, sizeof(PairDesc) * np) != hipSuccess) return MA_ENOMEM;
     if (hipMalloc(&P->d_state, sizeof(PairState) * np) != hipSuccess) return MA_ENOMEM;
     if (hipMalloc(&P->d_ids, sizeof(int) * np) != hipSuccess) return MA_ENOMEM;
-    if (hipMalloc(&P->d_lists, sizeof(int) * 6 * (size_t)np) != hipSuccess) return MA_ENOMEM;
+    // live, solving, class table (2), counts (2), running, running counts
+    if (hipMalloc(&P->d_lists, sizeof(int) * 8 * (size_t)np) != hipSuccess) return MA_ENOMEM;
     P->pairs_cap = np;
   }
   P->h_desc.assign(np, PairDesc{});
@@ -468,12 +470,18 @@ void compact_views(ma_plan* P, ClassList cls, int n_live, int n_solve, std::vect
 // queued after each iteration, and the host reads the one queued two iterations
 // earlier (so the device queue never drains while the host waits): once no pair is
 // inside the cycle, the remaining iterations, which would all exit at once, are not
-// launched.  At most two such iterations are queued.
+// launched.  At most two such iterations are queued.  Pairs leave the cycle at
+// different iterations; once that summary shows fewer than three quarters of a
+// launch's pairs still inside, the launch lists are compacted on the device to those
+// pairs and the grids sized by the summary's count (an upper bound for every later
+// iteration of the cycle), so that the blocks of pairs that left are not launched.
 int launch_cycle_body(ma_plan* P, ClassList cls, int npairs, hipStream_t st) {
   const int m = P->opt.gmres_m;
   constexpr int LAG = 2, FIRST = 2;
+  std::vector<Class> run(cls.begin(), cls.end());  // the launch views of the iterations
+  const size_t cap = P->pairs_cap;
   for (int j = 0; j < m; ++j) {
-    for (const Class& c : cls) {
+    for (const Class& c : run) {
       L_B(P, c, PB_MATVEC, j, st);
       L_C(P, c, PC_MATVEC, j, st);
       L_A(P, c, PA_ARNOLDI, j + 1, st);
@@ -489,7 +497,24 @@ int launch_cycle_body(ma_plan* P, ClassList cls, int npairs, hipStream_t st) {
       const int old = (j - LAG) % (LAG + 1);
       const int e = wait_summary(P, 1 + old, P->ring_seq[old], st);
       if (e) return e;
-      if (P->h_summary[MA_SUMMARY_INTS * (1 + old) + 8] == 0) break;
+      const int nrun = P->h_summary[MA_SUMMARY_INTS * (1 + old) + 8];
+      if (nrun == 0) break;
+      // running lists after this iteration, in the plan's lists past the counts: each
+      // class's slice at the offset of its pairs among all launched (the views' counts
+      // sum to at most the capacity)
+      int* lists = P->d_lists + 6 * cap;
+      int* counts = P->d_lists + 7 * cap;
+      size_t off = 0;
+      for (int k = 0; k < cls.n; ++k) {
+        const Class& c = cls.p[k];
+        if (4 * nrun < 3 * run[k].count) {
+          launch_compact_running(P->d_state, c.d_ids, c.active_n, c.count, lists + off, counts + k, st);
+          run[k].d_ids = lists + off;
+          run[k].active_n = counts + k;
+          run[k].count = nrun;
+        }
+        off += (size_t)c.count;
+      }
     }
   }
   return MA_OK;
