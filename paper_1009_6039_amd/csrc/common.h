@@ -123,7 +123,10 @@ struct LaunchCtx {
   // is sized by an upper bound the host knows)
   const int* active_n;
   int bicg_max;  // BiCG iterations per Newton step (finite-difference step)
-  int bicg_pad;
+  // pass A's Arnoldi step in a solve: pass C blocks per pair whose inner-product
+  // partials pass A folds itself (their region of the partials comes first, pass A's own
+  // after it); 0: the coefficients come from the pair's state (the autotuner's launches)
+  int dots_nblk;
 };
 
 // Global-address-space view of a device buffer.  Accesses through it compile to

@@ -60,29 +60,10 @@ __device__ void arnoldi_close(PairState& s, const LaunchCtx& c, int jn, double w
   }
 }
 
-// h[l][j] = <w, v_l> for l <= j from the pass-C partials (one block per pair).
-// Lane l of group g sums blocks g, g + 8, ... (32 loads in flight per round).
-__global__ __launch_bounds__(256) void k_dots_finalize(LaunchCtx c, int j, int nblk) {
-  const int p = pair_of_block(c);
-  if (p < 0) return;
-  const PairDesc d = c.desc[p];
-  PairState& s = c.st[p];
-  if (!(s.phase == PH_SOLVE && s.gm_running)) return;
-  __shared__ double red[8][32];
-  const int l = threadIdx.x & 31, grp = threadIdx.x >> 5;
-  const double t = l <= j ? strided_sum<32>(d.part, MA_MMAX + 1, l, grp, 8, nblk) : 0.0;
-  red[grp][l] = t;
-  __syncthreads();
-  if (threadIdx.x <= j) {
-    double u = 0.0;
-    for (int g2 = 0; g2 < 8; ++g2) u += red[g2][threadIdx.x];
-    s.Hm[j * (MA_MMAX + 1) + threadIdx.x] = u * s.vscale[threadIdx.x];
-  }
-}
-
-// ||w'|| from the pass-A partials, then the rotations and the convergence test (on a
-// copy of the pair's state in LDS, loaded together with the partials)
-__global__ __launch_bounds__(256) void k_arnoldi_finalize(LaunchCtx c, int jn, int nblk) {
+// ||w'|| from the pass-A partials (at off, after pass C's), then the rotations and the
+// convergence test (on a copy of the pair's state in LDS, loaded together with the
+// partials)
+__global__ __launch_bounds__(256) void k_arnoldi_finalize(LaunchCtx c, int jn, int nblk, long off) {
   const int p = pair_of_block(c);
   if (p < 0) return;
   const PairDesc d = c.desc[p];
@@ -94,7 +75,7 @@ __global__ __launch_bounds__(256) void k_arnoldi_finalize(LaunchCtx c, int jn, i
   sw.load(&s);
   const int kinds[1] = {0};
   double t[1];
-  fold_partials<1>(d.part, nblk, kinds, t, scratch);
+  fold_partials<1>(d.part + off, nblk, kinds, t, scratch);
   sw.to_lds(&ls);
   __syncthreads();
   if (threadIdx.x == 0) arnoldi_close(ls, c, jn, t[0]);
@@ -265,9 +246,15 @@ bool fft_size_supported(int n) {
 
 void launch_passA(const LaunchCtx& c, int n, int npairs, int mode, int jn, const float2* tw, hipStream_t st,
                   const TimedLaunch& ev) {
-  launch_passA_only(c, n, npairs, mode, jn, tw, st, ev);
-  if (mode == PA_ARNOLDI)
-    hipLaunchKernelGGL(k_arnoldi_finalize, dim3(1, npairs), dim3(256), 0, st, c, jn, passA_blocks(n, c.var[0]));
+  // the Arnoldi step folds the inner products of the pass C before it itself (no
+  // separate fold kernel) and writes its norm partials after pass C's
+  LaunchCtx ca = c;
+  ca.dots_nblk = mode == PA_ARNOLDI ? passC_blocks(n, c.var[2]) : 0;
+  launch_passA_only(ca, n, npairs, mode, jn, tw, st, ev);
+  if (mode == PA_ARNOLDI) {
+    const long off = (long)ca.dots_nblk * (MA_MMAX + 1);
+    hipLaunchKernelGGL(k_arnoldi_finalize, dim3(1, npairs), dim3(256), 0, st, ca, jn, passA_blocks(n, c.var[0]), off);
+  }
   else if (mode == PA_INIT && c.precond == MA_PRECOND_DIAG)
     hipLaunchKernelGGL(k_rhs_finalize, dim3(1, npairs), dim3(256), 0, st, c, passA_blocks(n, c.var[0]));
   else if (mode == PA_PLAIN)
@@ -276,9 +263,8 @@ void launch_passA(const LaunchCtx& c, int n, int npairs, int mode, int jn, const
 
 void launch_passC(const LaunchCtx& c, int n, int npairs, int mode, int j, const float2* tw, hipStream_t st,
                   const TimedLaunch& ev) {
+  // (the matvec's inner products are folded by the next pass A)
   launch_passC_only(c, n, npairs, mode, j, tw, st, ev);
-  if (mode == PC_MATVEC)
-    hipLaunchKernelGGL(k_dots_finalize, dim3(1, npairs), dim3(256), 0, st, c, j, passC_blocks(n, c.var[2]));
 }
 
 void launch_restart(const LaunchCtx& c, int n, int npairs, hipStream_t st) {

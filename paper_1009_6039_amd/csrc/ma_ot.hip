@@ -104,14 +104,15 @@ namespace {
 
 // partial-sum slots per pair: the largest need over all launch-geometry variants
 size_t part_doubles(int n) {
-  size_t need = 256 * 4;
+  size_t need = 256 * 4, c_max = 0, a_max = 0;
   need = std::max(need, (size_t)bicg_blocks(n) * 5);
   for (int v = 0; v < MA_NVARIANTS; ++v) {
     need = std::max(need, (size_t)residual_blocks(n, v) * MA_NPART_RES);
-    need = std::max(need, (size_t)passC_blocks(n, v) * (MA_MMAX + 1));
-    need = std::max(need, (size_t)passA_blocks(n, v) + 16);
+    c_max = std::max(c_max, (size_t)passC_blocks(n, v) * (MA_MMAX + 1));
+    a_max = std::max(a_max, (size_t)passA_blocks(n, v));
   }
-  return need;
+  // pass C's inner-product partials, then pass A's norm partials of the Arnoldi step
+  return std::max(need, c_max + a_max + 16);
 }
 
 size_t pair_bytes(int n, int m, bool bicg) {
@@ -292,6 +293,7 @@ LaunchCtx make_ctx(const ma_plan* P, const Class& cl, int kind = MA_PROF_NONE, b
   c.boundary_frac = P->opt.boundary_frac;
   c.forcing = P->opt.forcing;
   c.bicg_max = P->opt.bicg_max_iters;
+  c.dots_nblk = 0;  // set by the Arnoldi step's launcher
   auto t = P->tune.find(cl.n);
   for (int k = 0; k < 4; ++k) c.var[k] = t == P->tune.end() ? 0 : t->second.v[k];
   return c;

@@ -104,6 +104,28 @@ __device__ __forceinline__ void put_pair(float2* L, int k, float2 A, float2 B) {
 }
 __device__ __forceinline__ float2 times_i(float s, float2 a) { return make_float2(-s * a.y, s * a.x); }
 
+// h_l = <w, v_l>, l < nv, from pass C's block partials (nblk blocks of MA_MMAX + 1
+// slots), in an order that does not depend on the block size: item (l, g), g < 32, sums
+// blocks g, g + 32, ... (strided_sum<4>); the 32 items of one l sit in one half of a
+// wave and are added by DPP prefix sums within rows of 16 and the two row totals.  The
+// block size is a multiple of 64.  out (LDS) receives h_l; ends with a barrier.
+__device__ __forceinline__ void fold_inner_products(const double* part, int nblk, int nv, double* out) {
+  const int lane = threadIdx.x & 63;
+  for (int base = 0; base < 32 * nv; base += blockDim.x) {  // the same trip count in every thread
+    const int t = base + threadIdx.x, l = t >> 5, g = t & 31;
+    double x = l < nv ? strided_sum<4>(part, MA_MMAX + 1, l, g, 32, nblk) : 0.0;
+    x += row_shr<1>(x);
+    x += row_shr<2>(x);
+    x += row_shr<4>(x);
+    x += row_shr<8>(x);
+    const double h0 = read_lane(x, 15) + read_lane(x, 31), h1 = read_lane(x, 47) + read_lane(x, 63);
+    const int l0 = (base + (threadIdx.x & ~63)) >> 5;  // the wave's first l
+    if (lane == 0 && l0 < nv) out[l0] = h0;
+    if (lane == 0 && l0 + 1 < nv) out[l0 + 1] = h1;
+  }
+  __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
 // pass A
 // ---------------------------------------------------------------------------
@@ -132,7 +154,18 @@ __global__ __launch_bounds__((Cfg<N, G>::A_BLOCK)) void k_passA(LaunchCtx c, int
   bool usex = false;
   if (mode == PA_ARNOLDI) nv = jn;
   else if (mode == PA_RECOVER) { nv = s.gm_k; usex = s.gm_cycle > 0; }
-  if (threadIdx.x < nv) {
+  if (mode == PA_ARNOLDI && c.dots_nblk > 0) {
+    // the column h[.][jn - 1] of the Hessenberg matrix from pass C's partials (every
+    // block folds them the same way; block 0 records the column)
+    __shared__ double hl[MA_MMAX + 1];
+    fold_inner_products(d.part, c.dots_nblk, nv, hl);
+    if (threadIdx.x < nv) {
+      const int l = threadIdx.x;
+      const double h = hl[l] * s.vscale[l];
+      cf[l] = (float)(h * s.vscale[l]);
+      if (blockIdx.x == 0) c.st[p].Hm[(jn - 1) * (MA_MMAX + 1) + l] = h;
+    }
+  } else if (threadIdx.x < nv) {
     const int l = threadIdx.x;
     cf[l] = mode == PA_ARNOLDI ? (float)(s.Hm[(jn - 1) * (MA_MMAX + 1) + l] * s.vscale[l]) : (float)s.y[l];
   }
@@ -260,7 +293,9 @@ __global__ __launch_bounds__((Cfg<N, G>::A_BLOCK)) void k_passA(LaunchCtx c, int
     double v[1] = {(double)nrm};
     const int kinds[1] = {0};
     block_reduce<1>(v, kinds, scratch);
-    if (threadIdx.x == 0) d.part[blockIdx.x] = v[0];
+    // after pass C's partials when pass A folds those itself
+    const long off = mode == PA_ARNOLDI ? (long)c.dots_nblk * (MA_MMAX + 1) : 0;
+    if (threadIdx.x == 0) d.part[off + blockIdx.x] = v[0];
   }
 }
 
@@ -447,7 +482,7 @@ __device__ __forceinline__ void passC_load_coef(const PairDesc& d, int row0, Pas
 
 // Pass C's epilogue: w = a11 alpha11 + 2 a12 alpha12 + a22 alpha22 + b1 beta1 + b2 beta2 at
 // the block's points (left-scaled if the option is on), stored as V[j+1], and the
-// block's partial inner products <w, v_l>, l <= j, for k_dots_finalize.  zat(pp, t, jj)
+// block's partial inner products <w, v_l>, l <= j, which the next pass A folds.  zat(pp, t, jj)
 // is element jj of derived transform t of the block's row pair pp: t = 0 alpha11 + i
 // beta1 of row a, 1 alpha12 + i beta2 of row a, 2 and 3 the same for row b, 4 alpha22 of
 // row a (.x) and row b (.y).  The caller synchronises the block before the call.
@@ -489,7 +524,7 @@ __device__ __forceinline__ void passC_combine(const LaunchCtx& c, const PairDesc
     wa[q] = a;
     wb[q] = b;
   }
-  // block reduction of the j+1 inner products (fixed order); folded by k_dots_finalize
+  // block reduction of the j+1 inner products (fixed order); folded by the next pass A
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   stream_vectors<2 * PER>(
       j + 1,
@@ -891,7 +926,18 @@ __global__ __launch_bounds__(64 * W) void k_passA_w(LaunchCtx c, int mode, int j
   bool usex = false;
   if (mode == PA_ARNOLDI) nv = jn;
   else if (mode == PA_RECOVER) { nv = s.gm_k; usex = s.gm_cycle > 0; }
-  if (threadIdx.x < nv) {
+  if (mode == PA_ARNOLDI && c.dots_nblk > 0) {
+    // the column h[.][jn - 1] of the Hessenberg matrix from pass C's partials (every
+    // block folds them the same way; block 0 records the column)
+    __shared__ double hl[MA_MMAX + 1];
+    fold_inner_products(d.part, c.dots_nblk, nv, hl);
+    if (threadIdx.x < nv) {
+      const int l = threadIdx.x;
+      const double h = hl[l] * s.vscale[l];
+      cf[l] = (float)(h * s.vscale[l]);
+      if (blockIdx.x == 0) c.st[p].Hm[(jn - 1) * (MA_MMAX + 1) + l] = h;
+    }
+  } else if (threadIdx.x < nv) {
     const int l = threadIdx.x;
     cf[l] = mode == PA_ARNOLDI ? (float)(s.Hm[(jn - 1) * (MA_MMAX + 1) + l] * s.vscale[l]) : (float)s.y[l];
   }
@@ -1008,7 +1054,9 @@ __global__ __launch_bounds__(64 * W) void k_passA_w(LaunchCtx c, int mode, int j
     double v[1] = {(double)nrm};
     const int kinds[1] = {0};
     block_reduce<1>(v, kinds, scratch);
-    if (threadIdx.x == 0) d.part[blockIdx.x] = v[0];
+    // after pass C's partials when pass A folds those itself
+    const long off = mode == PA_ARNOLDI ? (long)c.dots_nblk * (MA_MMAX + 1) : 0;
+    if (threadIdx.x == 0) d.part[off + blockIdx.x] = v[0];
   }
 }
 
